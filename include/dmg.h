@@ -1,0 +1,217 @@
+/*
+ * dmg.h -- deflated adaptive-multigrid solver for the 2D Schwinger-model
+ * Wilson-Dirac system D x = b on one AMD MI355X (gfx950).
+ *
+ * The method is that of Whyte, Wilcox and Morgan, "Deflated GMRES with
+ * Multigrid for Lattice QCD" (Methods section): a three-grid adaptive
+ * multigrid preconditioner for an outer FGMRES(8); GMRES(2) pre- and
+ * post-smoothing on the fine and intermediate grids; a partial intermediate
+ * solve to 0.2 ||b||; and a deflated coarse solve, GMRES-DR(m, k) on the first
+ * coarse call and GMRES-Proj(m, k) on every later call, reusing the k
+ * eigenvectors.  Cost is counted in matrix-vector products (Mvps) per grid and
+ * in fine-equivalent Mvps, eq. (1) of the Results section.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Complex numbers are interleaved (re, im) pairs of the element type:
+ *    double for DMG_FP64 data, float for DMG_FP32 data.
+ *  - Fine lattice Nx x Nt, site s = x + Nx * t.  A fine field has 2 complex
+ *    components per site, layout [t][x][spin].  A blocked (intermediate or
+ *    coarse) field has 24 complex components per site, layout [T][X][24];
+ *    components 0..11 have chirality +, 12..23 chirality - (Gamma_5 =
+ *    diag(I_12, -I_12)).  Blocking is 4 x 4 sites; block (X, T) holds the
+ *    sites x in [4X, 4X+4), t in [4T, 4T+4).
+ *  - Multi-RHS fields (nrhs > 1) are nrhs single fields stored back to back.
+ *  - ptr_kind selects where caller buffers live: DMG_PTR_HOST (copied through
+ *    the context's stream, call returns after the result is on the host) or
+ *    DMG_PTR_DEVICE (stream-ordered on the context's stream, not synchronised).
+ *  - Every call returns a dmg_status.  Negative values are errors, positive
+ *    values warnings; the message of the last failure is dmg_last_error().
+ *    Nothing throws or aborts across the ABI.
+ *  - Handles are owned by the caller and released with the matching
+ *    *_destroy call, which accepts NULL.  A hierarchy refers to its gauge and
+ *    context; destroy dependants first.
+ */
+#ifndef DMG_H
+#define DMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int dmg_status;
+enum {
+  DMG_OK = 0,
+  DMG_W_NOT_CONVERGED = 1,   /* solve stopped at its iteration cap; best iterate written */
+  DMG_E_INVALID = -1,        /* bad argument, shape or state */
+  DMG_E_NONFINITE = -2,      /* NaN or Inf in an input */
+  DMG_E_HIP = -3,            /* HIP runtime error */
+  DMG_E_BUDGET = -4,         /* allocation would exceed the context's HBM budget */
+  DMG_E_NOMEM = -5,          /* device allocation failed */
+  DMG_E_BREAKDOWN = -6       /* numerical breakdown (rank-deficient block, singular small system) */
+};
+
+enum { DMG_PTR_HOST = 0, DMG_PTR_DEVICE = 1 };
+
+/* Precision of the multigrid preconditioner.  The outer FGMRES (Arnoldi
+ * vectors, orthogonalisation, least squares, true residual) is always FP64. */
+typedef enum { DMG_FP64 = 0, DMG_FP32 = 1 } dmg_precision;
+
+typedef struct dmg_context dmg_context;
+typedef struct dmg_gauge dmg_gauge;
+typedef struct dmg_hierarchy dmg_hierarchy;
+typedef struct dmg_deflation dmg_deflation;
+
+/* Device allocator hooks.  alloc(bytes, user) returns device memory or NULL;
+ * free(ptr, user) releases it.  NULL hooks mean hipMalloc / hipFree. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* user);
+  void (*free)(void* ptr, void* user);
+  void* user;
+} dmg_allocator;
+
+/* ---------------------------------------------------------------- context */
+
+/* Bind a device and a HIP stream (hipStream_t, NULL = default stream).  The
+ * caller keeps the stream.  hbm_budget (bytes, 0 = unlimited) caps the device
+ * memory the context may hold; allocations beyond it fail with DMG_E_BUDGET. */
+dmg_status dmg_context_create(int device, void* hip_stream, const dmg_allocator* alloc,
+                              size_t hbm_budget, dmg_context** out);
+void dmg_context_destroy(dmg_context* ctx);
+/* Message of the last failing call on ctx ("" if none).  Valid until the next call. */
+const char* dmg_last_error(const dmg_context* ctx);
+/* Bytes of device memory currently held by the context. */
+size_t dmg_context_bytes_in_use(const dmg_context* ctx);
+
+/* ------------------------------------------------------------------ gauge */
+
+/* Upload U(1) links U_mu(x, t) = exp(i theta[t][x][mu]) (mu = 0: x, 1: t;
+ * host array of 2 * Nx * Nt doubles, radians).  With t_antiperiodic != 0 the
+ * fermion sees antiperiodic time boundaries (the links on the last time slice
+ * enter D with a minus sign).  The array is copied; FP64 and FP32 copies are
+ * kept on the device.  DMG_E_INVALID if Nx or Nt is odd or < 4;
+ * DMG_E_NONFINITE on a non-finite angle. */
+dmg_status dmg_gauge_create(dmg_context* ctx, int Nx, int Nt, const double* theta,
+                            int t_antiperiodic, dmg_gauge** out);
+void dmg_gauge_destroy(dmg_gauge* g);
+
+/* out = D in (dagger = 0) or D^dagger in (dagger = 1), D the Wilson-Dirac
+ * operator of the Methods section in the r = 1, "m0 + 2" normalisation:
+ *   (D psi)(s) = (m0 + 2) psi(s) - 1/2 sum_mu [ (1 - g_mu) U_mu(s) psi(s + mu)
+ *                                           + (1 + g_mu) U_mu(s - mu)^* psi(s - mu) ]
+ * with g_0 = sigma_1, g_1 = sigma_2; D^dagger = sigma_3 D sigma_3.
+ * in/out: nrhs fine fields of precision p; in and out must not overlap. */
+dmg_status dmg_apply_dirac(dmg_context* ctx, const dmg_gauge* g, double m0, int dagger,
+                           dmg_precision p, const void* in, void* out, int nrhs, int ptr_kind);
+
+/* -------------------------------------------------------------- hierarchy */
+
+typedef struct {
+  int nvec;              /* near-null vectors per level (12) */
+  double null_tol;       /* CG tolerance of D D^dagger e = -D D^dagger x (1e-4) */
+  int null_max_iters;    /* CG iteration cap per level (2000) */
+} dmg_setup_params;
+
+/* Build the three-grid hierarchy (Methods section): for each of the two
+ * coarsenings, 12 near-null vectors psi = x + e from D D^dagger e = -D D^dagger x
+ * solved by CG to null_tol; global orthonormalisation; chiral doubling with
+ * (1 +- gamma_5)/2; restriction to 4 x 4 blocks and local orthonormalisation
+ * (the columns of P); Galerkin operator P^dagger A P.
+ *   start0: nvec fine fields (FP64, layout above) -- the random x of level 0;
+ *   start1: nvec intermediate fields (FP64, 24 * (Nx/4) * (Nt/4) complex each).
+ * With inject_nullvecs != 0 the two arrays are taken as the finished near-null
+ * vectors psi instead and no CG is run (used to check the rest of the setup).
+ * Nx and Nt must be divisible by 16 (DMG_E_INVALID).  DMG_E_BREAKDOWN if a
+ * local block loses rank.  The hierarchy is device resident and FP64; FP32
+ * copies of every operator are made for the mixed-precision form. */
+dmg_status dmg_setup(dmg_context* ctx, const dmg_gauge* g, double m0, const dmg_setup_params* prm,
+                     const void* start0, const void* start1, int inject_nullvecs, int ptr_kind,
+                     dmg_hierarchy** out);
+void dmg_hierarchy_destroy(dmg_hierarchy* h);
+
+/* Parts of a hierarchy that can be copied out (parity checks, checkpoints). */
+typedef enum {
+  DMG_PART_NULLVECS = 0,  /* level 0 or 1: nvec fields psi before orthonormalisation */
+  DMG_PART_P = 1,         /* level 0 or 1: prolongator, [site][dof][12] complex; dof 2 or 24;
+                             entry (s, a, k) is column 12 * c(a) + k of block B(s) */
+  DMG_PART_BLOCKS = 2,    /* level 1 or 2: operator blocks [S][d][col][row] complex (each 24 x 24
+                             block column-major), d = 0 self, 1 +x, 2 -x, 3 +t, 4 -t: the
+                             coupling from site S + d into site S */
+  DMG_PART_SETUP_ITERS = 3 /* level 0 or 1: nvec int32 CG iteration counts */
+} dmg_part;
+/* Copy a part to a caller-owned host buffer of exactly the part's size in
+ * bytes (DMG_E_INVALID otherwise); dmg_hierarchy_part_bytes reports it. */
+dmg_status dmg_hierarchy_export(dmg_hierarchy* h, int level, int part, void* host_buf, size_t bytes);
+size_t dmg_hierarchy_part_bytes(const dmg_hierarchy* h, int level, int part);
+
+/* Operator and transfer hooks on one level of a hierarchy (parity checks).
+ *   DMG_OP_APPLY:    out = A_level in        (level 0, 1, 2)
+ *   DMG_OP_APPLY_DAG: out = A_level^dagger in (level 0, 1, 2)
+ *   DMG_OP_RESTRICT: out = P_level^dagger in (level 0 or 1: level -> level + 1)
+ *   DMG_OP_PROLONG:  out = P_level in        (level 0 or 1: level + 1 -> level)
+ * Buffers are single fields of precision p. */
+enum { DMG_OP_APPLY = 0, DMG_OP_APPLY_DAG = 1, DMG_OP_RESTRICT = 2, DMG_OP_PROLONG = 3 };
+dmg_status dmg_hierarchy_apply(dmg_hierarchy* h, int level, int op, dmg_precision p,
+                               const void* in, void* out, int ptr_kind);
+
+/* -------------------------------------------------------------- deflation */
+
+/* Coarse-grid deflation space (Methods section): EMPTY until the first coarse
+ * solve runs GMRES-DR(m, k), which leaves A V_k = V_{k+1} Hbar_k; READY after
+ * that, when every coarse solve is GMRES-Proj(m, k).  Tied to one hierarchy. */
+dmg_status dmg_deflation_create(dmg_hierarchy* h, int m, int k, dmg_deflation** out);
+/* Fill the space now by GMRES-DR on the given coarse right-hand side (FP64,
+ * 24 * (Nx/16) * (Nt/16) complex) to tol. */
+dmg_status dmg_deflation_build(dmg_deflation* d, const void* rhs, double tol, int ptr_kind);
+void dmg_deflation_reset(dmg_deflation* d);
+int dmg_deflation_ready(const dmg_deflation* d);
+/* Copy the space out: V (n x (k+1), column j at offset j * n) and Hbar
+ * ((k+1) x k, column-major), FP64 complex.  Either buffer may be NULL. */
+dmg_status dmg_deflation_export(const dmg_deflation* d, void* V, void* H, int* k_out);
+void dmg_deflation_destroy(dmg_deflation* d);
+
+/* ------------------------------------------------------------------ solve */
+
+typedef struct {
+  double tol;              /* outer true relative residual (1e-8) */
+  int outer_m;             /* FGMRES restart length (8) */
+  int max_outer_iters;     /* cap on outer Arnoldi steps (400) */
+  int smooth_steps;        /* GMRES smoother steps (2) */
+  double int_tol;          /* partial intermediate solve, relative (0.2) */
+  int int_m;               /* its FGMRES restart length (8) */
+  int int_max_iters;       /* its iteration cap (16) */
+  double coarse_tol_first; /* GMRES-DR tolerance on the first coarse call (1e-8) */
+  double coarse_tol_later; /* GMRES-Proj tolerance afterwards (1e-2) */
+  int coarse_max_iters;    /* cap on coarse Arnoldi steps per call (5000) */
+  dmg_precision precond;   /* preconditioner precision (outer is FP64) */
+  int use_x0;              /* 1: x holds the initial guess */
+} dmg_solve_params;
+
+typedef struct {
+  int outer_iters;
+  int converged;
+  long long fine_mvps, int_mvps, coarse_mvps;
+  double fine_equiv_mvps;   /* eq. (1) */
+  double true_rel_resid;    /* ||b - D x|| / ||b|| in FP64 */
+  int coarse_calls, coarse_dr_calls;
+  double elapsed_ms;
+} dmg_solve_stats;
+
+/* Fill p with the paper's defaults. */
+void dmg_solve_params_default(dmg_solve_params* p);
+void dmg_setup_params_default(dmg_setup_params* p);
+
+/* Solve D x = b for nrhs fine right-hand sides (FP64), one after the other,
+ * sharing the hierarchy and the deflation space (NULL: GMRES(m) coarse solves
+ * with no deflation).  stats: array of nrhs entries (may be NULL).  Returns
+ * DMG_OK, or DMG_W_NOT_CONVERGED if some RHS hit its cap (best iterate written). */
+dmg_status dmg_solve(dmg_context* ctx, dmg_hierarchy* h, dmg_deflation* d, const dmg_solve_params* prm,
+                     const void* b, void* x, int nrhs, int ptr_kind, dmg_solve_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DMG_H */

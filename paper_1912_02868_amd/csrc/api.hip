@@ -1,0 +1,443 @@
+// C-ABI entry points of libdmg (declared in include/dmg.h).  Every entry point
+// catches the library's errors and returns a status; messages are kept per
+// context.
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <new>
+
+#include "solver.h"
+
+namespace dmg {
+
+void* dev_alloc(dmg_context* c, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  if (c->budget && c->in_use + bytes > c->budget)
+    throw Error{DMG_E_BUDGET, "allocation of " + std::to_string(bytes) + " bytes exceeds the HBM budget (" +
+                                  std::to_string(c->in_use) + " of " + std::to_string(c->budget) + " in use)"};
+  void* p = nullptr;
+  if (c->alloc.alloc) {
+    p = c->alloc.alloc(bytes, c->alloc.user);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+  }
+  if (!p) throw Error{DMG_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
+  c->in_use += bytes;
+  return p;
+}
+
+void dev_free(dmg_context* c, void* p, size_t bytes) {
+  if (!p) return;
+  if (c->alloc.free) c->alloc.free(p, c->alloc.user);
+  else (void)hipFree(p);
+  c->in_use -= std::min(bytes ? bytes : 16, c->in_use);
+}
+
+// links U = exp(i theta), antiperiodic sign on the temporal links of the last time slice
+__global__ void k_links(const double* theta, int Nx, int Nt, int anti, double2* U64, float2* U32) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 2 * Nx * Nt) return;
+  const int mu = e & 1, s = e >> 1, t = s / Nx;
+  double sn, cs;
+  sincos(theta[e], &sn, &cs);
+  if (anti && mu == 1 && t == Nt - 1) { sn = -sn; cs = -cs; }
+  U64[e] = make_double2(cs, sn);
+  U32[e] = make_float2((float)cs, (float)sn);
+}
+
+template <typename F>
+static dmg_status guard(dmg_context* c, F&& f) {
+  try {
+    if (c) c->err.clear();
+    return f();
+  } catch (const Error& e) {
+    if (c) c->err = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    if (c) c->err = "host allocation failed";
+    return DMG_E_NOMEM;
+  } catch (const std::exception& e) {
+    if (c) c->err = e.what();
+    return DMG_E_INVALID;
+  }
+}
+
+// copy between caller buffers and device scratch
+static void to_device(dmg_context* c, void* dst, const void* src, size_t bytes, int ptr_kind) {
+  DMG_HIP(hipMemcpyAsync(dst, src, bytes, ptr_kind == DMG_PTR_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                         c->stream));
+}
+static void from_device(dmg_context* c, void* dst, const void* src, size_t bytes, int ptr_kind) {
+  DMG_HIP(hipMemcpyAsync(dst, src, bytes, ptr_kind == DMG_PTR_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                         c->stream));
+  if (ptr_kind == DMG_PTR_HOST) DMG_HIP(hipStreamSynchronize(c->stream));
+}
+
+static bool all_finite(const double* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+}  // namespace dmg
+
+using namespace dmg;
+
+extern "C" {
+
+void dmg_solve_params_default(dmg_solve_params* p) {
+  if (!p) return;
+  p->tol = 1e-8;
+  p->outer_m = 8;
+  p->max_outer_iters = 400;
+  p->smooth_steps = 2;
+  p->int_tol = 0.2;
+  p->int_m = 8;
+  p->int_max_iters = 16;
+  p->coarse_tol_first = 1e-8;
+  p->coarse_tol_later = 1e-2;
+  p->coarse_max_iters = 5000;
+  p->precond = DMG_FP64;
+  p->use_x0 = 0;
+}
+
+void dmg_setup_params_default(dmg_setup_params* p) {
+  if (!p) return;
+  p->nvec = 12;
+  p->null_tol = 1e-4;
+  p->null_max_iters = 2000;
+}
+
+dmg_status dmg_context_create(int device, void* hip_stream, const dmg_allocator* alloc, size_t hbm_budget,
+                              dmg_context** out) {
+  if (!out) return DMG_E_INVALID;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return DMG_E_INVALID;
+  if (hipSetDevice(device) != hipSuccess) return DMG_E_HIP;
+  dmg_context* c = new (std::nothrow) dmg_context();
+  if (!c) return DMG_E_NOMEM;
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  if (alloc) c->alloc = *alloc;
+  c->budget = hbm_budget;
+  *out = c;
+  return DMG_OK;
+}
+
+void dmg_context_destroy(dmg_context* ctx) { delete ctx; }
+
+const char* dmg_last_error(const dmg_context* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+size_t dmg_context_bytes_in_use(const dmg_context* ctx) { return ctx ? ctx->in_use : 0; }
+
+dmg_status dmg_gauge_create(dmg_context* ctx, int Nx, int Nt, const double* theta, int t_antiperiodic,
+                            dmg_gauge** out) {
+  if (!ctx || !out) return DMG_E_INVALID;
+  return guard(ctx, [&]() -> dmg_status {
+    *out = nullptr;
+    DMG_CHECK(theta, DMG_E_INVALID, "theta is NULL");
+    DMG_CHECK(Nx >= 4 && Nt >= 4 && Nx % 2 == 0 && Nt % 2 == 0, DMG_E_INVALID, "lattice extents must be even and >= 4");
+    const size_t ne = 2 * (size_t)Nx * Nt;
+    DMG_CHECK(all_finite(theta, ne), DMG_E_NONFINITE, "non-finite link angle");
+    dmg_gauge* g = new dmg_gauge();
+    g->ctx = ctx;
+    g->Nx = Nx;
+    g->Nt = Nt;
+    try {
+      g->U64 = (double2*)dev_alloc(ctx, sizeof(double2) * ne);
+      g->U32 = (float2*)dev_alloc(ctx, sizeof(float2) * ne);
+      double* th = (double*)dev_alloc(ctx, sizeof(double) * ne);
+      DMG_HIP(hipMemcpyAsync(th, theta, sizeof(double) * ne, hipMemcpyHostToDevice, ctx->stream));
+      hipLaunchKernelGGL(k_links, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, ctx->stream, th, Nx, Nt,
+                         t_antiperiodic ? 1 : 0, g->U64, g->U32);
+      DMG_LAUNCH_CHECK();
+      DMG_HIP(hipStreamSynchronize(ctx->stream));
+      dev_free(ctx, th, sizeof(double) * ne);
+    } catch (...) {
+      dmg_gauge_destroy(g);
+      throw;
+    }
+    *out = g;
+    return DMG_OK;
+  });
+}
+
+void dmg_gauge_destroy(dmg_gauge* g) {
+  if (!g) return;
+  dev_free(g->ctx, g->U64, sizeof(double2) * 2 * (size_t)g->Nx * g->Nt);
+  dev_free(g->ctx, g->U32, sizeof(float2) * 2 * (size_t)g->Nx * g->Nt);
+  delete g;
+}
+
+dmg_status dmg_apply_dirac(dmg_context* ctx, const dmg_gauge* g, double m0, int dagger, dmg_precision p,
+                           const void* in, void* out, int nrhs, int ptr_kind) {
+  if (!ctx) return DMG_E_INVALID;
+  return guard(ctx, [&]() -> dmg_status {
+    DMG_CHECK(g && in && out && nrhs >= 1, DMG_E_INVALID, "apply_dirac: bad arguments");
+    DMG_CHECK(std::isfinite(m0), DMG_E_NONFINITE, "non-finite mass");
+    const size_t es = p == DMG_FP64 ? sizeof(double2) : sizeof(float2);
+    const size_t bytes = es * 2 * (size_t)g->Nx * g->Nt * nrhs;
+    DevBuf bi, bo;
+    const void* din = in;
+    void* dout = out;
+    if (ptr_kind == DMG_PTR_HOST) {
+      bi.alloc(ctx, bytes);
+      bo.alloc(ctx, bytes);
+      to_device(ctx, bi.p, in, bytes, DMG_PTR_HOST);
+      din = bi.p;
+      dout = bo.p;
+    }
+    if (p == DMG_FP64)
+      launch_wilson<double>(ctx->stream, g->U64, (const double2*)din, (double2*)dout, m0, g->Nx, g->Nt, dagger ? 1 : 0,
+                            nrhs);
+    else
+      launch_wilson<float>(ctx->stream, g->U32, (const float2*)din, (float2*)dout, m0, g->Nx, g->Nt, dagger ? 1 : 0,
+                           nrhs);
+    if (ptr_kind == DMG_PTR_HOST) from_device(ctx, out, dout, bytes, DMG_PTR_HOST);
+    return DMG_OK;
+  });
+}
+
+dmg_status dmg_setup(dmg_context* ctx, const dmg_gauge* g, double m0, const dmg_setup_params* prm, const void* start0,
+                     const void* start1, int inject_nullvecs, int ptr_kind, dmg_hierarchy** out) {
+  if (!ctx || !out) return DMG_E_INVALID;
+  return guard(ctx, [&]() -> dmg_status {
+    *out = nullptr;
+    DMG_CHECK(g && start0 && start1, DMG_E_INVALID, "setup: NULL argument");
+    DMG_CHECK(g->Nx % 16 == 0 && g->Nt % 16 == 0, DMG_E_INVALID,
+              "three grids with 4 x 4 blocking need Nx and Nt divisible by 16");
+    DMG_CHECK(std::isfinite(m0), DMG_E_NONFINITE, "non-finite mass");
+    dmg_setup_params sp;
+    dmg_setup_params_default(&sp);
+    if (prm) sp = *prm;
+    DMG_CHECK(sp.nvec == NV && sp.null_tol > 0.0 && sp.null_max_iters >= 1, DMG_E_INVALID, "setup parameters");
+    dmg_hierarchy* h = new dmg_hierarchy();
+    try {
+      h->ctx = ctx;
+      h->g = g;
+      h->m0 = m0;
+      h->prm = sp;
+      DMG_HIP(hipHostMalloc((void**)&h->host_status, 256, hipHostMallocDefault));
+      h->partials.alloc(ctx, sizeof(double2) * 80 * 1024);
+      h->counters.alloc(ctx, sizeof(unsigned) * 64);
+      h->flags.alloc(ctx, sizeof(int) * 64);
+      DMG_HIP(hipMemsetAsync(h->counters.p, 0, sizeof(unsigned) * 64, ctx->stream));
+      DMG_HIP(hipMemsetAsync(h->flags.p, 0, sizeof(int) * 64, ctx->stream));
+      Op& f = h->op[0];
+      f.kind = 0;
+      f.Lx = g->Nx;
+      f.Lt = g->Nt;
+      f.n = 2 * (int64_t)g->Nx * g->Nt;
+      f.U64 = g->U64;
+      f.U32 = g->U32;
+      f.m0 = m0;
+      const size_t b0 = sizeof(double2) * (size_t)f.n * sp.nvec;
+      const size_t b1 = sizeof(double2) * (size_t)(f.n / 2 / 16 * NC) * sp.nvec;
+      DevBuf s0, s1;
+      const double2* d0 = (const double2*)start0;
+      const double2* d1 = (const double2*)start1;
+      if (ptr_kind == DMG_PTR_HOST) {
+        DMG_CHECK(all_finite((const double*)start0, b0 / sizeof(double)) &&
+                      all_finite((const double*)start1, b1 / sizeof(double)),
+                  DMG_E_NONFINITE, "non-finite start vector");
+        s0.alloc(ctx, b0);
+        s1.alloc(ctx, b1);
+        to_device(ctx, s0.p, start0, b0, DMG_PTR_HOST);
+        to_device(ctx, s1.p, start1, b1, DMG_PTR_HOST);
+        d0 = s0.as<double2>();
+        d1 = s1.as<double2>();
+      }
+      build_hierarchy(h, d0, d1, inject_nullvecs);
+    } catch (...) {
+      delete h;
+      throw;
+    }
+    *out = h;
+    return DMG_OK;
+  });
+}
+
+void dmg_hierarchy_destroy(dmg_hierarchy* h) { delete h; }
+
+size_t dmg_hierarchy_part_bytes(const dmg_hierarchy* h, int level, int part) {
+  if (!h) return 0;
+  switch (part) {
+    case DMG_PART_NULLVECS:
+      return (level == 0 || level == 1) ? sizeof(double2) * (size_t)h->op[level].n * h->prm.nvec : 0;
+    case DMG_PART_P:
+      return (level == 0 || level == 1) ? sizeof(double2) * (size_t)h->op[level].n * NV : 0;
+    case DMG_PART_BLOCKS:
+      return (level == 1 || level == 2) ? sizeof(double2) * (size_t)h->op[level].Lx * h->op[level].Lt * 5 * NC * NC
+                                        : 0;
+    case DMG_PART_SETUP_ITERS:
+      return (level == 0 || level == 1) ? sizeof(int) * (size_t)h->prm.nvec : 0;
+    default:
+      return 0;
+  }
+}
+
+dmg_status dmg_hierarchy_export(dmg_hierarchy* h, int level, int part, void* host_buf, size_t bytes) {
+  if (!h) return DMG_E_INVALID;
+  return guard(h->ctx, [&]() -> dmg_status {
+    const size_t need = dmg_hierarchy_part_bytes(h, level, part);
+    DMG_CHECK(need > 0 && bytes == need && host_buf, DMG_E_INVALID, "export: bad level, part or size");
+    const void* src = nullptr;
+    switch (part) {
+      case DMG_PART_NULLVECS: src = h->null[level].p; break;
+      case DMG_PART_P: src = h->P64[level].p; break;
+      case DMG_PART_BLOCKS: src = h->A64[level].p; break;
+      default:
+        std::memcpy(host_buf, h->setup_iters[level], need);
+        return DMG_OK;
+    }
+    from_device(h->ctx, host_buf, src, need, DMG_PTR_HOST);
+    return DMG_OK;
+  });
+}
+
+dmg_status dmg_hierarchy_apply(dmg_hierarchy* h, int level, int op, dmg_precision p, const void* in, void* out,
+                               int ptr_kind) {
+  if (!h) return DMG_E_INVALID;
+  return guard(h->ctx, [&]() -> dmg_status {
+    DMG_CHECK(in && out && level >= 0 && level <= 2, DMG_E_INVALID, "hierarchy_apply: bad arguments");
+    const bool is_transfer = op == DMG_OP_RESTRICT || op == DMG_OP_PROLONG;
+    DMG_CHECK(!is_transfer || level <= 1, DMG_E_INVALID, "transfers exist between levels 0-1 and 1-2");
+    const size_t es = p == DMG_FP64 ? sizeof(double2) : sizeof(float2);
+    int64_t nin = h->op[level].n, nout = h->op[level].n;
+    if (op == DMG_OP_RESTRICT) nout = h->op[level + 1].n;
+    if (op == DMG_OP_PROLONG) nin = h->op[level + 1].n;
+    dmg_context* c = h->ctx;
+    DevBuf bi, bo;
+    const void* din = in;
+    void* dout = out;
+    if (ptr_kind == DMG_PTR_HOST) {
+      bi.alloc(c, es * nin);
+      bo.alloc(c, es * nout);
+      to_device(c, bi.p, in, es * nin, DMG_PTR_HOST);
+      din = bi.p;
+      dout = bo.p;
+    }
+    hipStream_t s = c->stream;
+    const Transfer& tr = h->tr[level < 2 ? level : 1];
+    if (p == DMG_FP64) {
+      switch (op) {
+        case DMG_OP_APPLY: h->op[level].apply(s, (const double2*)din, (double2*)dout, 0, nullptr); break;
+        case DMG_OP_APPLY_DAG: h->op[level].apply(s, (const double2*)din, (double2*)dout, 1, nullptr); break;
+        case DMG_OP_RESTRICT:
+          launch_restrict<double>(s, tr.P64, (const double2*)din, (double2*)dout, tr.Lx, tr.Lt, tr.dof);
+          break;
+        case DMG_OP_PROLONG:
+          launch_prolong<double>(s, tr.P64, (const double2*)din, (double2*)dout, tr.Lx, tr.Lt, tr.dof, 0);
+          break;
+        default: DMG_CHECK(false, DMG_E_INVALID, "unknown op");
+      }
+    } else {
+      switch (op) {
+        case DMG_OP_APPLY: h->op[level].apply(s, (const float2*)din, (float2*)dout, 0, nullptr); break;
+        case DMG_OP_APPLY_DAG: h->op[level].apply(s, (const float2*)din, (float2*)dout, 1, nullptr); break;
+        case DMG_OP_RESTRICT:
+          launch_restrict<float>(s, tr.P32, (const float2*)din, (float2*)dout, tr.Lx, tr.Lt, tr.dof);
+          break;
+        case DMG_OP_PROLONG:
+          launch_prolong<float>(s, tr.P32, (const float2*)din, (float2*)dout, tr.Lx, tr.Lt, tr.dof, 0);
+          break;
+        default: DMG_CHECK(false, DMG_E_INVALID, "unknown op");
+      }
+    }
+    if (ptr_kind == DMG_PTR_HOST) from_device(c, out, dout, es * nout, DMG_PTR_HOST);
+    return DMG_OK;
+  });
+}
+
+dmg_status dmg_deflation_create(dmg_hierarchy* h, int m, int k, dmg_deflation** out) {
+  if (!h || !out) return DMG_E_INVALID;
+  return guard(h->ctx, [&]() -> dmg_status {
+    *out = nullptr;
+    DMG_CHECK(m >= 2 && m <= MMAX && k >= 1 && k < m, DMG_E_INVALID, "deflation sizes need 1 <= k < m <= 64");
+    dmg_deflation* d = new dmg_deflation();
+    d->h = h;
+    d->m = m;
+    d->k = k;
+    *out = d;
+    return DMG_OK;
+  });
+}
+
+dmg_status dmg_deflation_build(dmg_deflation* d, const void* rhs, double tol, int ptr_kind) {
+  if (!d) return DMG_E_INVALID;
+  dmg_hierarchy* h = d->h;
+  return guard(h->ctx, [&]() -> dmg_status {
+    DMG_CHECK(rhs && tol > 0.0, DMG_E_INVALID, "deflation_build: bad arguments");
+    const int64_t n = h->op[2].n;
+    DevBuf b, x;
+    b.alloc(h->ctx, sizeof(double2) * n);
+    x.alloc(h->ctx, sizeof(double2) * n);
+    to_device(h->ctx, b.p, rhs, sizeof(double2) * n, ptr_kind);
+    d->ready = 0;
+    coarse_gmres_dr(h, d, b.as<double2>(), x.as<double2>(), tol, 100000);
+    DMG_HIP(hipStreamSynchronize(h->ctx->stream));
+    return DMG_OK;
+  });
+}
+
+void dmg_deflation_reset(dmg_deflation* d) {
+  if (!d) return;
+  d->ready = 0;
+  d->cast_ready = 0;
+  d->kk = 0;
+}
+
+int dmg_deflation_ready(const dmg_deflation* d) { return d ? d->ready : 0; }
+
+dmg_status dmg_deflation_export(const dmg_deflation* d, void* V, void* H, int* k_out) {
+  if (!d) return DMG_E_INVALID;
+  dmg_hierarchy* h = d->h;
+  return guard(h->ctx, [&]() -> dmg_status {
+    DMG_CHECK(d->ready, DMG_E_INVALID, "deflation space is empty");
+    if (k_out) *k_out = d->kk;
+    const int64_t n = h->op[2].n;
+    if (V) from_device(h->ctx, V, d->V64.p, sizeof(double2) * n * (d->kk + 1), DMG_PTR_HOST);
+    if (H) from_device(h->ctx, H, d->H.p, sizeof(double2) * (d->kk + 1) * d->kk, DMG_PTR_HOST);
+    return DMG_OK;
+  });
+}
+
+void dmg_deflation_destroy(dmg_deflation* d) { delete d; }
+
+dmg_status dmg_solve(dmg_context* ctx, dmg_hierarchy* h, dmg_deflation* d, const dmg_solve_params* prm, const void* b,
+                     void* x, int nrhs, int ptr_kind, dmg_solve_stats* stats) {
+  if (!ctx || !h) return DMG_E_INVALID;
+  return guard(ctx, [&]() -> dmg_status {
+    DMG_CHECK(h->ctx == ctx, DMG_E_INVALID, "hierarchy belongs to another context");
+    DMG_CHECK(b && x && nrhs >= 1, DMG_E_INVALID, "solve: bad arguments");
+    dmg_solve_params p;
+    dmg_solve_params_default(&p);
+    if (prm) p = *prm;
+    DMG_CHECK(p.tol > 0.0 && p.int_tol > 0.0 && p.coarse_tol_first > 0.0 && p.coarse_tol_later > 0.0 &&
+                  p.max_outer_iters >= 1 && p.int_max_iters >= 1 && p.coarse_max_iters >= 1,
+              DMG_E_INVALID, "solve parameters");
+    const int64_t n = h->op[0].n;
+    const size_t fb = sizeof(double2) * n;
+    if (!h->ob.p) {
+      h->ob.alloc(ctx, fb);
+      h->ox.alloc(ctx, fb);
+    }
+    dmg_status worst = DMG_OK;
+    for (int i = 0; i < nrhs; ++i) {
+      const char* bi = (const char*)b + fb * i;
+      char* xi = (char*)x + fb * i;
+      if (ptr_kind == DMG_PTR_HOST)
+        DMG_CHECK(all_finite((const double*)bi, 2 * (size_t)n), DMG_E_NONFINITE, "non-finite right-hand side");
+      to_device(ctx, h->ob.p, bi, fb, ptr_kind);
+      if (p.use_x0) to_device(ctx, h->ox.p, xi, fb, ptr_kind);
+      dmg_status st = outer_solve(h, d, &p, h->ob.as<double2>(), h->ox.as<double2>(), stats ? stats + i : nullptr);
+      from_device(ctx, xi, h->ox.p, fb, ptr_kind);
+      if (st != DMG_OK) worst = st;
+    }
+    return worst;
+  });
+}
+
+}  // extern "C"

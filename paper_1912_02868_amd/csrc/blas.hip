@@ -1,0 +1,483 @@
+// Vector kernels of the Krylov solvers: Gram-Schmidt dot products and updates,
+// norms, linear combinations and casts.  Reductions are deterministic: each
+// workgroup writes its partial sums, and the last workgroup to finish (counted
+// with one atomic ticket) adds the partials in workgroup order and runs the
+// small epilogue of the step (Hessenberg entries, Givens update).
+#include "kernels.h"
+
+namespace dmg {
+
+constexpr int RB = 256;          // threads per reduction workgroup
+constexpr int RW = RB / 64;      // wavefronts per reduction workgroup
+constexpr int MAXRED = 512;      // largest reduction grid
+
+int red_blocks(int64_t n) {
+  int64_t b = (n + RB - 1) / RB;
+  if (b < 1) b = 1;
+  if (b > MAXRED) b = MAXRED;
+  return (int)b;
+}
+
+__device__ inline double2 wave_sum(double2 v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    v.x += __shfl_xor(v.x, off, 64);
+    v.y += __shfl_xor(v.y, off, 64);
+  }
+  return v;
+}
+
+// Sum `v` over the workgroup for quantity q; result valid in lds[0][q] after the caller's barrier.
+__device__ inline void wg_accumulate(double2 (*lds)[MMAX + 2], int q, double2 v) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6][q] = v;
+}
+
+__device__ inline double2 wg_result(double2 (*lds)[MMAX + 2], int q) {
+  double2 r = lds[0][q];
+  for (int w = 1; w < RW; ++w) r = cadd(r, lds[w][q]);
+  return r;
+}
+
+// Ticket: true in exactly one (the last) workgroup, after all partials are visible.
+__device__ inline bool last_block(unsigned* counter) {
+  __shared__ int am_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned t = atomicAdd(counter, 1u);
+    am_last = (t == gridDim.x * gridDim.y - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (am_last) {
+    __threadfence();
+    if (threadIdx.x == 0) *counter = 0u;
+  }
+  return am_last != 0;
+}
+
+// ---------------------------------------------------------------- Givens update (one thread)
+__device__ void givens_update(KState* ks, int j) {
+  constexpr int LD = MMAX + 1;
+  double2* col = ks->H + (int64_t)LD * j;
+  double2* r = ks->R + (int64_t)LD * j;
+  for (int i = 0; i <= j + 1; ++i) r[i] = col[i];
+  for (int q = 0; q < ks->nrot; ++q) {
+    const int p = ks->rot_p[q];
+    if (p + 1 > j + 1) continue;
+    const double c = ks->rot_c[q];
+    const double2 s = ks->rot_s[q];
+    const double2 a = r[p], b = r[p + 1];
+    r[p] = cadd(cscale(a, c), cmul(s, b));
+    r[p + 1] = csub(cscale(b, c), cmul(cconj(s), a));
+  }
+  // new rotation on rows (j, j+1) zeroing r[j+1]
+  const double2 a = r[j], b = r[j + 1];
+  const double na = sqrt(cabs2(a)), nb = sqrt(cabs2(b));
+  double c;
+  double2 s;
+  if (nb == 0.0) {
+    c = 1.0; s = mk(0.0, 0.0);
+  } else if (na == 0.0) {
+    c = 0.0; s = cscale(cconj(b), 1.0 / nb);
+  } else {
+    const double nr = sqrt(na * na + nb * nb);
+    c = na / nr;
+    s = cscale(cmul(cconj(b), a), 1.0 / (na * nr));
+  }
+  r[j] = cadd(cscale(a, c), cmul(s, b));
+  r[j + 1] = mk(0.0, 0.0);
+  const double2 gj = ks->g[j], gj1 = ks->g[j + 1];
+  ks->g[j] = cadd(cscale(gj, c), cmul(s, gj1));
+  ks->g[j + 1] = csub(cscale(gj1, c), cmul(cconj(s), gj));
+  const int q = ks->nrot;
+  ks->rot_p[q] = j;
+  ks->rot_c[q] = c;
+  ks->rot_s[q] = s;
+  ks->nrot = q + 1;
+  ks->est = sqrt(cabs2(ks->g[j + 1]));
+  ks->steps = j + 1;
+}
+
+// ---------------------------------------------------------------- Arnoldi kernels
+// (a) h_i = V_i^H w (i <= j) and ||w||^2; w is column j+1.
+template <typename R>
+__global__ void __launch_bounds__(RB) k_arn_dots1(const cx<R>* __restrict__ V, int64_t ld, int64_t n, int j,
+                                                  KState* ks, double2* partials, unsigned* counter) {
+  if (ks->done) return;
+  __shared__ double2 lds[RW][MMAX + 2];
+  const cx<R>* w = V + (int64_t)(j + 1) * ld;
+  const int64_t stride = (int64_t)gridDim.x * RB;
+  const int64_t e0 = (int64_t)blockIdx.x * RB + threadIdx.x;
+  for (int i = 0; i <= j + 1; ++i) {
+    const cx<R>* vi = V + (int64_t)i * ld;
+    double2 acc = mk(0.0, 0.0);
+    for (int64_t e = e0; e < n; e += stride) cfmac(acc, to_d(vi[e]), to_d(w[e]));
+    wg_accumulate(lds, i, acc);
+  }
+  __syncthreads();
+  const int nq = j + 2;
+  for (int q = threadIdx.x; q < nq; q += RB) partials[(int64_t)q * gridDim.x + blockIdx.x] = wg_result(lds, q);
+  if (!last_block(counter)) return;
+  constexpr int LD = MMAX + 1;
+  for (int q = threadIdx.x; q < nq; q += RB) {
+    double2 r = mk(0.0, 0.0);
+    for (int b = 0; b < (int)gridDim.x; ++b) r = cadd(r, partials[(int64_t)q * gridDim.x + b]);
+    if (q <= j) ks->H[LD * j + q] = r;
+    else ks->wn0 = sqrt(r.x);
+  }
+  for (int q = j + 2 + threadIdx.x; q <= MMAX; q += RB) ks->H[LD * j + q] = mk(0.0, 0.0);
+}
+
+// (b) w -= sum_i H[i, j] V_i; then h2_i = V_i^H w; H[i, j] += h2_i.
+template <typename R>
+__global__ void __launch_bounds__(RB) k_arn_update_dots2(cx<R>* __restrict__ V, int64_t ld, int64_t n, int j,
+                                                         KState* ks, double2* partials, unsigned* counter) {
+  if (ks->done) return;
+  __shared__ double2 lds[RW][MMAX + 2];
+  __shared__ double2 coef[MMAX + 1];
+  constexpr int LD = MMAX + 1;
+  for (int i = threadIdx.x; i <= j; i += RB) coef[i] = ks->H[LD * j + i];
+  __syncthreads();
+  cx<R>* w = V + (int64_t)(j + 1) * ld;
+  const int64_t stride = (int64_t)gridDim.x * RB;
+  const int64_t e0 = (int64_t)blockIdx.x * RB + threadIdx.x;
+  for (int64_t e = e0; e < n; e += stride) {
+    double2 acc = to_d(w[e]);
+    for (int i = 0; i <= j; ++i) {
+      const double2 v = to_d(V[(int64_t)i * ld + e]);
+      acc = csub(acc, cmul(coef[i], v));
+    }
+    w[e] = from_d<R>(acc);
+  }
+  for (int i = 0; i <= j; ++i) {
+    const cx<R>* vi = V + (int64_t)i * ld;
+    double2 acc = mk(0.0, 0.0);
+    for (int64_t e = e0; e < n; e += stride) cfmac(acc, to_d(vi[e]), to_d(w[e]));
+    wg_accumulate(lds, i, acc);
+  }
+  __syncthreads();
+  const int nq = j + 1;
+  for (int q = threadIdx.x; q < nq; q += RB) partials[(int64_t)q * gridDim.x + blockIdx.x] = wg_result(lds, q);
+  if (!last_block(counter)) return;
+  for (int q = threadIdx.x; q < nq; q += RB) {
+    double2 r = mk(0.0, 0.0);
+    for (int b = 0; b < (int)gridDim.x; ++b) r = cadd(r, partials[(int64_t)q * gridDim.x + b]);
+    ks->h2[q] = r;
+    ks->H[LD * j + q] = cadd(ks->H[LD * j + q], r);
+  }
+}
+
+// (c) w -= sum_i h2_i V_i; ||w|| -> H[j+1, j]; Givens update; convergence flag.
+template <typename R>
+__global__ void __launch_bounds__(RB) k_arn_update_norm(cx<R>* __restrict__ V, int64_t ld, int64_t n, int j,
+                                                        KState* ks, double2* partials, unsigned* counter) {
+  if (ks->done) return;
+  __shared__ double2 lds[RW][MMAX + 2];
+  __shared__ double2 coef[MMAX + 1];
+  constexpr int LD = MMAX + 1;
+  for (int i = threadIdx.x; i <= j; i += RB) coef[i] = ks->h2[i];
+  __syncthreads();
+  cx<R>* w = V + (int64_t)(j + 1) * ld;
+  const int64_t stride = (int64_t)gridDim.x * RB;
+  const int64_t e0 = (int64_t)blockIdx.x * RB + threadIdx.x;
+  double2 nrm = mk(0.0, 0.0);
+  for (int64_t e = e0; e < n; e += stride) {
+    double2 acc = to_d(w[e]);
+    for (int i = 0; i <= j; ++i) acc = csub(acc, cmul(coef[i], to_d(V[(int64_t)i * ld + e])));
+    const cx<R> st = from_d<R>(acc);
+    w[e] = st;
+    const double2 sd = to_d(st);
+    nrm.x += cabs2(sd);
+  }
+  wg_accumulate(lds, 0, nrm);
+  __syncthreads();
+  if (threadIdx.x == 0) partials[blockIdx.x] = wg_result(lds, 0);
+  if (!last_block(counter)) return;
+  if (threadIdx.x == 0) {
+    double s2 = 0.0;
+    for (int b = 0; b < (int)gridDim.x; ++b) s2 += partials[b].x;
+    double hn = sqrt(s2);
+    int brk = 0;
+    if (!(hn > 1e-12 * ks->wn0)) { hn = 0.0; brk = 1; }
+    ks->H[LD * j + j + 1] = mk(hn, 0.0);
+    givens_update(ks, j);
+    if (brk) { ks->breakdown = 1; ks->est = 0.0; }
+    if (brk || ks->est <= ks->tol_abs) ks->done = 1;
+  }
+}
+
+// (d) V_{j+1} = w / h_{j+1, j}
+template <typename R>
+__global__ void __launch_bounds__(RB) k_arn_normalize(cx<R>* __restrict__ V, int64_t ld, int64_t n, int j,
+                                                      const KState* ks) {
+  if (ks->done && ks->breakdown) return;
+  constexpr int LD = MMAX + 1;
+  const double hn = ks->H[LD * j + j + 1].x;
+  if (hn == 0.0) return;
+  const double inv = 1.0 / hn;
+  cx<R>* w = V + (int64_t)(j + 1) * ld;
+  const int64_t stride = (int64_t)gridDim.x * RB;
+  for (int64_t e = (int64_t)blockIdx.x * RB + threadIdx.x; e < n; e += stride) {
+    double2 v = to_d(w[e]);
+    w[e] = from_d<R>(cscale(v, inv));
+  }
+}
+
+template <typename R>
+void launch_arnoldi_orth(hipStream_t s, cx<R>* V, int64_t ld, int64_t n, int j, KState* ks, double2* partials,
+                         unsigned* counter) {
+  const int G = red_blocks(n);
+  hipLaunchKernelGGL(k_arn_dots1<R>, dim3(G), dim3(RB), 0, s, V, ld, n, j, ks, partials, counter);
+  hipLaunchKernelGGL(k_arn_update_dots2<R>, dim3(G), dim3(RB), 0, s, V, ld, n, j, ks, partials, counter);
+  hipLaunchKernelGGL(k_arn_update_norm<R>, dim3(G), dim3(RB), 0, s, V, ld, n, j, ks, partials, counter);
+  hipLaunchKernelGGL(k_arn_normalize<R>, dim3(G), dim3(RB), 0, s, V, ld, n, j, ks);
+  DMG_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------- combinations
+template <typename R>
+__global__ void __launch_bounds__(RB) k_combine(cx<R>* __restrict__ x, const cx<R>* __restrict__ V, int64_t ld,
+                                                int64_t n, const KState* ks, int use_u, int accumulate) {
+  __shared__ double2 coef[MMAX + 2];
+  const int cnt = ks->steps + (use_u ? 1 : 0);
+  const double2* src = use_u ? ks->u : ks->y;
+  for (int i = threadIdx.x; i < cnt; i += RB) coef[i] = src[i];
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * RB;
+  for (int64_t e = (int64_t)blockIdx.x * RB + threadIdx.x; e < n; e += stride) {
+    double2 acc = accumulate ? to_d(x[e]) : mk(0.0, 0.0);
+    for (int i = 0; i < cnt; ++i) cfma(acc, coef[i], to_d(V[(int64_t)i * ld + e]));
+    x[e] = from_d<R>(acc);
+  }
+}
+
+template <typename R, typename RX>
+void launch_combine(hipStream_t s, cx<RX>* x, const cx<R>* V, int64_t ld, int64_t n, const KState* ks, int use_u,
+                    int accumulate) {
+  static_assert(sizeof(R) == sizeof(RX), "combine: same precision");
+  hipLaunchKernelGGL(k_combine<R>, dim3(red_blocks(n)), dim3(RB), 0, s, (cx<R>*)x, V, ld, n, ks, use_u, accumulate);
+  DMG_LAUNCH_CHECK();
+}
+
+template <typename R>
+__global__ void k_axpby(int64_t n, double a, const cx<R>* __restrict__ x, double b, cx<R>* __restrict__ y) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+    const double2 xv = to_d(x[e]), yv = to_d(y[e]);
+    y[e] = from_d<R>(mk(a * xv.x + b * yv.x, a * xv.y + b * yv.y));
+  }
+}
+
+template <typename R>
+void launch_axpby(hipStream_t s, int64_t n, double a, const cx<R>* x, double b, cx<R>* y) {
+  hipLaunchKernelGGL(k_axpby<R>, dim3(red_blocks(n)), dim3(RB), 0, s, n, a, x, b, y);
+  DMG_LAUNCH_CHECK();
+}
+
+template <typename R>
+void launch_xmy(hipStream_t s, int64_t n, const cx<R>* x, cx<R>* y) {
+  launch_axpby<R>(s, n, 1.0, x, -1.0, y);
+}
+
+__global__ void k_d2f(int64_t n, const double2* __restrict__ x, float2* __restrict__ y) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride)
+    y[e] = make_float2((float)x[e].x, (float)x[e].y);
+}
+__global__ void k_f2d(int64_t n, const float2* __restrict__ x, double2* __restrict__ y) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride)
+    y[e] = make_double2((double)x[e].x, (double)x[e].y);
+}
+void launch_cast_d2f(hipStream_t s, int64_t n, const double2* x, float2* y) {
+  hipLaunchKernelGGL(k_d2f, dim3(red_blocks(n)), dim3(RB), 0, s, n, x, y);
+  DMG_LAUNCH_CHECK();
+}
+void launch_cast_f2d(hipStream_t s, int64_t n, const float2* x, double2* y) {
+  hipLaunchKernelGGL(k_f2d, dim3(red_blocks(n)), dim3(RB), 0, s, n, x, y);
+  DMG_LAUNCH_CHECK();
+}
+void launch_d2f(hipStream_t s, int64_t n, const double2* x, float2* y) { launch_cast_d2f(s, n, x, y); }
+
+// ---------------------------------------------------------------- norms and cycle start
+// mode 0: out[0] = ||x||^2
+// mode 1: start a cycle from x: beta = ||x||, state reset, g = c = beta e1,
+//         tol_abs = tol_rel * bnorm (bnorm kept from an earlier call)
+// mode 2: as mode 1 and first set bnorm = ||x|| (the right-hand side of the solve)
+// mode 3: bnorm = ||x|| only
+template <typename R>
+__global__ void __launch_bounds__(RB) k_norm2(int64_t n, const cx<R>* __restrict__ x, double* out, KState* ks,
+                                              double tol_rel, int mode, double2* partials, unsigned* counter) {
+  __shared__ double2 lds[RW][MMAX + 2];
+  const int64_t stride = (int64_t)gridDim.x * RB;
+  double2 acc = mk(0.0, 0.0);
+  for (int64_t e = (int64_t)blockIdx.x * RB + threadIdx.x; e < n; e += stride) acc.x += cabs2(to_d(x[e]));
+  wg_accumulate(lds, 0, acc);
+  __syncthreads();
+  if (threadIdx.x == 0) partials[blockIdx.x] = wg_result(lds, 0);
+  if (!last_block(counter)) return;
+  if (threadIdx.x == 0) {
+    double s2 = 0.0;
+    for (int b = 0; b < (int)gridDim.x; ++b) s2 += partials[b].x;
+    if (mode == 0) { out[0] = s2; return; }
+    const double beta = sqrt(s2);
+    if (mode == 2 || mode == 3) ks->bnorm = beta;
+    if (mode == 3) return;
+    ks->beta = beta;
+    ks->est = beta;
+    ks->tol_abs = tol_rel * ks->bnorm;
+    ks->steps = 0;
+    ks->nrot = 0;
+    ks->breakdown = 0;
+    ks->done = (beta == 0.0 || beta <= ks->tol_abs) ? 1 : 0;
+    for (int i = 0; i <= MMAX; ++i) { ks->g[i] = mk(0.0, 0.0); ks->c[i] = mk(0.0, 0.0); }
+    ks->g[0] = mk(beta, 0.0);
+    ks->c[0] = mk(beta, 0.0);
+  }
+}
+
+template <typename R>
+void launch_norm2(hipStream_t s, int64_t n, const cx<R>* x, double* out, double2* partials, unsigned* counter) {
+  hipLaunchKernelGGL(k_norm2<R>, dim3(red_blocks(n)), dim3(RB), 0, s, n, x, out, (KState*)nullptr, 0.0, 0, partials,
+                     counter);
+  DMG_LAUNCH_CHECK();
+}
+
+template <typename R>
+void launch_set_bnorm(hipStream_t s, int64_t n, const cx<R>* x, KState* ks, double2* partials, unsigned* counter) {
+  hipLaunchKernelGGL(k_norm2<R>, dim3(red_blocks(n)), dim3(RB), 0, s, n, x, (double*)nullptr, ks, 0.0, 3, partials,
+                     counter);
+  DMG_LAUNCH_CHECK();
+}
+
+// y = x / beta with beta = ks->beta (zero vector if beta == 0)
+template <typename R>
+__global__ void k_scale_beta(int64_t n, const cx<R>* __restrict__ x, cx<R>* __restrict__ y, const KState* ks) {
+  const double beta = ks->beta;
+  const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride)
+    y[e] = from_d<R>(cscale(to_d(x[e]), inv));
+}
+
+template <typename R>
+void launch_cycle_start(hipStream_t s, const cx<R>* r, cx<R>* V0, int64_t n, KState* ks, double tol_rel,
+                        int set_bnorm, double2* partials, unsigned* counter) {
+  hipLaunchKernelGGL(k_norm2<R>, dim3(red_blocks(n)), dim3(RB), 0, s, n, r, (double*)nullptr, ks, tol_rel,
+                     set_bnorm ? 2 : 1, partials, counter);
+  hipLaunchKernelGGL(k_scale_beta<R>, dim3(red_blocks(n)), dim3(RB), 0, s, n, r, V0, (const KState*)ks);
+  DMG_LAUNCH_CHECK();
+}
+
+// y = x * scale[0]  (invert_sqrt: y = x / sqrt(scale[0]))
+template <typename R>
+__global__ void k_scale_dev(int64_t n, const cx<R>* __restrict__ x, cx<R>* __restrict__ y, const double* scale,
+                            int invert_sqrt) {
+  double f = scale[0];
+  if (invert_sqrt) f = f > 0.0 ? 1.0 / sqrt(f) : 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride)
+    y[e] = from_d<R>(cscale(to_d(x[e]), f));
+}
+
+template <typename R>
+void launch_scale_dev(hipStream_t s, int64_t n, const cx<R>* x, cx<R>* y, const double* scale, int invert_sqrt) {
+  hipLaunchKernelGGL(k_scale_dev<R>, dim3(red_blocks(n)), dim3(RB), 0, s, n, x, y, scale, invert_sqrt);
+  DMG_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------- multi-dot / multi-axpy / basis rotation
+template <typename R>
+__global__ void __launch_bounds__(RB) k_multidot(const cx<R>* __restrict__ V, int64_t ld, int nv,
+                                                 const cx<R>* __restrict__ w, int64_t n, double2* out,
+                                                 double2* partials, unsigned* counter) {
+  __shared__ double2 lds[RW][MMAX + 2];
+  const int64_t stride = (int64_t)gridDim.x * RB;
+  const int64_t e0 = (int64_t)blockIdx.x * RB + threadIdx.x;
+  for (int i = 0; i < nv; ++i) {
+    const cx<R>* vi = V + (int64_t)i * ld;
+    double2 acc = mk(0.0, 0.0);
+    for (int64_t e = e0; e < n; e += stride) cfmac(acc, to_d(vi[e]), to_d(w[e]));
+    wg_accumulate(lds, i, acc);
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < nv; q += RB) partials[(int64_t)q * gridDim.x + blockIdx.x] = wg_result(lds, q);
+  if (!last_block(counter)) return;
+  for (int q = threadIdx.x; q < nv; q += RB) {
+    double2 r = mk(0.0, 0.0);
+    for (int b = 0; b < (int)gridDim.x; ++b) r = cadd(r, partials[(int64_t)q * gridDim.x + b]);
+    out[q] = r;
+  }
+}
+
+template <typename R>
+void launch_multidot(hipStream_t s, const cx<R>* V, int64_t ld, int nv, const cx<R>* w, int64_t n, double2* out,
+                     double2* partials, unsigned* counter) {
+  hipLaunchKernelGGL(k_multidot<R>, dim3(red_blocks(n)), dim3(RB), 0, s, V, ld, nv, w, n, out, partials, counter);
+  DMG_LAUNCH_CHECK();
+}
+
+template <typename R>
+__global__ void __launch_bounds__(RB) k_multi_axpy(cx<R>* __restrict__ w, const cx<R>* __restrict__ V, int64_t ld,
+                                                   int nv, const double2* coef_g, int64_t n, double sign) {
+  __shared__ double2 coef[MMAX + 2];
+  for (int i = threadIdx.x; i < nv; i += RB) coef[i] = cscale(coef_g[i], sign);
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * RB;
+  for (int64_t e = (int64_t)blockIdx.x * RB + threadIdx.x; e < n; e += stride) {
+    double2 acc = to_d(w[e]);
+    for (int i = 0; i < nv; ++i) acc = csub(acc, cmul(coef[i], to_d(V[(int64_t)i * ld + e])));
+    w[e] = from_d<R>(acc);
+  }
+}
+
+template <typename R>
+void launch_multi_axpy(hipStream_t s, cx<R>* w, const cx<R>* V, int64_t ld, int nv, const double2* coef, int64_t n,
+                       double sign) {
+  hipLaunchKernelGGL(k_multi_axpy<R>, dim3(red_blocks(n)), dim3(RB), 0, s, w, V, ld, nv, coef, n, sign);
+  DMG_LAUNCH_CHECK();
+}
+
+template <typename R>
+__global__ void __launch_bounds__(RB) k_basis_rotate(const cx<R>* __restrict__ Vin, cx<R>* __restrict__ Vout,
+                                                     int64_t ld, int64_t n, const double2* __restrict__ P, int ldp,
+                                                     int rows, int cols) {
+  const int64_t stride = (int64_t)gridDim.x * RB;
+  for (int64_t e = (int64_t)blockIdx.x * RB + threadIdx.x; e < n; e += stride) {
+    for (int jc = 0; jc < cols; ++jc) {
+      double2 acc = mk(0.0, 0.0);
+      for (int i = 0; i < rows; ++i) cfma(acc, P[i + (int64_t)ldp * jc], to_d(Vin[(int64_t)i * ld + e]));
+      Vout[(int64_t)jc * ld + e] = from_d<R>(acc);
+    }
+  }
+}
+
+template <typename R>
+void launch_basis_rotate(hipStream_t s, const cx<R>* Vin, cx<R>* Vout, int64_t ld, int64_t n, const double2* P,
+                         int ldp, int rows, int cols) {
+  hipLaunchKernelGGL(k_basis_rotate<R>, dim3(red_blocks(n)), dim3(RB), 0, s, Vin, Vout, ld, n, P, ldp, rows, cols);
+  DMG_LAUNCH_CHECK();
+}
+
+#define INST(R)                                                                                                     \
+  template void launch_arnoldi_orth<R>(hipStream_t, cx<R>*, int64_t, int64_t, int, KState*, double2*, unsigned*); \
+  template void launch_combine<R, R>(hipStream_t, cx<R>*, const cx<R>*, int64_t, int64_t, const KState*, int, int); \
+  template void launch_axpby<R>(hipStream_t, int64_t, double, const cx<R>*, double, cx<R>*);                       \
+  template void launch_xmy<R>(hipStream_t, int64_t, const cx<R>*, cx<R>*);                                         \
+  template void launch_norm2<R>(hipStream_t, int64_t, const cx<R>*, double*, double2*, unsigned*);                  \
+  template void launch_cycle_start<R>(hipStream_t, const cx<R>*, cx<R>*, int64_t, KState*, double, int, double2*,  \
+                                      unsigned*);                                                                   \
+  template void launch_set_bnorm<R>(hipStream_t, int64_t, const cx<R>*, KState*, double2*, unsigned*);              \
+  template void launch_multidot<R>(hipStream_t, const cx<R>*, int64_t, int, const cx<R>*, int64_t, double2*,       \
+                                   double2*, unsigned*);                                                            \
+  template void launch_multi_axpy<R>(hipStream_t, cx<R>*, const cx<R>*, int64_t, int, const double2*, int64_t,     \
+                                     double);                                                                       \
+  template void launch_basis_rotate<R>(hipStream_t, const cx<R>*, cx<R>*, int64_t, int64_t, const double2*, int,   \
+                                       int, int);                                                                   \
+  template void launch_scale_dev<R>(hipStream_t, int64_t, const cx<R>*, cx<R>*, const double*, int);
+INST(double)
+INST(float)
+#undef INST
+
+}  // namespace dmg

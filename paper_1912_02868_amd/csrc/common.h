@@ -1,0 +1,126 @@
+// Internal declarations shared by the HIP sources of libdmg (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/dmg.h"
+
+namespace dmg {
+
+// ---------------------------------------------------------------- complex types
+template <typename R> struct C2;
+template <> struct C2<double> { using T = double2; };
+template <> struct C2<float> { using T = float2; };
+template <typename R> using cx = typename C2<R>::T;
+
+__host__ __device__ inline double2 mk(double a, double b) { return make_double2(a, b); }
+__host__ __device__ inline float2 mkf(float a, float b) { return make_float2(a, b); }
+
+template <typename R> __host__ __device__ inline cx<R> make_cx(R a, R b) { cx<R> z; z.x = a; z.y = b; return z; }
+
+template <typename T> __host__ __device__ inline T cadd(T a, T b) { T z; z.x = a.x + b.x; z.y = a.y + b.y; return z; }
+template <typename T> __host__ __device__ inline T csub(T a, T b) { T z; z.x = a.x - b.x; z.y = a.y - b.y; return z; }
+template <typename T> __host__ __device__ inline T cmul(T a, T b) {
+  T z; z.x = a.x * b.x - a.y * b.y; z.y = a.x * b.y + a.y * b.x; return z;
+}
+// conj(a) * b
+template <typename T> __host__ __device__ inline T cmulc(T a, T b) {
+  T z; z.x = a.x * b.x + a.y * b.y; z.y = a.x * b.y - a.y * b.x; return z;
+}
+template <typename T> __host__ __device__ inline T cconj(T a) { T z; z.x = a.x; z.y = -a.y; return z; }
+template <typename T, typename S> __host__ __device__ inline T cscale(T a, S s) { T z; z.x = a.x * s; z.y = a.y * s; return z; }
+// acc += a * b
+template <typename T> __host__ __device__ inline void cfma(T& acc, T a, T b) {
+  acc.x = fma(a.x, b.x, acc.x); acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y); acc.y = fma(a.y, b.x, acc.y);
+}
+// acc += conj(a) * b
+template <typename T> __host__ __device__ inline void cfmac(T& acc, T a, T b) {
+  acc.x = fma(a.x, b.x, acc.x); acc.x = fma(a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y); acc.y = fma(-a.y, b.x, acc.y);
+}
+__host__ __device__ inline double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+__host__ __device__ inline double2 to_d(double2 a) { return a; }
+__host__ __device__ inline double2 to_d(float2 a) { return make_double2(a.x, a.y); }
+template <typename R> __host__ __device__ inline cx<R> from_d(double2 a) { return make_cx<R>((R)a.x, (R)a.y); }
+
+// ---------------------------------------------------------------- errors
+struct Error {
+  dmg_status code;
+  std::string msg;
+};
+
+#define DMG_HIP(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      throw ::dmg::Error{DMG_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define DMG_CHECK(cond, code, msg)                          \
+  do {                                                      \
+    if (!(cond)) throw ::dmg::Error{(code), std::string(msg)}; \
+  } while (0)
+
+#define DMG_LAUNCH_CHECK() DMG_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------- lattice constants
+constexpr int NC = 24;      // dof per blocked site
+constexpr int NV = 12;      // near-null vectors (per chirality)
+constexpr int BLK = 4;      // blocking factor per direction
+constexpr int MMAX = 64;    // largest Krylov cycle held by the small-dense state
+constexpr int ROTMAX = MMAX * (MMAX + 1) / 2 + 2 * MMAX;
+
+// Small-dense state of one Krylov cycle, resident in device memory (FP64).
+// Column-major (m + 1) x m Hessenberg: H[i + (MMAX + 1) * j].
+struct KState {
+  double2 H[(MMAX + 1) * MMAX];   // unrotated Arnoldi matrix
+  double2 R[(MMAX + 1) * MMAX];   // rotated (upper triangular) factor
+  double2 g[MMAX + 1];            // rotated right-hand side
+  double2 c[MMAX + 1];            // unrotated right-hand side
+  double2 y[MMAX + 1];            // least-squares solution / small work vector
+  double2 u[MMAX + 1];            // residual coordinates c - H y
+  double2 h2[MMAX + 1];           // scratch (second Gram-Schmidt pass)
+  double2 rot_s[ROTMAX];
+  double rot_c[ROTMAX];
+  int rot_p[ROTMAX];
+  int nrot;
+  int steps;                      // Arnoldi columns completed in this cycle
+  int done;                       // 1: stop (converged, breakdown or cap)
+  int breakdown;
+  double tol_abs;                 // stop when |g_{j+1}| <= tol_abs
+  double est;                     // current least-squares residual norm
+  double beta;                    // norm of the starting residual
+  double wn0;                     // ||A v_j|| before orthogonalisation
+  double bnorm;                   // ||b|| of the enclosing solve
+  double scratch[8];
+};
+
+}  // namespace dmg
+
+struct dmg_context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  dmg_allocator alloc{nullptr, nullptr, nullptr};
+  size_t budget = 0;
+  size_t in_use = 0;
+  std::string err;
+};
+
+namespace dmg {
+// Device memory through the context's allocator hooks, charged against its budget.
+void* dev_alloc(dmg_context* c, size_t bytes);
+void dev_free(dmg_context* c, void* p, size_t bytes);
+}  // namespace dmg
+
+struct dmg_gauge {
+  dmg_context* ctx = nullptr;
+  int Nx = 0, Nt = 0;
+  double2* U64 = nullptr;  // [t][x][mu], fermion sign folded in
+  float2* U32 = nullptr;
+};

@@ -1,0 +1,450 @@
+// Small dense FP64 work of the Krylov solvers, done on the device by one
+// workgroup: least-squares back-substitution, the GMRES-DR deflated restart
+// (harmonic Ritz eigenproblem, choice of the k smallest, new basis change and
+// Hbar_k), Givens QR of a full (k+1) x k block, and the GMRES-Proj projection.
+#include "kernels.h"
+
+namespace dmg {
+
+constexpr int LD = MMAX + 1;
+constexpr int DW = 64;  // threads of the dense kernels (one wavefront)
+
+__device__ inline double cabs_(double2 a) { return sqrt(cabs2(a)); }
+__device__ inline double2 cdiv(double2 a, double2 b) {
+  const double d = cabs2(b);
+  return mk((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+__device__ inline double2 csqrt_(double2 z) {
+  const double r = sqrt(sqrt(cabs2(z)));
+  const double th = 0.5 * atan2(z.y, z.x);
+  return mk(r * cos(th), r * sin(th));
+}
+
+// Givens rotation G = [c s; -conj(s) c] (c real) with G [a; b] = [r; 0].
+__device__ inline void make_givens(double2 a, double2 b, double& c, double2& s) {
+  const double na = cabs_(a), nb = cabs_(b);
+  if (nb == 0.0) { c = 1.0; s = mk(0.0, 0.0); return; }
+  if (na == 0.0) { c = 0.0; s = cscale(cconj(b), 1.0 / nb); return; }
+  const double nr = sqrt(na * na + nb * nb);
+  c = na / nr;
+  s = cscale(cmul(cconj(b), a), 1.0 / (na * nr));
+}
+
+// ---------------------------------------------------------------- least squares
+__global__ void k_ls_solve(KState* ks) {
+  if (threadIdx.x != 0) return;
+  const int n = ks->steps;
+  for (int i = n - 1; i >= 0; --i) {
+    double2 acc = ks->g[i];
+    for (int l = i + 1; l < n; ++l) acc = csub(acc, cmul(ks->R[i + LD * l], ks->y[l]));
+    const double2 d = ks->R[i + LD * i];
+    ks->y[i] = cabs2(d) > 0.0 ? cdiv(acc, d) : mk(0.0, 0.0);
+  }
+  for (int i = 0; i <= n; ++i) {
+    double2 acc = ks->c[i];
+    for (int l = 0; l < n; ++l) acc = csub(acc, cmul(ks->H[i + LD * l], ks->y[l]));
+    ks->u[i] = acc;
+  }
+}
+
+void launch_ls_solve(hipStream_t s, KState* ks) {
+  hipLaunchKernelGGL(k_ls_solve, dim3(1), dim3(1), 0, s, ks);
+  DMG_LAUNCH_CHECK();
+}
+
+// Givens QR of the leading (k+1) x k block of ks->H (full after a deflated restart):
+// rotations on adjacent rows, bottom-up in each column; rotated copy to ks->R, c -> g.
+__device__ void qr_block_serial(KState* ks, int k) {
+  for (int jc = 0; jc < k; ++jc)
+    for (int i = 0; i <= k; ++i) ks->R[i + LD * jc] = ks->H[i + LD * jc];
+  for (int i = 0; i <= MMAX; ++i) ks->g[i] = (i <= k) ? ks->c[i] : mk(0.0, 0.0);
+  ks->nrot = 0;
+  for (int jc = 0; jc < k; ++jc) {
+    for (int r = k; r > jc; --r) {
+      double c;
+      double2 s;
+      make_givens(ks->R[r - 1 + LD * jc], ks->R[r + LD * jc], c, s);
+      for (int q = jc; q < k; ++q) {
+        const double2 a = ks->R[r - 1 + LD * q], b = ks->R[r + LD * q];
+        ks->R[r - 1 + LD * q] = cadd(cscale(a, c), cmul(s, b));
+        ks->R[r + LD * q] = csub(cscale(b, c), cmul(cconj(s), a));
+      }
+      ks->R[r + LD * jc] = mk(0.0, 0.0);
+      const double2 a = ks->g[r - 1], b = ks->g[r];
+      ks->g[r - 1] = cadd(cscale(a, c), cmul(s, b));
+      ks->g[r] = csub(cscale(b, c), cmul(cconj(s), a));
+      const int q = ks->nrot++;
+      ks->rot_p[q] = r - 1;
+      ks->rot_c[q] = c;
+      ks->rot_s[q] = s;
+    }
+  }
+  ks->est = cabs_(ks->g[k]);
+}
+
+__global__ void k_qr_block(KState* ks, int k) {
+  if (threadIdx.x == 0) qr_block_serial(ks, k);
+}
+
+void launch_qr_block(hipStream_t s, KState* ks, int k) {
+  hipLaunchKernelGGL(k_qr_block, dim3(1), dim3(1), 0, s, ks, k);
+  DMG_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------- GMRES-Proj projection
+// d = argmin || c - Hk d ||, Hk (k+1) x k column-major with ld k+1; y = d, u = Hk d.
+__global__ void k_proj_solve(const double2* Hk, int k, KState* ks) {
+  if (threadIdx.x != 0) return;
+  // work copy into R/g using the block QR
+  for (int jc = 0; jc < k; ++jc)
+    for (int i = 0; i <= k; ++i) ks->H[i + LD * jc] = Hk[i + (k + 1) * jc];
+  qr_block_serial(ks, k);
+  for (int i = k - 1; i >= 0; --i) {
+    double2 acc = ks->g[i];
+    for (int l = i + 1; l < k; ++l) acc = csub(acc, cmul(ks->R[i + LD * l], ks->y[l]));
+    const double2 d = ks->R[i + LD * i];
+    ks->y[i] = cabs2(d) > 0.0 ? cdiv(acc, d) : mk(0.0, 0.0);
+  }
+  for (int i = 0; i <= k; ++i) {
+    double2 acc = mk(0.0, 0.0);
+    for (int l = 0; l < k; ++l) acc = cadd(acc, cmul(Hk[i + (k + 1) * l], ks->y[l]));
+    ks->u[i] = acc;
+  }
+  ks->steps = k;
+}
+
+void launch_proj_solve(hipStream_t s, const double2* Hk, int k, KState* ks) {
+  hipLaunchKernelGGL(k_proj_solve, dim3(1), dim3(1), 0, s, Hk, k, ks);
+  DMG_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------- eigenproblem helpers
+// All routines run on one wavefront (DW threads) with matrices column-major in LDS:
+// A[i + n * j].
+
+// Hessenberg reduction by Householder reflections, accumulating X (A_orig = X A X^H).
+__device__ void hessenberg(double2* A, double2* X, double2* v, int n) {
+  const int t = threadIdx.x;
+  for (int e = t; e < n * n; e += DW) X[e] = ((e % n) == (e / n)) ? mk(1.0, 0.0) : mk(0.0, 0.0);
+  __syncthreads();
+  for (int col = 0; col + 2 < n; ++col) {
+    // x = A[col+1 .. n-1, col]
+    double xn2 = 0.0;
+    for (int i = col + 2; i < n; ++i) xn2 += cabs2(A[i + n * col]);
+    if (xn2 == 0.0) { __syncthreads(); continue; }
+    const double2 alpha = A[col + 1 + n * col];
+    const double anorm = cabs_(alpha);
+    const double xnorm = sqrt(xn2 + anorm * anorm);
+    const double2 ph = anorm > 0.0 ? cscale(alpha, 1.0 / anorm) : mk(1.0, 0.0);
+    const double2 beta = cscale(ph, -xnorm);
+    // v = x - beta e1 (indices col+1 .. n-1 stored at v[0 .. n-col-2])
+    const int len = n - col - 1;
+    for (int i = t; i < len; i += DW) v[i] = (i == 0) ? csub(alpha, beta) : A[col + 1 + i + n * col];
+    __syncthreads();
+    double vv = 0.0;
+    for (int i = 0; i < len; ++i) vv += cabs2(v[i]);
+    const double f = 2.0 / vv;
+    // left: A[col+1:, j] -= f v (v^H A[col+1:, j]) for all columns j
+    for (int jc = t; jc < n; jc += DW) {
+      double2 d = mk(0.0, 0.0);
+      for (int i = 0; i < len; ++i) cfmac(d, v[i], A[col + 1 + i + n * jc]);
+      d = cscale(d, f);
+      for (int i = 0; i < len; ++i) A[col + 1 + i + n * jc] = csub(A[col + 1 + i + n * jc], cmul(v[i], d));
+    }
+    __syncthreads();
+    // right: A[i, col+1:] -= f (A[i, col+1:] v) v^H for all rows; same for X
+    for (int r = t; r < 2 * n; r += DW) {
+      double2* M = (r < n) ? A : X;
+      const int i = (r < n) ? r : r - n;
+      double2 d = mk(0.0, 0.0);
+      for (int l = 0; l < len; ++l) cfma(d, M[i + n * (col + 1 + l)], v[l]);
+      d = cscale(d, f);
+      for (int l = 0; l < len; ++l)
+        M[i + n * (col + 1 + l)] = csub(M[i + n * (col + 1 + l)], cmul(d, cconj(v[l])));
+    }
+    __syncthreads();
+    if (t == 0)
+      for (int i = col + 2; i < n; ++i) A[i + n * col] = mk(0.0, 0.0);
+    __syncthreads();
+  }
+}
+
+// Complex Schur form of the Hessenberg A by single-shift implicit QR (Wilkinson shifts,
+// exceptional shifts every 10 iterations).  Returns 0 on success.
+__device__ int schur_qr(double2* A, double2* X, int n, int* flag_sh) {
+  const int t = threadIdx.x;
+  const double eps = 2.220446049250313e-16;
+  int hi = n - 1, iter = 0, total = 0;
+  while (hi > 0) {
+    // locate the active block [lo, hi]
+    int lo = hi;
+    while (lo > 0) {
+      double sc = cabs_(A[lo - 1 + n * (lo - 1)]) + cabs_(A[lo + n * lo]);
+      if (sc == 0.0) sc = 1.0;
+      if (cabs_(A[lo + n * (lo - 1)]) <= eps * sc) break;
+      --lo;
+    }
+    __syncthreads();
+    if (lo > 0 && t == 0) A[lo + n * (lo - 1)] = mk(0.0, 0.0);
+    __syncthreads();
+    if (lo == hi) { --hi; iter = 0; continue; }
+    if (++total > 60 * n) return 1;
+    ++iter;
+    // shift
+    const double2 a = A[hi - 1 + n * (hi - 1)], b = A[hi - 1 + n * hi], c = A[hi + n * (hi - 1)], d = A[hi + n * hi];
+    double2 mu;
+    if (iter % 11 == 10) {
+      mu = cadd(d, mk(cabs_(c), 0.0));
+    } else {
+      const double2 hm = cscale(csub(a, d), 0.5);
+      const double2 disc = csqrt_(cadd(cmul(hm, hm), cmul(b, c)));
+      const double2 m0 = cscale(cadd(a, d), 0.5);
+      const double2 m1 = cadd(m0, disc), m2 = csub(m0, disc);
+      mu = (cabs_(csub(m1, d)) <= cabs_(csub(m2, d))) ? m1 : m2;
+    }
+    double2 x = csub(A[lo + n * lo], mu), y = A[lo + 1 + n * lo];
+    for (int k = lo; k < hi; ++k) {
+      double cg;
+      double2 sg;
+      make_givens(x, y, cg, sg);
+      __syncthreads();
+      // left: rows k, k+1, columns from max(lo, k-1) .. n-1
+      const int c0 = (k > lo) ? k - 1 : lo;
+      for (int jc = c0 + t; jc < n; jc += DW) {
+        const double2 p = A[k + n * jc], q = A[k + 1 + n * jc];
+        A[k + n * jc] = cadd(cscale(p, cg), cmul(sg, q));
+        A[k + 1 + n * jc] = csub(cscale(q, cg), cmul(cconj(sg), p));
+      }
+      __syncthreads();
+      // right: columns k, k+1 by G^H, rows 0 .. min(k+2, hi); and X (all rows)
+      const int r1 = (k + 2 < hi) ? k + 2 : hi;
+      for (int rr = t; rr < (r1 + 1) + n; rr += DW) {
+        double2* M = (rr <= r1) ? A : X;
+        const int i = (rr <= r1) ? rr : rr - (r1 + 1);
+        const double2 p = M[i + n * k], q = M[i + n * (k + 1)];
+        M[i + n * k] = cadd(cscale(p, cg), cmul(q, cconj(sg)));
+        M[i + n * (k + 1)] = csub(cscale(q, cg), cmul(p, sg));
+      }
+      __syncthreads();
+      if (k + 1 < hi) {
+        x = A[k + 1 + n * k];
+        y = A[k + 2 + n * k];
+      }
+    }
+    __syncthreads();
+  }
+  (void)flag_sh;
+  return 0;
+}
+
+// ---------------------------------------------------------------- GMRES-DR deflated restart
+// Inputs in ks: H ((m+1) x m, unrotated), c, u = c - H d (the residual coordinates s).
+// Scratch: work (global) of at least (3 m m + 4 (m+1)(k+1) + 8 m + 64) double2.
+// Output: P ((m+1) x (k+1), ld m+1) in Pout; ks->H <- Hbar_k, ks->c <- P^H s, rotations
+// reset for the full block (unless final_mode), steps = k.
+__global__ void __launch_bounds__(DW) k_dr_restart(KState* ks, int m, int k, double2* Pout, int final_mode,
+                                                   double2* work, int* status) {
+  extern __shared__ double2 sh[];
+  const int t = threadIdx.x;
+  double2* A = sh;              // m x m
+  double2* X = sh + m * m;      // m x m
+  double2* v = sh + 2 * m * m;  // m + 1
+  double2* Hb = work;                        // (m+1) x m copy of Hbar
+  double2* W = Hb + (m + 1) * m;             // (m+1) x (k+1)
+  double2* T1 = W + (m + 1) * (k + 1);       // (m+1) x k
+  double2* f = T1 + (m + 1) * k;             // m
+  double2* s = f + m;                        // m + 1
+  double2* theta = s + m + 1;                // m
+  int* sel = (int*)(theta + m);              // k ints (fits in m double2)
+  __shared__ int fail;
+  if (t == 0) fail = 0;
+  for (int e = t; e < (m + 1) * m; e += DW) Hb[e] = ks->H[(e % (m + 1)) + LD * (e / (m + 1))];
+  for (int i = t; i <= m; i += DW) s[i] = ks->u[i];
+  __syncthreads();
+  const double h = Hb[m + (m + 1) * (m - 1)].x;  // h_{m+1,m}, real >= 0
+
+  // f = H^{-H} e_m : Gaussian elimination with partial pivoting on M = H^H (in A), rhs in v
+  for (int e = t; e < m * m; e += DW) {
+    const int i = e % m, j = e / m;
+    A[e] = cconj(Hb[j + (m + 1) * i]);
+  }
+  for (int i = t; i < m; i += DW) v[i] = (i == m - 1) ? mk(1.0, 0.0) : mk(0.0, 0.0);
+  __syncthreads();
+  for (int p = 0; p < m; ++p) {
+    __shared__ int piv;
+    if (t == 0) {
+      int best = p;
+      double bv = cabs_(A[p + m * p]);
+      for (int i = p + 1; i < m; ++i) {
+        const double a = cabs_(A[i + m * p]);
+        if (a > bv) { bv = a; best = i; }
+      }
+      piv = best;
+      if (bv == 0.0) fail = 1;
+    }
+    __syncthreads();
+    if (fail) break;
+    if (piv != p) {
+      for (int jc = t; jc < m; jc += DW) {
+        const double2 tmp = A[p + m * jc];
+        A[p + m * jc] = A[piv + m * jc];
+        A[piv + m * jc] = tmp;
+      }
+      if (t == 0) { const double2 tmp = v[p]; v[p] = v[piv]; v[piv] = tmp; }
+    }
+    __syncthreads();
+    const double2 dp = A[p + m * p];
+    for (int i = p + 1 + t; i < m; i += DW) {
+      const double2 fct = cdiv(A[i + m * p], dp);
+      for (int jc = p; jc < m; ++jc) A[i + m * jc] = csub(A[i + m * jc], cmul(fct, A[p + m * jc]));
+      v[i] = csub(v[i], cmul(fct, v[p]));
+    }
+    __syncthreads();
+  }
+  if (fail) { if (t == 0) *status = 2; return; }
+  if (t == 0) {
+    for (int i = m - 1; i >= 0; --i) {
+      double2 acc = v[i];
+      for (int l = i + 1; l < m; ++l) acc = csub(acc, cmul(A[i + m * l], f[l]));
+      f[i] = cdiv(acc, A[i + m * i]);
+    }
+  }
+  __syncthreads();
+  // G = H + |h|^2 f e_m^T into A
+  for (int e = t; e < m * m; e += DW) {
+    const int i = e % m, j = e / m;
+    double2 g = Hb[i + (m + 1) * j];
+    if (j == m - 1) g = cadd(g, cscale(f[i], h * h));
+    A[e] = g;
+  }
+  __syncthreads();
+  hessenberg(A, X, v, m);
+  if (schur_qr(A, X, m, nullptr)) { if (t == 0) *status = 3; return; }
+  __syncthreads();
+  // eigenvalues and the order: key (round(|theta| / max|theta|, 12), Im theta, index)
+  for (int i = t; i < m; i += DW) theta[i] = A[i + m * i];
+  __syncthreads();
+  double mx = 0.0;
+  for (int i = 0; i < m; ++i) mx = fmax(mx, cabs_(theta[i]));
+  if (mx == 0.0) mx = 1e-300;
+  for (int e = t; e < m; e += DW) {
+    const double ke = rint(cabs_(theta[e]) / mx * 1e12);
+    int rank = 0;
+    for (int o = 0; o < m; ++o) {
+      if (o == e) continue;
+      const double ko = rint(cabs_(theta[o]) / mx * 1e12);
+      const bool less = (ko < ke) || (ko == ke && (theta[o].y < theta[e].y || (theta[o].y == theta[e].y && o < e)));
+      rank += less ? 1 : 0;
+    }
+    if (rank < k) sel[rank] = e;
+  }
+  __syncthreads();
+  // eigenvectors of the triangular T = A for the selected values, into T1 columns (length m)
+  double tn = 0.0;
+  for (int e = 0; e < m * m; ++e) tn += cabs2(A[e]);
+  const double smin = fmax(sqrt(tn) * 2.220446049250313e-16, 1e-300);
+  for (int q = t; q < k; q += DW) {
+    const int e = sel[q];
+    double2* y = T1 + (m + 1) * q;
+    for (int i = 0; i < m; ++i) y[i] = mk(0.0, 0.0);
+    y[e] = mk(1.0, 0.0);
+    const double2 lam = A[e + m * e];
+    for (int i = e - 1; i >= 0; --i) {
+      double2 acc = mk(0.0, 0.0);
+      for (int l = i + 1; l <= e; ++l) cfma(acc, A[i + m * l], y[l]);
+      double2 den = csub(A[i + m * i], lam);
+      if (cabs_(den) < smin) den = mk(smin, 0.0);
+      y[i] = cscale(cdiv(acc, den), -1.0);
+    }
+  }
+  __syncthreads();
+  // W[:, q] = [X y_q ; 0]
+  for (int e = t; e < (m + 1) * k; e += DW) {
+    const int i = e % (m + 1), q = e / (m + 1);
+    double2 acc = mk(0.0, 0.0);
+    if (i < m)
+      for (int l = 0; l < m; ++l) cfma(acc, X[i + m * l], T1[l + (m + 1) * q]);
+    W[i + (m + 1) * q] = acc;
+  }
+  // last column: s (restart) or the harmonic residual direction [-|h|^2 f; h] (final)
+  for (int i = t; i <= m; i += DW) {
+    double2 w;
+    if (final_mode) w = (i < m) ? cscale(f[i], -h * h) : mk(h, 0.0);
+    else w = s[i];
+    W[i + (m + 1) * k] = w;
+  }
+  __syncthreads();
+  // orthonormalise the k+1 columns (modified Gram-Schmidt, two passes), lanes over rows
+  for (int q = 0; q <= k; ++q) {
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int p = 0; p < q; ++p) {
+        __shared__ double2 red[DW];
+        double2 acc = mk(0.0, 0.0);
+        for (int i = t; i <= m; i += DW) cfmac(acc, W[i + (m + 1) * p], W[i + (m + 1) * q]);
+        red[t] = acc;
+        __syncthreads();
+        double2 dot = mk(0.0, 0.0);
+        for (int l = 0; l < DW; ++l) dot = cadd(dot, red[l]);
+        __syncthreads();
+        for (int i = t; i <= m; i += DW) W[i + (m + 1) * q] = csub(W[i + (m + 1) * q], cmul(dot, W[i + (m + 1) * p]));
+        __syncthreads();
+      }
+    }
+    __shared__ double2 red2[DW];
+    double nn = 0.0;
+    for (int i = t; i <= m; i += DW) nn += cabs2(W[i + (m + 1) * q]);
+    red2[t] = mk(nn, 0.0);
+    __syncthreads();
+    double tot = 0.0;
+    for (int l = 0; l < DW; ++l) tot += red2[l].x;
+    __syncthreads();
+    if (!(tot > 0.0)) { if (t == 0) *status = 4; return; }
+    const double inv = 1.0 / sqrt(tot);
+    for (int i = t; i <= m; i += DW) W[i + (m + 1) * q] = cscale(W[i + (m + 1) * q], inv);
+    __syncthreads();
+  }
+  // T1 = Hbar P_k  ((m+1) x k); Hk = P^H T1 ((k+1) x k); c_new = P^H s
+  for (int e = t; e < (m + 1) * k; e += DW) {
+    const int i = e % (m + 1), q = e / (m + 1);
+    double2 acc = mk(0.0, 0.0);
+    for (int l = 0; l < m; ++l) cfma(acc, Hb[i + (m + 1) * l], W[l + (m + 1) * q]);
+    T1[e] = acc;
+  }
+  __syncthreads();
+  for (int e = t; e < LD * MMAX; e += DW) ks->H[e] = mk(0.0, 0.0);
+  __syncthreads();
+  for (int e = t; e < (k + 1) * k; e += DW) {
+    const int i = e % (k + 1), q = e / (k + 1);
+    double2 acc = mk(0.0, 0.0);
+    for (int l = 0; l <= m; ++l) cfmac(acc, W[l + (m + 1) * i], T1[l + (m + 1) * q]);
+    ks->H[i + LD * q] = acc;
+  }
+  for (int i = t; i <= MMAX; i += DW) {
+    double2 acc = mk(0.0, 0.0);
+    if (i <= k)
+      for (int l = 0; l <= m; ++l) cfmac(acc, W[l + (m + 1) * i], s[l]);
+    ks->c[i] = acc;
+  }
+  for (int e = t; e < (m + 1) * (k + 1); e += DW) Pout[e] = W[e];
+  __syncthreads();
+  if (t == 0) {
+    if (!final_mode) qr_block_serial(ks, k);
+    ks->steps = k;
+    ks->done = 0;
+    ks->breakdown = 0;
+    *status = 0;
+  }
+}
+
+size_t dr_work_elems(int m, int k) {
+  return (size_t)(m + 1) * m + 2 * (size_t)(m + 1) * (k + 1) + (size_t)(m + 1) * k + 4 * (size_t)m + 64;
+}
+
+void launch_dr_restart(hipStream_t st, KState* ks, int m, int k, double2* Pout, int final_mode, double2* work,
+                            int* status) {
+  const size_t shm = (size_t)(2 * m * m + m + 2) * sizeof(double2);
+  hipLaunchKernelGGL(k_dr_restart, dim3(1), dim3(DW), shm, st, ks, m, k, Pout, final_mode, work, status);
+  DMG_LAUNCH_CHECK();
+}
+
+}  // namespace dmg

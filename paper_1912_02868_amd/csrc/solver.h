@@ -1,0 +1,124 @@
+// Multigrid hierarchy, deflation space and Krylov solvers of libdmg (host
+// orchestration of the device kernels).
+#pragma once
+
+#include <memory>
+
+#include "kernels.h"
+
+namespace dmg {
+
+// Device memory owned through the context (allocator hooks + budget).
+struct DevBuf {
+  dmg_context* ctx = nullptr;
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void alloc(dmg_context* c, size_t b);
+  void release();
+  template <typename T> T* as() const { return (T*)p; }
+};
+
+// One level's operator: the fine Wilson-Dirac stencil or a 24-dof block stencil.
+struct Op {
+  int kind = 0;  // 0 Wilson, 1 block stencil
+  int Lx = 0, Lt = 0;
+  int64_t n = 0;  // complex entries of one field
+  const double2* U64 = nullptr;
+  const float2* U32 = nullptr;
+  double m0 = 0.0;
+  const double2* A64 = nullptr;
+  const float2* A32 = nullptr;
+  void apply(hipStream_t s, const double2* in, double2* out, int dag, const int* skip) const {
+    if (kind == 0) launch_wilson<double>(s, U64, in, out, m0, Lx, Lt, dag, 1, skip);
+    else launch_block_apply<double>(s, A64, in, out, Lx, Lt, dag, skip);
+  }
+  void apply(hipStream_t s, const float2* in, float2* out, int dag, const int* skip) const {
+    if (kind == 0) launch_wilson<float>(s, U32, in, out, m0, Lx, Lt, dag, 1, skip);
+    else launch_block_apply<float>(s, A32, in, out, Lx, Lt, dag, skip);
+  }
+};
+
+struct Transfer {  // P from level l (Lx x Lt sites, dof per site) to level l + 1
+  int Lx = 0, Lt = 0, dof = 0;
+  const double2* P64 = nullptr;
+  const float2* P32 = nullptr;
+  const double2* P(const double2*) const { return P64; }
+  const float2* P(const float2*) const { return P32; }
+};
+
+// Status fields of a KState read back to the host (layout of KState's tail).
+struct KStatus {
+  int nrot, steps, done, breakdown;
+  double tol_abs, est, beta, wn0, bnorm;
+};
+
+// Krylov workspace: basis V (m + 1 fields), optional Z (m fields), small-dense state.
+struct KWS {
+  int m = 0;
+  int64_t n = 0;
+  DevBuf V, Z, ks;
+  void alloc(dmg_context* c, int m_, int64_t n_, size_t esize, bool flexible);
+  KState* state() const { return ks.as<KState>(); }
+};
+
+struct Counters {
+  long long mv[3] = {0, 0, 0};
+  int coarse_calls = 0, dr_calls = 0;
+};
+
+template <typename R> struct Precond;
+
+}  // namespace dmg
+
+struct dmg_deflation {
+  dmg_hierarchy* h = nullptr;
+  int m = 30, k = 10;
+  int kk = 0;      // vectors actually stored (k, or the whole Krylov space if shorter)
+  int ready = 0;
+  int cast_ready = 0;  // FP32 copy of V up to date
+  dmg::DevBuf V64, V32, H;  // V: n_c x (kk + 1); H: (kk + 1) x kk column-major, ld kk + 1
+};
+
+struct dmg_hierarchy {
+  dmg_context* ctx = nullptr;
+  const dmg_gauge* g = nullptr;
+  double m0 = 0.0;
+  dmg_setup_params prm{};
+  dmg::Op op[3];
+  dmg::Transfer tr[2];
+  dmg::DevBuf A64[3], A32[3], P64[2], P32[2], null[2];
+  int setup_iters[2][64] = {};
+  // reduction scratch, small device flags, host mirror
+  dmg::DevBuf partials, counters, flags;
+  dmg::KStatus* host_status = nullptr;  // pinned
+  // GMRES-DR workspace (FP64)
+  dmg::KWS dr;
+  dmg::DevBuf dr_Vtmp, dr_P, dr_work, dr_coef;
+  int dr_m = 0, dr_k = 0;
+  // outer FGMRES (FP64)
+  dmg::KWS outer;
+  dmg::DevBuf ob, ox, or_, oz32, ov32, bn2;
+  std::unique_ptr<dmg::Precond<double>> pc64;
+  std::unique_ptr<dmg::Precond<float>> pc32;
+  dmg::Counters cnt;
+  dmg_hierarchy();
+  ~dmg_hierarchy();
+};
+
+namespace dmg {
+
+// setup (near-null vectors, prolongators, Galerkin operators)
+void build_hierarchy(dmg_hierarchy* h, const double2* start0, const double2* start1, int inject);
+// GMRES-DR on the coarse operator in FP64 from x = 0; fills the deflation space.
+// Returns the Arnoldi steps taken.
+int coarse_gmres_dr(dmg_hierarchy* h, dmg_deflation* d, const double2* b, double2* x, double tol, int max_iters);
+// outer solve of one right-hand side (device buffers b, x; x holds x0 when use_x0)
+dmg_status outer_solve(dmg_hierarchy* h, dmg_deflation* d, const dmg_solve_params* p, const double2* b, double2* x,
+                       dmg_solve_stats* st);
+void sync_status(dmg_hierarchy* h, const KState* ks, KStatus* out);
+
+}  // namespace dmg

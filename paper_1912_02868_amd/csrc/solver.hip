@@ -1,0 +1,670 @@
+// Host orchestration of the deflated three-grid solve (Methods section):
+// hierarchy setup, the GMRES(2) smoother, the intermediate and fine cycles, the
+// partial intermediate solve, the deflated coarse solve (GMRES-DR, then
+// GMRES-Proj), and the outer FP64 FGMRES(8).  All arithmetic runs in the device
+// kernels; the host only enqueues them and reads back the few scalars that
+// decide control flow (one status read per Arnoldi step of the outer and
+// intermediate solves, one per cycle of the coarse solves).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "solver.h"
+
+namespace dmg {
+
+static_assert(offsetof(KState, steps) == offsetof(KState, nrot) + 4, "KState tail layout");
+static_assert(offsetof(KState, tol_abs) == offsetof(KState, nrot) + 16, "KState tail layout");
+static_assert(offsetof(KState, bnorm) == offsetof(KState, nrot) + offsetof(KStatus, bnorm), "KState tail layout");
+
+void DevBuf::alloc(dmg_context* c, size_t b) {
+  release();
+  ctx = c;
+  p = dev_alloc(c, b);
+  bytes = b;
+}
+void DevBuf::release() {
+  if (p) dev_free(ctx, p, bytes);
+  p = nullptr;
+  bytes = 0;
+}
+
+void KWS::alloc(dmg_context* c, int m_, int64_t n_, size_t esize, bool flexible) {
+  m = m_;
+  n = n_;
+  V.alloc(c, esize * (size_t)n * (m + 1));
+  if (flexible) Z.alloc(c, esize * (size_t)n * m);
+  ks.alloc(c, sizeof(KState));
+  DMG_HIP(hipMemsetAsync(ks.p, 0, sizeof(KState), c->stream));
+}
+
+void sync_status(dmg_hierarchy* h, const KState* ks, KStatus* out) {
+  hipStream_t s = h->ctx->stream;
+  DMG_HIP(hipMemcpyAsync(h->host_status, &ks->nrot, sizeof(KStatus), hipMemcpyDeviceToHost, s));
+  DMG_HIP(hipStreamSynchronize(s));
+  *out = *h->host_status;
+}
+
+static double read_double(dmg_hierarchy* h, const double* p) {
+  hipStream_t s = h->ctx->stream;
+  DMG_HIP(hipMemcpyAsync(h->host_status, p, sizeof(double), hipMemcpyDeviceToHost, s));
+  DMG_HIP(hipStreamSynchronize(s));
+  double v;
+  std::memcpy(&v, h->host_status, sizeof(double));
+  return v;
+}
+
+static double2* PART(dmg_hierarchy* h) { return h->partials.as<double2>(); }
+static unsigned* CNT(dmg_hierarchy* h) { return h->counters.as<unsigned>(); }
+
+// ---------------------------------------------------------------- coarse GMRES-DR (FP64)
+static void ensure_dr(dmg_hierarchy* h, int m, int k) {
+  if (h->dr_m == m && h->dr_k == k && h->dr.V.p) return;
+  const int64_t n = h->op[2].n;
+  h->dr.alloc(h->ctx, m, n, sizeof(double2), false);
+  h->dr_Vtmp.alloc(h->ctx, sizeof(double2) * (size_t)n * (k + 1));
+  h->dr_P.alloc(h->ctx, sizeof(double2) * (size_t)(m + 1) * (k + 1));
+  h->dr_work.alloc(h->ctx, sizeof(double2) * dr_work_elems(m, k));
+  h->dr_coef.alloc(h->ctx, sizeof(double2) * (MMAX + 2));
+  h->dr_m = m;
+  h->dr_k = k;
+}
+
+static void check_dr_status(dmg_hierarchy* h) {
+  int st = 0;
+  DMG_HIP(hipMemcpyAsync(&st, h->flags.as<int>(), sizeof(int), hipMemcpyDeviceToHost, h->ctx->stream));
+  DMG_HIP(hipStreamSynchronize(h->ctx->stream));
+  DMG_CHECK(st == 0, DMG_E_BREAKDOWN, "GMRES-DR restart failed (singular Hessenberg or eigenvalue iteration)");
+}
+
+int coarse_gmres_dr(dmg_hierarchy* h, dmg_deflation* d, const double2* b, double2* x, double tol, int max_iters) {
+  const int m = d->m, k = d->k;
+  DMG_CHECK(m <= MMAX && k >= 1 && k < m, DMG_E_INVALID, "GMRES-DR sizes");
+  ensure_dr(h, m, k);
+  hipStream_t s = h->ctx->stream;
+  const Op& A = h->op[2];
+  const int64_t n = A.n;
+  KState* ks = h->dr.state();
+  double2* V = h->dr.V.as<double2>();
+  int* status = h->flags.as<int>();
+  DMG_HIP(hipMemsetAsync(status, 0, sizeof(int), s));
+  DMG_HIP(hipMemsetAsync(x, 0, sizeof(double2) * n, s));
+  launch_cycle_start<double>(s, b, V, n, ks, tol, 1, PART(h), CNT(h));
+  int j0 = 0, iters = 0;
+  KStatus st{};
+  for (;;) {
+    for (int j = j0; j < m; ++j) {
+      A.apply(s, V + (int64_t)j * n, V + (int64_t)(j + 1) * n, 0, &ks->done);
+      launch_arnoldi_orth<double>(s, V, n, n, j, ks, PART(h), CNT(h));
+    }
+    launch_ls_solve(s, ks);
+    launch_combine<double, double>(s, x, V, n, n, ks, 0, 1);
+    sync_status(h, ks, &st);
+    iters += st.steps - j0;
+    h->cnt.mv[2] += st.steps - j0;
+    if (st.done || iters >= max_iters) break;
+    // deflated restart: keep the k smallest harmonic Ritz vectors and the residual
+    launch_dr_restart(s, ks, m, k, h->dr_P.as<double2>(), 0, h->dr_work.as<double2>(), status);
+    launch_basis_rotate<double>(s, V, h->dr_Vtmp.as<double2>(), n, n, h->dr_P.as<double2>(), m + 1, m + 1, k + 1);
+    DMG_HIP(hipMemcpyAsync(V, h->dr_Vtmp.p, sizeof(double2) * n * (k + 1), hipMemcpyDeviceToDevice, s));
+    // re-orthogonalise v_{k+1} against v_1 .. v_k
+    double2* coef = h->dr_coef.as<double2>();
+    launch_multidot<double>(s, V, n, k, V + (int64_t)k * n, n, coef, PART(h), CNT(h));
+    launch_multi_axpy<double>(s, V + (int64_t)k * n, V, n, k, coef, n, 1.0);
+    launch_norm2<double>(s, n, V + (int64_t)k * n, (double*)(coef + MMAX), PART(h), CNT(h));
+    launch_scale_dev<double>(s, n, V + (int64_t)k * n, V + (int64_t)k * n, (const double*)(coef + MMAX), 1);
+    j0 = k;
+  }
+  check_dr_status(h);
+  // store the deflation space A V_k = V_{k+1} Hbar_k
+  const int cols = st.steps;
+  if (cols > k && !st.breakdown) {
+    launch_dr_restart(s, ks, cols, k, h->dr_P.as<double2>(), 1, h->dr_work.as<double2>(), status);
+    d->V64.alloc(h->ctx, sizeof(double2) * (size_t)n * (k + 1));
+    d->H.alloc(h->ctx, sizeof(double2) * (size_t)(k + 1) * k);
+    launch_basis_rotate<double>(s, V, d->V64.as<double2>(), n, n, h->dr_P.as<double2>(), cols + 1, cols + 1, k + 1);
+    DMG_HIP(hipMemcpy2DAsync(d->H.p, sizeof(double2) * (k + 1), ks->H, sizeof(double2) * (MMAX + 1),
+                             sizeof(double2) * (k + 1), k, hipMemcpyDeviceToDevice, s));
+    d->kk = k;
+    check_dr_status(h);
+  } else {
+    const int kk = std::max(cols, 1);
+    d->V64.alloc(h->ctx, sizeof(double2) * (size_t)n * (kk + 1));
+    d->H.alloc(h->ctx, sizeof(double2) * (size_t)(kk + 1) * kk);
+    DMG_HIP(hipMemcpyAsync(d->V64.p, V, sizeof(double2) * n * (kk + 1), hipMemcpyDeviceToDevice, s));
+    DMG_HIP(hipMemcpy2DAsync(d->H.p, sizeof(double2) * (kk + 1), ks->H, sizeof(double2) * (MMAX + 1),
+                             sizeof(double2) * (kk + 1), kk, hipMemcpyDeviceToDevice, s));
+    d->kk = kk;
+  }
+  d->ready = 1;
+  d->cast_ready = 0;
+  h->cnt.dr_calls++;
+  return iters;
+}
+
+// ---------------------------------------------------------------- batched CG on A A^dagger (FP64)
+// x_f = argmin for A A^dagger x_f = b_f, f < nvec, each stopping at ||r_f|| <= tol ||b_f||.
+static void cg_normal(dmg_hierarchy* h, int lvl, int nvec, const double2* b, double2* x, double tol, int max_iters,
+                      int* iters_host) {
+  hipStream_t s = h->ctx->stream;
+  const Op& A = h->op[lvl];
+  const int64_t n = A.n;
+  const size_t fb = sizeof(double2) * (size_t)n * nvec;
+  DevBuf r, p, q, t, sc;
+  r.alloc(h->ctx, fb);
+  p.alloc(h->ctx, fb);
+  q.alloc(h->ctx, fb);
+  t.alloc(h->ctx, fb);
+  // scalars: pq[2 nvec], rrn[2 nvec], rr[nvec], alpha, beta, b2 (doubles); active, iters (ints)
+  sc.alloc(h->ctx, sizeof(double) * 8 * 64 + sizeof(int) * 2 * 64);
+  double* pq = sc.as<double>();
+  double* rrn = pq + 128;
+  double* rr = rrn + 128;
+  double* alpha = rr + 64;
+  double* beta = alpha + 64;
+  double* b2 = beta + 64;
+  int* active = (int*)(b2 + 64);
+  int* its = active + 64;
+  DMG_CHECK(nvec <= 64, DMG_E_INVALID, "too many CG fields");
+  auto normal = [&](const double2* in, double2* out) {
+    if (A.kind == 0) {
+      launch_wilson<double>(s, A.U64, in, t.as<double2>(), A.m0, A.Lx, A.Lt, 1, nvec);
+      launch_wilson<double>(s, A.U64, t.as<double2>(), out, A.m0, A.Lx, A.Lt, 0, nvec);
+    } else {
+      for (int f = 0; f < nvec; ++f) {
+        launch_block_apply<double>(s, A.A64, in + f * n, t.as<double2>() + f * n, A.Lx, A.Lt, 1);
+        launch_block_apply<double>(s, A.A64, t.as<double2>() + f * n, out + f * n, A.Lx, A.Lt, 0);
+      }
+    }
+    h->cnt.mv[lvl] += 2 * nvec;
+  };
+  DMG_HIP(hipMemsetAsync(x, 0, fb, s));
+  DMG_HIP(hipMemcpyAsync(r.p, b, fb, hipMemcpyDeviceToDevice, s));
+  DMG_HIP(hipMemcpyAsync(p.p, b, fb, hipMemcpyDeviceToDevice, s));
+  launch_batched_dots(s, n, nvec, b, b, rrn, PART(h), CNT(h));
+  // rr = b2 = ||b||^2, all active
+  std::vector<int> ones(nvec, 1), zeros(nvec, 0);
+  DMG_HIP(hipMemcpyAsync(active, ones.data(), sizeof(int) * nvec, hipMemcpyHostToDevice, s));
+  DMG_HIP(hipMemcpyAsync(its, zeros.data(), sizeof(int) * nvec, hipMemcpyHostToDevice, s));
+  DMG_HIP(hipMemcpy2DAsync(rr, sizeof(double), rrn, 2 * sizeof(double), sizeof(double), nvec,
+                           hipMemcpyDeviceToDevice, s));
+  DMG_HIP(hipMemcpy2DAsync(b2, sizeof(double), rrn, 2 * sizeof(double), sizeof(double), nvec,
+                           hipMemcpyDeviceToDevice, s));
+  std::vector<int> act(nvec);
+  for (int it = 1; it <= max_iters; ++it) {
+    normal(p.as<double2>(), q.as<double2>());
+    launch_batched_dots(s, n, nvec, p.as<double2>(), q.as<double2>(), pq, PART(h), CNT(h));
+    launch_cg_scalars(s, nvec, pq, rrn, rr, alpha, beta, active, b2, tol * tol, its, 0);
+    launch_cg_update<double>(s, n, nvec, x, r.as<double2>(), p.as<double2>(), q.as<double2>(), alpha, beta, active, 0);
+    launch_batched_dots(s, n, nvec, r.as<double2>(), r.as<double2>(), rrn, PART(h), CNT(h));
+    launch_cg_scalars(s, nvec, pq, rrn, rr, alpha, beta, active, b2, tol * tol, its, 1);
+    launch_cg_update<double>(s, n, nvec, x, r.as<double2>(), p.as<double2>(), q.as<double2>(), alpha, beta, active, 1);
+    if (it % 4 == 0 || it == max_iters) {
+      DMG_HIP(hipMemcpyAsync(act.data(), active, sizeof(int) * nvec, hipMemcpyDeviceToHost, s));
+      DMG_HIP(hipStreamSynchronize(s));
+      bool any = false;
+      for (int f = 0; f < nvec; ++f) any = any || act[f];
+      if (!any) break;
+    }
+  }
+  if (iters_host) {
+    DMG_HIP(hipMemcpyAsync(iters_host, its, sizeof(int) * nvec, hipMemcpyDeviceToHost, s));
+    DMG_HIP(hipStreamSynchronize(s));
+  }
+}
+
+// ---------------------------------------------------------------- setup
+// Global orthonormalisation: modified Gram-Schmidt over the whole lattice, two passes.
+static void global_mgs2(dmg_hierarchy* h, double2* W, int64_t n, int nvec) {
+  hipStream_t s = h->ctx->stream;
+  DevBuf coef;
+  coef.alloc(h->ctx, sizeof(double2) * 4);
+  double2* c = coef.as<double2>();
+  for (int k = 0; k < nvec; ++k) {
+    double2* wk = W + (int64_t)k * n;
+    for (int pass = 0; pass < 2; ++pass)
+      for (int j = 0; j < k; ++j) {
+        launch_multidot<double>(s, W + (int64_t)j * n, n, 1, wk, n, c, PART(h), CNT(h));
+        launch_multi_axpy<double>(s, wk, W + (int64_t)j * n, n, 1, c, n, 1.0);
+      }
+    launch_norm2<double>(s, n, wk, (double*)(c + 2), PART(h), CNT(h));
+    launch_scale_dev<double>(s, n, wk, wk, (const double*)(c + 2), 1);
+  }
+}
+
+void build_hierarchy(dmg_hierarchy* h, const double2* start0, const double2* start1, int inject) {
+  hipStream_t s = h->ctx->stream;
+  const int nvec = h->prm.nvec;
+  DMG_CHECK(nvec == NV, DMG_E_INVALID, "the blocked layout holds 12 near-null vectors per chirality");
+  for (int lvl = 0; lvl < 2; ++lvl) {
+    const Op& A = h->op[lvl];
+    const int64_t n = A.n;
+    const size_t fb = sizeof(double2) * (size_t)n * nvec;
+    const double2* start = lvl == 0 ? start0 : start1;
+    h->null[lvl].alloc(h->ctx, fb);
+    double2* psi = h->null[lvl].as<double2>();
+    if (inject) {
+      DMG_HIP(hipMemcpyAsync(psi, start, fb, hipMemcpyDeviceToDevice, s));
+    } else {
+      // b = -A A^dagger x ; solve A A^dagger e = b ; psi = x + e
+      DevBuf bb, tt;
+      bb.alloc(h->ctx, fb);
+      tt.alloc(h->ctx, fb);
+      double2* b = bb.as<double2>();
+      if (A.kind == 0) {
+        launch_wilson<double>(s, A.U64, start, tt.as<double2>(), A.m0, A.Lx, A.Lt, 1, nvec);
+        launch_wilson<double>(s, A.U64, tt.as<double2>(), b, A.m0, A.Lx, A.Lt, 0, nvec);
+      } else {
+        for (int f = 0; f < nvec; ++f) {
+          launch_block_apply<double>(s, A.A64, start + f * n, tt.as<double2>() + f * n, A.Lx, A.Lt, 1);
+          launch_block_apply<double>(s, A.A64, tt.as<double2>() + f * n, b + f * n, A.Lx, A.Lt, 0);
+        }
+      }
+      launch_axpby<double>(s, n * nvec, 0.0, b, -1.0, b);
+      cg_normal(h, lvl, nvec, b, psi, h->prm.null_tol, h->prm.null_max_iters, h->setup_iters[lvl]);
+      launch_axpby<double>(s, n * nvec, 1.0, start, 1.0, psi);
+    }
+    // global orthonormalisation (on a copy), chiral split + local orthonormalisation
+    DevBuf W;
+    W.alloc(h->ctx, fb);
+    DMG_HIP(hipMemcpyAsync(W.p, psi, fb, hipMemcpyDeviceToDevice, s));
+    global_mgs2(h, W.as<double2>(), n, nvec);
+    const int dof = lvl == 0 ? 2 : NC;
+    const int64_t pe = (int64_t)A.Lx * A.Lt * dof * NV;
+    h->P64[lvl].alloc(h->ctx, sizeof(double2) * pe);
+    h->P32[lvl].alloc(h->ctx, sizeof(float2) * pe);
+    int* status = h->flags.as<int>();
+    DMG_HIP(hipMemsetAsync(status, 0, sizeof(int), s));
+    launch_local_ortho(s, W.as<double2>(), n, nvec, h->P64[lvl].as<double2>(), A.Lx, A.Lt, dof, status);
+    int st = 0;
+    DMG_HIP(hipMemcpyAsync(&st, status, sizeof(int), hipMemcpyDeviceToHost, s));
+    DMG_HIP(hipStreamSynchronize(s));
+    DMG_CHECK(st == 0, DMG_E_BREAKDOWN, "local orthonormalisation lost rank in a block");
+    launch_d2f(s, pe, h->P64[lvl].as<double2>(), h->P32[lvl].as<float2>());
+    h->tr[lvl] = Transfer{A.Lx, A.Lt, dof, h->P64[lvl].as<double2>(), h->P32[lvl].as<float2>()};
+    // Galerkin operator of the next level
+    const int CLx = A.Lx / BLK, CLt = A.Lt / BLK;
+    const int64_t ce = (int64_t)CLx * CLt * 5 * NC * NC;
+    h->A64[lvl + 1].alloc(h->ctx, sizeof(double2) * ce);
+    h->A32[lvl + 1].alloc(h->ctx, sizeof(float2) * ce);
+    if (lvl == 0) {
+      DevBuf wb;
+      wb.alloc(h->ctx, sizeof(double2) * (size_t)A.Lx * A.Lt * 5 * 4);
+      launch_wilson_blocks(s, A.U64, A.m0, A.Lx, A.Lt, wb.as<double2>());
+      launch_galerkin(s, wb.as<double2>(), h->P64[0].as<double2>(), A.Lx, A.Lt, 2, h->A64[1].as<double2>());
+      DMG_HIP(hipStreamSynchronize(s));
+    } else {
+      launch_galerkin(s, h->A64[1].as<double2>(), h->P64[1].as<double2>(), A.Lx, A.Lt, NC, h->A64[2].as<double2>());
+    }
+    launch_d2f(s, ce, h->A64[lvl + 1].as<double2>(), h->A32[lvl + 1].as<float2>());
+    Op& C = h->op[lvl + 1];
+    C.kind = 1;
+    C.Lx = CLx;
+    C.Lt = CLt;
+    C.n = (int64_t)CLx * CLt * NC;
+    C.A64 = h->A64[lvl + 1].as<double2>();
+    C.A32 = h->A32[lvl + 1].as<float2>();
+    DMG_HIP(hipStreamSynchronize(s));
+  }
+}
+
+// ---------------------------------------------------------------- preconditioner (precision R)
+template <typename R>
+struct Precond {
+  using T = cx<R>;
+  dmg_hierarchy* h;
+  int smooth_steps = 2;
+  KWS sm[2];                       // smoother bases, levels 0 and 1
+  DevBuf y[2], r[2], r2[2], sv[2];  // cycle vectors
+  KWS e1;                          // partial intermediate solve (flexible)
+  DevBuf e1r, e1x, bh;
+  DevBuf bc, ec, bc64, ec64, pr;   // coarse vectors
+  KWS proj;                        // GMRES-Proj cycles
+  int proj_m = 0;
+  const dmg_solve_params* p = nullptr;
+  dmg_deflation* defl = nullptr;
+
+  explicit Precond(dmg_hierarchy* hh) : h(hh) {}
+
+  hipStream_t S() const { return h->ctx->stream; }
+  const T* Pm(int lvl) const { return (const T*)h->tr[lvl].P((const T*)nullptr); }
+
+  void ensure(const dmg_solve_params* prm, dmg_deflation* d) {
+    p = prm;
+    defl = d;
+    dmg_context* c = h->ctx;
+    const size_t es = sizeof(T);
+    if (!sm[0].V.p || smooth_steps != prm->smooth_steps) {
+      smooth_steps = prm->smooth_steps;
+      for (int l = 0; l < 2; ++l) {
+        const int64_t n = h->op[l].n;
+        sm[l].alloc(c, smooth_steps, n, es, false);
+        y[l].alloc(c, es * n);
+        r[l].alloc(c, es * n);
+        r2[l].alloc(c, es * n);
+        sv[l].alloc(c, es * n);
+      }
+      const int64_t n2 = h->op[2].n;
+      bc.alloc(c, es * n2);
+      ec.alloc(c, es * n2);
+      pr.alloc(c, es * n2);
+      bc64.alloc(c, sizeof(double2) * n2);
+      ec64.alloc(c, sizeof(double2) * n2);
+    }
+    if (!e1.V.p || e1.m != prm->int_m) {
+      const int64_t n1 = h->op[1].n;
+      e1.alloc(c, prm->int_m, n1, es, true);
+      e1r.alloc(c, es * n1);
+      e1x.alloc(c, es * n1);
+      bh.alloc(c, es * n1);
+    }
+    const int pm = d ? d->m : 1;
+    if (!proj.V.p || proj_m < pm) {
+      proj.alloc(c, pm, h->op[2].n, es, false);
+      proj_m = pm;
+    }
+  }
+
+  // GMRES(s) from x = 0 on level lvl: y = approximate A^{-1} v; r = v - A y from the
+  // Arnoldi relation when requested (no extra matrix-vector product).
+  void smooth(int lvl, const T* v, T* yout, T* rout) {
+    KWS& w = sm[lvl];
+    KState* ks = w.state();
+    T* V = w.V.as<T>();
+    const int64_t n = w.n;
+    launch_cycle_start<R>(S(), v, V, n, ks, -1.0, 1, PART(h), CNT(h));
+    for (int j = 0; j < smooth_steps; ++j) {
+      h->op[lvl].apply(S(), V + j * n, V + (j + 1) * n, 0, &ks->done);
+      launch_arnoldi_orth<R>(S(), V, n, n, j, ks, PART(h), CNT(h));
+      h->cnt.mv[lvl]++;
+    }
+    launch_ls_solve(S(), ks);
+    launch_combine<R, R>(S(), yout, V, n, n, ks, 0, 0);
+    if (rout) launch_combine<R, R>(S(), rout, V, n, n, ks, 1, 0);
+  }
+
+  // GMRES-Proj(m, k): projection over the deflation space, then GMRES(m - k) cycles.
+  void gmres_proj(const T* b, T* x, double tol) {
+    dmg_deflation* d = defl;
+    const Op& A = h->op[2];
+    const int64_t n = A.n;
+    const int k = d->kk;
+    const int mm = std::max(d->m - k, 1);
+    const T* DV = dvec(d);
+    const double2* DH = d->H.as<double2>();
+    KState* ks = proj.state();
+    T* V = proj.V.as<T>();
+    T* rr = pr.as<T>();
+    DMG_HIP(hipMemsetAsync(x, 0, sizeof(T) * n, S()));
+    DMG_HIP(hipMemcpyAsync(rr, b, sizeof(T) * n, hipMemcpyDeviceToDevice, S()));
+    launch_set_bnorm<R>(S(), n, b, ks, PART(h), CNT(h));
+    int iters = 0;
+    KStatus st{};
+    for (;;) {
+      launch_multidot<R>(S(), DV, n, k + 1, rr, n, ks->c, PART(h), CNT(h));
+      launch_proj_solve(S(), DH, k, ks);
+      launch_combine<R, R>(S(), x, DV, n, n, ks, 0, 1);
+      launch_multi_axpy<R>(S(), rr, DV, n, k + 1, ks->u, n, 1.0);
+      launch_cycle_start<R>(S(), rr, V, n, ks, tol, 0, PART(h), CNT(h));
+      for (int j = 0; j < mm; ++j) {
+        A.apply(S(), V + j * n, V + (j + 1) * n, 0, &ks->done);
+        launch_arnoldi_orth<R>(S(), V, n, n, j, ks, PART(h), CNT(h));
+      }
+      launch_ls_solve(S(), ks);
+      launch_combine<R, R>(S(), x, V, n, n, ks, 0, 1);
+      launch_combine<R, R>(S(), rr, V, n, n, ks, 1, 0);
+      sync_status(h, ks, &st);
+      iters += st.steps;
+      h->cnt.mv[2] += st.steps;
+      if (st.est <= st.tol_abs || st.breakdown || iters >= p->coarse_max_iters) break;
+    }
+  }
+
+  const T* dvec(dmg_deflation* d);
+
+  void coarse_solve(const T* b, T* x) {
+    h->cnt.coarse_calls++;
+    if (!defl) {
+      coarse_cgne(b, x);
+      return;
+    }
+    if (!defl->ready) {
+      const int64_t n = h->op[2].n;
+      if constexpr (sizeof(R) == sizeof(double)) {
+        coarse_gmres_dr(h, defl, (const double2*)b, (double2*)x, p->coarse_tol_first, p->coarse_max_iters);
+      } else {
+        launch_cast_f2d(S(), n, (const float2*)b, bc64.as<double2>());
+        coarse_gmres_dr(h, defl, bc64.as<double2>(), ec64.as<double2>(), p->coarse_tol_first, p->coarse_max_iters);
+        launch_cast_d2f(S(), n, ec64.as<double2>(), (float2*)x);
+      }
+      return;
+    }
+    double tol = p->coarse_tol_later;
+    if (sizeof(R) == sizeof(float)) tol = std::max(tol, 1e-5);
+    gmres_proj(b, x, tol);
+  }
+
+  // non-deflated comparison: CG on D_c D_c^dagger y = b, x = D_c^dagger y (FP64)
+  void coarse_cgne(const T* b, T* x) {
+    const int64_t n = h->op[2].n;
+    const double2* b64;
+    if constexpr (sizeof(R) == sizeof(double)) b64 = (const double2*)b;
+    else {
+      launch_cast_f2d(S(), n, (const float2*)b, bc64.as<double2>());
+      b64 = bc64.as<double2>();
+    }
+    DevBuf y;
+    y.alloc(h->ctx, sizeof(double2) * n);
+    int it = 0;
+    cg_normal(h, 2, 1, b64, y.as<double2>(), p->coarse_tol_first, p->coarse_max_iters, &it);
+    double2* x64 = (sizeof(R) == sizeof(double)) ? (double2*)x : ec64.as<double2>();
+    h->op[2].apply(S(), y.as<double2>(), x64, 1, nullptr);
+    h->cnt.mv[2]++;
+    if constexpr (sizeof(R) == sizeof(float)) launch_cast_d2f(S(), n, ec64.as<double2>(), (float2*)x);
+  }
+
+  // intermediate cycle M1: smooth, coarse correction, smooth
+  void cycle1(const T* v, T* out) {
+    const int64_t n = h->op[1].n;
+    T* y1 = y[1].as<T>();
+    T* r1 = r[1].as<T>();
+    T* q = r2[1].as<T>();
+    T* s1 = sv[1].as<T>();
+    smooth(1, v, y1, r1);
+    launch_restrict<R>(S(), Pm(1), r1, bc.as<T>(), h->tr[1].Lx, h->tr[1].Lt, NC);
+    coarse_solve(bc.as<T>(), ec.as<T>());
+    launch_prolong<R>(S(), Pm(1), ec.as<T>(), y1, h->tr[1].Lx, h->tr[1].Lt, NC, 1);
+    h->op[1].apply(S(), y1, q, 0, nullptr);
+    h->cnt.mv[1]++;
+    launch_xmy<R>(S(), n, v, q);
+    smooth(1, q, s1, nullptr);
+    launch_axpby<R>(S(), n, 1.0, y1, 1.0, s1);
+    DMG_HIP(hipMemcpyAsync(out, s1, sizeof(T) * n, hipMemcpyDeviceToDevice, S()));
+  }
+
+  // partial intermediate solve E1: FGMRES(int_m) on D_hat with M1 to int_tol ||b||
+  void partial_solve(const T* b, T* x) {
+    const Op& A = h->op[1];
+    const int64_t n = A.n;
+    KState* ks = e1.state();
+    T* V = e1.V.as<T>();
+    T* Z = e1.Z.as<T>();
+    DMG_HIP(hipMemsetAsync(x, 0, sizeof(T) * n, S()));
+    const T* rr = b;
+    int iters = 0;
+    bool first = true;
+    KStatus st{};
+    while (iters < p->int_max_iters) {
+      launch_cycle_start<R>(S(), rr, V, n, ks, p->int_tol, first ? 1 : 0, PART(h), CNT(h));
+      first = false;
+      const int mm = std::min(e1.m, p->int_max_iters - iters);
+      for (int j = 0; j < mm; ++j) {
+        cycle1(V + j * n, Z + j * n);
+        A.apply(S(), Z + j * n, V + (j + 1) * n, 0, nullptr);
+        h->cnt.mv[1]++;
+        launch_arnoldi_orth<R>(S(), V, n, n, j, ks, PART(h), CNT(h));
+        sync_status(h, ks, &st);
+        if (st.done) break;
+      }
+      launch_ls_solve(S(), ks);
+      launch_combine<R, R>(S(), x, Z, n, n, ks, 0, 1);
+      iters += st.steps;
+      if (st.est <= st.tol_abs || st.breakdown || iters >= p->int_max_iters) break;
+      T* res = e1r.as<T>();
+      A.apply(S(), x, res, 0, nullptr);
+      h->cnt.mv[1]++;
+      launch_xmy<R>(S(), n, b, res);
+      rr = res;
+    }
+  }
+
+  // fine cycle M0: smooth, partial intermediate solve, smooth
+  void cycle0(const T* v, T* out) {
+    const int64_t n = h->op[0].n;
+    T* y0 = y[0].as<T>();
+    T* r0 = r[0].as<T>();
+    T* q = r2[0].as<T>();
+    T* s0 = sv[0].as<T>();
+    smooth(0, v, y0, r0);
+    launch_restrict<R>(S(), Pm(0), r0, bh.as<T>(), h->tr[0].Lx, h->tr[0].Lt, 2);
+    partial_solve(bh.as<T>(), e1x.as<T>());
+    launch_prolong<R>(S(), Pm(0), e1x.as<T>(), y0, h->tr[0].Lx, h->tr[0].Lt, 2, 1);
+    h->op[0].apply(S(), y0, q, 0, nullptr);
+    h->cnt.mv[0]++;
+    launch_xmy<R>(S(), n, v, q);
+    smooth(0, q, s0, nullptr);
+    launch_axpby<R>(S(), n, 1.0, y0, 1.0, s0);
+    DMG_HIP(hipMemcpyAsync(out, s0, sizeof(T) * n, hipMemcpyDeviceToDevice, S()));
+  }
+};
+
+template <>
+const double2* Precond<double>::dvec(dmg_deflation* d) {
+  return d->V64.as<double2>();
+}
+template <>
+const float2* Precond<float>::dvec(dmg_deflation* d) {
+  if (!d->cast_ready) {
+    const int64_t n = h->op[2].n;
+    d->V32.alloc(h->ctx, sizeof(float2) * (size_t)n * (d->kk + 1));
+    launch_cast_d2f(S(), n * (d->kk + 1), d->V64.as<double2>(), d->V32.as<float2>());
+    d->cast_ready = 1;
+  }
+  return d->V32.as<float2>();
+}
+
+// ---------------------------------------------------------------- outer FGMRES (FP64)
+dmg_status outer_solve(dmg_hierarchy* h, dmg_deflation* d, const dmg_solve_params* p, const double2* b, double2* x,
+                       dmg_solve_stats* stout) {
+  auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = h->ctx->stream;
+  DMG_CHECK(p->outer_m >= 1 && p->outer_m <= MMAX && p->int_m >= 1 && p->int_m <= MMAX && p->smooth_steps >= 1 &&
+                p->smooth_steps <= MMAX,
+            DMG_E_INVALID, "restart lengths must lie in [1, 64]");
+  DMG_CHECK(!d || d->h == h, DMG_E_INVALID, "deflation space belongs to another hierarchy");
+  h->cnt = Counters{};
+  const Op& A = h->op[0];
+  const int64_t n = A.n;
+  const bool fp32 = p->precond == DMG_FP32;
+  if (!h->outer.V.p || h->outer.m != p->outer_m) {
+    h->outer.alloc(h->ctx, p->outer_m, n, sizeof(double2), true);
+    h->or_.alloc(h->ctx, sizeof(double2) * n);
+    h->bn2.alloc(h->ctx, sizeof(double) * 4);
+  }
+  if (fp32 && !h->ov32.p) {
+    h->ov32.alloc(h->ctx, sizeof(float2) * n);
+    h->oz32.alloc(h->ctx, sizeof(float2) * n);
+  }
+  if (fp32) {
+    if (!h->pc32) h->pc32.reset(new Precond<float>(h));
+    h->pc32->ensure(p, d);
+  } else {
+    if (!h->pc64) h->pc64.reset(new Precond<double>(h));
+    h->pc64->ensure(p, d);
+  }
+  KState* ks = h->outer.state();
+  double2* V = h->outer.V.as<double2>();
+  double2* Z = h->outer.Z.as<double2>();
+  double2* r = h->or_.as<double2>();
+  double* scal = h->bn2.as<double>();
+  if (p->use_x0) {
+    A.apply(s, x, r, 0, nullptr);
+    h->cnt.mv[0]++;
+    launch_xmy<double>(s, n, b, r);
+  } else {
+    DMG_HIP(hipMemsetAsync(x, 0, sizeof(double2) * n, s));
+    DMG_HIP(hipMemcpyAsync(r, b, sizeof(double2) * n, hipMemcpyDeviceToDevice, s));
+  }
+  launch_norm2<double>(s, n, b, scal, PART(h), CNT(h));
+  launch_set_bnorm<double>(s, n, b, ks, PART(h), CNT(h));
+  const double bnorm = std::sqrt(read_double(h, scal));
+  int iters = 0;
+  double rel = 0.0;
+  bool conv = false;
+  if (bnorm == 0.0) {
+    DMG_HIP(hipMemsetAsync(x, 0, sizeof(double2) * n, s));
+    conv = true;
+  } else {
+    // initial residual check (x0 given)
+    launch_norm2<double>(s, n, r, scal, PART(h), CNT(h));
+    rel = std::sqrt(read_double(h, scal)) / bnorm;
+    conv = rel <= p->tol;
+    KStatus st{};
+    while (!conv && iters < p->max_outer_iters) {
+      launch_cycle_start<double>(s, r, V, n, ks, p->tol, 0, PART(h), CNT(h));
+      const int mm = std::min(p->outer_m, p->max_outer_iters - iters);
+      for (int j = 0; j < mm; ++j) {
+        double2* vj = V + (int64_t)j * n;
+        double2* zj = Z + (int64_t)j * n;
+        if (fp32) {
+          launch_cast_d2f(s, n, vj, h->ov32.as<float2>());
+          h->pc32->cycle0(h->ov32.as<float2>(), h->oz32.as<float2>());
+          launch_cast_f2d(s, n, h->oz32.as<float2>(), zj);
+        } else {
+          h->pc64->cycle0(vj, zj);
+        }
+        A.apply(s, zj, V + (int64_t)(j + 1) * n, 0, nullptr);
+        h->cnt.mv[0]++;
+        launch_arnoldi_orth<double>(s, V, n, n, j, ks, PART(h), CNT(h));
+        sync_status(h, ks, &st);
+        if (st.done) break;
+      }
+      launch_ls_solve(s, ks);
+      launch_combine<double, double>(s, x, Z, n, n, ks, 0, 1);
+      iters += st.steps;
+      // true residual r = b - D x
+      A.apply(s, x, r, 0, nullptr);
+      h->cnt.mv[0]++;
+      launch_xmy<double>(s, n, b, r);
+      launch_norm2<double>(s, n, r, scal, PART(h), CNT(h));
+      rel = std::sqrt(read_double(h, scal)) / bnorm;
+      conv = rel <= p->tol;
+      if (st.steps == 0) break;
+    }
+  }
+  DMG_HIP(hipStreamSynchronize(s));
+  auto t1 = std::chrono::steady_clock::now();
+  if (stout) {
+    dmg_solve_stats& o = *stout;
+    o.outer_iters = iters;
+    o.converged = conv ? 1 : 0;
+    o.fine_mvps = h->cnt.mv[0];
+    o.int_mvps = h->cnt.mv[1];
+    o.coarse_mvps = h->cnt.mv[2];
+    const double n0 = (double)h->op[0].n, n1 = (double)h->op[1].n, n2 = (double)h->op[2].n;
+    o.fine_equiv_mvps = h->cnt.mv[0] + n1 / n0 * h->cnt.mv[1] + n2 / n0 * h->cnt.mv[2];
+    o.true_rel_resid = rel;
+    o.coarse_calls = h->cnt.coarse_calls;
+    o.coarse_dr_calls = h->cnt.dr_calls;
+    o.elapsed_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  }
+  return conv ? DMG_OK : DMG_W_NOT_CONVERGED;
+}
+
+}  // namespace dmg
+
+dmg_hierarchy::dmg_hierarchy() = default;
+dmg_hierarchy::~dmg_hierarchy() {
+  if (host_status) hipHostFree(host_status);
+}

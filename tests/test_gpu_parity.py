@@ -1,0 +1,263 @@
+"""GPU parity of the HIP library against the FP64 oracle, through the C-ABI.
+
+Per-apply FP64 parity is 1e-13 relative (norm-wise and element-wise against the
+largest entry); FP32 applies are held to 2e-6.  Lattice sizes span one partial
+workgroup (8 x 6), several workgroups with a ragged tail (36 x 18) and the
+workload sizes (64^2, 256^2).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import multigrid, wilson
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dmg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1912_02868_amd as dmg
+    dmg.lib()
+    return dmg
+
+
+@pytest.fixture(scope="module")
+def ctx(dmg):
+    return dmg.Context(0)
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _elem(a, b):
+    return np.max(np.abs(a - b)) / np.max(np.abs(b))
+
+
+def _theta(Nx, Nt, seed):
+    """A random U(1) field of any shape (the gauge generator needs square lattices)."""
+    rng = synth.rng_for(Nx, Nt, 9, seed)
+    return rng.uniform(-np.pi, np.pi, size=(Nt, Nx, 2))
+
+
+@pytest.mark.parametrize("Nx,Nt", [(8, 6), (36, 18), (64, 64), (256, 256)])
+@pytest.mark.parametrize("dagger", [0, 1])
+def test_wilson_fp64(dmg, ctx, Nx, Nt, dagger):
+    th = synth.gauge_angles(Nx, 0) if Nx == Nt else _theta(Nx, Nt, 0)
+    m0 = -0.07
+    D = wilson.dirac_matrix(th, m0)
+    if dagger:
+        D = D.conj().T.tocsr()
+    x = synth.gaussian_complex(2 * Nx * Nt, Nx, Nt, 7, 0)
+    g = dmg.Gauge(ctx, th)
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.empty_like(xd)
+    dmg.apply_dirac(ctx, g, m0, xd, yd, dagger=bool(dagger))
+    torch.cuda.synchronize()
+    y = yd.cpu().numpy()
+    ref = D @ x
+    assert _rel(y, ref) < 1e-13 and _elem(y, ref) < 1e-13
+
+
+def test_wilson_fp32_host_and_multi_rhs(dmg, ctx):
+    Nx, Nt = 36, 18
+    th = _theta(Nx, Nt, 1)
+    D = wilson.dirac_matrix(th, 0.1)
+    g = dmg.Gauge(ctx, th)
+    xs = np.stack([synth.gaussian_complex(2 * Nx * Nt, Nx, Nt, 7, j) for j in range(3)])
+    out = np.empty_like(xs)
+    dmg.apply_dirac(ctx, g, 0.1, xs, out, nrhs=3)             # host pointers, FP64, 3 RHS
+    for j in range(3):
+        assert _rel(out[j], D @ xs[j]) < 1e-13
+    x32 = torch.from_numpy(xs[0].astype(np.complex64)).cuda()
+    y32 = torch.empty_like(x32)
+    dmg.apply_dirac(ctx, g, 0.1, x32, y32)
+    torch.cuda.synchronize()
+    assert _rel(y32.cpu().numpy().astype(complex), D @ xs[0].astype(np.complex64).astype(complex)) < 2e-6
+
+
+def test_gauge_errors(dmg, ctx):
+    bad = np.zeros((6, 5, 2))
+    with pytest.raises(dmg.DmgError) as e:
+        dmg.Gauge(ctx, bad)
+    assert e.value.code == dmg.DMG_E_INVALID
+    nan = np.zeros((8, 8, 2))
+    nan[3, 2, 1] = np.nan
+    with pytest.raises(dmg.DmgError) as e:
+        dmg.Gauge(ctx, nan)
+    assert e.value.code == dmg.DMG_E_NONFINITE
+
+
+# ---------------------------------------------------------------- setup with injected near-null vectors
+def _oracle_hier(N, cfg, m0):
+    th = synth.gauge_angles(N, cfg)
+    H = multigrid.Hierarchy(th, m0, synth.near_null_starts(N, cfg, 0), synth.near_null_starts(N, cfg, 1))
+    return th, H
+
+
+@pytest.fixture(scope="module", params=[16, 64])
+def injected(request, dmg, ctx):
+    N = request.param
+    m0 = 0.02 if N == 16 else synth.bare_mass(64, 0)
+    th, H = _oracle_hier(N, 0, m0)
+    g = dmg.Gauge(ctx, th)
+    n0 = np.ascontiguousarray(H.levels[0].null)
+    n1 = np.ascontiguousarray(H.levels[1].null)
+    hg = dmg.Hierarchy(ctx, g, m0, n0, n1, inject=True)
+    return N, th, m0, H, g, hg
+
+
+def _oracle_P_layout(L):
+    """Oracle prolongator in the library's [site][dof][12] layout."""
+    P = L.P.toarray()
+    n_f, n_c = P.shape
+    dof = L.dof
+    half = dof // 2
+    out = np.zeros((n_f // dof, dof, 12), dtype=complex)
+    for s in range(n_f // dof):
+        x, t = s % L.Lx, s // L.Lx
+        B = x // 4 + (L.Lx // 4) * (t // 4)
+        for a in range(dof):
+            c = a // half
+            out[s, a, :] = P[dof * s + a, 24 * B + 12 * c: 24 * B + 12 * c + 12]
+    return out.ravel()
+
+
+def test_injected_prolongators(dmg, injected):
+    N, th, m0, H, g, hg = injected
+    for lvl in range(2):
+        Pg = hg.export(lvl, dmg.PART_P)
+        Po = _oracle_P_layout(H.levels[lvl])
+        assert _elem(Pg, Po) < 1e-12, f"level {lvl}"
+
+
+def test_injected_operators_action(dmg, ctx, injected):
+    N, th, m0, H, g, hg = injected
+    for lvl in range(3):
+        A = H.levels[lvl].A
+        n = A.shape[0]
+        v = synth.gaussian_complex(n, N, lvl, 8, 0)
+        for op, M in [(dmg.OP_APPLY, A), (dmg.OP_APPLY_DAG, A.conj().T.tocsr())]:
+            out = np.empty(n, dtype=complex)
+            hg.apply(lvl, op, v, out)
+            tol = 1e-13 if lvl == 0 else 1e-12
+            assert _rel(out, M @ v) < tol, f"level {lvl} op {op}"
+
+
+def test_injected_transfers(dmg, injected):
+    N, th, m0, H, g, hg = injected
+    for lvl in range(2):
+        P = H.levels[lvl].P
+        nf, nc = P.shape
+        v = synth.gaussian_complex(nf, N, lvl, 8, 1)
+        e = synth.gaussian_complex(nc, N, lvl, 8, 2)
+        r = np.empty(nc, dtype=complex)
+        hg.apply(lvl, dmg.OP_RESTRICT, v, r)
+        assert _rel(r, P.conj().T @ v) < 1e-13
+        p = np.empty(nf, dtype=complex)
+        hg.apply(lvl, dmg.OP_PROLONG, e, p)
+        assert _rel(p, P @ e) < 1e-13
+
+
+def test_injected_blocks_64(dmg, injected):
+    N, th, m0, H, g, hg = injected
+    if N != 64:
+        pytest.skip("blocks are compared where no two directions reach the same site")
+    for lvl, (Lx, Lt) in [(1, (16, 16)), (2, (4, 4))]:
+        Bg = hg.export(lvl, dmg.PART_BLOCKS).reshape(Lx * Lt, 5, 24, 24).transpose(0, 1, 3, 2)
+        Bo = multigrid.stencil_blocks(H.levels[lvl].A, Lx, Lt)
+        assert _elem(Bg, Bo) < 1e-12
+
+
+def test_fp32_operators(dmg, injected):
+    N, th, m0, H, g, hg = injected
+    for lvl in (1, 2):
+        A = H.levels[lvl].A
+        v = synth.gaussian_complex(A.shape[0], N, lvl, 8, 3)
+        vd = torch.from_numpy(v.astype(np.complex64)).cuda()
+        od = torch.empty_like(vd)
+        hg.apply(lvl, dmg.OP_APPLY, vd, od)
+        torch.cuda.synchronize()
+        assert _rel(od.cpu().numpy().astype(complex), A @ v) < 1e-5
+
+
+# ---------------------------------------------------------------- deflation space
+def test_gmres_dr_deflation_space(dmg, injected):
+    N, th, m0, H, g, hg = injected
+    if N != 64:
+        pytest.skip("needs a coarse space larger than m")
+    Dc = H.levels[2].A.toarray()
+    nc = Dc.shape[0]
+    d = dmg.Deflation(hg, 30, 10)
+    b = synth.gaussian_complex(nc, 64, 0, 4, 0)
+    d.build(b, 1e-8)
+    assert d.ready
+    V, Hk = d.export(nc)
+    k = Hk.shape[1]
+    assert k == 10
+    assert np.linalg.norm(V.conj().T @ V - np.eye(k + 1)) < 1e-11
+    assert np.linalg.norm(Dc @ V[:, :k] - V @ Hk) / np.linalg.norm(Hk) < 1e-10
+    # the kept space holds the smallest eigenvalues of D_c
+    lam = np.linalg.eigvals(Dc)
+    small = lam[np.argsort(np.abs(lam))[:3]]
+    ritz = np.linalg.eigvals(np.linalg.lstsq(V[:, :k], Dc @ V[:, :k], rcond=None)[0])
+    for t in small:
+        assert np.min(np.abs(ritz - t)) < 1e-3 * abs(t) + 1e-6
+
+
+# ---------------------------------------------------------------- whole solves
+def _solve_and_check(dmg, ctx, hg, D, b, defl=None, **kw):
+    x = np.zeros_like(b)
+    st, stats = dmg.solve(ctx, hg, defl, b, x, params=dmg.solve_params(**kw))
+    res = np.linalg.norm(b - D @ x) / np.linalg.norm(b)
+    return st, stats[0], x, res
+
+
+def test_solve_fp64_64_injected(dmg, ctx, injected):
+    N, th, m0, H, g, hg = injected
+    if N != 64:
+        pytest.skip("workload-sized solve")
+    import scipy.sparse.linalg as spla
+    D = H.levels[0].A
+    d = dmg.Deflation(hg, 30, 10)
+    lu = spla.splu(D.tocsc())
+    for j in range(3):
+        b = synth.rhs(64, 0, j)
+        st, s, x, res = _solve_and_check(dmg, ctx, hg, D, b, d)
+        assert st == dmg.DMG_OK and s["converged"] == 1
+        assert res <= 1e-8 and abs(res - s["true_rel_resid"]) < 1e-10
+        xr = lu.solve(b)
+        assert _rel(x, xr) < 1e-6
+        assert s["coarse_dr_calls"] == (1 if j == 0 else 0)
+
+
+def test_solve_fp32_preconditioner_64(dmg, ctx, injected):
+    N, th, m0, H, g, hg = injected
+    if N != 64:
+        pytest.skip("workload-sized solve")
+    import scipy.sparse.linalg as spla
+    D = H.levels[0].A
+    d = dmg.Deflation(hg, 30, 10)
+    b = synth.rhs(64, 0, 1)
+    st, s, x, res = _solve_and_check(dmg, ctx, hg, D, b, d, precond=dmg.FP32)
+    assert st == dmg.DMG_OK and res <= 1e-8
+    assert _rel(x, spla.splu(D.tocsc()).solve(b)) < 1e-6
+
+
+def test_solve_zero_rhs_and_cap(dmg, ctx, injected):
+    N, th, m0, H, g, hg = injected
+    if N != 16:
+        pytest.skip("small lattice")
+    D = H.levels[0].A
+    d = dmg.Deflation(hg, 12, 4)
+    b = np.zeros(D.shape[0], dtype=complex)
+    x = np.ones_like(b)
+    st, stats = dmg.solve(ctx, hg, d, b, x)
+    assert st == dmg.DMG_OK and stats[0]["outer_iters"] == 0 and np.all(x == 0)
+    b = synth.rhs(16, 0, 0)
+    st, stats = dmg.solve(ctx, hg, d, b, x, params=dmg.solve_params(tol=1e-17, max_outer_iters=3))
+    assert st == dmg.DMG_W_NOT_CONVERGED and stats[0]["outer_iters"] == 3
