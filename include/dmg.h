@@ -188,6 +188,8 @@ typedef struct {
   int coarse_max_iters;    /* cap on coarse Arnoldi steps per call (5000) */
   dmg_precision precond;   /* preconditioner precision (outer is FP64) */
   int use_x0;              /* 1: x holds the initial guess */
+  int coarse_persistent;   /* 1: each GMRES-Proj coarse solve is one cooperative kernel launch
+                              (default); 0: one launch per Arnoldi sub-step */
 } dmg_solve_params;
 
 typedef struct {

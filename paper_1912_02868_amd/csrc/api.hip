@@ -100,6 +100,7 @@ void dmg_solve_params_default(dmg_solve_params* p) {
   p->coarse_max_iters = 5000;
   p->precond = DMG_FP64;
   p->use_x0 = 0;
+  p->coarse_persistent = 1;
 }
 
 void dmg_setup_params_default(dmg_setup_params* p) {

@@ -1,0 +1,560 @@
+// Persistent coarse-grid GMRES-Proj(m, k) (Methods section: every coarse solve after
+// the first is a projection over the GMRES-DR space followed by GMRES cycles).
+//
+// One cooperative launch runs a whole coarse solve.  About 32 workgroups each own
+// `spw` consecutive coarse sites; a workgroup keeps its slices of the Krylov basis,
+// of the deflation basis and of x and r in LDS for the whole solve (and its 24 x 24
+// blocks too when they fit).  Neighbour values for the stencil travel through one
+// global exchange vector; dot products are summed per workgroup, written to
+// global memory, and after a grid barrier every workgroup adds the same partials
+// in the same order, so all workgroups hold identical small-dense state and take
+// identical control decisions without further communication.
+//
+// The grid barrier is a flag array: each workgroup publishes its barrier
+// generation with one release store and its first wavefront polls all flags
+// (acquire loads, bounded spin).  Its cost grows slowly with the number of
+// workgroups, unlike a single atomic counter whose arrivals serialise; hence few,
+// larger workgroups.  An Arnoldi step costs two barriers: one to exchange v_j for
+// the stencil, one for the Gram-Schmidt reduction.  The orthogonalisation is
+// classical Gram-Schmidt with the norm from ||w||^2 - ||h||^2; when that
+// difference shows more than 99.99 % cancellation a second pass with an exact
+// norm is taken (one more barrier).  In exact arithmetic this is the Arnoldi
+// process of GMRES; the oracle uses modified Gram-Schmidt twice.
+#include "kernels.h"
+
+namespace dmg {
+
+constexpr int CP_THREADS = 256;
+constexpr int CP_WAVES = CP_THREADS / 64;
+constexpr int CP_QMAX = 32;     // quantities per reduction
+constexpr int CP_CHUNKS = 8;    // partial-sum chunks per quantity (fixed summation order)
+
+struct CPArgs {
+  const void* A;          // coarse blocks [S][d][col][row]
+  int Lx, Lt;
+  const void* DV;         // deflation basis, k + 1 fields
+  const double2* DH;      // Hbar_k, (k+1) x k column-major
+  int k;
+  const void* b;
+  void* x;
+  double tol;
+  int mm;                 // GMRES cycle length m - k
+  int max_iters;
+  void* xchg;             // exchange field (n entries)
+  double2* partials;      // 2 x CP_QMAX x G
+  int* out_iters;
+  double* out_relres;
+  unsigned* flags;        // G barrier flags, CP_FLAGPAD apart, zero at launch
+  int* err;               // set when a barrier wait exceeds its spin limit
+  int spw;                // sites per workgroup
+  int a_in_lds;
+};
+
+constexpr int CP_FLAGPAD = 32;  // one flag per 128-byte line
+
+// Flag-array grid barrier (see the file comment).  `gen` counts this workgroup's
+// barriers; a wait longer than the spin limit sets *err and gives up, so no wave
+// can hang the device.
+__device__ inline void cp_barrier(unsigned* flags, int G, unsigned gen, int* err) {
+  __syncthreads();
+  if (threadIdx.x == 0)
+    __hip_atomic_store(&flags[blockIdx.x * CP_FLAGPAD], gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x < 64) {
+    for (int b = threadIdx.x; b < G; b += 64) {
+      long spins = 0;
+      while (__hip_atomic_load(&flags[b * CP_FLAGPAD], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < gen) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > (1L << 24)) {
+          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+__host__ __device__ inline size_t cp_align(size_t v) { return (v + 15) & ~(size_t)15; }
+
+// LDS layout (bytes) shared by host sizing and the kernel.
+struct CPLayout {
+  size_t A, Vb, DVb, xl, rl, wl, xs, part, Hr, rc, rs, g, y, u, Hk, Rk, kc, ks, kp, red, cs, res, tot;
+  __host__ __device__ CPLayout(int spw, int mm, int k, size_t es, int a_in_lds) {
+    const size_t ne = (size_t)spw * NC;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = cp_align(o + bytes); return at; };
+    A = take(a_in_lds ? (size_t)spw * 5 * NC * NC * es : 0);
+    Vb = take((size_t)(mm + 1) * ne * es);
+    DVb = take((size_t)(k + 1) * ne * es);
+    xl = take(ne * es);
+    rl = take(ne * es);
+    wl = take(ne * es);
+    xs = take((size_t)spw * 5 * NC * es);
+    part = take((size_t)spw * 5 * NC * sizeof(double2));
+    Hr = take((size_t)(mm + 1) * mm * sizeof(double2));
+    rc = take((size_t)mm * sizeof(double));
+    rs = take((size_t)mm * sizeof(double2));
+    const size_t sv = (size_t)((mm > k ? mm : k) + 1) * sizeof(double2);  // also holds projection vectors
+    g = take(sv);
+    y = take(sv);
+    u = take(sv);
+    Hk = take((size_t)(k + 1) * k * sizeof(double2));
+    Rk = take((size_t)(k + 1) * k * sizeof(double2));
+    kc = take((size_t)(k * (k + 1) / 2 + 1) * sizeof(double));
+    ks = take((size_t)(k * (k + 1) / 2 + 1) * sizeof(double2));
+    kp = take((size_t)(k * (k + 1) / 2 + 1) * sizeof(int));
+    red = take((size_t)CP_QMAX * CP_WAVES * sizeof(double2));
+    cs = take((size_t)CP_QMAX * CP_CHUNKS * sizeof(double2));
+    res = take((size_t)(CP_QMAX + 2) * sizeof(double2));
+    tot = o;
+  }
+};
+
+__device__ inline double2 cp_wave_sum(double2 v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    v.x += __shfl_xor(v.x, off, 64);
+    v.y += __shfl_xor(v.y, off, 64);
+  }
+  return v;
+}
+
+__device__ inline void cp_givens(double2 a, double2 b, double& c, double2& s) {
+  const double na = sqrt(cabs2(a)), nb = sqrt(cabs2(b));
+  if (nb == 0.0) { c = 1.0; s = mk(0.0, 0.0); return; }
+  if (na == 0.0) { c = 0.0; s = cscale(cconj(b), 1.0 / nb); return; }
+  const double nr = sqrt(na * na + nb * nb);
+  c = na / nr;
+  s = cscale(cmul(cconj(b), a), 1.0 / (na * nr));
+}
+__device__ inline double2 cp_div(double2 a, double2 b) {
+  const double d = cabs2(b);
+  return mk((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+
+template <typename R, bool ALDS>
+__global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
+  using T = cx<R>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  unsigned gen = 0;
+  const int G = gridDim.x, gi = blockIdx.x, tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int V = a.Lx * a.Lt;
+  const int S0 = gi * a.spw;
+  const int nsl = min(a.spw, V - S0);
+  const int ne = nsl * NC;
+  const int mm = a.mm, k = a.k;
+  const CPLayout L(a.spw, mm, k, sizeof(T), ALDS ? 1 : 0);
+  T* Ab = (T*)(smem + L.A);
+  T* Vb = (T*)(smem + L.Vb);
+  T* DVb = (T*)(smem + L.DVb);
+  T* xl = (T*)(smem + L.xl);
+  T* rl = (T*)(smem + L.rl);
+  T* wl = (T*)(smem + L.wl);
+  T* xs = (T*)(smem + L.xs);
+  double2* part = (double2*)(smem + L.part);
+  double2* Hr = (double2*)(smem + L.Hr);
+  double* rc = (double*)(smem + L.rc);
+  double2* rs = (double2*)(smem + L.rs);
+  double2* gv = (double2*)(smem + L.g);
+  double2* yv = (double2*)(smem + L.y);
+  double2* uv = (double2*)(smem + L.u);
+  double2* Hk = (double2*)(smem + L.Hk);
+  double2* Rk = (double2*)(smem + L.Rk);
+  double* kc = (double*)(smem + L.kc);
+  double2* ksn = (double2*)(smem + L.ks);
+  int* kp = (int*)(smem + L.kp);
+  double2(*red)[CP_WAVES] = (double2(*)[CP_WAVES])(smem + L.red);
+  double2(*csum)[CP_CHUNKS] = (double2(*)[CP_CHUNKS])(smem + L.cs);
+  double2* res = (double2*)(smem + L.res);
+  __shared__ double sh_scal[8];
+  __shared__ int sh_flag[4];
+
+  const T* Ag = (const T*)a.A;
+  const T* DVg = (const T*)a.DV;
+  const T* bg = (const T*)a.b;
+  T* xg = (T*)a.x;
+  T* xch = (T*)a.xchg;
+  const int64_t n = (int64_t)V * NC;
+  const int64_t e0 = (int64_t)S0 * NC;
+  int rbuf = 0;
+
+  // ---------------------------------------------------------------- reduction helpers
+  // Each thread adds its contribution for quantity q; after all quantities, wg_finish
+  // publishes the workgroup sums and the grid-wide sums land in res[q].
+  auto contrib = [&](int q, double2 v) {
+    v = cp_wave_sum(v);
+    if (lane == 0) red[q][wave] = v;
+  };
+  auto grid_reduce = [&](int nq) {
+    __syncthreads();
+    double2* P = a.partials + (size_t)rbuf * CP_QMAX * G;
+    if (tid < nq) {
+      double2 s = red[tid][0];
+      for (int w = 1; w < CP_WAVES; ++w) s = cadd(s, red[tid][w]);
+      P[(size_t)tid * G + gi] = s;
+    }
+    cp_barrier(a.flags, G, ++gen, a.err);
+    const int q = tid / CP_CHUNKS, c = tid % CP_CHUNKS;
+    if (q < nq) {
+      const int per = (G + CP_CHUNKS - 1) / CP_CHUNKS;
+      const int lo = c * per, hi = min(G, lo + per);
+      double2 s = mk(0.0, 0.0);
+      for (int b = lo; b < hi; ++b) s = cadd(s, P[(size_t)q * G + b]);
+      csum[q][c] = s;
+    }
+    __syncthreads();
+    if (tid < nq) {
+      double2 s = csum[tid][0];
+      for (int c2 = 1; c2 < CP_CHUNKS; ++c2) s = cadd(s, csum[tid][c2]);
+      res[tid] = s;
+    }
+    __syncthreads();
+    rbuf ^= 1;
+  };
+
+  // ---------------------------------------------------------------- load the resident data
+  if (ALDS) {
+    const T* src = Ag + (int64_t)S0 * 5 * NC * NC;
+    for (int t = tid; t < nsl * 5 * NC * NC; t += CP_THREADS) Ab[t] = src[t];
+  }
+  for (int t = tid; t < (k + 1) * ne; t += CP_THREADS) {
+    const int i = t / ne, e = t % ne;
+    DVb[t] = DVg[(int64_t)i * n + e0 + e];
+  }
+  for (int t = tid; t < ne; t += CP_THREADS) {
+    rl[t] = bg[e0 + t];
+    xl[t] = make_cx<R>(R(0), R(0));
+  }
+  for (int t = tid; t < (k + 1) * k; t += CP_THREADS) Hk[t] = a.DH[t];
+  __syncthreads();
+  // Givens QR of Hbar_k (identical in every workgroup)
+  if (tid == 0) {
+    for (int t = 0; t < (k + 1) * k; ++t) Rk[t] = Hk[t];
+    int nr = 0;
+    for (int jc = 0; jc < k; ++jc)
+      for (int r = k; r > jc; --r) {
+        double c;
+        double2 s;
+        cp_givens(Rk[r - 1 + (k + 1) * jc], Rk[r + (k + 1) * jc], c, s);
+        for (int q = jc; q < k; ++q) {
+          const double2 x0 = Rk[r - 1 + (k + 1) * q], x1 = Rk[r + (k + 1) * q];
+          Rk[r - 1 + (k + 1) * q] = cadd(cscale(x0, c), cmul(s, x1));
+          Rk[r + (k + 1) * q] = csub(cscale(x1, c), cmul(cconj(s), x0));
+        }
+        Rk[r + (k + 1) * jc] = mk(0.0, 0.0);
+        kc[nr] = c;
+        ksn[nr] = s;
+        kp[nr] = r - 1;
+        ++nr;
+      }
+  }
+  // ||b||
+  {
+    double2 v = mk(0.0, 0.0);
+    for (int t = tid; t < ne; t += CP_THREADS) v.x += cabs2(to_d(rl[t]));
+    contrib(0, v);
+    grid_reduce(1);
+  }
+  const double bnorm = sqrt(res[0].x);
+  const double tol_abs = a.tol * bnorm;
+  int iters = 0;
+  bool converged = bnorm == 0.0;
+  double est = bnorm;
+
+  while (!converged && iters < a.max_iters) {
+    // ------------------------------------------------------------ projection over V_{k+1}
+    for (int i = 0; i <= k; ++i) {
+      double2 v = mk(0.0, 0.0);
+      for (int t = tid; t < ne; t += CP_THREADS) cfmac(v, to_d(DVb[i * ne + t]), to_d(rl[t]));
+      contrib(i, v);
+    }
+    grid_reduce(k + 1);
+    if (tid == 0) {
+      // d = argmin || c - Hk d || via the stored rotations
+      for (int i = 0; i <= k; ++i) uv[i] = res[i];
+      for (int q = 0; q < k * (k + 1) / 2; ++q) {
+        const int p = kp[q];
+        const double2 x0 = uv[p], x1 = uv[p + 1];
+        uv[p] = cadd(cscale(x0, kc[q]), cmul(ksn[q], x1));
+        uv[p + 1] = csub(cscale(x1, kc[q]), cmul(cconj(ksn[q]), x0));
+      }
+      for (int i = k - 1; i >= 0; --i) {
+        double2 acc = uv[i];
+        for (int l = i + 1; l < k; ++l) acc = csub(acc, cmul(Rk[i + (k + 1) * l], yv[l]));
+        const double2 d = Rk[i + (k + 1) * i];
+        yv[i] = cabs2(d) > 0.0 ? cp_div(acc, d) : mk(0.0, 0.0);
+      }
+      for (int i = 0; i <= k; ++i) {
+        double2 acc = mk(0.0, 0.0);
+        for (int l = 0; l < k; ++l) cfma(acc, Hk[i + (k + 1) * l], yv[l]);
+        uv[i] = acc;
+      }
+    }
+    __syncthreads();
+    for (int t = tid; t < ne; t += CP_THREADS) {
+      double2 xv = to_d(xl[t]), rv = to_d(rl[t]);
+      for (int i = 0; i < k; ++i) cfma(xv, yv[i], to_d(DVb[i * ne + t]));
+      for (int i = 0; i <= k; ++i) rv = csub(rv, cmul(uv[i], to_d(DVb[i * ne + t])));
+      xl[t] = from_d<R>(xv);
+      rl[t] = from_d<R>(rv);
+      xch[e0 + t] = from_d<R>(rv);
+    }
+    // ------------------------------------------------------------ GMRES(mm) cycle from r
+    {
+      double2 v = mk(0.0, 0.0);
+      for (int t = tid; t < ne; t += CP_THREADS) v.x += cabs2(to_d(rl[t]));
+      contrib(0, v);
+      grid_reduce(1);
+    }
+    double hprev = sqrt(res[0].x);  // beta; xchg holds the unnormalised start vector
+    est = hprev;
+    if (hprev <= tol_abs || hprev == 0.0) {
+      converged = true;
+      break;
+    }
+    if (tid == 0) {
+      for (int i = 0; i <= mm; ++i) gv[i] = mk(0.0, 0.0);
+      gv[0] = mk(hprev, 0.0);
+    }
+    int steps = 0;
+    bool brk = false, stop = false;
+    // cancellation below which the Pythagorean norm is replaced by a second pass
+    const double eta = sizeof(R) == sizeof(float) ? 1e-4 : 1e-8;
+    for (int j = 0; j < mm; ++j) {
+      // xchg holds hprev * v_j (written before the last barrier)
+      const double inv = 1.0 / hprev;
+      for (int t = tid; t < ne; t += CP_THREADS) {
+        const T src = (j == 0) ? rl[t] : wl[t];
+        Vb[j * ne + t] = from_d<R>(cscale(to_d(src), inv));
+      }
+      for (int t = tid; t < nsl * 5 * NC; t += CP_THREADS) {
+        const int sl = t / (5 * NC), d = (t / NC) % 5, jj = t % NC;
+        const int S = S0 + sl, X = S % a.Lx, Tt = S / a.Lx;
+        int nb;
+        switch (d) {
+          case 0: nb = S; break;
+          case 1: nb = ((X + 1 == a.Lx) ? 0 : X + 1) + a.Lx * Tt; break;
+          case 2: nb = ((X == 0) ? a.Lx - 1 : X - 1) + a.Lx * Tt; break;
+          case 3: nb = X + a.Lx * ((Tt + 1 == a.Lt) ? 0 : Tt + 1); break;
+          default: nb = X + a.Lx * ((Tt == 0) ? a.Lt - 1 : Tt - 1); break;
+        }
+        xs[t] = xch[(int64_t)nb * NC + jj];
+      }
+      __syncthreads();
+      for (int t = tid; t < nsl * 5 * NC; t += CP_THREADS) {
+        const int sl = t / (5 * NC), d = (t / NC) % 5, i = t % NC;
+        const T* blk = ALDS ? (Ab + ((int64_t)sl * 5 + d) * NC * NC) : (Ag + ((int64_t)(S0 + sl) * 5 + d) * NC * NC);
+        const T* xv = xs + (sl * 5 + d) * NC;
+        double2 acc = mk(0.0, 0.0);
+#pragma unroll 8
+        for (int jj = 0; jj < NC; ++jj) cfma(acc, to_d(blk[jj * NC + i]), to_d(xv[jj]));
+        part[t] = acc;
+      }
+      __syncthreads();
+      for (int t = tid; t < ne; t += CP_THREADS) {
+        const int sl = t / NC, i = t % NC;
+        double2 y = part[(sl * 5 + 0) * NC + i];
+        for (int d = 1; d < 5; ++d) y = cadd(y, part[(sl * 5 + d) * NC + i]);
+        wl[t] = from_d<R>(cscale(y, inv));
+      }
+      __syncthreads();
+      // h_i = V_i^H w (i <= j) and ||w||^2 in one reduction
+      for (int i = 0; i <= j + 1; ++i) {
+        double2 v = mk(0.0, 0.0);
+        if (i <= j) {
+          for (int t = tid; t < ne; t += CP_THREADS) cfmac(v, to_d(Vb[i * ne + t]), to_d(wl[t]));
+        } else {
+          for (int t = tid; t < ne; t += CP_THREADS) v.x += cabs2(to_d(wl[t]));
+        }
+        contrib(i, v);
+      }
+      grid_reduce(j + 2);
+      const double ww = res[j + 1].x;
+      double hh = 0.0;
+      for (int i = 0; i <= j; ++i) hh += cabs2(res[i]);
+      double hn2 = ww - hh;
+      if (tid <= j) {
+        Hr[tid + (mm + 1) * j] = res[tid];
+        uv[tid] = res[tid];
+      }
+      __syncthreads();
+      for (int t = tid; t < ne; t += CP_THREADS) {
+        double2 w = to_d(wl[t]);
+        for (int i = 0; i <= j; ++i) w = csub(w, cmul(uv[i], to_d(Vb[i * ne + t])));
+        wl[t] = from_d<R>(w);
+      }
+      __syncthreads();
+      if (!(hn2 > eta * ww)) {
+        // heavy cancellation: second Gram-Schmidt pass with the exact norm of the first
+        for (int i = 0; i <= j + 1; ++i) {
+          double2 v = mk(0.0, 0.0);
+          if (i <= j) {
+            for (int t = tid; t < ne; t += CP_THREADS) cfmac(v, to_d(Vb[i * ne + t]), to_d(wl[t]));
+          } else {
+            for (int t = tid; t < ne; t += CP_THREADS) v.x += cabs2(to_d(wl[t]));
+          }
+          contrib(i, v);
+        }
+        grid_reduce(j + 2);
+        double hh2 = 0.0;
+        for (int i = 0; i <= j; ++i) hh2 += cabs2(res[i]);
+        hn2 = res[j + 1].x - hh2;
+        if (tid <= j) {
+          Hr[tid + (mm + 1) * j] = cadd(Hr[tid + (mm + 1) * j], res[tid]);
+          uv[tid] = res[tid];
+        }
+        __syncthreads();
+        for (int t = tid; t < ne; t += CP_THREADS) {
+          double2 w = to_d(wl[t]);
+          for (int i = 0; i <= j; ++i) w = csub(w, cmul(uv[i], to_d(Vb[i * ne + t])));
+          wl[t] = from_d<R>(w);
+        }
+        __syncthreads();
+      }
+      double hn = sqrt(fmax(hn2, 0.0));
+      if (!(hn > 1e-12 * sqrt(ww))) { hn = 0.0; brk = true; }
+      if (tid == 0) {
+        double2* col = Hr + (mm + 1) * j;
+        col[j + 1] = mk(hn, 0.0);
+        for (int q = 0; q < j; ++q) {
+          const double2 x0 = col[q], x1 = col[q + 1];
+          col[q] = cadd(cscale(x0, rc[q]), cmul(rs[q], x1));
+          col[q + 1] = csub(cscale(x1, rc[q]), cmul(cconj(rs[q]), x0));
+        }
+        double c;
+        double2 sg;
+        cp_givens(col[j], col[j + 1], c, sg);
+        col[j] = cadd(cscale(col[j], c), cmul(sg, col[j + 1]));
+        col[j + 1] = mk(0.0, 0.0);
+        rc[j] = c;
+        rs[j] = sg;
+        const double2 g0 = gv[j], g1 = gv[j + 1];
+        gv[j] = cadd(cscale(g0, c), cmul(sg, g1));
+        gv[j + 1] = csub(cscale(g1, c), cmul(cconj(sg), g0));
+        sh_scal[0] = sqrt(cabs2(gv[j + 1]));
+      }
+      __syncthreads();
+      est = brk ? 0.0 : sh_scal[0];
+      steps = j + 1;
+      hprev = hn;
+      if (brk || est <= tol_abs || iters + steps >= a.max_iters) { stop = true; break; }
+      if (j + 1 < mm) {
+        // publish hprev * v_{j+1} for the next stencil
+        for (int t = tid; t < ne; t += CP_THREADS) xch[e0 + t] = wl[t];
+        cp_barrier(a.flags, G, ++gen, a.err);
+      }
+    }
+    // ------------------------------------------------------------ end of cycle: x += V y, r = V u
+    if (tid == 0) {
+      for (int i = steps - 1; i >= 0; --i) {
+        double2 acc = gv[i];
+        for (int l = i + 1; l < steps; ++l) acc = csub(acc, cmul(Hr[i + (mm + 1) * l], yv[l]));
+        const double2 d = Hr[i + (mm + 1) * i];
+        yv[i] = cabs2(d) > 0.0 ? cp_div(acc, d) : mk(0.0, 0.0);
+      }
+      // residual coordinates: u = Omega^H (g_steps e_steps)
+      for (int i = 0; i <= steps; ++i) uv[i] = mk(0.0, 0.0);
+      uv[steps] = brk ? mk(0.0, 0.0) : gv[steps];
+      for (int q = steps - 1; q >= 0; --q) {
+        const double2 x0 = uv[q], x1 = uv[q + 1];
+        // inverse of [c s; -conj(s) c] is [c -s; conj(s) c]
+        uv[q] = csub(cscale(x0, rc[q]), cmul(rs[q], x1));
+        uv[q + 1] = cadd(cmul(cconj(rs[q]), x0), cscale(x1, rc[q]));
+      }
+    }
+    __syncthreads();
+    const double invn = hprev > 0.0 ? 1.0 / hprev : 0.0;
+    for (int t = tid; t < ne; t += CP_THREADS) {
+      double2 xv = to_d(xl[t]);
+      double2 rv = mk(0.0, 0.0);
+      for (int i = 0; i < steps; ++i) {
+        const double2 vi = to_d(Vb[i * ne + t]);
+        cfma(xv, yv[i], vi);
+        cfma(rv, uv[i], vi);
+      }
+      cfma(rv, uv[steps], cscale(to_d(wl[t]), invn));
+      xl[t] = from_d<R>(xv);
+      rl[t] = from_d<R>(rv);
+    }
+    __syncthreads();
+    iters += steps;
+    if (brk || est <= tol_abs) converged = true;
+    if (stop && !converged) break;  // iteration cap
+  }
+  for (int t = tid; t < ne; t += CP_THREADS) xg[e0 + t] = xl[t];
+  if (gi == 0 && tid == 0) {
+    a.out_iters[0] = iters;
+    a.out_relres[0] = bnorm > 0.0 ? est / bnorm : 0.0;
+  }
+}
+
+size_t coarse_proj_lds(int spw, int mm, int k, size_t es, int a_in_lds) {
+  return CPLayout(spw, mm, k, es, a_in_lds).tot;
+}
+
+template <typename R>
+static int try_launch(hipStream_t st, CPArgs& a, int G, size_t lds, bool alds) {
+  void* args[] = {&a};
+  const void* fn = alds ? (const void*)k_coarse_proj<R, true> : (const void*)k_coarse_proj<R, false>;
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, CP_THREADS, lds) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  int dev = 0, ncu = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (per_cu < 1 || G > per_cu * ncu) return 0;
+  if (hipMemsetAsync(a.flags, 0, sizeof(unsigned) * CP_FLAGPAD * G, st) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  hipError_t e = hipLaunchCooperativeKernel(fn, dim3(G), dim3(CP_THREADS), args, (unsigned)lds, st);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return 1;
+}
+
+size_t coarse_proj_flag_words(int G) { return (size_t)CP_FLAGPAD * G; }
+
+// Returns 1 if the persistent kernel was launched, 0 if it cannot run co-resident here
+// (the caller then uses the multi-kernel path).  `groups` is the target number of
+// workgroups (0: 32).
+template <typename R>
+int launch_coarse_proj(hipStream_t st, const cx<R>* A, int Lx, int Lt, const cx<R>* DV, const double2* DH, int k,
+                       const cx<R>* b, cx<R>* x, double tol, int mm, int max_iters, cx<R>* xchg,
+                       double2* partials, size_t partials_elems, int* out_iters, double* out_relres,
+                       unsigned* flags, size_t flag_words, int* err, int groups) {
+  if (mm + 2 > CP_QMAX || k + 1 > CP_QMAX || mm < 1) return 0;
+  const int V = Lx * Lt;
+  const size_t lds_max = 160 * 1024;
+  if (groups <= 0) groups = 32;
+  int spw = (V + groups - 1) / groups;
+  if (spw > 10) spw = 10;  // one thread per local entry
+  const int G = (V + spw - 1) / spw;
+  if ((size_t)2 * CP_QMAX * G > partials_elems || (size_t)CP_FLAGPAD * G > flag_words) return 0;
+  for (int alds = 1; alds >= 0; --alds) {
+    const size_t lds = coarse_proj_lds(spw, mm, k, sizeof(cx<R>), alds);
+    if (lds > lds_max) continue;
+    CPArgs a{A, Lx, Lt, DV, DH, k, b, x, tol, mm, max_iters, xchg, partials, out_iters, out_relres,
+             flags, err, spw, alds};
+    if (try_launch<R>(st, a, G, lds, alds == 1)) return 1;
+  }
+  return 0;
+}
+
+template int launch_coarse_proj<double>(hipStream_t, const double2*, int, int, const double2*, const double2*, int,
+                                        const double2*, double2*, double, int, int, double2*, double2*, size_t,
+                                        int*, double*, unsigned*, size_t, int*, int);
+template int launch_coarse_proj<float>(hipStream_t, const float2*, int, int, const float2*, const double2*, int,
+                                       const float2*, float2*, double, int, int, float2*, double2*, size_t, int*,
+                                       double*, unsigned*, size_t, int*, int);
+
+}  // namespace dmg

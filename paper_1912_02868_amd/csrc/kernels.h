@@ -92,6 +92,18 @@ void launch_qr_block(hipStream_t s, KState* ks, int k);
 // stored deflation matrix Hk ((k+1) x k column-major, ld k+1); y = d, u = Hbar_k d.
 void launch_proj_solve(hipStream_t s, const double2* Hk, int k, KState* ks);
 
+// ---------------------------------------------------------------- persistent coarse solve (coarse.hip)
+// One cooperative launch per GMRES-Proj(m, k) coarse solve from x = 0.  Returns 0 (nothing
+// launched) when the grid cannot be co-resident; out_iters / out_relres receive the Arnoldi
+// steps taken and the final recurrence residual relative to ||b||.  flags: barrier words
+// (coarse_proj_flag_words(G) needed, zeroed by the launcher); err: set on a barrier timeout.
+template <typename R>
+int launch_coarse_proj(hipStream_t st, const cx<R>* A, int Lx, int Lt, const cx<R>* DV, const double2* DH, int k,
+                       const cx<R>* b, cx<R>* x, double tol, int mm, int max_iters, cx<R>* xchg,
+                       double2* partials, size_t partials_elems, int* out_iters, double* out_relres,
+                       unsigned* flags, size_t flag_words, int* err, int groups);
+size_t coarse_proj_flag_words(int G);
+
 // ---------------------------------------------------------------- setup (setup.hip)
 // Batched CG on A A^dagger for nvec fields (x, r, p, q stored as nvec consecutive fields).
 void launch_cg_scalars(hipStream_t s, int nvec, const double* pq, const double* rr_new, double* rr, double* alpha,

@@ -322,6 +322,8 @@ struct Precond {
   DevBuf bc, ec, bc64, ec64, pr;   // coarse vectors
   KWS proj;                        // GMRES-Proj cycles
   int proj_m = 0;
+  DevBuf xchg;                     // exchange field of the persistent coarse solve
+  DevBuf bflags;                   // its grid-barrier flags
   const dmg_solve_params* p = nullptr;
   dmg_deflation* defl = nullptr;
 
@@ -393,6 +395,27 @@ struct Precond {
     const int mm = std::max(d->m - k, 1);
     const T* DV = dvec(d);
     const double2* DH = d->H.as<double2>();
+    if (p->coarse_persistent) {
+      if (!xchg.p) xchg.alloc(h->ctx, sizeof(T) * n);
+      int* it_d = h->flags.as<int>() + 8;
+      double* rr_d = (double*)(h->flags.as<int>() + 16);
+      const T* Ab = (const T*)(sizeof(R) == sizeof(double) ? (const void*)A.A64 : (const void*)A.A32);
+      if (!bflags.p) bflags.alloc(h->ctx, sizeof(unsigned) * coarse_proj_flag_words(256));
+      int* err_d = h->flags.as<int>() + 9;  // read back together with the step count
+      if (launch_coarse_proj<R>(S(), Ab, A.Lx, A.Lt, DV, DH, k, b, x, tol, mm, p->coarse_max_iters,
+                                xchg.as<T>(), PART(h), h->partials.bytes / sizeof(double2), it_d, rr_d,
+                                bflags.as<unsigned>(), bflags.bytes / sizeof(unsigned), err_d, 0)) {
+        DMG_HIP(hipMemcpyAsync(h->host_status, it_d, 4 * sizeof(int), hipMemcpyDeviceToHost, S()));
+        DMG_HIP(hipStreamSynchronize(S()));
+        const int* hs = (const int*)h->host_status;
+        if (hs[1] != 0) {
+          DMG_HIP(hipMemsetAsync(err_d, 0, sizeof(int), S()));
+          DMG_CHECK(false, DMG_E_HIP, "persistent coarse solve: a grid-barrier wait timed out");
+        }
+        h->cnt.mv[2] += hs[0];
+        return;
+      }
+    }
     KState* ks = proj.state();
     T* V = proj.V.as<T>();
     T* rr = pr.as<T>();

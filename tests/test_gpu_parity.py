@@ -261,3 +261,28 @@ def test_solve_zero_rhs_and_cap(dmg, ctx, injected):
     b = synth.rhs(16, 0, 0)
     st, stats = dmg.solve(ctx, hg, d, b, x, params=dmg.solve_params(tol=1e-17, max_outer_iters=3))
     assert st == dmg.DMG_W_NOT_CONVERGED and stats[0]["outer_iters"] == 3
+
+
+@pytest.mark.parametrize("precond", [0, 1])
+def test_persistent_coarse_matches_multikernel(dmg, ctx, injected, precond):
+    """The one-launch GMRES-Proj coarse solve and the kernel-per-step path agree."""
+    N, th, m0, H, g, hg = injected
+    if N != 64:
+        pytest.skip("workload-sized solve")
+    D = H.levels[0].A
+    out = {}
+    for persistent in (0, 1):
+        d = dmg.Deflation(hg, 30, 10)
+        xs, ss = [], []
+        for j in range(2):
+            b = synth.rhs(64, 0, j)
+            st, s, x, res = _solve_and_check(dmg, ctx, hg, D, b, d, precond=precond, coarse_persistent=persistent)
+            assert st == dmg.DMG_OK and res <= 1e-8
+            xs.append(x)
+            ss.append(s)
+        out[persistent] = (xs, ss)
+    for j in range(2):
+        assert _rel(out[1][0][j], out[0][0][j]) < 1e-6
+        assert abs(out[1][1][j]["outer_iters"] - out[0][1][j]["outer_iters"]) <= 1
+        c0, c1 = out[0][1][j]["coarse_mvps"], out[1][1][j]["coarse_mvps"]
+        assert abs(c1 - c0) <= 0.1 * c0 + 5
