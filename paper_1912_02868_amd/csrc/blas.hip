@@ -9,7 +9,9 @@ namespace dmg {
 
 constexpr int RB = 256;          // threads per reduction workgroup
 constexpr int RW = RB / 64;      // wavefronts per reduction workgroup
-constexpr int MAXRED = 512;      // largest reduction grid
+constexpr int MAXRED = 128;      // largest reduction grid (the last workgroup adds <= RB partials per quantity)
+constexpr int QB = 8;            // quantities whose loads are issued together
+constexpr int NROT_LDS = 128;    // Givens rotations staged in LDS by the update
 
 int red_blocks(int64_t n) {
   int64_t b = (n + RB - 1) / RB;
@@ -27,7 +29,7 @@ __device__ inline double2 wave_sum(double2 v) {
   return v;
 }
 
-// Sum `v` over the workgroup for quantity q; result valid in lds[0][q] after the caller's barrier.
+// Sum `v` over the workgroup for quantity q; result valid through wg_result after a barrier.
 __device__ inline void wg_accumulate(double2 (*lds)[MMAX + 2], int q, double2 v) {
   v = wave_sum(v);
   if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6][q] = v;
@@ -56,47 +58,126 @@ __device__ inline bool last_block(unsigned* counter) {
   return am_last != 0;
 }
 
-// ---------------------------------------------------------------- Givens update (one thread)
+// Per-workgroup partial dots conj(V_i) . w for i < nv (and ||w||^2 as quantity nv when
+// with_norm), QB quantities per pass so their loads are in flight together.  Leaves the
+// workgroup sums in lds (read with wg_result after a barrier).
+template <typename R>
+__device__ void block_dots(const cx<R>* __restrict__ V, int64_t ld, int nv, const cx<R>* __restrict__ w, int64_t n,
+                           bool with_norm, double2 (*lds)[MMAX + 2]) {
+  const int64_t stride = (int64_t)gridDim.x * RB;
+  const int64_t e0 = (int64_t)blockIdx.x * RB + threadIdx.x;
+  for (int i0 = 0; i0 < nv; i0 += QB) {
+    double2 acc[QB];
+#pragma unroll
+    for (int u = 0; u < QB; ++u) acc[u] = mk(0.0, 0.0);
+    for (int64_t e = e0; e < n; e += stride) {
+      const double2 wv = to_d(w[e]);
+      double2 vv[QB];
+#pragma unroll
+      for (int u = 0; u < QB; ++u) vv[u] = (i0 + u < nv) ? to_d(V[(int64_t)(i0 + u) * ld + e]) : mk(0.0, 0.0);
+#pragma unroll
+      for (int u = 0; u < QB; ++u) cfmac(acc[u], vv[u], wv);
+    }
+#pragma unroll
+    for (int u = 0; u < QB; ++u)
+      if (i0 + u < nv) wg_accumulate(lds, i0 + u, acc[u]);
+  }
+  if (with_norm) {
+    double2 acc = mk(0.0, 0.0);
+    for (int64_t e = e0; e < n; e += stride) acc.x += cabs2(to_d(w[e]));
+    wg_accumulate(lds, nv, acc);
+  }
+}
+
+// Publish the workgroup sums of quantities q < nq as partials[q][blockIdx].
+__device__ inline void publish(double2 (*lds)[MMAX + 2], int nq, double2* partials) {
+  __syncthreads();
+  for (int q = threadIdx.x; q < nq; q += RB) partials[(int64_t)q * gridDim.x + blockIdx.x] = wg_result(lds, q);
+}
+
+// In the last workgroup: res[q] = sum over workgroups of partials[q][b], in a fixed order,
+// with all threads loading.  res is in LDS; ends with a barrier.
+__device__ void last_sums(const double2* partials, int nq, double2 (*lds)[MMAX + 2], double2* res) {
+  const int nblk = gridDim.x;
+  const int t = threadIdx.x;
+  for (int q0 = 0; q0 < nq; q0 += QB) {
+    double2 v[QB];
+#pragma unroll
+    for (int u = 0; u < QB; ++u) v[u] = (q0 + u < nq && t < nblk) ? partials[(int64_t)(q0 + u) * nblk + t] : mk(0.0, 0.0);
+#pragma unroll
+    for (int u = 0; u < QB; ++u)
+      if (q0 + u < nq) wg_accumulate(lds, q0 + u, v[u]);
+  }
+  __syncthreads();
+  for (int q = t; q < nq; q += RB) res[q] = wg_result(lds, q);
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- Givens update
+// Column j of the Hessenberg (already in ks->H) is rotated by the stored rotations and a
+// new one that annihilates its subdiagonal; the right-hand side g follows.  All threads of
+// the workgroup stage the column and the rotations in LDS; thread 0 does the serial part.
 __device__ void givens_update(KState* ks, int j) {
   constexpr int LD = MMAX + 1;
-  double2* col = ks->H + (int64_t)LD * j;
-  double2* r = ks->R + (int64_t)LD * j;
-  for (int i = 0; i <= j + 1; ++i) r[i] = col[i];
-  for (int q = 0; q < ks->nrot; ++q) {
-    const int p = ks->rot_p[q];
-    if (p + 1 > j + 1) continue;
-    const double c = ks->rot_c[q];
-    const double2 s = ks->rot_s[q];
-    const double2 a = r[p], b = r[p + 1];
-    r[p] = cadd(cscale(a, c), cmul(s, b));
-    r[p + 1] = csub(cscale(b, c), cmul(cconj(s), a));
+  __shared__ double2 col[MMAX + 2];
+  __shared__ double rcs[NROT_LDS];
+  __shared__ double2 rss[NROT_LDS];
+  __shared__ int rps[NROT_LDS];
+  __shared__ double2 gg[2];
+  const int t = threadIdx.x;
+  const int nrot = ks->nrot;
+  for (int i = t; i <= j + 1; i += RB) col[i] = ks->H[LD * j + i];
+  for (int q = t; q < nrot && q < NROT_LDS; q += RB) {
+    rcs[q] = ks->rot_c[q];
+    rss[q] = ks->rot_s[q];
+    rps[q] = ks->rot_p[q];
   }
-  // new rotation on rows (j, j+1) zeroing r[j+1]
-  const double2 a = r[j], b = r[j + 1];
-  const double na = sqrt(cabs2(a)), nb = sqrt(cabs2(b));
-  double c;
-  double2 s;
-  if (nb == 0.0) {
-    c = 1.0; s = mk(0.0, 0.0);
-  } else if (na == 0.0) {
-    c = 0.0; s = cscale(cconj(b), 1.0 / nb);
-  } else {
-    const double nr = sqrt(na * na + nb * nb);
-    c = na / nr;
-    s = cscale(cmul(cconj(b), a), 1.0 / (na * nr));
+  if (t == 0) {
+    gg[0] = ks->g[j];
+    gg[1] = ks->g[j + 1];
   }
-  r[j] = cadd(cscale(a, c), cmul(s, b));
-  r[j + 1] = mk(0.0, 0.0);
-  const double2 gj = ks->g[j], gj1 = ks->g[j + 1];
-  ks->g[j] = cadd(cscale(gj, c), cmul(s, gj1));
-  ks->g[j + 1] = csub(cscale(gj1, c), cmul(cconj(s), gj));
-  const int q = ks->nrot;
-  ks->rot_p[q] = j;
-  ks->rot_c[q] = c;
-  ks->rot_s[q] = s;
-  ks->nrot = q + 1;
-  ks->est = sqrt(cabs2(ks->g[j + 1]));
-  ks->steps = j + 1;
+  __syncthreads();
+  if (t == 0) {
+    for (int q = 0; q < nrot; ++q) {
+      const bool in_lds = q < NROT_LDS;
+      const int p = in_lds ? rps[q] : ks->rot_p[q];
+      if (p + 1 > j + 1) continue;
+      const double c = in_lds ? rcs[q] : ks->rot_c[q];
+      const double2 s = in_lds ? rss[q] : ks->rot_s[q];
+      const double2 a = col[p], b = col[p + 1];
+      col[p] = cadd(cscale(a, c), cmul(s, b));
+      col[p + 1] = csub(cscale(b, c), cmul(cconj(s), a));
+    }
+    // new rotation on rows (j, j+1) zeroing col[j+1]
+    const double2 a = col[j], b = col[j + 1];
+    const double na = sqrt(cabs2(a)), nb = sqrt(cabs2(b));
+    double c;
+    double2 s;
+    if (nb == 0.0) {
+      c = 1.0; s = mk(0.0, 0.0);
+    } else if (na == 0.0) {
+      c = 0.0; s = cscale(cconj(b), 1.0 / nb);
+    } else {
+      const double nr = sqrt(na * na + nb * nb);
+      c = na / nr;
+      s = cscale(cmul(cconj(b), a), 1.0 / (na * nr));
+    }
+    col[j] = cadd(cscale(a, c), cmul(s, b));
+    col[j + 1] = mk(0.0, 0.0);
+    const double2 gj = gg[0], gj1 = gg[1];
+    const double2 ng0 = cadd(cscale(gj, c), cmul(s, gj1));
+    const double2 ng1 = csub(cscale(gj1, c), cmul(cconj(s), gj));
+    ks->g[j] = ng0;
+    ks->g[j + 1] = ng1;
+    ks->rot_p[nrot] = j;
+    ks->rot_c[nrot] = c;
+    ks->rot_s[nrot] = s;
+    ks->nrot = nrot + 1;
+    ks->est = sqrt(cabs2(ng1));
+    ks->steps = j + 1;
+  }
+  __syncthreads();
+  for (int i = t; i <= j + 1; i += RB) ks->R[LD * j + i] = col[i];
 }
 
 // ---------------------------------------------------------------- Arnoldi kernels
@@ -106,27 +187,18 @@ __global__ void __launch_bounds__(RB) k_arn_dots1(const cx<R>* __restrict__ V, i
                                                   KState* ks, double2* partials, unsigned* counter) {
   if (ks->done) return;
   __shared__ double2 lds[RW][MMAX + 2];
+  __shared__ double2 res[MMAX + 2];
   const cx<R>* w = V + (int64_t)(j + 1) * ld;
-  const int64_t stride = (int64_t)gridDim.x * RB;
-  const int64_t e0 = (int64_t)blockIdx.x * RB + threadIdx.x;
-  for (int i = 0; i <= j + 1; ++i) {
-    const cx<R>* vi = V + (int64_t)i * ld;
-    double2 acc = mk(0.0, 0.0);
-    for (int64_t e = e0; e < n; e += stride) cfmac(acc, to_d(vi[e]), to_d(w[e]));
-    wg_accumulate(lds, i, acc);
-  }
-  __syncthreads();
-  const int nq = j + 2;
-  for (int q = threadIdx.x; q < nq; q += RB) partials[(int64_t)q * gridDim.x + blockIdx.x] = wg_result(lds, q);
+  block_dots<R>(V, ld, j + 1, w, n, true, lds);
+  publish(lds, j + 2, partials);
   if (!last_block(counter)) return;
+  last_sums(partials, j + 2, lds, res);
   constexpr int LD = MMAX + 1;
-  for (int q = threadIdx.x; q < nq; q += RB) {
-    double2 r = mk(0.0, 0.0);
-    for (int b = 0; b < (int)gridDim.x; ++b) r = cadd(r, partials[(int64_t)q * gridDim.x + b]);
-    if (q <= j) ks->H[LD * j + q] = r;
-    else ks->wn0 = sqrt(r.x);
+  for (int q = threadIdx.x; q <= MMAX; q += RB) {
+    if (q <= j) ks->H[LD * j + q] = res[q];
+    else if (q > j + 1) ks->H[LD * j + q] = mk(0.0, 0.0);
   }
-  for (int q = j + 2 + threadIdx.x; q <= MMAX; q += RB) ks->H[LD * j + q] = mk(0.0, 0.0);
+  if (threadIdx.x == 0) ks->wn0 = sqrt(res[j + 1].x);
 }
 
 // (b) w -= sum_i H[i, j] V_i; then h2_i = V_i^H w; H[i, j] += h2_i.
@@ -135,36 +207,24 @@ __global__ void __launch_bounds__(RB) k_arn_update_dots2(cx<R>* __restrict__ V, 
                                                          KState* ks, double2* partials, unsigned* counter) {
   if (ks->done) return;
   __shared__ double2 lds[RW][MMAX + 2];
-  __shared__ double2 coef[MMAX + 1];
+  __shared__ double2 coef[MMAX + 2];
   constexpr int LD = MMAX + 1;
   for (int i = threadIdx.x; i <= j; i += RB) coef[i] = ks->H[LD * j + i];
   __syncthreads();
   cx<R>* w = V + (int64_t)(j + 1) * ld;
   const int64_t stride = (int64_t)gridDim.x * RB;
-  const int64_t e0 = (int64_t)blockIdx.x * RB + threadIdx.x;
-  for (int64_t e = e0; e < n; e += stride) {
+  for (int64_t e = (int64_t)blockIdx.x * RB + threadIdx.x; e < n; e += stride) {
     double2 acc = to_d(w[e]);
-    for (int i = 0; i <= j; ++i) {
-      const double2 v = to_d(V[(int64_t)i * ld + e]);
-      acc = csub(acc, cmul(coef[i], v));
-    }
+    for (int i = 0; i <= j; ++i) acc = csub(acc, cmul(coef[i], to_d(V[(int64_t)i * ld + e])));
     w[e] = from_d<R>(acc);
   }
-  for (int i = 0; i <= j; ++i) {
-    const cx<R>* vi = V + (int64_t)i * ld;
-    double2 acc = mk(0.0, 0.0);
-    for (int64_t e = e0; e < n; e += stride) cfmac(acc, to_d(vi[e]), to_d(w[e]));
-    wg_accumulate(lds, i, acc);
-  }
-  __syncthreads();
-  const int nq = j + 1;
-  for (int q = threadIdx.x; q < nq; q += RB) partials[(int64_t)q * gridDim.x + blockIdx.x] = wg_result(lds, q);
+  block_dots<R>(V, ld, j + 1, w, n, false, lds);
+  publish(lds, j + 1, partials);
   if (!last_block(counter)) return;
-  for (int q = threadIdx.x; q < nq; q += RB) {
-    double2 r = mk(0.0, 0.0);
-    for (int b = 0; b < (int)gridDim.x; ++b) r = cadd(r, partials[(int64_t)q * gridDim.x + b]);
-    ks->h2[q] = r;
-    ks->H[LD * j + q] = cadd(ks->H[LD * j + q], r);
+  last_sums(partials, j + 1, lds, coef);
+  for (int q = threadIdx.x; q <= j; q += RB) {
+    ks->h2[q] = coef[q];
+    ks->H[LD * j + q] = cadd(ks->H[LD * j + q], coef[q]);
   }
 }
 
@@ -174,34 +234,31 @@ __global__ void __launch_bounds__(RB) k_arn_update_norm(cx<R>* __restrict__ V, i
                                                         KState* ks, double2* partials, unsigned* counter) {
   if (ks->done) return;
   __shared__ double2 lds[RW][MMAX + 2];
-  __shared__ double2 coef[MMAX + 1];
+  __shared__ double2 coef[MMAX + 2];
   constexpr int LD = MMAX + 1;
   for (int i = threadIdx.x; i <= j; i += RB) coef[i] = ks->h2[i];
   __syncthreads();
   cx<R>* w = V + (int64_t)(j + 1) * ld;
   const int64_t stride = (int64_t)gridDim.x * RB;
-  const int64_t e0 = (int64_t)blockIdx.x * RB + threadIdx.x;
   double2 nrm = mk(0.0, 0.0);
-  for (int64_t e = e0; e < n; e += stride) {
+  for (int64_t e = (int64_t)blockIdx.x * RB + threadIdx.x; e < n; e += stride) {
     double2 acc = to_d(w[e]);
     for (int i = 0; i <= j; ++i) acc = csub(acc, cmul(coef[i], to_d(V[(int64_t)i * ld + e])));
     const cx<R> st = from_d<R>(acc);
     w[e] = st;
-    const double2 sd = to_d(st);
-    nrm.x += cabs2(sd);
+    nrm.x += cabs2(to_d(st));
   }
   wg_accumulate(lds, 0, nrm);
-  __syncthreads();
-  if (threadIdx.x == 0) partials[blockIdx.x] = wg_result(lds, 0);
+  publish(lds, 1, partials);
   if (!last_block(counter)) return;
+  last_sums(partials, 1, lds, coef);
+  double hn = sqrt(coef[0].x);
+  const bool brk = !(hn > 1e-12 * ks->wn0);
+  if (brk) hn = 0.0;
+  if (threadIdx.x == 0) ks->H[LD * j + j + 1] = mk(hn, 0.0);
+  __syncthreads();
+  givens_update(ks, j);
   if (threadIdx.x == 0) {
-    double s2 = 0.0;
-    for (int b = 0; b < (int)gridDim.x; ++b) s2 += partials[b].x;
-    double hn = sqrt(s2);
-    int brk = 0;
-    if (!(hn > 1e-12 * ks->wn0)) { hn = 0.0; brk = 1; }
-    ks->H[LD * j + j + 1] = mk(hn, 0.0);
-    givens_update(ks, j);
     if (brk) { ks->breakdown = 1; ks->est = 0.0; }
     if (brk || ks->est <= ks->tol_abs) ks->done = 1;
   }
@@ -310,16 +367,16 @@ template <typename R>
 __global__ void __launch_bounds__(RB) k_norm2(int64_t n, const cx<R>* __restrict__ x, double* out, KState* ks,
                                               double tol_rel, int mode, double2* partials, unsigned* counter) {
   __shared__ double2 lds[RW][MMAX + 2];
+  __shared__ double2 res[2];
   const int64_t stride = (int64_t)gridDim.x * RB;
   double2 acc = mk(0.0, 0.0);
   for (int64_t e = (int64_t)blockIdx.x * RB + threadIdx.x; e < n; e += stride) acc.x += cabs2(to_d(x[e]));
   wg_accumulate(lds, 0, acc);
-  __syncthreads();
-  if (threadIdx.x == 0) partials[blockIdx.x] = wg_result(lds, 0);
+  publish(lds, 1, partials);
   if (!last_block(counter)) return;
+  last_sums(partials, 1, lds, res);
   if (threadIdx.x == 0) {
-    double s2 = 0.0;
-    for (int b = 0; b < (int)gridDim.x; ++b) s2 += partials[b].x;
+    const double s2 = res[0].x;
     if (mode == 0) { out[0] = s2; return; }
     const double beta = sqrt(s2);
     if (mode == 2 || mode == 3) ks->bnorm = beta;
@@ -331,9 +388,13 @@ __global__ void __launch_bounds__(RB) k_norm2(int64_t n, const cx<R>* __restrict
     ks->nrot = 0;
     ks->breakdown = 0;
     ks->done = (beta == 0.0 || beta <= ks->tol_abs) ? 1 : 0;
-    for (int i = 0; i <= MMAX; ++i) { ks->g[i] = mk(0.0, 0.0); ks->c[i] = mk(0.0, 0.0); }
-    ks->g[0] = mk(beta, 0.0);
-    ks->c[0] = mk(beta, 0.0);
+  }
+  if (mode == 1 || mode == 2) {
+    const double beta = sqrt(res[0].x);
+    for (int i = threadIdx.x; i <= MMAX; i += RB) {
+      ks->g[i] = (i == 0) ? mk(beta, 0.0) : mk(0.0, 0.0);
+      ks->c[i] = (i == 0) ? mk(beta, 0.0) : mk(0.0, 0.0);
+    }
   }
 }
 
@@ -393,22 +454,12 @@ __global__ void __launch_bounds__(RB) k_multidot(const cx<R>* __restrict__ V, in
                                                  const cx<R>* __restrict__ w, int64_t n, double2* out,
                                                  double2* partials, unsigned* counter) {
   __shared__ double2 lds[RW][MMAX + 2];
-  const int64_t stride = (int64_t)gridDim.x * RB;
-  const int64_t e0 = (int64_t)blockIdx.x * RB + threadIdx.x;
-  for (int i = 0; i < nv; ++i) {
-    const cx<R>* vi = V + (int64_t)i * ld;
-    double2 acc = mk(0.0, 0.0);
-    for (int64_t e = e0; e < n; e += stride) cfmac(acc, to_d(vi[e]), to_d(w[e]));
-    wg_accumulate(lds, i, acc);
-  }
-  __syncthreads();
-  for (int q = threadIdx.x; q < nv; q += RB) partials[(int64_t)q * gridDim.x + blockIdx.x] = wg_result(lds, q);
+  __shared__ double2 res[MMAX + 2];
+  block_dots<R>(V, ld, nv, w, n, false, lds);
+  publish(lds, nv, partials);
   if (!last_block(counter)) return;
-  for (int q = threadIdx.x; q < nv; q += RB) {
-    double2 r = mk(0.0, 0.0);
-    for (int b = 0; b < (int)gridDim.x; ++b) r = cadd(r, partials[(int64_t)q * gridDim.x + b]);
-    out[q] = r;
-  }
+  last_sums(partials, nv, lds, res);
+  for (int q = threadIdx.x; q < nv; q += RB) out[q] = res[q];
 }
 
 template <typename R>

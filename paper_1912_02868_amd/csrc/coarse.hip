@@ -20,12 +20,16 @@
 // difference shows more than 99.99 % cancellation a second pass with an exact
 // norm is taken (one more barrier).  In exact arithmetic this is the Arnoldi
 // process of GMRES; the oracle uses modified Gram-Schmidt twice.
+#include <cstdio>
+#include <cstdlib>
+
 #include "kernels.h"
 
 namespace dmg {
 
-constexpr int CP_THREADS = 256;
+constexpr int CP_THREADS = 1024;  // 16 wavefronts: enough loads in flight to stream the blocks
 constexpr int CP_WAVES = CP_THREADS / 64;
+constexpr int CP_RWAVES = 4;    // wavefronts holding the local entries (<= 240 of them)
 constexpr int CP_QMAX = 32;     // quantities per reduction
 constexpr int CP_CHUNKS = 8;    // partial-sum chunks per quantity (fixed summation order)
 
@@ -90,7 +94,7 @@ struct CPLayout {
     rl = take(ne * es);
     wl = take(ne * es);
     xs = take((size_t)spw * 5 * NC * es);
-    part = take((size_t)spw * 5 * NC * sizeof(double2));
+    part = take((size_t)(spw * 5 * NC > CP_QMAX * 32 ? spw * 5 * NC : CP_QMAX * 32) * sizeof(double2));
     Hr = take((size_t)(mm + 1) * mm * sizeof(double2));
     rc = take((size_t)mm * sizeof(double));
     rs = take((size_t)mm * sizeof(double2));
@@ -103,8 +107,8 @@ struct CPLayout {
     kc = take((size_t)(k * (k + 1) / 2 + 1) * sizeof(double));
     ks = take((size_t)(k * (k + 1) / 2 + 1) * sizeof(double2));
     kp = take((size_t)(k * (k + 1) / 2 + 1) * sizeof(int));
-    red = take((size_t)CP_QMAX * CP_WAVES * sizeof(double2));
-    cs = take((size_t)CP_QMAX * CP_CHUNKS * sizeof(double2));
+    red = take((size_t)CP_QMAX * CP_RWAVES * sizeof(double2));
+    cs = part;  // chunk sums reuse the stencil partials (never live at the same time)
     res = take((size_t)(CP_QMAX + 2) * sizeof(double2));
     tot = o;
   }
@@ -164,7 +168,7 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
   double* kc = (double*)(smem + L.kc);
   double2* ksn = (double2*)(smem + L.ks);
   int* kp = (int*)(smem + L.kp);
-  double2(*red)[CP_WAVES] = (double2(*)[CP_WAVES])(smem + L.red);
+  double2(*red)[CP_RWAVES] = (double2(*)[CP_RWAVES])(smem + L.red);
   double2(*csum)[CP_CHUNKS] = (double2(*)[CP_CHUNKS])(smem + L.cs);
   double2* res = (double2*)(smem + L.res);
   __shared__ double sh_scal[8];
@@ -180,38 +184,47 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
   int rbuf = 0;
 
   // ---------------------------------------------------------------- reduction helpers
-  // Each thread adds its contribution for quantity q; after all quantities, wg_finish
-  // publishes the workgroup sums and the grid-wide sums land in res[q].
-  auto contrib = [&](int q, double2 v) {
-    v = cp_wave_sum(v);
-    if (lane == 0) red[q][wave] = v;
+  // wg_sums: per-workgroup sums of nq quantities, term(q, e) over the local entries e;
+  // 32 threads per quantity, then one thread adds the 32 partials (fixed order) into
+  // red[q][0].  grid_reduce: publish red[q][0], barrier, every workgroup adds all
+  // workgroups' sums in the same order into res[q].
+  auto wg_sums = [&](int nq, auto&& term) {
+    const int q = tid >> 5, c = tid & 31;
+    if (q < nq) {
+      double2 sm = mk(0.0, 0.0);
+      for (int e = c; e < ne; e += 32) sm = cadd(sm, term(q, e));
+      part[q * 32 + c] = sm;
+    }
+    __syncthreads();
+    if (tid < nq) {
+      double2 sm = part[tid * 32];
+      for (int c2 = 1; c2 < 32; ++c2) sm = cadd(sm, part[tid * 32 + c2]);
+      red[tid][0] = sm;
+    }
   };
   auto grid_reduce = [&](int nq) {
     __syncthreads();
     double2* P = a.partials + (size_t)rbuf * CP_QMAX * G;
-    if (tid < nq) {
-      double2 s = red[tid][0];
-      for (int w = 1; w < CP_WAVES; ++w) s = cadd(s, red[tid][w]);
-      P[(size_t)tid * G + gi] = s;
-    }
+    if (tid < nq) P[(size_t)tid * G + gi] = red[tid][0];
     cp_barrier(a.flags, G, ++gen, a.err);
     const int q = tid / CP_CHUNKS, c = tid % CP_CHUNKS;
     if (q < nq) {
       const int per = (G + CP_CHUNKS - 1) / CP_CHUNKS;
       const int lo = c * per, hi = min(G, lo + per);
-      double2 s = mk(0.0, 0.0);
-      for (int b = lo; b < hi; ++b) s = cadd(s, P[(size_t)q * G + b]);
-      csum[q][c] = s;
+      double2 sm = mk(0.0, 0.0);
+      for (int b = lo; b < hi; ++b) sm = cadd(sm, P[(size_t)q * G + b]);
+      csum[q][c] = sm;
     }
     __syncthreads();
     if (tid < nq) {
-      double2 s = csum[tid][0];
-      for (int c2 = 1; c2 < CP_CHUNKS; ++c2) s = cadd(s, csum[tid][c2]);
-      res[tid] = s;
+      double2 sm = csum[tid][0];
+      for (int c2 = 1; c2 < CP_CHUNKS; ++c2) sm = cadd(sm, csum[tid][c2]);
+      res[tid] = sm;
     }
     __syncthreads();
     rbuf ^= 1;
   };
+  auto sq = [&](const T* v) { return [=](int, int e) { return mk(cabs2(to_d(v[e])), 0.0); }; };
 
   // ---------------------------------------------------------------- load the resident data
   if (ALDS) {
@@ -250,12 +263,8 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
       }
   }
   // ||b||
-  {
-    double2 v = mk(0.0, 0.0);
-    for (int t = tid; t < ne; t += CP_THREADS) v.x += cabs2(to_d(rl[t]));
-    contrib(0, v);
-    grid_reduce(1);
-  }
+  wg_sums(1, sq(rl));
+  grid_reduce(1);
   const double bnorm = sqrt(res[0].x);
   const double tol_abs = a.tol * bnorm;
   int iters = 0;
@@ -264,11 +273,11 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
 
   while (!converged && iters < a.max_iters) {
     // ------------------------------------------------------------ projection over V_{k+1}
-    for (int i = 0; i <= k; ++i) {
+    wg_sums(k + 1, [&](int q, int e) {
       double2 v = mk(0.0, 0.0);
-      for (int t = tid; t < ne; t += CP_THREADS) cfmac(v, to_d(DVb[i * ne + t]), to_d(rl[t]));
-      contrib(i, v);
-    }
+      cfmac(v, to_d(DVb[q * ne + e]), to_d(rl[e]));
+      return v;
+    });
     grid_reduce(k + 1);
     if (tid == 0) {
       // d = argmin || c - Hk d || via the stored rotations
@@ -301,12 +310,9 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
       xch[e0 + t] = from_d<R>(rv);
     }
     // ------------------------------------------------------------ GMRES(mm) cycle from r
-    {
-      double2 v = mk(0.0, 0.0);
-      for (int t = tid; t < ne; t += CP_THREADS) v.x += cabs2(to_d(rl[t]));
-      contrib(0, v);
-      grid_reduce(1);
-    }
+    __syncthreads();
+    wg_sums(1, sq(rl));
+    grid_reduce(1);
     double hprev = sqrt(res[0].x);  // beta; xchg holds the unnormalised start vector
     est = hprev;
     if (hprev <= tol_abs || hprev == 0.0) {
@@ -346,9 +352,15 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
         const int sl = t / (5 * NC), d = (t / NC) % 5, i = t % NC;
         const T* blk = ALDS ? (Ab + ((int64_t)sl * 5 + d) * NC * NC) : (Ag + ((int64_t)(S0 + sl) * 5 + d) * NC * NC);
         const T* xv = xs + (sl * 5 + d) * NC;
+        T av[NC / 2];
         double2 acc = mk(0.0, 0.0);
-#pragma unroll 8
-        for (int jj = 0; jj < NC; ++jj) cfma(acc, to_d(blk[jj * NC + i]), to_d(xv[jj]));
+#pragma unroll
+        for (int h2 = 0; h2 < 2; ++h2) {
+#pragma unroll
+          for (int jj = 0; jj < NC / 2; ++jj) av[jj] = blk[(h2 * (NC / 2) + jj) * NC + i];
+#pragma unroll
+          for (int jj = 0; jj < NC / 2; ++jj) cfma(acc, to_d(av[jj]), to_d(xv[h2 * (NC / 2) + jj]));
+        }
         part[t] = acc;
       }
       __syncthreads();
@@ -360,62 +372,50 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
       }
       __syncthreads();
       // h_i = V_i^H w (i <= j) and ||w||^2 in one reduction
-      for (int i = 0; i <= j + 1; ++i) {
+      auto dots = [&](int q, int e) {
         double2 v = mk(0.0, 0.0);
-        if (i <= j) {
-          for (int t = tid; t < ne; t += CP_THREADS) cfmac(v, to_d(Vb[i * ne + t]), to_d(wl[t]));
-        } else {
-          for (int t = tid; t < ne; t += CP_THREADS) v.x += cabs2(to_d(wl[t]));
-        }
-        contrib(i, v);
-      }
+        if (q <= j) cfmac(v, to_d(Vb[q * ne + e]), to_d(wl[e]));
+        else v.x = cabs2(to_d(wl[e]));
+        return v;
+      };
+      wg_sums(j + 2, dots);
       grid_reduce(j + 2);
       const double ww = res[j + 1].x;
       double hh = 0.0;
       for (int i = 0; i <= j; ++i) hh += cabs2(res[i]);
       double hn2 = ww - hh;
-      if (tid <= j) {
-        Hr[tid + (mm + 1) * j] = res[tid];
-        uv[tid] = res[tid];
-      }
-      __syncthreads();
-      for (int t = tid; t < ne; t += CP_THREADS) {
-        double2 w = to_d(wl[t]);
-        for (int i = 0; i <= j; ++i) w = csub(w, cmul(uv[i], to_d(Vb[i * ne + t])));
-        wl[t] = from_d<R>(w);
-      }
-      __syncthreads();
+      bool updated = false;
       if (!(hn2 > eta * ww)) {
-        // heavy cancellation: second Gram-Schmidt pass with the exact norm of the first
-        for (int i = 0; i <= j + 1; ++i) {
-          double2 v = mk(0.0, 0.0);
-          if (i <= j) {
-            for (int t = tid; t < ne; t += CP_THREADS) cfmac(v, to_d(Vb[i * ne + t]), to_d(wl[t]));
-          } else {
-            for (int t = tid; t < ne; t += CP_THREADS) v.x += cabs2(to_d(wl[t]));
-          }
-          contrib(i, v);
+        // heavy cancellation: apply the first pass, then a second pass with an exact norm
+        if (tid <= j) Hr[tid + (mm + 1) * j] = res[tid];
+        for (int t = tid; t < ne; t += CP_THREADS) {
+          double2 w = to_d(wl[t]);
+          for (int i = 0; i <= j; ++i) w = csub(w, cmul(res[i], to_d(Vb[i * ne + t])));
+          wl[t] = from_d<R>(w);
         }
+        __syncthreads();
+        wg_sums(j + 2, dots);
         grid_reduce(j + 2);
         double hh2 = 0.0;
         for (int i = 0; i <= j; ++i) hh2 += cabs2(res[i]);
         hn2 = res[j + 1].x - hh2;
-        if (tid <= j) {
-          Hr[tid + (mm + 1) * j] = cadd(Hr[tid + (mm + 1) * j], res[tid]);
-          uv[tid] = res[tid];
-        }
-        __syncthreads();
+        if (tid <= j) Hr[tid + (mm + 1) * j] = cadd(Hr[tid + (mm + 1) * j], res[tid]);
         for (int t = tid; t < ne; t += CP_THREADS) {
           double2 w = to_d(wl[t]);
-          for (int i = 0; i <= j; ++i) w = csub(w, cmul(uv[i], to_d(Vb[i * ne + t])));
+          for (int i = 0; i <= j; ++i) w = csub(w, cmul(res[i], to_d(Vb[i * ne + t])));
           wl[t] = from_d<R>(w);
         }
         __syncthreads();
+        updated = true;
       }
       double hn = sqrt(fmax(hn2, 0.0));
       if (!(hn > 1e-12 * sqrt(ww))) { hn = 0.0; brk = true; }
-      if (tid == 0) {
+      // the Givens update (one thread of an otherwise idle wavefront) overlaps the
+      // Gram-Schmidt update, the exchange write and the exchange barrier
+      if (tid == CP_THREADS - 64) {
         double2* col = Hr + (mm + 1) * j;
+        if (!updated)
+          for (int i = 0; i <= j; ++i) col[i] = res[i];
         col[j + 1] = mk(hn, 0.0);
         for (int q = 0; q < j; ++q) {
           const double2 x0 = col[q], x1 = col[q + 1];
@@ -434,16 +434,20 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
         gv[j + 1] = csub(cscale(g1, c), cmul(cconj(sg), g0));
         sh_scal[0] = sqrt(cabs2(gv[j + 1]));
       }
-      __syncthreads();
+      for (int t = tid; t < ne; t += CP_THREADS) {
+        double2 w = to_d(wl[t]);
+        if (!updated)
+          for (int i = 0; i <= j; ++i) w = csub(w, cmul(res[i], to_d(Vb[i * ne + t])));
+        const T ws = from_d<R>(w);
+        wl[t] = ws;
+        if (j + 1 < mm) xch[e0 + t] = ws;  // hn * v_{j+1} for the next stencil
+      }
+      if (j + 1 < mm) cp_barrier(a.flags, G, ++gen, a.err);
+      else __syncthreads();
       est = brk ? 0.0 : sh_scal[0];
       steps = j + 1;
       hprev = hn;
       if (brk || est <= tol_abs || iters + steps >= a.max_iters) { stop = true; break; }
-      if (j + 1 < mm) {
-        // publish hprev * v_{j+1} for the next stencil
-        for (int t = tid; t < ne; t += CP_THREADS) xch[e0 + t] = wl[t];
-        cp_barrier(a.flags, G, ++gen, a.err);
-      }
     }
     // ------------------------------------------------------------ end of cycle: x += V y, r = V u
     if (tid == 0) {
@@ -484,7 +488,7 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
   }
   for (int t = tid; t < ne; t += CP_THREADS) xg[e0 + t] = xl[t];
   if (gi == 0 && tid == 0) {
-    a.out_iters[0] = iters;
+    a.out_iters[0] += iters;  // accumulated over the calls of one outer solve
     a.out_relres[0] = bnorm > 0.0 ? est / bnorm : 0.0;
   }
 }
@@ -493,29 +497,47 @@ size_t coarse_proj_lds(int spw, int mm, int k, size_t es, int a_in_lds) {
   return CPLayout(spw, mm, k, es, a_in_lds).tot;
 }
 
+static bool cp_debug() {
+  static const int on = [] {
+    const char* e = getenv("DMG_DEBUG");
+    return (e && *e && *e != '0') ? 1 : 0;
+  }();
+  return on != 0;
+}
+
 template <typename R>
 static int try_launch(hipStream_t st, CPArgs& a, int G, size_t lds, bool alds) {
   void* args[] = {&a};
   const void* fn = alds ? (const void*)k_coarse_proj<R, true> : (const void*)k_coarse_proj<R, false>;
-  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) {
+    if (cp_debug()) fprintf(stderr, "[dmg] coarse kernel: set LDS %zu failed: %s\n", lds, hipGetErrorString(e));
     (void)hipGetLastError();
     return 0;
   }
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, CP_THREADS, lds) != hipSuccess) {
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, CP_THREADS, lds);
+  if (e != hipSuccess) {
+    if (cp_debug()) fprintf(stderr, "[dmg] coarse kernel: occupancy query failed: %s\n", hipGetErrorString(e));
     (void)hipGetLastError();
     return 0;
   }
   int dev = 0, ncu = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  if (per_cu < 1 || G > per_cu * ncu) return 0;
+  if (per_cu < 1 || G > per_cu * ncu) {
+    if (cp_debug())
+      fprintf(stderr, "[dmg] coarse kernel: %d workgroups of %d threads, LDS %zu: %d per CU x %d CUs\n", G,
+              CP_THREADS, lds, per_cu, ncu);
+    return 0;
+  }
   if (hipMemsetAsync(a.flags, 0, sizeof(unsigned) * CP_FLAGPAD * G, st) != hipSuccess) {
     (void)hipGetLastError();
     return 0;
   }
-  hipError_t e = hipLaunchCooperativeKernel(fn, dim3(G), dim3(CP_THREADS), args, (unsigned)lds, st);
+  e = hipLaunchCooperativeKernel(fn, dim3(G), dim3(CP_THREADS), args, (unsigned)lds, st);
   if (e != hipSuccess) {
+    if (cp_debug()) fprintf(stderr, "[dmg] coarse kernel: cooperative launch failed: %s\n", hipGetErrorString(e));
     (void)hipGetLastError();
     return 0;
   }
@@ -540,9 +562,13 @@ int launch_coarse_proj(hipStream_t st, const cx<R>* A, int Lx, int Lt, const cx<
   if (spw > 10) spw = 10;  // one thread per local entry
   const int G = (V + spw - 1) / spw;
   if ((size_t)2 * CP_QMAX * G > partials_elems || (size_t)CP_FLAGPAD * G > flag_words) return 0;
+  static_assert(CP_RWAVES * 64 >= 10 * NC, "local entries must sit in the reducing wavefronts");
   for (int alds = 1; alds >= 0; --alds) {
     const size_t lds = coarse_proj_lds(spw, mm, k, sizeof(cx<R>), alds);
-    if (lds > lds_max) continue;
+    if (lds > lds_max) {
+      if (cp_debug() && alds == 0) fprintf(stderr, "[dmg] coarse kernel: LDS %zu exceeds %zu\n", lds, lds_max);
+      continue;
+    }
     CPArgs a{A, Lx, Lt, DV, DH, k, b, x, tol, mm, max_iters, xchg, partials, out_iters, out_relres,
              flags, err, spw, alds};
     if (try_launch<R>(st, a, G, lds, alds == 1)) return 1;

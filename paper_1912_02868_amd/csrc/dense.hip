@@ -31,24 +31,39 @@ __device__ inline void make_givens(double2 a, double2 b, double& c, double2& s) 
 }
 
 // ---------------------------------------------------------------- least squares
-__global__ void k_ls_solve(KState* ks) {
-  if (threadIdx.x != 0) return;
+// y = R^{-1} g over the completed steps (R and g staged in LDS by all threads, the
+// back-substitution by one), then u = c - H y with one thread per row.
+__global__ void __launch_bounds__(DW) k_ls_solve(KState* ks) {
+  __shared__ double2 Rs[MMAX * MMAX];
+  __shared__ double2 gs[MMAX + 1];
+  __shared__ double2 ys[MMAX + 1];
+  const int t = threadIdx.x;
   const int n = ks->steps;
-  for (int i = n - 1; i >= 0; --i) {
-    double2 acc = ks->g[i];
-    for (int l = i + 1; l < n; ++l) acc = csub(acc, cmul(ks->R[i + LD * l], ks->y[l]));
-    const double2 d = ks->R[i + LD * i];
-    ks->y[i] = cabs2(d) > 0.0 ? cdiv(acc, d) : mk(0.0, 0.0);
+  for (int e = t; e < n * n; e += DW) {
+    const int i = e % n, l = e / n;
+    Rs[e] = (i <= l) ? ks->R[i + LD * l] : mk(0.0, 0.0);
   }
-  for (int i = 0; i <= n; ++i) {
+  for (int i = t; i < n; i += DW) gs[i] = ks->g[i];
+  __syncthreads();
+  if (t == 0) {
+    for (int i = n - 1; i >= 0; --i) {
+      double2 acc = gs[i];
+      for (int l = i + 1; l < n; ++l) acc = csub(acc, cmul(Rs[i + n * l], ys[l]));
+      const double2 d = Rs[i + n * i];
+      ys[i] = cabs2(d) > 0.0 ? cdiv(acc, d) : mk(0.0, 0.0);
+    }
+  }
+  __syncthreads();
+  for (int i = t; i < n; i += DW) ks->y[i] = ys[i];
+  for (int i = t; i <= n; i += DW) {
     double2 acc = ks->c[i];
-    for (int l = 0; l < n; ++l) acc = csub(acc, cmul(ks->H[i + LD * l], ks->y[l]));
+    for (int l = 0; l < n; ++l) acc = csub(acc, cmul(ks->H[i + LD * l], ys[l]));
     ks->u[i] = acc;
   }
 }
 
 void launch_ls_solve(hipStream_t s, KState* ks) {
-  hipLaunchKernelGGL(k_ls_solve, dim3(1), dim3(1), 0, s, ks);
+  hipLaunchKernelGGL(k_ls_solve, dim3(1), dim3(DW), 0, s, ks);
   DMG_LAUNCH_CHECK();
 }
 

@@ -76,6 +76,27 @@ class SolveStats(C.Structure):
 
 
 _lib = None
+_live = []  # handles closed (newest first) at interpreter exit, before torch tears down
+
+
+def _register(obj):
+    import weakref
+    _live.append(weakref.ref(obj))
+
+
+def _close_all():
+    for ref in reversed(_live):
+        obj = ref()
+        if obj is not None:
+            try:
+                obj.close()
+            except Exception:
+                pass
+    _live.clear()
+
+
+import atexit  # noqa: E402
+atexit.register(_close_all)
 
 
 def lib():
@@ -167,12 +188,17 @@ class Context:
         if torch_alloc:
             dev = device
 
+            alloc_fn = torch.cuda.caching_allocator_alloc
+            free_fn = torch.cuda.caching_allocator_delete
+
             def _a(nbytes, user):
-                with torch.cuda.device(dev):
-                    return torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream)
+                return alloc_fn(int(nbytes), dev, stream)
 
             def _f(ptr, user):
-                torch.cuda.caching_allocator_delete(ptr)
+                try:
+                    free_fn(ptr)
+                except Exception:
+                    pass  # interpreter shutdown: torch already released its pools
 
             self._alloc = Allocator(Allocator._fields_[0][1](_a), Allocator._fields_[1][1](_f), None)
         self.h = C.c_void_p()
@@ -180,6 +206,7 @@ class Context:
                                       C.byref(self._alloc) if self._alloc else None, budget, C.byref(self.h))
         if st != DMG_OK:
             raise DmgError(st, "context creation failed")
+        _register(self)
 
     def check(self, st, what=""):
         if st < 0:
@@ -211,6 +238,7 @@ class Gauge:
         self.h = C.c_void_p()
         ctx.check(lib().dmg_gauge_create(ctx.h, Nx, Nt, theta.ctypes.data_as(C.c_void_p), int(antiperiodic),
                                          C.byref(self.h)), "gauge_create")
+        _register(self)
 
     def close(self):
         if self.h:
@@ -242,6 +270,7 @@ class Hierarchy:
         prm = params or setup_params()
         self.h = C.c_void_p()
         ctx.check(lib().dmg_setup(ctx.h, g.h, m0, C.byref(prm), p0, p1, int(inject), k0, C.byref(self.h)), "setup")
+        _register(self)
 
     def part_bytes(self, level, part) -> int:
         return lib().dmg_hierarchy_part_bytes(self.h, level, part)
@@ -278,6 +307,7 @@ class Deflation:
         self.hier = hier
         self.h = C.c_void_p()
         hier.ctx.check(lib().dmg_deflation_create(hier.h, m, k, C.byref(self.h)), "deflation_create")
+        _register(self)
 
     def build(self, rhs, tol: float = 1e-8):
         p, kind = _ptr(rhs)
