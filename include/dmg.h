@@ -161,7 +161,8 @@ dmg_status dmg_hierarchy_apply(dmg_hierarchy* h, int level, int op, dmg_precisio
 
 /* Coarse-grid deflation space (Methods section): EMPTY until the first coarse
  * solve runs GMRES-DR(m, k), which leaves A V_k = V_{k+1} Hbar_k; READY after
- * that, when every coarse solve is GMRES-Proj(m, k).  Tied to one hierarchy. */
+ * that, when every coarse solve is GMRES-Proj(m, k).  Tied to one hierarchy.
+ * Sizes: 1 <= k < m <= 64 and k <= 31 (DMG_E_INVALID otherwise). */
 dmg_status dmg_deflation_create(dmg_hierarchy* h, int m, int k, dmg_deflation** out);
 /* Fill the space now by GMRES-DR on the given coarse right-hand side (FP64,
  * 24 * (Nx/16) * (Nt/16) complex) to tol. */

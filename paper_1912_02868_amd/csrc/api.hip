@@ -356,7 +356,8 @@ dmg_status dmg_deflation_create(dmg_hierarchy* h, int m, int k, dmg_deflation** 
   if (!h || !out) return DMG_E_INVALID;
   return guard(h->ctx, [&]() -> dmg_status {
     *out = nullptr;
-    DMG_CHECK(m >= 2 && m <= MMAX && k >= 1 && k < m, DMG_E_INVALID, "deflation sizes need 1 <= k < m <= 64");
+    DMG_CHECK(m >= 2 && m <= MMAX && k >= 1 && k < m && k <= 31, DMG_E_INVALID,
+              "deflation sizes need 1 <= k < m <= 64 and k <= 31");
     dmg_deflation* d = new dmg_deflation();
     d->h = h;
     d->m = m;

@@ -3,6 +3,8 @@
 // workgroup writes its partial sums, and the last workgroup to finish (counted
 // with one atomic ticket) adds the partials in workgroup order and runs the
 // small epilogue of the step (Hessenberg entries, Givens update).
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace dmg {
@@ -292,6 +294,104 @@ void launch_arnoldi_orth(hipStream_t s, cx<R>* V, int64_t ld, int64_t n, int j, 
   DMG_LAUNCH_CHECK();
 }
 
+// ---------------------------------------------------------------- two-step GMRES smoother
+// GMRES(2) from x0 = 0 minimises || v - A (c0 v + c1 A v) || over (c0, c1): the least-squares
+// fit of v by [w1, w2] = [A v, A^2 v].  One reduction forms the Gram entries
+// (w1.w1, w1.w2, w2.w2, w1.v, w2.v); the last workgroup solves the 2 x 2 normal equations
+// (falling back to the one-term fit when [w1, w2] is numerically rank one).
+// coef receives c0, c1 (double2 each).
+template <typename R>
+__global__ void __launch_bounds__(RB) k_smooth2_dots(const cx<R>* __restrict__ v, const cx<R>* __restrict__ w1,
+                                                     const cx<R>* __restrict__ w2, int64_t n, double2* coef,
+                                                     double2* partials, unsigned* counter) {
+  __shared__ double2 lds[RW][MMAX + 2];
+  __shared__ double2 res[8];
+  const int64_t stride = (int64_t)gridDim.x * RB;
+  double2 a11 = mk(0.0, 0.0), a12 = mk(0.0, 0.0), a22 = mk(0.0, 0.0), b1 = mk(0.0, 0.0), b2 = mk(0.0, 0.0);
+  for (int64_t e = (int64_t)blockIdx.x * RB + threadIdx.x; e < n; e += stride) {
+    const double2 vv = to_d(v[e]), x1 = to_d(w1[e]), x2 = to_d(w2[e]);
+    a11.x += cabs2(x1);
+    cfmac(a12, x1, x2);
+    a22.x += cabs2(x2);
+    cfmac(b1, x1, vv);
+    cfmac(b2, x2, vv);
+  }
+  wg_accumulate(lds, 0, a11);
+  wg_accumulate(lds, 1, a12);
+  wg_accumulate(lds, 2, a22);
+  wg_accumulate(lds, 3, b1);
+  wg_accumulate(lds, 4, b2);
+  publish(lds, 5, partials);
+  if (!last_block(counter)) return;
+  last_sums(partials, 5, lds, res);
+  if (threadIdx.x == 0) {
+    const double g11 = res[0].x, g22 = res[2].x;
+    const double2 g12 = res[1], r1 = res[3], r2 = res[4];
+    double2 c0 = mk(0.0, 0.0), c1 = mk(0.0, 0.0);
+    const double det = g11 * g22 - cabs2(g12);  // Gram determinant (>= 0)
+    if (g11 > 0.0 && det > 1e-13 * g11 * g22) {
+      // [g11 g12; conj(g12) g22] [c0; c1] = [r1; r2]
+      const double inv = 1.0 / det;
+      c0 = cscale(csub(cscale(r1, g22), cmul(g12, r2)), inv);
+      c1 = cscale(csub(cscale(r2, g11), cmul(cconj(g12), r1)), inv);
+    } else if (g11 > 0.0) {
+      c0 = cscale(r1, 1.0 / g11);
+    }
+    coef[0] = c0;
+    coef[1] = c1;
+  }
+}
+
+// y = c0 v + c1 w1;  r = v - c0 w1 - c1 w2 (r optional)
+template <typename R>
+__global__ void __launch_bounds__(RB) k_smooth2_combine(const cx<R>* __restrict__ v, const cx<R>* __restrict__ w1,
+                                                        const cx<R>* __restrict__ w2, int64_t n, const double2* coef,
+                                                        cx<R>* __restrict__ y, cx<R>* __restrict__ r) {
+  const double2 c0 = coef[0], c1 = coef[1];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+    const double2 vv = to_d(v[e]), x1 = to_d(w1[e]);
+    double2 yv = mk(0.0, 0.0);
+    cfma(yv, c0, vv);
+    cfma(yv, c1, x1);
+    y[e] = from_d<R>(yv);
+    if (r) {
+      double2 rv = vv;
+      rv = csub(rv, cmul(c0, x1));
+      rv = csub(rv, cmul(c1, to_d(w2[e])));
+      r[e] = from_d<R>(rv);
+    }
+  }
+}
+
+template <typename R>
+void launch_smooth2(hipStream_t s, const cx<R>* v, const cx<R>* w1, const cx<R>* w2, int64_t n, double2* coef,
+                    cx<R>* y, cx<R>* r, double2* partials, unsigned* counter) {
+  hipLaunchKernelGGL(k_smooth2_dots<R>, dim3(red_blocks(n)), dim3(RB), 0, s, v, w1, w2, n, coef, partials, counter);
+  const int64_t nb = std::min<int64_t>((n + RB - 1) / RB, 2048);
+  hipLaunchKernelGGL(k_smooth2_combine<R>, dim3((unsigned)nb), dim3(RB), 0, s, v, w1, w2, n, (const double2*)coef, y,
+                     r);
+  DMG_LAUNCH_CHECK();
+}
+
+// z = a x + b y  (separate output)
+template <typename R>
+__global__ void k_axpbyz(int64_t n, double a, const cx<R>* __restrict__ x, double b, const cx<R>* __restrict__ y,
+                         cx<R>* __restrict__ z) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+    const double2 xv = to_d(x[e]), yv = to_d(y[e]);
+    z[e] = from_d<R>(mk(a * xv.x + b * yv.x, a * xv.y + b * yv.y));
+  }
+}
+
+template <typename R>
+void launch_axpbyz(hipStream_t s, int64_t n, double a, const cx<R>* x, double b, const cx<R>* y, cx<R>* z) {
+  const int64_t nb = std::min<int64_t>((n + RB - 1) / RB, 2048);
+  hipLaunchKernelGGL(k_axpbyz<R>, dim3((unsigned)nb), dim3(RB), 0, s, n, a, x, b, y, z);
+  DMG_LAUNCH_CHECK();
+}
+
 // ---------------------------------------------------------------- combinations
 template <typename R>
 __global__ void __launch_bounds__(RB) k_combine(cx<R>* __restrict__ x, const cx<R>* __restrict__ V, int64_t ld,
@@ -526,7 +626,10 @@ void launch_basis_rotate(hipStream_t s, const cx<R>* Vin, cx<R>* Vout, int64_t l
                                      double);                                                                       \
   template void launch_basis_rotate<R>(hipStream_t, const cx<R>*, cx<R>*, int64_t, int64_t, const double2*, int,   \
                                        int, int);                                                                   \
-  template void launch_scale_dev<R>(hipStream_t, int64_t, const cx<R>*, cx<R>*, const double*, int);
+  template void launch_scale_dev<R>(hipStream_t, int64_t, const cx<R>*, cx<R>*, const double*, int);              \
+  template void launch_smooth2<R>(hipStream_t, const cx<R>*, const cx<R>*, const cx<R>*, int64_t, double2*, cx<R>*, \
+                                  cx<R>*, double2*, unsigned*);                                                    \
+  template void launch_axpbyz<R>(hipStream_t, int64_t, double, const cx<R>*, double, const cx<R>*, cx<R>*);
 INST(double)
 INST(float)
 #undef INST

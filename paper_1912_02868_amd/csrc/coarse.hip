@@ -37,7 +37,8 @@ struct CPArgs {
   const void* A;          // coarse blocks [S][d][col][row]
   int Lx, Lt;
   const void* DV;         // deflation basis, k + 1 fields
-  const double2* DH;      // Hbar_k, (k+1) x k column-major
+  const double2* DM;      // Hbar_k^+, k x (k+1) column-major
+  const double2* DP;      // Hbar_k Hbar_k^+, (k+1) x (k+1) column-major
   int k;
   const void* b;
   void* x;
@@ -102,11 +103,9 @@ struct CPLayout {
     g = take(sv);
     y = take(sv);
     u = take(sv);
-    Hk = take((size_t)(k + 1) * k * sizeof(double2));
-    Rk = take((size_t)(k + 1) * k * sizeof(double2));
-    kc = take((size_t)(k * (k + 1) / 2 + 1) * sizeof(double));
-    ks = take((size_t)(k * (k + 1) / 2 + 1) * sizeof(double2));
-    kp = take((size_t)(k * (k + 1) / 2 + 1) * sizeof(int));
+    Hk = take((size_t)(k + 1) * k * sizeof(double2));        // M
+    Rk = take((size_t)(k + 1) * (k + 1) * sizeof(double2));  // Pi
+    kc = ks = kp = 0;
     red = take((size_t)CP_QMAX * CP_RWAVES * sizeof(double2));
     cs = part;  // chunk sums reuse the stencil partials (never live at the same time)
     res = take((size_t)(CP_QMAX + 2) * sizeof(double2));
@@ -163,11 +162,8 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
   double2* gv = (double2*)(smem + L.g);
   double2* yv = (double2*)(smem + L.y);
   double2* uv = (double2*)(smem + L.u);
-  double2* Hk = (double2*)(smem + L.Hk);
-  double2* Rk = (double2*)(smem + L.Rk);
-  double* kc = (double*)(smem + L.kc);
-  double2* ksn = (double2*)(smem + L.ks);
-  int* kp = (int*)(smem + L.kp);
+  double2* Mk = (double2*)(smem + L.Hk);
+  double2* Pk = (double2*)(smem + L.Rk);
   double2(*red)[CP_RWAVES] = (double2(*)[CP_RWAVES])(smem + L.red);
   double2(*csum)[CP_CHUNKS] = (double2(*)[CP_CHUNKS])(smem + L.cs);
   double2* res = (double2*)(smem + L.res);
@@ -239,29 +235,9 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
     rl[t] = bg[e0 + t];
     xl[t] = make_cx<R>(R(0), R(0));
   }
-  for (int t = tid; t < (k + 1) * k; t += CP_THREADS) Hk[t] = a.DH[t];
+  for (int t = tid; t < (k + 1) * k; t += CP_THREADS) Mk[t] = a.DM[t];
+  for (int t = tid; t < (k + 1) * (k + 1); t += CP_THREADS) Pk[t] = a.DP[t];
   __syncthreads();
-  // Givens QR of Hbar_k (identical in every workgroup)
-  if (tid == 0) {
-    for (int t = 0; t < (k + 1) * k; ++t) Rk[t] = Hk[t];
-    int nr = 0;
-    for (int jc = 0; jc < k; ++jc)
-      for (int r = k; r > jc; --r) {
-        double c;
-        double2 s;
-        cp_givens(Rk[r - 1 + (k + 1) * jc], Rk[r + (k + 1) * jc], c, s);
-        for (int q = jc; q < k; ++q) {
-          const double2 x0 = Rk[r - 1 + (k + 1) * q], x1 = Rk[r + (k + 1) * q];
-          Rk[r - 1 + (k + 1) * q] = cadd(cscale(x0, c), cmul(s, x1));
-          Rk[r + (k + 1) * q] = csub(cscale(x1, c), cmul(cconj(s), x0));
-        }
-        Rk[r + (k + 1) * jc] = mk(0.0, 0.0);
-        kc[nr] = c;
-        ksn[nr] = s;
-        kp[nr] = r - 1;
-        ++nr;
-      }
-  }
   // ||b||
   wg_sums(1, sq(rl));
   grid_reduce(1);
@@ -279,26 +255,16 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
       return v;
     });
     grid_reduce(k + 1);
-    if (tid == 0) {
-      // d = argmin || c - Hk d || via the stored rotations
-      for (int i = 0; i <= k; ++i) uv[i] = res[i];
-      for (int q = 0; q < k * (k + 1) / 2; ++q) {
-        const int p = kp[q];
-        const double2 x0 = uv[p], x1 = uv[p + 1];
-        uv[p] = cadd(cscale(x0, kc[q]), cmul(ksn[q], x1));
-        uv[p + 1] = csub(cscale(x1, kc[q]), cmul(cconj(ksn[q]), x0));
-      }
-      for (int i = k - 1; i >= 0; --i) {
-        double2 acc = uv[i];
-        for (int l = i + 1; l < k; ++l) acc = csub(acc, cmul(Rk[i + (k + 1) * l], yv[l]));
-        const double2 d = Rk[i + (k + 1) * i];
-        yv[i] = cabs2(d) > 0.0 ? cp_div(acc, d) : mk(0.0, 0.0);
-      }
-      for (int i = 0; i <= k; ++i) {
-        double2 acc = mk(0.0, 0.0);
-        for (int l = 0; l < k; ++l) cfma(acc, Hk[i + (k + 1) * l], yv[l]);
-        uv[i] = acc;
-      }
+    // d = M c minimises || c - Hbar_k d ||; u = Pi c = Hbar_k d
+    if (tid < k) {
+      double2 acc = mk(0.0, 0.0);
+      for (int l = 0; l <= k; ++l) cfma(acc, Mk[tid + k * l], res[l]);
+      yv[tid] = acc;
+    } else if (tid >= 64 && tid <= 64 + k) {
+      const int i = tid - 64;
+      double2 acc = mk(0.0, 0.0);
+      for (int l = 0; l <= k; ++l) cfma(acc, Pk[i + (k + 1) * l], res[l]);
+      uv[i] = acc;
     }
     __syncthreads();
     for (int t = tid; t < ne; t += CP_THREADS) {
@@ -550,7 +516,8 @@ size_t coarse_proj_flag_words(int G) { return (size_t)CP_FLAGPAD * G; }
 // (the caller then uses the multi-kernel path).  `groups` is the target number of
 // workgroups (0: 32).
 template <typename R>
-int launch_coarse_proj(hipStream_t st, const cx<R>* A, int Lx, int Lt, const cx<R>* DV, const double2* DH, int k,
+int launch_coarse_proj(hipStream_t st, const cx<R>* A, int Lx, int Lt, const cx<R>* DV, const double2* DM,
+                       const double2* DP, int k,
                        const cx<R>* b, cx<R>* x, double tol, int mm, int max_iters, cx<R>* xchg,
                        double2* partials, size_t partials_elems, int* out_iters, double* out_relres,
                        unsigned* flags, size_t flag_words, int* err, int groups) {
@@ -569,17 +536,19 @@ int launch_coarse_proj(hipStream_t st, const cx<R>* A, int Lx, int Lt, const cx<
       if (cp_debug() && alds == 0) fprintf(stderr, "[dmg] coarse kernel: LDS %zu exceeds %zu\n", lds, lds_max);
       continue;
     }
-    CPArgs a{A, Lx, Lt, DV, DH, k, b, x, tol, mm, max_iters, xchg, partials, out_iters, out_relres,
+    CPArgs a{A, Lx, Lt, DV, DM, DP, k, b, x, tol, mm, max_iters, xchg, partials, out_iters, out_relres,
              flags, err, spw, alds};
     if (try_launch<R>(st, a, G, lds, alds == 1)) return 1;
   }
   return 0;
 }
 
-template int launch_coarse_proj<double>(hipStream_t, const double2*, int, int, const double2*, const double2*, int,
+template int launch_coarse_proj<double>(hipStream_t, const double2*, int, int, const double2*, const double2*,
+                                        const double2*, int,
                                         const double2*, double2*, double, int, int, double2*, double2*, size_t,
                                         int*, double*, unsigned*, size_t, int*, int);
-template int launch_coarse_proj<float>(hipStream_t, const float2*, int, int, const float2*, const double2*, int,
+template int launch_coarse_proj<float>(hipStream_t, const float2*, int, int, const float2*, const double2*,
+                                       const double2*, int,
                                        const float2*, float2*, double, int, int, float2*, double2*, size_t, int*,
                                        double*, unsigned*, size_t, int*, int);
 

@@ -97,6 +97,62 @@ __device__ void qr_block_serial(KState* ks, int k) {
   ks->est = cabs_(ks->g[k]);
 }
 
+// Same rotations as qr_block_serial, computed on an LDS copy (scratch: >= (k+1) * k
+// double2) so the serial part never waits on global memory.
+constexpr int QRL_MAXROT = 528;  // k <= 32
+__device__ void qr_block_lds(KState* ks, int k, double2* scratch) {
+  const int t = threadIdx.x;
+  const int nr = k * (k + 1) / 2;
+  __shared__ double2 gq[MMAX + 1];
+  __shared__ double rcq[QRL_MAXROT];
+  __shared__ double2 rsq[QRL_MAXROT];
+  __shared__ int rpq[QRL_MAXROT];
+  if (nr > QRL_MAXROT) {
+    if (t == 0) qr_block_serial(ks, k);
+    __syncthreads();
+    return;
+  }
+  double2* Rq = scratch;
+  for (int e = t; e < (k + 1) * k; e += blockDim.x) Rq[e] = ks->H[(e % (k + 1)) + LD * (e / (k + 1))];
+  for (int i = t; i <= k; i += blockDim.x) gq[i] = ks->c[i];
+  __syncthreads();
+  if (t == 0) {
+    int q = 0;
+    for (int jc = 0; jc < k; ++jc)
+      for (int r = k; r > jc; --r) {
+        double c;
+        double2 sg;
+        make_givens(Rq[r - 1 + (k + 1) * jc], Rq[r + (k + 1) * jc], c, sg);
+        for (int q2 = jc; q2 < k; ++q2) {
+          const double2 a = Rq[r - 1 + (k + 1) * q2], b = Rq[r + (k + 1) * q2];
+          Rq[r - 1 + (k + 1) * q2] = cadd(cscale(a, c), cmul(sg, b));
+          Rq[r + (k + 1) * q2] = csub(cscale(b, c), cmul(cconj(sg), a));
+        }
+        Rq[r + (k + 1) * jc] = mk(0.0, 0.0);
+        const double2 a = gq[r - 1], b = gq[r];
+        gq[r - 1] = cadd(cscale(a, c), cmul(sg, b));
+        gq[r] = csub(cscale(b, c), cmul(cconj(sg), a));
+        rcq[q] = c;
+        rsq[q] = sg;
+        rpq[q] = r - 1;
+        ++q;
+      }
+  }
+  __syncthreads();
+  for (int e = t; e < (k + 1) * k; e += blockDim.x) ks->R[(e % (k + 1)) + LD * (e / (k + 1))] = Rq[e];
+  for (int i = t; i <= MMAX; i += blockDim.x) ks->g[i] = (i <= k) ? gq[i] : mk(0.0, 0.0);
+  for (int q = t; q < nr; q += blockDim.x) {
+    ks->rot_c[q] = rcq[q];
+    ks->rot_s[q] = rsq[q];
+    ks->rot_p[q] = rpq[q];
+  }
+  if (t == 0) {
+    ks->nrot = nr;
+    ks->est = cabs_(gq[k]);
+  }
+  __syncthreads();
+}
+
 __global__ void k_qr_block(KState* ks, int k) {
   if (threadIdx.x == 0) qr_block_serial(ks, k);
 }
@@ -130,6 +186,75 @@ __global__ void k_proj_solve(const double2* Hk, int k, KState* ks) {
 
 void launch_proj_solve(hipStream_t s, const double2* Hk, int k, KState* ks) {
   hipLaunchKernelGGL(k_proj_solve, dim3(1), dim3(1), 0, s, Hk, k, ks);
+  DMG_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------- projection matrices of a deflation space
+// For Hbar_k ((k+1) x k, column-major, ld k+1) with Givens QR Hbar_k = Q [R; 0]:
+//   M  = R^{-1} [I_k 0] Q^H   (k x (k+1)): d = M c minimises || c - Hbar_k d ||
+//   Pi = Hbar_k M             ((k+1) x (k+1)): the projector onto range(Hbar_k)
+// Both column-major.  One workgroup; column i of M is formed by one thread.
+constexpr int KDMAX = 32;  // largest deflation space handled here
+__global__ void __launch_bounds__(DW) k_defl_prepare(const double2* Hk, int k, double2* M, double2* Pi) {
+  __shared__ double2 Rs[(KDMAX + 1) * KDMAX];
+  __shared__ double rc[KDMAX * (KDMAX + 1) / 2];
+  __shared__ double2 rsn[KDMAX * (KDMAX + 1) / 2];
+  __shared__ int rp[KDMAX * (KDMAX + 1) / 2];
+  __shared__ double2 Ms[KDMAX * (KDMAX + 1)];
+  const int t = threadIdx.x;
+  const int K1 = k + 1;
+  for (int e = t; e < K1 * k; e += DW) Rs[e] = Hk[e];
+  __syncthreads();
+  if (t == 0) {
+    int q = 0;
+    for (int jc = 0; jc < k; ++jc)
+      for (int r = k; r > jc; --r) {
+        double c;
+        double2 sg;
+        make_givens(Rs[r - 1 + K1 * jc], Rs[r + K1 * jc], c, sg);
+        for (int q2 = jc; q2 < k; ++q2) {
+          const double2 a = Rs[r - 1 + K1 * q2], b = Rs[r + K1 * q2];
+          Rs[r - 1 + K1 * q2] = cadd(cscale(a, c), cmul(sg, b));
+          Rs[r + K1 * q2] = csub(cscale(b, c), cmul(cconj(sg), a));
+        }
+        Rs[r + K1 * jc] = mk(0.0, 0.0);
+        rc[q] = c;
+        rsn[q] = sg;
+        rp[q] = r - 1;
+        ++q;
+      }
+  }
+  __syncthreads();
+  const int nr = k * (k + 1) / 2;
+  for (int col = t; col < K1; col += DW) {
+    double2 v[KDMAX + 1];
+    for (int i = 0; i <= k; ++i) v[i] = mk(i == col ? 1.0 : 0.0, 0.0);
+    for (int q = 0; q < nr; ++q) {
+      const int p = rp[q];
+      const double2 a = v[p], b = v[p + 1];
+      v[p] = cadd(cscale(a, rc[q]), cmul(rsn[q], b));
+      v[p + 1] = csub(cscale(b, rc[q]), cmul(cconj(rsn[q]), a));
+    }
+    for (int i = k - 1; i >= 0; --i) {
+      double2 acc = v[i];
+      for (int l = i + 1; l < k; ++l) acc = csub(acc, cmul(Rs[i + K1 * l], Ms[l + k * col]));
+      const double2 d = Rs[i + K1 * i];
+      Ms[i + k * col] = cabs2(d) > 0.0 ? cdiv(acc, d) : mk(0.0, 0.0);
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < k * K1; e += DW) M[e] = Ms[e];
+  for (int e = t; e < K1 * K1; e += DW) {
+    const int i = e % K1, col = e / K1;
+    double2 acc = mk(0.0, 0.0);
+    for (int l = 0; l < k; ++l) cfma(acc, Hk[i + K1 * l], Ms[l + k * col]);
+    Pi[e] = acc;
+  }
+}
+
+void launch_defl_prepare(hipStream_t s, const double2* Hk, int k, double2* M, double2* Pi) {
+  DMG_CHECK(k >= 1 && k <= KDMAX, DMG_E_INVALID, "deflation spaces above 32 vectors are not supported");
+  hipLaunchKernelGGL(k_defl_prepare, dim3(1), dim3(DW), 0, s, Hk, k, M, Pi);
   DMG_LAUNCH_CHECK();
 }
 
@@ -261,16 +386,17 @@ __global__ void __launch_bounds__(DW) k_dr_restart(KState* ks, int m, int k, dou
                                                    double2* work, int* status) {
   extern __shared__ double2 sh[];
   const int t = threadIdx.x;
-  double2* A = sh;              // m x m
-  double2* X = sh + m * m;      // m x m
-  double2* v = sh + 2 * m * m;  // m + 1
-  double2* Hb = work;                        // (m+1) x m copy of Hbar
+  (void)work;
+  double2* A = sh;                           // m x m
+  double2* X = A + m * m;                    // m x m
+  double2* v = X + m * m;                    // m + 1
+  double2* Hb = v + (m + 1);                 // (m+1) x m copy of Hbar
   double2* W = Hb + (m + 1) * m;             // (m+1) x (k+1)
   double2* T1 = W + (m + 1) * (k + 1);       // (m+1) x k
   double2* f = T1 + (m + 1) * k;             // m
   double2* s = f + m;                        // m + 1
   double2* theta = s + m + 1;                // m
-  int* sel = (int*)(theta + m);              // k ints (fits in m double2)
+  int* sel = (int*)(theta + m);              // k ints
   __shared__ int fail;
   if (t == 0) fail = 0;
   for (int e = t; e < (m + 1) * m; e += DW) Hb[e] = ks->H[(e % (m + 1)) + LD * (e / (m + 1))];
@@ -442,8 +568,9 @@ __global__ void __launch_bounds__(DW) k_dr_restart(KState* ks, int m, int k, dou
   }
   for (int e = t; e < (m + 1) * (k + 1); e += DW) Pout[e] = W[e];
   __syncthreads();
+  __syncthreads();
+  if (!final_mode) qr_block_lds(ks, k, A);  // A is free again: scratch for the block QR
   if (t == 0) {
-    if (!final_mode) qr_block_serial(ks, k);
     ks->steps = k;
     ks->done = 0;
     ks->breakdown = 0;
@@ -455,9 +582,16 @@ size_t dr_work_elems(int m, int k) {
   return (size_t)(m + 1) * m + 2 * (size_t)(m + 1) * (k + 1) + (size_t)(m + 1) * k + 4 * (size_t)m + 64;
 }
 
+static size_t dr_lds_bytes(int m, int k) {
+  return sizeof(double2) * ((size_t)2 * m * m + (m + 1) + (size_t)(m + 1) * m + (size_t)(m + 1) * (k + 1) +
+                            (size_t)(m + 1) * k + m + (m + 1) + m + (k + 1) / 2 + 2);
+}
+
 void launch_dr_restart(hipStream_t st, KState* ks, int m, int k, double2* Pout, int final_mode, double2* work,
-                            int* status) {
-  const size_t shm = (size_t)(2 * m * m + m + 2) * sizeof(double2);
+                       int* status) {
+  const size_t shm = dr_lds_bytes(m, k);
+  DMG_CHECK(shm <= 150 * 1024 && (size_t)m * m >= (size_t)(k + 1) * k, DMG_E_INVALID, "GMRES-DR sizes too large");
+  DMG_HIP(hipFuncSetAttribute((const void*)k_dr_restart, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
   hipLaunchKernelGGL(k_dr_restart, dim3(1), dim3(DW), shm, st, ks, m, k, Pout, final_mode, work, status);
   DMG_LAUNCH_CHECK();
 }

@@ -9,13 +9,14 @@ namespace dmg {
 
 // ---------------------------------------------------------------- stencils (stencil.hip)
 // Fine Wilson-Dirac operator; U has the fermion boundary sign folded in.
+// With `sub` non-null the output is sub - D in (a residual in one pass).
 template <typename R>
 void launch_wilson(hipStream_t st, const cx<R>* U, const cx<R>* in, cx<R>* out, double m0, int Nx, int Nt,
-                   int dagger, int nrhs, const int* skip = nullptr);
+                   int dagger, int nrhs, const int* skip = nullptr, const cx<R>* sub = nullptr);
 // Blocked-lattice operator: 5 blocks of 24 x 24 per site, stored [S][d][col][row].
 template <typename R>
 void launch_block_apply(hipStream_t st, const cx<R>* A, const cx<R>* in, cx<R>* out, int Lx, int Lt, int dagger,
-                        const int* skip = nullptr);
+                        const int* skip = nullptr, const cx<R>* sub = nullptr);
 // Restriction out = P^dagger in and prolongation out (+)= P in.  P is [site][dof][12] on the
 // finer lattice Lx x Lt with `dof` components per site.
 template <typename R>
@@ -76,6 +77,15 @@ void launch_basis_rotate(hipStream_t s, const cx<R>* Vin, cx<R>* Vout, int64_t l
 template <typename R>
 void launch_scale_dev(hipStream_t s, int64_t n, const cx<R>* x, cx<R>* y, const double* scale, int invert_sqrt);
 
+// Two-step GMRES smoother from x0 = 0 given w1 = A v and w2 = A w1: y = c0 v + c1 w1
+// minimising || v - A y ||, and r = v - A y (skipped when r is null).  coef: 2 device double2.
+template <typename R>
+void launch_smooth2(hipStream_t s, const cx<R>* v, const cx<R>* w1, const cx<R>* w2, int64_t n, double2* coef,
+                    cx<R>* y, cx<R>* r, double2* partials, unsigned* counter);
+// z = a x + b y
+template <typename R>
+void launch_axpbyz(hipStream_t s, int64_t n, double a, const cx<R>* x, double b, const cx<R>* y, cx<R>* z);
+
 // ---------------------------------------------------------------- small dense (dense.hip)
 // Back-substitution y = R^{-1} g for the completed steps; then u = c - H y.
 void launch_ls_solve(hipStream_t s, KState* ks);
@@ -93,16 +103,22 @@ void launch_qr_block(hipStream_t s, KState* ks, int k);
 void launch_proj_solve(hipStream_t s, const double2* Hk, int k, KState* ks);
 
 // ---------------------------------------------------------------- persistent coarse solve (coarse.hip)
-// One cooperative launch per GMRES-Proj(m, k) coarse solve from x = 0.  Returns 0 (nothing
+// One cooperative launch per GMRES-Proj(m, k) coarse solve from x = 0; DM and DP are the
+// projection matrices of launch_defl_prepare.  Returns 0 (nothing
 // launched) when the grid cannot be co-resident; out_iters / out_relres receive the Arnoldi
 // steps taken and the final recurrence residual relative to ||b||.  flags: barrier words
 // (coarse_proj_flag_words(G) needed, zeroed by the launcher); err: set on a barrier timeout.
 template <typename R>
-int launch_coarse_proj(hipStream_t st, const cx<R>* A, int Lx, int Lt, const cx<R>* DV, const double2* DH, int k,
+int launch_coarse_proj(hipStream_t st, const cx<R>* A, int Lx, int Lt, const cx<R>* DV, const double2* DM,
+                       const double2* DP, int k,
                        const cx<R>* b, cx<R>* x, double tol, int mm, int max_iters, cx<R>* xchg,
                        double2* partials, size_t partials_elems, int* out_iters, double* out_relres,
                        unsigned* flags, size_t flag_words, int* err, int groups);
 size_t coarse_proj_flag_words(int G);
+
+// Projection matrices of a deflation space: M = Hbar_k^+ (k x (k+1)) and Pi = Hbar_k M
+// ((k+1) x (k+1)), column-major.
+void launch_defl_prepare(hipStream_t s, const double2* Hk, int k, double2* M, double2* Pi);
 
 // ---------------------------------------------------------------- setup (setup.hip)
 // Batched CG on A A^dagger for nvec fields (x, r, p, q stored as nvec consecutive fields).

@@ -32,13 +32,16 @@ struct Op {
   double m0 = 0.0;
   const double2* A64 = nullptr;
   const float2* A32 = nullptr;
-  void apply(hipStream_t s, const double2* in, double2* out, int dag, const int* skip) const {
-    if (kind == 0) launch_wilson<double>(s, U64, in, out, m0, Lx, Lt, dag, 1, skip);
-    else launch_block_apply<double>(s, A64, in, out, Lx, Lt, dag, skip);
+  // out = A in (sub null) or out = sub - A in
+  void apply(hipStream_t s, const double2* in, double2* out, int dag, const int* skip,
+             const double2* sub = nullptr) const {
+    if (kind == 0) launch_wilson<double>(s, U64, in, out, m0, Lx, Lt, dag, 1, skip, sub);
+    else launch_block_apply<double>(s, A64, in, out, Lx, Lt, dag, skip, sub);
   }
-  void apply(hipStream_t s, const float2* in, float2* out, int dag, const int* skip) const {
-    if (kind == 0) launch_wilson<float>(s, U32, in, out, m0, Lx, Lt, dag, 1, skip);
-    else launch_block_apply<float>(s, A32, in, out, Lx, Lt, dag, skip);
+  void apply(hipStream_t s, const float2* in, float2* out, int dag, const int* skip,
+             const float2* sub = nullptr) const {
+    if (kind == 0) launch_wilson<float>(s, U32, in, out, m0, Lx, Lt, dag, 1, skip, sub);
+    else launch_block_apply<float>(s, A32, in, out, Lx, Lt, dag, skip, sub);
   }
 };
 
@@ -81,6 +84,7 @@ struct dmg_deflation {
   int ready = 0;
   int cast_ready = 0;  // FP32 copy of V up to date
   dmg::DevBuf V64, V32, H;  // V: n_c x (kk + 1); H: (kk + 1) x kk column-major, ld kk + 1
+  dmg::DevBuf M, Pi;        // projection matrices Hbar^+ (kk x (kk+1)) and Hbar Hbar^+
 };
 
 struct dmg_hierarchy {

@@ -137,6 +137,9 @@ int coarse_gmres_dr(dmg_hierarchy* h, dmg_deflation* d, const double2* b, double
                              sizeof(double2) * (kk + 1), kk, hipMemcpyDeviceToDevice, s));
     d->kk = kk;
   }
+  d->M.alloc(h->ctx, sizeof(double2) * (size_t)d->kk * (d->kk + 1));
+  d->Pi.alloc(h->ctx, sizeof(double2) * (size_t)(d->kk + 1) * (d->kk + 1));
+  launch_defl_prepare(s, d->H.as<double2>(), d->kk, d->M.as<double2>(), d->Pi.as<double2>());
   d->ready = 1;
   d->cast_ready = 0;
   h->cnt.dr_calls++;
@@ -369,12 +372,21 @@ struct Precond {
   }
 
   // GMRES(s) from x = 0 on level lvl: y = approximate A^{-1} v; r = v - A y from the
-  // Arnoldi relation when requested (no extra matrix-vector product).
+  // least-squares relation when requested (no extra matrix-vector product).  Two steps
+  // (the paper's smoother) use the fused kernels: w1 = A v, w2 = A w1, one Gram reduction
+  // with the 2 x 2 solve, one combination.  Other step counts run the Arnoldi kernels.
   void smooth(int lvl, const T* v, T* yout, T* rout) {
     KWS& w = sm[lvl];
     KState* ks = w.state();
     T* V = w.V.as<T>();
     const int64_t n = w.n;
+    if (smooth_steps == 2) {
+      h->op[lvl].apply(S(), v, V, 0, nullptr);
+      h->op[lvl].apply(S(), V, V + n, 0, nullptr);
+      h->cnt.mv[lvl] += 2;
+      launch_smooth2<R>(S(), v, V, V + n, n, ks->y, yout, rout, PART(h), CNT(h));
+      return;
+    }
     launch_cycle_start<R>(S(), v, V, n, ks, -1.0, 1, PART(h), CNT(h));
     for (int j = 0; j < smooth_steps; ++j) {
       h->op[lvl].apply(S(), V + j * n, V + (j + 1) * n, 0, &ks->done);
@@ -402,7 +414,8 @@ struct Precond {
       const T* Ab = (const T*)(sizeof(R) == sizeof(double) ? (const void*)A.A64 : (const void*)A.A32);
       if (!bflags.p) bflags.alloc(h->ctx, sizeof(unsigned) * coarse_proj_flag_words(256));
       int* err_d = h->flags.as<int>() + 9;  // read back together with the step count
-      if (launch_coarse_proj<R>(S(), Ab, A.Lx, A.Lt, DV, DH, k, b, x, tol, mm, p->coarse_max_iters,
+      if (launch_coarse_proj<R>(S(), Ab, A.Lx, A.Lt, DV, d->M.as<double2>(), d->Pi.as<double2>(), k, b, x, tol, mm,
+                                p->coarse_max_iters,
                                 xchg.as<T>(), PART(h), h->partials.bytes / sizeof(double2), it_d, rr_d,
                                 bflags.as<unsigned>(), bflags.bytes / sizeof(unsigned), err_d, 0)) {
         (void)err_d;  // step count and barrier status are read once per outer solve
@@ -491,12 +504,10 @@ struct Precond {
     launch_restrict<R>(S(), Pm(1), r1, bc.as<T>(), h->tr[1].Lx, h->tr[1].Lt, NC);
     coarse_solve(bc.as<T>(), ec.as<T>());
     launch_prolong<R>(S(), Pm(1), ec.as<T>(), y1, h->tr[1].Lx, h->tr[1].Lt, NC, 1);
-    h->op[1].apply(S(), y1, q, 0, nullptr);
+    h->op[1].apply(S(), y1, q, 0, nullptr, v);  // q = v - D_hat y1
     h->cnt.mv[1]++;
-    launch_xmy<R>(S(), n, v, q);
     smooth(1, q, s1, nullptr);
-    launch_axpby<R>(S(), n, 1.0, y1, 1.0, s1);
-    DMG_HIP(hipMemcpyAsync(out, s1, sizeof(T) * n, hipMemcpyDeviceToDevice, S()));
+    launch_axpbyz<R>(S(), n, 1.0, y1, 1.0, s1, out);
   }
 
   // partial intermediate solve E1: FGMRES(int_m) on D_hat with M1 to int_tol ||b||
@@ -528,9 +539,8 @@ struct Precond {
       iters += st.steps;
       if (st.est <= st.tol_abs || st.breakdown || iters >= p->int_max_iters) break;
       T* res = e1r.as<T>();
-      A.apply(S(), x, res, 0, nullptr);
+      A.apply(S(), x, res, 0, nullptr, b);
       h->cnt.mv[1]++;
-      launch_xmy<R>(S(), n, b, res);
       rr = res;
     }
   }
@@ -546,12 +556,10 @@ struct Precond {
     launch_restrict<R>(S(), Pm(0), r0, bh.as<T>(), h->tr[0].Lx, h->tr[0].Lt, 2);
     partial_solve(bh.as<T>(), e1x.as<T>());
     launch_prolong<R>(S(), Pm(0), e1x.as<T>(), y0, h->tr[0].Lx, h->tr[0].Lt, 2, 1);
-    h->op[0].apply(S(), y0, q, 0, nullptr);
+    h->op[0].apply(S(), y0, q, 0, nullptr, v);  // q = v - D y0
     h->cnt.mv[0]++;
-    launch_xmy<R>(S(), n, v, q);
     smooth(0, q, s0, nullptr);
-    launch_axpby<R>(S(), n, 1.0, y0, 1.0, s0);
-    DMG_HIP(hipMemcpyAsync(out, s0, sizeof(T) * n, hipMemcpyDeviceToDevice, S()));
+    launch_axpbyz<R>(S(), n, 1.0, y0, 1.0, s0, out);
   }
 };
 
@@ -652,9 +660,8 @@ dmg_status outer_solve(dmg_hierarchy* h, dmg_deflation* d, const dmg_solve_param
       launch_combine<double, double>(s, x, Z, n, n, ks, 0, 1);
       iters += st.steps;
       // true residual r = b - D x
-      A.apply(s, x, r, 0, nullptr);
+      A.apply(s, x, r, 0, nullptr, b);
       h->cnt.mv[0]++;
-      launch_xmy<double>(s, n, b, r);
       launch_norm2<double>(s, n, r, scal, PART(h), CNT(h));
       rel = std::sqrt(read_double(h, scal)) / bnorm;
       conv = rel <= p->tol;

@@ -16,7 +16,7 @@ template <typename T> __device__ inline T cmul_i(T z) { T r; r.x = -z.y; r.y = z
 template <typename R>
 __global__ void __launch_bounds__(256) k_wilson(const cx<R>* __restrict__ U, const cx<R>* __restrict__ in,
                                                 cx<R>* __restrict__ out, R diag, int Nx, int Nt, int dagger,
-                                                const int* skip) {
+                                                const int* skip, const cx<R>* __restrict__ sub) {
   if (skip && *skip) return;
   using T = cx<R>;
   const int V = Nx * Nt;
@@ -63,16 +63,20 @@ __global__ void __launch_bounds__(256) k_wilson(const cx<R>* __restrict__ U, con
     acc0 = csub(acc0, cscale(w, half));
     acc1 = csub(acc1, cscale(cmul_i(w), half * sg));
   }
+  if (sub) {
+    acc0 = csub(sub[off + 2 * s], acc0);
+    acc1 = csub(sub[off + 2 * s + 1], acc1);
+  }
   out[2 * s] = acc0;
   out[2 * s + 1] = acc1;
 }
 
 template <typename R>
 void launch_wilson(hipStream_t st, const cx<R>* U, const cx<R>* in, cx<R>* out, double m0, int Nx, int Nt,
-                   int dagger, int nrhs, const int* skip) {
+                   int dagger, int nrhs, const int* skip, const cx<R>* sub) {
   const int V = Nx * Nt;
   dim3 grid((V + 255) / 256, nrhs);
-  hipLaunchKernelGGL(k_wilson<R>, grid, dim3(256), 0, st, U, in, out, (R)(m0 + 2.0), Nx, Nt, dagger, skip);
+  hipLaunchKernelGGL(k_wilson<R>, grid, dim3(256), 0, st, U, in, out, (R)(m0 + 2.0), Nx, Nt, dagger, skip, sub);
   DMG_LAUNCH_CHECK();
 }
 
@@ -86,7 +90,7 @@ constexpr int BA_SITES = 4;  // sites per workgroup: 4 * 5 * 24 = 480 threads
 template <typename R>
 __global__ void __launch_bounds__(512) k_block_apply(const cx<R>* __restrict__ A, const cx<R>* __restrict__ in,
                                                      cx<R>* __restrict__ out, int Lx, int Lt, int dagger,
-                                                     const int* skip) {
+                                                     const int* skip, const cx<R>* __restrict__ sub) {
   if (skip && *skip) return;
   using T = cx<R>;
   __shared__ T xs[BA_SITES][5][NC];
@@ -128,16 +132,17 @@ __global__ void __launch_bounds__(512) k_block_apply(const cx<R>* __restrict__ A
     y = cadd(y, part[ls][3][i]);
     y = cadd(y, part[ls][4][i]);
     if (dagger && i >= NV) { y.x = -y.x; y.y = -y.y; }
+    if (sub) y = csub(sub[(int64_t)S * NC + i], y);
     out[(int64_t)S * NC + i] = y;
   }
 }
 
 template <typename R>
 void launch_block_apply(hipStream_t st, const cx<R>* A, const cx<R>* in, cx<R>* out, int Lx, int Lt, int dagger,
-                        const int* skip) {
+                        const int* skip, const cx<R>* sub) {
   const int V = Lx * Lt;
   hipLaunchKernelGGL(k_block_apply<R>, dim3((V + BA_SITES - 1) / BA_SITES), dim3(BA_SITES * 5 * NC), 0, st, A, in,
-                     out, Lx, Lt, dagger, skip);
+                     out, Lx, Lt, dagger, skip, sub);
   DMG_LAUNCH_CHECK();
 }
 
@@ -215,8 +220,9 @@ void launch_prolong(hipStream_t st, const cx<R>* P, const cx<R>* coarse, cx<R>* 
 
 #define INST(R)                                                                                                   \
   template void launch_wilson<R>(hipStream_t, const cx<R>*, const cx<R>*, cx<R>*, double, int, int, int, int,     \
-                                 const int*);                                                                     \
-  template void launch_block_apply<R>(hipStream_t, const cx<R>*, const cx<R>*, cx<R>*, int, int, int, const int*); \
+                                 const int*, const cx<R>*);                                                       \
+  template void launch_block_apply<R>(hipStream_t, const cx<R>*, const cx<R>*, cx<R>*, int, int, int, const int*,  \
+                                      const cx<R>*);                                                              \
   template void launch_restrict<R>(hipStream_t, const cx<R>*, const cx<R>*, cx<R>*, int, int, int);               \
   template void launch_prolong<R>(hipStream_t, const cx<R>*, const cx<R>*, cx<R>*, int, int, int, int);
 INST(double)
