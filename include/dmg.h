@@ -86,6 +86,17 @@ const char* dmg_last_error(const dmg_context* ctx);
 /* Bytes of device memory currently held by the context. */
 size_t dmg_context_bytes_in_use(const dmg_context* ctx);
 
+/* Kernel timing: for the kernels whose bit (1 << DMG_KT_*) is set in `mask`, the
+ * library brackets every launch with HIP events on the context's stream
+ * (mask 0 turns timing off).  Reading synchronises the stream and returns, per
+ * kernel, the summed event time, the launch count and the work units processed
+ * (coarse solve: Arnoldi steps; intermediate stencil: blocked sites).  Every
+ * call of dmg_kernel_timer resets the sums. */
+enum { DMG_KT_COARSE_PROJ = 0, DMG_KT_BLOCK_APPLY_INT = 1, DMG_KT_COUNT = 2 };
+dmg_status dmg_kernel_timer(dmg_context* ctx, int mask);
+dmg_status dmg_kernel_timer_read(dmg_context* ctx, int kernel, double* total_ms, long long* launches,
+                                 long long* units);
+
 /* ------------------------------------------------------------------ gauge */
 
 /* Upload U(1) links U_mu(x, t) = exp(i theta[t][x][mu]) (mu = 0: x, 1: t;

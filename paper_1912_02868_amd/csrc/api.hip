@@ -34,6 +34,23 @@ void dev_free(dmg_context* c, void* p, size_t bytes) {
   c->in_use -= std::min(bytes ? bytes : 16, c->in_use);
 }
 
+hipEvent_t timer_mark(dmg_context* c, int kernel) {
+  if (!(c->timing & (1 << kernel))) return nullptr;
+  if (c->ev_used == c->ev_pool.size()) {
+    hipEvent_t e;
+    DMG_HIP(hipEventCreate(&e));
+    c->ev_pool.push_back(e);
+  }
+  hipEvent_t e = c->ev_pool[c->ev_used++];
+  DMG_HIP(hipEventRecord(e, c->stream));
+  return e;
+}
+
+void timer_span(dmg_context* c, int kernel, hipEvent_t a, hipEvent_t b, long long units) {
+  if (!(c->timing & (1 << kernel)) || !a || !b) return;
+  c->spans.push_back({kernel, a, b, units});
+}
+
 // links U = exp(i theta), antiperiodic sign on the temporal links of the last time slice
 __global__ void k_links(const double* theta, int Nx, int Nt, int anti, double2* U64, float2* U32) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -110,6 +127,10 @@ void dmg_setup_params_default(dmg_setup_params* p) {
   p->null_max_iters = 2000;
 }
 
+dmg_context::~dmg_context() {
+  for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+}
+
 dmg_status dmg_context_create(int device, void* hip_stream, const dmg_allocator* alloc, size_t hbm_budget,
                               dmg_context** out) {
   if (!out) return DMG_E_INVALID;
@@ -128,6 +149,42 @@ dmg_status dmg_context_create(int device, void* hip_stream, const dmg_allocator*
 }
 
 void dmg_context_destroy(dmg_context* ctx) { delete ctx; }
+
+dmg_status dmg_kernel_timer(dmg_context* ctx, int mask) {
+  if (!ctx) return DMG_E_INVALID;
+  return guard(ctx, [&]() -> dmg_status {
+    DMG_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->timing = mask & ((1 << DMG_KT_COUNT) - 1);
+    ctx->spans.clear();
+    ctx->ev_used = 0;
+    for (long long& u : ctx->pending_units) u = 0;
+    return DMG_OK;
+  });
+}
+
+dmg_status dmg_kernel_timer_read(dmg_context* ctx, int kernel, double* total_ms, long long* launches,
+                                 long long* units) {
+  if (!ctx) return DMG_E_INVALID;
+  return guard(ctx, [&]() -> dmg_status {
+    DMG_CHECK(kernel >= 0 && kernel < DMG_KT_COUNT, DMG_E_INVALID, "unknown timed kernel");
+    DMG_HIP(hipStreamSynchronize(ctx->stream));
+    double ms = 0.0;
+    long long n = 0, u = 0;
+    for (const auto& sp : ctx->spans) {
+      if (sp.kernel != kernel) continue;
+      float t = 0.0f;
+      DMG_HIP(hipEventElapsedTime(&t, sp.a, sp.b));
+      ms += t;
+      ++n;
+      u += sp.units;
+    }
+    if (kernel == DMG_KT_COARSE_PROJ) u = ctx->pending_units[kernel];
+    if (total_ms) *total_ms = ms;
+    if (launches) *launches = n;
+    if (units) *units = u;
+    return DMG_OK;
+  });
+}
 
 const char* dmg_last_error(const dmg_context* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 

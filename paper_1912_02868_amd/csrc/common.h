@@ -110,7 +110,21 @@ struct dmg_context {
   size_t budget = 0;
   size_t in_use = 0;
   std::string err;
+  // kernel timer (dmg_kernel_timer): event pairs per timed kernel, work units per launch
+  int timing = 0;  // bit mask of timed kernels
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  struct Span { int kernel; hipEvent_t a, b; long long units; };
+  std::vector<Span> spans;
+  long long pending_units[4] = {0, 0, 0, 0};
+  ~dmg_context();
 };
+
+namespace dmg {
+// Records an event on the context's stream when kernel `kernel` is timed (nullptr otherwise).
+hipEvent_t timer_mark(dmg_context* c, int kernel);
+void timer_span(dmg_context* c, int kernel, hipEvent_t a, hipEvent_t b, long long units);
+}  // namespace dmg
 
 namespace dmg {
 // Device memory through the context's allocator hooks, charged against its budget.

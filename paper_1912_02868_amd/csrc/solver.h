@@ -33,10 +33,14 @@ struct Op {
   const double2* A64 = nullptr;
   const float2* A32 = nullptr;
   // out = A in (sub null) or out = sub - A in
+  dmg_context* ctx = nullptr;  // for the kernel timer
+  int timer_id = -1;            // DMG_KT_* of this operator's stencil, or -1
   void apply(hipStream_t s, const double2* in, double2* out, int dag, const int* skip,
              const double2* sub = nullptr) const {
+    hipEvent_t ta = (timer_id >= 0 && ctx) ? timer_mark(ctx, timer_id) : nullptr;
     if (kind == 0) launch_wilson<double>(s, U64, in, out, m0, Lx, Lt, dag, 1, skip, sub);
     else launch_block_apply<double>(s, A64, in, out, Lx, Lt, dag, skip, sub);
+    if (ta) timer_span(ctx, timer_id, ta, timer_mark(ctx, timer_id), (long long)Lx * Lt);
   }
   void apply(hipStream_t s, const float2* in, float2* out, int dag, const int* skip,
              const float2* sub = nullptr) const {

@@ -302,6 +302,8 @@ void build_hierarchy(dmg_hierarchy* h, const double2* start0, const double2* sta
     }
     launch_d2f(s, ce, h->A64[lvl + 1].as<double2>(), h->A32[lvl + 1].as<float2>());
     Op& C = h->op[lvl + 1];
+    C.ctx = h->ctx;
+    C.timer_id = lvl == 0 ? DMG_KT_BLOCK_APPLY_INT : -1;
     C.kind = 1;
     C.Lx = CLx;
     C.Lt = CLt;
@@ -414,11 +416,13 @@ struct Precond {
       const T* Ab = (const T*)(sizeof(R) == sizeof(double) ? (const void*)A.A64 : (const void*)A.A32);
       if (!bflags.p) bflags.alloc(h->ctx, sizeof(unsigned) * coarse_proj_flag_words(256));
       int* err_d = h->flags.as<int>() + 9;  // read back together with the step count
+      hipEvent_t ta = timer_mark(h->ctx, DMG_KT_COARSE_PROJ);
       if (launch_coarse_proj<R>(S(), Ab, A.Lx, A.Lt, DV, d->M.as<double2>(), d->Pi.as<double2>(), k, b, x, tol, mm,
                                 p->coarse_max_iters,
                                 xchg.as<T>(), PART(h), h->partials.bytes / sizeof(double2), it_d, rr_d,
                                 bflags.as<unsigned>(), bflags.bytes / sizeof(unsigned), err_d, 0)) {
         (void)err_d;  // step count and barrier status are read once per outer solve
+        timer_span(h->ctx, DMG_KT_COARSE_PROJ, ta, timer_mark(h->ctx, DMG_KT_COARSE_PROJ), 0);
         return;
       }
     }
@@ -675,6 +679,7 @@ dmg_status outer_solve(dmg_hierarchy* h, dmg_deflation* d, const dmg_solve_param
     const int* hs = (const int*)h->host_status;
     DMG_CHECK(hs[1] == 0, DMG_E_HIP, "persistent coarse solve: a grid-barrier wait timed out");
     h->cnt.mv[2] += hs[0];
+    if (h->ctx->timing & (1 << DMG_KT_COARSE_PROJ)) h->ctx->pending_units[DMG_KT_COARSE_PROJ] += hs[0];
   }
   if (stout) {
     dmg_solve_stats& o = *stout;

@@ -38,7 +38,9 @@ EXPORTED = [
     "dmg_deflation_create", "dmg_deflation_build", "dmg_deflation_reset", "dmg_deflation_ready",
     "dmg_deflation_export", "dmg_deflation_destroy",
     "dmg_solve_params_default", "dmg_setup_params_default", "dmg_solve",
+    "dmg_kernel_timer", "dmg_kernel_timer_read",
 ]
+KT_COARSE_PROJ, KT_BLOCK_APPLY_INT = 0, 1
 
 
 class DmgError(RuntimeError):
@@ -131,6 +133,9 @@ def lib():
         "dmg_solve_params_default": (None, [C.POINTER(SolveParams)]),
         "dmg_setup_params_default": (None, [C.POINTER(SetupParams)]),
         "dmg_solve": (i, [vp, vp, vp, C.POINTER(SolveParams), vp, vp, i, i, C.POINTER(SolveStats)]),
+        "dmg_kernel_timer": (i, [vp, i]),
+        "dmg_kernel_timer_read": (i, [vp, i, C.POINTER(C.c_double), C.POINTER(C.c_longlong),
+                                      C.POINTER(C.c_longlong)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -212,6 +217,19 @@ class Context:
         if st < 0:
             raise DmgError(st, f"{what}: {lib().dmg_last_error(self.h).decode()}")
         return st
+
+    def timer(self, *kernels: int):
+        """Time the given kernels (KT_*) from now on, resetting the sums; no argument stops timing."""
+        mask = 0
+        for k in kernels:
+            mask |= 1 << k
+        self.check(lib().dmg_kernel_timer(self.h, mask), "kernel_timer")
+
+    def timer_read(self, kernel: int):
+        """(total ms, launches, work units) of a timed kernel since the timer was enabled."""
+        ms, n, u = C.c_double(), C.c_longlong(), C.c_longlong()
+        self.check(lib().dmg_kernel_timer_read(self.h, kernel, C.byref(ms), C.byref(n), C.byref(u)), "timer_read")
+        return ms.value, n.value, u.value
 
     @property
     def bytes_in_use(self) -> int:
