@@ -85,6 +85,9 @@ void dmg_context_destroy(dmg_context* ctx);
 const char* dmg_last_error(const dmg_context* ctx);
 /* Bytes of device memory currently held by the context. */
 size_t dmg_context_bytes_in_use(const dmg_context* ctx);
+/* Changes the HBM budget (0: none).  Memory already held is kept even when it
+ * exceeds the new budget; later allocations past it fail with DMG_E_BUDGET. */
+dmg_status dmg_context_set_budget(dmg_context* ctx, size_t hbm_budget);
 
 /* Kernel timing: for the kernels whose bit (1 << DMG_KT_*) is set in `mask`, the
  * library brackets every launch with HIP events on the context's stream
@@ -200,8 +203,10 @@ typedef struct {
   int coarse_max_iters;    /* cap on coarse Arnoldi steps per call (5000) */
   dmg_precision precond;   /* preconditioner precision (outer is FP64) */
   int use_x0;              /* 1: x holds the initial guess */
-  int coarse_persistent;   /* 1: each GMRES-Proj coarse solve is one cooperative kernel launch
-                              (default); 0: one launch per Arnoldi sub-step */
+  int coarse_persistent;   /* each GMRES-Proj coarse solve as one persistent kernel: 1 cooperative
+                              launch (default), 2 plain launch (only when nothing else runs on
+                              the device: the grid must become co-resident); 0: one launch per
+                              Arnoldi sub-step */
 } dmg_solve_params;
 
 typedef struct {
@@ -219,11 +224,77 @@ void dmg_solve_params_default(dmg_solve_params* p);
 void dmg_setup_params_default(dmg_setup_params* p);
 
 /* Solve D x = b for nrhs fine right-hand sides (FP64), one after the other,
- * sharing the hierarchy and the deflation space (NULL: GMRES(m) coarse solves
- * with no deflation).  stats: array of nrhs entries (may be NULL).  Returns
- * DMG_OK, or DMG_W_NOT_CONVERGED if some RHS hit its cap (best iterate written). */
+ * sharing the hierarchy and the deflation space (Sec. 2-3: the space found by
+ * GMRES-DR in the first coarse solve serves every later coarse solve through
+ * GMRES-Proj).  d == NULL gives the non-deflated comparison method: every coarse
+ * solve is CG on the normal equations D_c D_c^dagger y = b_c, x = D_c^dagger y, to
+ * coarse_tol_first.  b and x hold nrhs fields of 2 * Nx * Nt complex doubles
+ * ([t][x][spin], interleaved re/im).  stats: array of nrhs entries (may be NULL).
+ * Returns DMG_OK, or DMG_W_NOT_CONVERGED if some RHS hit its cap (best iterate
+ * written). */
 dmg_status dmg_solve(dmg_context* ctx, dmg_hierarchy* h, dmg_deflation* d, const dmg_solve_params* prm,
                      const void* b, void* x, int nrhs, int ptr_kind, dmg_solve_stats* stats);
+
+/* ---------------------------------------------------------------------------
+ * Batch: continuous batching of independent solves (serving form).
+ *
+ * A batch owns `capacity` slots.  Each slot has its own device stream, host worker
+ * thread and solver workspace, so the solves of different slots overlap on the
+ * device.  A slot takes one right-hand side of any hierarchy of the batch's context
+ * (different configurations and lattice sizes may share a batch); slots join and
+ * leave between steps:
+ *
+ *   admit(slot, h, d, b)  -> slot RUNNING        (FREE slots only)
+ *   step(min_iters)       -> every RUNNING slot with no advance in flight starts one:
+ *                            whole FGMRES(m) cycles until it ran at least min_iters
+ *                            more outer iterations or finished (then it becomes
+ *                            DONE).  Returns once some advance has ended; the others
+ *                            go on in the background, so short solves are retired
+ *                            and their slots refilled while long ones run.
+ *   retire(slot, x)       -> DONE slot returns its solution and becomes FREE
+ *
+ * The calls on one batch come from one host thread.
+ * The outer FGMRES cycles are never cut, so a solve performs the same arithmetic
+ * whatever the step sizes and whichever other solves share the batch; the result
+ * is bitwise that of dmg_solve with the same parameters and deflation state.
+ * The deflation space of an admitted solve must be READY (dmg_deflation_build, or
+ * an earlier dmg_solve) and is only read, so results do not depend on arrival
+ * order; d == NULL selects the non-deflated method.  A hierarchy and its deflation
+ * space must outlive the slots that use them and must not be rebuilt or reset
+ * while admitted.  Persistent coarse solves in a batch are launched cooperatively
+ * (coarse_persistent 2 is taken as 1): the runtime then places the whole grid at
+ * once, while a plain-launched grid could wait behind the other slots' kernels for
+ * its last workgroups.  At most DMG_BATCH_MAX_SLOTS slots.
+ * ------------------------------------------------------------------------- */
+typedef struct dmg_batch dmg_batch;
+#define DMG_BATCH_MAX_SLOTS 8
+
+enum { DMG_SLOT_FREE = 0, DMG_SLOT_RUNNING = 1, DMG_SLOT_DONE = 2 };
+
+/* prm: solve parameters of every slot (NULL: defaults).  Errors: DMG_E_INVALID (capacity outside [1, DMG_BATCH_MAX_SLOTS], bad
+ * parameters), DMG_E_HIP (stream creation). */
+dmg_status dmg_batch_create(dmg_context* ctx, int capacity, const dmg_solve_params* prm, dmg_batch** out);
+/* Copies b (one fine field of h, host or device by ptr_kind) into the slot and
+ * allocates the slot's workspace for h (DMG_E_BUDGET past the context's HBM
+ * budget: the request is not admitted and the slot stays FREE).  DMG_E_INVALID if
+ * the slot is not FREE, h belongs to another context, or d is not READY. */
+dmg_status dmg_batch_admit(dmg_batch* bt, int slot, dmg_hierarchy* h, dmg_deflation* d, const void* b,
+                           int ptr_kind);
+/* Starts an advance on every idle RUNNING slot as described above and waits until
+ * one advance (of any slot) has ended; returns at once if none is in flight.
+ * n_done (may be NULL): slots now DONE.  A solve that fails becomes DONE with its
+ * error, reported by retire; step itself fails only on invalid arguments. */
+dmg_status dmg_batch_step(dmg_batch* bt, int min_iters, int* n_done);
+/* Copies the slot's solution to x (host or device by ptr_kind), fills stats (may be
+ * NULL; elapsed_ms runs from admission) and frees the slot.  Returns the solve's
+ * status (DMG_OK, DMG_W_NOT_CONVERGED or its error; dmg_last_error has the text).
+ * DMG_E_INVALID if the slot is not DONE. */
+dmg_status dmg_batch_retire(dmg_batch* bt, int slot, void* x, int ptr_kind, dmg_solve_stats* stats);
+/* DMG_SLOT_* of a slot, or -1 for a bad slot index. */
+int dmg_batch_slot_state(dmg_batch* bt, int slot);
+/* Waits for advances in flight, the slots' streams and threads, then releases
+ * everything; tolerates NULL. */
+void dmg_batch_destroy(dmg_batch* bt);
 
 #ifdef __cplusplus
 }

@@ -12,6 +12,7 @@ namespace dmg {
 
 void* dev_alloc(dmg_context* c, size_t bytes) {
   if (bytes == 0) bytes = 16;
+  std::lock_guard<std::mutex> lk(c->mu);
   if (c->budget && c->in_use + bytes > c->budget)
     throw Error{DMG_E_BUDGET, "allocation of " + std::to_string(bytes) + " bytes exceeds the HBM budget (" +
                                   std::to_string(c->in_use) + " of " + std::to_string(c->budget) + " in use)"};
@@ -29,25 +30,28 @@ void* dev_alloc(dmg_context* c, size_t bytes) {
 
 void dev_free(dmg_context* c, void* p, size_t bytes) {
   if (!p) return;
+  std::lock_guard<std::mutex> lk(c->mu);
   if (c->alloc.free) c->alloc.free(p, c->alloc.user);
   else (void)hipFree(p);
   c->in_use -= std::min(bytes ? bytes : 16, c->in_use);
 }
 
-hipEvent_t timer_mark(dmg_context* c, int kernel) {
+hipEvent_t timer_mark(dmg_context* c, int kernel, hipStream_t stream) {
   if (!(c->timing & (1 << kernel))) return nullptr;
+  std::lock_guard<std::mutex> lk(c->mu);
   if (c->ev_used == c->ev_pool.size()) {
     hipEvent_t e;
     DMG_HIP(hipEventCreate(&e));
     c->ev_pool.push_back(e);
   }
   hipEvent_t e = c->ev_pool[c->ev_used++];
-  DMG_HIP(hipEventRecord(e, c->stream));
+  DMG_HIP(hipEventRecord(e, stream));
   return e;
 }
 
 void timer_span(dmg_context* c, int kernel, hipEvent_t a, hipEvent_t b, long long units) {
   if (!(c->timing & (1 << kernel)) || !a || !b) return;
+  std::lock_guard<std::mutex> lk(c->mu);
   c->spans.push_back({kernel, a, b, units});
 }
 
@@ -81,14 +85,20 @@ static dmg_status guard(dmg_context* c, F&& f) {
 }
 
 // copy between caller buffers and device scratch
-static void to_device(dmg_context* c, void* dst, const void* src, size_t bytes, int ptr_kind) {
+static void to_device(hipStream_t s, void* dst, const void* src, size_t bytes, int ptr_kind) {
   DMG_HIP(hipMemcpyAsync(dst, src, bytes, ptr_kind == DMG_PTR_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
-                         c->stream));
+                         s));
+}
+static void from_device(hipStream_t s, void* dst, const void* src, size_t bytes, int ptr_kind) {
+  DMG_HIP(hipMemcpyAsync(dst, src, bytes, ptr_kind == DMG_PTR_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                         s));
+  if (ptr_kind == DMG_PTR_HOST) DMG_HIP(hipStreamSynchronize(s));
+}
+static void to_device(dmg_context* c, void* dst, const void* src, size_t bytes, int ptr_kind) {
+  to_device(c->stream, dst, src, bytes, ptr_kind);
 }
 static void from_device(dmg_context* c, void* dst, const void* src, size_t bytes, int ptr_kind) {
-  DMG_HIP(hipMemcpyAsync(dst, src, bytes, ptr_kind == DMG_PTR_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
-                         c->stream));
-  if (ptr_kind == DMG_PTR_HOST) DMG_HIP(hipStreamSynchronize(c->stream));
+  from_device(c->stream, dst, src, bytes, ptr_kind);
 }
 
 static bool all_finite(const double* p, size_t n) {
@@ -190,6 +200,13 @@ const char* dmg_last_error(const dmg_context* ctx) { return ctx ? ctx->err.c_str
 
 size_t dmg_context_bytes_in_use(const dmg_context* ctx) { return ctx ? ctx->in_use : 0; }
 
+dmg_status dmg_context_set_budget(dmg_context* ctx, size_t hbm_budget) {
+  if (!ctx) return DMG_E_INVALID;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->budget = hbm_budget;
+  return DMG_OK;
+}
+
 dmg_status dmg_gauge_create(dmg_context* ctx, int Nx, int Nt, const double* theta, int t_antiperiodic,
                             dmg_gauge** out) {
   if (!ctx || !out) return DMG_E_INVALID;
@@ -277,12 +294,7 @@ dmg_status dmg_setup(dmg_context* ctx, const dmg_gauge* g, double m0, const dmg_
       h->g = g;
       h->m0 = m0;
       h->prm = sp;
-      DMG_HIP(hipHostMalloc((void**)&h->host_status, 256, hipHostMallocDefault));
-      h->partials.alloc(ctx, sizeof(double2) * 80 * 1024);
-      h->counters.alloc(ctx, sizeof(unsigned) * 64);
-      h->flags.alloc(ctx, sizeof(int) * 64);
-      DMG_HIP(hipMemsetAsync(h->counters.p, 0, sizeof(unsigned) * 64, ctx->stream));
-      DMG_HIP(hipMemsetAsync(h->flags.p, 0, sizeof(int) * 64, ctx->stream));
+      h->main.init(ctx, ctx->stream, false);
       Op& f = h->op[0];
       f.kind = 0;
       f.Lx = g->Nx;
@@ -435,7 +447,7 @@ dmg_status dmg_deflation_build(dmg_deflation* d, const void* rhs, double tol, in
     x.alloc(h->ctx, sizeof(double2) * n);
     to_device(h->ctx, b.p, rhs, sizeof(double2) * n, ptr_kind);
     d->ready = 0;
-    coarse_gmres_dr(h, d, b.as<double2>(), x.as<double2>(), tol, 100000);
+    coarse_gmres_dr(h, &h->main, d, b.as<double2>(), x.as<double2>(), tol, 100000);
     DMG_HIP(hipStreamSynchronize(h->ctx->stream));
     return DMG_OK;
   });
@@ -479,9 +491,10 @@ dmg_status dmg_solve(dmg_context* ctx, dmg_hierarchy* h, dmg_deflation* d, const
               DMG_E_INVALID, "solve parameters");
     const int64_t n = h->op[0].n;
     const size_t fb = sizeof(double2) * n;
-    if (!h->ob.p) {
-      h->ob.alloc(ctx, fb);
-      h->ox.alloc(ctx, fb);
+    Work* w = &h->main;
+    if (!w->ob.p) {
+      w->ob.alloc(ctx, fb);
+      w->ox.alloc(ctx, fb);
     }
     dmg_status worst = DMG_OK;
     for (int i = 0; i < nrhs; ++i) {
@@ -489,10 +502,10 @@ dmg_status dmg_solve(dmg_context* ctx, dmg_hierarchy* h, dmg_deflation* d, const
       char* xi = (char*)x + fb * i;
       if (ptr_kind == DMG_PTR_HOST)
         DMG_CHECK(all_finite((const double*)bi, 2 * (size_t)n), DMG_E_NONFINITE, "non-finite right-hand side");
-      to_device(ctx, h->ob.p, bi, fb, ptr_kind);
-      if (p.use_x0) to_device(ctx, h->ox.p, xi, fb, ptr_kind);
-      dmg_status st = outer_solve(h, d, &p, h->ob.as<double2>(), h->ox.as<double2>(), stats ? stats + i : nullptr);
-      from_device(ctx, xi, h->ox.p, fb, ptr_kind);
+      to_device(ctx, w->ob.p, bi, fb, ptr_kind);
+      if (p.use_x0) to_device(ctx, w->ox.p, xi, fb, ptr_kind);
+      dmg_status st = outer_solve(h, w, d, &p, w->ob.as<double2>(), w->ox.as<double2>(), stats ? stats + i : nullptr);
+      from_device(ctx, xi, w->ox.p, fb, ptr_kind);
       if (st != DMG_OK) worst = st;
     }
     return worst;

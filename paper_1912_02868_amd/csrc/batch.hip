@@ -1,0 +1,291 @@
+// Continuous batching of independent solves: slots with their own stream, host
+// worker thread and solver workspace.  The solves of different slots overlap on the
+// device; each advances by whole outer FGMRES cycles, so its arithmetic is the same
+// alone or in a mix.
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <thread>
+
+#include "solver.h"
+
+using namespace dmg;
+
+struct dmg_batch {
+  struct Slot {
+    Work w;
+    int state = DMG_SLOT_FREE;
+    bool begun = false;
+    dmg_hierarchy* h = nullptr;
+    dmg_deflation* d = nullptr;
+    DevBuf b, x;
+    dmg_status status = DMG_OK;
+    std::string err;
+    dmg_solve_stats stats{};
+    bool go = false;    // an advance is requested
+    bool busy = false;  // an advance is in flight (the worker owns the slot)
+    int iters = 1;
+    std::chrono::steady_clock::time_point t_admit;
+    std::thread th;
+  };
+  dmg_context* ctx = nullptr;
+  int cap = 0;
+  dmg_solve_params p{};
+  std::vector<std::unique_ptr<Slot>> slots;
+  std::mutex mu;
+  std::condition_variable cv_go, cv_done;
+  long long completions = 0;  // advances finished
+  bool quit = false;
+
+  void worker(int i);
+  ~dmg_batch();
+};
+
+void dmg_batch::worker(int i) {
+  Slot& sl = *slots[i];
+  (void)hipSetDevice(ctx->device);
+  for (;;) {
+    int iters;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv_go.wait(lk, [&] { return quit || sl.go; });
+      if (quit) return;
+      sl.go = false;
+      iters = sl.iters;
+    }
+    bool done = false;
+    dmg_status status = DMG_OK;
+    std::string err;
+    try {
+      if (!sl.begun) {
+        outer_begin(sl.h, &sl.w, sl.d, &p, sl.b.as<double2>(), sl.x.as<double2>());
+        sl.w.run.t0 = sl.t_admit;
+        sl.begun = true;
+      }
+      if (outer_advance(&sl.w, iters)) {
+        status = outer_finish(&sl.w, &sl.stats);
+        done = true;
+      }
+    } catch (const Error& e) {
+      status = e.code;
+      err = e.msg;
+      done = true;
+      (void)hipStreamSynchronize(sl.w.stream);
+      (void)hipGetLastError();
+    } catch (const std::exception& e) {
+      status = DMG_E_INVALID;
+      err = e.what();
+      done = true;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if (done) {
+      sl.status = status;
+      sl.err = err;
+      sl.state = DMG_SLOT_DONE;
+    }
+    sl.busy = false;
+    ++completions;
+    cv_done.notify_all();
+  }
+}
+
+dmg_batch::~dmg_batch() {
+  {
+    std::unique_lock<std::mutex> lk(mu);
+    cv_done.wait(lk, [&] {
+      for (auto& s : slots)
+        if (s->busy) return false;
+      return true;
+    });
+    quit = true;
+  }
+  cv_go.notify_all();
+  for (auto& s : slots)
+    if (s->th.joinable()) s->th.join();
+  slots.clear();  // each Work waits for its stream before releasing memory
+}
+
+namespace {
+
+template <typename F>
+dmg_status guarded(dmg_context* c, F&& f) {
+  try {
+    if (c) c->err.clear();
+    return f();
+  } catch (const Error& e) {
+    if (c) c->err = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    if (c) c->err = "host allocation failed";
+    return DMG_E_NOMEM;
+  } catch (const std::exception& e) {
+    if (c) c->err = e.what();
+    return DMG_E_INVALID;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+dmg_status dmg_batch_create(dmg_context* ctx, int capacity, const dmg_solve_params* prm, dmg_batch** out) {
+  if (!ctx || !out) return DMG_E_INVALID;
+  *out = nullptr;
+  return guarded(ctx, [&]() -> dmg_status {
+    DMG_CHECK(capacity >= 1 && capacity <= DMG_BATCH_MAX_SLOTS, DMG_E_INVALID, "batch capacity outside [1, 8]");
+    dmg_solve_params p;
+    dmg_solve_params_default(&p);
+    if (prm) p = *prm;
+    DMG_CHECK(p.tol > 0.0 && p.int_tol > 0.0 && p.coarse_tol_first > 0.0 && p.coarse_tol_later > 0.0 &&
+                  p.max_outer_iters >= 1 && p.int_max_iters >= 1 && p.coarse_max_iters >= 1 &&
+                  p.outer_m >= 1 && p.outer_m <= MMAX && p.int_m >= 1 && p.int_m <= MMAX &&
+                  p.smooth_steps >= 1 && p.smooth_steps <= MMAX && !p.use_x0,
+              DMG_E_INVALID, "batch solve parameters (use_x0 is not supported)");
+    // Persistent coarse solves in a batch use cooperative launches, which the runtime
+    // places only when the whole grid fits: a plain-launched grid on one stream can
+    // wait behind the other slots' work for its last workgroups.
+    if (p.coarse_persistent == 2) p.coarse_persistent = 1;
+    std::unique_ptr<dmg_batch> bt(new dmg_batch());
+    bt->ctx = ctx;
+    bt->cap = capacity;
+    bt->p = p;
+    for (int i = 0; i < capacity; ++i) {
+      bt->slots.emplace_back(new dmg_batch::Slot());
+      hipStream_t s = nullptr;
+      DMG_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+      bt->slots.back()->w.init(ctx, s, true);
+    }
+    DMG_HIP(hipStreamSynchronize(ctx->stream));
+    for (auto& s : bt->slots) DMG_HIP(hipStreamSynchronize(s->w.stream));
+    for (int i = 0; i < capacity; ++i) {
+      dmg_batch* raw = bt.get();
+      bt->slots[i]->th = std::thread([raw, i] { raw->worker(i); });
+    }
+    *out = bt.release();
+    return DMG_OK;
+  });
+}
+
+dmg_status dmg_batch_admit(dmg_batch* bt, int slot, dmg_hierarchy* h, dmg_deflation* d, const void* b,
+                           int ptr_kind) {
+  if (!bt) return DMG_E_INVALID;
+  return guarded(bt->ctx, [&]() -> dmg_status {
+    DMG_CHECK(slot >= 0 && slot < bt->cap && h && b, DMG_E_INVALID, "batch_admit: bad arguments");
+    DMG_CHECK(ptr_kind == DMG_PTR_HOST || ptr_kind == DMG_PTR_DEVICE, DMG_E_INVALID, "batch_admit: pointer kind");
+    dmg_batch::Slot& sl = *bt->slots[slot];
+    {
+      std::lock_guard<std::mutex> lk(bt->mu);
+      DMG_CHECK(sl.state == DMG_SLOT_FREE, DMG_E_INVALID, "batch_admit: slot is busy");
+    }
+    DMG_CHECK(h->ctx == bt->ctx, DMG_E_INVALID, "batch_admit: hierarchy belongs to another context");
+    DMG_CHECK(!d || (d->h == h && d->ready), DMG_E_INVALID,
+              "batch_admit: the deflation space must belong to the hierarchy and be built");
+    const int64_t n = h->op[0].n;
+    const size_t fb = sizeof(double2) * n;
+    if (ptr_kind == DMG_PTR_HOST) {
+      const double* v = (const double*)b;
+      for (int64_t i = 0; i < 2 * n; ++i)
+        DMG_CHECK(std::isfinite(v[i]), DMG_E_NONFINITE, "non-finite right-hand side");
+    }
+    // workspace for h first: a budget failure leaves the slot FREE
+    prepare_work(h, &sl.w, d, &bt->p);
+    if (bt->p.precond == DMG_FP32) prepare_deflation_fp32(&sl.w, d);
+    if (sl.b.bytes != fb) {
+      DMG_HIP(hipStreamSynchronize(sl.w.stream));
+      sl.b.alloc(bt->ctx, fb);
+      sl.x.alloc(bt->ctx, fb);
+    }
+    hipStream_t s = sl.w.stream;
+    if (ptr_kind == DMG_PTR_HOST) {
+      DMG_HIP(hipMemcpyAsync(sl.b.p, b, fb, hipMemcpyHostToDevice, s));
+      DMG_HIP(hipStreamSynchronize(s));
+    } else {
+      // device input: order the copy after the caller's stream
+      hipEvent_t e;
+      DMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      DMG_HIP(hipEventRecord(e, bt->ctx->stream));
+      DMG_HIP(hipStreamWaitEvent(s, e, 0));
+      DMG_HIP(hipEventDestroy(e));
+      DMG_HIP(hipMemcpyAsync(sl.b.p, b, fb, hipMemcpyDeviceToDevice, s));
+    }
+    sl.h = h;
+    sl.d = d;
+    sl.t_admit = std::chrono::steady_clock::now();
+    sl.begun = false;
+    sl.status = DMG_OK;
+    sl.err.clear();
+    sl.stats = dmg_solve_stats{};
+    std::lock_guard<std::mutex> lk(bt->mu);
+    sl.state = DMG_SLOT_RUNNING;
+    return DMG_OK;
+  });
+}
+
+dmg_status dmg_batch_step(dmg_batch* bt, int min_iters, int* n_done) {
+  if (!bt) return DMG_E_INVALID;
+  return guarded(bt->ctx, [&]() -> dmg_status {
+    DMG_CHECK(min_iters >= 1, DMG_E_INVALID, "batch_step: min_iters must be >= 1");
+    std::unique_lock<std::mutex> lk(bt->mu);
+    const long long c0 = bt->completions;
+    int busy = 0;
+    for (auto& s : bt->slots) {
+      if (s->state == DMG_SLOT_RUNNING && !s->busy) {
+        s->busy = true;
+        s->go = true;
+        s->iters = min_iters;
+      }
+      busy += s->busy ? 1 : 0;
+    }
+    bt->cv_go.notify_all();
+    if (busy) bt->cv_done.wait(lk, [&] { return bt->completions != c0; });
+    if (n_done) {
+      int k = 0;
+      for (auto& s : bt->slots) k += s->state == DMG_SLOT_DONE ? 1 : 0;
+      *n_done = k;
+    }
+    return DMG_OK;
+  });
+}
+
+dmg_status dmg_batch_retire(dmg_batch* bt, int slot, void* x, int ptr_kind, dmg_solve_stats* stats) {
+  if (!bt) return DMG_E_INVALID;
+  dmg_context* c = bt->ctx;
+  dmg_status st = guarded(c, [&]() -> dmg_status {
+    DMG_CHECK(slot >= 0 && slot < bt->cap && x, DMG_E_INVALID, "batch_retire: bad arguments");
+    DMG_CHECK(ptr_kind == DMG_PTR_HOST || ptr_kind == DMG_PTR_DEVICE, DMG_E_INVALID, "batch_retire: pointer kind");
+    dmg_batch::Slot& sl = *bt->slots[slot];
+    {
+      std::lock_guard<std::mutex> lk(bt->mu);
+      DMG_CHECK(sl.state == DMG_SLOT_DONE && !sl.busy, DMG_E_INVALID, "batch_retire: slot has no finished solve");
+      sl.state = DMG_SLOT_FREE;
+    }
+    if (stats) *stats = sl.stats;
+    if (sl.status < 0) throw Error{sl.status, sl.err};
+    hipStream_t s = sl.w.stream;
+    const size_t fb = sl.x.bytes;
+    DMG_HIP(hipMemcpyAsync(x, sl.x.p, fb, ptr_kind == DMG_PTR_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                           s));
+    if (ptr_kind == DMG_PTR_HOST) {
+      DMG_HIP(hipStreamSynchronize(s));
+    } else {
+      // device output: make the caller's stream wait for the copy
+      hipEvent_t e;
+      DMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      DMG_HIP(hipEventRecord(e, s));
+      DMG_HIP(hipStreamWaitEvent(c->stream, e, 0));
+      DMG_HIP(hipEventDestroy(e));
+    }
+    return sl.status;
+  });
+  return st;
+}
+
+int dmg_batch_slot_state(dmg_batch* bt, int slot) {
+  if (!bt || slot < 0 || slot >= bt->cap) return -1;
+  std::lock_guard<std::mutex> lk(bt->mu);
+  return bt->slots[slot]->state;
+}
+
+void dmg_batch_destroy(dmg_batch* bt) { delete bt; }
+
+}  // extern "C"

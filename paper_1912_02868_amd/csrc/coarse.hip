@@ -1,7 +1,7 @@
 // Persistent coarse-grid GMRES-Proj(m, k) (Methods section: every coarse solve after
 // the first is a projection over the GMRES-DR space followed by GMRES cycles).
 //
-// One cooperative launch runs a whole coarse solve.  About 32 workgroups each own
+// One launch runs a whole coarse solve.  About 32 workgroups each own
 // `spw` consecutive coarse sites; a workgroup keeps its slices of the Krylov basis,
 // of the deflation basis and of x and r in LDS for the whole solve (and its 24 x 24
 // blocks too when they fit).  Neighbour values for the stencil travel through one
@@ -11,8 +11,11 @@
 // identical control decisions without further communication.
 //
 // The grid barrier is a flag array: each workgroup publishes its barrier
-// generation with one release store and its first wavefront polls all flags
-// (acquire loads, bounded spin).  Its cost grows slowly with the number of
+// generation with one store and its first wavefront polls all flags (bounded
+// spin).  The exchanged data itself is stored and loaded with device-scope atomic
+// accesses, and every wavefront waits for its stores before the workgroup barrier
+// that precedes the flag store, so the flags need no cache write-back or
+// invalidation.  Its cost grows slowly with the number of
 // workgroups, unlike a single atomic counter whose arrivals serialise; hence few,
 // larger workgroups.  An Arnoldi step costs two barriers: one to exchange v_j for
 // the stencil, one for the Gram-Schmidt reduction.  The orthogonalisation is
@@ -57,26 +60,76 @@ struct CPArgs {
 
 constexpr int CP_FLAGPAD = 32;  // one flag per 128-byte line
 
+// Data exchanged between workgroups inside one launch (the stencil exchange field and
+// the per-workgroup partial sums) is written and read with device-scope atomic
+// accesses, which go to the device's coherence point rather than a compute die's own
+// L2.  A wavefront then only has to wait for its own stores to complete before the
+// barrier; no cache write-back is needed.
+__device__ inline void cp_store(double2* p, double2 v) {
+  __hip_atomic_store(&p->x, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&p->y, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void cp_store(float2* p, float2 v) {
+  unsigned long long u;
+  __builtin_memcpy(&u, &v, sizeof(u));
+  __hip_atomic_store((unsigned long long*)p, u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline double2 cp_load(const double2* p) {
+  return mk(__hip_atomic_load(&p->x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+            __hip_atomic_load(&p->y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ inline float2 cp_load(const float2* p) {
+  const unsigned long long u =
+      __hip_atomic_load((const unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  float2 v;
+  __builtin_memcpy(&v, &u, sizeof(v));
+  return v;
+}
+// s_waitcnt vmcnt(0) (expcnt and lgkmcnt left at their maxima): this wavefront's
+// outstanding vector-memory operations have completed.
+__device__ inline void cp_wait_stores() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // Flag-array grid barrier (see the file comment).  `gen` counts this workgroup's
 // barriers; a wait longer than the spin limit sets *err and gives up, so no wave
 // can hang the device.
-__device__ inline void cp_barrier(unsigned* flags, int G, unsigned gen, int* err) {
+// Returns true when the grid must stop: some wait (here or in another workgroup) ran
+// past its spin limit.  After that every barrier returns at once, and the caller
+// leaves its loops, so the whole grid drains quickly.
+// Every wavefront waits for its own exchange stores before the workgroup barrier: a
+// wavefront's wait covers only its own outstanding stores, so the flag store of
+// wavefront 0 alone would not order the other wavefronts' stores before it.
+__device__ inline bool cp_barrier(unsigned* flags, int G, unsigned gen, int* err) {
+  __shared__ int aborted;
+  cp_wait_stores();
   __syncthreads();
-  if (threadIdx.x == 0)
-    __hip_atomic_store(&flags[blockIdx.x * CP_FLAGPAD], gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-  if (threadIdx.x < 64) {
-    for (int b = threadIdx.x; b < G; b += 64) {
+  if (threadIdx.x == 0) {
+    aborted = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // relaxed: every datum the flag publishes was stored with a device-scope atomic
+    // that completed before the workgroup barrier above
+    __hip_atomic_store(&flags[blockIdx.x * CP_FLAGPAD], gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  if (threadIdx.x < 64 && !aborted) {
+    bool timed_out = false;
+    for (int b = threadIdx.x; b < G && !timed_out; b += 64) {
       long spins = 0;
-      while (__hip_atomic_load(&flags[b * CP_FLAGPAD], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < gen) {
+      // relaxed: the published data is read with device-scope atomics after this wait,
+      // so no cache invalidation is needed (it would also evict the operator's blocks)
+      while (__hip_atomic_load(&flags[b * CP_FLAGPAD], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
         __builtin_amdgcn_s_sleep(1);
-        if (++spins > (1L << 24)) {
-          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (++spins > (1L << 22)) {
+          timed_out = true;
           break;
         }
       }
     }
+    if (timed_out) {
+      __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      aborted = 1;
+    }
   }
   __syncthreads();
+  return aborted != 0;
 }
 
 __host__ __device__ inline size_t cp_align(size_t v) { return (v + 15) & ~(size_t)15; }
@@ -140,6 +193,7 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
   using T = cx<R>;
   extern __shared__ __align__(16) unsigned char smem[];
   unsigned gen = 0;
+  bool dead = false;  // a barrier wait timed out: stop everything
   const int G = gridDim.x, gi = blockIdx.x, tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int V = a.Lx * a.Lt;
@@ -201,14 +255,14 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
   auto grid_reduce = [&](int nq) {
     __syncthreads();
     double2* P = a.partials + (size_t)rbuf * CP_QMAX * G;
-    if (tid < nq) P[(size_t)tid * G + gi] = red[tid][0];
-    cp_barrier(a.flags, G, ++gen, a.err);
+    if (tid < nq) cp_store(&P[(size_t)tid * G + gi], red[tid][0]);
+    dead = dead || cp_barrier(a.flags, G, ++gen, a.err);
     const int q = tid / CP_CHUNKS, c = tid % CP_CHUNKS;
     if (q < nq) {
       const int per = (G + CP_CHUNKS - 1) / CP_CHUNKS;
       const int lo = c * per, hi = min(G, lo + per);
       double2 sm = mk(0.0, 0.0);
-      for (int b = lo; b < hi; ++b) sm = cadd(sm, P[(size_t)q * G + b]);
+      for (int b = lo; b < hi; ++b) sm = cadd(sm, cp_load(&P[(size_t)q * G + b]));
       csum[q][c] = sm;
     }
     __syncthreads();
@@ -247,7 +301,7 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
   bool converged = bnorm == 0.0;
   double est = bnorm;
 
-  while (!converged && iters < a.max_iters) {
+  while (!converged && !dead && iters < a.max_iters) {
     // ------------------------------------------------------------ projection over V_{k+1}
     wg_sums(k + 1, [&](int q, int e) {
       double2 v = mk(0.0, 0.0);
@@ -273,7 +327,7 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
       for (int i = 0; i <= k; ++i) rv = csub(rv, cmul(uv[i], to_d(DVb[i * ne + t])));
       xl[t] = from_d<R>(xv);
       rl[t] = from_d<R>(rv);
-      xch[e0 + t] = from_d<R>(rv);
+      cp_store(&xch[e0 + t], from_d<R>(rv));
     }
     // ------------------------------------------------------------ GMRES(mm) cycle from r
     __syncthreads();
@@ -281,6 +335,7 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
     grid_reduce(1);
     double hprev = sqrt(res[0].x);  // beta; xchg holds the unnormalised start vector
     est = hprev;
+    if (dead) break;
     if (hprev <= tol_abs || hprev == 0.0) {
       converged = true;
       break;
@@ -311,7 +366,7 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
           case 3: nb = X + a.Lx * ((Tt + 1 == a.Lt) ? 0 : Tt + 1); break;
           default: nb = X + a.Lx * ((Tt == 0) ? a.Lt - 1 : Tt - 1); break;
         }
-        xs[t] = xch[(int64_t)nb * NC + jj];
+        xs[t] = cp_load(&xch[(int64_t)nb * NC + jj]);
       }
       __syncthreads();
       for (int t = tid; t < nsl * 5 * NC; t += CP_THREADS) {
@@ -406,14 +461,14 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
           for (int i = 0; i <= j; ++i) w = csub(w, cmul(res[i], to_d(Vb[i * ne + t])));
         const T ws = from_d<R>(w);
         wl[t] = ws;
-        if (j + 1 < mm) xch[e0 + t] = ws;  // hn * v_{j+1} for the next stencil
+        if (j + 1 < mm) cp_store(&xch[e0 + t], ws);  // hn * v_{j+1} for the next stencil
       }
-      if (j + 1 < mm) cp_barrier(a.flags, G, ++gen, a.err);
+      if (j + 1 < mm) dead = dead || cp_barrier(a.flags, G, ++gen, a.err);
       else __syncthreads();
       est = brk ? 0.0 : sh_scal[0];
       steps = j + 1;
       hprev = hn;
-      if (brk || est <= tol_abs || iters + steps >= a.max_iters) { stop = true; break; }
+      if (dead || brk || est <= tol_abs || iters + steps >= a.max_iters) { stop = true; break; }
     }
     // ------------------------------------------------------------ end of cycle: x += V y, r = V u
     if (tid == 0) {
@@ -472,7 +527,7 @@ static bool cp_debug() {
 }
 
 template <typename R>
-static int try_launch(hipStream_t st, CPArgs& a, int G, size_t lds, bool alds) {
+static int try_launch(hipStream_t st, CPArgs& a, int G, size_t lds, bool alds, int coop) {
   void* args[] = {&a};
   const void* fn = alds ? (const void*)k_coarse_proj<R, true> : (const void*)k_coarse_proj<R, false>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -501,9 +556,18 @@ static int try_launch(hipStream_t st, CPArgs& a, int G, size_t lds, bool alds) {
     (void)hipGetLastError();
     return 0;
   }
-  e = hipLaunchCooperativeKernel(fn, dim3(G), dim3(CP_THREADS), args, (unsigned)lds, st);
+  if (coop) {
+    e = hipLaunchCooperativeKernel(fn, dim3(G), dim3(CP_THREADS), args, (unsigned)lds, st);
+  } else {
+    // Plain launch: the grid (G <= 256 workgroups, one per CU) always fits the device,
+    // so every workgroup is placed once earlier kernels drain; the barrier's spin limit
+    // bounds any wait.
+    if (alds) hipLaunchKernelGGL((k_coarse_proj<R, true>), dim3(G), dim3(CP_THREADS), lds, st, a);
+    else hipLaunchKernelGGL((k_coarse_proj<R, false>), dim3(G), dim3(CP_THREADS), lds, st, a);
+    e = hipGetLastError();
+  }
   if (e != hipSuccess) {
-    if (cp_debug()) fprintf(stderr, "[dmg] coarse kernel: cooperative launch failed: %s\n", hipGetErrorString(e));
+    if (cp_debug()) fprintf(stderr, "[dmg] coarse kernel: launch failed: %s\n", hipGetErrorString(e));
     (void)hipGetLastError();
     return 0;
   }
@@ -520,7 +584,7 @@ int launch_coarse_proj(hipStream_t st, const cx<R>* A, int Lx, int Lt, const cx<
                        const double2* DP, int k,
                        const cx<R>* b, cx<R>* x, double tol, int mm, int max_iters, cx<R>* xchg,
                        double2* partials, size_t partials_elems, int* out_iters, double* out_relres,
-                       unsigned* flags, size_t flag_words, int* err, int groups) {
+                       unsigned* flags, size_t flag_words, int* err, int groups, int coop) {
   if (mm + 2 > CP_QMAX || k + 1 > CP_QMAX || mm < 1) return 0;
   const int V = Lx * Lt;
   const size_t lds_max = 160 * 1024;
@@ -538,7 +602,7 @@ int launch_coarse_proj(hipStream_t st, const cx<R>* A, int Lx, int Lt, const cx<
     }
     CPArgs a{A, Lx, Lt, DV, DM, DP, k, b, x, tol, mm, max_iters, xchg, partials, out_iters, out_relres,
              flags, err, spw, alds};
-    if (try_launch<R>(st, a, G, lds, alds == 1)) return 1;
+    if (try_launch<R>(st, a, G, lds, alds == 1, coop)) return 1;
   }
   return 0;
 }
@@ -546,10 +610,10 @@ int launch_coarse_proj(hipStream_t st, const cx<R>* A, int Lx, int Lt, const cx<
 template int launch_coarse_proj<double>(hipStream_t, const double2*, int, int, const double2*, const double2*,
                                         const double2*, int,
                                         const double2*, double2*, double, int, int, double2*, double2*, size_t,
-                                        int*, double*, unsigned*, size_t, int*, int);
+                                        int*, double*, unsigned*, size_t, int*, int, int);
 template int launch_coarse_proj<float>(hipStream_t, const float2*, int, int, const float2*, const double2*,
                                        const double2*, int,
                                        const float2*, float2*, double, int, int, float2*, double2*, size_t, int*,
-                                       double*, unsigned*, size_t, int*, int);
+                                       double*, unsigned*, size_t, int*, int, int);
 
 }  // namespace dmg

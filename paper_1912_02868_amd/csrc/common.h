@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -109,6 +110,7 @@ struct dmg_context {
   dmg_allocator alloc{nullptr, nullptr, nullptr};
   size_t budget = 0;
   size_t in_use = 0;
+  std::mutex mu;  // allocation accounting and the kernel timer (batch slots run on host threads)
   std::string err;
   // kernel timer (dmg_kernel_timer): event pairs per timed kernel, work units per launch
   int timing = 0;  // bit mask of timed kernels
@@ -121,8 +123,8 @@ struct dmg_context {
 };
 
 namespace dmg {
-// Records an event on the context's stream when kernel `kernel` is timed (nullptr otherwise).
-hipEvent_t timer_mark(dmg_context* c, int kernel);
+// Records an event on `stream` when kernel `kernel` is timed (nullptr otherwise).
+hipEvent_t timer_mark(dmg_context* c, int kernel, hipStream_t stream);
 void timer_span(dmg_context* c, int kernel, hipEvent_t a, hipEvent_t b, long long units);
 }  // namespace dmg
 

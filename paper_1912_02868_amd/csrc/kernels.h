@@ -108,12 +108,13 @@ void launch_proj_solve(hipStream_t s, const double2* Hk, int k, KState* ks);
 // launched) when the grid cannot be co-resident; out_iters / out_relres receive the Arnoldi
 // steps taken and the final recurrence residual relative to ||b||.  flags: barrier words
 // (coarse_proj_flag_words(G) needed, zeroed by the launcher); err: set on a barrier timeout.
+// coop = 1: cooperative launch; 0: plain launch (the grid fits the device by construction).
 template <typename R>
 int launch_coarse_proj(hipStream_t st, const cx<R>* A, int Lx, int Lt, const cx<R>* DV, const double2* DM,
                        const double2* DP, int k,
                        const cx<R>* b, cx<R>* x, double tol, int mm, int max_iters, cx<R>* xchg,
                        double2* partials, size_t partials_elems, int* out_iters, double* out_relres,
-                       unsigned* flags, size_t flag_words, int* err, int groups);
+                       unsigned* flags, size_t flag_words, int* err, int groups, int coop);
 size_t coarse_proj_flag_words(int G);
 
 // Projection matrices of a deflation space: M = Hbar_k^+ (k x (k+1)) and Pi = Hbar_k M

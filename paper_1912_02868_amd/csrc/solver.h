@@ -2,6 +2,7 @@
 // orchestration of the device kernels).
 #pragma once
 
+#include <chrono>
 #include <memory>
 
 #include "kernels.h"
@@ -37,10 +38,10 @@ struct Op {
   int timer_id = -1;            // DMG_KT_* of this operator's stencil, or -1
   void apply(hipStream_t s, const double2* in, double2* out, int dag, const int* skip,
              const double2* sub = nullptr) const {
-    hipEvent_t ta = (timer_id >= 0 && ctx) ? timer_mark(ctx, timer_id) : nullptr;
+    hipEvent_t ta = (timer_id >= 0 && ctx) ? timer_mark(ctx, timer_id, s) : nullptr;
     if (kind == 0) launch_wilson<double>(s, U64, in, out, m0, Lx, Lt, dag, 1, skip, sub);
     else launch_block_apply<double>(s, A64, in, out, Lx, Lt, dag, skip, sub);
-    if (ta) timer_span(ctx, timer_id, ta, timer_mark(ctx, timer_id), (long long)Lx * Lt);
+    if (ta) timer_span(ctx, timer_id, ta, timer_mark(ctx, timer_id, s), (long long)Lx * Lt);
   }
   void apply(hipStream_t s, const float2* in, float2* out, int dag, const int* skip,
              const float2* sub = nullptr) const {
@@ -79,6 +80,43 @@ struct Counters {
 
 template <typename R> struct Precond;
 
+// Mutable state of one solve in flight: its stream, reduction scratch, status mirror,
+// Mvp counters and every Krylov workspace.  A hierarchy owns one (for dmg_solve and
+// the setup); each slot of a batch owns another, so solves on different streams share
+// only the read-only operators and the frozen deflation space.
+struct Work {
+  dmg_context* ctx = nullptr;  // allocator, budget, error text
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  DevBuf partials, counters, flags;
+  KStatus* host_status = nullptr;  // pinned
+  Counters cnt;
+  // outer FGMRES (FP64)
+  KWS outer;
+  DevBuf ob, ox, or_, oz32, ov32, bn2;
+  std::unique_ptr<Precond<double>> pc64;
+  std::unique_ptr<Precond<float>> pc32;
+  // GMRES-DR (FP64)
+  KWS dr;
+  DevBuf dr_Vtmp, dr_P, dr_work, dr_coef;
+  int dr_m = 0, dr_k = 0;
+  // state of a resumable outer solve (one right-hand side)
+  struct Run {
+    dmg_hierarchy* h = nullptr;
+    dmg_deflation* d = nullptr;
+    dmg_solve_params p{};
+    const double2* b = nullptr;
+    double2* x = nullptr;
+    double bnorm = 0.0, rel = 0.0;
+    int iters = 0;
+    bool conv = false, done = false;
+    std::chrono::steady_clock::time_point t0;
+  } run;
+  void init(dmg_context* c, hipStream_t s, bool owns);
+  Work();
+  ~Work();
+};
+
 }  // namespace dmg
 
 struct dmg_deflation {
@@ -100,33 +138,34 @@ struct dmg_hierarchy {
   dmg::Transfer tr[2];
   dmg::DevBuf A64[3], A32[3], P64[2], P32[2], null[2];
   int setup_iters[2][64] = {};
-  // reduction scratch, small device flags, host mirror
-  dmg::DevBuf partials, counters, flags;
-  dmg::KStatus* host_status = nullptr;  // pinned
-  // GMRES-DR workspace (FP64)
-  dmg::KWS dr;
-  dmg::DevBuf dr_Vtmp, dr_P, dr_work, dr_coef;
-  int dr_m = 0, dr_k = 0;
-  // outer FGMRES (FP64)
-  dmg::KWS outer;
-  dmg::DevBuf ob, ox, or_, oz32, ov32, bn2;
-  std::unique_ptr<dmg::Precond<double>> pc64;
-  std::unique_ptr<dmg::Precond<float>> pc32;
-  dmg::Counters cnt;
+  dmg::Work main;  // workspace of dmg_solve, the setup and the deflation build (context stream)
   dmg_hierarchy();
   ~dmg_hierarchy();
 };
 
 namespace dmg {
 
-// setup (near-null vectors, prolongators, Galerkin operators)
+// setup (near-null vectors, prolongators, Galerkin operators), on h->main
 void build_hierarchy(dmg_hierarchy* h, const double2* start0, const double2* start1, int inject);
 // GMRES-DR on the coarse operator in FP64 from x = 0; fills the deflation space.
 // Returns the Arnoldi steps taken.
-int coarse_gmres_dr(dmg_hierarchy* h, dmg_deflation* d, const double2* b, double2* x, double tol, int max_iters);
-// outer solve of one right-hand side (device buffers b, x; x holds x0 when use_x0)
-dmg_status outer_solve(dmg_hierarchy* h, dmg_deflation* d, const dmg_solve_params* p, const double2* b, double2* x,
-                       dmg_solve_stats* st);
-void sync_status(dmg_hierarchy* h, const KState* ks, KStatus* out);
+int coarse_gmres_dr(dmg_hierarchy* h, Work* w, dmg_deflation* d, const double2* b, double2* x, double tol,
+                    int max_iters);
+// outer solve of one right-hand side (device buffers b, x; x holds x0 when use_x0) on workspace w
+dmg_status outer_solve(dmg_hierarchy* h, Work* w, dmg_deflation* d, const dmg_solve_params* p, const double2* b,
+                       double2* x, dmg_solve_stats* st);
+// The same solve in three parts: begin (initial residual), advance by whole FGMRES cycles
+// until at least `min_iters` more outer iterations ran or the solve ended (returns true
+// once it ended), finish (statistics).  The arithmetic does not depend on how the
+// advance calls split the cycles.
+void outer_begin(dmg_hierarchy* h, Work* w, dmg_deflation* d, const dmg_solve_params* p, const double2* b,
+                 double2* x);
+bool outer_advance(Work* w, int min_iters);
+dmg_status outer_finish(Work* w, dmg_solve_stats* st);
+// allocate every buffer a solve of h with these parameters touches on workspace w
+void prepare_work(dmg_hierarchy* h, Work* w, dmg_deflation* d, const dmg_solve_params* p);
+// FP32 copy of a ready deflation space (made once, on w's stream, which is synchronised)
+void prepare_deflation_fp32(Work* w, dmg_deflation* d);
+void sync_status(Work* w, const KState* ks, KStatus* out);
 
 }  // namespace dmg

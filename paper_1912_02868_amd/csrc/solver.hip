@@ -10,6 +10,8 @@
 #include <cmath>
 #include <cstring>
 
+#include <limits>
+
 #include "solver.h"
 
 namespace dmg {
@@ -39,95 +41,118 @@ void KWS::alloc(dmg_context* c, int m_, int64_t n_, size_t esize, bool flexible)
   DMG_HIP(hipMemsetAsync(ks.p, 0, sizeof(KState), c->stream));
 }
 
-void sync_status(dmg_hierarchy* h, const KState* ks, KStatus* out) {
-  hipStream_t s = h->ctx->stream;
-  DMG_HIP(hipMemcpyAsync(h->host_status, &ks->nrot, sizeof(KStatus), hipMemcpyDeviceToHost, s));
+void sync_status(Work* w, const KState* ks, KStatus* out) {
+  hipStream_t s = w->stream;
+  DMG_HIP(hipMemcpyAsync(w->host_status, &ks->nrot, sizeof(KStatus), hipMemcpyDeviceToHost, s));
   DMG_HIP(hipStreamSynchronize(s));
-  *out = *h->host_status;
+  *out = *w->host_status;
 }
 
-static double read_double(dmg_hierarchy* h, const double* p) {
-  hipStream_t s = h->ctx->stream;
-  DMG_HIP(hipMemcpyAsync(h->host_status, p, sizeof(double), hipMemcpyDeviceToHost, s));
+static double read_double(Work* w, const double* p) {
+  hipStream_t s = w->stream;
+  DMG_HIP(hipMemcpyAsync(w->host_status, p, sizeof(double), hipMemcpyDeviceToHost, s));
   DMG_HIP(hipStreamSynchronize(s));
   double v;
-  std::memcpy(&v, h->host_status, sizeof(double));
+  std::memcpy(&v, w->host_status, sizeof(double));
   return v;
 }
 
-static double2* PART(dmg_hierarchy* h) { return h->partials.as<double2>(); }
-static unsigned* CNT(dmg_hierarchy* h) { return h->counters.as<unsigned>(); }
+static double2* PART(Work* w) { return w->partials.as<double2>(); }
+static unsigned* CNT(Work* w) { return w->counters.as<unsigned>(); }
 
-// ---------------------------------------------------------------- coarse GMRES-DR (FP64)
-static void ensure_dr(dmg_hierarchy* h, int m, int k) {
-  if (h->dr_m == m && h->dr_k == k && h->dr.V.p) return;
-  const int64_t n = h->op[2].n;
-  h->dr.alloc(h->ctx, m, n, sizeof(double2), false);
-  h->dr_Vtmp.alloc(h->ctx, sizeof(double2) * (size_t)n * (k + 1));
-  h->dr_P.alloc(h->ctx, sizeof(double2) * (size_t)(m + 1) * (k + 1));
-  h->dr_work.alloc(h->ctx, sizeof(double2) * dr_work_elems(m, k));
-  h->dr_coef.alloc(h->ctx, sizeof(double2) * (MMAX + 2));
-  h->dr_m = m;
-  h->dr_k = k;
+Work::Work() = default;
+
+void Work::init(dmg_context* c, hipStream_t s, bool owns) {
+  ctx = c;
+  stream = s;
+  own_stream = owns;
+  DMG_HIP(hipHostMalloc((void**)&host_status, 256, hipHostMallocDefault));
+  partials.alloc(c, sizeof(double2) * 80 * 1024);
+  counters.alloc(c, sizeof(unsigned) * 64);
+  flags.alloc(c, sizeof(int) * 64);
+  DMG_HIP(hipMemsetAsync(counters.p, 0, sizeof(unsigned) * 64, s));
+  DMG_HIP(hipMemsetAsync(flags.p, 0, sizeof(int) * 64, s));
 }
 
-static void check_dr_status(dmg_hierarchy* h) {
+Work::~Work() {
+  if (stream) (void)hipStreamSynchronize(stream);
+  pc64.reset();
+  pc32.reset();
+  if (host_status) (void)hipHostFree(host_status);
+  if (own_stream && stream) (void)hipStreamDestroy(stream);
+}
+
+// ---------------------------------------------------------------- coarse GMRES-DR (FP64)
+static void ensure_dr(dmg_hierarchy* h, Work* w, int m, int k) {
+  if (w->dr_m == m && w->dr_k == k && w->dr.V.p) return;
+  const int64_t n = h->op[2].n;
+  w->dr.alloc(w->ctx, m, n, sizeof(double2), false);
+  w->dr_Vtmp.alloc(w->ctx, sizeof(double2) * (size_t)n * (k + 1));
+  w->dr_P.alloc(w->ctx, sizeof(double2) * (size_t)(m + 1) * (k + 1));
+  w->dr_work.alloc(w->ctx, sizeof(double2) * dr_work_elems(m, k));
+  w->dr_coef.alloc(w->ctx, sizeof(double2) * (MMAX + 2));
+  w->dr_m = m;
+  w->dr_k = k;
+}
+
+static void check_dr_status(Work* w) {
   int st = 0;
-  DMG_HIP(hipMemcpyAsync(&st, h->flags.as<int>(), sizeof(int), hipMemcpyDeviceToHost, h->ctx->stream));
-  DMG_HIP(hipStreamSynchronize(h->ctx->stream));
+  DMG_HIP(hipMemcpyAsync(&st, w->flags.as<int>(), sizeof(int), hipMemcpyDeviceToHost, w->stream));
+  DMG_HIP(hipStreamSynchronize(w->stream));
   DMG_CHECK(st == 0, DMG_E_BREAKDOWN, "GMRES-DR restart failed (singular Hessenberg or eigenvalue iteration)");
 }
 
-int coarse_gmres_dr(dmg_hierarchy* h, dmg_deflation* d, const double2* b, double2* x, double tol, int max_iters) {
+int coarse_gmres_dr(dmg_hierarchy* h, Work* w, dmg_deflation* d, const double2* b, double2* x, double tol,
+                    int max_iters) {
   const int m = d->m, k = d->k;
   DMG_CHECK(m <= MMAX && k >= 1 && k < m, DMG_E_INVALID, "GMRES-DR sizes");
-  ensure_dr(h, m, k);
-  hipStream_t s = h->ctx->stream;
+  ensure_dr(h, w, m, k);
+  hipStream_t s = w->stream;
   const Op& A = h->op[2];
   const int64_t n = A.n;
-  KState* ks = h->dr.state();
-  double2* V = h->dr.V.as<double2>();
-  int* status = h->flags.as<int>();
+  KState* ks = w->dr.state();
+  double2* V = w->dr.V.as<double2>();
+  int* status = w->flags.as<int>();
   DMG_HIP(hipMemsetAsync(status, 0, sizeof(int), s));
   DMG_HIP(hipMemsetAsync(x, 0, sizeof(double2) * n, s));
-  launch_cycle_start<double>(s, b, V, n, ks, tol, 1, PART(h), CNT(h));
+  launch_cycle_start<double>(s, b, V, n, ks, tol, 1, PART(w), CNT(w));
   int j0 = 0, iters = 0;
   KStatus st{};
   for (;;) {
     for (int j = j0; j < m; ++j) {
       A.apply(s, V + (int64_t)j * n, V + (int64_t)(j + 1) * n, 0, &ks->done);
-      launch_arnoldi_orth<double>(s, V, n, n, j, ks, PART(h), CNT(h));
+      launch_arnoldi_orth<double>(s, V, n, n, j, ks, PART(w), CNT(w));
     }
     launch_ls_solve(s, ks);
     launch_combine<double, double>(s, x, V, n, n, ks, 0, 1);
-    sync_status(h, ks, &st);
+    sync_status(w, ks, &st);
     iters += st.steps - j0;
-    h->cnt.mv[2] += st.steps - j0;
+    w->cnt.mv[2] += st.steps - j0;
     if (st.done || iters >= max_iters) break;
     // deflated restart: keep the k smallest harmonic Ritz vectors and the residual
-    launch_dr_restart(s, ks, m, k, h->dr_P.as<double2>(), 0, h->dr_work.as<double2>(), status);
-    launch_basis_rotate<double>(s, V, h->dr_Vtmp.as<double2>(), n, n, h->dr_P.as<double2>(), m + 1, m + 1, k + 1);
-    DMG_HIP(hipMemcpyAsync(V, h->dr_Vtmp.p, sizeof(double2) * n * (k + 1), hipMemcpyDeviceToDevice, s));
+    launch_dr_restart(s, ks, m, k, w->dr_P.as<double2>(), 0, w->dr_work.as<double2>(), status);
+    launch_basis_rotate<double>(s, V, w->dr_Vtmp.as<double2>(), n, n, w->dr_P.as<double2>(), m + 1, m + 1, k + 1);
+    DMG_HIP(hipMemcpyAsync(V, w->dr_Vtmp.p, sizeof(double2) * n * (k + 1), hipMemcpyDeviceToDevice, s));
     // re-orthogonalise v_{k+1} against v_1 .. v_k
-    double2* coef = h->dr_coef.as<double2>();
-    launch_multidot<double>(s, V, n, k, V + (int64_t)k * n, n, coef, PART(h), CNT(h));
+    double2* coef = w->dr_coef.as<double2>();
+    launch_multidot<double>(s, V, n, k, V + (int64_t)k * n, n, coef, PART(w), CNT(w));
     launch_multi_axpy<double>(s, V + (int64_t)k * n, V, n, k, coef, n, 1.0);
-    launch_norm2<double>(s, n, V + (int64_t)k * n, (double*)(coef + MMAX), PART(h), CNT(h));
+    launch_norm2<double>(s, n, V + (int64_t)k * n, (double*)(coef + MMAX), PART(w), CNT(w));
     launch_scale_dev<double>(s, n, V + (int64_t)k * n, V + (int64_t)k * n, (const double*)(coef + MMAX), 1);
     j0 = k;
   }
-  check_dr_status(h);
+  check_dr_status(w);
   // store the deflation space A V_k = V_{k+1} Hbar_k
   const int cols = st.steps;
   if (cols > k && !st.breakdown) {
-    launch_dr_restart(s, ks, cols, k, h->dr_P.as<double2>(), 1, h->dr_work.as<double2>(), status);
+    launch_dr_restart(s, ks, cols, k, w->dr_P.as<double2>(), 1, w->dr_work.as<double2>(), status);
     d->V64.alloc(h->ctx, sizeof(double2) * (size_t)n * (k + 1));
     d->H.alloc(h->ctx, sizeof(double2) * (size_t)(k + 1) * k);
-    launch_basis_rotate<double>(s, V, d->V64.as<double2>(), n, n, h->dr_P.as<double2>(), cols + 1, cols + 1, k + 1);
+    launch_basis_rotate<double>(s, V, d->V64.as<double2>(), n, n, w->dr_P.as<double2>(), cols + 1, cols + 1, k + 1);
     DMG_HIP(hipMemcpy2DAsync(d->H.p, sizeof(double2) * (k + 1), ks->H, sizeof(double2) * (MMAX + 1),
                              sizeof(double2) * (k + 1), k, hipMemcpyDeviceToDevice, s));
     d->kk = k;
-    check_dr_status(h);
+    check_dr_status(w);
   } else {
     const int kk = std::max(cols, 1);
     d->V64.alloc(h->ctx, sizeof(double2) * (size_t)n * (kk + 1));
@@ -142,15 +167,15 @@ int coarse_gmres_dr(dmg_hierarchy* h, dmg_deflation* d, const double2* b, double
   launch_defl_prepare(s, d->H.as<double2>(), d->kk, d->M.as<double2>(), d->Pi.as<double2>());
   d->ready = 1;
   d->cast_ready = 0;
-  h->cnt.dr_calls++;
+  w->cnt.dr_calls++;
   return iters;
 }
 
 // ---------------------------------------------------------------- batched CG on A A^dagger (FP64)
 // x_f = argmin for A A^dagger x_f = b_f, f < nvec, each stopping at ||r_f|| <= tol ||b_f||.
-static void cg_normal(dmg_hierarchy* h, int lvl, int nvec, const double2* b, double2* x, double tol, int max_iters,
+static void cg_normal(dmg_hierarchy* h, Work* w, int lvl, int nvec, const double2* b, double2* x, double tol, int max_iters,
                       int* iters_host) {
-  hipStream_t s = h->ctx->stream;
+  hipStream_t s = w->stream;
   const Op& A = h->op[lvl];
   const int64_t n = A.n;
   const size_t fb = sizeof(double2) * (size_t)n * nvec;
@@ -180,12 +205,12 @@ static void cg_normal(dmg_hierarchy* h, int lvl, int nvec, const double2* b, dou
         launch_block_apply<double>(s, A.A64, t.as<double2>() + f * n, out + f * n, A.Lx, A.Lt, 0);
       }
     }
-    h->cnt.mv[lvl] += 2 * nvec;
+    w->cnt.mv[lvl] += 2 * nvec;
   };
   DMG_HIP(hipMemsetAsync(x, 0, fb, s));
   DMG_HIP(hipMemcpyAsync(r.p, b, fb, hipMemcpyDeviceToDevice, s));
   DMG_HIP(hipMemcpyAsync(p.p, b, fb, hipMemcpyDeviceToDevice, s));
-  launch_batched_dots(s, n, nvec, b, b, rrn, PART(h), CNT(h));
+  launch_batched_dots(s, n, nvec, b, b, rrn, PART(w), CNT(w));
   // rr = b2 = ||b||^2, all active
   std::vector<int> ones(nvec, 1), zeros(nvec, 0);
   DMG_HIP(hipMemcpyAsync(active, ones.data(), sizeof(int) * nvec, hipMemcpyHostToDevice, s));
@@ -197,10 +222,10 @@ static void cg_normal(dmg_hierarchy* h, int lvl, int nvec, const double2* b, dou
   std::vector<int> act(nvec);
   for (int it = 1; it <= max_iters; ++it) {
     normal(p.as<double2>(), q.as<double2>());
-    launch_batched_dots(s, n, nvec, p.as<double2>(), q.as<double2>(), pq, PART(h), CNT(h));
+    launch_batched_dots(s, n, nvec, p.as<double2>(), q.as<double2>(), pq, PART(w), CNT(w));
     launch_cg_scalars(s, nvec, pq, rrn, rr, alpha, beta, active, b2, tol * tol, its, 0);
     launch_cg_update<double>(s, n, nvec, x, r.as<double2>(), p.as<double2>(), q.as<double2>(), alpha, beta, active, 0);
-    launch_batched_dots(s, n, nvec, r.as<double2>(), r.as<double2>(), rrn, PART(h), CNT(h));
+    launch_batched_dots(s, n, nvec, r.as<double2>(), r.as<double2>(), rrn, PART(w), CNT(w));
     launch_cg_scalars(s, nvec, pq, rrn, rr, alpha, beta, active, b2, tol * tol, its, 1);
     launch_cg_update<double>(s, n, nvec, x, r.as<double2>(), p.as<double2>(), q.as<double2>(), alpha, beta, active, 1);
     if (it % 4 == 0 || it == max_iters) {
@@ -211,16 +236,15 @@ static void cg_normal(dmg_hierarchy* h, int lvl, int nvec, const double2* b, dou
       if (!any) break;
     }
   }
-  if (iters_host) {
-    DMG_HIP(hipMemcpyAsync(iters_host, its, sizeof(int) * nvec, hipMemcpyDeviceToHost, s));
-    DMG_HIP(hipStreamSynchronize(s));
-  }
+  if (iters_host) DMG_HIP(hipMemcpyAsync(iters_host, its, sizeof(int) * nvec, hipMemcpyDeviceToHost, s));
+  // the work fields are freed on return: let the stream drain first
+  DMG_HIP(hipStreamSynchronize(s));
 }
 
 // ---------------------------------------------------------------- setup
 // Global orthonormalisation: modified Gram-Schmidt over the whole lattice, two passes.
-static void global_mgs2(dmg_hierarchy* h, double2* W, int64_t n, int nvec) {
-  hipStream_t s = h->ctx->stream;
+static void global_mgs2(dmg_hierarchy* h, Work* w, double2* W, int64_t n, int nvec) {
+  hipStream_t s = w->stream;
   DevBuf coef;
   coef.alloc(h->ctx, sizeof(double2) * 4);
   double2* c = coef.as<double2>();
@@ -228,16 +252,17 @@ static void global_mgs2(dmg_hierarchy* h, double2* W, int64_t n, int nvec) {
     double2* wk = W + (int64_t)k * n;
     for (int pass = 0; pass < 2; ++pass)
       for (int j = 0; j < k; ++j) {
-        launch_multidot<double>(s, W + (int64_t)j * n, n, 1, wk, n, c, PART(h), CNT(h));
+        launch_multidot<double>(s, W + (int64_t)j * n, n, 1, wk, n, c, PART(w), CNT(w));
         launch_multi_axpy<double>(s, wk, W + (int64_t)j * n, n, 1, c, n, 1.0);
       }
-    launch_norm2<double>(s, n, wk, (double*)(c + 2), PART(h), CNT(h));
+    launch_norm2<double>(s, n, wk, (double*)(c + 2), PART(w), CNT(w));
     launch_scale_dev<double>(s, n, wk, wk, (const double*)(c + 2), 1);
   }
 }
 
 void build_hierarchy(dmg_hierarchy* h, const double2* start0, const double2* start1, int inject) {
-  hipStream_t s = h->ctx->stream;
+  Work* w = &h->main;
+  hipStream_t s = w->stream;
   const int nvec = h->prm.nvec;
   DMG_CHECK(nvec == NV, DMG_E_INVALID, "the blocked layout holds 12 near-null vectors per chirality");
   for (int lvl = 0; lvl < 2; ++lvl) {
@@ -265,19 +290,19 @@ void build_hierarchy(dmg_hierarchy* h, const double2* start0, const double2* sta
         }
       }
       launch_axpby<double>(s, n * nvec, 0.0, b, -1.0, b);
-      cg_normal(h, lvl, nvec, b, psi, h->prm.null_tol, h->prm.null_max_iters, h->setup_iters[lvl]);
+      cg_normal(h, w, lvl, nvec, b, psi, h->prm.null_tol, h->prm.null_max_iters, h->setup_iters[lvl]);
       launch_axpby<double>(s, n * nvec, 1.0, start, 1.0, psi);
     }
     // global orthonormalisation (on a copy), chiral split + local orthonormalisation
     DevBuf W;
     W.alloc(h->ctx, fb);
     DMG_HIP(hipMemcpyAsync(W.p, psi, fb, hipMemcpyDeviceToDevice, s));
-    global_mgs2(h, W.as<double2>(), n, nvec);
+    global_mgs2(h, w, W.as<double2>(), n, nvec);
     const int dof = lvl == 0 ? 2 : NC;
     const int64_t pe = (int64_t)A.Lx * A.Lt * dof * NV;
     h->P64[lvl].alloc(h->ctx, sizeof(double2) * pe);
     h->P32[lvl].alloc(h->ctx, sizeof(float2) * pe);
-    int* status = h->flags.as<int>();
+    int* status = w->flags.as<int>();
     DMG_HIP(hipMemsetAsync(status, 0, sizeof(int), s));
     launch_local_ortho(s, W.as<double2>(), n, nvec, h->P64[lvl].as<double2>(), A.Lx, A.Lt, dof, status);
     int st = 0;
@@ -319,6 +344,7 @@ template <typename R>
 struct Precond {
   using T = cx<R>;
   dmg_hierarchy* h;
+  Work* w;
   int smooth_steps = 2;
   KWS sm[2];                       // smoother bases, levels 0 and 1
   DevBuf y[2], r[2], r2[2], sv[2];  // cycle vectors
@@ -329,18 +355,19 @@ struct Precond {
   int proj_m = 0;
   DevBuf xchg;                     // exchange field of the persistent coarse solve
   DevBuf bflags;                   // its grid-barrier flags
+  DevBuf cg_y;                     // CGNE iterate of the non-deflated coarse solve
   const dmg_solve_params* p = nullptr;
   dmg_deflation* defl = nullptr;
 
-  explicit Precond(dmg_hierarchy* hh) : h(hh) {}
+  Precond(dmg_hierarchy* hh, Work* ww) : h(hh), w(ww) {}
 
-  hipStream_t S() const { return h->ctx->stream; }
+  hipStream_t S() const { return w->stream; }
   const T* Pm(int lvl) const { return (const T*)h->tr[lvl].P((const T*)nullptr); }
 
   void ensure(const dmg_solve_params* prm, dmg_deflation* d) {
     p = prm;
     defl = d;
-    dmg_context* c = h->ctx;
+    dmg_context* c = w->ctx;
     const size_t es = sizeof(T);
     if (!sm[0].V.p || smooth_steps != prm->smooth_steps) {
       smooth_steps = prm->smooth_steps;
@@ -371,6 +398,11 @@ struct Precond {
       proj.alloc(c, pm, h->op[2].n, es, false);
       proj_m = pm;
     }
+    if (d && prm->coarse_persistent) {
+      if (!xchg.p) xchg.alloc(c, es * h->op[2].n);
+      if (!bflags.p) bflags.alloc(c, sizeof(unsigned) * coarse_proj_flag_words(256));
+    }
+    if (!d && !cg_y.p) cg_y.alloc(c, sizeof(double2) * h->op[2].n);
   }
 
   // GMRES(s) from x = 0 on level lvl: y = approximate A^{-1} v; r = v - A y from the
@@ -378,22 +410,22 @@ struct Precond {
   // (the paper's smoother) use the fused kernels: w1 = A v, w2 = A w1, one Gram reduction
   // with the 2 x 2 solve, one combination.  Other step counts run the Arnoldi kernels.
   void smooth(int lvl, const T* v, T* yout, T* rout) {
-    KWS& w = sm[lvl];
-    KState* ks = w.state();
-    T* V = w.V.as<T>();
-    const int64_t n = w.n;
+    KWS& ws = sm[lvl];
+    KState* ks = ws.state();
+    T* V = ws.V.as<T>();
+    const int64_t n = ws.n;
     if (smooth_steps == 2) {
       h->op[lvl].apply(S(), v, V, 0, nullptr);
       h->op[lvl].apply(S(), V, V + n, 0, nullptr);
-      h->cnt.mv[lvl] += 2;
-      launch_smooth2<R>(S(), v, V, V + n, n, ks->y, yout, rout, PART(h), CNT(h));
+      w->cnt.mv[lvl] += 2;
+      launch_smooth2<R>(S(), v, V, V + n, n, ks->y, yout, rout, PART(w), CNT(w));
       return;
     }
-    launch_cycle_start<R>(S(), v, V, n, ks, -1.0, 1, PART(h), CNT(h));
+    launch_cycle_start<R>(S(), v, V, n, ks, -1.0, 1, PART(w), CNT(w));
     for (int j = 0; j < smooth_steps; ++j) {
       h->op[lvl].apply(S(), V + j * n, V + (j + 1) * n, 0, &ks->done);
-      launch_arnoldi_orth<R>(S(), V, n, n, j, ks, PART(h), CNT(h));
-      h->cnt.mv[lvl]++;
+      launch_arnoldi_orth<R>(S(), V, n, n, j, ks, PART(w), CNT(w));
+      w->cnt.mv[lvl]++;
     }
     launch_ls_solve(S(), ks);
     launch_combine<R, R>(S(), yout, V, n, n, ks, 0, 0);
@@ -410,19 +442,20 @@ struct Precond {
     const T* DV = dvec(d);
     const double2* DH = d->H.as<double2>();
     if (p->coarse_persistent) {
-      if (!xchg.p) xchg.alloc(h->ctx, sizeof(T) * n);
-      int* it_d = h->flags.as<int>() + 8;
-      double* rr_d = (double*)(h->flags.as<int>() + 16);
+      if (!xchg.p) xchg.alloc(w->ctx, sizeof(T) * n);
+      int* it_d = w->flags.as<int>() + 8;
+      double* rr_d = (double*)(w->flags.as<int>() + 16);
       const T* Ab = (const T*)(sizeof(R) == sizeof(double) ? (const void*)A.A64 : (const void*)A.A32);
-      if (!bflags.p) bflags.alloc(h->ctx, sizeof(unsigned) * coarse_proj_flag_words(256));
-      int* err_d = h->flags.as<int>() + 9;  // read back together with the step count
-      hipEvent_t ta = timer_mark(h->ctx, DMG_KT_COARSE_PROJ);
+      if (!bflags.p) bflags.alloc(w->ctx, sizeof(unsigned) * coarse_proj_flag_words(256));
+      int* err_d = w->flags.as<int>() + 9;  // read back together with the step count
+      hipEvent_t ta = timer_mark(h->ctx, DMG_KT_COARSE_PROJ, S());
       if (launch_coarse_proj<R>(S(), Ab, A.Lx, A.Lt, DV, d->M.as<double2>(), d->Pi.as<double2>(), k, b, x, tol, mm,
                                 p->coarse_max_iters,
-                                xchg.as<T>(), PART(h), h->partials.bytes / sizeof(double2), it_d, rr_d,
-                                bflags.as<unsigned>(), bflags.bytes / sizeof(unsigned), err_d, 0)) {
+                                xchg.as<T>(), PART(w), w->partials.bytes / sizeof(double2), it_d, rr_d,
+                                bflags.as<unsigned>(), bflags.bytes / sizeof(unsigned), err_d, 0,
+                                p->coarse_persistent == 1 ? 1 : 0)) {
         (void)err_d;  // step count and barrier status are read once per outer solve
-        timer_span(h->ctx, DMG_KT_COARSE_PROJ, ta, timer_mark(h->ctx, DMG_KT_COARSE_PROJ), 0);
+        timer_span(h->ctx, DMG_KT_COARSE_PROJ, ta, timer_mark(h->ctx, DMG_KT_COARSE_PROJ, S()), 0);
         return;
       }
     }
@@ -431,25 +464,25 @@ struct Precond {
     T* rr = pr.as<T>();
     DMG_HIP(hipMemsetAsync(x, 0, sizeof(T) * n, S()));
     DMG_HIP(hipMemcpyAsync(rr, b, sizeof(T) * n, hipMemcpyDeviceToDevice, S()));
-    launch_set_bnorm<R>(S(), n, b, ks, PART(h), CNT(h));
+    launch_set_bnorm<R>(S(), n, b, ks, PART(w), CNT(w));
     int iters = 0;
     KStatus st{};
     for (;;) {
-      launch_multidot<R>(S(), DV, n, k + 1, rr, n, ks->c, PART(h), CNT(h));
+      launch_multidot<R>(S(), DV, n, k + 1, rr, n, ks->c, PART(w), CNT(w));
       launch_proj_solve(S(), DH, k, ks);
       launch_combine<R, R>(S(), x, DV, n, n, ks, 0, 1);
       launch_multi_axpy<R>(S(), rr, DV, n, k + 1, ks->u, n, 1.0);
-      launch_cycle_start<R>(S(), rr, V, n, ks, tol, 0, PART(h), CNT(h));
+      launch_cycle_start<R>(S(), rr, V, n, ks, tol, 0, PART(w), CNT(w));
       for (int j = 0; j < mm; ++j) {
         A.apply(S(), V + j * n, V + (j + 1) * n, 0, &ks->done);
-        launch_arnoldi_orth<R>(S(), V, n, n, j, ks, PART(h), CNT(h));
+        launch_arnoldi_orth<R>(S(), V, n, n, j, ks, PART(w), CNT(w));
       }
       launch_ls_solve(S(), ks);
       launch_combine<R, R>(S(), x, V, n, n, ks, 0, 1);
       launch_combine<R, R>(S(), rr, V, n, n, ks, 1, 0);
-      sync_status(h, ks, &st);
+      sync_status(w, ks, &st);
       iters += st.steps;
-      h->cnt.mv[2] += st.steps;
+      w->cnt.mv[2] += st.steps;
       if (st.est <= st.tol_abs || st.breakdown || iters >= p->coarse_max_iters) break;
     }
   }
@@ -457,7 +490,7 @@ struct Precond {
   const T* dvec(dmg_deflation* d);
 
   void coarse_solve(const T* b, T* x) {
-    h->cnt.coarse_calls++;
+    w->cnt.coarse_calls++;
     if (!defl) {
       coarse_cgne(b, x);
       return;
@@ -465,10 +498,10 @@ struct Precond {
     if (!defl->ready) {
       const int64_t n = h->op[2].n;
       if constexpr (sizeof(R) == sizeof(double)) {
-        coarse_gmres_dr(h, defl, (const double2*)b, (double2*)x, p->coarse_tol_first, p->coarse_max_iters);
+        coarse_gmres_dr(h, w, defl, (const double2*)b, (double2*)x, p->coarse_tol_first, p->coarse_max_iters);
       } else {
         launch_cast_f2d(S(), n, (const float2*)b, bc64.as<double2>());
-        coarse_gmres_dr(h, defl, bc64.as<double2>(), ec64.as<double2>(), p->coarse_tol_first, p->coarse_max_iters);
+        coarse_gmres_dr(h, w, defl, bc64.as<double2>(), ec64.as<double2>(), p->coarse_tol_first, p->coarse_max_iters);
         launch_cast_d2f(S(), n, ec64.as<double2>(), (float2*)x);
       }
       return;
@@ -487,13 +520,12 @@ struct Precond {
       launch_cast_f2d(S(), n, (const float2*)b, bc64.as<double2>());
       b64 = bc64.as<double2>();
     }
-    DevBuf y;
-    y.alloc(h->ctx, sizeof(double2) * n);
+    if (!cg_y.p) cg_y.alloc(w->ctx, sizeof(double2) * n);
     int it = 0;
-    cg_normal(h, 2, 1, b64, y.as<double2>(), p->coarse_tol_first, p->coarse_max_iters, &it);
+    cg_normal(h, w, 2, 1, b64, cg_y.as<double2>(), p->coarse_tol_first, p->coarse_max_iters, &it);
     double2* x64 = (sizeof(R) == sizeof(double)) ? (double2*)x : ec64.as<double2>();
-    h->op[2].apply(S(), y.as<double2>(), x64, 1, nullptr);
-    h->cnt.mv[2]++;
+    h->op[2].apply(S(), cg_y.as<double2>(), x64, 1, nullptr);
+    w->cnt.mv[2]++;
     if constexpr (sizeof(R) == sizeof(float)) launch_cast_d2f(S(), n, ec64.as<double2>(), (float2*)x);
   }
 
@@ -509,7 +541,7 @@ struct Precond {
     coarse_solve(bc.as<T>(), ec.as<T>());
     launch_prolong<R>(S(), Pm(1), ec.as<T>(), y1, h->tr[1].Lx, h->tr[1].Lt, NC, 1);
     h->op[1].apply(S(), y1, q, 0, nullptr, v);  // q = v - D_hat y1
-    h->cnt.mv[1]++;
+    w->cnt.mv[1]++;
     smooth(1, q, s1, nullptr);
     launch_axpbyz<R>(S(), n, 1.0, y1, 1.0, s1, out);
   }
@@ -527,15 +559,15 @@ struct Precond {
     bool first = true;
     KStatus st{};
     while (iters < p->int_max_iters) {
-      launch_cycle_start<R>(S(), rr, V, n, ks, p->int_tol, first ? 1 : 0, PART(h), CNT(h));
+      launch_cycle_start<R>(S(), rr, V, n, ks, p->int_tol, first ? 1 : 0, PART(w), CNT(w));
       first = false;
       const int mm = std::min(e1.m, p->int_max_iters - iters);
       for (int j = 0; j < mm; ++j) {
         cycle1(V + j * n, Z + j * n);
         A.apply(S(), Z + j * n, V + (j + 1) * n, 0, nullptr);
-        h->cnt.mv[1]++;
-        launch_arnoldi_orth<R>(S(), V, n, n, j, ks, PART(h), CNT(h));
-        sync_status(h, ks, &st);
+        w->cnt.mv[1]++;
+        launch_arnoldi_orth<R>(S(), V, n, n, j, ks, PART(w), CNT(w));
+        sync_status(w, ks, &st);
         if (st.done) break;
       }
       launch_ls_solve(S(), ks);
@@ -544,7 +576,7 @@ struct Precond {
       if (st.est <= st.tol_abs || st.breakdown || iters >= p->int_max_iters) break;
       T* res = e1r.as<T>();
       A.apply(S(), x, res, 0, nullptr, b);
-      h->cnt.mv[1]++;
+      w->cnt.mv[1]++;
       rr = res;
     }
   }
@@ -561,7 +593,7 @@ struct Precond {
     partial_solve(bh.as<T>(), e1x.as<T>());
     launch_prolong<R>(S(), Pm(0), e1x.as<T>(), y0, h->tr[0].Lx, h->tr[0].Lt, 2, 1);
     h->op[0].apply(S(), y0, q, 0, nullptr, v);  // q = v - D y0
-    h->cnt.mv[0]++;
+    w->cnt.mv[0]++;
     smooth(0, q, s0, nullptr);
     launch_axpbyz<R>(S(), n, 1.0, y0, 1.0, s0, out);
   }
@@ -575,7 +607,7 @@ template <>
 const float2* Precond<float>::dvec(dmg_deflation* d) {
   if (!d->cast_ready) {
     const int64_t n = h->op[2].n;
-    d->V32.alloc(h->ctx, sizeof(float2) * (size_t)n * (d->kk + 1));
+    d->V32.alloc(w->ctx, sizeof(float2) * (size_t)n * (d->kk + 1));
     launch_cast_d2f(S(), n * (d->kk + 1), d->V64.as<double2>(), d->V32.as<float2>());
     d->cast_ready = 1;
   }
@@ -583,124 +615,197 @@ const float2* Precond<float>::dvec(dmg_deflation* d) {
 }
 
 // ---------------------------------------------------------------- outer FGMRES (FP64)
-dmg_status outer_solve(dmg_hierarchy* h, dmg_deflation* d, const dmg_solve_params* p, const double2* b, double2* x,
-                       dmg_solve_stats* stout) {
-  auto t0 = std::chrono::steady_clock::now();
-  hipStream_t s = h->ctx->stream;
+void prepare_work(dmg_hierarchy* h, Work* w, dmg_deflation* d, const dmg_solve_params* p) {
   DMG_CHECK(p->outer_m >= 1 && p->outer_m <= MMAX && p->int_m >= 1 && p->int_m <= MMAX && p->smooth_steps >= 1 &&
                 p->smooth_steps <= MMAX,
             DMG_E_INVALID, "restart lengths must lie in [1, 64]");
   DMG_CHECK(!d || d->h == h, DMG_E_INVALID, "deflation space belongs to another hierarchy");
-  h->cnt = Counters{};
+  const int64_t n = h->op[0].n;
+  const bool fp32 = p->precond == DMG_FP32;
+  if (!w->outer.V.p || w->outer.m != p->outer_m || w->outer.n != n) {
+    w->outer.alloc(w->ctx, p->outer_m, n, sizeof(double2), true);
+    w->or_.alloc(w->ctx, sizeof(double2) * n);
+    w->bn2.alloc(w->ctx, sizeof(double) * 4);
+    w->ov32.release();
+    w->oz32.release();
+  }
+  if (fp32 && !w->ov32.p) {
+    w->ov32.alloc(w->ctx, sizeof(float2) * n);
+    w->oz32.alloc(w->ctx, sizeof(float2) * n);
+  }
+  // a preconditioner workspace serves any hierarchy with the same level sizes
+  auto same = [&](const dmg_hierarchy* o) {
+    for (int l = 0; l < 3; ++l)
+      if (o->op[l].n != h->op[l].n || o->op[l].Lx != h->op[l].Lx) return false;
+    return true;
+  };
+  if (fp32) {
+    if (w->pc32 && w->pc32->h != h && !same(w->pc32->h)) w->pc32.reset();
+    if (!w->pc32) w->pc32.reset(new Precond<float>(h, w));
+    w->pc32->h = h;
+    w->pc32->ensure(p, d);
+  } else {
+    if (w->pc64 && w->pc64->h != h && !same(w->pc64->h)) w->pc64.reset();
+    if (!w->pc64) w->pc64.reset(new Precond<double>(h, w));
+    w->pc64->h = h;
+    w->pc64->ensure(p, d);
+  }
+  if (d && d->m != w->dr_m) {
+    // GMRES-DR workspace, used when this solve builds the deflation space
+    ensure_dr(h, w, d->m, d->k);
+  }
+}
+
+void prepare_deflation_fp32(Work* w, dmg_deflation* d) {
+  if (!d || !d->ready || d->cast_ready) return;
+  const int64_t n = d->h->op[2].n;
+  d->V32.alloc(w->ctx, sizeof(float2) * (size_t)n * (d->kk + 1));
+  launch_cast_d2f(w->stream, n * (d->kk + 1), d->V64.as<double2>(), d->V32.as<float2>());
+  DMG_HIP(hipStreamSynchronize(w->stream));
+  d->cast_ready = 1;
+}
+
+void outer_begin(dmg_hierarchy* h, Work* w, dmg_deflation* d, const dmg_solve_params* p, const double2* b,
+                 double2* x) {
+  Work::Run& R = w->run;
+  R = Work::Run{};
+  R.t0 = std::chrono::steady_clock::now();
+  R.h = h;
+  R.d = d;
+  R.p = *p;
+  R.b = b;
+  R.x = x;
+  prepare_work(h, w, d, &R.p);
+  hipStream_t s = w->stream;
+  w->cnt = Counters{};
   // device accumulators of the persistent coarse solves: [8] Arnoldi steps, [9] barrier timeout
-  DMG_HIP(hipMemsetAsync(h->flags.as<int>() + 8, 0, 2 * sizeof(int), s));
+  DMG_HIP(hipMemsetAsync(w->flags.as<int>() + 8, 0, 2 * sizeof(int), s));
   const Op& A = h->op[0];
   const int64_t n = A.n;
-  const bool fp32 = p->precond == DMG_FP32;
-  if (!h->outer.V.p || h->outer.m != p->outer_m) {
-    h->outer.alloc(h->ctx, p->outer_m, n, sizeof(double2), true);
-    h->or_.alloc(h->ctx, sizeof(double2) * n);
-    h->bn2.alloc(h->ctx, sizeof(double) * 4);
-  }
-  if (fp32 && !h->ov32.p) {
-    h->ov32.alloc(h->ctx, sizeof(float2) * n);
-    h->oz32.alloc(h->ctx, sizeof(float2) * n);
-  }
-  if (fp32) {
-    if (!h->pc32) h->pc32.reset(new Precond<float>(h));
-    h->pc32->ensure(p, d);
-  } else {
-    if (!h->pc64) h->pc64.reset(new Precond<double>(h));
-    h->pc64->ensure(p, d);
-  }
-  KState* ks = h->outer.state();
-  double2* V = h->outer.V.as<double2>();
-  double2* Z = h->outer.Z.as<double2>();
-  double2* r = h->or_.as<double2>();
-  double* scal = h->bn2.as<double>();
-  if (p->use_x0) {
+  KState* ks = w->outer.state();
+  double2* r = w->or_.as<double2>();
+  double* scal = w->bn2.as<double>();
+  if (R.p.use_x0) {
     A.apply(s, x, r, 0, nullptr);
-    h->cnt.mv[0]++;
+    w->cnt.mv[0]++;
     launch_xmy<double>(s, n, b, r);
   } else {
     DMG_HIP(hipMemsetAsync(x, 0, sizeof(double2) * n, s));
     DMG_HIP(hipMemcpyAsync(r, b, sizeof(double2) * n, hipMemcpyDeviceToDevice, s));
   }
-  launch_norm2<double>(s, n, b, scal, PART(h), CNT(h));
-  launch_set_bnorm<double>(s, n, b, ks, PART(h), CNT(h));
-  const double bnorm = std::sqrt(read_double(h, scal));
-  int iters = 0;
-  double rel = 0.0;
-  bool conv = false;
-  if (bnorm == 0.0) {
+  launch_norm2<double>(s, n, b, scal, PART(w), CNT(w));
+  launch_set_bnorm<double>(s, n, b, ks, PART(w), CNT(w));
+  R.bnorm = std::sqrt(read_double(w, scal));
+  if (R.bnorm == 0.0) {
     DMG_HIP(hipMemsetAsync(x, 0, sizeof(double2) * n, s));
-    conv = true;
-  } else {
-    // initial residual check (x0 given)
-    launch_norm2<double>(s, n, r, scal, PART(h), CNT(h));
-    rel = std::sqrt(read_double(h, scal)) / bnorm;
-    conv = rel <= p->tol;
-    KStatus st{};
-    while (!conv && iters < p->max_outer_iters) {
-      launch_cycle_start<double>(s, r, V, n, ks, p->tol, 0, PART(h), CNT(h));
-      const int mm = std::min(p->outer_m, p->max_outer_iters - iters);
-      for (int j = 0; j < mm; ++j) {
-        double2* vj = V + (int64_t)j * n;
-        double2* zj = Z + (int64_t)j * n;
-        if (fp32) {
-          launch_cast_d2f(s, n, vj, h->ov32.as<float2>());
-          h->pc32->cycle0(h->ov32.as<float2>(), h->oz32.as<float2>());
-          launch_cast_f2d(s, n, h->oz32.as<float2>(), zj);
-        } else {
-          h->pc64->cycle0(vj, zj);
-        }
-        A.apply(s, zj, V + (int64_t)(j + 1) * n, 0, nullptr);
-        h->cnt.mv[0]++;
-        launch_arnoldi_orth<double>(s, V, n, n, j, ks, PART(h), CNT(h));
-        sync_status(h, ks, &st);
-        if (st.done) break;
+    R.conv = true;
+    R.done = true;
+    return;
+  }
+  // initial residual check (x0 given)
+  launch_norm2<double>(s, n, r, scal, PART(w), CNT(w));
+  R.rel = std::sqrt(read_double(w, scal)) / R.bnorm;
+  R.conv = R.rel <= R.p.tol;
+  R.done = R.conv;
+}
+
+bool outer_advance(Work* w, int min_iters) {
+  Work::Run& R = w->run;
+  if (R.done) return true;
+  dmg_hierarchy* h = R.h;
+  const dmg_solve_params* p = &R.p;
+  hipStream_t s = w->stream;
+  const Op& A = h->op[0];
+  const int64_t n = A.n;
+  const bool fp32 = p->precond == DMG_FP32;
+  if (fp32) w->pc32->ensure(p, R.d);
+  else w->pc64->ensure(p, R.d);
+  KState* ks = w->outer.state();
+  double2* V = w->outer.V.as<double2>();
+  double2* Z = w->outer.Z.as<double2>();
+  double2* r = w->or_.as<double2>();
+  double* scal = w->bn2.as<double>();
+  double2* x = R.x;
+  const int start = R.iters;
+  KStatus st{};
+  while (!R.conv && R.iters < p->max_outer_iters && R.iters - start < min_iters) {
+    launch_cycle_start<double>(s, r, V, n, ks, p->tol, 0, PART(w), CNT(w));
+    const int mm = std::min(p->outer_m, p->max_outer_iters - R.iters);
+    for (int j = 0; j < mm; ++j) {
+      double2* vj = V + (int64_t)j * n;
+      double2* zj = Z + (int64_t)j * n;
+      if (fp32) {
+        launch_cast_d2f(s, n, vj, w->ov32.as<float2>());
+        w->pc32->cycle0(w->ov32.as<float2>(), w->oz32.as<float2>());
+        launch_cast_f2d(s, n, w->oz32.as<float2>(), zj);
+      } else {
+        w->pc64->cycle0(vj, zj);
       }
-      launch_ls_solve(s, ks);
-      launch_combine<double, double>(s, x, Z, n, n, ks, 0, 1);
-      iters += st.steps;
-      // true residual r = b - D x
-      A.apply(s, x, r, 0, nullptr, b);
-      h->cnt.mv[0]++;
-      launch_norm2<double>(s, n, r, scal, PART(h), CNT(h));
-      rel = std::sqrt(read_double(h, scal)) / bnorm;
-      conv = rel <= p->tol;
-      if (st.steps == 0) break;
+      A.apply(s, zj, V + (int64_t)(j + 1) * n, 0, nullptr);
+      w->cnt.mv[0]++;
+      launch_arnoldi_orth<double>(s, V, n, n, j, ks, PART(w), CNT(w));
+      sync_status(w, ks, &st);
+      if (st.done) break;
+    }
+    launch_ls_solve(s, ks);
+    launch_combine<double, double>(s, x, Z, n, n, ks, 0, 1);
+    R.iters += st.steps;
+    // true residual r = b - D x
+    A.apply(s, x, r, 0, nullptr, R.b);
+    w->cnt.mv[0]++;
+    launch_norm2<double>(s, n, r, scal, PART(w), CNT(w));
+    R.rel = std::sqrt(read_double(w, scal)) / R.bnorm;
+    R.conv = R.rel <= p->tol;
+    if (st.steps == 0) {
+      R.done = true;
+      break;
     }
   }
-  DMG_HIP(hipMemcpyAsync(h->host_status, h->flags.as<int>() + 8, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  if (R.conv || R.iters >= p->max_outer_iters) R.done = true;
+  return R.done;
+}
+
+dmg_status outer_finish(Work* w, dmg_solve_stats* stout) {
+  Work::Run& R = w->run;
+  dmg_hierarchy* h = R.h;
+  hipStream_t s = w->stream;
+  DMG_HIP(hipMemcpyAsync(w->host_status, w->flags.as<int>() + 8, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
   DMG_HIP(hipStreamSynchronize(s));
   auto t1 = std::chrono::steady_clock::now();
   {
-    const int* hs = (const int*)h->host_status;
+    const int* hs = (const int*)w->host_status;
     DMG_CHECK(hs[1] == 0, DMG_E_HIP, "persistent coarse solve: a grid-barrier wait timed out");
-    h->cnt.mv[2] += hs[0];
-    if (h->ctx->timing & (1 << DMG_KT_COARSE_PROJ)) h->ctx->pending_units[DMG_KT_COARSE_PROJ] += hs[0];
+    w->cnt.mv[2] += hs[0];
+    if (h->ctx->timing & (1 << DMG_KT_COARSE_PROJ)) {
+      std::lock_guard<std::mutex> lk(h->ctx->mu);
+      h->ctx->pending_units[DMG_KT_COARSE_PROJ] += hs[0];
+    }
   }
   if (stout) {
     dmg_solve_stats& o = *stout;
-    o.outer_iters = iters;
-    o.converged = conv ? 1 : 0;
-    o.fine_mvps = h->cnt.mv[0];
-    o.int_mvps = h->cnt.mv[1];
-    o.coarse_mvps = h->cnt.mv[2];
+    o.outer_iters = R.iters;
+    o.converged = R.conv ? 1 : 0;
+    o.fine_mvps = w->cnt.mv[0];
+    o.int_mvps = w->cnt.mv[1];
+    o.coarse_mvps = w->cnt.mv[2];
     const double n0 = (double)h->op[0].n, n1 = (double)h->op[1].n, n2 = (double)h->op[2].n;
-    o.fine_equiv_mvps = h->cnt.mv[0] + n1 / n0 * h->cnt.mv[1] + n2 / n0 * h->cnt.mv[2];
-    o.true_rel_resid = rel;
-    o.coarse_calls = h->cnt.coarse_calls;
-    o.coarse_dr_calls = h->cnt.dr_calls;
-    o.elapsed_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    o.fine_equiv_mvps = w->cnt.mv[0] + n1 / n0 * w->cnt.mv[1] + n2 / n0 * w->cnt.mv[2];
+    o.true_rel_resid = R.rel;
+    o.coarse_calls = w->cnt.coarse_calls;
+    o.coarse_dr_calls = w->cnt.dr_calls;
+    o.elapsed_ms = std::chrono::duration<double, std::milli>(t1 - R.t0).count();
   }
-  return conv ? DMG_OK : DMG_W_NOT_CONVERGED;
+  return R.conv ? DMG_OK : DMG_W_NOT_CONVERGED;
+}
+
+dmg_status outer_solve(dmg_hierarchy* h, Work* w, dmg_deflation* d, const dmg_solve_params* p, const double2* b,
+                       double2* x, dmg_solve_stats* stout) {
+  outer_begin(h, w, d, p, b, x);
+  outer_advance(w, std::numeric_limits<int>::max());
+  return outer_finish(w, stout);
 }
 
 }  // namespace dmg
 
 dmg_hierarchy::dmg_hierarchy() = default;
-dmg_hierarchy::~dmg_hierarchy() {
-  if (host_status) hipHostFree(host_status);
-}
+dmg_hierarchy::~dmg_hierarchy() = default;

@@ -32,6 +32,7 @@ OP_APPLY, OP_APPLY_DAG, OP_RESTRICT, OP_PROLONG = 0, 1, 2, 3
 
 EXPORTED = [
     "dmg_context_create", "dmg_context_destroy", "dmg_last_error", "dmg_context_bytes_in_use",
+    "dmg_context_set_budget",
     "dmg_gauge_create", "dmg_gauge_destroy", "dmg_apply_dirac",
     "dmg_setup", "dmg_hierarchy_destroy", "dmg_hierarchy_export", "dmg_hierarchy_part_bytes",
     "dmg_hierarchy_apply",
@@ -39,7 +40,11 @@ EXPORTED = [
     "dmg_deflation_export", "dmg_deflation_destroy",
     "dmg_solve_params_default", "dmg_setup_params_default", "dmg_solve",
     "dmg_kernel_timer", "dmg_kernel_timer_read",
+    "dmg_batch_create", "dmg_batch_admit", "dmg_batch_step", "dmg_batch_retire", "dmg_batch_slot_state",
+    "dmg_batch_destroy",
 ]
+SLOT_FREE, SLOT_RUNNING, SLOT_DONE = 0, 1, 2
+BATCH_MAX_SLOTS = 8
 KT_COARSE_PROJ, KT_BLOCK_APPLY_INT = 0, 1
 
 
@@ -116,6 +121,7 @@ def lib():
         "dmg_context_destroy": (None, [vp]),
         "dmg_last_error": (C.c_char_p, [vp]),
         "dmg_context_bytes_in_use": (sz, [vp]),
+        "dmg_context_set_budget": (i, [vp, sz]),
         "dmg_gauge_create": (i, [vp, i, i, vp, i, pp]),
         "dmg_gauge_destroy": (None, [vp]),
         "dmg_apply_dirac": (i, [vp, vp, d, i, i, vp, vp, i, i]),
@@ -134,6 +140,12 @@ def lib():
         "dmg_setup_params_default": (None, [C.POINTER(SetupParams)]),
         "dmg_solve": (i, [vp, vp, vp, C.POINTER(SolveParams), vp, vp, i, i, C.POINTER(SolveStats)]),
         "dmg_kernel_timer": (i, [vp, i]),
+        "dmg_batch_create": (i, [vp, i, C.POINTER(SolveParams), pp]),
+        "dmg_batch_admit": (i, [vp, i, vp, vp, vp, i]),
+        "dmg_batch_step": (i, [vp, i, C.POINTER(C.c_int)]),
+        "dmg_batch_retire": (i, [vp, i, vp, i, C.POINTER(SolveStats)]),
+        "dmg_batch_slot_state": (i, [vp, i]),
+        "dmg_batch_destroy": (None, [vp]),
         "dmg_kernel_timer_read": (i, [vp, i, C.POINTER(C.c_double), C.POINTER(C.c_longlong),
                                       C.POINTER(C.c_longlong)]),
     }
@@ -234,6 +246,10 @@ class Context:
     @property
     def bytes_in_use(self) -> int:
         return lib().dmg_context_bytes_in_use(self.h)
+
+    def set_budget(self, nbytes: int):
+        """HBM budget of later allocations (0: none)."""
+        self.check(lib().dmg_context_set_budget(self.h, int(nbytes)), "set_budget")
 
     def close(self):
         if self.h:
@@ -369,3 +385,50 @@ def solve(ctx: Context, hier: Hierarchy, defl, b, x, nrhs: int = 1, params: Solv
     st = lib().dmg_solve(ctx.h, hier.h, defl.h if defl is not None else None, C.byref(prm), pb, px, nrhs, kb, stats)
     ctx.check(st, "solve")
     return st, [s.as_dict() for s in stats]
+
+
+class Batch:
+    """Slots of concurrent independent solves (continuous batching); see dmg_batch_* in dmg.h."""
+
+    def __init__(self, ctx: Context, capacity: int, params: SolveParams | None = None):
+        self.ctx = ctx
+        self.capacity = capacity
+        self.h = C.c_void_p()
+        prm = params or solve_params()
+        ctx.check(lib().dmg_batch_create(ctx.h, capacity, C.byref(prm), C.byref(self.h)), "batch_create")
+        _register(self)
+
+    def admit(self, slot: int, hier: Hierarchy, defl, b) -> int:
+        """Admit one right-hand side; returns the status (DMG_E_BUDGET leaves the slot free)."""
+        pb, kb = _ptr(b)
+        st = lib().dmg_batch_admit(self.h, slot, hier.h, defl.h if defl is not None else None, pb, kb)
+        if st != DMG_E_BUDGET:
+            self.ctx.check(st, "batch_admit")
+        return st
+
+    def step(self, min_iters: int = 1) -> int:
+        n = C.c_int()
+        self.ctx.check(lib().dmg_batch_step(self.h, min_iters, C.byref(n)), "batch_step")
+        return n.value
+
+    def state(self, slot: int) -> int:
+        return lib().dmg_batch_slot_state(self.h, slot)
+
+    def retire(self, slot: int, x):
+        """Copy the slot's solution into x; returns (status, stats dict).  Errors raise."""
+        px, kx = _ptr(x)
+        stats = SolveStats()
+        st = lib().dmg_batch_retire(self.h, slot, px, kx, C.byref(stats))
+        self.ctx.check(st, "batch_retire")
+        return st, stats.as_dict()
+
+    def close(self):
+        if self.h:
+            lib().dmg_batch_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
