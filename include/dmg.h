@@ -168,6 +168,13 @@ size_t dmg_hierarchy_part_bytes(const dmg_hierarchy* h, int level, int part);
  *   DMG_OP_PROLONG:  out = P_level in        (level 0 or 1: level + 1 -> level)
  * Buffers are single fields of precision p. */
 enum { DMG_OP_APPLY = 0, DMG_OP_APPLY_DAG = 1, DMG_OP_RESTRICT = 2, DMG_OP_PROLONG = 3 };
+/* The multi-right-hand-side kernels of dmg_solve_batched on nrhs fields at once
+ * (parity hook): op DMG_OP_APPLY, DMG_OP_RESTRICT or DMG_OP_PROLONG as above; in and
+ * out hold nrhs consecutive fields of precision p (1 <= nrhs <= 64).  FP32 block
+ * stencils with 16 or more right-hand sides run on the matrix cores; mfma = 0 forces
+ * the vector-FMA kernel instead. */
+dmg_status dmg_hierarchy_apply_batched(dmg_hierarchy* h, int level, int op, dmg_precision p, const void* in,
+                                       void* out, int nrhs, int ptr_kind, int mfma);
 dmg_status dmg_hierarchy_apply(dmg_hierarchy* h, int level, int op, dmg_precision p,
                                const void* in, void* out, int ptr_kind);
 
@@ -234,6 +241,23 @@ void dmg_setup_params_default(dmg_setup_params* p);
  * written). */
 dmg_status dmg_solve(dmg_context* ctx, dmg_hierarchy* h, dmg_deflation* d, const dmg_solve_params* prm,
                      const void* b, void* x, int nrhs, int ptr_kind, dmg_solve_stats* stats);
+
+/* Solves D x = b for nrhs right-hand sides of one hierarchy jointly: the method of
+ * dmg_solve (outer FGMRES(outer_m), the three-grid cycle with the partial
+ * intermediate solve, GMRES-Proj coarse solves) advanced in lockstep, every launch
+ * covering all right-hand sides (multi-RHS stencils, transfers, Gram-Schmidt and
+ * projection kernels) while each right-hand side keeps its own Krylov state and
+ * stopping decisions.  The deflation space is shared and read only, so d must be
+ * READY (Sec. 2-3: the eigenvectors found once serve all later right-hand sides).
+ * Layout of b and x as in dmg_solve (nrhs consecutive fields).  Limits: 1 <= nrhs
+ * <= 64; outer_m, int_m and d's m - k at most 24; smooth_steps 2; use_x0 0
+ * (DMG_E_INVALID otherwise).  stats (nrhs entries, may be NULL): Mvp counts are
+ * the lockstep applications made while that right-hand side was iterating;
+ * elapsed_ms is the whole call.  Iterates agree with dmg_solve's to rounding
+ * (different reduction order).  The workspace is kept in the hierarchy between
+ * calls with the same shape. */
+dmg_status dmg_solve_batched(dmg_context* ctx, dmg_hierarchy* h, dmg_deflation* d, const dmg_solve_params* prm,
+                             const void* b, void* x, int nrhs, int ptr_kind, dmg_solve_stats* stats);
 
 /* ---------------------------------------------------------------------------
  * Batch: continuous batching of independent solves (serving form).

@@ -6,6 +6,7 @@
 #include <exception>
 #include <new>
 
+#include "mrhs.h"
 #include "solver.h"
 
 namespace dmg {
@@ -509,6 +510,107 @@ dmg_status dmg_solve(dmg_context* ctx, dmg_hierarchy* h, dmg_deflation* d, const
       if (st != DMG_OK) worst = st;
     }
     return worst;
+  });
+}
+
+dmg_status dmg_hierarchy_apply_batched(dmg_hierarchy* h, int level, int op, dmg_precision p, const void* in,
+                                       void* out, int nrhs, int ptr_kind, int mfma) {
+  if (!h) return DMG_E_INVALID;
+  return guard(h->ctx, [&]() -> dmg_status {
+    DMG_CHECK(in && out && level >= 0 && level <= 2 && nrhs >= 1 && nrhs <= 64, DMG_E_INVALID,
+              "hierarchy_apply_batched: bad arguments");
+    DMG_CHECK(op == DMG_OP_APPLY || ((op == DMG_OP_RESTRICT || op == DMG_OP_PROLONG) && level <= 1), DMG_E_INVALID,
+              "hierarchy_apply_batched: op");
+    DMG_CHECK(ptr_kind == DMG_PTR_HOST || ptr_kind == DMG_PTR_DEVICE, DMG_E_INVALID, "pointer kind");
+    int nb = 1;
+    while (nb < nrhs) nb *= 2;
+    const size_t es = p == DMG_FP64 ? sizeof(double2) : sizeof(float2);
+    int64_t nin = h->op[level].n, nout = h->op[level].n;
+    if (op == DMG_OP_RESTRICT) nout = h->op[level + 1].n;
+    if (op == DMG_OP_PROLONG) nin = h->op[level + 1].n;
+    dmg_context* c = h->ctx;
+    hipStream_t s = c->stream;
+    DevBuf bi, bo, gi, go;
+    const void* din = in;
+    void* dout = out;
+    if (ptr_kind == DMG_PTR_HOST) {
+      bi.alloc(c, es * nin * nrhs);
+      bo.alloc(c, es * nout * nrhs);
+      to_device(c, bi.p, in, es * nin * nrhs, DMG_PTR_HOST);
+      din = bi.p;
+      dout = bo.p;
+    }
+    gi.alloc(c, es * nin * nb);
+    go.alloc(c, es * nout * nb);
+    const Op& A = h->op[level];
+    const Transfer& tr = h->tr[level < 2 ? level : 1];
+    const bool was = b_block_mfma_enabled();
+    b_block_mfma_enable(mfma != 0);
+    auto run = [&](auto tag) {
+      using T = decltype(tag);
+      using R = decltype(T{}.x);
+      launch_b_gather<T>(s, (const T*)din, gi.as<T>(), nin, nrhs, nb);
+      if (op == DMG_OP_APPLY) {
+        if (A.kind == 0)
+          launch_b_wilson<R>(s, (const T*)(sizeof(R) == 8 ? (const void*)A.U64 : (const void*)A.U32), gi.as<T>(),
+                             go.as<T>(), A.m0, A.Lx, A.Lt, nb, nullptr);
+        else
+          launch_b_block<R>(s, (const T*)(sizeof(R) == 8 ? (const void*)A.A64 : (const void*)A.A32), gi.as<T>(),
+                            go.as<T>(), A.Lx, A.Lt, nb, nullptr);
+      } else if (op == DMG_OP_RESTRICT) {
+        launch_b_restrict<R>(s, tr.P((const T*)nullptr), gi.as<T>(), go.as<T>(), tr.Lx, tr.Lt, tr.dof, nb);
+      } else {
+        launch_b_prolong<R>(s, tr.P((const T*)nullptr), gi.as<T>(), go.as<T>(), tr.Lx, tr.Lt, tr.dof, nb, 0);
+      }
+      launch_b_scatter<T>(s, go.as<T>(), (T*)dout, nout, nrhs, nb);
+    };
+    try {
+      if (p == DMG_FP64) run(double2{});
+      else run(float2{});
+    } catch (...) {
+      b_block_mfma_enable(was);
+      throw;
+    }
+    b_block_mfma_enable(was);
+    if (ptr_kind == DMG_PTR_HOST) from_device(c, out, bo.p, es * nout * nrhs, DMG_PTR_HOST);
+    else DMG_HIP(hipStreamSynchronize(s));
+    return DMG_OK;
+  });
+}
+
+dmg_status dmg_solve_batched(dmg_context* ctx, dmg_hierarchy* h, dmg_deflation* d, const dmg_solve_params* prm,
+                             const void* b, void* x, int nrhs, int ptr_kind, dmg_solve_stats* stats) {
+  if (!ctx || !h) return DMG_E_INVALID;
+  return guard(ctx, [&]() -> dmg_status {
+    DMG_CHECK(h->ctx == ctx, DMG_E_INVALID, "hierarchy belongs to another context");
+    DMG_CHECK(b && x && nrhs >= 1 && nrhs <= 64, DMG_E_INVALID, "solve_batched: 1 <= nrhs <= 64");
+    DMG_CHECK(ptr_kind == DMG_PTR_HOST || ptr_kind == DMG_PTR_DEVICE, DMG_E_INVALID, "pointer kind");
+    DMG_CHECK(d && d->h == h && d->ready, DMG_E_INVALID,
+              "solve_batched: the deflation space must belong to the hierarchy and be built");
+    dmg_solve_params p;
+    dmg_solve_params_default(&p);
+    if (prm) p = *prm;
+    DMG_CHECK(p.tol > 0.0 && p.int_tol > 0.0 && p.coarse_tol_later > 0.0 && p.max_outer_iters >= 1 &&
+                  p.int_max_iters >= 1 && p.coarse_max_iters >= 1 && p.outer_m >= 1 && p.outer_m <= 24 &&
+                  p.int_m >= 1 && p.int_m <= 24 && p.smooth_steps == 2 && !p.use_x0 && d->m - d->kk <= 24,
+              DMG_E_INVALID, "solve_batched parameters (restart lengths <= 24, two smoothing steps, no x0)");
+    const int64_t n = h->op[0].n;
+    const size_t fb = sizeof(double2) * n * nrhs;
+    if (p.precond == DMG_FP32) prepare_deflation_fp32(&h->main, d);
+    DevBuf bb, xb;
+    const double2* bd = (const double2*)b;
+    double2* xd = (double2*)x;
+    if (ptr_kind == DMG_PTR_HOST) {
+      DMG_CHECK(all_finite((const double*)b, 2 * (size_t)n * nrhs), DMG_E_NONFINITE, "non-finite right-hand side");
+      bb.alloc(ctx, fb);
+      xb.alloc(ctx, fb);
+      to_device(ctx, bb.p, b, fb, ptr_kind);
+      bd = bb.as<double2>();
+      xd = xb.as<double2>();
+    }
+    dmg_status st = batched_solve(h, d, &p, bd, xd, nrhs, stats);
+    if (ptr_kind == DMG_PTR_HOST) from_device(ctx, x, xb.p, fb, ptr_kind);
+    return st;
   });
 }
 

@@ -190,6 +190,8 @@ dmg_status dmg_batch_admit(dmg_batch* bt, int slot, dmg_hierarchy* h, dmg_deflat
     // workspace for h first: a budget failure leaves the slot FREE
     prepare_work(h, &sl.w, d, &bt->p);
     if (bt->p.precond == DMG_FP32) prepare_deflation_fp32(&sl.w, d);
+    // workspace initialisation may have been queued on the context's stream
+    DMG_HIP(hipStreamSynchronize(bt->ctx->stream));
     if (sl.b.bytes != fb) {
       DMG_HIP(hipStreamSynchronize(sl.w.stream));
       sl.b.alloc(bt->ctx, fb);

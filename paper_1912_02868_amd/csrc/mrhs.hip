@@ -1,0 +1,991 @@
+// Multi-right-hand-side kernels of the lockstep solver (layout and state in mrhs.h).
+// Every reduction is deterministic and runs in two launches: each workgroup reduces
+// its threads in a fixed order into partials, then one workgroup per right-hand side
+// adds the partials in a fixed order and applies the small-dense step for that
+// right-hand side.  Right-hand sides never mix: a thread owns one right-hand side
+// r = threadIdx.x mod nb throughout a kernel.
+#include <algorithm>
+
+#include "mrhs.h"
+
+namespace dmg {
+
+constexpr int BT = 256;      // threads of the vector and reduction kernels
+constexpr int BMAXBLK = 128; // most workgroups of a reduction
+
+int bred_blocks(int64_t N) {
+  int64_t b = (N + BT * 2 - 1) / (BT * 2);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, BMAXBLK));
+}
+size_t bred_partials(int nb) { return (size_t)BMAXBLK * MQ * nb; }
+
+static bool g_block_mfma = true;
+bool b_block_mfma_enabled() { return g_block_mfma; }
+void b_block_mfma_enable(bool on) { g_block_mfma = on; }
+
+static inline int vec_blocks(int64_t N) { return (int)std::max<int64_t>(1, std::min<int64_t>((N + BT - 1) / BT, 4096)); }
+
+__device__ inline double2 bcdiv(double2 a, double2 b) {
+  const double d = b.x * b.x + b.y * b.y;
+  return mk((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+
+// Block partials of the per-thread accumulators acc[q], q < nq, into
+// part[(block * nq + q) * nb + r]; threads with the same r are added in thread order.
+template <int NQ>
+__device__ void b_publish(const double2 (&acc)[NQ], int nq, int nb, double2* part) {
+  __shared__ double2 red[4][BT];
+  const int t = threadIdx.x;
+  const int per = BT / nb;
+#pragma unroll
+  for (int q0 = 0; q0 < NQ; q0 += 4) {
+    if (q0 < nq) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (q0 + u < NQ) red[u][t] = acc[q0 + u];
+      __syncthreads();
+      if (t < 4 * nb) {
+        const int u = t / nb, r = t % nb;
+        if (q0 + u < nq) {
+          double2 s = red[u][r];
+          for (int k = 1; k < per; ++k) s = cadd(s, red[u][k * nb + r]);
+          part[((int64_t)blockIdx.x * nq + q0 + u) * nb + r] = s;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Second phase of every batched reduction: one workgroup per right-hand side adds the
+// workgroups' partials of each quantity (4 lanes per quantity, then the lanes in
+// order) and applies the step's small-dense epilogue to that right-hand side.
+enum FinMode { FIN_NORM0, FIN_NORM3, FIN_START, FIN_ARN1, FIN_ARN2, FIN_ARN3, FIN_SMOOTH2, FIN_PROJ };
+
+struct FinArgs {
+  int mode, nq, nblk, nb, j, k;
+  double tol_rel;
+  int bnorm_too;  // FIN_START: also record bnorm = beta
+  double* out;
+  double2* coef;
+  const double2* M;
+  const double2* Pi;
+  int* alldone;   // FIN_START / FIN_ARN3: set to 1 when every right-hand side is done
+  unsigned* cnt;  // ticket of the alldone update
+};
+
+constexpr int LDH = MB + 1;
+
+__device__ void fin_start(BS& b, double s2, const FinArgs& a) {
+  const double beta = sqrt(s2);
+  if (a.bnorm_too) b.bnorm = beta;
+  b.steps = 0;
+  b.brk = 0;
+  for (int i = 0; i <= MB; ++i) {
+    b.g[i] = (i == 0) ? mk(beta, 0.0) : mk(0.0, 0.0);
+    b.c[i] = b.g[i];
+  }
+  b.tol_abs = a.tol_rel * b.bnorm;
+  if (!b.active) {
+    b.beta = 0.0;
+    b.est = 0.0;
+    b.done = 1;
+  } else {
+    b.beta = beta;
+    b.est = beta;
+    b.done = (beta == 0.0 || beta <= b.tol_abs || b.cap < 1) ? 1 : 0;
+  }
+}
+
+// column j: rotate by the cycle's rotations, annihilate the subdiagonal, update g
+__device__ void fin_givens(BS& b, int j, double hn_sq) {
+  double hn = sqrt(hn_sq);
+  const bool brk = !(hn > 1e-12 * b.wn0);
+  if (brk) hn = 0.0;
+  b.H[LDH * j + j + 1] = mk(hn, 0.0);
+  double2 col[MB + 1];
+  for (int i = 0; i <= j + 1; ++i) col[i] = b.H[LDH * j + i];
+  for (int q = 0; q < j; ++q) {
+    const double c = b.rc[q];
+    const double2 sn = b.rs[q];
+    const double2 x = col[q], y = col[q + 1];
+    col[q] = cadd(cscale(x, c), cmul(sn, y));
+    col[q + 1] = csub(cscale(y, c), cmul(cconj(sn), x));
+  }
+  const double2 x = col[j], y = col[j + 1];
+  const double na = sqrt(cabs2(x)), ny = sqrt(cabs2(y));
+  double c;
+  double2 sn;
+  if (ny == 0.0) {
+    c = 1.0;
+    sn = mk(0.0, 0.0);
+  } else if (na == 0.0) {
+    c = 0.0;
+    sn = cscale(cconj(y), 1.0 / ny);
+  } else {
+    const double nr = sqrt(na * na + ny * ny);
+    c = na / nr;
+    sn = cscale(cmul(cconj(y), x), 1.0 / (na * nr));
+  }
+  col[j] = cadd(cscale(x, c), cmul(sn, y));
+  col[j + 1] = mk(0.0, 0.0);
+  for (int i = 0; i <= j + 1; ++i) b.Rm[LDH * j + i] = col[i];
+  const double2 gj = b.g[j], gj1 = b.g[j + 1];
+  b.g[j] = cadd(cscale(gj, c), cmul(sn, gj1));
+  const double2 ng1 = csub(cscale(gj1, c), cmul(cconj(sn), gj));
+  b.g[j + 1] = ng1;
+  b.rc[j] = c;
+  b.rs[j] = sn;
+  b.est = sqrt(cabs2(ng1));
+  b.steps = j + 1;
+  if (brk) {
+    b.brk = 1;
+    b.est = 0.0;
+  }
+  if (brk || b.est <= b.tol_abs || b.steps >= b.cap) b.done = 1;
+}
+
+__global__ void __launch_bounds__(BT) kb_final(const double2* __restrict__ part, BS* bs, FinArgs a) {
+  const bool arn = a.mode == FIN_ARN1 || a.mode == FIN_ARN2 || a.mode == FIN_ARN3;
+  if (arn && *a.alldone) return;
+  __shared__ double2 lanes[64][4];
+  __shared__ double2 tot[64];
+  const int r = blockIdx.x, t = threadIdx.x;
+  const int q = t >> 2, g = t & 3;
+  if (q < a.nq) {
+    double2 s0 = mk(0.0, 0.0), s1 = mk(0.0, 0.0);
+    int b = g;
+    for (; b + 4 < a.nblk; b += 8) {
+      s0 = cadd(s0, part[((int64_t)b * a.nq + q) * a.nb + r]);
+      s1 = cadd(s1, part[((int64_t)(b + 4) * a.nq + q) * a.nb + r]);
+    }
+    if (b < a.nblk) s0 = cadd(s0, part[((int64_t)b * a.nq + q) * a.nb + r]);
+    lanes[q][g] = cadd(s0, s1);
+  }
+  __syncthreads();
+  if (t < a.nq) tot[t] = cadd(cadd(lanes[t][0], lanes[t][1]), cadd(lanes[t][2], lanes[t][3]));
+  __syncthreads();
+  if (a.mode == FIN_SMOOTH2) {
+    // two-step smoother: least-squares fit of v by [w1, w2] from the Gram entries
+    if (t == 0) {
+      const double g11 = tot[0].x, g22 = tot[2].x;
+      const double2 g12 = tot[1], r1 = tot[3], r2 = tot[4];
+      double2 c0 = mk(0.0, 0.0), c1 = mk(0.0, 0.0);
+      const double det = g11 * g22 - cabs2(g12);  // Gram determinant (>= 0)
+      if (g11 > 0.0 && det > 1e-13 * g11 * g22) {
+        const double inv = 1.0 / det;
+        c0 = cscale(csub(cscale(r1, g22), cmul(g12, r2)), inv);
+        c1 = cscale(csub(cscale(r2, g11), cmul(cconj(g12), r1)), inv);
+      } else if (g11 > 0.0) {
+        c0 = cscale(r1, 1.0 / g11);
+      }
+      a.coef[2 * r] = c0;
+      a.coef[2 * r + 1] = c1;
+    }
+    return;
+  }
+  BS& b = bs[r];
+  const int j = a.j;
+  switch (a.mode) {
+    case FIN_NORM0:
+      if (t == 0) a.out[r] = tot[0].x;
+      break;
+    case FIN_NORM3:
+      if (t == 0) b.bnorm = sqrt(tot[0].x);
+      break;
+    case FIN_START:
+      if (t == 0) fin_start(b, tot[0].x, a);
+      break;
+    case FIN_ARN1:
+      if (!b.done) {
+        for (int i = t; i <= MB; i += BT) {
+          if (i <= j) b.H[LDH * j + i] = tot[i];
+          else if (i > j + 1) b.H[LDH * j + i] = mk(0.0, 0.0);
+        }
+        if (t == 0) b.wn0 = sqrt(tot[j + 1].x);
+      }
+      break;
+    case FIN_ARN2:
+      if (!b.done)
+        for (int i = t; i <= j; i += BT) {
+          b.h2[i] = tot[i];
+          b.H[LDH * j + i] = cadd(b.H[LDH * j + i], tot[i]);
+        }
+      break;
+    case FIN_ARN3:
+      if (t == 0 && !b.done) fin_givens(b, j, tot[0].x);
+      break;
+    case FIN_PROJ:
+      if (b.active) {
+        // y_i = sum_l M[i + k l] c_l (i < k), u_i = sum_l Pi[i + (k+1) l] c_l (i <= k)
+        const int k = a.k;
+        for (int i = t; i < 2 * k + 1; i += BT) {
+          double2 acc = mk(0.0, 0.0);
+          if (i < k) {
+            for (int l = 0; l <= k; ++l) cfma(acc, a.M[i + (int64_t)k * l], tot[l]);
+            b.y[i] = acc;
+          } else {
+            const int ii = i - k;
+            for (int l = 0; l <= k; ++l) cfma(acc, a.Pi[ii + (int64_t)(k + 1) * l], tot[l]);
+            b.u[ii] = acc;
+          }
+        }
+      }
+      break;
+  }
+  if (a.mode == FIN_START || a.mode == FIN_ARN3) {
+    __shared__ int last;
+    __threadfence();
+    __syncthreads();
+    if (t == 0) last = (atomicAdd(a.cnt, 1u) == (unsigned)a.nb - 1) ? 1 : 0;
+    __syncthreads();
+    if (last && t == 0) {
+      __threadfence();
+      int all = 1;
+      for (int i = 0; i < a.nb; ++i) all &= bs[i].done ? 1 : 0;
+      *a.alldone = all;
+      *a.cnt = 0u;
+    }
+  }
+}
+
+static void launch_final(hipStream_t s, const double2* part, BS* bs, const FinArgs& a) {
+  hipLaunchKernelGGL(kb_final, dim3(a.nb), dim3(BT), 0, s, part, bs, a);
+  DMG_LAUNCH_CHECK();
+}
+
+static FinArgs fin(int mode, int nq, int nblk, int nb) {
+  FinArgs a{};
+  a.mode = mode;
+  a.nq = nq;
+  a.nblk = nblk;
+  a.nb = nb;
+  return a;
+}
+
+// ---------------------------------------------------------------- norms and cycle start
+template <typename R>
+__global__ void __launch_bounds__(BT) kb_norm(const cx<R>* __restrict__ x, int64_t n, int nb, double2* part) {
+  const int64_t N = n * nb;
+  const int64_t stride = (int64_t)gridDim.x * BT;
+  double2 acc[1] = {mk(0.0, 0.0)};
+  for (int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x; i < N; i += stride) acc[0].x += cabs2(to_d(x[i]));
+  b_publish<1>(acc, 1, nb, part);
+}
+
+template <typename R>
+void launch_b_norm(hipStream_t s, const cx<R>* x, int64_t n, int nb, BS* bs, double tol_rel, int mode, double* out,
+                   int* alldone, double2* part, unsigned* cnt) {
+  const int G = bred_blocks(n * nb);
+  hipLaunchKernelGGL(kb_norm<R>, dim3(G), dim3(BT), 0, s, x, n, nb, part);
+  FinArgs a = fin(mode == 0 ? FIN_NORM0 : mode == 3 ? FIN_NORM3 : FIN_START, 1, G, nb);
+  a.tol_rel = tol_rel;
+  a.bnorm_too = mode == 2 ? 1 : 0;
+  a.out = out;
+  a.alldone = alldone;
+  a.cnt = cnt;
+  launch_final(s, part, bs, a);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(BT) kb_scale_beta(const cx<R>* __restrict__ x, cx<R>* __restrict__ y, int64_t n,
+                                                    int nb, const BS* bs) {
+  const int r = threadIdx.x & (nb - 1);
+  const double beta = bs[r].beta;
+  const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
+  const int64_t N = n * nb;
+  const int64_t stride = (int64_t)gridDim.x * BT;
+  for (int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x; i < N; i += stride) y[i] = from_d<R>(cscale(to_d(x[i]), inv));
+}
+
+template <typename R>
+void launch_b_scale_beta(hipStream_t s, const cx<R>* x, cx<R>* y, int64_t n, int nb, const BS* bs) {
+  hipLaunchKernelGGL(kb_scale_beta<R>, dim3(vec_blocks(n * nb)), dim3(BT), 0, s, x, y, n, nb, bs);
+  DMG_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------- Arnoldi (CGS2)
+
+// (a) h_i = V_i^H w (i <= j) and ||w||^2 with w = V_{j+1}
+template <typename R>
+__global__ void __launch_bounds__(BT) kb_arn_dots1(const cx<R>* __restrict__ V, int64_t ld, int64_t n, int nb, int j,
+                                                   const int* alldone, double2* part) {
+  if (*alldone) return;
+  const int64_t N = n * nb;
+  const int64_t stride = (int64_t)gridDim.x * BT;
+  const cx<R>* w = V + (int64_t)(j + 1) * ld;
+  double2 acc[MB + 2];
+#pragma unroll
+  for (int q = 0; q < MB + 2; ++q) acc[q] = mk(0.0, 0.0);
+  for (int64_t e = (int64_t)blockIdx.x * BT + threadIdx.x; e < N; e += stride) {
+    const double2 wv = to_d(w[e]);
+#pragma unroll
+    for (int i = 0; i < MB + 1; ++i)
+      if (i <= j) cfmac(acc[i], to_d(V[(int64_t)i * ld + e]), wv);
+#pragma unroll
+    for (int i = 0; i < MB + 2; ++i)
+      if (i == j + 1) acc[i].x += cabs2(wv);
+  }
+  b_publish<MB + 2>(acc, j + 2, nb, part);
+}
+
+// (b) w -= sum_i H[i, j] V_i, then h2_i = V_i^H w (added to H[i, j] by the final phase)
+template <typename R>
+__global__ void __launch_bounds__(BT) kb_arn_update_dots2(cx<R>* __restrict__ V, int64_t ld, int64_t n, int nb, int j,
+                                                          const BS* bs, const int* alldone, double2* part) {
+  if (*alldone) return;
+  const int r0 = threadIdx.x & (nb - 1);
+  const bool skip = bs[r0].done != 0;
+  double2 cf[MB + 1];
+#pragma unroll
+  for (int i = 0; i < MB + 1; ++i) cf[i] = (i <= j) ? bs[r0].H[LDH * j + i] : mk(0.0, 0.0);
+  const int64_t N = n * nb;
+  const int64_t stride = (int64_t)gridDim.x * BT;
+  cx<R>* w = V + (int64_t)(j + 1) * ld;
+  double2 acc[MB + 1];
+#pragma unroll
+  for (int q = 0; q < MB + 1; ++q) acc[q] = mk(0.0, 0.0);
+  for (int64_t e = (int64_t)blockIdx.x * BT + threadIdx.x; e < N; e += stride) {
+    double2 wv = to_d(w[e]);
+    if (!skip) {
+#pragma unroll
+      for (int i = 0; i < MB + 1; ++i)
+        if (i <= j) wv = csub(wv, cmul(cf[i], to_d(V[(int64_t)i * ld + e])));
+      const cx<R> st = from_d<R>(wv);
+      w[e] = st;
+      wv = to_d(st);
+    }
+#pragma unroll
+    for (int i = 0; i < MB + 1; ++i)
+      if (i <= j) cfmac(acc[i], to_d(V[(int64_t)i * ld + e]), wv);
+  }
+  b_publish<MB + 1>(acc, j + 1, nb, part);
+}
+
+// (c) w -= sum_i h2_i V_i and ||w||^2 (the final phase does the Givens update)
+template <typename R>
+__global__ void __launch_bounds__(BT) kb_arn_update_norm(cx<R>* __restrict__ V, int64_t ld, int64_t n, int nb, int j,
+                                                         const BS* bs, const int* alldone, double2* part) {
+  if (*alldone) return;
+  const int r0 = threadIdx.x & (nb - 1);
+  const bool skip = bs[r0].done != 0;
+  double2 cf[MB + 1];
+#pragma unroll
+  for (int i = 0; i < MB + 1; ++i) cf[i] = (i <= j) ? bs[r0].h2[i] : mk(0.0, 0.0);
+  const int64_t N = n * nb;
+  const int64_t stride = (int64_t)gridDim.x * BT;
+  cx<R>* w = V + (int64_t)(j + 1) * ld;
+  double2 acc[1] = {mk(0.0, 0.0)};
+  for (int64_t e = (int64_t)blockIdx.x * BT + threadIdx.x; e < N; e += stride) {
+    double2 wv = to_d(w[e]);
+    if (!skip) {
+#pragma unroll
+      for (int i = 0; i < MB + 1; ++i)
+        if (i <= j) wv = csub(wv, cmul(cf[i], to_d(V[(int64_t)i * ld + e])));
+      const cx<R> st = from_d<R>(wv);
+      w[e] = st;
+      wv = to_d(st);
+    }
+    acc[0].x += cabs2(wv);
+  }
+  b_publish<1>(acc, 1, nb, part);
+}
+
+// (d) V_{j+1} = w / h_{j+1, j} for the right-hand sides that took step j
+template <typename R>
+__global__ void __launch_bounds__(BT) kb_arn_normalize(cx<R>* __restrict__ V, int64_t ld, int64_t n, int nb, int j,
+                                                       const BS* bs) {
+  const int r0 = threadIdx.x & (nb - 1);
+  const BS& b = bs[r0];
+  if (b.steps != j + 1 || b.brk) return;
+  const double hn = b.H[LDH * j + j + 1].x;
+  if (hn == 0.0) return;
+  const double inv = 1.0 / hn;
+  cx<R>* w = V + (int64_t)(j + 1) * ld;
+  const int64_t N = n * nb;
+  const int64_t stride = (int64_t)gridDim.x * BT;
+  for (int64_t e = (int64_t)blockIdx.x * BT + threadIdx.x; e < N; e += stride) w[e] = from_d<R>(cscale(to_d(w[e]), inv));
+}
+
+template <typename R>
+void launch_b_arnoldi(hipStream_t s, cx<R>* V, int64_t ld, int64_t n, int nb, int j, BS* bs, int* alldone,
+                      double2* part, unsigned* cnt) {
+  const int G = bred_blocks(n * nb);
+  FinArgs a = fin(FIN_ARN1, j + 2, G, nb);
+  a.j = j;
+  a.alldone = alldone;
+  a.cnt = cnt;
+  hipLaunchKernelGGL(kb_arn_dots1<R>, dim3(G), dim3(BT), 0, s, (const cx<R>*)V, ld, n, nb, j, (const int*)alldone, part);
+  launch_final(s, part, bs, a);
+  hipLaunchKernelGGL(kb_arn_update_dots2<R>, dim3(G), dim3(BT), 0, s, V, ld, n, nb, j, (const BS*)bs,
+                     (const int*)alldone, part);
+  a.mode = FIN_ARN2;
+  a.nq = j + 1;
+  launch_final(s, part, bs, a);
+  hipLaunchKernelGGL(kb_arn_update_norm<R>, dim3(G), dim3(BT), 0, s, V, ld, n, nb, j, (const BS*)bs,
+                     (const int*)alldone, part);
+  a.mode = FIN_ARN3;
+  a.nq = 1;
+  launch_final(s, part, bs, a);
+  hipLaunchKernelGGL(kb_arn_normalize<R>, dim3(vec_blocks(n * nb)), dim3(BT), 0, s, V, ld, n, nb, j, (const BS*)bs);
+  DMG_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------- least squares, combinations
+// One workgroup per right-hand side: y = Rm^{-1} g (steps terms), u = c - H y.
+__global__ void __launch_bounds__(64) kb_ls_solve(BS* bs) {
+  __shared__ double2 Rs[LDH * MB];
+  __shared__ double2 ys[MB + 1];
+  BS& b = bs[blockIdx.x];
+  const int t = threadIdx.x;
+  const int n = b.active ? b.steps : 0;
+  for (int e = t; e < LDH * n; e += 64) Rs[e] = b.Rm[e];
+  __syncthreads();
+  if (t == 0) {
+    for (int i = n - 1; i >= 0; --i) {
+      double2 acc = b.g[i];
+      for (int l = i + 1; l < n; ++l) acc = csub(acc, cmul(Rs[i + LDH * l], ys[l]));
+      const double2 d = Rs[i + LDH * i];
+      ys[i] = cabs2(d) > 0.0 ? bcdiv(acc, d) : mk(0.0, 0.0);
+    }
+  }
+  __syncthreads();
+  for (int i = t; i < n; i += 64) b.y[i] = ys[i];
+  for (int i = t; i <= n; i += 64) {
+    double2 acc = b.c[i];
+    for (int l = 0; l < n; ++l) acc = csub(acc, cmul(b.H[i + LDH * l], ys[l]));
+    b.u[i] = acc;
+  }
+}
+
+void launch_b_ls_solve(hipStream_t s, BS* bs, int nb) {
+  hipLaunchKernelGGL(kb_ls_solve, dim3(nb), dim3(64), 0, s, bs);
+  DMG_LAUNCH_CHECK();
+}
+
+template <typename R>
+__global__ void __launch_bounds__(BT) kb_combine(cx<R>* __restrict__ x, const cx<R>* __restrict__ V, int64_t ld,
+                                                 int64_t n, int nb, const BS* bs, int use_u, int accumulate) {
+  const int r0 = threadIdx.x & (nb - 1);
+  const BS& b = bs[r0];
+  if (!b.active) return;
+  const int cntc = b.steps + (use_u ? 1 : 0);
+  const double2* src = use_u ? b.u : b.y;
+  double2 cf[MB + 1];
+#pragma unroll
+  for (int i = 0; i < MB + 1; ++i) cf[i] = (i < cntc) ? src[i] : mk(0.0, 0.0);
+  const int64_t N = n * nb;
+  const int64_t stride = (int64_t)gridDim.x * BT;
+  for (int64_t e = (int64_t)blockIdx.x * BT + threadIdx.x; e < N; e += stride) {
+    double2 acc = accumulate ? to_d(x[e]) : mk(0.0, 0.0);
+#pragma unroll
+    for (int i = 0; i < MB + 1; ++i)
+      if (i < cntc) cfma(acc, cf[i], to_d(V[(int64_t)i * ld + e]));
+    x[e] = from_d<R>(acc);
+  }
+}
+
+template <typename R>
+void launch_b_combine(hipStream_t s, cx<R>* x, const cx<R>* V, int64_t ld, int64_t n, int nb, const BS* bs, int use_u,
+                      int accumulate) {
+  hipLaunchKernelGGL(kb_combine<R>, dim3(vec_blocks(n * nb)), dim3(BT), 0, s, x, V, ld, n, nb, bs, use_u, accumulate);
+  DMG_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------- two-step smoother
+template <typename R>
+__global__ void __launch_bounds__(BT) kb_smooth2_dots(const cx<R>* __restrict__ v, const cx<R>* __restrict__ w1,
+                                                      const cx<R>* __restrict__ w2, int64_t n, int nb, double2* part) {
+  const int64_t N = n * nb;
+  const int64_t stride = (int64_t)gridDim.x * BT;
+  double2 acc[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) acc[q] = mk(0.0, 0.0);
+  for (int64_t e = (int64_t)blockIdx.x * BT + threadIdx.x; e < N; e += stride) {
+    const double2 vv = to_d(v[e]), x1 = to_d(w1[e]), x2 = to_d(w2[e]);
+    acc[0].x += cabs2(x1);
+    cfmac(acc[1], x1, x2);
+    acc[2].x += cabs2(x2);
+    cfmac(acc[3], x1, vv);
+    cfmac(acc[4], x2, vv);
+  }
+  b_publish<5>(acc, 5, nb, part);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(BT) kb_smooth2_combine(const cx<R>* __restrict__ v, const cx<R>* __restrict__ w1,
+                                                         const cx<R>* __restrict__ w2, int64_t n, int nb,
+                                                         const double2* coef, cx<R>* __restrict__ y,
+                                                         cx<R>* __restrict__ rr) {
+  const int r0 = threadIdx.x & (nb - 1);
+  const double2 c0 = coef[2 * r0], c1 = coef[2 * r0 + 1];
+  const int64_t N = n * nb;
+  const int64_t stride = (int64_t)gridDim.x * BT;
+  for (int64_t e = (int64_t)blockIdx.x * BT + threadIdx.x; e < N; e += stride) {
+    const double2 vv = to_d(v[e]), x1 = to_d(w1[e]);
+    double2 yv = mk(0.0, 0.0);
+    cfma(yv, c0, vv);
+    cfma(yv, c1, x1);
+    y[e] = from_d<R>(yv);
+    if (rr) {
+      double2 rv = vv;
+      rv = csub(rv, cmul(c0, x1));
+      rv = csub(rv, cmul(c1, to_d(w2[e])));
+      rr[e] = from_d<R>(rv);
+    }
+  }
+}
+
+template <typename R>
+void launch_b_smooth2(hipStream_t s, const cx<R>* v, const cx<R>* w1, const cx<R>* w2, int64_t n, int nb,
+                      double2* coef, cx<R>* y, cx<R>* r, double2* part, unsigned* cnt) {
+  const int G = bred_blocks(n * nb);
+  hipLaunchKernelGGL(kb_smooth2_dots<R>, dim3(G), dim3(BT), 0, s, v, w1, w2, n, nb, part);
+  FinArgs a = fin(FIN_SMOOTH2, 5, G, nb);
+  a.coef = coef;
+  launch_final(s, part, nullptr, a);
+  hipLaunchKernelGGL(kb_smooth2_combine<R>, dim3(vec_blocks(n * nb)), dim3(BT), 0, s, v, w1, w2, n, nb,
+                     (const double2*)coef, y, r);
+  DMG_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------- GMRES-Proj projection
+// c_i = DV_i^H r (i <= k) per right-hand side (the final phase forms y = M c and u = Pi c)
+template <typename R>
+__global__ void __launch_bounds__(BT) kb_proj_dots(const cx<R>* __restrict__ DV, int k, const cx<R>* __restrict__ rr,
+                                                   int64_t n, int nb, double2* part) {
+  const int64_t N = n * nb;
+  const int64_t stride = (int64_t)gridDim.x * BT;
+  const int lg = __ffs(nb) - 1;
+  double2 acc[MQ];
+#pragma unroll
+  for (int q = 0; q < MQ; ++q) acc[q] = mk(0.0, 0.0);
+  for (int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x; i < N; i += stride) {
+    const int64_t e = i >> lg;
+    const double2 rv = to_d(rr[i]);
+#pragma unroll
+    for (int q = 0; q < MQ; ++q)
+      if (q <= k) cfmac(acc[q], to_d(DV[(int64_t)q * n + e]), rv);
+  }
+  b_publish<MQ>(acc, k + 1, nb, part);
+}
+
+// x += sum_{i<k} y_i DV_i ; r -= sum_{i<=k} u_i DV_i (active right-hand sides)
+template <typename R>
+__global__ void __launch_bounds__(BT) kb_proj_apply(const cx<R>* __restrict__ DV, int k, cx<R>* __restrict__ x,
+                                                    cx<R>* __restrict__ rr, int64_t n, int nb, const BS* bs) {
+  __shared__ double2 cy[MQ][NBMAX];
+  __shared__ double2 cu[MQ][NBMAX];
+  for (int p = threadIdx.x; p < (k + 1) * nb; p += BT) {
+    const int r = p % nb, q = p / nb;
+    cy[q][r] = (q < k) ? bs[r].y[q] : mk(0.0, 0.0);
+    cu[q][r] = bs[r].u[q];
+  }
+  __syncthreads();
+  const int r0 = threadIdx.x & (nb - 1);
+  if (!bs[r0].active) return;
+  const int lg = __ffs(nb) - 1;
+  const int64_t N = n * nb;
+  const int64_t stride = (int64_t)gridDim.x * BT;
+  for (int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x; i < N; i += stride) {
+    const int64_t e = i >> lg;
+    double2 xv = to_d(x[i]), rv = to_d(rr[i]);
+    for (int q = 0; q <= k; ++q) {
+      const double2 dv = to_d(DV[(int64_t)q * n + e]);
+      cfma(xv, cy[q][r0], dv);
+      rv = csub(rv, cmul(cu[q][r0], dv));
+    }
+    x[i] = from_d<R>(xv);
+    rr[i] = from_d<R>(rv);
+  }
+}
+
+template <typename R>
+void launch_b_project(hipStream_t s, const cx<R>* DV, int k, const double2* M, const double2* Pi, cx<R>* x, cx<R>* r,
+                      int64_t n, int nb, BS* bs, double2* part, unsigned* cnt) {
+  const int G = bred_blocks(n * nb);
+  hipLaunchKernelGGL(kb_proj_dots<R>, dim3(G), dim3(BT), 0, s, DV, k, (const cx<R>*)r, n, nb, part);
+  FinArgs a = fin(FIN_PROJ, k + 1, G, nb);
+  a.k = k;
+  a.M = M;
+  a.Pi = Pi;
+  launch_final(s, part, bs, a);
+  hipLaunchKernelGGL(kb_proj_apply<R>, dim3(vec_blocks(n * nb)), dim3(BT), 0, s, DV, k, x, r, n, nb, (const BS*)bs);
+  DMG_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------- stencils
+template <typename T> __device__ inline T bmul_i(T z) { T r; r.x = -z.y; r.y = z.x; return r; }
+
+// Wilson-Dirac operator on a batched field: one thread per (site, right-hand side),
+// both spins (the spin-projected hops of the single-field stencil).
+template <typename R>
+__global__ void __launch_bounds__(BT) kb_wilson(const cx<R>* __restrict__ U, const cx<R>* __restrict__ in,
+                                                cx<R>* __restrict__ out, R diag, int Nx, int Nt, int nb,
+                                                const cx<R>* __restrict__ sub, const int* skip) {
+  if (skip && *skip) return;
+  using T = cx<R>;
+  const int lg = __ffs(nb) - 1;
+  const int64_t idx = (int64_t)blockIdx.x * BT + threadIdx.x;
+  const int V = Nx * Nt;
+  if (idx >= (int64_t)V * nb) return;
+  const int s = (int)(idx >> lg), r = (int)(idx & (nb - 1));
+  const int x = s % Nx, t = s / Nx;
+  const int xp = (x + 1 == Nx) ? 0 : x + 1, xm = (x == 0) ? Nx - 1 : x - 1;
+  const int tp = (t + 1 == Nt) ? 0 : t + 1, tm = (t == 0) ? Nt - 1 : t - 1;
+  const int sxp = xp + Nx * t, sxm = xm + Nx * t, stp = x + Nx * tp, stm = x + Nx * tm;
+  auto at = [&](int site, int spin) { return in[((int64_t)(2 * site + spin) << lg) + r]; };
+  const R half = R(0.5);
+  T acc0 = cscale(at(s, 0), diag), acc1 = cscale(at(s, 1), diag);
+  {
+    T h = csub(at(sxp, 0), at(sxp, 1));
+    T w = cmul(U[2 * s + 0], h);
+    acc0 = csub(acc0, cscale(w, half));
+    acc1 = cadd(acc1, cscale(w, half));
+  }
+  {
+    T h = cadd(at(sxm, 0), at(sxm, 1));
+    T w = cmulc(U[2 * sxm + 0], h);
+    acc0 = csub(acc0, cscale(w, half));
+    acc1 = csub(acc1, cscale(w, half));
+  }
+  {
+    T h = cadd(at(stp, 0), bmul_i(at(stp, 1)));
+    T w = cmul(U[2 * s + 1], h);
+    acc0 = csub(acc0, cscale(w, half));
+    acc1 = cadd(acc1, cscale(bmul_i(w), half));
+  }
+  {
+    T h = csub(at(stm, 0), bmul_i(at(stm, 1)));
+    T w = cmulc(U[2 * stm + 1], h);
+    acc0 = csub(acc0, cscale(w, half));
+    acc1 = csub(acc1, cscale(bmul_i(w), half));
+  }
+  const int64_t o0 = ((int64_t)(2 * s) << lg) + r, o1 = o0 + nb;
+  if (sub) {
+    acc0 = csub(sub[o0], acc0);
+    acc1 = csub(sub[o1], acc1);
+  }
+  out[o0] = acc0;
+  out[o1] = acc1;
+}
+
+template <typename R>
+void launch_b_wilson(hipStream_t s, const cx<R>* U, const cx<R>* in, cx<R>* out, double m0, int Nx, int Nt, int nb,
+                     const cx<R>* sub, const int* skip) {
+  const int64_t N = (int64_t)Nx * Nt * nb;
+  hipLaunchKernelGGL(kb_wilson<R>, dim3((unsigned)((N + BT - 1) / BT)), dim3(BT), 0, s, U, in, out, (R)(m0 + 2.0), Nx,
+                     Nt, nb, sub, skip);
+  DMG_LAUNCH_CHECK();
+}
+
+// Blocked operator on a batched field, one site per workgroup: out(S) = sum_d A_d(S) in(S+d).
+// The five neighbours' 24 x nb values are staged in LDS together when they fit in
+// 64 KB (one round of global loads), else one direction at a time; thread o owns
+// outputs (row i, right-hand side r) = (o / nb, o % nb), o = threadIdx.x + BT k.
+template <typename R>
+__global__ void __launch_bounds__(BT) kb_block(const cx<R>* __restrict__ A, const cx<R>* __restrict__ in,
+                                               cx<R>* __restrict__ out, int Lx, int Lt, int nb,
+                                               const cx<R>* __restrict__ sub, const int* skip) {
+  if (skip && *skip) return;
+  using T = cx<R>;
+  constexpr int OPT = NC * NBMAX / BT;  // most outputs per thread
+  extern __shared__ __align__(16) unsigned char kb_smem[];
+  T* xs = (T*)kb_smem;
+  const int S = blockIdx.x;
+  const int X = S % Lx, Tt = S / Lx;
+  const int tid = threadIdx.x;
+  const int nout = NC * nb;
+  const bool all5 = (size_t)5 * nout * sizeof(T) <= 65536;
+  int nbS[5];
+  nbS[0] = S;
+  nbS[1] = ((X + 1 == Lx) ? 0 : X + 1) + Lx * Tt;
+  nbS[2] = ((X == 0) ? Lx - 1 : X - 1) + Lx * Tt;
+  nbS[3] = X + Lx * ((Tt + 1 == Lt) ? 0 : Tt + 1);
+  nbS[4] = X + Lx * ((Tt == 0) ? Lt - 1 : Tt - 1);
+  double2 acc[OPT];
+#pragma unroll
+  for (int k = 0; k < OPT; ++k) acc[k] = mk(0.0, 0.0);
+  for (int d0 = 0; d0 < 5; d0 += all5 ? 5 : 1) {
+    const int nd = all5 ? 5 : 1;
+    __syncthreads();
+    for (int dd = 0; dd < nd; ++dd)
+      for (int p = tid; p < nout; p += BT) xs[dd * nout + p] = in[(int64_t)nbS[d0 + dd] * nout + p];
+    __syncthreads();
+    for (int dd = 0; dd < nd; ++dd) {
+      const T* a = A + ((int64_t)S * 5 + d0 + dd) * NC * NC;
+      const T* xd = xs + dd * nout;
+#pragma unroll
+      for (int k = 0; k < OPT; ++k) {
+        const int o = tid + BT * k;
+        if (o < nout) {
+          const int i = o / nb, r = o % nb;
+          T sacc = make_cx<R>(R(0), R(0));
+#pragma unroll 8
+          for (int c = 0; c < NC; ++c) cfma(sacc, a[c * NC + i], xd[c * nb + r]);
+          acc[k] = cadd(acc[k], to_d(sacc));
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < OPT; ++k) {
+    const int o = tid + BT * k;
+    if (o < nout) {
+      const int64_t g = (int64_t)S * nout + o;
+      double2 y = acc[k];
+      if (sub) y = csub(to_d(sub[g]), y);
+      out[g] = from_d<R>(y);
+    }
+  }
+}
+
+// FP32 blocked operator on the matrix cores for nb = 16, 32 or 64 right-hand sides.
+// Per site and direction the complex product A_d (24 x 24) X_d (24 x nb) is the real
+// product [[Ar, -Ai], [Ai, Ar]] (48 x 48) [Xr; Xi] (48 x nb), run as 16 x 16 x 4 FP32
+// MFMA tiles: 3 row tiles x nb/16 column tiles x 12 k-steps, accumulated over the
+// five directions in the MFMA registers.  The neighbours' real and imaginary parts are
+// staged in LDS as separate planes; the A operand is read straight from memory (16
+// consecutive rows of one column per lane group).  Tile (m, nt) of the 48 x nb result
+// is owned by wavefront t mod 4 for t = m + 3 nt; results pass through LDS to be
+// written as complex entries (row i: real part row i, imaginary part row 24 + i).
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(BT) kb_block_mfma(const float2* __restrict__ A, const float2* __restrict__ in,
+                                                    float2* __restrict__ out, int Lx, int Lt, int nb,
+                                                    const float2* __restrict__ sub, const int* skip) {
+  if (skip && *skip) return;
+  extern __shared__ __align__(16) unsigned char kb_smem[];
+  float* xre = (float*)kb_smem;            // [5][24][nb]
+  float* xim = xre + 5 * NC * nb;          // [5][24][nb]
+  const int S = blockIdx.x;
+  const int X = S % Lx, Tt = S / Lx;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nout = NC * nb;
+  int nbS[5];
+  nbS[0] = S;
+  nbS[1] = ((X + 1 == Lx) ? 0 : X + 1) + Lx * Tt;
+  nbS[2] = ((X == 0) ? Lx - 1 : X - 1) + Lx * Tt;
+  nbS[3] = X + Lx * ((Tt + 1 == Lt) ? 0 : Tt + 1);
+  nbS[4] = X + Lx * ((Tt == 0) ? Lt - 1 : Tt - 1);
+  for (int d = 0; d < 5; ++d)
+    for (int p = tid; p < nout; p += BT) {
+      const float2 v = in[(int64_t)nbS[d] * nout + p];
+      xre[d * nout + p] = v.x;
+      xim[d * nout + p] = v.y;
+    }
+  __syncthreads();
+  const int NT = nb / 16;
+  const int ntiles = 3 * NT;
+  v4f acc[3];
+#pragma unroll
+  for (int u = 0; u < 3; ++u) acc[u] = v4f{0.f, 0.f, 0.f, 0.f};
+  const int li = lane & 15, lk = lane >> 4;
+  for (int d = 0; d < 5; ++d) {
+    const float2* a = A + ((int64_t)S * 5 + d) * NC * NC;
+    const float* pr = xre + d * nout;
+    const float* pi = xim + d * nout;
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int t = wave + 4 * u;
+      if (t < ntiles) {
+        const int m = t % 3, nt = t / 3;
+        const int I = 16 * m + li;             // row of the 48-row product
+        const int i = I < NC ? I : I - NC;
+        const int j = 16 * nt + li;            // column (right-hand side)
+#pragma unroll
+        for (int kk = 0; kk < 12; ++kk) {
+          const int K = 4 * kk + lk;           // row of [Xr; Xi]
+          const int c = K < NC ? K : K - NC;
+          const float2 av = a[c * NC + i];
+          const float aval = (I < NC) ? (K < NC ? av.x : -av.y) : (K < NC ? av.y : av.x);
+          const float bval = (K < NC) ? pr[c * nb + j] : pi[c * nb + j];
+          acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(aval, bval, acc[u], 0, 0, 0);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // result planes [48][nb] reuse the staging area
+  float* res = xre;
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    const int t = wave + 4 * u;
+    if (t < ntiles) {
+      const int m = t % 3, nt = t / 3;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) res[(16 * m + 4 * lk + v) * nb + 16 * nt + li] = acc[u][v];
+    }
+  }
+  __syncthreads();
+  for (int o = tid; o < nout; o += BT) {
+    const int i = o / nb, r = o % nb;
+    float2 y = make_float2(res[i * nb + r], res[(NC + i) * nb + r]);
+    const int64_t g = (int64_t)S * nout + o;
+    if (sub) y = make_float2(sub[g].x - y.x, sub[g].y - y.y);
+    out[g] = y;
+  }
+}
+
+template <typename R>
+void launch_b_block(hipStream_t s, const cx<R>* A, const cx<R>* in, cx<R>* out, int Lx, int Lt, int nb,
+                    const cx<R>* sub, const int* skip) {
+  if constexpr (sizeof(R) == sizeof(float)) {
+    if (nb >= 16 && b_block_mfma_enabled()) {
+      const size_t lds = (size_t)2 * 5 * NC * nb * sizeof(float);
+      hipLaunchKernelGGL(kb_block_mfma, dim3(Lx * Lt), dim3(BT), lds, s, (const float2*)A, (const float2*)in,
+                         (float2*)out, Lx, Lt, nb, (const float2*)sub, skip);
+      DMG_LAUNCH_CHECK();
+      return;
+    }
+  }
+  const size_t one = (size_t)NC * nb * sizeof(cx<R>);
+  const size_t lds = 5 * one <= 65536 ? 5 * one : one;
+  hipLaunchKernelGGL(kb_block<R>, dim3(Lx * Lt), dim3(BT), lds, s, A, in, out, Lx, Lt, nb, sub, skip);
+  DMG_LAUNCH_CHECK();
+}
+
+// Restriction on batched fields, one workgroup per coarse site (see the single-field kernel).
+template <typename R>
+__global__ void __launch_bounds__(BT) kb_restrict(const cx<R>* __restrict__ P, const cx<R>* __restrict__ fine,
+                                                  cx<R>* __restrict__ coarse, int Lx, int Lt, int dof, int nb) {
+  using T = cx<R>;
+  const int B = blockIdx.x;
+  const int BX = Lx / BLK;
+  const int X = B % BX, Tb = B / BX;
+  const int h = dof / 2;
+  const int nout = NC * nb;
+  for (int o = threadIdx.x; o < nout; o += BT) {
+    const int oo = o / nb, r = o % nb;
+    const int c = oo / NV, k = oo % NV;
+    double2 acc = mk(0.0, 0.0);
+    for (int sl = 0; sl < BLK * BLK; ++sl) {
+      const int s = (BLK * X + sl % BLK) + Lx * (BLK * Tb + sl / BLK);
+      for (int ii = 0; ii < h; ++ii) {
+        const int a = c * h + ii;
+        const int64_t fe = (int64_t)s * dof + a;
+        const T p = P[fe * NV + k];
+        cfmac(acc, to_d(p), to_d(fine[fe * nb + r]));
+      }
+    }
+    coarse[(int64_t)B * nout + o] = from_d<R>(acc);
+  }
+}
+
+template <typename R>
+void launch_b_restrict(hipStream_t s, const cx<R>* P, const cx<R>* fine, cx<R>* coarse, int Lx, int Lt, int dof,
+                       int nb) {
+  const int nbk = (Lx / BLK) * (Lt / BLK);
+  hipLaunchKernelGGL(kb_restrict<R>, dim3(nbk), dim3(BT), 0, s, P, fine, coarse, Lx, Lt, dof, nb);
+  DMG_LAUNCH_CHECK();
+}
+
+template <typename R>
+__global__ void __launch_bounds__(BT) kb_prolong(const cx<R>* __restrict__ P, const cx<R>* __restrict__ coarse,
+                                                 cx<R>* __restrict__ fine, int Lx, int Lt, int dof, int nb,
+                                                 int accumulate) {
+  using T = cx<R>;
+  const int lg = __ffs(nb) - 1;
+  const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
+  const int64_t n = (int64_t)Lx * Lt * dof;
+  if (i >= n * nb) return;
+  const int64_t e = i >> lg;
+  const int r = (int)(i & (nb - 1));
+  const int s = (int)(e / dof), a = (int)(e % dof);
+  const int x = s % Lx, t = s / Lx;
+  const int B = x / BLK + (Lx / BLK) * (t / BLK);
+  const int c = a / (dof / 2);
+  const T* p = P + e * NV;
+  const T* cv = coarse + ((int64_t)B * NC + c * NV) * nb + r;
+  double2 acc = accumulate ? to_d(fine[i]) : mk(0.0, 0.0);
+#pragma unroll
+  for (int k = 0; k < NV; ++k) cfma(acc, to_d(p[k]), to_d(cv[(int64_t)k * nb]));
+  fine[i] = from_d<R>(acc);
+}
+
+template <typename R>
+void launch_b_prolong(hipStream_t s, const cx<R>* P, const cx<R>* coarse, cx<R>* fine, int Lx, int Lt, int dof, int nb,
+                      int accumulate) {
+  const int64_t N = (int64_t)Lx * Lt * dof * nb;
+  hipLaunchKernelGGL(kb_prolong<R>, dim3((unsigned)((N + BT - 1) / BT)), dim3(BT), 0, s, P, coarse, fine, Lx, Lt, dof,
+                     nb, accumulate);
+  DMG_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------- layout changes, flags
+template <typename T>
+__global__ void kb_gather(const T* __restrict__ in, T* __restrict__ out, int64_t n, int nrhs, int nb) {
+  const int lg = __ffs(nb) - 1;
+  const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
+  if (i >= n * nb) return;
+  const int64_t e = i >> lg;
+  const int r = (int)(i & (nb - 1));
+  T z;
+  z.x = 0;
+  z.y = 0;
+  out[i] = (r < nrhs) ? in[(int64_t)r * n + e] : z;
+}
+
+template <typename T>
+__global__ void kb_scatter(const T* __restrict__ in, T* __restrict__ out, int64_t n, int nrhs, int nb) {
+  const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
+  if (i >= n * nrhs) return;
+  const int64_t r = i / n, e = i % n;
+  out[i] = in[e * nb + r];
+}
+
+template <typename T>
+void launch_b_gather(hipStream_t s, const T* in, T* out, int64_t n, int nrhs, int nb) {
+  hipLaunchKernelGGL(kb_gather<T>, dim3((unsigned)((n * nb + BT - 1) / BT)), dim3(BT), 0, s, in, out, n, nrhs, nb);
+  DMG_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_b_scatter(hipStream_t s, const T* in, T* out, int64_t n, int nrhs, int nb) {
+  hipLaunchKernelGGL(kb_scatter<T>, dim3((unsigned)((n * nrhs + BT - 1) / BT)), dim3(BT), 0, s, in, out, n, nrhs, nb);
+  DMG_LAUNCH_CHECK();
+}
+template void launch_b_gather<double2>(hipStream_t, const double2*, double2*, int64_t, int, int);
+template void launch_b_gather<float2>(hipStream_t, const float2*, float2*, int64_t, int, int);
+template void launch_b_scatter<double2>(hipStream_t, const double2*, double2*, int64_t, int, int);
+template void launch_b_scatter<float2>(hipStream_t, const float2*, float2*, int64_t, int, int);
+
+struct StateArg {
+  int v[2 * NBMAX];
+};
+
+__global__ void kb_set_state(BS* bs, StateArg st, int nb) {
+  const int r = threadIdx.x;
+  if (r >= nb) return;
+  bs[r].active = st.v[2 * r];
+  bs[r].cap = st.v[2 * r + 1];
+}
+
+void launch_b_set_state(hipStream_t s, BS* bs, const int* host_st, int nb) {
+  StateArg a;
+  for (int i = 0; i < 2 * nb; ++i) a.v[i] = host_st[i];
+  hipLaunchKernelGGL(kb_set_state, dim3(1), dim3(NBMAX), 0, s, bs, a, nb);
+  DMG_LAUNCH_CHECK();
+}
+
+#define INST(R)                                                                                                        \
+  template void launch_b_norm<R>(hipStream_t, const cx<R>*, int64_t, int, BS*, double, int, double*, int*, double2*,   \
+                                 unsigned*);                                                                           \
+  template void launch_b_scale_beta<R>(hipStream_t, const cx<R>*, cx<R>*, int64_t, int, const BS*);                   \
+  template void launch_b_arnoldi<R>(hipStream_t, cx<R>*, int64_t, int64_t, int, int, BS*, int*, double2*, unsigned*); \
+  template void launch_b_combine<R>(hipStream_t, cx<R>*, const cx<R>*, int64_t, int64_t, int, const BS*, int, int);   \
+  template void launch_b_smooth2<R>(hipStream_t, const cx<R>*, const cx<R>*, const cx<R>*, int64_t, int, double2*,    \
+                                    cx<R>*, cx<R>*, double2*, unsigned*);                                              \
+  template void launch_b_project<R>(hipStream_t, const cx<R>*, int, const double2*, const double2*, cx<R>*, cx<R>*,   \
+                                    int64_t, int, BS*, double2*, unsigned*);                                           \
+  template void launch_b_wilson<R>(hipStream_t, const cx<R>*, const cx<R>*, cx<R>*, double, int, int, int,            \
+                                   const cx<R>*, const int*);                                                          \
+  template void launch_b_block<R>(hipStream_t, const cx<R>*, const cx<R>*, cx<R>*, int, int, int, const cx<R>*,       \
+                                  const int*);                                                                         \
+  template void launch_b_restrict<R>(hipStream_t, const cx<R>*, const cx<R>*, cx<R>*, int, int, int, int);            \
+  template void launch_b_prolong<R>(hipStream_t, const cx<R>*, const cx<R>*, cx<R>*, int, int, int, int, int);
+INST(double)
+INST(float)
+#undef INST
+
+}  // namespace dmg

@@ -1,0 +1,470 @@
+// Lockstep multi-right-hand-side solve: the method of the single-field solver (outer
+// FGMRES with the three-grid cycle, partial intermediate solve, GMRES-Proj coarse
+// solves over a shared deflation space) applied to nb right-hand sides at once.
+// Every right-hand side keeps its own Krylov state and stopping decisions; each
+// launch processes all of them, so a matrix entry is read once per launch for the
+// whole batch and the launch latency of the small coarse grid is shared.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstddef>
+#include <cstring>
+#include <vector>
+
+#include "mrhs.h"
+#include "solver.h"
+
+namespace dmg {
+
+// Krylov basis of one level for nb right-hand sides: V (m + 1 batched fields), Z (m
+// fields when flexible), per right-hand-side state, and the "all done" flag.
+struct BKry {
+  int m = 0;
+  int64_t n = 0;
+  DevBuf V, Z, bs, flag;
+  void alloc(dmg_context* c, hipStream_t s, int m_, int64_t n_, int nb, size_t es, bool flexible) {
+    m = m_;
+    n = n_;
+    const size_t fb = es * (size_t)n * nb;
+    V.alloc(c, fb * (m + 1));
+    DMG_HIP(hipMemsetAsync(V.p, 0, V.bytes, s));
+    if (flexible) {
+      Z.alloc(c, fb * m);
+      DMG_HIP(hipMemsetAsync(Z.p, 0, Z.bytes, s));
+    }
+    bs.alloc(c, sizeof(BS) * nb);
+    DMG_HIP(hipMemsetAsync(bs.p, 0, bs.bytes, s));
+    flag.alloc(c, sizeof(int) * 4);
+    DMG_HIP(hipMemsetAsync(flag.p, 0, flag.bytes, s));
+  }
+  BS* st() const { return bs.as<BS>(); }
+  int* alldone() const { return flag.as<int>(); }
+};
+
+// Shared scratch of one batched solve.
+struct BShared {
+  dmg_context* ctx = nullptr;
+  hipStream_t s = nullptr;
+  int nb = 0;
+  DevBuf part, cnt, coef;
+  BSTail* tail = nullptr;  // pinned, nb entries
+  int* hflag = nullptr;    // pinned
+  ~BShared() {
+    if (tail) (void)hipHostFree(tail);
+    if (hflag) (void)hipHostFree(hflag);
+  }
+  void init(dmg_context* c, hipStream_t st, int nb_) {
+    ctx = c;
+    s = st;
+    nb = nb_;
+    part.alloc(c, sizeof(double2) * bred_partials(nb));
+    cnt.alloc(c, sizeof(unsigned) * 4);
+    DMG_HIP(hipMemsetAsync(cnt.p, 0, cnt.bytes, s));
+    coef.alloc(c, sizeof(double2) * 2 * NBMAX);
+    DMG_HIP(hipHostMalloc((void**)&tail, sizeof(BSTail) * NBMAX, hipHostMallocDefault));
+    DMG_HIP(hipHostMalloc((void**)&hflag, sizeof(int) * 4, hipHostMallocDefault));
+  }
+  double2* P() const { return part.as<double2>(); }
+  unsigned* C() const { return cnt.as<unsigned>(); }
+  // tails of all right-hand sides of a state array (synchronises the stream)
+  void read_tails(const BS* bs) {
+    DMG_HIP(hipMemcpy2DAsync(tail, sizeof(BSTail), (const char*)bs + offsetof(BS, beta), sizeof(BS), sizeof(BSTail),
+                             nb, hipMemcpyDeviceToHost, s));
+    DMG_HIP(hipStreamSynchronize(s));
+  }
+  bool all_done(const int* flag) {
+    DMG_HIP(hipMemcpyAsync(hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    DMG_HIP(hipStreamSynchronize(s));
+    return hflag[0] != 0;
+  }
+  void set_state(BS* bs, const std::vector<int>& act, const std::vector<int>& cap) {
+    std::vector<int> st(2 * nb);
+    for (int r = 0; r < nb; ++r) {
+      st[2 * r] = act[r];
+      st[2 * r + 1] = cap[r];
+    }
+    launch_b_set_state(s, bs, st.data(), nb);
+  }
+};
+
+static_assert(offsetof(BS, pad_) - offsetof(BS, beta) + sizeof(int) == sizeof(BSTail), "BS tail layout");
+
+// The three-grid preconditioner on batched fields in precision R.
+template <typename R>
+struct BPre {
+  using T = cx<R>;
+  dmg_hierarchy* h = nullptr;
+  dmg_deflation* d = nullptr;
+  const dmg_solve_params* p = nullptr;
+  BShared* sh = nullptr;
+  int nb = 0;
+  DevBuf smw[2], y[2], r[2], q[2], sv[2];
+  BKry e1;
+  DevBuf e1r, e1x, bh;
+  DevBuf bc, ec, pr;
+  BKry proj;
+  long long mv[3] = {0, 0, 0};
+
+  hipStream_t S() const { return sh->s; }
+  int64_t N(int l) const { return h->op[l].n; }
+  const T* Pm(int l) const { return (const T*)h->tr[l].P((const T*)nullptr); }
+
+  void alloc(dmg_hierarchy* hh, dmg_deflation* dd, const dmg_solve_params* pp, BShared* s, int nb_) {
+    h = hh;
+    d = dd;
+    p = pp;
+    sh = s;
+    nb = nb_;
+    dmg_context* c = h->ctx;
+    const size_t es = sizeof(T);
+    auto field = [&](DevBuf& b, int l, int count) {
+      b.alloc(c, es * (size_t)N(l) * nb * count);
+      DMG_HIP(hipMemsetAsync(b.p, 0, b.bytes, S()));
+    };
+    for (int l = 0; l < 2; ++l) {
+      field(smw[l], l, 2);
+      field(y[l], l, 1);
+      field(r[l], l, 1);
+      field(q[l], l, 1);
+      field(sv[l], l, 1);
+    }
+    e1.alloc(c, S(), p->int_m, N(1), nb, es, true);
+    field(e1r, 1, 1);
+    field(e1x, 1, 1);
+    field(bh, 1, 1);
+    field(bc, 2, 1);
+    field(ec, 2, 1);
+    field(pr, 2, 1);
+    proj.alloc(c, S(), std::max(d->m - d->kk, 1), N(2), nb, es, false);
+  }
+
+  void apply(int l, const T* in, T* out, const T* sub, const int* skip) {
+    const Op& A = h->op[l];
+    if (A.kind == 0) {
+      const T* U = (const T*)(sizeof(R) == sizeof(double) ? (const void*)A.U64 : (const void*)A.U32);
+      launch_b_wilson<R>(S(), U, in, out, A.m0, A.Lx, A.Lt, nb, sub, skip);
+    } else {
+      const T* Ab = (const T*)(sizeof(R) == sizeof(double) ? (const void*)A.A64 : (const void*)A.A32);
+      launch_b_block<R>(S(), Ab, in, out, A.Lx, A.Lt, nb, sub, skip);
+    }
+  }
+
+  // two-step GMRES smoother from 0 (fused form): y = approximate A^{-1} v, r = v - A y
+  void smooth(int l, const T* v, T* yout, T* rout) {
+    T* w1 = smw[l].as<T>();
+    T* w2 = w1 + N(l) * nb;
+    apply(l, v, w1, nullptr, nullptr);
+    apply(l, w1, w2, nullptr, nullptr);
+    mv[l] += 2;
+    launch_b_smooth2<R>(S(), v, w1, w2, N(l), nb, sh->coef.as<double2>(), yout, rout, sh->P(), sh->C());
+  }
+
+  const T* dvec() const {
+    return (const T*)(sizeof(R) == sizeof(double) ? (const void*)d->V64.p : (const void*)d->V32.p);
+  }
+
+  // GMRES-Proj(m, k) from x = 0 on the coarse grid, one stopping decision per right-hand side
+  void coarse_solve(const T* b, T* x) {
+    const int64_t n = N(2);
+    const int k = d->kk, mm = proj.m;
+    double tol = p->coarse_tol_later;
+    if (sizeof(R) == sizeof(float)) tol = std::max(tol, 1e-5);
+    T* rr = pr.as<T>();
+    T* V = proj.V.as<T>();
+    const int64_t ld = n * nb;
+    BS* bs = proj.st();
+    DMG_HIP(hipMemsetAsync(x, 0, sizeof(T) * ld, S()));
+    DMG_HIP(hipMemcpyAsync(rr, b, sizeof(T) * ld, hipMemcpyDeviceToDevice, S()));
+    std::vector<int> act(nb, 1), cap(nb, mm), it(nb, 0);
+    sh->set_state(bs, act, cap);
+    launch_b_norm<R>(S(), b, n, nb, bs, 0.0, 3, nullptr, nullptr, sh->P(), sh->C());
+    for (;;) {
+      launch_b_project<R>(S(), dvec(), k, d->M.as<double2>(), d->Pi.as<double2>(), x, rr, n, nb, bs, sh->P(), sh->C());
+      launch_b_norm<R>(S(), rr, n, nb, bs, tol, 1, nullptr, proj.alldone(), sh->P(), sh->C());
+      launch_b_scale_beta<R>(S(), rr, V, n, nb, bs);
+      for (int j = 0; j < mm; ++j) {
+        apply(2, V + j * ld, V + (j + 1) * ld, nullptr, proj.alldone());
+        launch_b_arnoldi<R>(S(), V, ld, n, nb, j, bs, proj.alldone(), sh->P(), sh->C());
+      }
+      launch_b_ls_solve(S(), bs, nb);
+      launch_b_combine<R>(S(), x, V, ld, n, nb, bs, 0, 1);
+      launch_b_combine<R>(S(), rr, V, ld, n, nb, bs, 1, 0);
+      sh->read_tails(bs);
+      int most = 0;
+      bool any = false;
+      for (int r = 0; r < nb; ++r) {
+        const BSTail& t = sh->tail[r];
+        if (!act[r]) continue;
+        it[r] += t.steps;
+        most = std::max(most, t.steps);
+        const bool stop = t.est <= t.tol_abs || t.brk || it[r] >= p->coarse_max_iters || t.steps == 0;
+        act[r] = stop ? 0 : 1;
+        any = any || !stop;
+      }
+      mv[2] += most;
+      if (!any) break;
+      sh->set_state(bs, act, cap);
+    }
+  }
+
+  // intermediate cycle M1: smooth, coarse correction, smooth
+  void cycle1(const T* v, T* out) {
+    const int64_t n = N(1);
+    T* y1 = y[1].as<T>();
+    T* r1 = r[1].as<T>();
+    T* q1 = q[1].as<T>();
+    T* s1 = sv[1].as<T>();
+    smooth(1, v, y1, r1);
+    launch_b_restrict<R>(S(), Pm(1), r1, bc.as<T>(), h->tr[1].Lx, h->tr[1].Lt, NC, nb);
+    coarse_solve(bc.as<T>(), ec.as<T>());
+    launch_b_prolong<R>(S(), Pm(1), ec.as<T>(), y1, h->tr[1].Lx, h->tr[1].Lt, NC, nb, 1);
+    apply(1, y1, q1, v, nullptr);  // q = v - D_hat y1
+    mv[1]++;
+    smooth(1, q1, s1, nullptr);
+    launch_axpbyz<R>(S(), n * nb, 1.0, y1, 1.0, s1, out);
+  }
+
+  // partial intermediate solve: FGMRES(int_m) on D_hat with M1 to int_tol ||b|| (per RHS)
+  void partial_solve(const T* b, T* x) {
+    const int64_t n = N(1);
+    const int64_t ld = n * nb;
+    BS* bs = e1.st();
+    T* V = e1.V.as<T>();
+    T* Z = e1.Z.as<T>();
+    DMG_HIP(hipMemsetAsync(x, 0, sizeof(T) * ld, S()));
+    const T* rr = b;
+    std::vector<int> act(nb, 1), cap(nb, std::min(e1.m, p->int_max_iters)), it(nb, 0);
+    bool first = true;
+    for (;;) {
+      sh->set_state(bs, act, cap);
+      launch_b_norm<R>(S(), rr, n, nb, bs, p->int_tol, first ? 2 : 1, nullptr, e1.alldone(), sh->P(), sh->C());
+      launch_b_scale_beta<R>(S(), rr, V, n, nb, bs);
+      first = false;
+      int jmax = 0;
+      for (int r = 0; r < nb; ++r)
+        if (act[r]) jmax = std::max(jmax, cap[r]);
+      for (int j = 0; j < jmax; ++j) {
+        cycle1(V + j * ld, Z + j * ld);
+        apply(1, Z + j * ld, V + (j + 1) * ld, nullptr, e1.alldone());
+        mv[1]++;
+        launch_b_arnoldi<R>(S(), V, ld, n, nb, j, bs, e1.alldone(), sh->P(), sh->C());
+        if (sh->all_done(e1.alldone())) break;
+      }
+      launch_b_ls_solve(S(), bs, nb);
+      launch_b_combine<R>(S(), x, Z, ld, n, nb, bs, 0, 1);
+      sh->read_tails(bs);
+      bool any = false;
+      for (int r = 0; r < nb; ++r) {
+        const BSTail& t = sh->tail[r];
+        if (!act[r]) continue;
+        it[r] += t.steps;
+        const bool stop = t.est <= t.tol_abs || t.brk || it[r] >= p->int_max_iters;
+        act[r] = stop ? 0 : 1;
+        cap[r] = std::min(e1.m, p->int_max_iters - it[r]);
+        any = any || !stop;
+      }
+      if (!any) break;
+      T* res = e1r.as<T>();
+      apply(1, x, res, b, nullptr);
+      mv[1]++;
+      rr = res;
+    }
+  }
+
+  // fine cycle M0: smooth, partial intermediate solve, smooth
+  void cycle0(const T* v, T* out) {
+    const int64_t n = N(0);
+    T* y0 = y[0].as<T>();
+    T* r0 = r[0].as<T>();
+    T* q0 = q[0].as<T>();
+    T* s0 = sv[0].as<T>();
+    smooth(0, v, y0, r0);
+    launch_b_restrict<R>(S(), Pm(0), r0, bh.as<T>(), h->tr[0].Lx, h->tr[0].Lt, 2, nb);
+    partial_solve(bh.as<T>(), e1x.as<T>());
+    launch_b_prolong<R>(S(), Pm(0), e1x.as<T>(), y0, h->tr[0].Lx, h->tr[0].Lt, 2, nb, 1);
+    apply(0, y0, q0, v, nullptr);  // q = v - D y0
+    mv[0]++;
+    smooth(0, q0, s0, nullptr);
+    launch_axpbyz<R>(S(), n * nb, 1.0, y0, 1.0, s0, out);
+  }
+};
+
+struct BWork {
+  int nb = 0, outer_m = 0, int_m = 0, precond = -1, dm = 0, dk = 0;
+  const dmg_deflation* d = nullptr;
+  BShared sh;
+  BKry outer;
+  DevBuf B, X, Rr, v32, z32, rn;
+  BPre<double> pc64;
+  BPre<float> pc32;
+};
+
+void destroy_bwork(BWork* b) {
+  if (b && b->sh.s) (void)hipStreamSynchronize(b->sh.s);
+  delete b;
+}
+
+static BWork* get_bwork(dmg_hierarchy* h, dmg_deflation* d, const dmg_solve_params* p, int nb) {
+  BWork* w = h->bwork;
+  if (w && w->nb == nb && w->outer_m == p->outer_m && w->int_m == p->int_m && w->precond == p->precond && w->d == d &&
+      w->dm == d->m && w->dk == d->kk)
+    return w;
+  destroy_bwork(w);
+  h->bwork = nullptr;
+  dmg_context* c = h->ctx;
+  hipStream_t s = c->stream;
+  w = new BWork();
+  try {
+    w->nb = nb;
+    w->outer_m = p->outer_m;
+    w->int_m = p->int_m;
+    w->precond = p->precond;
+    w->d = d;
+    w->dm = d->m;
+    w->dk = d->kk;
+    w->sh.init(c, s, nb);
+    const int64_t n0 = h->op[0].n;
+    const size_t fb = sizeof(double2) * (size_t)n0 * nb;
+    w->outer.alloc(c, s, p->outer_m, n0, nb, sizeof(double2), true);
+    w->B.alloc(c, fb);
+    w->X.alloc(c, fb);
+    w->Rr.alloc(c, fb);
+    w->rn.alloc(c, sizeof(double) * NBMAX);
+    if (p->precond == DMG_FP32) {
+      w->v32.alloc(c, fb / 2);
+      w->z32.alloc(c, fb / 2);
+      w->pc32.alloc(h, d, p, &w->sh, nb);
+    } else {
+      w->pc64.alloc(h, d, p, &w->sh, nb);
+    }
+  } catch (...) {
+    delete w;
+    throw;
+  }
+  h->bwork = w;
+  return w;
+}
+
+dmg_status batched_solve(dmg_hierarchy* h, dmg_deflation* d, const dmg_solve_params* p, const double2* b, double2* x,
+                         int nrhs, dmg_solve_stats* stout) {
+  auto t0 = std::chrono::steady_clock::now();
+  int nb = 1;
+  while (nb < nrhs) nb *= 2;
+  BWork* w = get_bwork(h, d, p, nb);
+  BShared& sh = w->sh;
+  hipStream_t s = sh.s;
+  const bool fp32 = p->precond == DMG_FP32;
+  // the preconditioner reads the parameters through this pointer during the call
+  w->pc64.p = p;
+  w->pc32.p = p;
+  for (int l = 0; l < 3; ++l) {
+    w->pc64.mv[l] = 0;
+    w->pc32.mv[l] = 0;
+  }
+  const Op& A = h->op[0];
+  const int64_t n = A.n;
+  const int64_t ld = n * nb;
+  double2* B = w->B.as<double2>();
+  double2* X = w->X.as<double2>();
+  double2* Rr = w->Rr.as<double2>();
+  double2* V = w->outer.V.as<double2>();
+  double2* Z = w->outer.Z.as<double2>();
+  BS* bs = w->outer.st();
+  launch_b_gather(s, b, B, n, nrhs, nb);
+  DMG_HIP(hipMemsetAsync(X, 0, sizeof(double2) * ld, s));
+  DMG_HIP(hipMemcpyAsync(Rr, B, sizeof(double2) * ld, hipMemcpyDeviceToDevice, s));
+  std::vector<int> act(nb, 0), cap(nb, 0), it(nb, 0), conv(nb, 0);
+  std::vector<double> rel(nb, 0.0), bn(nb, 0.0);
+  std::vector<long long> mvr(3 * nb, 0);
+  for (int r = 0; r < nrhs; ++r) act[r] = 1;
+  sh.set_state(bs, act, cap);
+  launch_b_norm<double>(s, B, n, nb, bs, 0.0, 3, nullptr, nullptr, sh.P(), sh.C());
+  sh.read_tails(bs);
+  for (int r = 0; r < nb; ++r) {
+    bn[r] = sh.tail[r].bnorm;
+    if (r < nrhs && bn[r] == 0.0) {
+      act[r] = 0;
+      conv[r] = 1;
+    }
+  }
+  long long mv_prev[3] = {0, 0, 0};
+  auto pc_mv = [&](int l) { return fp32 ? w->pc32.mv[l] : w->pc64.mv[l]; };
+  long long mv0 = 0;
+  for (;;) {
+    bool any = false;
+    for (int r = 0; r < nb; ++r) {
+      if (act[r] && it[r] >= p->max_outer_iters) act[r] = 0;
+      cap[r] = act[r] ? std::min(p->outer_m, p->max_outer_iters - it[r]) : 0;
+      any = any || act[r];
+    }
+    if (!any) break;
+    sh.set_state(bs, act, cap);
+    launch_b_norm<double>(s, Rr, n, nb, bs, p->tol, 1, nullptr, w->outer.alldone(), sh.P(), sh.C());
+    launch_b_scale_beta<double>(s, Rr, V, n, nb, bs);
+    long long cyc0 = mv0;
+    for (int j = 0; j < p->outer_m; ++j) {
+      double2* vj = V + j * ld;
+      double2* zj = Z + j * ld;
+      if (fp32) {
+        launch_cast_d2f(s, ld, vj, w->v32.as<float2>());
+        w->pc32.cycle0(w->v32.as<float2>(), w->z32.as<float2>());
+        launch_cast_f2d(s, ld, w->z32.as<float2>(), zj);
+      } else {
+        w->pc64.cycle0(vj, zj);
+      }
+      launch_b_wilson<double>(s, A.U64, zj, V + (j + 1) * ld, A.m0, A.Lx, A.Lt, nb, nullptr, w->outer.alldone());
+      mv0++;
+      launch_b_arnoldi<double>(s, V, ld, n, nb, j, bs, w->outer.alldone(), sh.P(), sh.C());
+      if (sh.all_done(w->outer.alldone())) break;
+    }
+    launch_b_ls_solve(s, bs, nb);
+    launch_b_combine<double>(s, X, Z, ld, n, nb, bs, 0, 1);
+    launch_b_wilson<double>(s, A.U64, X, Rr, A.m0, A.Lx, A.Lt, nb, B, nullptr);  // Rr = B - D X
+    mv0++;
+    launch_b_norm<double>(s, Rr, n, nb, bs, 0.0, 0, w->rn.as<double>(), nullptr, sh.P(), sh.C());
+    std::vector<double> rn(nb);
+    DMG_HIP(hipMemcpyAsync(rn.data(), w->rn.p, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+    sh.read_tails(bs);
+    const long long d0 = mv0 - cyc0;
+    long long dl[3] = {0, 0, 0};
+    for (int l = 1; l < 3; ++l) {
+      dl[l] = pc_mv(l) - mv_prev[l];
+      mv_prev[l] = pc_mv(l);
+    }
+    const long long dpre0 = pc_mv(0) - mv_prev[0];
+    mv_prev[0] = pc_mv(0);
+    for (int r = 0; r < nb; ++r) {
+      if (!act[r]) continue;
+      const BSTail& t = sh.tail[r];
+      it[r] += t.steps;
+      mvr[3 * r + 0] += d0 + dpre0;
+      mvr[3 * r + 1] += dl[1];
+      mvr[3 * r + 2] += dl[2];
+      rel[r] = std::sqrt(rn[r]) / bn[r];
+      conv[r] = rel[r] <= p->tol ? 1 : 0;
+      if (conv[r] || t.steps == 0) act[r] = 0;
+    }
+  }
+  launch_b_scatter(s, X, x, n, nrhs, nb);
+  DMG_HIP(hipStreamSynchronize(s));
+  auto t1 = std::chrono::steady_clock::now();
+  bool all = true;
+  for (int r = 0; r < nrhs; ++r) {
+    all = all && conv[r];
+    if (!stout) continue;
+    dmg_solve_stats& o = stout[r];
+    o = dmg_solve_stats{};
+    o.outer_iters = it[r];
+    o.converged = conv[r];
+    o.fine_mvps = mvr[3 * r];
+    o.int_mvps = mvr[3 * r + 1];
+    o.coarse_mvps = mvr[3 * r + 2];
+    const double n0 = (double)h->op[0].n, n1 = (double)h->op[1].n, n2 = (double)h->op[2].n;
+    o.fine_equiv_mvps = o.fine_mvps + n1 / n0 * o.int_mvps + n2 / n0 * o.coarse_mvps;
+    o.true_rel_resid = rel[r];
+    o.elapsed_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  }
+  return all ? DMG_OK : DMG_W_NOT_CONVERGED;
+}
+
+}  // namespace dmg

@@ -79,6 +79,8 @@ struct Counters {
 };
 
 template <typename R> struct Precond;
+struct BWork;                 // workspace of the lockstep multi-right-hand-side solve
+void destroy_bwork(BWork* b);
 
 // Mutable state of one solve in flight: its stream, reduction scratch, status mirror,
 // Mvp counters and every Krylov workspace.  A hierarchy owns one (for dmg_solve and
@@ -139,6 +141,7 @@ struct dmg_hierarchy {
   dmg::DevBuf A64[3], A32[3], P64[2], P32[2], null[2];
   int setup_iters[2][64] = {};
   dmg::Work main;  // workspace of dmg_solve, the setup and the deflation build (context stream)
+  dmg::BWork* bwork = nullptr;  // workspace of dmg_solve_batched (kept between calls)
   dmg_hierarchy();
   ~dmg_hierarchy();
 };
@@ -166,6 +169,9 @@ dmg_status outer_finish(Work* w, dmg_solve_stats* st);
 void prepare_work(dmg_hierarchy* h, Work* w, dmg_deflation* d, const dmg_solve_params* p);
 // FP32 copy of a ready deflation space (made once, on w's stream, which is synchronised)
 void prepare_deflation_fp32(Work* w, dmg_deflation* d);
+// lockstep solve of nrhs right-hand sides (batched fields in device memory, RHS-major)
+dmg_status batched_solve(dmg_hierarchy* h, dmg_deflation* d, const dmg_solve_params* p, const double2* b, double2* x,
+                         int nrhs, dmg_solve_stats* st);
 void sync_status(Work* w, const KState* ks, KStatus* out);
 
 }  // namespace dmg

@@ -808,4 +808,4 @@ dmg_status outer_solve(dmg_hierarchy* h, Work* w, dmg_deflation* d, const dmg_so
 }  // namespace dmg
 
 dmg_hierarchy::dmg_hierarchy() = default;
-dmg_hierarchy::~dmg_hierarchy() = default;
+dmg_hierarchy::~dmg_hierarchy() { dmg::destroy_bwork(bwork); }

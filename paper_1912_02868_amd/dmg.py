@@ -35,10 +35,10 @@ EXPORTED = [
     "dmg_context_set_budget",
     "dmg_gauge_create", "dmg_gauge_destroy", "dmg_apply_dirac",
     "dmg_setup", "dmg_hierarchy_destroy", "dmg_hierarchy_export", "dmg_hierarchy_part_bytes",
-    "dmg_hierarchy_apply",
+    "dmg_hierarchy_apply", "dmg_hierarchy_apply_batched",
     "dmg_deflation_create", "dmg_deflation_build", "dmg_deflation_reset", "dmg_deflation_ready",
     "dmg_deflation_export", "dmg_deflation_destroy",
-    "dmg_solve_params_default", "dmg_setup_params_default", "dmg_solve",
+    "dmg_solve_params_default", "dmg_setup_params_default", "dmg_solve", "dmg_solve_batched",
     "dmg_kernel_timer", "dmg_kernel_timer_read",
     "dmg_batch_create", "dmg_batch_admit", "dmg_batch_step", "dmg_batch_retire", "dmg_batch_slot_state",
     "dmg_batch_destroy",
@@ -130,6 +130,7 @@ def lib():
         "dmg_hierarchy_export": (i, [vp, i, i, vp, sz]),
         "dmg_hierarchy_part_bytes": (sz, [vp, i, i]),
         "dmg_hierarchy_apply": (i, [vp, i, i, i, vp, vp, i]),
+        "dmg_hierarchy_apply_batched": (i, [vp, i, i, i, vp, vp, i, i, i]),
         "dmg_deflation_create": (i, [vp, i, i, pp]),
         "dmg_deflation_build": (i, [vp, vp, d, i]),
         "dmg_deflation_reset": (None, [vp]),
@@ -139,6 +140,7 @@ def lib():
         "dmg_solve_params_default": (None, [C.POINTER(SolveParams)]),
         "dmg_setup_params_default": (None, [C.POINTER(SetupParams)]),
         "dmg_solve": (i, [vp, vp, vp, C.POINTER(SolveParams), vp, vp, i, i, C.POINTER(SolveStats)]),
+        "dmg_solve_batched": (i, [vp, vp, vp, C.POINTER(SolveParams), vp, vp, i, i, C.POINTER(SolveStats)]),
         "dmg_kernel_timer": (i, [vp, i]),
         "dmg_batch_create": (i, [vp, i, C.POINTER(SolveParams), pp]),
         "dmg_batch_admit": (i, [vp, i, vp, vp, vp, i]),
@@ -324,6 +326,15 @@ class Hierarchy:
         self.ctx.check(lib().dmg_hierarchy_apply(self.h, level, op, prec, pin, pout, kind), "hierarchy_apply")
         return out
 
+    def apply_batched(self, level: int, op: int, x, out, nrhs: int, mfma: bool = True):
+        """The multi-right-hand-side kernels on nrhs consecutive fields."""
+        prec = FP32 if str(getattr(x, "dtype", "")).endswith("complex64") else FP64
+        pin, kind = _ptr(x)
+        pout, _ = _ptr(out)
+        self.ctx.check(lib().dmg_hierarchy_apply_batched(self.h, level, op, prec, pin, pout, nrhs, kind,
+                                                         1 if mfma else 0), "hierarchy_apply_batched")
+        return out
+
     def close(self):
         if self.h:
             lib().dmg_hierarchy_destroy(self.h)
@@ -373,6 +384,19 @@ class Deflation:
             self.close()
         except Exception:
             pass
+
+
+def solve_batched(ctx: Context, hier: Hierarchy, defl, b, x, nrhs: int, params: SolveParams | None = None):
+    """Solve D x = b for nrhs right-hand sides jointly (lockstep); returns (status, [stats dicts])."""
+    prm = params or solve_params()
+    pb, kb = _ptr(b)
+    px, kx = _ptr(x)
+    assert kb == kx
+    stats = (SolveStats * nrhs)()
+    st = lib().dmg_solve_batched(ctx.h, hier.h, defl.h if defl is not None else None, C.byref(prm), pb, px, nrhs,
+                                 kb, stats)
+    ctx.check(st, "solve_batched")
+    return st, [s.as_dict() for s in stats]
 
 
 def solve(ctx: Context, hier: Hierarchy, defl, b, x, nrhs: int = 1, params: SolveParams | None = None):
