@@ -260,12 +260,48 @@ dmg_status dmg_solve_batched(dmg_context* ctx, dmg_hierarchy* h, dmg_deflation* 
                              const void* b, void* x, int nrhs, int ptr_kind, dmg_solve_stats* stats);
 
 /* ---------------------------------------------------------------------------
- * Batch: continuous batching of independent solves (serving form).
+ * Batch: iteration-level continuous batching on one hierarchy (serving form).
  *
- * A batch owns `capacity` slots.  Each slot has its own device stream, host worker
+ * The slots of a batch are the lanes of dmg_solve_batched's lockstep engine: a
+ * request joins a free slot between outer FGMRES(outer_m) cycles (x starts at 0),
+ * every step runs whole cycles of all running slots in one set of multi-RHS
+ * launches, and a slot leaves when its true relative residual reaches tol or it hit
+ * max_outer_iters.  A slot's arithmetic depends only on its own data and on the
+ * batch's lane count (capacity rounded up to a power of two), so a request gets the
+ * same result alone or in any mix on batches of equal capacity.  The deflation space
+ * must be READY and is only read.
+ *
+ *   admit(slot, b)        FREE -> RUNNING (DONE at once for b = 0)
+ *   step(min_iters)       ceil(min_iters / outer_m) lockstep cycles; finished -> DONE
+ *   retire(slot, x)       DONE -> FREE, returns the solution and its statistics
+ * ------------------------------------------------------------------------- */
+typedef struct dmg_batch dmg_batch;
+#define DMG_BATCH_MAX_LANES 64
+enum { DMG_SLOT_FREE = 0, DMG_SLOT_RUNNING = 1, DMG_SLOT_DONE = 2 };
+
+/* capacity in [1, 64]; parameter limits as dmg_solve_batched.  Errors: DMG_E_INVALID,
+ * DMG_E_BUDGET / DMG_E_NOMEM (workspace). */
+dmg_status dmg_batch_create(dmg_hierarchy* h, dmg_deflation* d, int capacity, const dmg_solve_params* prm,
+                            dmg_batch** out);
+/* b: one fine field (host or device by ptr_kind).  DMG_E_INVALID if the slot is not
+ * FREE; DMG_E_NONFINITE for a non-finite host b. */
+dmg_status dmg_batch_admit(dmg_batch* bt, int slot, const void* b, int ptr_kind);
+/* n_done (may be NULL): slots now DONE. */
+dmg_status dmg_batch_step(dmg_batch* bt, int min_iters, int* n_done);
+/* x: one fine field (host or device); stats may be NULL (elapsed_ms from admission).
+ * Returns DMG_OK or DMG_W_NOT_CONVERGED; DMG_E_INVALID if the slot is not DONE. */
+dmg_status dmg_batch_retire(dmg_batch* bt, int slot, void* x, int ptr_kind, dmg_solve_stats* stats);
+/* DMG_SLOT_* of a slot, or -1 for a bad index. */
+int dmg_batch_slot_state(dmg_batch* bt, int slot);
+void dmg_batch_destroy(dmg_batch* bt);
+
+/* ---------------------------------------------------------------------------
+ * Pool: independent solves of any resident hierarchy, overlapped on the device.
+ *
+ * A pool owns `capacity` slots.  Each slot has its own device stream, host worker
  * thread and solver workspace, so the solves of different slots overlap on the
  * device.  A slot takes one right-hand side of any hierarchy of the batch's context
- * (different configurations and lattice sizes may share a batch); slots join and
+ * (different configurations and lattice sizes may share a pool); slots join and
  * leave between steps:
  *
  *   admit(slot, h, d, b)  -> slot RUNNING        (FREE slots only)
@@ -277,48 +313,46 @@ dmg_status dmg_solve_batched(dmg_context* ctx, dmg_hierarchy* h, dmg_deflation* 
  *                            and their slots refilled while long ones run.
  *   retire(slot, x)       -> DONE slot returns its solution and becomes FREE
  *
- * The calls on one batch come from one host thread.
+ * The calls on one pool come from one host thread.
  * The outer FGMRES cycles are never cut, so a solve performs the same arithmetic
- * whatever the step sizes and whichever other solves share the batch; the result
+ * whatever the step sizes and whichever other solves share the pool; the result
  * is bitwise that of dmg_solve with the same parameters and deflation state.
  * The deflation space of an admitted solve must be READY (dmg_deflation_build, or
  * an earlier dmg_solve) and is only read, so results do not depend on arrival
  * order; d == NULL selects the non-deflated method.  A hierarchy and its deflation
  * space must outlive the slots that use them and must not be rebuilt or reset
- * while admitted.  Persistent coarse solves in a batch are launched cooperatively
+ * while admitted.  Persistent coarse solves in a pool are launched cooperatively
  * (coarse_persistent 2 is taken as 1): the runtime then places the whole grid at
  * once, while a plain-launched grid could wait behind the other slots' kernels for
- * its last workgroups.  At most DMG_BATCH_MAX_SLOTS slots.
+ * its last workgroups.  At most DMG_POOL_MAX_SLOTS slots.
  * ------------------------------------------------------------------------- */
-typedef struct dmg_batch dmg_batch;
-#define DMG_BATCH_MAX_SLOTS 8
+typedef struct dmg_pool dmg_pool;
+#define DMG_POOL_MAX_SLOTS 8
 
-enum { DMG_SLOT_FREE = 0, DMG_SLOT_RUNNING = 1, DMG_SLOT_DONE = 2 };
-
-/* prm: solve parameters of every slot (NULL: defaults).  Errors: DMG_E_INVALID (capacity outside [1, DMG_BATCH_MAX_SLOTS], bad
+/* prm: solve parameters of every slot (NULL: defaults).  Errors: DMG_E_INVALID (capacity outside [1, DMG_POOL_MAX_SLOTS], bad
  * parameters), DMG_E_HIP (stream creation). */
-dmg_status dmg_batch_create(dmg_context* ctx, int capacity, const dmg_solve_params* prm, dmg_batch** out);
+dmg_status dmg_pool_create(dmg_context* ctx, int capacity, const dmg_solve_params* prm, dmg_pool** out);
 /* Copies b (one fine field of h, host or device by ptr_kind) into the slot and
  * allocates the slot's workspace for h (DMG_E_BUDGET past the context's HBM
  * budget: the request is not admitted and the slot stays FREE).  DMG_E_INVALID if
  * the slot is not FREE, h belongs to another context, or d is not READY. */
-dmg_status dmg_batch_admit(dmg_batch* bt, int slot, dmg_hierarchy* h, dmg_deflation* d, const void* b,
+dmg_status dmg_pool_admit(dmg_pool* bt, int slot, dmg_hierarchy* h, dmg_deflation* d, const void* b,
                            int ptr_kind);
 /* Starts an advance on every idle RUNNING slot as described above and waits until
  * one advance (of any slot) has ended; returns at once if none is in flight.
  * n_done (may be NULL): slots now DONE.  A solve that fails becomes DONE with its
  * error, reported by retire; step itself fails only on invalid arguments. */
-dmg_status dmg_batch_step(dmg_batch* bt, int min_iters, int* n_done);
+dmg_status dmg_pool_step(dmg_pool* bt, int min_iters, int* n_done);
 /* Copies the slot's solution to x (host or device by ptr_kind), fills stats (may be
  * NULL; elapsed_ms runs from admission) and frees the slot.  Returns the solve's
  * status (DMG_OK, DMG_W_NOT_CONVERGED or its error; dmg_last_error has the text).
  * DMG_E_INVALID if the slot is not DONE. */
-dmg_status dmg_batch_retire(dmg_batch* bt, int slot, void* x, int ptr_kind, dmg_solve_stats* stats);
+dmg_status dmg_pool_retire(dmg_pool* bt, int slot, void* x, int ptr_kind, dmg_solve_stats* stats);
 /* DMG_SLOT_* of a slot, or -1 for a bad slot index. */
-int dmg_batch_slot_state(dmg_batch* bt, int slot);
+int dmg_pool_slot_state(dmg_pool* bt, int slot);
 /* Waits for advances in flight, the slots' streams and threads, then releases
  * everything; tolerates NULL. */
-void dmg_batch_destroy(dmg_batch* bt);
+void dmg_pool_destroy(dmg_pool* bt);
 
 #ifdef __cplusplus
 }

@@ -93,6 +93,10 @@ template <typename T>
 void launch_b_gather(hipStream_t s, const T* in, T* out, int64_t n, int nrhs, int nb);
 template <typename T>
 void launch_b_scatter(hipStream_t s, const T* in, T* out, int64_t n, int nrhs, int nb);
+// lane r of a batched field: dst lane = src lane (src null: zero)
+void launch_b_lane_copy(hipStream_t s, const double2* src, double2* dst, int64_t n, int nb, int r);
+// to_lane = 1: lane r of out = single field in; 0: single field out = lane r of in
+void launch_b_lane_io(hipStream_t s, const double2* in, double2* out, int64_t n, int nb, int r, int to_lane);
 // per right-hand-side flags for the next cycle: bs[r].active = st[2r], bs[r].cap = st[2r+1]
 void launch_b_set_state(hipStream_t s, BS* bs, const int* st, int nb);
 

@@ -950,6 +950,32 @@ template void launch_b_gather<float2>(hipStream_t, const float2*, float2*, int64
 template void launch_b_scatter<double2>(hipStream_t, const double2*, double2*, int64_t, int, int);
 template void launch_b_scatter<float2>(hipStream_t, const float2*, float2*, int64_t, int, int);
 
+// lane r of a batched field: dst[e][r] = src ? src[e][r] (batched) : 0
+__global__ void kb_lane_copy(const double2* __restrict__ src, double2* __restrict__ dst, int64_t n, int nb, int r) {
+  const int64_t e = (int64_t)blockIdx.x * BT + threadIdx.x;
+  if (e >= n) return;
+  dst[e * nb + r] = src ? src[e * nb + r] : mk(0.0, 0.0);
+}
+
+void launch_b_lane_copy(hipStream_t s, const double2* src, double2* dst, int64_t n, int nb, int r) {
+  hipLaunchKernelGGL(kb_lane_copy, dim3((unsigned)((n + BT - 1) / BT)), dim3(BT), 0, s, src, dst, n, nb, r);
+  DMG_LAUNCH_CHECK();
+}
+
+// single field <-> lane r of a batched field
+__global__ void kb_lane_io(const double2* __restrict__ in, double2* __restrict__ out, int64_t n, int nb, int r,
+                           int to_lane) {
+  const int64_t e = (int64_t)blockIdx.x * BT + threadIdx.x;
+  if (e >= n) return;
+  if (to_lane) out[e * nb + r] = in[e];
+  else out[e] = in[e * nb + r];
+}
+
+void launch_b_lane_io(hipStream_t s, const double2* in, double2* out, int64_t n, int nb, int r, int to_lane) {
+  hipLaunchKernelGGL(kb_lane_io, dim3((unsigned)((n + BT - 1) / BT)), dim3(BT), 0, s, in, out, n, nb, r, to_lane);
+  DMG_LAUNCH_CHECK();
+}
+
 struct StateArg {
   int v[2 * NBMAX];
 };

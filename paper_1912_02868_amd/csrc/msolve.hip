@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstddef>
 #include <cstring>
+#include <memory>
 #include <vector>
 
 #include "mrhs.h"
@@ -289,14 +290,37 @@ struct BPre {
   }
 };
 
+// Lane engine: nb interleaved right-hand sides ("lanes") advanced by lockstep outer
+// FGMRES cycles.  A lane joins between cycles (its x starts at 0, its residual at b)
+// and leaves when it converged or reached its iteration cap; a lane's arithmetic
+// depends only on its own data and on nb, never on the other lanes.
 struct BWork {
+  dmg_hierarchy* h = nullptr;
   int nb = 0, outer_m = 0, int_m = 0, precond = -1, dm = 0, dk = 0;
   const dmg_deflation* d = nullptr;
+  dmg_solve_params p{};
   BShared sh;
   BKry outer;
   DevBuf B, X, Rr, v32, z32, rn;
   BPre<double> pc64;
   BPre<float> pc32;
+  // per-lane host state
+  std::vector<int> act, it, conv;
+  std::vector<double> rel, bn;
+  std::vector<long long> mvr;
+  std::vector<std::chrono::steady_clock::time_point> t_in;
+  long long mv_prev[3] = {0, 0, 0};
+
+  void init(dmg_hierarchy* hh, dmg_deflation* dd, const dmg_solve_params* pp, int nb_);
+  void reset_lanes();
+  void start_lanes(const std::vector<int>& lanes);  // B lanes hold the right-hand sides
+  void cycle();                                     // one outer cycle of every active lane
+  bool any_active() const {
+    for (int r = 0; r < nb; ++r)
+      if (act[r]) return true;
+    return false;
+  }
+  void stats(int r, dmg_solve_stats* o, std::chrono::steady_clock::time_point now) const;
 };
 
 void destroy_bwork(BWork* b) {
@@ -304,167 +328,335 @@ void destroy_bwork(BWork* b) {
   delete b;
 }
 
-static BWork* get_bwork(dmg_hierarchy* h, dmg_deflation* d, const dmg_solve_params* p, int nb) {
-  BWork* w = h->bwork;
-  if (w && w->nb == nb && w->outer_m == p->outer_m && w->int_m == p->int_m && w->precond == p->precond && w->d == d &&
-      w->dm == d->m && w->dk == d->kk)
-    return w;
-  destroy_bwork(w);
-  h->bwork = nullptr;
+void BWork::init(dmg_hierarchy* hh, dmg_deflation* dd, const dmg_solve_params* pp, int nb_) {
+  h = hh;
+  d = dd;
+  p = *pp;
+  nb = nb_;
+  outer_m = p.outer_m;
+  int_m = p.int_m;
+  precond = p.precond;
+  dm = dd->m;
+  dk = dd->kk;
   dmg_context* c = h->ctx;
   hipStream_t s = c->stream;
-  w = new BWork();
-  try {
-    w->nb = nb;
-    w->outer_m = p->outer_m;
-    w->int_m = p->int_m;
-    w->precond = p->precond;
-    w->d = d;
-    w->dm = d->m;
-    w->dk = d->kk;
-    w->sh.init(c, s, nb);
-    const int64_t n0 = h->op[0].n;
-    const size_t fb = sizeof(double2) * (size_t)n0 * nb;
-    w->outer.alloc(c, s, p->outer_m, n0, nb, sizeof(double2), true);
-    w->B.alloc(c, fb);
-    w->X.alloc(c, fb);
-    w->Rr.alloc(c, fb);
-    w->rn.alloc(c, sizeof(double) * NBMAX);
-    if (p->precond == DMG_FP32) {
-      w->v32.alloc(c, fb / 2);
-      w->z32.alloc(c, fb / 2);
-      w->pc32.alloc(h, d, p, &w->sh, nb);
+  sh.init(c, s, nb);
+  const int64_t n0 = h->op[0].n;
+  const size_t fb = sizeof(double2) * (size_t)n0 * nb;
+  outer.alloc(c, s, p.outer_m, n0, nb, sizeof(double2), true);
+  B.alloc(c, fb);
+  X.alloc(c, fb);
+  Rr.alloc(c, fb);
+  for (DevBuf* b : {&B, &X, &Rr}) DMG_HIP(hipMemsetAsync(b->p, 0, b->bytes, s));
+  rn.alloc(c, sizeof(double) * NBMAX);
+  if (p.precond == DMG_FP32) {
+    v32.alloc(c, fb / 2);
+    z32.alloc(c, fb / 2);
+    pc32.alloc(h, dd, &p, &sh, nb);
+  } else {
+    pc64.alloc(h, dd, &p, &sh, nb);
+  }
+  reset_lanes();
+}
+
+void BWork::reset_lanes() {
+  act.assign(nb, 0);
+  it.assign(nb, 0);
+  conv.assign(nb, 0);
+  rel.assign(nb, 0.0);
+  bn.assign(nb, 0.0);
+  mvr.assign(3 * nb, 0);
+  t_in.assign(nb, std::chrono::steady_clock::now());
+}
+
+void BWork::start_lanes(const std::vector<int>& lanes) {
+  hipStream_t s = sh.s;
+  const int64_t n = h->op[0].n;
+  BS* bs = outer.st();
+  // ||b|| of every lane (the other lanes' values are recomputed unchanged)
+  launch_b_norm<double>(s, B.as<double2>(), n, nb, bs, 0.0, 3, nullptr, nullptr, sh.P(), sh.C());
+  for (int r : lanes) {
+    launch_b_lane_copy(s, B.as<double2>(), Rr.as<double2>(), n, nb, r);
+    launch_b_lane_copy(s, (const double2*)nullptr, X.as<double2>(), n, nb, r);
+  }
+  sh.read_tails(bs);
+  const auto now = std::chrono::steady_clock::now();
+  for (int r : lanes) {
+    bn[r] = sh.tail[r].bnorm;
+    it[r] = 0;
+    rel[r] = bn[r] > 0.0 ? 1.0 : 0.0;
+    conv[r] = bn[r] == 0.0 ? 1 : 0;
+    act[r] = bn[r] > 0.0 ? 1 : 0;
+    for (int l = 0; l < 3; ++l) mvr[3 * r + l] = 0;
+    t_in[r] = now;
+  }
+}
+
+void BWork::cycle() {
+  hipStream_t s = sh.s;
+  const bool fp32 = precond == DMG_FP32;
+  const Op& A = h->op[0];
+  const int64_t n = A.n;
+  const int64_t ld = n * nb;
+  double2* Bp = B.as<double2>();
+  double2* Xp = X.as<double2>();
+  double2* Rp = Rr.as<double2>();
+  double2* V = outer.V.as<double2>();
+  double2* Z = outer.Z.as<double2>();
+  BS* bs = outer.st();
+  auto pc_mv = [&](int l) { return fp32 ? pc32.mv[l] : pc64.mv[l]; };
+  std::vector<int> cap(nb, 0);
+  for (int r = 0; r < nb; ++r) {
+    if (act[r] && it[r] >= p.max_outer_iters) act[r] = 0;
+    cap[r] = act[r] ? std::min(p.outer_m, p.max_outer_iters - it[r]) : 0;
+  }
+  sh.set_state(bs, act, cap);
+  launch_b_norm<double>(s, Rp, n, nb, bs, p.tol, 1, nullptr, outer.alldone(), sh.P(), sh.C());
+  launch_b_scale_beta<double>(s, Rp, V, n, nb, bs);
+  long long fine = 0;
+  for (int j = 0; j < p.outer_m; ++j) {
+    double2* vj = V + j * ld;
+    double2* zj = Z + j * ld;
+    if (fp32) {
+      launch_cast_d2f(s, ld, vj, v32.as<float2>());
+      pc32.cycle0(v32.as<float2>(), z32.as<float2>());
+      launch_cast_f2d(s, ld, z32.as<float2>(), zj);
     } else {
-      w->pc64.alloc(h, d, p, &w->sh, nb);
+      pc64.cycle0(vj, zj);
     }
+    launch_b_wilson<double>(s, A.U64, zj, V + (j + 1) * ld, A.m0, A.Lx, A.Lt, nb, nullptr, outer.alldone());
+    fine++;
+    launch_b_arnoldi<double>(s, V, ld, n, nb, j, bs, outer.alldone(), sh.P(), sh.C());
+    if (sh.all_done(outer.alldone())) break;
+  }
+  launch_b_ls_solve(s, bs, nb);
+  launch_b_combine<double>(s, Xp, Z, ld, n, nb, bs, 0, 1);
+  launch_b_wilson<double>(s, A.U64, Xp, Rp, A.m0, A.Lx, A.Lt, nb, Bp, nullptr);  // Rr = B - D X
+  fine++;
+  launch_b_norm<double>(s, Rp, n, nb, bs, 0.0, 0, rn.as<double>(), nullptr, sh.P(), sh.C());
+  std::vector<double> rnh(nb);
+  DMG_HIP(hipMemcpyAsync(rnh.data(), rn.p, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+  sh.read_tails(bs);
+  long long dl[3];
+  for (int l = 0; l < 3; ++l) {
+    dl[l] = pc_mv(l) - mv_prev[l];
+    mv_prev[l] = pc_mv(l);
+  }
+  dl[0] += fine;
+  for (int r = 0; r < nb; ++r) {
+    if (!act[r]) continue;
+    const BSTail& t = sh.tail[r];
+    it[r] += t.steps;
+    for (int l = 0; l < 3; ++l) mvr[3 * r + l] += dl[l];
+    rel[r] = std::sqrt(rnh[r]) / bn[r];
+    conv[r] = rel[r] <= p.tol ? 1 : 0;
+    if (conv[r] || t.steps == 0 || it[r] >= p.max_outer_iters) act[r] = 0;
+  }
+}
+
+void BWork::stats(int r, dmg_solve_stats* o, std::chrono::steady_clock::time_point now) const {
+  *o = dmg_solve_stats{};
+  o->outer_iters = it[r];
+  o->converged = conv[r];
+  o->fine_mvps = mvr[3 * r];
+  o->int_mvps = mvr[3 * r + 1];
+  o->coarse_mvps = mvr[3 * r + 2];
+  const double n0 = (double)h->op[0].n, n1 = (double)h->op[1].n, n2 = (double)h->op[2].n;
+  o->fine_equiv_mvps = o->fine_mvps + n1 / n0 * o->int_mvps + n2 / n0 * o->coarse_mvps;
+  o->true_rel_resid = rel[r];
+  o->elapsed_ms = std::chrono::duration<double, std::milli>(now - t_in[r]).count();
+}
+
+BWork* create_bwork(dmg_hierarchy* h, dmg_deflation* d, const dmg_solve_params* p, int nb) {
+  BWork* w = new BWork();
+  try {
+    w->init(h, d, p, nb);
   } catch (...) {
     delete w;
     throw;
   }
-  h->bwork = w;
   return w;
+}
+
+static BWork* get_bwork(dmg_hierarchy* h, dmg_deflation* d, const dmg_solve_params* p, int nb) {
+  BWork* w = h->bwork;
+  if (w && w->nb == nb && w->outer_m == p->outer_m && w->int_m == p->int_m && w->precond == p->precond && w->d == d &&
+      w->dm == d->m && w->dk == d->kk) {
+    w->p = *p;
+    w->reset_lanes();
+    return w;
+  }
+  destroy_bwork(w);
+  h->bwork = nullptr;
+  h->bwork = create_bwork(h, d, p, nb);
+  return h->bwork;
 }
 
 dmg_status batched_solve(dmg_hierarchy* h, dmg_deflation* d, const dmg_solve_params* p, const double2* b, double2* x,
                          int nrhs, dmg_solve_stats* stout) {
-  auto t0 = std::chrono::steady_clock::now();
   int nb = 1;
   while (nb < nrhs) nb *= 2;
   BWork* w = get_bwork(h, d, p, nb);
-  BShared& sh = w->sh;
-  hipStream_t s = sh.s;
-  const bool fp32 = p->precond == DMG_FP32;
-  // the preconditioner reads the parameters through this pointer during the call
-  w->pc64.p = p;
-  w->pc32.p = p;
-  for (int l = 0; l < 3; ++l) {
-    w->pc64.mv[l] = 0;
-    w->pc32.mv[l] = 0;
-  }
-  const Op& A = h->op[0];
-  const int64_t n = A.n;
-  const int64_t ld = n * nb;
-  double2* B = w->B.as<double2>();
-  double2* X = w->X.as<double2>();
-  double2* Rr = w->Rr.as<double2>();
-  double2* V = w->outer.V.as<double2>();
-  double2* Z = w->outer.Z.as<double2>();
-  BS* bs = w->outer.st();
-  launch_b_gather(s, b, B, n, nrhs, nb);
-  DMG_HIP(hipMemsetAsync(X, 0, sizeof(double2) * ld, s));
-  DMG_HIP(hipMemcpyAsync(Rr, B, sizeof(double2) * ld, hipMemcpyDeviceToDevice, s));
-  std::vector<int> act(nb, 0), cap(nb, 0), it(nb, 0), conv(nb, 0);
-  std::vector<double> rel(nb, 0.0), bn(nb, 0.0);
-  std::vector<long long> mvr(3 * nb, 0);
-  for (int r = 0; r < nrhs; ++r) act[r] = 1;
-  sh.set_state(bs, act, cap);
-  launch_b_norm<double>(s, B, n, nb, bs, 0.0, 3, nullptr, nullptr, sh.P(), sh.C());
-  sh.read_tails(bs);
-  for (int r = 0; r < nb; ++r) {
-    bn[r] = sh.tail[r].bnorm;
-    if (r < nrhs && bn[r] == 0.0) {
-      act[r] = 0;
-      conv[r] = 1;
-    }
-  }
-  long long mv_prev[3] = {0, 0, 0};
-  auto pc_mv = [&](int l) { return fp32 ? w->pc32.mv[l] : w->pc64.mv[l]; };
-  long long mv0 = 0;
-  for (;;) {
-    bool any = false;
-    for (int r = 0; r < nb; ++r) {
-      if (act[r] && it[r] >= p->max_outer_iters) act[r] = 0;
-      cap[r] = act[r] ? std::min(p->outer_m, p->max_outer_iters - it[r]) : 0;
-      any = any || act[r];
-    }
-    if (!any) break;
-    sh.set_state(bs, act, cap);
-    launch_b_norm<double>(s, Rr, n, nb, bs, p->tol, 1, nullptr, w->outer.alldone(), sh.P(), sh.C());
-    launch_b_scale_beta<double>(s, Rr, V, n, nb, bs);
-    long long cyc0 = mv0;
-    for (int j = 0; j < p->outer_m; ++j) {
-      double2* vj = V + j * ld;
-      double2* zj = Z + j * ld;
-      if (fp32) {
-        launch_cast_d2f(s, ld, vj, w->v32.as<float2>());
-        w->pc32.cycle0(w->v32.as<float2>(), w->z32.as<float2>());
-        launch_cast_f2d(s, ld, w->z32.as<float2>(), zj);
-      } else {
-        w->pc64.cycle0(vj, zj);
-      }
-      launch_b_wilson<double>(s, A.U64, zj, V + (j + 1) * ld, A.m0, A.Lx, A.Lt, nb, nullptr, w->outer.alldone());
-      mv0++;
-      launch_b_arnoldi<double>(s, V, ld, n, nb, j, bs, w->outer.alldone(), sh.P(), sh.C());
-      if (sh.all_done(w->outer.alldone())) break;
-    }
-    launch_b_ls_solve(s, bs, nb);
-    launch_b_combine<double>(s, X, Z, ld, n, nb, bs, 0, 1);
-    launch_b_wilson<double>(s, A.U64, X, Rr, A.m0, A.Lx, A.Lt, nb, B, nullptr);  // Rr = B - D X
-    mv0++;
-    launch_b_norm<double>(s, Rr, n, nb, bs, 0.0, 0, w->rn.as<double>(), nullptr, sh.P(), sh.C());
-    std::vector<double> rn(nb);
-    DMG_HIP(hipMemcpyAsync(rn.data(), w->rn.p, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
-    sh.read_tails(bs);
-    const long long d0 = mv0 - cyc0;
-    long long dl[3] = {0, 0, 0};
-    for (int l = 1; l < 3; ++l) {
-      dl[l] = pc_mv(l) - mv_prev[l];
-      mv_prev[l] = pc_mv(l);
-    }
-    const long long dpre0 = pc_mv(0) - mv_prev[0];
-    mv_prev[0] = pc_mv(0);
-    for (int r = 0; r < nb; ++r) {
-      if (!act[r]) continue;
-      const BSTail& t = sh.tail[r];
-      it[r] += t.steps;
-      mvr[3 * r + 0] += d0 + dpre0;
-      mvr[3 * r + 1] += dl[1];
-      mvr[3 * r + 2] += dl[2];
-      rel[r] = std::sqrt(rn[r]) / bn[r];
-      conv[r] = rel[r] <= p->tol ? 1 : 0;
-      if (conv[r] || t.steps == 0) act[r] = 0;
-    }
-  }
-  launch_b_scatter(s, X, x, n, nrhs, nb);
+  hipStream_t s = w->sh.s;
+  const int64_t n = h->op[0].n;
+  launch_b_gather(s, b, w->B.as<double2>(), n, nrhs, nb);
+  std::vector<int> lanes(nrhs);
+  for (int r = 0; r < nrhs; ++r) lanes[r] = r;
+  w->start_lanes(lanes);
+  while (w->any_active()) w->cycle();
+  launch_b_scatter(s, w->X.as<double2>(), x, n, nrhs, nb);
   DMG_HIP(hipStreamSynchronize(s));
-  auto t1 = std::chrono::steady_clock::now();
+  const auto now = std::chrono::steady_clock::now();
   bool all = true;
   for (int r = 0; r < nrhs; ++r) {
-    all = all && conv[r];
-    if (!stout) continue;
-    dmg_solve_stats& o = stout[r];
-    o = dmg_solve_stats{};
-    o.outer_iters = it[r];
-    o.converged = conv[r];
-    o.fine_mvps = mvr[3 * r];
-    o.int_mvps = mvr[3 * r + 1];
-    o.coarse_mvps = mvr[3 * r + 2];
-    const double n0 = (double)h->op[0].n, n1 = (double)h->op[1].n, n2 = (double)h->op[2].n;
-    o.fine_equiv_mvps = o.fine_mvps + n1 / n0 * o.int_mvps + n2 / n0 * o.coarse_mvps;
-    o.true_rel_resid = rel[r];
-    o.elapsed_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    all = all && w->conv[r];
+    if (stout) w->stats(r, stout + r, now);
   }
   return all ? DMG_OK : DMG_W_NOT_CONVERGED;
 }
 
 }  // namespace dmg
+
+// ---------------------------------------------------------------- continuous batching (dmg_batch_*)
+// The lanes of the engine are slots that requests join and leave between outer cycles.
+using namespace dmg;
+
+struct dmg_batch {
+  dmg_hierarchy* h = nullptr;
+  dmg_deflation* d = nullptr;
+  int cap = 0;
+  BWork* w = nullptr;
+  std::vector<int> state;
+  ~dmg_batch() { destroy_bwork(w); }
+};
+
+namespace {
+
+template <typename F>
+dmg_status guarded(dmg_context* c, F&& f) {
+  try {
+    if (c) c->err.clear();
+    return f();
+  } catch (const Error& e) {
+    if (c) c->err = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    if (c) c->err = "host allocation failed";
+    return DMG_E_NOMEM;
+  } catch (const std::exception& e) {
+    if (c) c->err = e.what();
+    return DMG_E_INVALID;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+dmg_status dmg_batch_create(dmg_hierarchy* h, dmg_deflation* d, int capacity, const dmg_solve_params* prm,
+                            dmg_batch** out) {
+  if (!h || !out) return DMG_E_INVALID;
+  *out = nullptr;
+  return guarded(h->ctx, [&]() -> dmg_status {
+    DMG_CHECK(capacity >= 1 && capacity <= NBMAX, DMG_E_INVALID, "batch capacity outside [1, 64]");
+    DMG_CHECK(d && d->h == h && d->ready, DMG_E_INVALID,
+              "batch_create: the deflation space must belong to the hierarchy and be built");
+    dmg_solve_params p;
+    dmg_solve_params_default(&p);
+    if (prm) p = *prm;
+    DMG_CHECK(p.tol > 0.0 && p.int_tol > 0.0 && p.coarse_tol_later > 0.0 && p.max_outer_iters >= 1 &&
+                  p.int_max_iters >= 1 && p.coarse_max_iters >= 1 && p.outer_m >= 1 && p.outer_m <= MB &&
+                  p.int_m >= 1 && p.int_m <= MB && p.smooth_steps == 2 && !p.use_x0 && d->m - d->kk <= MB,
+              DMG_E_INVALID, "batch parameters (restart lengths <= 24, two smoothing steps, no x0)");
+    if (p.precond == DMG_FP32) prepare_deflation_fp32(&h->main, d);
+    int nb = 1;
+    while (nb < capacity) nb *= 2;
+    std::unique_ptr<dmg_batch> bt(new dmg_batch());
+    bt->h = h;
+    bt->d = d;
+    bt->cap = capacity;
+    bt->w = create_bwork(h, d, &p, nb);
+    bt->state.assign(capacity, DMG_SLOT_FREE);
+    DMG_HIP(hipStreamSynchronize(h->ctx->stream));
+    *out = bt.release();
+    return DMG_OK;
+  });
+}
+
+dmg_status dmg_batch_admit(dmg_batch* bt, int slot, const void* b, int ptr_kind) {
+  if (!bt) return DMG_E_INVALID;
+  dmg_context* c = bt->h->ctx;
+  return guarded(c, [&]() -> dmg_status {
+    DMG_CHECK(slot >= 0 && slot < bt->cap && b, DMG_E_INVALID, "batch_admit: bad arguments");
+    DMG_CHECK(ptr_kind == DMG_PTR_HOST || ptr_kind == DMG_PTR_DEVICE, DMG_E_INVALID, "batch_admit: pointer kind");
+    DMG_CHECK(bt->state[slot] == DMG_SLOT_FREE, DMG_E_INVALID, "batch_admit: slot is busy");
+    BWork* w = bt->w;
+    const int64_t n = bt->h->op[0].n;
+    hipStream_t s = c->stream;
+    DevBuf tmp;
+    const double2* src = (const double2*)b;
+    if (ptr_kind == DMG_PTR_HOST) {
+      const double* v = (const double*)b;
+      for (int64_t i = 0; i < 2 * n; ++i)
+        DMG_CHECK(std::isfinite(v[i]), DMG_E_NONFINITE, "non-finite right-hand side");
+      tmp.alloc(c, sizeof(double2) * n);
+      DMG_HIP(hipMemcpyAsync(tmp.p, b, sizeof(double2) * n, hipMemcpyHostToDevice, s));
+      src = tmp.as<double2>();
+    }
+    launch_b_lane_io(s, src, w->B.as<double2>(), n, w->nb, slot, 1);
+    w->start_lanes({slot});  // synchronises the stream
+    bt->state[slot] = w->act[slot] ? DMG_SLOT_RUNNING : DMG_SLOT_DONE;
+    return DMG_OK;
+  });
+}
+
+dmg_status dmg_batch_step(dmg_batch* bt, int min_iters, int* n_done) {
+  if (!bt) return DMG_E_INVALID;
+  return guarded(bt->h->ctx, [&]() -> dmg_status {
+    DMG_CHECK(min_iters >= 1, DMG_E_INVALID, "batch_step: min_iters must be >= 1");
+    BWork* w = bt->w;
+    const int cycles = (min_iters + w->p.outer_m - 1) / w->p.outer_m;
+    for (int c = 0; c < cycles && w->any_active(); ++c) w->cycle();
+    int k = 0;
+    for (int i = 0; i < bt->cap; ++i) {
+      if (bt->state[i] == DMG_SLOT_RUNNING && !w->act[i]) bt->state[i] = DMG_SLOT_DONE;
+      k += bt->state[i] == DMG_SLOT_DONE ? 1 : 0;
+    }
+    if (n_done) *n_done = k;
+    return DMG_OK;
+  });
+}
+
+dmg_status dmg_batch_retire(dmg_batch* bt, int slot, void* x, int ptr_kind, dmg_solve_stats* stats) {
+  if (!bt) return DMG_E_INVALID;
+  dmg_context* c = bt->h->ctx;
+  return guarded(c, [&]() -> dmg_status {
+    DMG_CHECK(slot >= 0 && slot < bt->cap && x, DMG_E_INVALID, "batch_retire: bad arguments");
+    DMG_CHECK(ptr_kind == DMG_PTR_HOST || ptr_kind == DMG_PTR_DEVICE, DMG_E_INVALID, "batch_retire: pointer kind");
+    DMG_CHECK(bt->state[slot] == DMG_SLOT_DONE, DMG_E_INVALID, "batch_retire: slot has no finished solve");
+    BWork* w = bt->w;
+    const int64_t n = bt->h->op[0].n;
+    hipStream_t s = c->stream;
+    if (ptr_kind == DMG_PTR_HOST) {
+      DevBuf tmp;
+      tmp.alloc(c, sizeof(double2) * n);
+      launch_b_lane_io(s, w->X.as<double2>(), tmp.as<double2>(), n, w->nb, slot, 0);
+      DMG_HIP(hipMemcpyAsync(x, tmp.p, sizeof(double2) * n, hipMemcpyDeviceToHost, s));
+      DMG_HIP(hipStreamSynchronize(s));
+    } else {
+      launch_b_lane_io(s, w->X.as<double2>(), (double2*)x, n, w->nb, slot, 0);
+    }
+    if (stats) w->stats(slot, stats, std::chrono::steady_clock::now());
+    bt->state[slot] = DMG_SLOT_FREE;
+    return w->conv[slot] ? DMG_OK : DMG_W_NOT_CONVERGED;
+  });
+}
+
+int dmg_batch_slot_state(dmg_batch* bt, int slot) {
+  if (!bt || slot < 0 || slot >= bt->cap) return -1;
+  return bt->state[slot];
+}
+
+void dmg_batch_destroy(dmg_batch* bt) { delete bt; }
+
+}  // extern "C"

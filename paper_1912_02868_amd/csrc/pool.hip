@@ -1,7 +1,7 @@
-// Continuous batching of independent solves: slots with their own stream, host
-// worker thread and solver workspace.  The solves of different slots overlap on the
-// device; each advances by whole outer FGMRES cycles, so its arithmetic is the same
-// alone or in a mix.
+// Pool of independent solves: slots with their own stream, host worker thread and
+// solver workspace, each taking a right-hand side of any hierarchy.  The solves of
+// different slots overlap on the device; each advances by whole outer FGMRES
+// cycles, so its arithmetic is the same alone or in a mix.
 #include <cmath>
 #include <condition_variable>
 #include <cstring>
@@ -11,7 +11,7 @@
 
 using namespace dmg;
 
-struct dmg_batch {
+struct dmg_pool {
   struct Slot {
     Work w;
     int state = DMG_SLOT_FREE;
@@ -38,10 +38,10 @@ struct dmg_batch {
   bool quit = false;
 
   void worker(int i);
-  ~dmg_batch();
+  ~dmg_pool();
 };
 
-void dmg_batch::worker(int i) {
+void dmg_pool::worker(int i) {
   Slot& sl = *slots[i];
   (void)hipSetDevice(ctx->device);
   for (;;) {
@@ -89,7 +89,7 @@ void dmg_batch::worker(int i) {
   }
 }
 
-dmg_batch::~dmg_batch() {
+dmg_pool::~dmg_pool() {
   {
     std::unique_lock<std::mutex> lk(mu);
     cv_done.wait(lk, [&] {
@@ -128,11 +128,11 @@ dmg_status guarded(dmg_context* c, F&& f) {
 
 extern "C" {
 
-dmg_status dmg_batch_create(dmg_context* ctx, int capacity, const dmg_solve_params* prm, dmg_batch** out) {
+dmg_status dmg_pool_create(dmg_context* ctx, int capacity, const dmg_solve_params* prm, dmg_pool** out) {
   if (!ctx || !out) return DMG_E_INVALID;
   *out = nullptr;
   return guarded(ctx, [&]() -> dmg_status {
-    DMG_CHECK(capacity >= 1 && capacity <= DMG_BATCH_MAX_SLOTS, DMG_E_INVALID, "batch capacity outside [1, 8]");
+    DMG_CHECK(capacity >= 1 && capacity <= DMG_POOL_MAX_SLOTS, DMG_E_INVALID, "pool capacity outside [1, 8]");
     dmg_solve_params p;
     dmg_solve_params_default(&p);
     if (prm) p = *prm;
@@ -140,46 +140,46 @@ dmg_status dmg_batch_create(dmg_context* ctx, int capacity, const dmg_solve_para
                   p.max_outer_iters >= 1 && p.int_max_iters >= 1 && p.coarse_max_iters >= 1 &&
                   p.outer_m >= 1 && p.outer_m <= MMAX && p.int_m >= 1 && p.int_m <= MMAX &&
                   p.smooth_steps >= 1 && p.smooth_steps <= MMAX && !p.use_x0,
-              DMG_E_INVALID, "batch solve parameters (use_x0 is not supported)");
+              DMG_E_INVALID, "pool solve parameters (use_x0 is not supported)");
     // Persistent coarse solves in a batch use cooperative launches, which the runtime
     // places only when the whole grid fits: a plain-launched grid on one stream can
     // wait behind the other slots' work for its last workgroups.
     if (p.coarse_persistent == 2) p.coarse_persistent = 1;
-    std::unique_ptr<dmg_batch> bt(new dmg_batch());
-    bt->ctx = ctx;
-    bt->cap = capacity;
-    bt->p = p;
+    std::unique_ptr<dmg_pool> pl(new dmg_pool());
+    pl->ctx = ctx;
+    pl->cap = capacity;
+    pl->p = p;
     for (int i = 0; i < capacity; ++i) {
-      bt->slots.emplace_back(new dmg_batch::Slot());
+      pl->slots.emplace_back(new dmg_pool::Slot());
       hipStream_t s = nullptr;
       DMG_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-      bt->slots.back()->w.init(ctx, s, true);
+      pl->slots.back()->w.init(ctx, s, true);
     }
     DMG_HIP(hipStreamSynchronize(ctx->stream));
-    for (auto& s : bt->slots) DMG_HIP(hipStreamSynchronize(s->w.stream));
+    for (auto& s : pl->slots) DMG_HIP(hipStreamSynchronize(s->w.stream));
     for (int i = 0; i < capacity; ++i) {
-      dmg_batch* raw = bt.get();
-      bt->slots[i]->th = std::thread([raw, i] { raw->worker(i); });
+      dmg_pool* raw = pl.get();
+      pl->slots[i]->th = std::thread([raw, i] { raw->worker(i); });
     }
-    *out = bt.release();
+    *out = pl.release();
     return DMG_OK;
   });
 }
 
-dmg_status dmg_batch_admit(dmg_batch* bt, int slot, dmg_hierarchy* h, dmg_deflation* d, const void* b,
+dmg_status dmg_pool_admit(dmg_pool* pl, int slot, dmg_hierarchy* h, dmg_deflation* d, const void* b,
                            int ptr_kind) {
-  if (!bt) return DMG_E_INVALID;
-  return guarded(bt->ctx, [&]() -> dmg_status {
-    DMG_CHECK(slot >= 0 && slot < bt->cap && h && b, DMG_E_INVALID, "batch_admit: bad arguments");
-    DMG_CHECK(ptr_kind == DMG_PTR_HOST || ptr_kind == DMG_PTR_DEVICE, DMG_E_INVALID, "batch_admit: pointer kind");
-    dmg_batch::Slot& sl = *bt->slots[slot];
+  if (!pl) return DMG_E_INVALID;
+  return guarded(pl->ctx, [&]() -> dmg_status {
+    DMG_CHECK(slot >= 0 && slot < pl->cap && h && b, DMG_E_INVALID, "pool_admit: bad arguments");
+    DMG_CHECK(ptr_kind == DMG_PTR_HOST || ptr_kind == DMG_PTR_DEVICE, DMG_E_INVALID, "pool_admit: pointer kind");
+    dmg_pool::Slot& sl = *pl->slots[slot];
     {
-      std::lock_guard<std::mutex> lk(bt->mu);
-      DMG_CHECK(sl.state == DMG_SLOT_FREE, DMG_E_INVALID, "batch_admit: slot is busy");
+      std::lock_guard<std::mutex> lk(pl->mu);
+      DMG_CHECK(sl.state == DMG_SLOT_FREE, DMG_E_INVALID, "pool_admit: slot is busy");
     }
-    DMG_CHECK(h->ctx == bt->ctx, DMG_E_INVALID, "batch_admit: hierarchy belongs to another context");
+    DMG_CHECK(h->ctx == pl->ctx, DMG_E_INVALID, "pool_admit: hierarchy belongs to another context");
     DMG_CHECK(!d || (d->h == h && d->ready), DMG_E_INVALID,
-              "batch_admit: the deflation space must belong to the hierarchy and be built");
+              "pool_admit: the deflation space must belong to the hierarchy and be built");
     const int64_t n = h->op[0].n;
     const size_t fb = sizeof(double2) * n;
     if (ptr_kind == DMG_PTR_HOST) {
@@ -188,14 +188,14 @@ dmg_status dmg_batch_admit(dmg_batch* bt, int slot, dmg_hierarchy* h, dmg_deflat
         DMG_CHECK(std::isfinite(v[i]), DMG_E_NONFINITE, "non-finite right-hand side");
     }
     // workspace for h first: a budget failure leaves the slot FREE
-    prepare_work(h, &sl.w, d, &bt->p);
-    if (bt->p.precond == DMG_FP32) prepare_deflation_fp32(&sl.w, d);
+    prepare_work(h, &sl.w, d, &pl->p);
+    if (pl->p.precond == DMG_FP32) prepare_deflation_fp32(&sl.w, d);
     // workspace initialisation may have been queued on the context's stream
-    DMG_HIP(hipStreamSynchronize(bt->ctx->stream));
+    DMG_HIP(hipStreamSynchronize(pl->ctx->stream));
     if (sl.b.bytes != fb) {
       DMG_HIP(hipStreamSynchronize(sl.w.stream));
-      sl.b.alloc(bt->ctx, fb);
-      sl.x.alloc(bt->ctx, fb);
+      sl.b.alloc(pl->ctx, fb);
+      sl.x.alloc(pl->ctx, fb);
     }
     hipStream_t s = sl.w.stream;
     if (ptr_kind == DMG_PTR_HOST) {
@@ -205,7 +205,7 @@ dmg_status dmg_batch_admit(dmg_batch* bt, int slot, dmg_hierarchy* h, dmg_deflat
       // device input: order the copy after the caller's stream
       hipEvent_t e;
       DMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-      DMG_HIP(hipEventRecord(e, bt->ctx->stream));
+      DMG_HIP(hipEventRecord(e, pl->ctx->stream));
       DMG_HIP(hipStreamWaitEvent(s, e, 0));
       DMG_HIP(hipEventDestroy(e));
       DMG_HIP(hipMemcpyAsync(sl.b.p, b, fb, hipMemcpyDeviceToDevice, s));
@@ -217,20 +217,20 @@ dmg_status dmg_batch_admit(dmg_batch* bt, int slot, dmg_hierarchy* h, dmg_deflat
     sl.status = DMG_OK;
     sl.err.clear();
     sl.stats = dmg_solve_stats{};
-    std::lock_guard<std::mutex> lk(bt->mu);
+    std::lock_guard<std::mutex> lk(pl->mu);
     sl.state = DMG_SLOT_RUNNING;
     return DMG_OK;
   });
 }
 
-dmg_status dmg_batch_step(dmg_batch* bt, int min_iters, int* n_done) {
-  if (!bt) return DMG_E_INVALID;
-  return guarded(bt->ctx, [&]() -> dmg_status {
-    DMG_CHECK(min_iters >= 1, DMG_E_INVALID, "batch_step: min_iters must be >= 1");
-    std::unique_lock<std::mutex> lk(bt->mu);
-    const long long c0 = bt->completions;
+dmg_status dmg_pool_step(dmg_pool* pl, int min_iters, int* n_done) {
+  if (!pl) return DMG_E_INVALID;
+  return guarded(pl->ctx, [&]() -> dmg_status {
+    DMG_CHECK(min_iters >= 1, DMG_E_INVALID, "pool_step: min_iters must be >= 1");
+    std::unique_lock<std::mutex> lk(pl->mu);
+    const long long c0 = pl->completions;
     int busy = 0;
-    for (auto& s : bt->slots) {
+    for (auto& s : pl->slots) {
       if (s->state == DMG_SLOT_RUNNING && !s->busy) {
         s->busy = true;
         s->go = true;
@@ -238,27 +238,27 @@ dmg_status dmg_batch_step(dmg_batch* bt, int min_iters, int* n_done) {
       }
       busy += s->busy ? 1 : 0;
     }
-    bt->cv_go.notify_all();
-    if (busy) bt->cv_done.wait(lk, [&] { return bt->completions != c0; });
+    pl->cv_go.notify_all();
+    if (busy) pl->cv_done.wait(lk, [&] { return pl->completions != c0; });
     if (n_done) {
       int k = 0;
-      for (auto& s : bt->slots) k += s->state == DMG_SLOT_DONE ? 1 : 0;
+      for (auto& s : pl->slots) k += s->state == DMG_SLOT_DONE ? 1 : 0;
       *n_done = k;
     }
     return DMG_OK;
   });
 }
 
-dmg_status dmg_batch_retire(dmg_batch* bt, int slot, void* x, int ptr_kind, dmg_solve_stats* stats) {
-  if (!bt) return DMG_E_INVALID;
-  dmg_context* c = bt->ctx;
+dmg_status dmg_pool_retire(dmg_pool* pl, int slot, void* x, int ptr_kind, dmg_solve_stats* stats) {
+  if (!pl) return DMG_E_INVALID;
+  dmg_context* c = pl->ctx;
   dmg_status st = guarded(c, [&]() -> dmg_status {
-    DMG_CHECK(slot >= 0 && slot < bt->cap && x, DMG_E_INVALID, "batch_retire: bad arguments");
-    DMG_CHECK(ptr_kind == DMG_PTR_HOST || ptr_kind == DMG_PTR_DEVICE, DMG_E_INVALID, "batch_retire: pointer kind");
-    dmg_batch::Slot& sl = *bt->slots[slot];
+    DMG_CHECK(slot >= 0 && slot < pl->cap && x, DMG_E_INVALID, "pool_retire: bad arguments");
+    DMG_CHECK(ptr_kind == DMG_PTR_HOST || ptr_kind == DMG_PTR_DEVICE, DMG_E_INVALID, "pool_retire: pointer kind");
+    dmg_pool::Slot& sl = *pl->slots[slot];
     {
-      std::lock_guard<std::mutex> lk(bt->mu);
-      DMG_CHECK(sl.state == DMG_SLOT_DONE && !sl.busy, DMG_E_INVALID, "batch_retire: slot has no finished solve");
+      std::lock_guard<std::mutex> lk(pl->mu);
+      DMG_CHECK(sl.state == DMG_SLOT_DONE && !sl.busy, DMG_E_INVALID, "pool_retire: slot has no finished solve");
       sl.state = DMG_SLOT_FREE;
     }
     if (stats) *stats = sl.stats;
@@ -282,12 +282,12 @@ dmg_status dmg_batch_retire(dmg_batch* bt, int slot, void* x, int ptr_kind, dmg_
   return st;
 }
 
-int dmg_batch_slot_state(dmg_batch* bt, int slot) {
-  if (!bt || slot < 0 || slot >= bt->cap) return -1;
-  std::lock_guard<std::mutex> lk(bt->mu);
-  return bt->slots[slot]->state;
+int dmg_pool_slot_state(dmg_pool* pl, int slot) {
+  if (!pl || slot < 0 || slot >= pl->cap) return -1;
+  std::lock_guard<std::mutex> lk(pl->mu);
+  return pl->slots[slot]->state;
 }
 
-void dmg_batch_destroy(dmg_batch* bt) { delete bt; }
+void dmg_pool_destroy(dmg_pool* pl) { delete pl; }
 
 }  // extern "C"

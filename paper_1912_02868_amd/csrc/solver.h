@@ -79,7 +79,7 @@ struct Counters {
 };
 
 template <typename R> struct Precond;
-struct BWork;                 // workspace of the lockstep multi-right-hand-side solve
+struct BWork;                 // lane engine of the lockstep multi-right-hand-side solve
 void destroy_bwork(BWork* b);
 
 // Mutable state of one solve in flight: its stream, reduction scratch, status mirror,

@@ -40,11 +40,14 @@ EXPORTED = [
     "dmg_deflation_export", "dmg_deflation_destroy",
     "dmg_solve_params_default", "dmg_setup_params_default", "dmg_solve", "dmg_solve_batched",
     "dmg_kernel_timer", "dmg_kernel_timer_read",
+    "dmg_pool_create", "dmg_pool_admit", "dmg_pool_step", "dmg_pool_retire", "dmg_pool_slot_state",
+    "dmg_pool_destroy",
     "dmg_batch_create", "dmg_batch_admit", "dmg_batch_step", "dmg_batch_retire", "dmg_batch_slot_state",
     "dmg_batch_destroy",
 ]
 SLOT_FREE, SLOT_RUNNING, SLOT_DONE = 0, 1, 2
-BATCH_MAX_SLOTS = 8
+POOL_MAX_SLOTS = 8
+BATCH_MAX_LANES = 64
 KT_COARSE_PROJ, KT_BLOCK_APPLY_INT = 0, 1
 
 
@@ -142,8 +145,14 @@ def lib():
         "dmg_solve": (i, [vp, vp, vp, C.POINTER(SolveParams), vp, vp, i, i, C.POINTER(SolveStats)]),
         "dmg_solve_batched": (i, [vp, vp, vp, C.POINTER(SolveParams), vp, vp, i, i, C.POINTER(SolveStats)]),
         "dmg_kernel_timer": (i, [vp, i]),
-        "dmg_batch_create": (i, [vp, i, C.POINTER(SolveParams), pp]),
-        "dmg_batch_admit": (i, [vp, i, vp, vp, vp, i]),
+        "dmg_pool_create": (i, [vp, i, C.POINTER(SolveParams), pp]),
+        "dmg_pool_admit": (i, [vp, i, vp, vp, vp, i]),
+        "dmg_pool_step": (i, [vp, i, C.POINTER(C.c_int)]),
+        "dmg_pool_retire": (i, [vp, i, vp, i, C.POINTER(SolveStats)]),
+        "dmg_pool_slot_state": (i, [vp, i]),
+        "dmg_pool_destroy": (None, [vp]),
+        "dmg_batch_create": (i, [vp, vp, i, C.POINTER(SolveParams), pp]),
+        "dmg_batch_admit": (i, [vp, i, vp, i]),
         "dmg_batch_step": (i, [vp, i, C.POINTER(C.c_int)]),
         "dmg_batch_retire": (i, [vp, i, vp, i, C.POINTER(SolveStats)]),
         "dmg_batch_slot_state": (i, [vp, i]),
@@ -411,21 +420,69 @@ def solve(ctx: Context, hier: Hierarchy, defl, b, x, nrhs: int = 1, params: Solv
     return st, [s.as_dict() for s in stats]
 
 
-class Batch:
-    """Slots of concurrent independent solves (continuous batching); see dmg_batch_* in dmg.h."""
+class Pool:
+    """Slots of concurrent independent solves of any resident hierarchy; see dmg_pool_* in dmg.h."""
 
     def __init__(self, ctx: Context, capacity: int, params: SolveParams | None = None):
         self.ctx = ctx
         self.capacity = capacity
         self.h = C.c_void_p()
         prm = params or solve_params()
-        ctx.check(lib().dmg_batch_create(ctx.h, capacity, C.byref(prm), C.byref(self.h)), "batch_create")
+        ctx.check(lib().dmg_pool_create(ctx.h, capacity, C.byref(prm), C.byref(self.h)), "pool_create")
         _register(self)
 
     def admit(self, slot: int, hier: Hierarchy, defl, b) -> int:
         """Admit one right-hand side; returns the status (DMG_E_BUDGET leaves the slot free)."""
         pb, kb = _ptr(b)
-        st = lib().dmg_batch_admit(self.h, slot, hier.h, defl.h if defl is not None else None, pb, kb)
+        st = lib().dmg_pool_admit(self.h, slot, hier.h, defl.h if defl is not None else None, pb, kb)
+        if st != DMG_E_BUDGET:
+            self.ctx.check(st, "pool_admit")
+        return st
+
+    def step(self, min_iters: int = 1) -> int:
+        n = C.c_int()
+        self.ctx.check(lib().dmg_pool_step(self.h, min_iters, C.byref(n)), "pool_step")
+        return n.value
+
+    def state(self, slot: int) -> int:
+        return lib().dmg_pool_slot_state(self.h, slot)
+
+    def retire(self, slot: int, x):
+        """Copy the slot's solution into x; returns (status, stats dict).  Errors raise."""
+        px, kx = _ptr(x)
+        stats = SolveStats()
+        st = lib().dmg_pool_retire(self.h, slot, px, kx, C.byref(stats))
+        self.ctx.check(st, "pool_retire")
+        return st, stats.as_dict()
+
+    def close(self):
+        if self.h:
+            lib().dmg_pool_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Lockstep lanes of one hierarchy with continuous admission; see dmg_batch_* in dmg.h."""
+
+    def __init__(self, hier: Hierarchy, defl, capacity: int, params: SolveParams | None = None):
+        self.hier = hier
+        self.ctx = hier.ctx
+        self.capacity = capacity
+        self.h = C.c_void_p()
+        prm = params or solve_params()
+        self.ctx.check(lib().dmg_batch_create(hier.h, defl.h, capacity, C.byref(prm), C.byref(self.h)),
+                       "batch_create")
+        _register(self)
+
+    def admit(self, slot: int, b) -> int:
+        pb, kb = _ptr(b)
+        st = lib().dmg_batch_admit(self.h, slot, pb, kb)
         if st != DMG_E_BUDGET:
             self.ctx.check(st, "batch_admit")
         return st
@@ -439,7 +496,6 @@ class Batch:
         return lib().dmg_batch_slot_state(self.h, slot)
 
     def retire(self, slot: int, x):
-        """Copy the slot's solution into x; returns (status, stats dict).  Errors raise."""
         px, kx = _ptr(x)
         stats = SolveStats()
         st = lib().dmg_batch_retire(self.h, slot, px, kx, C.byref(stats))

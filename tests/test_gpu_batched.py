@@ -164,3 +164,83 @@ def test_batched_transfers(dmg, inj64, prec, nrhs):
             ref_p = P @ xc[r].astype(complex)
             assert np.linalg.norm(rc[r] - ref_r) / np.linalg.norm(ref_r) < tol
             assert np.linalg.norm(pf[r] - ref_p) / np.linalg.norm(ref_p) < tol
+
+
+# ---------------------------------------------------------------- continuous batching on lanes (dmg_batch_*)
+def _run_lanes(dmg, bt, cap, jobs, min_iters=1):
+    queue = list(jobs)
+    busy, results = {}, {}
+    while queue or busy:
+        for i in range(cap):
+            if queue and bt.state(i) == dmg.SLOT_FREE:
+                key, b = queue.pop(0)
+                assert bt.admit(i, b) == dmg.DMG_OK
+                busy[i] = (key, b)
+        bt.step(min_iters)
+        for i in list(busy):
+            if bt.state(i) == dmg.SLOT_DONE:
+                key, b = busy.pop(i)
+                x = np.empty_like(b)
+                st, s = bt.retire(i, x)
+                results[key] = (x, st, s)
+    return results
+
+
+@pytest.mark.parametrize("precond", ["fp64", "fp32"])
+def test_lanes_alone_vs_mix(dmg, ctx, cfg64, precond):
+    """Requests joining and leaving lockstep lanes get bitwise the result they get alone
+    (one request in a batch of the same capacity); each reaches 1e-8 with the oracle's D."""
+    th, m0, g, h, d, D, lu = cfg64
+    prm = dmg.solve_params(precond=precond)
+    cap = 6  # 8 lanes
+    jobs = [(j, synth.rhs(64, 0, 10 + j)) for j in range(11)]
+    jobs[3] = (3, np.zeros_like(jobs[3][1]))
+    bt = dmg.Batch(h, d, cap, prm)
+    mix = _run_lanes(dmg, bt, cap, jobs)
+    alone = {}
+    for key, b in jobs[:5]:
+        alone.update(_run_lanes(dmg, bt, cap, [(key, b)], min_iters=3))
+    bt.close()
+    assert set(mix) == {j for j, _ in jobs}
+    for key, b in jobs:
+        x, st, s = mix[key]
+        assert st == dmg.DMG_OK and s["converged"] == 1
+        if key == 3:
+            assert np.all(x == 0) and s["outer_iters"] == 0
+            continue
+        res = np.linalg.norm(b - D @ x) / np.linalg.norm(b)
+        assert res <= 1e-8 * (1 + 1e-6) and abs(res - s["true_rel_resid"]) < 1e-12
+        if key in alone:
+            assert np.array_equal(x, alone[key][0]), key
+
+
+def test_lanes_device_and_errors(dmg, ctx, cfg64):
+    th, m0, g, h, d, D, lu = cfg64
+    for cap in (0, dmg.BATCH_MAX_LANES + 1):
+        with pytest.raises(dmg.DmgError) as e:
+            dmg.Batch(h, d, cap)
+        assert e.value.code == dmg.DMG_E_INVALID
+    fresh = dmg.Deflation(h, 30, 10)
+    with pytest.raises(dmg.DmgError) as e:
+        dmg.Batch(h, fresh, 4)
+    assert e.value.code == dmg.DMG_E_INVALID
+    fresh.close()
+    bt = dmg.Batch(h, d, 4)
+    b = synth.rhs(64, 0, 30)
+    bd = torch.from_numpy(b).cuda()
+    xd = torch.zeros_like(bd)
+    assert bt.admit(2, bd) == dmg.DMG_OK
+    with pytest.raises(dmg.DmgError) as e:
+        bt.admit(2, bd)
+    assert e.value.code == dmg.DMG_E_INVALID
+    with pytest.raises(dmg.DmgError) as e:
+        bt.retire(2, xd)
+    assert e.value.code == dmg.DMG_E_INVALID
+    while bt.state(2) != dmg.SLOT_DONE:
+        bt.step(8)
+    st, s = bt.retire(2, xd)
+    torch.cuda.synchronize()
+    x = xd.cpu().numpy()
+    assert st == dmg.DMG_OK and np.linalg.norm(b - D @ x) / np.linalg.norm(b) <= 1e-8 * (1 + 1e-6)
+    assert bt.state(2) == dmg.SLOT_FREE and bt.state(9) == -1
+    bt.close()

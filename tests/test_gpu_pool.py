@@ -1,9 +1,9 @@
-"""Continuous batching (dmg_batch_*) through the C-ABI.
+"""Pool of concurrent solves (dmg_pool_*) through the C-ABI.
 
-A solve admitted into a batch advances by whole outer FGMRES cycles on its own
+A solve admitted into a pool advances by whole outer FGMRES cycles on its own
 stream and workspace, with a deflation space frozen before admission, so its
 result must be bitwise the result of dmg_solve with the same parameters, whatever
-shares the batch.  Results are also checked against the oracle's operator (true
+shares the pool.  Results are also checked against the oracle's operator (true
 residual), and admission against the context's HBM budget.
 """
 import numpy as np
@@ -55,30 +55,30 @@ def _true_residual(th, m0, b, x):
     return np.linalg.norm(b - D @ x) / np.linalg.norm(b)
 
 
-def _run_batch(dmg, bt, capacity, jobs, min_iters=1):
-    """Continuous batching: admit into free slots, step, retire finished slots.
+def _run_pool(dmg, pl, capacity, jobs, min_iters=1):
+    """Admit into free slots, step, retire finished slots.
     jobs: list of (key, hierarchy, deflation, b).  Returns {key: (x, status, stats)}."""
     queue = list(jobs)
     busy = {}
     results = {}
     while queue or busy:
         for i in range(capacity):
-            if queue and bt.state(i) == dmg.SLOT_FREE:
+            if queue and pl.state(i) == dmg.SLOT_FREE:
                 key, h, d, b = queue.pop(0)
-                assert bt.admit(i, h, d, b) == dmg.DMG_OK
+                assert pl.admit(i, h, d, b) == dmg.DMG_OK
                 busy[i] = (key, b)
-        bt.step(min_iters)
+        pl.step(min_iters)
         for i in list(busy):
-            if bt.state(i) == dmg.SLOT_DONE:
+            if pl.state(i) == dmg.SLOT_DONE:
                 key, b = busy.pop(i)
                 x = np.empty_like(b)
-                st, s = bt.retire(i, x)
+                st, s = pl.retire(i, x)
                 results[key] = (x, st, s)
     return results
 
 
 @pytest.mark.parametrize("precond,persistent", [("fp64", 1), ("fp32", 1), ("fp64", 0)])
-def test_batch_alone_vs_mix(dmg, ctx, resident, precond, persistent):
+def test_pool_alone_vs_mix(dmg, ctx, resident, precond, persistent):
     prm = dmg.solve_params(precond=precond, coarse_persistent=persistent)
     alone = {}
     for N, cfg, j in REQUESTS:
@@ -92,13 +92,13 @@ def test_batch_alone_vs_mix(dmg, ctx, resident, precond, persistent):
     for N, cfg, j in REQUESTS:
         th, m0, g, h, d = resident[(N, cfg)]
         jobs.append(((N, cfg, j), h, d, synth.rhs(N, cfg, j)))
-    bt = dmg.Batch(ctx, 4, prm)
-    mix = _run_batch(dmg, bt, 4, jobs)
-    # the same requests one at a time in a one-slot batch, stepped one outer iteration at a time
-    bt1 = dmg.Batch(ctx, 1, prm)
-    single = _run_batch(dmg, bt1, 1, jobs[:3])
-    bt.close()
-    bt1.close()
+    pl = dmg.Pool(ctx, 4, prm)
+    mix = _run_pool(dmg, pl, 4, jobs)
+    # the same requests one at a time in a one-slot pool, stepped one outer iteration at a time
+    pl1 = dmg.Pool(ctx, 1, prm)
+    single = _run_pool(dmg, pl1, 1, jobs[:3])
+    pl.close()
+    pl1.close()
     assert set(mix) == set(alone)
     for key, (x, st, s) in mix.items():
         N, cfg, j = key
@@ -111,7 +111,7 @@ def test_batch_alone_vs_mix(dmg, ctx, resident, precond, persistent):
         assert np.array_equal(x, alone[key]), key
 
 
-def test_batch_device_buffers(dmg, ctx, resident):
+def test_pool_device_buffers(dmg, ctx, resident):
     """Device-pointer admission and retirement, ordered against the context's stream."""
     N, cfg = 64, 0
     th, m0, g, h, d = resident[(N, cfg)]
@@ -120,19 +120,19 @@ def test_batch_device_buffers(dmg, ctx, resident):
     dmg.solve(ctx, h, d, b, x_ref)
     bd = torch.from_numpy(b).cuda()
     xd = torch.zeros_like(bd)
-    bt = dmg.Batch(ctx, 2)
-    assert bt.admit(1, h, d, bd) == dmg.DMG_OK
-    while bt.state(1) != dmg.SLOT_DONE:
-        bt.step(3)
-    st, s = bt.retire(1, xd)
+    pl = dmg.Pool(ctx, 2)
+    assert pl.admit(1, h, d, bd) == dmg.DMG_OK
+    while pl.state(1) != dmg.SLOT_DONE:
+        pl.step(3)
+    st, s = pl.retire(1, xd)
     torch.cuda.synchronize()
     assert st == dmg.DMG_OK
     assert np.array_equal(xd.cpu().numpy(), x_ref)
-    bt.close()
+    pl.close()
 
 
-def test_batch_nondeflated_and_budget(dmg):
-    """d = NULL in a batch equals dmg_solve(d = NULL); a request whose workspace exceeds
+def test_pool_nondeflated_and_budget(dmg):
+    """d = NULL in a pool equals dmg_solve(d = NULL); a request whose workspace exceeds
     the context's HBM budget is refused with DMG_E_BUDGET and leaves its slot free."""
     N, cfg = 64, 0
     th = synth.gauge_angles(N, cfg)
@@ -141,66 +141,66 @@ def test_batch_nondeflated_and_budget(dmg):
     c = dmg.Context(0)
     g = dmg.Gauge(c, th)
     h = dmg.Hierarchy(c, g, m0, synth.near_null_starts(N, cfg, 0), synth.near_null_starts(N, cfg, 1))
-    bt = dmg.Batch(c, 1)
+    pl = dmg.Pool(c, 1)
     before = c.bytes_in_use
-    assert bt.admit(0, h, None, b) == dmg.DMG_OK
+    assert pl.admit(0, h, None, b) == dmg.DMG_OK
     slot_bytes = c.bytes_in_use - before
     assert slot_bytes > 0
-    while bt.state(0) != dmg.SLOT_DONE:
-        bt.step(1)
+    while pl.state(0) != dmg.SLOT_DONE:
+        pl.step(1)
     x = np.empty_like(b)
-    st, s = bt.retire(0, x)
+    st, s = pl.retire(0, x)
     assert st == dmg.DMG_OK and s["converged"] == 1 and s["coarse_dr_calls"] == 0 and s["coarse_calls"] > 0
     x_ref = np.empty_like(b)
     st, _ = dmg.solve(c, h, None, b, x_ref)
     assert st == dmg.DMG_OK
     assert np.array_equal(x, x_ref)
     assert _true_residual(th, m0, b, x) <= 1e-8 * (1 + 1e-6)
-    # a second one-slot batch under a budget that holds only half of a slot's workspace
-    bt2 = dmg.Batch(c, 1)
+    # a second one-slot pool under a budget that holds only half of a slot's workspace
+    pl2 = dmg.Pool(c, 1)
     c.set_budget(c.bytes_in_use + slot_bytes // 2)
-    assert bt2.admit(0, h, None, b) == dmg.DMG_E_BUDGET
-    assert bt2.state(0) == dmg.SLOT_FREE
-    assert bt2.step(1) == 0
-    # the first batch's slot keeps its workspace, so it still admits
-    assert bt.admit(0, h, None, b) == dmg.DMG_OK
-    while bt.state(0) != dmg.SLOT_DONE:
-        bt.step(1)
-    st, s = bt.retire(0, x)
+    assert pl2.admit(0, h, None, b) == dmg.DMG_E_BUDGET
+    assert pl2.state(0) == dmg.SLOT_FREE
+    assert pl2.step(1) == 0
+    # the first pool's slot keeps its workspace, so it still admits
+    assert pl.admit(0, h, None, b) == dmg.DMG_OK
+    while pl.state(0) != dmg.SLOT_DONE:
+        pl.step(1)
+    st, s = pl.retire(0, x)
     assert st == dmg.DMG_OK and np.array_equal(x, x_ref)
     c.set_budget(0)
-    for o in (bt2, bt, h, g, c):
+    for o in (pl2, pl, h, g, c):
         o.close()
 
 
-def test_batch_errors(dmg, ctx, resident):
+def test_pool_errors(dmg, ctx, resident):
     th, m0, g, h, d = resident[(64, 0)]
-    for cap in (0, dmg.BATCH_MAX_SLOTS + 1):
+    for cap in (0, dmg.POOL_MAX_SLOTS + 1):
         with pytest.raises(dmg.DmgError) as e:
-            dmg.Batch(ctx, cap)
+            dmg.Pool(ctx, cap)
         assert e.value.code == dmg.DMG_E_INVALID
     fresh = dmg.Deflation(h, 30, 10)  # never built
-    bt = dmg.Batch(ctx, 2)
+    pl = dmg.Pool(ctx, 2)
     b = synth.rhs(64, 0, 0)
     with pytest.raises(dmg.DmgError) as e:
-        bt.admit(0, h, fresh, b)
+        pl.admit(0, h, fresh, b)
     assert e.value.code == dmg.DMG_E_INVALID
     with pytest.raises(dmg.DmgError) as e:
-        bt.retire(0, np.empty_like(b))
+        pl.retire(0, np.empty_like(b))
     assert e.value.code == dmg.DMG_E_INVALID
     bad = b.copy()
     bad[5] = np.nan
     with pytest.raises(dmg.DmgError) as e:
-        bt.admit(0, h, d, bad)
+        pl.admit(0, h, d, bad)
     assert e.value.code == dmg.DMG_E_NONFINITE
-    assert bt.state(0) == dmg.SLOT_FREE
-    assert bt.admit(0, h, d, b) == dmg.DMG_OK
+    assert pl.state(0) == dmg.SLOT_FREE
+    assert pl.admit(0, h, d, b) == dmg.DMG_OK
     with pytest.raises(dmg.DmgError) as e:
-        bt.admit(0, h, d, b)
+        pl.admit(0, h, d, b)
     assert e.value.code == dmg.DMG_E_INVALID
     with pytest.raises(dmg.DmgError) as e:
-        bt.step(0)
+        pl.step(0)
     assert e.value.code == dmg.DMG_E_INVALID
-    assert bt.state(5) == -1
-    bt.close()  # destroys with a solve still admitted
+    assert pl.state(5) == -1
+    pl.close()  # destroys with a solve still admitted
     fresh.close()
