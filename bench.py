@@ -46,6 +46,15 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle solves for the CPU baseline")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-rhs", type=int, default=64, help="right-hand sides per lockstep solve")
+    ap.add_argument("--batched-configs", type=int, default=2)
+    ap.add_argument("--batched-lattice", type=int, default=0, help="lattice of the lockstep form (0: --lattice)")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-sizes", default="64,128,256,512")
+    ap.add_argument("--serve-configs", type=int, default=4, help="resident configurations per lattice size")
+    ap.add_argument("--serve-requests", type=int, default=200, help="requests per arrival rate")
+    ap.add_argument("--serve-capacity", type=int, default=16, help="lanes per resident configuration")
     return ap.parse_args()
 
 
@@ -140,6 +149,17 @@ def main():
     roof = coarse_roofline(N, coarse_ms, coarse_launches, coarse_steps, el64)
     roof_int = measure_stencil_roofline(torch, dmg, ctx, res[step_cfgs[0]][1], N)
 
+    # ------------------------------------------------------------ batched and served forms
+    out_batched = None
+    if not a.no_batched:
+        NB = a.batched_lattice or N
+        cfgs_b = step_cfgs[:a.batched_configs] if NB == N else list(range(a.batched_configs))
+        out_batched = batched_form(torch, dmg, ctx, NB, cfgs_b, a.batched_rhs, n_solves / el64)
+    out_served = None
+    if not a.no_serve:
+        out_served = served_form(torch, dmg, ctx, [int(v) for v in a.serve_sizes.split(",")], a.serve_configs,
+                                 a.serve_requests, a.serve_capacity, n_solves / el64)
+
     # ------------------------------------------------------------ CPU baseline (oracle)
     cpu = None
     if not a.no_cpu_baseline:
@@ -172,6 +192,8 @@ def main():
         "mean_mvps": {"fine": mean("fine_mvps"), "intermediate": mean("int_mvps"), "coarse": mean("coarse_mvps"),
                       "fine_equivalent": mean("fine_equiv_mvps")},
         "mixed": out_mixed,
+        "batched": out_batched,
+        "served": out_served,
         "roofline": roof,
         "roofline_intermediate_stencil": roof_int,
         "cpu_baseline": cpu,
@@ -221,6 +243,240 @@ def measure_stencil_roofline(torch, dmg, ctx, h, N, reps=200):
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": None, "avg_launch_us": avg_ms * 1e3,
             "algorithmic_bytes_per_launch": bytes_per_launch}
+
+
+def build_resident(dmg, ctx, synth, N, c):
+    """Hierarchy and a built deflation space (GMRES-DR on the seeded coarse warm-up
+    right-hand side) of one configuration: the state a server keeps on the device."""
+    import torch
+    g = dmg.Gauge(ctx, synth.gauge_angles(N, c))
+    h = dmg.Hierarchy(ctx, g, synth.bare_mass(N, c), torch.from_numpy(synth.near_null_starts(N, c, 0)).cuda(),
+                      torch.from_numpy(synth.near_null_starts(N, c, 1)).cuda())
+    d = dmg.Deflation(h, 30, 10)
+    d.build(synth.gaussian_complex(24 * (N // 16) ** 2, N, c, 4, 0), 1e-8)
+    return g, h, d
+
+
+def batched_form(torch, dmg, ctx, N, cfgs, nrhs, plain_rate):
+    """Lockstep multi-RHS solves (dmg_solve_batched): per configuration, right-hand sides
+    0 .. nrhs-1 solved jointly with the FP32 preconditioner (and again with the FP64 one)
+    over the configuration's deflation space built beforehand.  Latency of a right-hand
+    side = its call's wall time.  The multi-RHS block and Wilson stencils are timed by
+    the library's events over the FP32 region; the intermediate-grid block stencil alone
+    gives the matrix-core roofline."""
+    import synth
+    res = {c: build_resident(dmg, ctx, synth, N, c) for c in cfgs}
+    B = {c: torch.from_numpy(np.stack([synth.rhs(N, c, j) for j in range(nrhs)])).cuda() for c in cfgs}
+    X = torch.empty_like(B[cfgs[0]])
+    out = {"workload": f"{N}^2, {nrhs} right-hand sides per lockstep solve, configurations {list(cfgs)}",
+           "rhs_per_call": nrhs}
+    for prec in ("fp32", "fp64"):
+        prm = dmg.solve_params(precond=prec)
+        g, h, d = res[cfgs[0]]
+        dmg.solve_batched(ctx, h, d, B[cfgs[0]], X, nrhs, params=prm)  # workspace
+        torch.cuda.synchronize()
+        if prec == "fp32":
+            ctx.timer(dmg.KT_BLOCK_BATCHED, dmg.KT_WILSON_BATCHED)
+        lat, stats = [], []
+        t0 = time.perf_counter()
+        for c in cfgs:
+            g, h, d = res[c]
+            t1 = time.perf_counter()
+            st, ss = dmg.solve_batched(ctx, h, d, B[c], X, nrhs, params=prm)
+            torch.cuda.synchronize()
+            lat += [(time.perf_counter() - t1) * 1e3] * nrhs
+            stats += ss
+        el = time.perf_counter() - t0
+        kt = None
+        if prec == "fp32":
+            kt = {}
+            for name, k in (("block_batched", dmg.KT_BLOCK_BATCHED), ("wilson_batched", dmg.KT_WILSON_BATCHED)):
+                ms, n, u = ctx.timer_read(k)
+                kt[name] = {"ms": ms, "launches": n, "site_lanes": u, "share_of_timed_region": ms * 1e-3 / el}
+            ctx.timer()
+        out[prec] = {"value": len(cfgs) * nrhs / el, "unit": "solves/s",
+                     "dtype": ("f32" if prec == "fp32" else "f64") + " preconditioner, f64 outer",
+                     "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
+                     "all_converged_1e-8": all(s["converged"] and s["true_rel_resid"] <= 1e-8 for s in stats),
+                     "max_true_rel_resid": float(max(s["true_rel_resid"] for s in stats)),
+                     "mean_outer_iters": float(np.mean([s["outer_iters"] for s in stats])),
+                     "speedup_vs_plain_fp64": (len(cfgs) * nrhs / el) / plain_rate}
+        if kt:
+            out[prec]["kernels"] = kt
+    out["roofline_block_batched"] = batched_block_roofline(torch, dmg, ctx, res[cfgs[0]][1], N, nrhs)
+    out["roofline_wilson_batched"] = batched_wilson_roofline(torch, dmg, ctx, res[cfgs[0]][1], N, nrhs)
+    for g, h, d in res.values():
+        d.close()
+        h.close()
+    return out
+
+
+FP32_MFMA_PEAK_TFLOPS = 157.3
+
+
+def batched_block_roofline(torch, dmg, ctx, h, N, nrhs, reps=50):
+    """Multi-RHS intermediate-grid block stencil in FP32 on the matrix cores: per blocked
+    site and right-hand side 5 x 576 complex multiply-adds (23,040 flop); bytes per site:
+    the 5 FP32 blocks (23,040 B) plus input and output 24-vectors of every right-hand
+    side (384 nrhs B).  Timed by the library's events around each launch."""
+    L = N // 4
+    sites = L * L
+    n1 = sites * 24
+    x = torch.randn(nrhs, n1, dtype=torch.complex64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        h.apply_batched(1, dmg.OP_APPLY, x, y, nrhs)
+    ctx.timer(dmg.KT_BLOCK_BATCHED)
+    for _ in range(reps):
+        h.apply_batched(1, dmg.OP_APPLY, x, y, nrhs)
+    ms, n, u = ctx.timer_read(dmg.KT_BLOCK_BATCHED)
+    ctx.timer()
+    avg = ms / max(n, 1)
+    flops = sites * nrhs * 23040
+    byts = sites * (5 * 576 * 8 + 2 * 24 * 8 * nrhs)
+    tf = flops / (avg * 1e-3) / 1e12
+    return {"kernel": f"kb_block_mfma (FP32, {L}x{L} sites x 24 dof x {nrhs} right-hand sides, 16x16x4 MFMA)",
+            "bound": "mfma", "achieved": tf, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": tf / FP32_MFMA_PEAK_TFLOPS, "traffic": None, "avg_launch_us": avg * 1e3,
+            "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": byts,
+            "achieved_gbs": byts / (avg * 1e-3) / 1e9}
+
+
+def batched_wilson_roofline(torch, dmg, ctx, h, N, nrhs, reps=50):
+    """Multi-RHS fine Wilson stencil in FP32: per site 32 nrhs B of fields in and out plus
+    16 B of links (the links are read once for all right-hand sides)."""
+    sites = N * N
+    x = torch.randn(nrhs, 2 * sites, dtype=torch.complex64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        h.apply_batched(0, dmg.OP_APPLY, x, y, nrhs)
+    ctx.timer(dmg.KT_WILSON_BATCHED)
+    for _ in range(reps):
+        h.apply_batched(0, dmg.OP_APPLY, x, y, nrhs)
+    ms, n, u = ctx.timer_read(dmg.KT_WILSON_BATCHED)
+    ctx.timer()
+    avg = ms / max(n, 1)
+    byts = sites * (32 * nrhs + 16)
+    gbs = byts / (avg * 1e-3) / 1e9
+    return {"kernel": f"kb_wilson (FP32, {N}x{N} sites x {nrhs} right-hand sides)", "bound": "hbm",
+            "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+            "avg_launch_us": avg * 1e3, "algorithmic_bytes_per_launch": byts}
+
+
+def served_form(torch, dmg, ctx, sizes, ncfg, n_req, cap, plain_rate):
+    """Serving: single-RHS requests, each naming one of the resident configurations
+    (every size in `sizes` x configurations 0..ncfg-1, hierarchy and deflation space kept
+    on the device), arrive as a seeded Poisson stream; each configuration has a lane
+    batch (dmg_batch_*, FP32 preconditioner) that requests join and leave between outer
+    cycles.  The host loop admits waiting requests into free lanes (configurations with
+    running lanes or a queue of at least four), steps those batches one outer cycle each
+    in turn and retires finished lanes; when no batch runs, the oldest waiting request is
+    solved on its own (dmg_solve).  Latency = arrival to result ready.  The saturated rate (all requests at t = 0) sets
+    the three arrival rates, 0.5x, 0.9x and 1.2x of it."""
+    import synth
+    keys = [(N, c) for N in sizes for c in range(ncfg)]
+    res, batches = {}, {}
+    prm = dmg.solve_params(precond="fp32")
+    t0 = time.perf_counter()
+    for k in keys:
+        res[k] = build_resident(dmg, ctx, synth, *k)
+        batches[k] = dmg.Batch(res[k][1], res[k][2], cap, prm)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    bytes_resident = ctx.bytes_in_use
+
+    def requests(seed_rate, n):
+        rng = synth.rng_for(0, 0, 5, seed_rate)
+        picks = rng.integers(0, len(keys), size=n)
+        return [(keys[p], torch.from_numpy(synth.rhs(keys[p][0], keys[p][1], 1000 + i)).cuda())
+                for i, p in enumerate(picks)], rng
+
+    xout = {k: torch.empty(2 * k[0] * k[0], dtype=torch.complex128, device="cuda") for k in keys}
+
+    def serve(reqs, arrivals):
+        """Requests of a configuration with at least `lane_min` waiting (or already running
+        lanes) go through its lane batch; a configuration with fewer waiting requests gets
+        its oldest request solved on its own (single-RHS path), so that sparse traffic is
+        not charged a whole lockstep step per request."""
+        queues = {k: [] for k in keys}
+        busy = {k: {} for k in keys}
+        lat, bad = [], 0
+        nxt, done = 0, 0
+        lane_min = 4
+        t_start = time.perf_counter()
+
+        def finish(i, s):
+            nonlocal bad, done
+            lat.append((time.perf_counter() - t_start - arrivals[i]) * 1e3)
+            bad += 0 if (s["converged"] and s["true_rel_resid"] <= 1e-8) else 1
+            done += 1
+
+        while done < len(reqs):
+            now = time.perf_counter() - t_start
+            while nxt < len(reqs) and arrivals[nxt] <= now:
+                queues[reqs[nxt][0]].append(nxt)
+                nxt += 1
+            # lane batches: configurations with running lanes, or enough waiting requests
+            stepped = False
+            for k in keys:
+                bt = batches[k]
+                if busy[k] or len(queues[k]) >= lane_min:
+                    for sl in range(cap):
+                        if not queues[k]:
+                            break
+                        if bt.state(sl) == dmg.SLOT_FREE:
+                            i = queues[k].pop(0)
+                            bt.admit(sl, reqs[i][1])
+                            busy[k][sl] = i
+                if not busy[k]:
+                    continue
+                bt.step(1)
+                stepped = True
+                for sl in list(busy[k]):
+                    if bt.state(sl) == dmg.SLOT_DONE:
+                        i = busy[k].pop(sl)
+                        st, s = bt.retire(sl, xout[k])
+                        torch.cuda.synchronize()
+                        finish(i, s)
+            if stepped:
+                continue
+            # otherwise the oldest waiting request alone
+            heads = [(queues[k][0], k) for k in keys if queues[k]]
+            if heads:
+                i, k = min(heads)
+                queues[k].pop(0)
+                g, h, d = res[k]
+                st, ss = dmg.solve(ctx, h, d, reqs[i][1], xout[k], params=prm)
+                torch.cuda.synchronize()
+                finish(i, ss[0])
+            elif nxt < len(reqs):
+                time.sleep(max(0.0, arrivals[nxt] - (time.perf_counter() - t_start)))
+        return len(reqs) / (time.perf_counter() - t_start), lat, bad
+
+    reqs, _ = requests(0, min(n_req, 64))
+    serve(reqs, [0.0] * len(reqs))  # warm the lanes of every batch in use
+    reqs, _ = requests(1, n_req)
+    sat, lat_sat, bad = serve(reqs, [0.0] * len(reqs))
+    out = {"workload": f"{len(keys)} resident configurations ({', '.join(str(n) + '^2' for n in sizes)} x "
+                       f"{ncfg}), single-RHS requests, Poisson arrivals, {cap} lanes per configuration, "
+                       f"FP32 preconditioner",
+           "requests_per_rate": n_req, "setup_s": setup_s, "resident_bytes": bytes_resident,
+           "saturated": {"value": sat, "unit": "solves/s", "p50_ms": percentile(lat_sat, 50),
+                         "p99_ms": percentile(lat_sat, 99), "failures": bad},
+           "rates": []}
+    for ri, frac in enumerate((0.5, 0.9, 1.2)):
+        rate = frac * sat
+        reqs, rng = requests(2 + ri, n_req)
+        arrivals = list(np.cumsum(rng.exponential(1.0 / rate, size=n_req)))
+        thr, lat, bad = serve(reqs, arrivals)
+        out["rates"].append({"offered_per_s": rate, "fraction_of_saturated": frac, "value": thr, "unit": "solves/s",
+                             "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99), "failures": bad})
+    for k in keys:
+        batches[k].close()
+        g, h, d = res[k]
+        d.close()
+        h.close()
+    return out
 
 
 def cpu_baseline(N, budget_s, gpu_outer_iters):

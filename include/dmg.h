@@ -93,9 +93,21 @@ dmg_status dmg_context_set_budget(dmg_context* ctx, size_t hbm_budget);
  * library brackets every launch with HIP events on the context's stream
  * (mask 0 turns timing off).  Reading synchronises the stream and returns, per
  * kernel, the summed event time, the launch count and the work units processed
- * (coarse solve: Arnoldi steps; intermediate stencil: blocked sites).  Every
- * call of dmg_kernel_timer resets the sums. */
-enum { DMG_KT_COARSE_PROJ = 0, DMG_KT_BLOCK_APPLY_INT = 1, DMG_KT_COUNT = 2 };
+ * (coarse solve: Arnoldi steps; intermediate stencil: blocked sites; multi-RHS
+ * stencils: sites x right-hand-side lanes).  Every call of dmg_kernel_timer resets
+ * the sums.
+ *   DMG_KT_COARSE_PROJ      persistent coarse GMRES-Proj kernel (dmg_solve)
+ *   DMG_KT_BLOCK_APPLY_INT  single-field intermediate block stencil, FP64
+ *   DMG_KT_BLOCK_BATCHED    multi-RHS block stencil, levels 1 and 2 (lockstep solves,
+ *                           batches, dmg_hierarchy_apply_batched)
+ *   DMG_KT_WILSON_BATCHED   multi-RHS fine Wilson stencil (same callers) */
+enum {
+  DMG_KT_COARSE_PROJ = 0,
+  DMG_KT_BLOCK_APPLY_INT = 1,
+  DMG_KT_BLOCK_BATCHED = 2,
+  DMG_KT_WILSON_BATCHED = 3,
+  DMG_KT_COUNT = 4
+};
 dmg_status dmg_kernel_timer(dmg_context* ctx, int mask);
 dmg_status dmg_kernel_timer_read(dmg_context* ctx, int kernel, double* total_ms, long long* launches,
                                  long long* units);

@@ -551,12 +551,15 @@ dmg_status dmg_hierarchy_apply_batched(dmg_hierarchy* h, int level, int op, dmg_
       using R = decltype(T{}.x);
       launch_b_gather<T>(s, (const T*)din, gi.as<T>(), nin, nrhs, nb);
       if (op == DMG_OP_APPLY) {
+        const int kt = A.kind == 0 ? DMG_KT_WILSON_BATCHED : DMG_KT_BLOCK_BATCHED;
+        hipEvent_t ta = timer_mark(c, kt, s);
         if (A.kind == 0)
           launch_b_wilson<R>(s, (const T*)(sizeof(R) == 8 ? (const void*)A.U64 : (const void*)A.U32), gi.as<T>(),
                              go.as<T>(), A.m0, A.Lx, A.Lt, nb, nullptr);
         else
           launch_b_block<R>(s, (const T*)(sizeof(R) == 8 ? (const void*)A.A64 : (const void*)A.A32), gi.as<T>(),
                             go.as<T>(), A.Lx, A.Lt, nb, nullptr);
+        if (ta) timer_span(c, kt, ta, timer_mark(c, kt, s), (long long)A.Lx * A.Lt * nb);
       } else if (op == DMG_OP_RESTRICT) {
         launch_b_restrict<R>(s, tr.P((const T*)nullptr), gi.as<T>(), go.as<T>(), tr.Lx, tr.Lt, tr.dof, nb);
       } else {

@@ -141,6 +141,9 @@ struct BPre {
 
   void apply(int l, const T* in, T* out, const T* sub, const int* skip) {
     const Op& A = h->op[l];
+    dmg_context* c = h->ctx;
+    const int kt = A.kind == 0 ? DMG_KT_WILSON_BATCHED : DMG_KT_BLOCK_BATCHED;
+    hipEvent_t ta = timer_mark(c, kt, S());
     if (A.kind == 0) {
       const T* U = (const T*)(sizeof(R) == sizeof(double) ? (const void*)A.U64 : (const void*)A.U32);
       launch_b_wilson<R>(S(), U, in, out, A.m0, A.Lx, A.Lt, nb, sub, skip);
@@ -148,6 +151,7 @@ struct BPre {
       const T* Ab = (const T*)(sizeof(R) == sizeof(double) ? (const void*)A.A64 : (const void*)A.A32);
       launch_b_block<R>(S(), Ab, in, out, A.Lx, A.Lt, nb, sub, skip);
     }
+    if (ta) timer_span(c, kt, ta, timer_mark(c, kt, S()), (long long)A.Lx * A.Lt * nb);
   }
 
   // two-step GMRES smoother from 0 (fused form): y = approximate A^{-1} v, r = v - A y
@@ -424,7 +428,10 @@ void BWork::cycle() {
     } else {
       pc64.cycle0(vj, zj);
     }
+    hipEvent_t ta = timer_mark(h->ctx, DMG_KT_WILSON_BATCHED, s);
     launch_b_wilson<double>(s, A.U64, zj, V + (j + 1) * ld, A.m0, A.Lx, A.Lt, nb, nullptr, outer.alldone());
+    if (ta) timer_span(h->ctx, DMG_KT_WILSON_BATCHED, ta, timer_mark(h->ctx, DMG_KT_WILSON_BATCHED, s),
+                       (long long)A.Lx * A.Lt * nb);
     fine++;
     launch_b_arnoldi<double>(s, V, ld, n, nb, j, bs, outer.alldone(), sh.P(), sh.C());
     if (sh.all_done(outer.alldone())) break;

@@ -48,7 +48,7 @@ EXPORTED = [
 SLOT_FREE, SLOT_RUNNING, SLOT_DONE = 0, 1, 2
 POOL_MAX_SLOTS = 8
 BATCH_MAX_LANES = 64
-KT_COARSE_PROJ, KT_BLOCK_APPLY_INT = 0, 1
+KT_COARSE_PROJ, KT_BLOCK_APPLY_INT, KT_BLOCK_BATCHED, KT_WILSON_BATCHED = 0, 1, 2, 3
 
 
 class DmgError(RuntimeError):

@@ -235,6 +235,29 @@ def test_solve_fp64_64_injected(dmg, ctx, injected):
         assert s["coarse_dr_calls"] == (1 if j == 0 else 0)
 
 
+def test_solve_nondeflated_64(dmg, ctx, injected):
+    """The non-deflated comparison method (d = NULL: every coarse solve is CG on the
+    normal equations to coarse_tol_first) reaches the same solution; with the first
+    coarse tolerance at 1e-8 on every call it needs many more coarse operator
+    applications than the deflated method on the same right-hand side."""
+    N, th, m0, H, g, hg = injected
+    if N != 64:
+        pytest.skip("workload-sized solve")
+    import scipy.sparse.linalg as spla
+    D = H.levels[0].A
+    b = synth.rhs(64, 0, 2)
+    st, s_nd, x_nd, res_nd = _solve_and_check(dmg, ctx, hg, D, b, None)
+    assert st == dmg.DMG_OK and s_nd["converged"] == 1 and res_nd <= 1e-8
+    assert s_nd["coarse_dr_calls"] == 0 and s_nd["coarse_calls"] > 0
+    xr = spla.splu(D.tocsc()).solve(b)
+    assert _rel(x_nd, xr) < 1e-6
+    d = dmg.Deflation(hg, 30, 10)
+    _solve_and_check(dmg, ctx, hg, D, synth.rhs(64, 0, 0), d)  # builds the deflation space
+    st, s_d, x_d, res_d = _solve_and_check(dmg, ctx, hg, D, b, d)
+    assert st == dmg.DMG_OK and res_d <= 1e-8
+    assert s_nd["coarse_mvps"] > 2 * s_d["coarse_mvps"], (s_nd["coarse_mvps"], s_d["coarse_mvps"])
+
+
 def test_solve_fp32_preconditioner_64(dmg, ctx, injected):
     N, th, m0, H, g, hg = injected
     if N != 64:
