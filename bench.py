@@ -34,6 +34,10 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 RHS_PER_CONFIG = 5
+# HBM bytes per launch of k_coarse_proj<double, false> from the FETCH_SIZE and WRITE_SIZE counter
+# passes (scaled by the reference streaming kernels) recorded in profiles/k_coarse_proj_256_hbm_traffic.md;
+# valid while that kernel is unchanged
+COARSE_TRAFFIC_BYTES = 72_644_198
 
 
 def parse():
@@ -55,6 +59,8 @@ def parse():
     ap.add_argument("--serve-configs", type=int, default=4, help="resident configurations per lattice size")
     ap.add_argument("--serve-requests", type=int, default=200, help="requests per arrival rate")
     ap.add_argument("--serve-capacity", type=int, default=16, help="lanes per resident configuration")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for hardware byte counters)")
     return ap.parse_args()
 
 
@@ -145,6 +151,16 @@ def main():
             "max_true_rel_resid": float(max(s["true_rel_resid"] for s in st32)),
         }
 
+    if a.calibrate_copy:
+        # plain streaming kernels of known size: uniform_ writes 256 MiB; mul reads 256 MiB
+        # and writes 256 MiB per launch
+        src = torch.empty(256 * 2 ** 20 // 4, dtype=torch.float32, device="cuda").uniform_()
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+
     # ------------------------------------------------------------ roofline of the dominant kernel
     roof = coarse_roofline(N, coarse_ms, coarse_launches, coarse_steps, el64)
     roof_int = measure_stencil_roofline(torch, dmg, ctx, res[step_cfgs[0]][1], N)
@@ -210,10 +226,14 @@ def coarse_roofline(N, total_ms, launches, steps, timed_s):
     sites = (N // 16) ** 2
     bytes_per_step = sites * 5 * 24 * 24 * 16
     achieved = steps * bytes_per_step / (total_ms * 1e-3) / 1e9 if total_ms > 0 else 0.0
+    per_launch = steps / max(launches, 1) * bytes_per_step
     return {"kernel": "k_coarse_proj<double, false> (persistent GMRES-Proj, coarse grid "
                       f"{N // 16}x{N // 16} sites x 24 dof)",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": COARSE_TRAFFIC_BYTES if N == 256 else None,
+            "traffic_unit": "HBM bytes per launch (counters, profiles/k_coarse_proj_256_hbm_traffic.md)",
+            "algorithmic_bytes_per_launch": per_launch,
             "avg_launch_us": total_ms / max(launches, 1) * 1e3, "launches": launches,
             "arnoldi_steps": steps, "us_per_step": total_ms * 1e3 / max(steps, 1),
             "algorithmic_bytes_per_step": bytes_per_step,
@@ -374,7 +394,14 @@ def served_form(torch, dmg, ctx, sizes, ncfg, n_req, cap, plain_rate):
     solved on its own (dmg_solve).  Latency = arrival to result ready.  The saturated rate (all requests at t = 0) sets
     the three arrival rates, 0.5x, 0.9x and 1.2x of it."""
     import synth
-    keys = [(N, c) for N in sizes for c in range(ncfg)]
+
+    def known(N, c):
+        try:
+            synth.critical_mass(N, c)
+            return True
+        except KeyError:
+            return False
+    keys = [(N, c) for N in sizes for c in range(ncfg) if known(N, c)]
     res, batches = {}, {}
     prm = dmg.solve_params(precond="fp32")
     t0 = time.perf_counter()
@@ -457,9 +484,8 @@ def served_form(torch, dmg, ctx, sizes, ncfg, n_req, cap, plain_rate):
     serve(reqs, [0.0] * len(reqs))  # warm the lanes of every batch in use
     reqs, _ = requests(1, n_req)
     sat, lat_sat, bad = serve(reqs, [0.0] * len(reqs))
-    out = {"workload": f"{len(keys)} resident configurations ({', '.join(str(n) + '^2' for n in sizes)} x "
-                       f"{ncfg}), single-RHS requests, Poisson arrivals, {cap} lanes per configuration, "
-                       f"FP32 preconditioner",
+    out = {"workload": f"{len(keys)} resident configurations ({', '.join(f'{n}^2 {c}' for n, c in keys)}), "
+                       f"single-RHS requests, Poisson arrivals, {cap} lanes per configuration, FP32 preconditioner",
            "requests_per_rate": n_req, "setup_s": setup_s, "resident_bytes": bytes_resident,
            "saturated": {"value": sat, "unit": "solves/s", "p50_ms": percentile(lat_sat, 50),
                          "p99_ms": percentile(lat_sat, 99), "failures": bad},

@@ -148,22 +148,25 @@ __device__ void fin_givens(BS& b, int j, double hn_sq) {
 __global__ void __launch_bounds__(BT) kb_final(const double2* __restrict__ part, BS* bs, FinArgs a) {
   const bool arn = a.mode == FIN_ARN1 || a.mode == FIN_ARN2 || a.mode == FIN_ARN3;
   if (arn && *a.alldone) return;
-  __shared__ double2 lanes[64][4];
+  // G lanes per quantity (the largest power of two with G * nq <= BT); each lane adds
+  // the partials of workgroups g, g + G, ..., then a fixed-order tree adds the lanes
+  __shared__ double2 lanes[BT];
   __shared__ double2 tot[64];
   const int r = blockIdx.x, t = threadIdx.x;
-  const int q = t >> 2, g = t & 3;
+  int G = 1;
+  while (2 * G * a.nq <= BT) G *= 2;
+  const int q = t / G, g = t % G;
   if (q < a.nq) {
-    double2 s0 = mk(0.0, 0.0), s1 = mk(0.0, 0.0);
-    int b = g;
-    for (; b + 4 < a.nblk; b += 8) {
-      s0 = cadd(s0, part[((int64_t)b * a.nq + q) * a.nb + r]);
-      s1 = cadd(s1, part[((int64_t)(b + 4) * a.nq + q) * a.nb + r]);
-    }
-    if (b < a.nblk) s0 = cadd(s0, part[((int64_t)b * a.nq + q) * a.nb + r]);
-    lanes[q][g] = cadd(s0, s1);
+    double2 s0 = mk(0.0, 0.0);
+    for (int b = g; b < a.nblk; b += G) s0 = cadd(s0, part[((int64_t)b * a.nq + q) * a.nb + r]);
+    lanes[t] = s0;
   }
   __syncthreads();
-  if (t < a.nq) tot[t] = cadd(cadd(lanes[t][0], lanes[t][1]), cadd(lanes[t][2], lanes[t][3]));
+  for (int w = G / 2; w >= 1; w /= 2) {
+    if (q < a.nq && g < w) lanes[t] = cadd(lanes[t], lanes[t + w]);
+    __syncthreads();
+  }
+  if (t < a.nq) tot[t] = lanes[t * G];
   __syncthreads();
   if (a.mode == FIN_SMOOTH2) {
     // two-step smoother: least-squares fit of v by [w1, w2] from the Gram entries
