@@ -30,12 +30,12 @@ struct BS {
   int active;  // this right-hand side takes part in the current solve
   int brk;     // breakdown
   int cap;     // steps allowed in this cycle
-  int pad_;
+  int pass2;   // the current Arnoldi step needs a second Gram-Schmidt pass
 };
 // Host copy of a BS tail (beta .. cap), read back after a cycle.
 struct BSTail {
   double beta, bnorm, tol_abs, est, wn0;
-  int steps, done, active, brk, cap, pad_;
+  int steps, done, active, brk, cap, pass2;
 };
 
 int bred_blocks(int64_t n_entries);
@@ -55,8 +55,11 @@ void launch_b_norm(hipStream_t s, const cx<R>* x, int64_t n, int nb, BS* bs, dou
 // y = x / beta_r (0 when beta_r == 0)
 template <typename R>
 void launch_b_scale_beta(hipStream_t s, const cx<R>* x, cx<R>* y, int64_t n, int nb, const BS* bs);
-// Arnoldi step j (CGS twice, norm, Givens update) on batched basis V (field stride ld
-// entries); a right-hand side is done once it converged, broke down or took cap steps.
+// Arnoldi step j on batched basis V (field stride ld entries): classical Gram-Schmidt
+// with the norm from ||w||^2 - ||h||^2, and a second pass only for the right-hand sides
+// where that difference cancels (below eta ||w||^2); Givens update; a right-hand side is
+// done once it converged, broke down or took cap steps.  eta: 1e-8 for FP64 vectors,
+// 1e-4 for FP32.
 template <typename R>
 void launch_b_arnoldi(hipStream_t s, cx<R>* V, int64_t ld, int64_t n, int nb, int j, BS* bs, int* alldone,
                       double2* part, unsigned* cnt);

@@ -70,8 +70,10 @@ struct FinArgs {
   double2* coef;
   const double2* M;
   const double2* Pi;
-  int* alldone;   // FIN_START / FIN_ARN3: set to 1 when every right-hand side is done
+  int* alldone;   // FIN_START / FIN_ARN1 / FIN_ARN3: set to 1 when every right-hand side is done
   unsigned* cnt;  // ticket of the alldone update
+  double eta;     // FIN_ARN1: cancellation threshold of the one-pass norm
+  int* anyp2;     // FIN_ARN1: set when some right-hand side needs a second pass
 };
 
 constexpr int LDH = MB + 1;
@@ -147,7 +149,9 @@ __device__ void fin_givens(BS& b, int j, double hn_sq) {
 
 __global__ void __launch_bounds__(BT) kb_final(const double2* __restrict__ part, BS* bs, FinArgs a) {
   const bool arn = a.mode == FIN_ARN1 || a.mode == FIN_ARN2 || a.mode == FIN_ARN3;
-  if (arn && *a.alldone) return;
+  if (a.mode == FIN_ARN1 && *a.alldone) return;
+  if ((a.mode == FIN_ARN2 || a.mode == FIN_ARN3) && !*a.anyp2) return;
+  (void)arn;
   // G lanes per quantity (the largest power of two with G * nq <= BT); each lane adds
   // the partials of workgroups g, g + G, ..., then a fixed-order tree adds the lanes
   __shared__ double2 lanes[BT];
@@ -200,23 +204,41 @@ __global__ void __launch_bounds__(BT) kb_final(const double2* __restrict__ part,
       if (t == 0) fin_start(b, tot[0].x, a);
       break;
     case FIN_ARN1:
+      // h = V^H w and ||w||^2: keep h as column j; one-pass norm ||w||^2 - ||h||^2 unless it
+      // cancels, then the Givens update at once, else flag a second pass
       if (!b.done) {
         for (int i = t; i <= MB; i += BT) {
           if (i <= j) b.H[LDH * j + i] = tot[i];
           else if (i > j + 1) b.H[LDH * j + i] = mk(0.0, 0.0);
         }
-        if (t == 0) b.wn0 = sqrt(tot[j + 1].x);
+        if (t == 0) {
+          const double ww = tot[j + 1].x;
+          double hh = 0.0;
+          for (int i = 0; i <= j; ++i) hh += cabs2(tot[i]);
+          b.wn0 = sqrt(ww);
+          const double rest = ww - hh;
+          if (rest > a.eta * ww) {
+            b.pass2 = 0;
+            fin_givens(b, j, rest);
+          } else {
+            b.pass2 = 1;
+            atomicOr(a.anyp2, 1);
+          }
+        }
       }
       break;
     case FIN_ARN2:
-      if (!b.done)
+      if (b.pass2)
         for (int i = t; i <= j; i += BT) {
           b.h2[i] = tot[i];
           b.H[LDH * j + i] = cadd(b.H[LDH * j + i], tot[i]);
         }
       break;
     case FIN_ARN3:
-      if (t == 0 && !b.done) fin_givens(b, j, tot[0].x);
+      if (t == 0 && b.pass2) {
+        b.pass2 = 0;
+        fin_givens(b, j, tot[0].x);
+      }
       break;
     case FIN_PROJ:
       if (b.active) {
@@ -236,7 +258,7 @@ __global__ void __launch_bounds__(BT) kb_final(const double2* __restrict__ part,
       }
       break;
   }
-  if (a.mode == FIN_START || a.mode == FIN_ARN3) {
+  if (a.mode == FIN_START || a.mode == FIN_ARN1 || a.mode == FIN_ARN3) {
     __shared__ int last;
     __threadfence();
     __syncthreads();
@@ -312,8 +334,9 @@ void launch_b_scale_beta(hipStream_t s, const cx<R>* x, cx<R>* y, int64_t n, int
 // (a) h_i = V_i^H w (i <= j) and ||w||^2 with w = V_{j+1}
 template <typename R>
 __global__ void __launch_bounds__(BT) kb_arn_dots1(const cx<R>* __restrict__ V, int64_t ld, int64_t n, int nb, int j,
-                                                   const int* alldone, double2* part) {
+                                                   const int* alldone, int* anyp2, double2* part) {
   if (*alldone) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *anyp2 = 0;
   const int64_t N = n * nb;
   const int64_t stride = (int64_t)gridDim.x * BT;
   const cx<R>* w = V + (int64_t)(j + 1) * ld;
@@ -332,13 +355,13 @@ __global__ void __launch_bounds__(BT) kb_arn_dots1(const cx<R>* __restrict__ V, 
   b_publish<MB + 2>(acc, j + 2, nb, part);
 }
 
-// (b) w -= sum_i H[i, j] V_i, then h2_i = V_i^H w (added to H[i, j] by the final phase)
+// (b) w -= sum_i H[i, j] V_i for the right-hand sides that took step j (one-pass) or need
+// a second pass; h2_i = V_i^H w of the updated w (used by the second-pass lanes)
 template <typename R>
 __global__ void __launch_bounds__(BT) kb_arn_update_dots2(cx<R>* __restrict__ V, int64_t ld, int64_t n, int nb, int j,
-                                                          const BS* bs, const int* alldone, double2* part) {
-  if (*alldone) return;
+                                                          const BS* bs, double2* part) {
   const int r0 = threadIdx.x & (nb - 1);
-  const bool skip = bs[r0].done != 0;
+  const bool skip = !(bs[r0].steps == j + 1 || bs[r0].pass2);
   double2 cf[MB + 1];
 #pragma unroll
   for (int i = 0; i < MB + 1; ++i) cf[i] = (i <= j) ? bs[r0].H[LDH * j + i] : mk(0.0, 0.0);
@@ -365,13 +388,13 @@ __global__ void __launch_bounds__(BT) kb_arn_update_dots2(cx<R>* __restrict__ V,
   b_publish<MB + 1>(acc, j + 1, nb, part);
 }
 
-// (c) w -= sum_i h2_i V_i and ||w||^2 (the final phase does the Givens update)
+// (c) second pass: w -= sum_i h2_i V_i and ||w||^2 for the flagged right-hand sides
 template <typename R>
 __global__ void __launch_bounds__(BT) kb_arn_update_norm(cx<R>* __restrict__ V, int64_t ld, int64_t n, int nb, int j,
-                                                         const BS* bs, const int* alldone, double2* part) {
-  if (*alldone) return;
+                                                         const BS* bs, const int* anyp2, double2* part) {
+  if (!*anyp2) return;
   const int r0 = threadIdx.x & (nb - 1);
-  const bool skip = bs[r0].done != 0;
+  const bool skip = bs[r0].pass2 == 0;
   double2 cf[MB + 1];
 #pragma unroll
   for (int i = 0; i < MB + 1; ++i) cf[i] = (i <= j) ? bs[r0].h2[i] : mk(0.0, 0.0);
@@ -414,19 +437,22 @@ template <typename R>
 void launch_b_arnoldi(hipStream_t s, cx<R>* V, int64_t ld, int64_t n, int nb, int j, BS* bs, int* alldone,
                       double2* part, unsigned* cnt) {
   const int G = bred_blocks(n * nb);
+  int* anyp2 = alldone + 1;
   FinArgs a = fin(FIN_ARN1, j + 2, G, nb);
   a.j = j;
   a.alldone = alldone;
   a.cnt = cnt;
-  hipLaunchKernelGGL(kb_arn_dots1<R>, dim3(G), dim3(BT), 0, s, (const cx<R>*)V, ld, n, nb, j, (const int*)alldone, part);
+  a.anyp2 = anyp2;
+  a.eta = sizeof(R) == sizeof(float) ? 1e-4 : 1e-8;
+  hipLaunchKernelGGL(kb_arn_dots1<R>, dim3(G), dim3(BT), 0, s, (const cx<R>*)V, ld, n, nb, j, (const int*)alldone,
+                     anyp2, part);
   launch_final(s, part, bs, a);
-  hipLaunchKernelGGL(kb_arn_update_dots2<R>, dim3(G), dim3(BT), 0, s, V, ld, n, nb, j, (const BS*)bs,
-                     (const int*)alldone, part);
+  hipLaunchKernelGGL(kb_arn_update_dots2<R>, dim3(G), dim3(BT), 0, s, V, ld, n, nb, j, (const BS*)bs, part);
   a.mode = FIN_ARN2;
   a.nq = j + 1;
   launch_final(s, part, bs, a);
   hipLaunchKernelGGL(kb_arn_update_norm<R>, dim3(G), dim3(BT), 0, s, V, ld, n, nb, j, (const BS*)bs,
-                     (const int*)alldone, part);
+                     (const int*)anyp2, part);
   a.mode = FIN_ARN3;
   a.nq = 1;
   launch_final(s, part, bs, a);

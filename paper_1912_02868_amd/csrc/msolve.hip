@@ -88,7 +88,7 @@ struct BShared {
   }
 };
 
-static_assert(offsetof(BS, pad_) - offsetof(BS, beta) + sizeof(int) == sizeof(BSTail), "BS tail layout");
+static_assert(offsetof(BS, pass2) - offsetof(BS, beta) + sizeof(int) == sizeof(BSTail), "BS tail layout");
 
 // The three-grid preconditioner on batched fields in precision R.
 template <typename R>
