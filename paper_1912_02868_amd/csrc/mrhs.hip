@@ -83,6 +83,7 @@ __device__ void fin_start(BS& b, double s2, const FinArgs& a) {
   if (a.bnorm_too) b.bnorm = beta;
   b.steps = 0;
   b.brk = 0;
+  b.pass2 = 0;
   for (int i = 0; i <= MB; ++i) {
     b.g[i] = (i == 0) ? mk(beta, 0.0) : mk(0.0, 0.0);
     b.c[i] = b.g[i];
@@ -228,15 +229,15 @@ __global__ void __launch_bounds__(BT) kb_final(const double2* __restrict__ part,
       }
       break;
     case FIN_ARN2:
-      if (b.pass2)
+      if (b.pass2 == 1)
         for (int i = t; i <= j; i += BT) {
           b.h2[i] = tot[i];
           b.H[LDH * j + i] = cadd(b.H[LDH * j + i], tot[i]);
         }
       break;
     case FIN_ARN3:
-      if (t == 0 && b.pass2) {
-        b.pass2 = 0;
+      if (t == 0 && b.pass2 == 1) {
+        b.pass2 = 2;  // normalised by the next kernel
         fin_givens(b, j, tot[0].x);
       }
       break;
@@ -361,10 +362,18 @@ template <typename R>
 __global__ void __launch_bounds__(BT) kb_arn_update_dots2(cx<R>* __restrict__ V, int64_t ld, int64_t n, int nb, int j,
                                                           const BS* bs, double2* part) {
   const int r0 = threadIdx.x & (nb - 1);
-  const bool skip = !(bs[r0].steps == j + 1 || bs[r0].pass2);
+  const BS& b = bs[r0];
+  const bool one = b.steps == j + 1 && b.pass2 == 0;  // finished step j in one pass
+  const bool skip = !(one || b.pass2 == 1);
+  // one-pass lanes are normalised here: v_{j+1} = (w - V h) / h_{j+1, j}
+  double scale = 1.0;
+  if (one && !b.brk) {
+    const double hn = b.H[LDH * j + j + 1].x;
+    if (hn != 0.0) scale = 1.0 / hn;
+  }
   double2 cf[MB + 1];
 #pragma unroll
-  for (int i = 0; i < MB + 1; ++i) cf[i] = (i <= j) ? bs[r0].H[LDH * j + i] : mk(0.0, 0.0);
+  for (int i = 0; i < MB + 1; ++i) cf[i] = (i <= j) ? b.H[LDH * j + i] : mk(0.0, 0.0);
   const int64_t N = n * nb;
   const int64_t stride = (int64_t)gridDim.x * BT;
   cx<R>* w = V + (int64_t)(j + 1) * ld;
@@ -377,7 +386,7 @@ __global__ void __launch_bounds__(BT) kb_arn_update_dots2(cx<R>* __restrict__ V,
 #pragma unroll
       for (int i = 0; i < MB + 1; ++i)
         if (i <= j) wv = csub(wv, cmul(cf[i], to_d(V[(int64_t)i * ld + e])));
-      const cx<R> st = from_d<R>(wv);
+      const cx<R> st = from_d<R>(cscale(wv, scale));
       w[e] = st;
       wv = to_d(st);
     }
@@ -394,7 +403,7 @@ __global__ void __launch_bounds__(BT) kb_arn_update_norm(cx<R>* __restrict__ V, 
                                                          const BS* bs, const int* anyp2, double2* part) {
   if (!*anyp2) return;
   const int r0 = threadIdx.x & (nb - 1);
-  const bool skip = bs[r0].pass2 == 0;
+  const bool skip = bs[r0].pass2 != 1;
   double2 cf[MB + 1];
 #pragma unroll
   for (int i = 0; i < MB + 1; ++i) cf[i] = (i <= j) ? bs[r0].h2[i] : mk(0.0, 0.0);
@@ -417,13 +426,15 @@ __global__ void __launch_bounds__(BT) kb_arn_update_norm(cx<R>* __restrict__ V, 
   b_publish<1>(acc, 1, nb, part);
 }
 
-// (d) V_{j+1} = w / h_{j+1, j} for the right-hand sides that took step j
+// (d) V_{j+1} = w / h_{j+1, j} for the right-hand sides that took a second pass (the others
+// were normalised by (b))
 template <typename R>
 __global__ void __launch_bounds__(BT) kb_arn_normalize(cx<R>* __restrict__ V, int64_t ld, int64_t n, int nb, int j,
-                                                       const BS* bs) {
+                                                       const BS* bs, const int* anyp2) {
+  if (!*anyp2) return;
   const int r0 = threadIdx.x & (nb - 1);
   const BS& b = bs[r0];
-  if (b.steps != j + 1 || b.brk) return;
+  if (b.pass2 != 2 || b.steps != j + 1 || b.brk) return;
   const double hn = b.H[LDH * j + j + 1].x;
   if (hn == 0.0) return;
   const double inv = 1.0 / hn;
@@ -456,7 +467,8 @@ void launch_b_arnoldi(hipStream_t s, cx<R>* V, int64_t ld, int64_t n, int nb, in
   a.mode = FIN_ARN3;
   a.nq = 1;
   launch_final(s, part, bs, a);
-  hipLaunchKernelGGL(kb_arn_normalize<R>, dim3(vec_blocks(n * nb)), dim3(BT), 0, s, V, ld, n, nb, j, (const BS*)bs);
+  hipLaunchKernelGGL(kb_arn_normalize<R>, dim3(vec_blocks(n * nb)), dim3(BT), 0, s, V, ld, n, nb, j, (const BS*)bs,
+                     (const int*)anyp2);
   DMG_LAUNCH_CHECK();
 }
 
