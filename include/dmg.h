@@ -226,6 +226,8 @@ typedef struct {
                               launch (default), 2 plain launch (only when nothing else runs on
                               the device: the grid must become co-resident); 0: one launch per
                               Arnoldi sub-step */
+  int int_mode;            /* intermediate grid: 0 partial solve (FGMRES(int_m) to int_tol, the
+                              default); 1 one intermediate cycle (smoothing-only treatment) */
 } dmg_solve_params;
 
 typedef struct {
@@ -238,7 +240,9 @@ typedef struct {
   double elapsed_ms;
 } dmg_solve_stats;
 
-/* Fill p with the paper's defaults. */
+/* Fill p with the paper's defaults.  GMRES-DR (first coarse call) also ends when a cycle
+ * lowers its residual by less than 1 % (a tolerance such as 1e-15 that the arithmetic
+ * cannot reach). */
 void dmg_solve_params_default(dmg_solve_params* p);
 void dmg_setup_params_default(dmg_setup_params* p);
 
@@ -253,6 +257,19 @@ void dmg_setup_params_default(dmg_setup_params* p);
  * written). */
 dmg_status dmg_solve(dmg_context* ctx, dmg_hierarchy* h, dmg_deflation* d, const dmg_solve_params* prm,
                      const void* b, void* x, int nrhs, int ptr_kind, dmg_solve_stats* stats);
+
+/* Fine-grid comparison solvers without multigrid (the paper's baselines, Results):
+ *   DMG_FINE_CGNE      CG on D D^dagger y = b, x = D^dagger y, all nrhs fields in one
+ *                      batched CG (m, k ignored); stats: outer_iters = CG iterations,
+ *                      fine_mvps = 2 per iteration + 1
+ *   DMG_FINE_GMRES_DR  GMRES-DR(m, k) on D from 0 for each right-hand side with a fresh
+ *                      deflation space (2 <= m <= 64, 1 <= k < m, k <= 31); outer_iters =
+ *                      Arnoldi steps
+ * Both stop at relative residual tol (max_iters: CG iterations or Arnoldi steps) and report
+ * the true relative residual.  b, x: nrhs fields (host or device by ptr_kind). */
+enum { DMG_FINE_CGNE = 0, DMG_FINE_GMRES_DR = 1 };
+dmg_status dmg_solve_fine(dmg_context* ctx, dmg_hierarchy* h, int method, int m, int k, double tol, int max_iters,
+                          const void* b, void* x, int nrhs, int ptr_kind, dmg_solve_stats* stats);
 
 /* Solves D x = b for nrhs right-hand sides of one hierarchy jointly: the method of
  * dmg_solve (outer FGMRES(outer_m), the three-grid cycle with the partial

@@ -161,6 +161,7 @@ class SolveInfo:
     cycles: int = 0
     rel_resid: float = np.nan
     converged: bool = False
+    stagnated: bool = False
     history: list = field(default_factory=list)
 
 
@@ -271,14 +272,16 @@ def _compress(V, H_bar, k, s=None):
     return Vk1, Hk, P, theta
 
 
-def gmres_dr(A, b, m, k, tol, max_cycles=1000):
+def gmres_dr(A, b, m, k, tol, max_cycles=1000, stall=0.99):
     """GMRES-DR(m, k) from x0 = 0 (Morgan, deflated restarting).
 
     Returns (x, info, Deflation).  Each cycle extends the Arnoldi relation to m
     columns, solves min || c - Hbar d ||, and restarts with the k smallest
     harmonic Ritz vectors plus the residual direction, so that the kept space
     satisfies A V_k = V_{k+1} Hbar_k.  On termination the space is compressed
-    once more to k vectors for later projections.
+    once more to k vectors for later projections.  A cycle that lowers the
+    residual by less than the factor `stall` ends the solve (a tolerance below
+    what the arithmetic reaches, such as 1e-15, otherwise never stops).
     """
     n = b.shape[0]
     x = np.zeros_like(b)
@@ -320,6 +323,10 @@ def gmres_dr(A, b, m, k, tol, max_cycles=1000):
         info.history.append(est / bn)
         if converged or hn == 0.0:
             info.converged = True
+            info.rel_resid = est / bn
+            break
+        if stall and len(info.history) > 1 and info.history[-1] > stall * info.history[-2]:
+            info.stagnated = True
             info.rel_resid = est / bn
             break
         s = c - H @ d

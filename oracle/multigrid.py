@@ -57,6 +57,9 @@ class Params:
     coarse_tol_later: float = 1e-2
     deflate: bool = True
     coarse_cgne_tol: float = 1e-8
+    # "partial": the intermediate grid is solved by FGMRES to int_tol (the paper's partial
+    # solve); "cycle": one intermediate cycle M1 (smoothing-only intermediate treatment)
+    intermediate: str = "partial"
 
 
 @dataclass
@@ -276,12 +279,14 @@ class Hierarchy:
         return x
 
     def cycle0(self, v):
-        """Fine cycle M0: smooth, intermediate partial solve, smooth."""
+        """Fine cycle M0: smooth, intermediate partial solve (or one intermediate cycle), smooth."""
         p = self.params
         A = self._op(0)
         P = self.levels[0].P
         y1, r = krylov.gmres_steps(A, v, p.smooth_steps)
-        y2 = y1 + P @ self.partial_solve(P.conj().T @ r)
+        rh = P.conj().T @ r
+        e = self.partial_solve(rh) if p.intermediate == "partial" else self.cycle1(rh)
+        y2 = y1 + P @ e
         r2 = v - A(y2)
         y3 = y2 + krylov.gmres_steps(A, r2, p.smooth_steps)[0]
         return y3

@@ -129,6 +129,7 @@ void dmg_solve_params_default(dmg_solve_params* p) {
   p->precond = DMG_FP64;
   p->use_x0 = 0;
   p->coarse_persistent = 1;
+  p->int_mode = 0;
 }
 
 void dmg_setup_params_default(dmg_setup_params* p) {
@@ -488,7 +489,8 @@ dmg_status dmg_solve(dmg_context* ctx, dmg_hierarchy* h, dmg_deflation* d, const
     dmg_solve_params_default(&p);
     if (prm) p = *prm;
     DMG_CHECK(p.tol > 0.0 && p.int_tol > 0.0 && p.coarse_tol_first > 0.0 && p.coarse_tol_later > 0.0 &&
-                  p.max_outer_iters >= 1 && p.int_max_iters >= 1 && p.coarse_max_iters >= 1,
+                  p.max_outer_iters >= 1 && p.int_max_iters >= 1 && p.coarse_max_iters >= 1 &&
+                  (p.int_mode == 0 || p.int_mode == 1),
               DMG_E_INVALID, "solve parameters");
     const int64_t n = h->op[0].n;
     const size_t fb = sizeof(double2) * n;
@@ -581,6 +583,35 @@ dmg_status dmg_hierarchy_apply_batched(dmg_hierarchy* h, int level, int op, dmg_
   });
 }
 
+dmg_status dmg_solve_fine(dmg_context* ctx, dmg_hierarchy* h, int method, int m, int k, double tol, int max_iters,
+                          const void* b, void* x, int nrhs, int ptr_kind, dmg_solve_stats* stats) {
+  if (!ctx || !h) return DMG_E_INVALID;
+  return guard(ctx, [&]() -> dmg_status {
+    DMG_CHECK(h->ctx == ctx, DMG_E_INVALID, "hierarchy belongs to another context");
+    DMG_CHECK(b && x && nrhs >= 1 && nrhs <= 64 && tol > 0.0 && max_iters >= 1, DMG_E_INVALID,
+              "solve_fine: bad arguments");
+    DMG_CHECK(method == DMG_FINE_CGNE || method == DMG_FINE_GMRES_DR, DMG_E_INVALID, "solve_fine: method");
+    DMG_CHECK(ptr_kind == DMG_PTR_HOST || ptr_kind == DMG_PTR_DEVICE, DMG_E_INVALID, "pointer kind");
+    const int64_t n = h->op[0].n;
+    const size_t fb = sizeof(double2) * n * nrhs;
+    DevBuf bb, xb;
+    const double2* bd = (const double2*)b;
+    double2* xd = (double2*)x;
+    if (ptr_kind == DMG_PTR_HOST) {
+      DMG_CHECK(all_finite((const double*)b, 2 * (size_t)n * nrhs), DMG_E_NONFINITE, "non-finite right-hand side");
+      bb.alloc(ctx, fb);
+      xb.alloc(ctx, fb);
+      to_device(ctx, bb.p, b, fb, ptr_kind);
+      bd = bb.as<double2>();
+      xd = xb.as<double2>();
+    }
+    dmg_status st = fine_solve(h, method, m, k, tol, max_iters, bd, xd, nrhs, stats);
+    if (ptr_kind == DMG_PTR_HOST) from_device(ctx, x, xb.p, fb, ptr_kind);
+    else DMG_HIP(hipStreamSynchronize(ctx->stream));
+    return st;
+  });
+}
+
 dmg_status dmg_solve_batched(dmg_context* ctx, dmg_hierarchy* h, dmg_deflation* d, const dmg_solve_params* prm,
                              const void* b, void* x, int nrhs, int ptr_kind, dmg_solve_stats* stats) {
   if (!ctx || !h) return DMG_E_INVALID;
@@ -595,8 +626,10 @@ dmg_status dmg_solve_batched(dmg_context* ctx, dmg_hierarchy* h, dmg_deflation* 
     if (prm) p = *prm;
     DMG_CHECK(p.tol > 0.0 && p.int_tol > 0.0 && p.coarse_tol_later > 0.0 && p.max_outer_iters >= 1 &&
                   p.int_max_iters >= 1 && p.coarse_max_iters >= 1 && p.outer_m >= 1 && p.outer_m <= 24 &&
-                  p.int_m >= 1 && p.int_m <= 24 && p.smooth_steps == 2 && !p.use_x0 && d->m - d->kk <= 24,
-              DMG_E_INVALID, "solve_batched parameters (restart lengths <= 24, two smoothing steps, no x0)");
+                  p.int_m >= 1 && p.int_m <= 24 && p.smooth_steps == 2 && !p.use_x0 && d->m - d->kk <= 24 &&
+                  p.int_mode == 0,
+              DMG_E_INVALID, "solve_batched parameters (restart lengths <= 24, two smoothing steps, no x0, "
+                             "partial intermediate solve)");
     const int64_t n = h->op[0].n;
     const size_t fb = sizeof(double2) * n * nrhs;
     if (p.precond == DMG_FP32) prepare_deflation_fp32(&h->main, d);

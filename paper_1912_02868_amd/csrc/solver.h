@@ -150,10 +150,14 @@ namespace dmg {
 
 // setup (near-null vectors, prolongators, Galerkin operators), on h->main
 void build_hierarchy(dmg_hierarchy* h, const double2* start0, const double2* start1, int inject);
-// GMRES-DR on the coarse operator in FP64 from x = 0; fills the deflation space.
-// Returns the Arnoldi steps taken.
+// GMRES-DR on the operator of level lvl (2: coarse) in FP64 from x = 0; fills the
+// deflation space.  Returns the Arnoldi steps taken.
 int coarse_gmres_dr(dmg_hierarchy* h, Work* w, dmg_deflation* d, const double2* b, double2* x, double tol,
-                    int max_iters);
+                    int max_iters, int lvl = 2);
+// fine-grid comparison solvers without multigrid: CG on D D^dagger (x = D^dagger y) for
+// nrhs fields at once, or GMRES-DR(m, k) per right-hand side
+dmg_status fine_solve(dmg_hierarchy* h, int method, int m, int k, double tol, int max_iters, const double2* b,
+                      double2* x, int nrhs, dmg_solve_stats* st);
 // outer solve of one right-hand side (device buffers b, x; x holds x0 when use_x0) on workspace w
 dmg_status outer_solve(dmg_hierarchy* h, Work* w, dmg_deflation* d, const dmg_solve_params* p, const double2* b,
                        double2* x, dmg_solve_stats* st);

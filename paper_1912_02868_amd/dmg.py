@@ -38,7 +38,7 @@ EXPORTED = [
     "dmg_hierarchy_apply", "dmg_hierarchy_apply_batched",
     "dmg_deflation_create", "dmg_deflation_build", "dmg_deflation_reset", "dmg_deflation_ready",
     "dmg_deflation_export", "dmg_deflation_destroy",
-    "dmg_solve_params_default", "dmg_setup_params_default", "dmg_solve", "dmg_solve_batched",
+    "dmg_solve_params_default", "dmg_setup_params_default", "dmg_solve", "dmg_solve_batched", "dmg_solve_fine",
     "dmg_kernel_timer", "dmg_kernel_timer_read",
     "dmg_pool_create", "dmg_pool_admit", "dmg_pool_step", "dmg_pool_retire", "dmg_pool_slot_state",
     "dmg_pool_destroy",
@@ -72,7 +72,7 @@ class SolveParams(C.Structure):
                 ("smooth_steps", C.c_int), ("int_tol", C.c_double), ("int_m", C.c_int),
                 ("int_max_iters", C.c_int), ("coarse_tol_first", C.c_double),
                 ("coarse_tol_later", C.c_double), ("coarse_max_iters", C.c_int),
-                ("precond", C.c_int), ("use_x0", C.c_int), ("coarse_persistent", C.c_int)]
+                ("precond", C.c_int), ("use_x0", C.c_int), ("coarse_persistent", C.c_int), ("int_mode", C.c_int)]
 
 
 class SolveStats(C.Structure):
@@ -144,6 +144,7 @@ def lib():
         "dmg_setup_params_default": (None, [C.POINTER(SetupParams)]),
         "dmg_solve": (i, [vp, vp, vp, C.POINTER(SolveParams), vp, vp, i, i, C.POINTER(SolveStats)]),
         "dmg_solve_batched": (i, [vp, vp, vp, C.POINTER(SolveParams), vp, vp, i, i, C.POINTER(SolveStats)]),
+        "dmg_solve_fine": (i, [vp, vp, i, i, i, d, i, vp, vp, i, i, C.POINTER(SolveStats)]),
         "dmg_kernel_timer": (i, [vp, i]),
         "dmg_pool_create": (i, [vp, i, C.POINTER(SolveParams), pp]),
         "dmg_pool_admit": (i, [vp, i, vp, vp, vp, i]),
@@ -393,6 +394,21 @@ class Deflation:
             self.close()
         except Exception:
             pass
+
+
+FINE_CGNE, FINE_GMRES_DR = 0, 1
+
+
+def solve_fine(ctx: Context, hier: Hierarchy, method: int, b, x, nrhs: int = 1, tol: float = 1e-8,
+               max_iters: int = 100000, m: int = 40, k: int = 10):
+    """Fine-grid comparison solvers without multigrid; returns (status, [stats dicts])."""
+    pb, kb = _ptr(b)
+    px, kx = _ptr(x)
+    assert kb == kx
+    stats = (SolveStats * nrhs)()
+    st = lib().dmg_solve_fine(ctx.h, hier.h, method, m, k, tol, max_iters, pb, px, nrhs, kb, stats)
+    ctx.check(st, "solve_fine")
+    return st, [s.as_dict() for s in stats]
 
 
 def solve_batched(ctx: Context, hier: Hierarchy, defl, b, x, nrhs: int, params: SolveParams | None = None):

@@ -258,6 +258,54 @@ def test_solve_nondeflated_64(dmg, ctx, injected):
     assert s_nd["coarse_mvps"] > 2 * s_d["coarse_mvps"], (s_nd["coarse_mvps"], s_d["coarse_mvps"])
 
 
+def test_solve_smoothing_only_schedule_64(dmg, ctx, injected):
+    """Smoothing-only intermediate treatment (one intermediate cycle) with the oversolved
+    coarse schedule 1e-15 then 1e-8 (the first coarse call ends at the GMRES-DR
+    stagnation exit): the outer solve still reaches 1e-8 and sparse LU's solution."""
+    N, th, m0, H, g, hg = injected
+    if N != 64:
+        pytest.skip("workload-sized solve")
+    import scipy.sparse.linalg as spla
+    D = H.levels[0].A
+    d = dmg.Deflation(hg, 30, 10)
+    b = synth.rhs(64, 0, 4)
+    st, s, x, res = _solve_and_check(dmg, ctx, hg, D, b, d, int_mode=1, coarse_tol_first=1e-15,
+                                     coarse_tol_later=1e-8)
+    assert st == dmg.DMG_OK and s["converged"] == 1 and res <= 1e-8
+    assert s["coarse_dr_calls"] == 1 and s["int_mvps"] > 0
+    assert _rel(x, spla.splu(D.tocsc()).solve(b)) < 1e-6
+
+
+def test_fine_baselines_64(dmg, ctx, injected):
+    """Fine-grid comparison solvers without multigrid (CGNE on two right-hand sides at once,
+    GMRES-DR(40, 10)) reach 1e-8 and sparse LU's solution, and need many more fine-grid
+    operator applications than the deflated multigrid solve (eq. (1) fine-equivalent
+    count) on the same right-hand side."""
+    N, th, m0, H, g, hg = injected
+    if N != 64:
+        pytest.skip("workload-sized solve")
+    import scipy.sparse.linalg as spla
+    D = H.levels[0].A
+    lu = spla.splu(D.tocsc())
+    b = np.stack([synth.rhs(64, 0, 5), synth.rhs(64, 0, 6)])
+    x = np.zeros_like(b)
+    st, stats = dmg.solve_fine(ctx, hg, dmg.FINE_CGNE, b, x, 2)
+    assert st == dmg.DMG_OK
+    for f in range(2):
+        res = np.linalg.norm(b[f] - D @ x[f]) / np.linalg.norm(b[f])
+        assert stats[f]["converged"] == 1 and res <= 1e-8 * (1 + 1e-6) and abs(res - stats[f]["true_rel_resid"]) < 1e-12
+        assert _rel(x[f], lu.solve(b[f])) < 1e-6
+    x1 = np.zeros_like(b[0])
+    st, sdr = dmg.solve_fine(ctx, hg, dmg.FINE_GMRES_DR, b[0], x1, 1, m=40, k=10)
+    assert st == dmg.DMG_OK and sdr[0]["converged"] == 1
+    assert np.linalg.norm(b[0] - D @ x1) / np.linalg.norm(b[0]) <= 1e-8 * (1 + 1e-6)
+    assert _rel(x1, lu.solve(b[0])) < 1e-6
+    d = dmg.Deflation(hg, 30, 10)
+    _solve_and_check(dmg, ctx, hg, D, synth.rhs(64, 0, 0), d)
+    st, smg, xm, resm = _solve_and_check(dmg, ctx, hg, D, b[0], d)
+    assert smg["fine_equiv_mvps"] < stats[0]["fine_mvps"] and smg["fine_equiv_mvps"] < sdr[0]["fine_mvps"]
+
+
 def test_solve_fp32_preconditioner_64(dmg, ctx, injected):
     N, th, m0, H, g, hg = injected
     if N != 64:

@@ -117,6 +117,21 @@ def test_gmres_dr_relation_after_every_restart(monkeypatch):
     assert len(seen) >= 2 and max(seen) < 1e-12
 
 
+def test_gmres_dr_unreachable_tolerance_stops():
+    """Tolerance 1e-15 is below what FP64 reaches on this system: the stagnation exit ends
+    the solve near the arithmetic's floor, and the stored space still satisfies
+    A V_k = V_{k+1} Hbar_k."""
+    A = _dirac(8, 0, 0.02)
+    b = synth.rhs(8, 0, 3)
+    x, info, defl = krylov.gmres_dr(_op(A), b, 20, 6, 1e-15, max_cycles=200)
+    assert info.cycles < 200
+    assert info.stagnated or info.converged
+    assert np.linalg.norm(b - A @ x) / np.linalg.norm(b) < 1e-12
+    k = defl.k
+    rel = np.linalg.norm(A @ defl.V[:, :k] - defl.V @ defl.H) / np.linalg.norm(defl.H)
+    assert rel < 1e-10
+
+
 def test_gmres_dr_k0_is_gmres():
     A = _dirac(8, 2, 0.05)
     b = synth.rhs(8, 2, 2)

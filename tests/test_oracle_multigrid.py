@@ -146,6 +146,22 @@ def test_non_deflated_variant_solves(h16):
     assert info.converged and np.linalg.norm(b - Hn.levels[0].A @ x) / np.linalg.norm(b) <= 1e-8
 
 
+def test_smoothing_only_variant_solves(h16):
+    """The paper's smoothing-only intermediate treatment (one intermediate cycle instead of
+    the partial solve) with the oversolved coarse schedule 1e-15 (first call, ended by the
+    GMRES-DR stagnation exit) then 1e-8: the solve still reaches 1e-8 and sparse LU's
+    solution."""
+    H, th, m0 = h16
+    Hs = multigrid.Hierarchy(th, m0, synth.near_null_starts(16, 2, 0), synth.near_null_starts(16, 2, 1),
+                             multigrid.Params(intermediate="cycle", coarse_tol_first=1e-15, coarse_tol_later=1e-8))
+    b = synth.rhs(16, 2, 2)
+    x, info = Hs.solve(b)
+    D = Hs.levels[0].A
+    assert info.converged and np.linalg.norm(b - D @ x) / np.linalg.norm(b) <= 1e-8
+    xr = spla.splu(D.tocsc()).solve(b)
+    assert np.linalg.norm(x - xr) / np.linalg.norm(xr) < 1e-6
+
+
 def test_fine_equivalent_weights(h16):
     H, _, _ = h16
     c = multigrid.Counters(fine=10, inter=8, coarse=64, n_fine=512, n_int=384, n_coarse=24)
