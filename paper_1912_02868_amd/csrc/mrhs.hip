@@ -11,7 +11,7 @@
 namespace dmg {
 
 constexpr int BT = 256;      // threads of the vector and reduction kernels
-constexpr int BMAXBLK = 128; // most workgroups of a reduction
+constexpr int BMAXBLK = 512; // most workgroups of a reduction
 
 int bred_blocks(int64_t N) {
   int64_t b = (N + BT * 2 - 1) / (BT * 2);
@@ -31,7 +31,8 @@ __device__ inline double2 bcdiv(double2 a, double2 b) {
 }
 
 // Block partials of the per-thread accumulators acc[q], q < nq, into
-// part[(block * nq + q) * nb + r]; threads with the same r are added in thread order.
+// part[(r * nq + q) * G + block] (G workgroups, so that the second phase reads each
+// right-hand side's partials contiguously); threads with the same r are added in thread order.
 template <int NQ>
 __device__ void b_publish(const double2 (&acc)[NQ], int nq, int nb, double2* part) {
   __shared__ double2 red[4][BT];
@@ -49,7 +50,7 @@ __device__ void b_publish(const double2 (&acc)[NQ], int nq, int nb, double2* par
         if (q0 + u < nq) {
           double2 s = red[u][r];
           for (int k = 1; k < per; ++k) s = cadd(s, red[u][k * nb + r]);
-          part[((int64_t)blockIdx.x * nq + q0 + u) * nb + r] = s;
+          part[((int64_t)r * nq + q0 + u) * gridDim.x + blockIdx.x] = s;
         }
       }
       __syncthreads();
@@ -163,7 +164,8 @@ __global__ void __launch_bounds__(BT) kb_final(const double2* __restrict__ part,
   const int q = t / G, g = t % G;
   if (q < a.nq) {
     double2 s0 = mk(0.0, 0.0);
-    for (int b = g; b < a.nblk; b += G) s0 = cadd(s0, part[((int64_t)b * a.nq + q) * a.nb + r]);
+    const double2* pq = part + ((int64_t)r * a.nq + q) * a.nblk;
+    for (int b = g; b < a.nblk; b += G) s0 = cadd(s0, pq[b]);
     lanes[t] = s0;
   }
   __syncthreads();
@@ -711,9 +713,80 @@ __global__ void __launch_bounds__(BT) kb_wilson(const cx<R>* __restrict__ U, con
   out[o1] = acc1;
 }
 
+// FP32 form with two lanes per thread: each neighbour spin is one 16-byte load covering both lanes,
+// and the output stores are nontemporal (the 2 x nb x 8 B written per site are not re-read by this
+// kernel).  The per-lane arithmetic is the same sequence of operations as kb_wilson's.
+__device__ inline float2 half2of(float4 v, int h) { return h ? make_float2(v.z, v.w) : make_float2(v.x, v.y); }
+
+__global__ void __launch_bounds__(BT) kb_wilson_pair(const float2* __restrict__ U, const float4* __restrict__ in,
+                                                     float4* __restrict__ out, float diag, int Nx, int Nt, int nb,
+                                                     const float4* __restrict__ sub, const int* skip) {
+  if (skip && *skip) return;
+  const int hb = nb >> 1;  // lane pairs = float4 per (site, spin); a power of two
+  const int lg = __ffs(hb) - 1;
+  const int64_t idx = (int64_t)blockIdx.x * BT + threadIdx.x;
+  const int V = Nx * Nt;
+  if (idx >= (int64_t)V * hb) return;
+  const int s = (int)(idx >> lg), rp = (int)(idx & (hb - 1));
+  const int x = s % Nx, t = s / Nx;
+  const int xp = (x + 1 == Nx) ? 0 : x + 1, xm = (x == 0) ? Nx - 1 : x - 1;
+  const int tp = (t + 1 == Nt) ? 0 : t + 1, tm = (t == 0) ? Nt - 1 : t - 1;
+  const int sxp = xp + Nx * t, sxm = xm + Nx * t, stp = x + Nx * tp, stm = x + Nx * tm;
+  auto at = [&](int site, int spin) { return in[((int64_t)(2 * site + spin) << lg) + rp]; };
+  const float4 a0 = at(s, 0), a1 = at(s, 1);
+  const float4 p0 = at(sxp, 0), p1 = at(sxp, 1), m0 = at(sxm, 0), m1 = at(sxm, 1);
+  const float4 u0 = at(stp, 0), u1 = at(stp, 1), n0 = at(stm, 0), n1 = at(stm, 1);
+  const float2 ux = U[2 * s], uxm = U[2 * sxm], ut = U[2 * s + 1], utm = U[2 * stm + 1];
+  float r0[4], r1[4];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    float2 acc0 = cscale(half2of(a0, h), diag), acc1 = cscale(half2of(a1, h), diag);
+    {
+      const float2 z = cmul(ux, csub(half2of(p0, h), half2of(p1, h)));
+      acc0 = csub(acc0, cscale(z, 0.5f));
+      acc1 = cadd(acc1, cscale(z, 0.5f));
+    }
+    {
+      const float2 z = cmulc(uxm, cadd(half2of(m0, h), half2of(m1, h)));
+      acc0 = csub(acc0, cscale(z, 0.5f));
+      acc1 = csub(acc1, cscale(z, 0.5f));
+    }
+    {
+      const float2 z = cmul(ut, cadd(half2of(u0, h), bmul_i(half2of(u1, h))));
+      acc0 = csub(acc0, cscale(z, 0.5f));
+      acc1 = cadd(acc1, cscale(bmul_i(z), 0.5f));
+    }
+    {
+      const float2 z = cmulc(utm, csub(half2of(n0, h), bmul_i(half2of(n1, h))));
+      acc0 = csub(acc0, cscale(z, 0.5f));
+      acc1 = csub(acc1, cscale(bmul_i(z), 0.5f));
+    }
+    r0[2 * h] = acc0.x; r0[2 * h + 1] = acc0.y;
+    r1[2 * h] = acc1.x; r1[2 * h + 1] = acc1.y;
+  }
+  const int64_t i0 = ((int64_t)(2 * s) << lg) + rp, i1 = i0 + hb;
+  if (sub) {
+    const float4 s0 = sub[i0], s1 = sub[i1];
+    r0[0] = s0.x - r0[0]; r0[1] = s0.y - r0[1]; r0[2] = s0.z - r0[2]; r0[3] = s0.w - r0[3];
+    r1[0] = s1.x - r1[0]; r1[1] = s1.y - r1[1]; r1[2] = s1.z - r1[2]; r1[3] = s1.w - r1[3];
+  }
+  typedef float f4v __attribute__((ext_vector_type(4)));
+  __builtin_nontemporal_store(f4v{r0[0], r0[1], r0[2], r0[3]}, reinterpret_cast<f4v*>(out + i0));
+  __builtin_nontemporal_store(f4v{r1[0], r1[1], r1[2], r1[3]}, reinterpret_cast<f4v*>(out + i1));
+}
+
 template <typename R>
 void launch_b_wilson(hipStream_t s, const cx<R>* U, const cx<R>* in, cx<R>* out, double m0, int Nx, int Nt, int nb,
                      const cx<R>* sub, const int* skip) {
+  if constexpr (sizeof(R) == sizeof(float)) {
+    if (nb >= 2) {
+      const int64_t N2 = (int64_t)Nx * Nt * (nb / 2);
+      hipLaunchKernelGGL(kb_wilson_pair, dim3((unsigned)((N2 + BT - 1) / BT)), dim3(BT), 0, s, (const float2*)U,
+                         (const float4*)in, (float4*)out, (float)(m0 + 2.0), Nx, Nt, nb, (const float4*)sub, skip);
+      DMG_LAUNCH_CHECK();
+      return;
+    }
+  }
   const int64_t N = (int64_t)Nx * Nt * nb;
   hipLaunchKernelGGL(kb_wilson<R>, dim3((unsigned)((N + BT - 1) / BT)), dim3(BT), 0, s, U, in, out, (R)(m0 + 2.0), Nx,
                      Nt, nb, sub, skip);
