@@ -150,30 +150,41 @@ __device__ void fin_givens(BS& b, int j, double hn_sq) {
 }
 
 __global__ void __launch_bounds__(BT) kb_final(const double2* __restrict__ part, BS* bs, FinArgs a) {
-  const bool arn = a.mode == FIN_ARN1 || a.mode == FIN_ARN2 || a.mode == FIN_ARN3;
   if (a.mode == FIN_ARN1 && *a.alldone) return;
   if ((a.mode == FIN_ARN2 || a.mode == FIN_ARN3) && !*a.anyp2) return;
-  (void)arn;
-  // G lanes per quantity (the largest power of two with G * nq <= BT); each lane adds
-  // the partials of workgroups g, g + G, ..., then a fixed-order tree adds the lanes
-  __shared__ double2 lanes[BT];
+  // Each thread adds the partials b = t, t + BT, ... of every quantity (contiguous per
+  // quantity, so a wavefront's loads coalesce); a fixed shuffle tree adds the 64 lanes of a
+  // wavefront and the wavefronts' sums are added in order.
+  __shared__ double2 wsum[BT / 64][MQ];
   __shared__ double2 tot[64];
   const int r = blockIdx.x, t = threadIdx.x;
-  int G = 1;
-  while (2 * G * a.nq <= BT) G *= 2;
-  const int q = t / G, g = t % G;
-  if (q < a.nq) {
-    double2 s0 = mk(0.0, 0.0);
-    const double2* pq = part + ((int64_t)r * a.nq + q) * a.nblk;
-    for (int b = g; b < a.nblk; b += G) s0 = cadd(s0, pq[b]);
-    lanes[t] = s0;
+  const double2* pr = part + (int64_t)r * a.nq * a.nblk;
+  double2 sq[MQ];
+#pragma unroll
+  for (int q = 0; q < MQ; ++q) {
+    sq[q] = mk(0.0, 0.0);
+    if (q < a.nq)
+      for (int b = t; b < a.nblk; b += BT) sq[q] = cadd(sq[q], pr[(int64_t)q * a.nblk + b]);
+  }
+#pragma unroll
+  for (int q = 0; q < MQ; ++q) {
+    if (q < a.nq) {
+      double2 v = sq[q];
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        v.x += __shfl_down(v.x, off);
+        v.y += __shfl_down(v.y, off);
+      }
+      if ((t & 63) == 0) wsum[t >> 6][q] = v;
+    }
   }
   __syncthreads();
-  for (int w = G / 2; w >= 1; w /= 2) {
-    if (q < a.nq && g < w) lanes[t] = cadd(lanes[t], lanes[t + w]);
-    __syncthreads();
+  if (t < a.nq) {
+    double2 v = wsum[0][t];
+#pragma unroll
+    for (int w = 1; w < BT / 64; ++w) v = cadd(v, wsum[w][t]);
+    tot[t] = v;
   }
-  if (t < a.nq) tot[t] = lanes[t * G];
   __syncthreads();
   if (a.mode == FIN_SMOOTH2) {
     // two-step smoother: least-squares fit of v by [w1, w2] from the Gram entries
@@ -358,16 +369,15 @@ __global__ void __launch_bounds__(BT) kb_arn_dots1(const cx<R>* __restrict__ V, 
   b_publish<MB + 2>(acc, j + 2, nb, part);
 }
 
-// (b) w -= sum_i H[i, j] V_i for the right-hand sides that took step j (one-pass) or need
-// a second pass; h2_i = V_i^H w of the updated w (used by the second-pass lanes)
+// (b) w -= sum_i H[i, j] V_i for the right-hand sides that took step j in one pass (then
+// normalised at once: v_{j+1} = (w - V h) / h_{j+1, j}) or that need a second pass
 template <typename R>
-__global__ void __launch_bounds__(BT) kb_arn_update_dots2(cx<R>* __restrict__ V, int64_t ld, int64_t n, int nb, int j,
-                                                          const BS* bs, double2* part) {
+__global__ void __launch_bounds__(BT) kb_arn_update(cx<R>* __restrict__ V, int64_t ld, int64_t n, int nb, int j,
+                                                    const BS* bs) {
   const int r0 = threadIdx.x & (nb - 1);
   const BS& b = bs[r0];
-  const bool one = b.steps == j + 1 && b.pass2 == 0;  // finished step j in one pass
-  const bool skip = !(one || b.pass2 == 1);
-  // one-pass lanes are normalised here: v_{j+1} = (w - V h) / h_{j+1, j}
+  const bool one = b.steps == j + 1 && b.pass2 == 0;
+  if (!(one || b.pass2 == 1)) return;
   double scale = 1.0;
   if (one && !b.brk) {
     const double hn = b.H[LDH * j + j + 1].x;
@@ -379,23 +389,35 @@ __global__ void __launch_bounds__(BT) kb_arn_update_dots2(cx<R>* __restrict__ V,
   const int64_t N = n * nb;
   const int64_t stride = (int64_t)gridDim.x * BT;
   cx<R>* w = V + (int64_t)(j + 1) * ld;
+  for (int64_t e = (int64_t)blockIdx.x * BT + threadIdx.x; e < N; e += stride) {
+    double2 wv = to_d(w[e]);
+#pragma unroll
+    for (int i = 0; i < MB + 1; ++i)
+      if (i <= j) wv = csub(wv, cmul(cf[i], to_d(V[(int64_t)i * ld + e])));
+    w[e] = from_d<R>(cscale(wv, scale));
+  }
+}
+
+// (b') h2_i = V_i^H w of the updated w, for the right-hand sides that need a second pass
+template <typename R>
+__global__ void __launch_bounds__(BT) kb_arn_dots2(const cx<R>* __restrict__ V, int64_t ld, int64_t n, int nb, int j,
+                                                   const BS* bs, const int* anyp2, double2* part) {
+  if (!*anyp2) return;
+  const int r0 = threadIdx.x & (nb - 1);
+  const bool act = bs[r0].pass2 == 1;
+  const int64_t N = n * nb;
+  const int64_t stride = (int64_t)gridDim.x * BT;
+  const cx<R>* w = V + (int64_t)(j + 1) * ld;
   double2 acc[MB + 1];
 #pragma unroll
   for (int q = 0; q < MB + 1; ++q) acc[q] = mk(0.0, 0.0);
-  for (int64_t e = (int64_t)blockIdx.x * BT + threadIdx.x; e < N; e += stride) {
-    double2 wv = to_d(w[e]);
-    if (!skip) {
+  if (act)
+    for (int64_t e = (int64_t)blockIdx.x * BT + threadIdx.x; e < N; e += stride) {
+      const double2 wv = to_d(w[e]);
 #pragma unroll
       for (int i = 0; i < MB + 1; ++i)
-        if (i <= j) wv = csub(wv, cmul(cf[i], to_d(V[(int64_t)i * ld + e])));
-      const cx<R> st = from_d<R>(cscale(wv, scale));
-      w[e] = st;
-      wv = to_d(st);
+        if (i <= j) cfmac(acc[i], to_d(V[(int64_t)i * ld + e]), wv);
     }
-#pragma unroll
-    for (int i = 0; i < MB + 1; ++i)
-      if (i <= j) cfmac(acc[i], to_d(V[(int64_t)i * ld + e]), wv);
-  }
   b_publish<MB + 1>(acc, j + 1, nb, part);
 }
 
@@ -460,7 +482,9 @@ void launch_b_arnoldi(hipStream_t s, cx<R>* V, int64_t ld, int64_t n, int nb, in
   hipLaunchKernelGGL(kb_arn_dots1<R>, dim3(G), dim3(BT), 0, s, (const cx<R>*)V, ld, n, nb, j, (const int*)alldone,
                      anyp2, part);
   launch_final(s, part, bs, a);
-  hipLaunchKernelGGL(kb_arn_update_dots2<R>, dim3(G), dim3(BT), 0, s, V, ld, n, nb, j, (const BS*)bs, part);
+  hipLaunchKernelGGL(kb_arn_update<R>, dim3(vec_blocks(n * nb)), dim3(BT), 0, s, V, ld, n, nb, j, (const BS*)bs);
+  hipLaunchKernelGGL(kb_arn_dots2<R>, dim3(G), dim3(BT), 0, s, (const cx<R>*)V, ld, n, nb, j, (const BS*)bs,
+                     (const int*)anyp2, part);
   a.mode = FIN_ARN2;
   a.nq = j + 1;
   launch_final(s, part, bs, a);
