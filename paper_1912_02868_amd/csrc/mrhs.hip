@@ -85,10 +85,6 @@ __device__ void fin_start(BS& b, double s2, const FinArgs& a) {
   b.steps = 0;
   b.brk = 0;
   b.pass2 = 0;
-  for (int i = 0; i <= MB; ++i) {
-    b.g[i] = (i == 0) ? mk(beta, 0.0) : mk(0.0, 0.0);
-    b.c[i] = b.g[i];
-  }
   b.tol_abs = a.tol_rel * b.bnorm;
   if (!b.active) {
     b.beta = 0.0;
@@ -101,52 +97,62 @@ __device__ void fin_start(BS& b, double s2, const FinArgs& a) {
   }
 }
 
-// column j: rotate by the cycle's rotations, annihilate the subdiagonal, update g
-__device__ void fin_givens(BS& b, int j, double hn_sq) {
-  double hn = sqrt(hn_sq);
-  const bool brk = !(hn > 1e-12 * b.wn0);
-  if (brk) hn = 0.0;
-  b.H[LDH * j + j + 1] = mk(hn, 0.0);
-  double2 col[MB + 1];
-  for (int i = 0; i <= j + 1; ++i) col[i] = b.H[LDH * j + i];
-  for (int q = 0; q < j; ++q) {
-    const double c = b.rc[q];
-    const double2 sn = b.rs[q];
-    const double2 x = col[q], y = col[q + 1];
-    col[q] = cadd(cscale(x, c), cmul(sn, y));
-    col[q + 1] = csub(cscale(y, c), cmul(cconj(sn), x));
+// column j: rotate by the cycle's rotations, annihilate the subdiagonal, update g.  Called by
+// every thread of the workgroup with the same arguments; the column (col[i], i <= j) and the
+// rotations are staged in LDS and one thread runs the serial rotation chain.
+__device__ void fin_givens(BS& b, int j, double hn_sq, double2* col, double* rc, double2* rs) {
+  const int t = threadIdx.x;
+  for (int q = t; q < j; q += BT) {
+    rc[q] = b.rc[q];
+    rs[q] = b.rs[q];
   }
-  const double2 x = col[j], y = col[j + 1];
-  const double na = sqrt(cabs2(x)), ny = sqrt(cabs2(y));
-  double c;
-  double2 sn;
-  if (ny == 0.0) {
-    c = 1.0;
-    sn = mk(0.0, 0.0);
-  } else if (na == 0.0) {
-    c = 0.0;
-    sn = cscale(cconj(y), 1.0 / ny);
-  } else {
-    const double nr = sqrt(na * na + ny * ny);
-    c = na / nr;
-    sn = cscale(cmul(cconj(y), x), 1.0 / (na * nr));
+  __syncthreads();
+  if (t == 0) {
+    double hn = sqrt(hn_sq);
+    const bool brk = !(hn > 1e-12 * b.wn0);
+    if (brk) hn = 0.0;
+    b.H[LDH * j + j + 1] = mk(hn, 0.0);
+    col[j + 1] = mk(hn, 0.0);
+    for (int q = 0; q < j; ++q) {
+      const double c = rc[q];
+      const double2 sn = rs[q];
+      const double2 x = col[q], y = col[q + 1];
+      col[q] = cadd(cscale(x, c), cmul(sn, y));
+      col[q + 1] = csub(cscale(y, c), cmul(cconj(sn), x));
+    }
+    const double2 x = col[j], y = col[j + 1];
+    const double na = sqrt(cabs2(x)), ny = sqrt(cabs2(y));
+    double c;
+    double2 sn;
+    if (ny == 0.0) {
+      c = 1.0;
+      sn = mk(0.0, 0.0);
+    } else if (na == 0.0) {
+      c = 0.0;
+      sn = cscale(cconj(y), 1.0 / ny);
+    } else {
+      const double nr = sqrt(na * na + ny * ny);
+      c = na / nr;
+      sn = cscale(cmul(cconj(y), x), 1.0 / (na * nr));
+    }
+    col[j] = cadd(cscale(x, c), cmul(sn, y));
+    col[j + 1] = mk(0.0, 0.0);
+    const double2 gj = b.g[j], gj1 = b.g[j + 1];
+    b.g[j] = cadd(cscale(gj, c), cmul(sn, gj1));
+    const double2 ng1 = csub(cscale(gj1, c), cmul(cconj(sn), gj));
+    b.g[j + 1] = ng1;
+    b.rc[j] = c;
+    b.rs[j] = sn;
+    b.est = sqrt(cabs2(ng1));
+    b.steps = j + 1;
+    if (brk) {
+      b.brk = 1;
+      b.est = 0.0;
+    }
+    if (brk || b.est <= b.tol_abs || b.steps >= b.cap) b.done = 1;
   }
-  col[j] = cadd(cscale(x, c), cmul(sn, y));
-  col[j + 1] = mk(0.0, 0.0);
-  for (int i = 0; i <= j + 1; ++i) b.Rm[LDH * j + i] = col[i];
-  const double2 gj = b.g[j], gj1 = b.g[j + 1];
-  b.g[j] = cadd(cscale(gj, c), cmul(sn, gj1));
-  const double2 ng1 = csub(cscale(gj1, c), cmul(cconj(sn), gj));
-  b.g[j + 1] = ng1;
-  b.rc[j] = c;
-  b.rs[j] = sn;
-  b.est = sqrt(cabs2(ng1));
-  b.steps = j + 1;
-  if (brk) {
-    b.brk = 1;
-    b.est = 0.0;
-  }
-  if (brk || b.est <= b.tol_abs || b.steps >= b.cap) b.done = 1;
+  __syncthreads();
+  for (int i = t; i <= j + 1; i += BT) b.Rm[LDH * j + i] = col[i];
 }
 
 __global__ void __launch_bounds__(BT) kb_final(const double2* __restrict__ part, BS* bs, FinArgs a) {
@@ -215,15 +221,26 @@ __global__ void __launch_bounds__(BT) kb_final(const double2* __restrict__ part,
       if (t == 0) b.bnorm = sqrt(tot[0].x);
       break;
     case FIN_START:
+      for (int i = t; i <= MB; i += BT) b.g[i] = b.c[i] = (i == 0) ? mk(sqrt(tot[0].x), 0.0) : mk(0.0, 0.0);
       if (t == 0) fin_start(b, tot[0].x, a);
       break;
-    case FIN_ARN1:
+    case FIN_ARN1: {
       // h = V^H w and ||w||^2: keep h as column j; one-pass norm ||w||^2 - ||h||^2 unless it
       // cancels, then the Givens update at once, else flag a second pass
-      if (!b.done) {
+      __shared__ double2 col[MB + 2];
+      __shared__ double rc[MB], rest_s;
+      __shared__ double2 rs[MB];
+      __shared__ int one_s;
+      const bool was_done = b.done;  // read by every thread before any thread can change it
+      __syncthreads();
+      if (!was_done) {
         for (int i = t; i <= MB; i += BT) {
-          if (i <= j) b.H[LDH * j + i] = tot[i];
-          else if (i > j + 1) b.H[LDH * j + i] = mk(0.0, 0.0);
+          if (i <= j) {
+            b.H[LDH * j + i] = tot[i];
+            col[i] = tot[i];
+          } else if (i > j + 1) {
+            b.H[LDH * j + i] = mk(0.0, 0.0);
+          }
         }
         if (t == 0) {
           const double ww = tot[j + 1].x;
@@ -231,16 +248,20 @@ __global__ void __launch_bounds__(BT) kb_final(const double2* __restrict__ part,
           for (int i = 0; i <= j; ++i) hh += cabs2(tot[i]);
           b.wn0 = sqrt(ww);
           const double rest = ww - hh;
-          if (rest > a.eta * ww) {
+          one_s = rest > a.eta * ww ? 1 : 0;
+          rest_s = rest;
+          if (one_s) {
             b.pass2 = 0;
-            fin_givens(b, j, rest);
           } else {
             b.pass2 = 1;
             atomicOr(a.anyp2, 1);
           }
         }
+        __syncthreads();
+        if (one_s) fin_givens(b, j, rest_s, col, rc, rs);
       }
       break;
+    }
     case FIN_ARN2:
       if (b.pass2 == 1)
         for (int i = t; i <= j; i += BT) {
@@ -248,12 +269,19 @@ __global__ void __launch_bounds__(BT) kb_final(const double2* __restrict__ part,
           b.H[LDH * j + i] = cadd(b.H[LDH * j + i], tot[i]);
         }
       break;
-    case FIN_ARN3:
-      if (t == 0 && b.pass2 == 1) {
-        b.pass2 = 2;  // normalised by the next kernel
-        fin_givens(b, j, tot[0].x);
+    case FIN_ARN3: {
+      __shared__ double2 col3[MB + 2];
+      __shared__ double rc3[MB];
+      __shared__ double2 rs3[MB];
+      const bool p2 = b.pass2 == 1;
+      __syncthreads();
+      if (p2) {
+        for (int i = t; i <= j; i += BT) col3[i] = b.H[LDH * j + i];
+        if (t == 0) b.pass2 = 2;  // normalised by the next kernel
+        fin_givens(b, j, tot[0].x, col3, rc3, rs3);
       }
       break;
+    }
     case FIN_PROJ:
       if (b.active) {
         // y_i = sum_l M[i + k l] c_l (i < k), u_i = sum_l Pi[i + (k+1) l] c_l (i <= k)
@@ -278,12 +306,13 @@ __global__ void __launch_bounds__(BT) kb_final(const double2* __restrict__ part,
     __syncthreads();
     if (t == 0) last = (atomicAdd(a.cnt, 1u) == (unsigned)a.nb - 1) ? 1 : 0;
     __syncthreads();
-    if (last && t == 0) {
+    if (last) {
       __threadfence();
-      int all = 1;
-      for (int i = 0; i < a.nb; ++i) all &= bs[i].done ? 1 : 0;
-      *a.alldone = all;
-      *a.cnt = 0u;
+      const int all = __syncthreads_and(t < a.nb ? (bs[t].done ? 1 : 0) : 1);
+      if (t == 0) {
+        *a.alldone = all;
+        *a.cnt = 0u;
+      }
     }
   }
 }
