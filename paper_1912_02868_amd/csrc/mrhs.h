@@ -32,6 +32,11 @@ struct BS {
   int cap;     // steps allowed in this cycle
   int pass2;   // the current Arnoldi step needs a second Gram-Schmidt pass
 };
+// Every right-hand side of bs[0..nb) has done set (flags written by earlier kernels).  A
+// workgroup vote: every thread of a workgroup of at least nb threads calls it.
+__device__ inline bool lanes_all_done(const BS* bs, int nb) {
+  return __syncthreads_and(threadIdx.x < (unsigned)nb ? bs[threadIdx.x].done : 1) != 0;
+}
 // Host copy of a BS tail (beta .. cap), read back after a cycle.
 struct BSTail {
   double beta, bnorm, tol_abs, est, wn0;
@@ -47,11 +52,13 @@ size_t bred_partials(int nb);  // double2 entries of reduction scratch
 // ||x_r||^2 per right-hand side; mode 0: out[r]; mode 3: bs[r].bnorm = ||x_r||;
 // mode 1: cycle start (beta, g = c = beta e1, tol_abs = tol_rel * bnorm, done when beta
 // is 0 or below tol_abs, inactive right-hand sides done with no steps); mode 2: as 1
-// and bnorm = beta first.  In modes 1 and 2 *alldone is set when every right-hand side
-// is done (the batched stencils and Arnoldi kernels then return at once).
+// and bnorm = beta first.  Once every right-hand side is done, the batched stencils given
+// bs as their skip set and the Arnoldi kernels return at once.
 template <typename R>
 void launch_b_norm(hipStream_t s, const cx<R>* x, int64_t n, int nb, BS* bs, double tol_rel, int mode, double* out,
-                   int* alldone, double2* part, unsigned* cnt);
+                   double2* part);
+// *flag = 1 when every right-hand side of bs is done, else 0
+void launch_b_all_done(hipStream_t s, const BS* bs, int nb, int* flag);
 // y = x / beta_r (0 when beta_r == 0)
 template <typename R>
 void launch_b_scale_beta(hipStream_t s, const cx<R>* x, cx<R>* y, int64_t n, int nb, const BS* bs);
@@ -59,10 +66,10 @@ void launch_b_scale_beta(hipStream_t s, const cx<R>* x, cx<R>* y, int64_t n, int
 // with the norm from ||w||^2 - ||h||^2, and a second pass only for the right-hand sides
 // where that difference cancels (below eta ||w||^2); Givens update; a right-hand side is
 // done once it converged, broke down or took cap steps.  eta: 1e-8 for FP64 vectors,
-// 1e-4 for FP32.
+// 1e-4 for FP32.  anyp2: device flag of the step (some right-hand side needs a second pass).
 template <typename R>
-void launch_b_arnoldi(hipStream_t s, cx<R>* V, int64_t ld, int64_t n, int nb, int j, BS* bs, int* alldone,
-                      double2* part, unsigned* cnt);
+void launch_b_arnoldi(hipStream_t s, cx<R>* V, int64_t ld, int64_t n, int nb, int j, BS* bs, int* anyp2,
+                      double2* part);
 // y = Rm^{-1} g, u = c - H y per active right-hand side
 void launch_b_ls_solve(hipStream_t s, BS* bs, int nb);
 // x (+)= sum_i coef_i V_i with coef = y (steps terms) or u (steps + 1 terms); active only
@@ -72,19 +79,20 @@ void launch_b_combine(hipStream_t s, cx<R>* x, const cx<R>* V, int64_t ld, int64
 // two-step GMRES smoother from w1 = A v, w2 = A w1 (coef: 2 * nb double2 scratch)
 template <typename R>
 void launch_b_smooth2(hipStream_t s, const cx<R>* v, const cx<R>* w1, const cx<R>* w2, int64_t n, int nb,
-                      double2* coef, cx<R>* y, cx<R>* r, double2* part, unsigned* cnt);
+                      double2* coef, cx<R>* y, cx<R>* r, double2* part);
 // GMRES-Proj projection over a shared deflation basis DV (k + 1 single fields):
 // c = DV^H r, y = M c, u = Pi c per active right-hand side; then x += DV_k y, r -= DV u.
 template <typename R>
 void launch_b_project(hipStream_t s, const cx<R>* DV, int k, const double2* M, const double2* Pi, cx<R>* x, cx<R>* r,
-                      int64_t n, int nb, BS* bs, double2* part, unsigned* cnt);
-// stencils on batched fields (sub: out = sub - A in; skip: return at once when *skip)
+                      int64_t n, int nb, BS* bs, double2* part);
+// stencils on batched fields (sub: out = sub - A in; skip: return at once when every
+// right-hand side of the state array skip[0..nb) is done)
 template <typename R>
 void launch_b_wilson(hipStream_t s, const cx<R>* U, const cx<R>* in, cx<R>* out, double m0, int Nx, int Nt, int nb,
-                     const cx<R>* sub, const int* skip = nullptr);
+                     const cx<R>* sub, const BS* skip = nullptr);
 template <typename R>
 void launch_b_block(hipStream_t s, const cx<R>* A, const cx<R>* in, cx<R>* out, int Lx, int Lt, int nb,
-                    const cx<R>* sub, const int* skip = nullptr);
+                    const cx<R>* sub, const BS* skip = nullptr);
 template <typename R>
 void launch_b_restrict(hipStream_t s, const cx<R>* P, const cx<R>* fine, cx<R>* coarse, int Lx, int Lt, int dof,
                        int nb);

@@ -71,8 +71,6 @@ struct FinArgs {
   double2* coef;
   const double2* M;
   const double2* Pi;
-  int* alldone;   // FIN_START / FIN_ARN1 / FIN_ARN3: set to 1 when every right-hand side is done
-  unsigned* cnt;  // ticket of the alldone update
   double eta;     // FIN_ARN1: cancellation threshold of the one-pass norm
   int* anyp2;     // FIN_ARN1: set when some right-hand side needs a second pass
 };
@@ -97,25 +95,30 @@ __device__ void fin_start(BS& b, double s2, const FinArgs& a) {
   }
 }
 
+// Per right-hand-side state the Givens epilogue reads, staged in LDS at the start of the
+// second phase so that its loads overlap those of the partials.
+struct FinStage {
+  double rc[MB];
+  double2 rs[MB];
+  double2 g[2];   // g[j], g[j + 1]
+  double tol_abs, wn0;
+  int cap, done, pass2;
+};
+
 // column j: rotate by the cycle's rotations, annihilate the subdiagonal, update g.  Called by
-// every thread of the workgroup with the same arguments; the column (col[i], i <= j) and the
-// rotations are staged in LDS and one thread runs the serial rotation chain.
-__device__ void fin_givens(BS& b, int j, double hn_sq, double2* col, double* rc, double2* rs) {
+// every thread of the workgroup with the same arguments; the column (col[i], i <= j) is in
+// LDS and one thread runs the serial rotation chain.
+__device__ void fin_givens(BS& b, int j, double hn_sq, double wn0, double2* col, const FinStage& st) {
   const int t = threadIdx.x;
-  for (int q = t; q < j; q += BT) {
-    rc[q] = b.rc[q];
-    rs[q] = b.rs[q];
-  }
-  __syncthreads();
   if (t == 0) {
     double hn = sqrt(hn_sq);
-    const bool brk = !(hn > 1e-12 * b.wn0);
+    const bool brk = !(hn > 1e-12 * wn0);
     if (brk) hn = 0.0;
     b.H[LDH * j + j + 1] = mk(hn, 0.0);
     col[j + 1] = mk(hn, 0.0);
     for (int q = 0; q < j; ++q) {
-      const double c = rc[q];
-      const double2 sn = rs[q];
+      const double c = st.rc[q];
+      const double2 sn = st.rs[q];
       const double2 x = col[q], y = col[q + 1];
       col[q] = cadd(cscale(x, c), cmul(sn, y));
       col[q + 1] = csub(cscale(y, c), cmul(cconj(sn), x));
@@ -137,41 +140,67 @@ __device__ void fin_givens(BS& b, int j, double hn_sq, double2* col, double* rc,
     }
     col[j] = cadd(cscale(x, c), cmul(sn, y));
     col[j + 1] = mk(0.0, 0.0);
-    const double2 gj = b.g[j], gj1 = b.g[j + 1];
+    const double2 gj = st.g[0], gj1 = st.g[1];
     b.g[j] = cadd(cscale(gj, c), cmul(sn, gj1));
     const double2 ng1 = csub(cscale(gj1, c), cmul(cconj(sn), gj));
     b.g[j + 1] = ng1;
     b.rc[j] = c;
     b.rs[j] = sn;
-    b.est = sqrt(cabs2(ng1));
+    double est = sqrt(cabs2(ng1));
     b.steps = j + 1;
     if (brk) {
       b.brk = 1;
-      b.est = 0.0;
+      est = 0.0;
     }
-    if (brk || b.est <= b.tol_abs || b.steps >= b.cap) b.done = 1;
+    b.est = est;
+    if (brk || est <= st.tol_abs || j + 1 >= st.cap) b.done = 1;
   }
   __syncthreads();
   for (int i = t; i <= j + 1; i += BT) b.Rm[LDH * j + i] = col[i];
 }
 
 __global__ void __launch_bounds__(BT) kb_final(const double2* __restrict__ part, BS* bs, FinArgs a) {
-  if (a.mode == FIN_ARN1 && *a.alldone) return;
-  if ((a.mode == FIN_ARN2 || a.mode == FIN_ARN3) && !*a.anyp2) return;
-  // Each thread adds the partials b = t, t + BT, ... of every quantity (contiguous per
-  // quantity, so a wavefront's loads coalesce); a fixed shuffle tree adds the 64 lanes of a
-  // wavefront and the wavefronts' sums are added in order.
+  static_assert(BMAXBLK <= 2 * BT, "at most two partials per thread and quantity");
+  const int r = blockIdx.x, t = threadIdx.x;
+  const bool skip = a.mode == FIN_ARN1                           ? lanes_all_done(bs, a.nb)
+                    : (a.mode == FIN_ARN2 || a.mode == FIN_ARN3) ? !*a.anyp2
+                                                                 : false;
+  // Each thread adds the partials t and t + BT of every quantity (contiguous per quantity, so
+  // a wavefront's loads coalesce; all loads are issued before the first add); a fixed shuffle
+  // tree adds the 64 lanes of a wavefront and the wavefronts' sums are added in order.
   __shared__ double2 wsum[BT / 64][MQ];
   __shared__ double2 tot[64];
-  const int r = blockIdx.x, t = threadIdx.x;
+  __shared__ FinStage st;
   const double2* pr = part + (int64_t)r * a.nq * a.nblk;
+  const bool h0 = t < a.nblk, h1 = t + BT < a.nblk;
   double2 sq[MQ];
 #pragma unroll
   for (int q = 0; q < MQ; ++q) {
-    sq[q] = mk(0.0, 0.0);
-    if (q < a.nq)
-      for (int b = t; b < a.nblk; b += BT) sq[q] = cadd(sq[q], pr[(int64_t)q * a.nblk + b]);
+    double2 v0 = mk(0.0, 0.0), v1 = mk(0.0, 0.0);
+    if (q < a.nq) {
+      if (h0) v0 = pr[(int64_t)q * a.nblk + t];
+      if (h1) v1 = pr[(int64_t)q * a.nblk + t + BT];
+    }
+    sq[q] = cadd(v0, v1);
   }
+  BS& b = bs[r];
+  const int j = a.j;
+  if (a.mode == FIN_ARN1 || a.mode == FIN_ARN3) {
+    if (t < j) {
+      st.rc[t] = b.rc[t];
+      st.rs[t] = b.rs[t];
+    } else if (t == MB) {
+      st.g[0] = b.g[j];
+      st.g[1] = b.g[j + 1];
+    } else if (t == MB + 1) {
+      st.tol_abs = b.tol_abs;
+      st.wn0 = b.wn0;
+      st.cap = b.cap;
+      st.done = b.done;
+      st.pass2 = b.pass2;
+    }
+  }
+  if (skip) return;
 #pragma unroll
   for (int q = 0; q < MQ; ++q) {
     if (q < a.nq) {
@@ -211,8 +240,6 @@ __global__ void __launch_bounds__(BT) kb_final(const double2* __restrict__ part,
     }
     return;
   }
-  BS& b = bs[r];
-  const int j = a.j;
   switch (a.mode) {
     case FIN_NORM0:
       if (t == 0) a.out[r] = tot[0].x;
@@ -228,12 +255,9 @@ __global__ void __launch_bounds__(BT) kb_final(const double2* __restrict__ part,
       // h = V^H w and ||w||^2: keep h as column j; one-pass norm ||w||^2 - ||h||^2 unless it
       // cancels, then the Givens update at once, else flag a second pass
       __shared__ double2 col[MB + 2];
-      __shared__ double rc[MB], rest_s;
-      __shared__ double2 rs[MB];
+      __shared__ double rest_s, wn0_s;
       __shared__ int one_s;
-      const bool was_done = b.done;  // read by every thread before any thread can change it
-      __syncthreads();
-      if (!was_done) {
+      if (!st.done) {
         for (int i = t; i <= MB; i += BT) {
           if (i <= j) {
             b.H[LDH * j + i] = tot[i];
@@ -246,7 +270,9 @@ __global__ void __launch_bounds__(BT) kb_final(const double2* __restrict__ part,
           const double ww = tot[j + 1].x;
           double hh = 0.0;
           for (int i = 0; i <= j; ++i) hh += cabs2(tot[i]);
-          b.wn0 = sqrt(ww);
+          const double wn0 = sqrt(ww);
+          b.wn0 = wn0;
+          wn0_s = wn0;
           const double rest = ww - hh;
           one_s = rest > a.eta * ww ? 1 : 0;
           rest_s = rest;
@@ -258,7 +284,7 @@ __global__ void __launch_bounds__(BT) kb_final(const double2* __restrict__ part,
           }
         }
         __syncthreads();
-        if (one_s) fin_givens(b, j, rest_s, col, rc, rs);
+        if (one_s) fin_givens(b, j, rest_s, wn0_s, col, st);
       }
       break;
     }
@@ -271,14 +297,11 @@ __global__ void __launch_bounds__(BT) kb_final(const double2* __restrict__ part,
       break;
     case FIN_ARN3: {
       __shared__ double2 col3[MB + 2];
-      __shared__ double rc3[MB];
-      __shared__ double2 rs3[MB];
-      const bool p2 = b.pass2 == 1;
-      __syncthreads();
-      if (p2) {
+      if (st.pass2 == 1) {
         for (int i = t; i <= j; i += BT) col3[i] = b.H[LDH * j + i];
         if (t == 0) b.pass2 = 2;  // normalised by the next kernel
-        fin_givens(b, j, tot[0].x, col3, rc3, rs3);
+        __syncthreads();
+        fin_givens(b, j, tot[0].x, st.wn0, col3, st);
       }
       break;
     }
@@ -299,21 +322,6 @@ __global__ void __launch_bounds__(BT) kb_final(const double2* __restrict__ part,
         }
       }
       break;
-  }
-  if (a.mode == FIN_START || a.mode == FIN_ARN1 || a.mode == FIN_ARN3) {
-    __shared__ int last;
-    __threadfence();
-    __syncthreads();
-    if (t == 0) last = (atomicAdd(a.cnt, 1u) == (unsigned)a.nb - 1) ? 1 : 0;
-    __syncthreads();
-    if (last) {
-      __threadfence();
-      const int all = __syncthreads_and(t < a.nb ? (bs[t].done ? 1 : 0) : 1);
-      if (t == 0) {
-        *a.alldone = all;
-        *a.cnt = 0u;
-      }
-    }
   }
 }
 
@@ -341,17 +349,25 @@ __global__ void __launch_bounds__(BT) kb_norm(const cx<R>* __restrict__ x, int64
   b_publish<1>(acc, 1, nb, part);
 }
 
+__global__ void __launch_bounds__(NBMAX) kb_all_done(const BS* bs, int nb, int* flag) {
+  const bool all = lanes_all_done(bs, nb);
+  if (threadIdx.x == 0) *flag = all ? 1 : 0;
+}
+
+void launch_b_all_done(hipStream_t s, const BS* bs, int nb, int* flag) {
+  hipLaunchKernelGGL(kb_all_done, dim3(1), dim3(NBMAX), 0, s, bs, nb, flag);
+  DMG_LAUNCH_CHECK();
+}
+
 template <typename R>
 void launch_b_norm(hipStream_t s, const cx<R>* x, int64_t n, int nb, BS* bs, double tol_rel, int mode, double* out,
-                   int* alldone, double2* part, unsigned* cnt) {
+                   double2* part) {
   const int G = bred_blocks(n * nb);
   hipLaunchKernelGGL(kb_norm<R>, dim3(G), dim3(BT), 0, s, x, n, nb, part);
   FinArgs a = fin(mode == 0 ? FIN_NORM0 : mode == 3 ? FIN_NORM3 : FIN_START, 1, G, nb);
   a.tol_rel = tol_rel;
   a.bnorm_too = mode == 2 ? 1 : 0;
   a.out = out;
-  a.alldone = alldone;
-  a.cnt = cnt;
   launch_final(s, part, bs, a);
 }
 
@@ -377,8 +393,8 @@ void launch_b_scale_beta(hipStream_t s, const cx<R>* x, cx<R>* y, int64_t n, int
 // (a) h_i = V_i^H w (i <= j) and ||w||^2 with w = V_{j+1}
 template <typename R>
 __global__ void __launch_bounds__(BT) kb_arn_dots1(const cx<R>* __restrict__ V, int64_t ld, int64_t n, int nb, int j,
-                                                   const int* alldone, int* anyp2, double2* part) {
-  if (*alldone) return;
+                                                   const BS* bs, int* anyp2, double2* part) {
+  if (lanes_all_done(bs, nb)) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) *anyp2 = 0;
   const int64_t N = n * nb;
   const int64_t stride = (int64_t)gridDim.x * BT;
@@ -498,17 +514,14 @@ __global__ void __launch_bounds__(BT) kb_arn_normalize(cx<R>* __restrict__ V, in
 }
 
 template <typename R>
-void launch_b_arnoldi(hipStream_t s, cx<R>* V, int64_t ld, int64_t n, int nb, int j, BS* bs, int* alldone,
-                      double2* part, unsigned* cnt) {
+void launch_b_arnoldi(hipStream_t s, cx<R>* V, int64_t ld, int64_t n, int nb, int j, BS* bs, int* anyp2,
+                      double2* part) {
   const int G = bred_blocks(n * nb);
-  int* anyp2 = alldone + 1;
   FinArgs a = fin(FIN_ARN1, j + 2, G, nb);
   a.j = j;
-  a.alldone = alldone;
-  a.cnt = cnt;
   a.anyp2 = anyp2;
   a.eta = sizeof(R) == sizeof(float) ? 1e-4 : 1e-8;
-  hipLaunchKernelGGL(kb_arn_dots1<R>, dim3(G), dim3(BT), 0, s, (const cx<R>*)V, ld, n, nb, j, (const int*)alldone,
+  hipLaunchKernelGGL(kb_arn_dots1<R>, dim3(G), dim3(BT), 0, s, (const cx<R>*)V, ld, n, nb, j, (const BS*)bs,
                      anyp2, part);
   launch_final(s, part, bs, a);
   hipLaunchKernelGGL(kb_arn_update<R>, dim3(vec_blocks(n * nb)), dim3(BT), 0, s, V, ld, n, nb, j, (const BS*)bs);
@@ -634,7 +647,7 @@ __global__ void __launch_bounds__(BT) kb_smooth2_combine(const cx<R>* __restrict
 
 template <typename R>
 void launch_b_smooth2(hipStream_t s, const cx<R>* v, const cx<R>* w1, const cx<R>* w2, int64_t n, int nb,
-                      double2* coef, cx<R>* y, cx<R>* r, double2* part, unsigned* cnt) {
+                      double2* coef, cx<R>* y, cx<R>* r, double2* part) {
   const int G = bred_blocks(n * nb);
   hipLaunchKernelGGL(kb_smooth2_dots<R>, dim3(G), dim3(BT), 0, s, v, w1, w2, n, nb, part);
   FinArgs a = fin(FIN_SMOOTH2, 5, G, nb);
@@ -698,7 +711,7 @@ __global__ void __launch_bounds__(BT) kb_proj_apply(const cx<R>* __restrict__ DV
 
 template <typename R>
 void launch_b_project(hipStream_t s, const cx<R>* DV, int k, const double2* M, const double2* Pi, cx<R>* x, cx<R>* r,
-                      int64_t n, int nb, BS* bs, double2* part, unsigned* cnt) {
+                      int64_t n, int nb, BS* bs, double2* part) {
   const int G = bred_blocks(n * nb);
   hipLaunchKernelGGL(kb_proj_dots<R>, dim3(G), dim3(BT), 0, s, DV, k, (const cx<R>*)r, n, nb, part);
   FinArgs a = fin(FIN_PROJ, k + 1, G, nb);
@@ -718,8 +731,8 @@ template <typename T> __device__ inline T bmul_i(T z) { T r; r.x = -z.y; r.y = z
 template <typename R>
 __global__ void __launch_bounds__(BT) kb_wilson(const cx<R>* __restrict__ U, const cx<R>* __restrict__ in,
                                                 cx<R>* __restrict__ out, R diag, int Nx, int Nt, int nb,
-                                                const cx<R>* __restrict__ sub, const int* skip) {
-  if (skip && *skip) return;
+                                                const cx<R>* __restrict__ sub, const BS* skip) {
+  if (skip && lanes_all_done(skip, nb)) return;
   using T = cx<R>;
   const int lg = __ffs(nb) - 1;
   const int64_t idx = (int64_t)blockIdx.x * BT + threadIdx.x;
@@ -773,8 +786,8 @@ __device__ inline float2 half2of(float4 v, int h) { return h ? make_float2(v.z, 
 
 __global__ void __launch_bounds__(BT) kb_wilson_pair(const float2* __restrict__ U, const float4* __restrict__ in,
                                                      float4* __restrict__ out, float diag, int Nx, int Nt, int nb,
-                                                     const float4* __restrict__ sub, const int* skip) {
-  if (skip && *skip) return;
+                                                     const float4* __restrict__ sub, const BS* skip) {
+  if (skip && lanes_all_done(skip, nb)) return;
   const int hb = nb >> 1;  // lane pairs = float4 per (site, spin); a power of two
   const int lg = __ffs(hb) - 1;
   const int64_t idx = (int64_t)blockIdx.x * BT + threadIdx.x;
@@ -830,7 +843,7 @@ __global__ void __launch_bounds__(BT) kb_wilson_pair(const float2* __restrict__ 
 
 template <typename R>
 void launch_b_wilson(hipStream_t s, const cx<R>* U, const cx<R>* in, cx<R>* out, double m0, int Nx, int Nt, int nb,
-                     const cx<R>* sub, const int* skip) {
+                     const cx<R>* sub, const BS* skip) {
   if constexpr (sizeof(R) == sizeof(float)) {
     if (nb >= 2) {
       const int64_t N2 = (int64_t)Nx * Nt * (nb / 2);
@@ -853,8 +866,8 @@ void launch_b_wilson(hipStream_t s, const cx<R>* U, const cx<R>* in, cx<R>* out,
 template <typename R>
 __global__ void __launch_bounds__(BT) kb_block(const cx<R>* __restrict__ A, const cx<R>* __restrict__ in,
                                                cx<R>* __restrict__ out, int Lx, int Lt, int nb,
-                                               const cx<R>* __restrict__ sub, const int* skip) {
-  if (skip && *skip) return;
+                                               const cx<R>* __restrict__ sub, const BS* skip) {
+  if (skip && lanes_all_done(skip, nb)) return;
   using T = cx<R>;
   constexpr int OPT = NC * NBMAX / BT;  // most outputs per thread
   extern __shared__ __align__(16) unsigned char kb_smem[];
@@ -920,8 +933,8 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(BT) kb_block_mfma(const float2* __restrict__ A, const float2* __restrict__ in,
                                                     float2* __restrict__ out, int Lx, int Lt, int nb,
-                                                    const float2* __restrict__ sub, const int* skip) {
-  if (skip && *skip) return;
+                                                    const float2* __restrict__ sub, const BS* skip) {
+  if (skip && lanes_all_done(skip, nb)) return;
   extern __shared__ __align__(16) unsigned char kb_smem[];
   float* xre = (float*)kb_smem;            // [5][24][nb]
   float* xim = xre + 5 * NC * nb;          // [5][24][nb]
@@ -996,7 +1009,7 @@ __global__ void __launch_bounds__(BT) kb_block_mfma(const float2* __restrict__ A
 
 template <typename R>
 void launch_b_block(hipStream_t s, const cx<R>* A, const cx<R>* in, cx<R>* out, int Lx, int Lt, int nb,
-                    const cx<R>* sub, const int* skip) {
+                    const cx<R>* sub, const BS* skip) {
   if constexpr (sizeof(R) == sizeof(float)) {
     if (nb >= 16 && b_block_mfma_enabled()) {
       const size_t lds = (size_t)2 * 5 * NC * nb * sizeof(float);
@@ -1162,19 +1175,18 @@ void launch_b_set_state(hipStream_t s, BS* bs, const int* host_st, int nb) {
 }
 
 #define INST(R)                                                                                                        \
-  template void launch_b_norm<R>(hipStream_t, const cx<R>*, int64_t, int, BS*, double, int, double*, int*, double2*,   \
-                                 unsigned*);                                                                           \
+  template void launch_b_norm<R>(hipStream_t, const cx<R>*, int64_t, int, BS*, double, int, double*, double2*);      \
   template void launch_b_scale_beta<R>(hipStream_t, const cx<R>*, cx<R>*, int64_t, int, const BS*);                   \
-  template void launch_b_arnoldi<R>(hipStream_t, cx<R>*, int64_t, int64_t, int, int, BS*, int*, double2*, unsigned*); \
+  template void launch_b_arnoldi<R>(hipStream_t, cx<R>*, int64_t, int64_t, int, int, BS*, int*, double2*);            \
   template void launch_b_combine<R>(hipStream_t, cx<R>*, const cx<R>*, int64_t, int64_t, int, const BS*, int, int);   \
   template void launch_b_smooth2<R>(hipStream_t, const cx<R>*, const cx<R>*, const cx<R>*, int64_t, int, double2*,    \
-                                    cx<R>*, cx<R>*, double2*, unsigned*);                                              \
+                                    cx<R>*, cx<R>*, double2*);                                                         \
   template void launch_b_project<R>(hipStream_t, const cx<R>*, int, const double2*, const double2*, cx<R>*, cx<R>*,   \
-                                    int64_t, int, BS*, double2*, unsigned*);                                           \
+                                    int64_t, int, BS*, double2*);                                                      \
   template void launch_b_wilson<R>(hipStream_t, const cx<R>*, const cx<R>*, cx<R>*, double, int, int, int,            \
-                                   const cx<R>*, const int*);                                                          \
+                                   const cx<R>*, const BS*);                                                           \
   template void launch_b_block<R>(hipStream_t, const cx<R>*, const cx<R>*, cx<R>*, int, int, int, const cx<R>*,       \
-                                  const int*);                                                                         \
+                                  const BS*);                                                                          \
   template void launch_b_restrict<R>(hipStream_t, const cx<R>*, const cx<R>*, cx<R>*, int, int, int, int);            \
   template void launch_b_prolong<R>(hipStream_t, const cx<R>*, const cx<R>*, cx<R>*, int, int, int, int, int);
 INST(double)

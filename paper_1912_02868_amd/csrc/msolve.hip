@@ -18,7 +18,8 @@
 namespace dmg {
 
 // Krylov basis of one level for nb right-hand sides: V (m + 1 batched fields), Z (m
-// fields when flexible), per right-hand-side state, and the "all done" flag.
+// fields when flexible), per right-hand-side state, and device flags (0: all done, as
+// read by the host; 1: an Arnoldi step needs a second pass).
 struct BKry {
   int m = 0;
   int64_t n = 0;
@@ -39,7 +40,8 @@ struct BKry {
     DMG_HIP(hipMemsetAsync(flag.p, 0, flag.bytes, s));
   }
   BS* st() const { return bs.as<BS>(); }
-  int* alldone() const { return flag.as<int>(); }
+  int* flags() const { return flag.as<int>(); }
+  int* anyp2() const { return flag.as<int>() + 1; }
 };
 
 // Shared scratch of one batched solve.
@@ -47,7 +49,7 @@ struct BShared {
   dmg_context* ctx = nullptr;
   hipStream_t s = nullptr;
   int nb = 0;
-  DevBuf part, cnt, coef;
+  DevBuf part, coef;
   BSTail* tail = nullptr;  // pinned, nb entries
   int* hflag = nullptr;    // pinned
   ~BShared() {
@@ -59,21 +61,20 @@ struct BShared {
     s = st;
     nb = nb_;
     part.alloc(c, sizeof(double2) * bred_partials(nb));
-    cnt.alloc(c, sizeof(unsigned) * 4);
-    DMG_HIP(hipMemsetAsync(cnt.p, 0, cnt.bytes, s));
     coef.alloc(c, sizeof(double2) * 2 * NBMAX);
     DMG_HIP(hipHostMalloc((void**)&tail, sizeof(BSTail) * NBMAX, hipHostMallocDefault));
     DMG_HIP(hipHostMalloc((void**)&hflag, sizeof(int) * 4, hipHostMallocDefault));
   }
   double2* P() const { return part.as<double2>(); }
-  unsigned* C() const { return cnt.as<unsigned>(); }
   // tails of all right-hand sides of a state array (synchronises the stream)
   void read_tails(const BS* bs) {
     DMG_HIP(hipMemcpy2DAsync(tail, sizeof(BSTail), (const char*)bs + offsetof(BS, beta), sizeof(BS), sizeof(BSTail),
                              nb, hipMemcpyDeviceToHost, s));
     DMG_HIP(hipStreamSynchronize(s));
   }
-  bool all_done(const int* flag) {
+  // every right-hand side of bs is done (flag: a device int; synchronises the stream)
+  bool all_done(const BS* bs, int* flag) {
+    launch_b_all_done(s, bs, nb, flag);
     DMG_HIP(hipMemcpyAsync(hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
     DMG_HIP(hipStreamSynchronize(s));
     return hflag[0] != 0;
@@ -139,7 +140,7 @@ struct BPre {
     proj.alloc(c, S(), std::max(d->m - d->kk, 1), N(2), nb, es, false);
   }
 
-  void apply(int l, const T* in, T* out, const T* sub, const int* skip) {
+  void apply(int l, const T* in, T* out, const T* sub, const BS* skip) {
     const Op& A = h->op[l];
     dmg_context* c = h->ctx;
     const int kt = A.kind == 0 ? DMG_KT_WILSON_BATCHED : DMG_KT_BLOCK_BATCHED;
@@ -161,7 +162,7 @@ struct BPre {
     apply(l, v, w1, nullptr, nullptr);
     apply(l, w1, w2, nullptr, nullptr);
     mv[l] += 2;
-    launch_b_smooth2<R>(S(), v, w1, w2, N(l), nb, sh->coef.as<double2>(), yout, rout, sh->P(), sh->C());
+    launch_b_smooth2<R>(S(), v, w1, w2, N(l), nb, sh->coef.as<double2>(), yout, rout, sh->P());
   }
 
   const T* dvec() const {
@@ -182,14 +183,14 @@ struct BPre {
     DMG_HIP(hipMemcpyAsync(rr, b, sizeof(T) * ld, hipMemcpyDeviceToDevice, S()));
     std::vector<int> act(nb, 1), cap(nb, mm), it(nb, 0);
     sh->set_state(bs, act, cap);
-    launch_b_norm<R>(S(), b, n, nb, bs, 0.0, 3, nullptr, nullptr, sh->P(), sh->C());
+    launch_b_norm<R>(S(), b, n, nb, bs, 0.0, 3, nullptr, sh->P());
     for (;;) {
-      launch_b_project<R>(S(), dvec(), k, d->M.as<double2>(), d->Pi.as<double2>(), x, rr, n, nb, bs, sh->P(), sh->C());
-      launch_b_norm<R>(S(), rr, n, nb, bs, tol, 1, nullptr, proj.alldone(), sh->P(), sh->C());
+      launch_b_project<R>(S(), dvec(), k, d->M.as<double2>(), d->Pi.as<double2>(), x, rr, n, nb, bs, sh->P());
+      launch_b_norm<R>(S(), rr, n, nb, bs, tol, 1, nullptr, sh->P());
       launch_b_scale_beta<R>(S(), rr, V, n, nb, bs);
       for (int j = 0; j < mm; ++j) {
-        apply(2, V + j * ld, V + (j + 1) * ld, nullptr, proj.alldone());
-        launch_b_arnoldi<R>(S(), V, ld, n, nb, j, bs, proj.alldone(), sh->P(), sh->C());
+        apply(2, V + j * ld, V + (j + 1) * ld, nullptr, bs);
+        launch_b_arnoldi<R>(S(), V, ld, n, nb, j, bs, proj.anyp2(), sh->P());
       }
       launch_b_ls_solve(S(), bs, nb);
       launch_b_combine<R>(S(), x, V, ld, n, nb, bs, 0, 1);
@@ -242,7 +243,7 @@ struct BPre {
     bool first = true;
     for (;;) {
       sh->set_state(bs, act, cap);
-      launch_b_norm<R>(S(), rr, n, nb, bs, p->int_tol, first ? 2 : 1, nullptr, e1.alldone(), sh->P(), sh->C());
+      launch_b_norm<R>(S(), rr, n, nb, bs, p->int_tol, first ? 2 : 1, nullptr, sh->P());
       launch_b_scale_beta<R>(S(), rr, V, n, nb, bs);
       first = false;
       int jmax = 0;
@@ -250,10 +251,10 @@ struct BPre {
         if (act[r]) jmax = std::max(jmax, cap[r]);
       for (int j = 0; j < jmax; ++j) {
         cycle1(V + j * ld, Z + j * ld);
-        apply(1, Z + j * ld, V + (j + 1) * ld, nullptr, e1.alldone());
+        apply(1, Z + j * ld, V + (j + 1) * ld, nullptr, bs);
         mv[1]++;
-        launch_b_arnoldi<R>(S(), V, ld, n, nb, j, bs, e1.alldone(), sh->P(), sh->C());
-        if (sh->all_done(e1.alldone())) break;
+        launch_b_arnoldi<R>(S(), V, ld, n, nb, j, bs, e1.anyp2(), sh->P());
+        if (sh->all_done(bs, e1.flags())) break;
       }
       launch_b_ls_solve(S(), bs, nb);
       launch_b_combine<R>(S(), x, Z, ld, n, nb, bs, 0, 1);
@@ -378,7 +379,7 @@ void BWork::start_lanes(const std::vector<int>& lanes) {
   const int64_t n = h->op[0].n;
   BS* bs = outer.st();
   // ||b|| of every lane (the other lanes' values are recomputed unchanged)
-  launch_b_norm<double>(s, B.as<double2>(), n, nb, bs, 0.0, 3, nullptr, nullptr, sh.P(), sh.C());
+  launch_b_norm<double>(s, B.as<double2>(), n, nb, bs, 0.0, 3, nullptr, sh.P());
   for (int r : lanes) {
     launch_b_lane_copy(s, B.as<double2>(), Rr.as<double2>(), n, nb, r);
     launch_b_lane_copy(s, (const double2*)nullptr, X.as<double2>(), n, nb, r);
@@ -415,7 +416,7 @@ void BWork::cycle() {
     cap[r] = act[r] ? std::min(p.outer_m, p.max_outer_iters - it[r]) : 0;
   }
   sh.set_state(bs, act, cap);
-  launch_b_norm<double>(s, Rp, n, nb, bs, p.tol, 1, nullptr, outer.alldone(), sh.P(), sh.C());
+  launch_b_norm<double>(s, Rp, n, nb, bs, p.tol, 1, nullptr, sh.P());
   launch_b_scale_beta<double>(s, Rp, V, n, nb, bs);
   long long fine = 0;
   for (int j = 0; j < p.outer_m; ++j) {
@@ -429,18 +430,18 @@ void BWork::cycle() {
       pc64.cycle0(vj, zj);
     }
     hipEvent_t ta = timer_mark(h->ctx, DMG_KT_WILSON_BATCHED, s);
-    launch_b_wilson<double>(s, A.U64, zj, V + (j + 1) * ld, A.m0, A.Lx, A.Lt, nb, nullptr, outer.alldone());
+    launch_b_wilson<double>(s, A.U64, zj, V + (j + 1) * ld, A.m0, A.Lx, A.Lt, nb, nullptr, bs);
     if (ta) timer_span(h->ctx, DMG_KT_WILSON_BATCHED, ta, timer_mark(h->ctx, DMG_KT_WILSON_BATCHED, s),
                        (long long)A.Lx * A.Lt * nb);
     fine++;
-    launch_b_arnoldi<double>(s, V, ld, n, nb, j, bs, outer.alldone(), sh.P(), sh.C());
-    if (sh.all_done(outer.alldone())) break;
+    launch_b_arnoldi<double>(s, V, ld, n, nb, j, bs, outer.anyp2(), sh.P());
+    if (sh.all_done(bs, outer.flags())) break;
   }
   launch_b_ls_solve(s, bs, nb);
   launch_b_combine<double>(s, Xp, Z, ld, n, nb, bs, 0, 1);
   launch_b_wilson<double>(s, A.U64, Xp, Rp, A.m0, A.Lx, A.Lt, nb, Bp, nullptr);  // Rr = B - D X
   fine++;
-  launch_b_norm<double>(s, Rp, n, nb, bs, 0.0, 0, rn.as<double>(), nullptr, sh.P(), sh.C());
+  launch_b_norm<double>(s, Rp, n, nb, bs, 0.0, 0, rn.as<double>(), sh.P());
   std::vector<double> rnh(nb);
   DMG_HIP(hipMemcpyAsync(rnh.data(), rn.p, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
   sh.read_tails(bs);
