@@ -228,6 +228,10 @@ typedef struct {
                               Arnoldi sub-step */
   int int_mode;            /* intermediate grid: 0 partial solve (FGMRES(int_m) to int_tol, the
                               default); 1 one intermediate cycle (smoothing-only treatment) */
+  int graphs;              /* lockstep solves (dmg_solve_batched, dmg_batch_*): 1 replays each
+                              coarse GMRES-Proj cycle as one captured HIP graph (default, unless a
+                              batched-kernel timer is on); 0 launches its kernels one by one.
+                              Results are the same either way */
 } dmg_solve_params;
 
 typedef struct {

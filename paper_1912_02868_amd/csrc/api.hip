@@ -130,6 +130,7 @@ void dmg_solve_params_default(dmg_solve_params* p) {
   p->use_x0 = 0;
   p->coarse_persistent = 1;
   p->int_mode = 0;
+  p->graphs = 1;
 }
 
 void dmg_setup_params_default(dmg_setup_params* p) {

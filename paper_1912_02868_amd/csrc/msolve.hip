@@ -107,7 +107,20 @@ struct BPre {
   BKry proj;
   long long mv[3] = {0, 0, 0};
 
-  hipStream_t S() const { return sh->s; }
+  // One GMRES-Proj cycle of the coarse solve replayed as a captured HIP graph (its ~190
+  // kernels have no host decision inside; their arguments are baked in and keyed below).
+  hipStream_t cap_s = nullptr;  // capture stream (capture needs a stream other than the null stream)
+  hipStream_t cur = nullptr;    // set while capturing
+  hipGraphExec_t cyc = nullptr;
+  const void* cyc_key[6] = {};
+  double cyc_tol = 0.0;
+  int cyc_k = -1, cyc_m = -1;
+
+  ~BPre() {
+    if (cyc) (void)hipGraphExecDestroy(cyc);
+    if (cap_s) (void)hipStreamDestroy(cap_s);
+  }
+  hipStream_t S() const { return cur ? cur : sh->s; }
   int64_t N(int l) const { return h->op[l].n; }
   const T* Pm(int l) const { return (const T*)h->tr[l].P((const T*)nullptr); }
 
@@ -169,14 +182,71 @@ struct BPre {
     return (const T*)(sizeof(R) == sizeof(double) ? (const void*)d->V64.p : (const void*)d->V32.p);
   }
 
+  // projection over the deflation space, then one GMRES(m - k) cycle, for every active lane
+  void coarse_cycle_kernels(T* x, T* rr, double tol) {
+    const int64_t n = N(2);
+    const int k = d->kk, mm = proj.m;
+    T* V = proj.V.as<T>();
+    const int64_t ld = n * nb;
+    BS* bs = proj.st();
+    launch_b_project<R>(S(), dvec(), k, d->M.as<double2>(), d->Pi.as<double2>(), x, rr, n, nb, bs, sh->P());
+    launch_b_norm<R>(S(), rr, n, nb, bs, tol, 1, nullptr, sh->P());
+    launch_b_scale_beta<R>(S(), rr, V, n, nb, bs);
+    for (int j = 0; j < mm; ++j) {
+      apply(2, V + j * ld, V + (j + 1) * ld, nullptr, bs);
+      launch_b_arnoldi<R>(S(), V, ld, n, nb, j, bs, proj.anyp2(), sh->P());
+    }
+    launch_b_ls_solve(S(), bs, nb);
+    launch_b_combine<R>(S(), x, V, ld, n, nb, bs, 0, 1);
+    launch_b_combine<R>(S(), rr, V, ld, n, nb, bs, 1, 0);
+  }
+
+  void coarse_cycle(T* x, T* rr, double tol) {
+    const int timed = (1 << DMG_KT_BLOCK_BATCHED) | (1 << DMG_KT_WILSON_BATCHED);
+    if (!p->graphs || (h->ctx->timing & timed)) {
+      coarse_cycle_kernels(x, rr, tol);
+      return;
+    }
+    const void* key[6] = {x, rr, proj.V.p, dvec(), d->M.p, d->Pi.p};
+    bool same = cyc && cyc_tol == tol && cyc_k == d->kk && cyc_m == proj.m;
+    for (int i = 0; i < 6; ++i) same = same && key[i] == cyc_key[i];
+    if (!same) {
+      if (cyc) {
+        DMG_HIP(hipGraphExecDestroy(cyc));
+        cyc = nullptr;
+      }
+      if (!cap_s) DMG_HIP(hipStreamCreateWithFlags(&cap_s, hipStreamNonBlocking));
+      DMG_HIP(hipStreamBeginCapture(cap_s, hipStreamCaptureModeThreadLocal));
+      cur = cap_s;
+      hipGraph_t g = nullptr;
+      try {
+        coarse_cycle_kernels(x, rr, tol);
+      } catch (...) {
+        cur = nullptr;
+        (void)hipStreamEndCapture(cap_s, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      cur = nullptr;
+      DMG_HIP(hipStreamEndCapture(cap_s, &g));
+      const hipError_t e = hipGraphInstantiate(&cyc, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      DMG_HIP(e);
+      for (int i = 0; i < 6; ++i) cyc_key[i] = key[i];
+      cyc_tol = tol;
+      cyc_k = d->kk;
+      cyc_m = proj.m;
+    }
+    DMG_HIP(hipGraphLaunch(cyc, sh->s));
+  }
+
   // GMRES-Proj(m, k) from x = 0 on the coarse grid, one stopping decision per right-hand side
   void coarse_solve(const T* b, T* x) {
     const int64_t n = N(2);
-    const int k = d->kk, mm = proj.m;
+    const int mm = proj.m;
     double tol = p->coarse_tol_later;
     if (sizeof(R) == sizeof(float)) tol = std::max(tol, 1e-5);
     T* rr = pr.as<T>();
-    T* V = proj.V.as<T>();
     const int64_t ld = n * nb;
     BS* bs = proj.st();
     DMG_HIP(hipMemsetAsync(x, 0, sizeof(T) * ld, S()));
@@ -185,16 +255,7 @@ struct BPre {
     sh->set_state(bs, act, cap);
     launch_b_norm<R>(S(), b, n, nb, bs, 0.0, 3, nullptr, sh->P());
     for (;;) {
-      launch_b_project<R>(S(), dvec(), k, d->M.as<double2>(), d->Pi.as<double2>(), x, rr, n, nb, bs, sh->P());
-      launch_b_norm<R>(S(), rr, n, nb, bs, tol, 1, nullptr, sh->P());
-      launch_b_scale_beta<R>(S(), rr, V, n, nb, bs);
-      for (int j = 0; j < mm; ++j) {
-        apply(2, V + j * ld, V + (j + 1) * ld, nullptr, bs);
-        launch_b_arnoldi<R>(S(), V, ld, n, nb, j, bs, proj.anyp2(), sh->P());
-      }
-      launch_b_ls_solve(S(), bs, nb);
-      launch_b_combine<R>(S(), x, V, ld, n, nb, bs, 0, 1);
-      launch_b_combine<R>(S(), rr, V, ld, n, nb, bs, 1, 0);
+      coarse_cycle(x, rr, tol);
       sh->read_tails(bs);
       int most = 0;
       bool any = false;

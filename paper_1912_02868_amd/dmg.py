@@ -72,7 +72,8 @@ class SolveParams(C.Structure):
                 ("smooth_steps", C.c_int), ("int_tol", C.c_double), ("int_m", C.c_int),
                 ("int_max_iters", C.c_int), ("coarse_tol_first", C.c_double),
                 ("coarse_tol_later", C.c_double), ("coarse_max_iters", C.c_int),
-                ("precond", C.c_int), ("use_x0", C.c_int), ("coarse_persistent", C.c_int), ("int_mode", C.c_int)]
+                ("precond", C.c_int), ("use_x0", C.c_int), ("coarse_persistent", C.c_int), ("int_mode", C.c_int),
+                ("graphs", C.c_int)]
 
 
 class SolveStats(C.Structure):

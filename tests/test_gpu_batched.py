@@ -101,6 +101,32 @@ def test_batched_errors(dmg, ctx, cfg64):
     fresh.close()
 
 
+@pytest.mark.parametrize("precond", ["fp64", "fp32"])
+def test_batched_graph_replay_matches_eager(dmg, ctx, cfg64, precond):
+    """Each coarse GMRES-Proj cycle replayed from a captured HIP graph (hundreds of replays per
+    solve, with host reads between them) gives bitwise the solution of launching its kernels
+    one by one, on two solves in a row."""
+    th, m0, g, h, d, D, lu = cfg64
+    nrhs = 8
+    b = np.stack([synth.rhs(64, 0, 40 + j) for j in range(nrhs)])
+    out = {}
+    for graphs in (1, 0, 1):
+        xs = []
+        for rep in range(2):
+            x = np.empty_like(b)
+            st, stats = dmg.solve_batched(ctx, h, d, b, x, nrhs,
+                                          params=dmg.solve_params(precond=precond, graphs=graphs))
+            assert st == dmg.DMG_OK and all(s["converged"] == 1 for s in stats)
+            xs.append((x, [s["outer_iters"] for s in stats], [s["coarse_mvps"] for s in stats]))
+        assert np.array_equal(xs[0][0], xs[1][0]) and xs[0][1:] == xs[1][1:]
+        out.setdefault(graphs, []).append(xs[0])
+    eager, graph = out[0][0], out[1]
+    for gx in graph:
+        assert np.array_equal(gx[0], eager[0]) and gx[1:] == eager[1:]
+    for j in range(nrhs):
+        assert np.linalg.norm(b[j] - D @ eager[0][j]) / np.linalg.norm(b[j]) <= 1e-8 * (1 + 1e-6)
+
+
 # ---------------------------------------------------------------- multi-RHS kernels vs the oracle
 @pytest.fixture(scope="module")
 def inj64(dmg, ctx):
