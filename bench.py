@@ -59,6 +59,13 @@ def parse():
     ap.add_argument("--serve-configs", type=int, default=4, help="resident configurations per lattice size")
     ap.add_argument("--serve-requests", type=int, default=200, help="requests per arrival rate")
     ap.add_argument("--serve-capacity", type=int, default=16, help="lanes per resident configuration")
+    ap.add_argument("--scan", action="store_true",
+                    help="mass-gap and lattice-size scan of six solvers with power-law fits (prints its own JSON)")
+    ap.add_argument("--scan-sizes", default="64,128,256")
+    ap.add_argument("--scan-configs", type=int, default=2)
+    ap.add_argument("--scan-gaps", default="1e-1,1e-2,1e-3,1e-4")
+    ap.add_argument("--scan-fit-gap", type=float, default=1e-4)
+    ap.add_argument("--scan-rhs", type=int, default=2)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for hardware byte counters)")
     return ap.parse_args()
@@ -82,6 +89,12 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     dmg.lib()
+    if a.scan:
+        ctx = dmg.Context(0)
+        out = scan(torch, dmg, ctx, [int(v) for v in a.scan_sizes.split(",")], a.scan_configs,
+                   [float(v) for v in a.scan_gaps.split(",")], a.scan_fit_gap, a.scan_rhs)
+        print(json.dumps(out), flush=True)
+        return
     N = a.lattice
     ctx = dmg.Context(0)
     stream = torch.cuda.current_stream()
@@ -555,6 +568,106 @@ def cpu_baseline(N, budget_s, gpu_outer_iters):
                       f"({iters} outer iterations; the first solve includes GMRES-DR); oracle setup "
                       f"{setup_s:.1f} s not charged; scipy sparse products are single-threaded",
             "cpu": platform.processor() or platform.machine(), "host_cpus": os.cpu_count()}
+
+
+# ---------------------------------------------------------------- mass-gap / lattice-size scan
+SCAN_METHODS = ("deflated MG with partial solves", "deflated MG", "GMRES-DR", "nondeflated MG with partial solve",
+                "CGNE", "nondeflated MG")
+FINE_DR_M, FINE_DR_K = 48, 16  # the paper's fine GMRES-DR is (200, 40); the device restart (LDS-resident) takes m <= 48
+
+
+def power_fit(sizes, values):
+    """Least-squares line through (log size, log value): returns (alpha, standard error)."""
+    x = np.log(np.asarray(sizes, dtype=float))
+    y = np.log(np.asarray(values, dtype=float))
+    A = np.stack([x, np.ones_like(x)], axis=1)
+    coef, *_ = np.linalg.lstsq(A, y, rcond=None)
+    n = len(x)
+    if n <= 2 or len(set(x.tolist())) < 2:
+        return float(coef[0]), None
+    resid = y - A @ coef
+    s2 = float(resid @ resid) / (n - 2)
+    se = np.sqrt(s2 / float(((x - x.mean()) ** 2).sum()))
+    return float(coef[0]), float(se)
+
+
+def scan(torch, dmg, ctx, sizes, ncfg, gaps, fit_gap, nrhs):
+    """Fine-equivalent Mvps (eq. (1)) of six solvers over mass gaps m0 - m_c and lattice sizes,
+    on the synthetic ensembles (not the paper's configurations): deflated multigrid with the
+    partial intermediate solve (the default), deflated multigrid with intermediate smoothing
+    only and the 1e-15 / 1e-8 coarse schedule, the same two without deflation (coarse CGNE to
+    1e-8), fine-grid GMRES-DR and fine-grid CGNE.  Each configuration gets its own hierarchy at
+    each mass and a fresh deflation space; right-hand sides 0 .. nrhs-1 are solved in turn.
+    The power alpha in Mvps = size^alpha is fitted over sizes at the fit gap, with size the
+    number of lattice sites (alpha per lattice extent is twice that)."""
+    import synth
+    gaps = sorted(set(gaps + [fit_gap]), reverse=True)
+    rows = []
+    t_start = time.perf_counter()
+    for N in sizes:
+        for c in range(ncfg):
+            mc = synth.critical_mass(N, c)
+            g = dmg.Gauge(ctx, synth.gauge_angles(N, c))
+            B = [torch.from_numpy(synth.rhs(N, c, j)).cuda() for j in range(nrhs)]
+            X = torch.empty_like(B[0])
+            for gap in gaps:
+                t0 = time.perf_counter()
+                h = dmg.Hierarchy(ctx, g, mc + gap, torch.from_numpy(synth.near_null_starts(N, c, 0)).cuda(),
+                                  torch.from_numpy(synth.near_null_starts(N, c, 1)).cuda())
+                torch.cuda.synchronize()
+                setup_s = time.perf_counter() - t0
+                for meth in SCAN_METHODS:
+                    d = dmg.Deflation(h, 30, 10) if meth.startswith("deflated") else None
+                    prm = dmg.solve_params()
+                    if meth in ("deflated MG", "nondeflated MG"):
+                        prm = dmg.solve_params(int_mode=1, coarse_tol_first=1e-15, coarse_tol_later=1e-8)
+                    per = []
+                    t1 = time.perf_counter()
+                    for j in range(nrhs):
+                        if meth == "GMRES-DR":
+                            st, ss = dmg.solve_fine(ctx, h, dmg.FINE_GMRES_DR, B[j], X, m=FINE_DR_M, k=FINE_DR_K,
+                                                    max_iters=20000)
+                        elif meth == "CGNE":
+                            st, ss = dmg.solve_fine(ctx, h, dmg.FINE_CGNE, B[j], X, max_iters=200000)
+                        else:
+                            st, ss = dmg.solve(ctx, h, d, B[j], X, params=prm)
+                        per.append(ss[0])
+                    torch.cuda.synchronize()
+                    el = time.perf_counter() - t1
+                    if d is not None:
+                        d.close()
+                    row = {"N": N, "cfg": c, "gap": gap, "method": meth,
+                           "fine_equiv_mvps": float(np.mean([s["fine_equiv_mvps"] for s in per])),
+                           "fine_mvps": float(np.mean([s["fine_mvps"] for s in per])),
+                           "int_mvps": float(np.mean([s["int_mvps"] for s in per])),
+                           "coarse_mvps": float(np.mean([s["coarse_mvps"] for s in per])),
+                           "outer_iters": float(np.mean([s["outer_iters"] for s in per])),
+                           "converged": all(s["converged"] == 1 for s in per),
+                           "max_true_rel_resid": float(max(s["true_rel_resid"] for s in per)),
+                           "seconds": el, "setup_s": setup_s}
+                    rows.append(row)
+                    print(f"[scan] {N}^2 cfg {c} gap {gap:g} {meth}: {row['fine_equiv_mvps']:.0f} fine-equivalent "
+                          f"Mvps, converged {row['converged']}, {el:.1f} s", file=sys.stderr, flush=True)
+                h.close()
+            g.close()
+    def fits_at(gap):
+        out = {}
+        for meth in SCAN_METHODS:
+            pts = [(r["N"] * r["N"], r["fine_equiv_mvps"]) for r in rows
+                   if r["method"] == meth and r["gap"] == gap and r["converged"]]
+            if len({p[0] for p in pts}) >= 2:
+                a_, se = power_fit([p[0] for p in pts], [p[1] for p in pts])
+                out[meth] = {"alpha": a_, "stderr": se, "points": len(pts)}
+        return out
+
+    fits = fits_at(fit_gap)
+    fits_by_gap = {f"{gap:g}": fits_at(gap) for gap in gaps}
+    return {"scan": "fine-equivalent Mvps vs mass gap and lattice size (synthetic ensembles)",
+            "sizes": sizes, "configs_per_size": ncfg, "gaps": gaps, "rhs_per_config": nrhs,
+            "fit_gap": fit_gap, "size_measure": "lattice sites", "alpha_fits": fits,
+            "alpha_fits_by_gap": fits_by_gap,
+            "fine_gmres_dr": [FINE_DR_M, FINE_DR_K], "rows": rows,
+            "wall_s": time.perf_counter() - t_start}
 
 
 if __name__ == "__main__":

@@ -244,9 +244,10 @@ typedef struct {
   double elapsed_ms;
 } dmg_solve_stats;
 
-/* Fill p with the paper's defaults.  GMRES-DR (first coarse call) also ends when a cycle
- * lowers its residual by less than 1 % (a tolerance such as 1e-15 that the arithmetic
- * cannot reach). */
+/* Fill p with the paper's defaults.  GMRES-DR (first coarse call, and the fine-grid
+ * comparison solver) also ends when, with the relative residual already at or below 1e-10,
+ * a cycle lowers it by less than 1 % (a tolerance such as 1e-15 that the arithmetic cannot
+ * reach). */
 void dmg_solve_params_default(dmg_solve_params* p);
 void dmg_setup_params_default(dmg_setup_params* p);
 

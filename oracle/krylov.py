@@ -272,16 +272,18 @@ def _compress(V, H_bar, k, s=None):
     return Vk1, Hk, P, theta
 
 
-def gmres_dr(A, b, m, k, tol, max_cycles=1000, stall=0.99):
+def gmres_dr(A, b, m, k, tol, max_cycles=1000, stall=0.99, stall_floor=1e-10):
     """GMRES-DR(m, k) from x0 = 0 (Morgan, deflated restarting).
 
     Returns (x, info, Deflation).  Each cycle extends the Arnoldi relation to m
     columns, solves min || c - Hbar d ||, and restarts with the k smallest
     harmonic Ritz vectors plus the residual direction, so that the kept space
     satisfies A V_k = V_{k+1} Hbar_k.  On termination the space is compressed
-    once more to k vectors for later projections.  A cycle that lowers the
-    residual by less than the factor `stall` ends the solve (a tolerance below
-    what the arithmetic reaches, such as 1e-15, otherwise never stops).
+    once more to k vectors for later projections.  Once the relative residual
+    is at or below `stall_floor` (the rounding regime of these FP64 systems), a
+    cycle that lowers it by less than the factor `stall` ends the solve: a
+    tolerance below what the arithmetic reaches, such as 1e-15, otherwise never
+    stops, while a slow stretch above the floor is ordinary convergence.
     """
     n = b.shape[0]
     x = np.zeros_like(b)
@@ -325,7 +327,8 @@ def gmres_dr(A, b, m, k, tol, max_cycles=1000, stall=0.99):
             info.converged = True
             info.rel_resid = est / bn
             break
-        if stall and len(info.history) > 1 and info.history[-1] > stall * info.history[-2]:
+        if (stall and len(info.history) > 1 and info.history[-1] > stall * info.history[-2]
+                and info.history[-1] <= stall_floor):
             info.stagnated = True
             info.rel_resid = est / bn
             break

@@ -131,8 +131,9 @@ int coarse_gmres_dr(dmg_hierarchy* h, Work* w, dmg_deflation* d, const double2* 
     iters += st.steps - j0;
     w->cnt.mv[2] += st.steps - j0;
     if (st.done || iters >= max_iters) break;
-    // a cycle that lowers the residual by less than 1 % ends the solve (unreachable tolerance)
-    if (prev_est > 0.0 && st.est > 0.99 * prev_est) break;
+    // in the rounding regime (relative residual <= 1e-10), a cycle that lowers the residual by
+    // less than 1 % ends the solve (a tolerance the arithmetic cannot reach)
+    if (prev_est > 0.0 && st.est > 0.99 * prev_est && st.est <= 1e-10 * st.bnorm) break;
     prev_est = st.est;
     // deflated restart: keep the k smallest harmonic Ritz vectors and the residual
     launch_dr_restart(s, ks, m, k, w->dr_P.as<double2>(), 0, w->dr_work.as<double2>(), status);

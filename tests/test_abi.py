@@ -72,3 +72,19 @@ def test_bench_refuses_several_gpus():
     import sys
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_bench_power_fit():
+    """The scan's power-law fit: an exact power law gives its exponent with zero error; with
+    multiplicative noise the estimate stays within a few standard errors of the truth."""
+    import numpy as np
+    import bench
+    sizes = np.array([64, 128, 256, 64, 128, 256], dtype=float) ** 2
+    a, se = bench.power_fit(sizes, 7.0 * sizes ** 0.37)
+    assert abs(a - 0.37) < 1e-12 and se < 1e-12
+    rng = np.random.default_rng(5)
+    vals = 7.0 * sizes ** 0.37 * np.exp(0.05 * rng.standard_normal(len(sizes)))
+    a, se = bench.power_fit(sizes, vals)
+    assert se > 0 and abs(a - 0.37) < 4 * se
+    a, se = bench.power_fit([100.0, 100.0], [3.0, 4.0])
+    assert se is None

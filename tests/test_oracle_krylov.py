@@ -132,6 +132,23 @@ def test_gmres_dr_unreachable_tolerance_stops():
     assert rel < 1e-10
 
 
+def test_gmres_dr_slow_stretch_above_floor_continues():
+    """A cycle with less than 1 % progress ends GMRES-DR only in the rounding regime: on the
+    cyclic shift plus 0.05 I (eigenvalues on the unit circle moved by 0.05) a
+    short restarted cycle from e_1 leaves the residual at 0.9987, far above
+    the floor, so the solve runs to its cycle cap instead of calling that stagnation; with
+    the floor raised to 1 it stops after two cycles."""
+    n = 24
+    A = np.roll(np.eye(n), 1, axis=0).astype(complex) + 0.05 * np.eye(n)
+    b = np.zeros(n, dtype=complex)
+    b[0] = 1.0
+    x, info, _ = krylov.gmres_dr(_op(A), b, 6, 2, 1e-8, max_cycles=7)
+    assert not info.stagnated and not info.converged and info.cycles == 7
+    assert all(h > 0.99 for h in info.history)
+    x, info, _ = krylov.gmres_dr(_op(A), b, 6, 2, 1e-8, max_cycles=7, stall_floor=1.0)
+    assert info.stagnated and info.cycles == 2
+
+
 def test_gmres_dr_k0_is_gmres():
     A = _dirac(8, 2, 0.05)
     b = synth.rhs(8, 2, 2)
