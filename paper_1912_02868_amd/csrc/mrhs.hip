@@ -61,7 +61,7 @@ __device__ void b_publish(const double2 (&acc)[NQ], int nq, int nb, double2* par
 // Second phase of every batched reduction: one workgroup per right-hand side adds the
 // workgroups' partials of each quantity (4 lanes per quantity, then the lanes in
 // order) and applies the step's small-dense epilogue to that right-hand side.
-enum FinMode { FIN_NORM0, FIN_NORM3, FIN_START, FIN_ARN1, FIN_ARN2, FIN_ARN3, FIN_SMOOTH2, FIN_PROJ };
+enum FinMode { FIN_NORM0, FIN_NORM3, FIN_START, FIN_ARN1, FIN_ARN2, FIN_SMOOTH2, FIN_PROJ };
 
 struct FinArgs {
   int mode, nq, nblk, nb, j, k;
@@ -163,7 +163,7 @@ __global__ void __launch_bounds__(BT) kb_final(const double2* __restrict__ part,
   static_assert(BMAXBLK <= 2 * BT, "at most two partials per thread and quantity");
   const int r = blockIdx.x, t = threadIdx.x;
   const bool skip = a.mode == FIN_ARN1                           ? lanes_all_done(bs, a.nb)
-                    : (a.mode == FIN_ARN2 || a.mode == FIN_ARN3) ? !*a.anyp2
+                    : a.mode == FIN_ARN2                         ? !*a.anyp2
                                                                  : false;
   // Each thread adds the partials t and t + BT of every quantity (contiguous per quantity, so
   // a wavefront's loads coalesce; all loads are issued before the first add); a fixed shuffle
@@ -185,7 +185,7 @@ __global__ void __launch_bounds__(BT) kb_final(const double2* __restrict__ part,
   }
   BS& b = bs[r];
   const int j = a.j;
-  if (a.mode == FIN_ARN1 || a.mode == FIN_ARN3) {
+  if (a.mode == FIN_ARN1 || a.mode == FIN_ARN2) {
     if (t < j) {
       st.rc[t] = b.rc[t];
       st.rs[t] = b.rs[t];
@@ -288,20 +288,26 @@ __global__ void __launch_bounds__(BT) kb_final(const double2* __restrict__ part,
       }
       break;
     }
-    case FIN_ARN2:
-      if (b.pass2 == 1)
-        for (int i = t; i <= j; i += BT) {
-          b.h2[i] = tot[i];
-          b.H[LDH * j + i] = cadd(b.H[LDH * j + i], tot[i]);
-        }
-      break;
-    case FIN_ARN3: {
-      __shared__ double2 col3[MB + 2];
+    case FIN_ARN2: {
+      // second pass: H(:, j) += h2, norm ||w||^2 - ||h2||^2 (no cancellation after the first
+      // pass), then the Givens update; the next kernel subtracts V h2 and normalises
+      __shared__ double2 col2[MB + 2];
+      __shared__ double rest2;
       if (st.pass2 == 1) {
-        for (int i = t; i <= j; i += BT) col3[i] = b.H[LDH * j + i];
-        if (t == 0) b.pass2 = 2;  // normalised by the next kernel
+        for (int i = t; i <= j; i += BT) {
+          const double2 hij = cadd(b.H[LDH * j + i], tot[i]);
+          b.h2[i] = tot[i];
+          b.H[LDH * j + i] = hij;
+          col2[i] = hij;
+        }
+        if (t == 0) {
+          double hh = 0.0;
+          for (int i = 0; i <= j; ++i) hh += cabs2(tot[i]);
+          rest2 = tot[j + 1].x - hh;
+          b.pass2 = 2;
+        }
         __syncthreads();
-        fin_givens(b, j, tot[0].x, st.wn0, col3, st);
+        fin_givens(b, j, rest2 > 0.0 ? rest2 : 0.0, st.wn0, col2, st);
       }
       break;
     }
@@ -443,7 +449,8 @@ __global__ void __launch_bounds__(BT) kb_arn_update(cx<R>* __restrict__ V, int64
   }
 }
 
-// (b') h2_i = V_i^H w of the updated w, for the right-hand sides that need a second pass
+// (c) h2_i = V_i^H w and ||w||^2 of the updated w, for the right-hand sides that need a
+// second pass (returns at once when none does)
 template <typename R>
 __global__ void __launch_bounds__(BT) kb_arn_dots2(const cx<R>* __restrict__ V, int64_t ld, int64_t n, int nb, int j,
                                                    const BS* bs, const int* anyp2, double2* part) {
@@ -453,64 +460,49 @@ __global__ void __launch_bounds__(BT) kb_arn_dots2(const cx<R>* __restrict__ V, 
   const int64_t N = n * nb;
   const int64_t stride = (int64_t)gridDim.x * BT;
   const cx<R>* w = V + (int64_t)(j + 1) * ld;
-  double2 acc[MB + 1];
+  double2 acc[MB + 2];
 #pragma unroll
-  for (int q = 0; q < MB + 1; ++q) acc[q] = mk(0.0, 0.0);
+  for (int q = 0; q < MB + 2; ++q) acc[q] = mk(0.0, 0.0);
   if (act)
     for (int64_t e = (int64_t)blockIdx.x * BT + threadIdx.x; e < N; e += stride) {
       const double2 wv = to_d(w[e]);
 #pragma unroll
       for (int i = 0; i < MB + 1; ++i)
         if (i <= j) cfmac(acc[i], to_d(V[(int64_t)i * ld + e]), wv);
+#pragma unroll
+      for (int i = 0; i < MB + 2; ++i)
+        if (i == j + 1) acc[i].x += cabs2(wv);
     }
-  b_publish<MB + 1>(acc, j + 1, nb, part);
+  b_publish<MB + 2>(acc, j + 2, nb, part);
 }
 
-// (c) second pass: w -= sum_i h2_i V_i and ||w||^2 for the flagged right-hand sides
+// (d) second pass: v_{j+1} = (w - sum_i h2_i V_i) / h_{j+1, j} for the right-hand sides that
+// took it (their Givens update ran in the second phase of (c))
 template <typename R>
-__global__ void __launch_bounds__(BT) kb_arn_update_norm(cx<R>* __restrict__ V, int64_t ld, int64_t n, int nb, int j,
-                                                         const BS* bs, const int* anyp2, double2* part) {
-  if (!*anyp2) return;
-  const int r0 = threadIdx.x & (nb - 1);
-  const bool skip = bs[r0].pass2 != 1;
-  double2 cf[MB + 1];
-#pragma unroll
-  for (int i = 0; i < MB + 1; ++i) cf[i] = (i <= j) ? bs[r0].h2[i] : mk(0.0, 0.0);
-  const int64_t N = n * nb;
-  const int64_t stride = (int64_t)gridDim.x * BT;
-  cx<R>* w = V + (int64_t)(j + 1) * ld;
-  double2 acc[1] = {mk(0.0, 0.0)};
-  for (int64_t e = (int64_t)blockIdx.x * BT + threadIdx.x; e < N; e += stride) {
-    double2 wv = to_d(w[e]);
-    if (!skip) {
-#pragma unroll
-      for (int i = 0; i < MB + 1; ++i)
-        if (i <= j) wv = csub(wv, cmul(cf[i], to_d(V[(int64_t)i * ld + e])));
-      const cx<R> st = from_d<R>(wv);
-      w[e] = st;
-      wv = to_d(st);
-    }
-    acc[0].x += cabs2(wv);
-  }
-  b_publish<1>(acc, 1, nb, part);
-}
-
-// (d) V_{j+1} = w / h_{j+1, j} for the right-hand sides that took a second pass (the others
-// were normalised by (b))
-template <typename R>
-__global__ void __launch_bounds__(BT) kb_arn_normalize(cx<R>* __restrict__ V, int64_t ld, int64_t n, int nb, int j,
-                                                       const BS* bs, const int* anyp2) {
+__global__ void __launch_bounds__(BT) kb_arn_update2(cx<R>* __restrict__ V, int64_t ld, int64_t n, int nb, int j,
+                                                     const BS* bs, const int* anyp2) {
   if (!*anyp2) return;
   const int r0 = threadIdx.x & (nb - 1);
   const BS& b = bs[r0];
-  if (b.pass2 != 2 || b.steps != j + 1 || b.brk) return;
-  const double hn = b.H[LDH * j + j + 1].x;
-  if (hn == 0.0) return;
-  const double inv = 1.0 / hn;
+  if (b.pass2 != 2 || b.steps != j + 1) return;
+  double scale = 1.0;
+  if (!b.brk) {
+    const double hn = b.H[LDH * j + j + 1].x;
+    if (hn != 0.0) scale = 1.0 / hn;
+  }
+  double2 cf[MB + 1];
+#pragma unroll
+  for (int i = 0; i < MB + 1; ++i) cf[i] = (i <= j) ? b.h2[i] : mk(0.0, 0.0);
   cx<R>* w = V + (int64_t)(j + 1) * ld;
   const int64_t N = n * nb;
   const int64_t stride = (int64_t)gridDim.x * BT;
-  for (int64_t e = (int64_t)blockIdx.x * BT + threadIdx.x; e < N; e += stride) w[e] = from_d<R>(cscale(to_d(w[e]), inv));
+  for (int64_t e = (int64_t)blockIdx.x * BT + threadIdx.x; e < N; e += stride) {
+    double2 wv = to_d(w[e]);
+#pragma unroll
+    for (int i = 0; i < MB + 1; ++i)
+      if (i <= j) wv = csub(wv, cmul(cf[i], to_d(V[(int64_t)i * ld + e])));
+    w[e] = from_d<R>(cscale(wv, scale));
+  }
 }
 
 template <typename R>
@@ -528,14 +520,8 @@ void launch_b_arnoldi(hipStream_t s, cx<R>* V, int64_t ld, int64_t n, int nb, in
   hipLaunchKernelGGL(kb_arn_dots2<R>, dim3(G), dim3(BT), 0, s, (const cx<R>*)V, ld, n, nb, j, (const BS*)bs,
                      (const int*)anyp2, part);
   a.mode = FIN_ARN2;
-  a.nq = j + 1;
   launch_final(s, part, bs, a);
-  hipLaunchKernelGGL(kb_arn_update_norm<R>, dim3(G), dim3(BT), 0, s, V, ld, n, nb, j, (const BS*)bs,
-                     (const int*)anyp2, part);
-  a.mode = FIN_ARN3;
-  a.nq = 1;
-  launch_final(s, part, bs, a);
-  hipLaunchKernelGGL(kb_arn_normalize<R>, dim3(vec_blocks(n * nb)), dim3(BT), 0, s, V, ld, n, nb, j, (const BS*)bs,
+  hipLaunchKernelGGL(kb_arn_update2<R>, dim3(vec_blocks(n * nb)), dim3(BT), 0, s, V, ld, n, nb, j, (const BS*)bs,
                      (const int*)anyp2);
   DMG_LAUNCH_CHECK();
 }
