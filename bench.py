@@ -374,7 +374,7 @@ def batched_block_roofline(torch, dmg, ctx, h, N, nrhs, reps=50):
     flops = sites * nrhs * 23040
     byts = sites * (5 * 576 * 8 + 2 * 24 * 8 * nrhs)
     tf = flops / (avg * 1e-3) / 1e12
-    return {"kernel": f"kb_block_mfma (FP32, {L}x{L} sites x 24 dof x {nrhs} right-hand sides, 16x16x4 MFMA)",
+    return {"kernel": f"kb_block_mfma_p (FP32, {L}x{L} sites x 24 dof x {nrhs} right-hand sides, 16x16x4 MFMA)",
             "bound": "mfma", "achieved": tf, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": tf / FP32_MFMA_PEAK_TFLOPS, "traffic": None, "avg_launch_us": avg * 1e3,
             "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": byts,

@@ -909,85 +909,107 @@ __global__ void __launch_bounds__(BT) kb_block(const cx<R>* __restrict__ A, cons
 // FP32 blocked operator on the matrix cores for nb = 16, 32 or 64 right-hand sides.
 // Per site and direction the complex product A_d (24 x 24) X_d (24 x nb) is the real
 // product [[Ar, -Ai], [Ai, Ar]] (48 x 48) [Xr; Xi] (48 x nb), run as 16 x 16 x 4 FP32
-// MFMA tiles: 3 row tiles x nb/16 column tiles x 12 k-steps, accumulated over the
-// five directions in the MFMA registers.  The neighbours' real and imaginary parts are
-// staged in LDS as separate planes; the A operand is read straight from memory (16
-// consecutive rows of one column per lane group).  Tile (m, nt) of the 48 x nb result
-// is owned by wavefront t mod 4 for t = m + 3 nt; results pass through LDS to be
-// written as complex entries (row i: real part row i, imaginary part row 24 + i).
+// MFMA tiles: 3 row tiles x nb/16 column tiles x 12 k-steps, accumulated over the five
+// directions in the MFMA registers (direction, then k-step, for every tile).
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-__global__ void __launch_bounds__(BT) kb_block_mfma(const float2* __restrict__ A, const float2* __restrict__ in,
-                                                    float2* __restrict__ out, int Lx, int Lt, int nb,
-                                                    const float2* __restrict__ sub, const BS* skip) {
-  if (skip && lanes_all_done(skip, nb)) return;
-  extern __shared__ __align__(16) unsigned char kb_smem[];
-  float* xre = (float*)kb_smem;            // [5][24][nb]
-  float* xim = xre + 5 * NC * nb;          // [5][24][nb]
-  const int S = blockIdx.x;
-  const int X = S % Lx, Tt = S / Lx;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nout = NC * nb;
+// One workgroup per site with one wavefront per 16-lane column tile (NTW = nb / 16
+// wavefronts).  The five hop directions are streamed through two LDS stages (block d as re / im
+// planes, the neighbour field of direction d as re / im planes): while the matrix cores work on
+// direction d, the loads of direction d + 1 are in flight.  Each wavefront keeps the three row
+// tiles of its column tile in three independent accumulators, so every B fragment read from LDS
+// feeds three MFMAs.  Results pass through LDS to be written as complex entries (row i: real
+// part, row 24 + i: imaginary part).
+template <int NTW>
+__global__ void __launch_bounds__(64 * NTW) kb_block_mfma_p(const float2* __restrict__ A,
+                                                            const float2* __restrict__ in,
+                                                            float2* __restrict__ out, int Lx, int Lt,
+                                                            const float2* __restrict__ sub, const BS* skip) {
+  constexpr int TB = 64 * NTW;
+  constexpr int NBW = 16 * NTW;                    // lanes (right-hand sides)
+  constexpr int RA = (NC * NC + TB - 1) / TB;      // block entries staged per thread
+  constexpr int RX = NC * NBW / TB;                // field entries staged per thread (= 6)
+  if (skip && lanes_all_done(skip, NBW)) return;
+  __shared__ float sa[2][2][NC * NC];              // [stage][re, im][c * NC + i]
+  __shared__ float sx[2][2][NC * NBW];             // [stage][re, im][c * nb + r]
+  const int site = blockIdx.x;
+  const int X = site % Lx, Tt = site / Lx;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   int nbS[5];
-  nbS[0] = S;
+  nbS[0] = site;
   nbS[1] = ((X + 1 == Lx) ? 0 : X + 1) + Lx * Tt;
   nbS[2] = ((X == 0) ? Lx - 1 : X - 1) + Lx * Tt;
   nbS[3] = X + Lx * ((Tt + 1 == Lt) ? 0 : Tt + 1);
   nbS[4] = X + Lx * ((Tt == 0) ? Lt - 1 : Tt - 1);
-  for (int d = 0; d < 5; ++d)
-    for (int p = tid; p < nout; p += BT) {
-      const float2 v = in[(int64_t)nbS[d] * nout + p];
-      xre[d * nout + p] = v.x;
-      xim[d * nout + p] = v.y;
+  const int nout = NC * NBW;
+  float2 ra[RA], rx[RX];
+  auto fetch = [&](int d) {
+    const float2* ad = A + ((int64_t)site * 5 + d) * NC * NC;
+#pragma unroll
+    for (int q = 0; q < RA; ++q) {
+      const int p = tid + q * TB;
+      if (p < NC * NC) ra[q] = ad[p];
     }
-  __syncthreads();
-  const int NT = nb / 16;
-  const int ntiles = 3 * NT;
-  v4f acc[3];
+    const float2* xd = in + (int64_t)nbS[d] * nout;
 #pragma unroll
-  for (int u = 0; u < 3; ++u) acc[u] = v4f{0.f, 0.f, 0.f, 0.f};
-  const int li = lane & 15, lk = lane >> 4;
-  for (int d = 0; d < 5; ++d) {
-    const float2* a = A + ((int64_t)S * 5 + d) * NC * NC;
-    const float* pr = xre + d * nout;
-    const float* pi = xim + d * nout;
+    for (int q = 0; q < RX; ++q) rx[q] = xd[tid + q * TB];
+  };
+  auto stash = [&](int st) {
 #pragma unroll
-    for (int u = 0; u < 3; ++u) {
-      const int t = wave + 4 * u;
-      if (t < ntiles) {
-        const int m = t % 3, nt = t / 3;
-        const int I = 16 * m + li;             // row of the 48-row product
-        const int i = I < NC ? I : I - NC;
-        const int j = 16 * nt + li;            // column (right-hand side)
-#pragma unroll
-        for (int kk = 0; kk < 12; ++kk) {
-          const int K = 4 * kk + lk;           // row of [Xr; Xi]
-          const int c = K < NC ? K : K - NC;
-          const float2 av = a[c * NC + i];
-          const float aval = (I < NC) ? (K < NC ? av.x : -av.y) : (K < NC ? av.y : av.x);
-          const float bval = (K < NC) ? pr[c * nb + j] : pi[c * nb + j];
-          acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(aval, bval, acc[u], 0, 0, 0);
-        }
+    for (int q = 0; q < RA; ++q) {
+      const int p = tid + q * TB;
+      if (p < NC * NC) {
+        sa[st][0][p] = ra[q].x;
+        sa[st][1][p] = ra[q].y;
       }
     }
-  }
-  __syncthreads();
-  // result planes [48][nb] reuse the staging area
-  float* res = xre;
 #pragma unroll
-  for (int u = 0; u < 3; ++u) {
-    const int t = wave + 4 * u;
-    if (t < ntiles) {
-      const int m = t % 3, nt = t / 3;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) res[(16 * m + 4 * lk + v) * nb + 16 * nt + li] = acc[u][v];
+    for (int q = 0; q < RX; ++q) {
+      sx[st][0][tid + q * TB] = rx[q].x;
+      sx[st][1][tid + q * TB] = rx[q].y;
     }
-  }
+  };
+  const int li = lane & 15, lk = lane >> 4;
+  const int j = 16 * w + li;  // column (right-hand side) of this lane's B fragment
+  v4f acc[3];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) acc[m] = v4f{0.f, 0.f, 0.f, 0.f};
+  fetch(0);
+  stash(0);
   __syncthreads();
-  for (int o = tid; o < nout; o += BT) {
-    const int i = o / nb, r = o % nb;
-    float2 y = make_float2(res[i * nb + r], res[(NC + i) * nb + r]);
-    const int64_t g = (int64_t)S * nout + o;
+  for (int d = 0; d < 5; ++d) {
+    const int st = d & 1;
+    if (d + 1 < 5) fetch(d + 1);
+    const float* are = sa[st][0];
+    const float* aim = sa[st][1];
+#pragma unroll
+    for (int kk = 0; kk < 12; ++kk) {
+      const int K = 4 * kk + lk;  // row of [Xr; Xi]
+      const int c = K < NC ? K : K - NC;
+      const float bval = sx[st][K < NC ? 0 : 1][c * NBW + j];
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        const int I = 16 * m + li;  // row of the 48-row product
+        const int i = I < NC ? I : I - NC;
+        const float aval = (I < NC) ? (K < NC ? are[c * NC + i] : -aim[c * NC + i])
+                                    : (K < NC ? aim[c * NC + i] : are[c * NC + i]);
+        acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(aval, bval, acc[m], 0, 0, 0);
+      }
+    }
+    if (d + 1 < 5) stash(st ^ 1);
+    __syncthreads();
+  }
+  // result planes [48][nb] in the (now free) field stage 0
+  float* res = &sx[0][0][0];
+#pragma unroll
+  for (int m = 0; m < 3; ++m)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) res[(16 * m + 4 * lk + v) * NBW + j] = acc[m][v];
+  __syncthreads();
+  for (int o = tid; o < nout; o += TB) {
+    const int ii = o / NBW, r = o % NBW;
+    float2 y = make_float2(res[ii * NBW + r], res[(NC + ii) * NBW + r]);
+    const int64_t g = (int64_t)site * nout + o;
     if (sub) y = make_float2(sub[g].x - y.x, sub[g].y - y.y);
     out[g] = y;
   }
@@ -998,9 +1020,12 @@ void launch_b_block(hipStream_t s, const cx<R>* A, const cx<R>* in, cx<R>* out, 
                     const cx<R>* sub, const BS* skip) {
   if constexpr (sizeof(R) == sizeof(float)) {
     if (nb >= 16 && b_block_mfma_enabled()) {
-      const size_t lds = (size_t)2 * 5 * NC * nb * sizeof(float);
-      hipLaunchKernelGGL(kb_block_mfma, dim3(Lx * Lt), dim3(BT), lds, s, (const float2*)A, (const float2*)in,
-                         (float2*)out, Lx, Lt, nb, (const float2*)sub, skip);
+      const dim3 g((unsigned)(Lx * Lt));
+      const float2 *A2 = (const float2*)A, *in2 = (const float2*)in, *sub2 = (const float2*)sub;
+      float2* out2 = (float2*)out;
+      if (nb == 16) hipLaunchKernelGGL(kb_block_mfma_p<1>, g, dim3(64), 0, s, A2, in2, out2, Lx, Lt, sub2, skip);
+      else if (nb == 32) hipLaunchKernelGGL(kb_block_mfma_p<2>, g, dim3(128), 0, s, A2, in2, out2, Lx, Lt, sub2, skip);
+      else hipLaunchKernelGGL(kb_block_mfma_p<4>, g, dim3(256), 0, s, A2, in2, out2, Lx, Lt, sub2, skip);
       DMG_LAUNCH_CHECK();
       return;
     }
