@@ -182,9 +182,9 @@ size_t dmg_hierarchy_part_bytes(const dmg_hierarchy* h, int level, int part);
 enum { DMG_OP_APPLY = 0, DMG_OP_APPLY_DAG = 1, DMG_OP_RESTRICT = 2, DMG_OP_PROLONG = 3 };
 /* The multi-right-hand-side kernels of dmg_solve_batched on nrhs fields at once
  * (parity hook): op DMG_OP_APPLY, DMG_OP_RESTRICT or DMG_OP_PROLONG as above; in and
- * out hold nrhs consecutive fields of precision p (1 <= nrhs <= 64).  FP32 block
- * stencils with 16 or more right-hand sides run on the matrix cores; mfma = 0 forces
- * the vector-FMA kernel instead. */
+ * out hold nrhs consecutive fields of precision p (1 <= nrhs <= 64).  Block stencils
+ * (FP32 and FP64) with 16 or more right-hand sides run on the matrix cores; mfma = 0
+ * forces the vector-FMA kernel instead. */
 dmg_status dmg_hierarchy_apply_batched(dmg_hierarchy* h, int level, int op, dmg_precision p, const void* in,
                                        void* out, int nrhs, int ptr_kind, int mfma);
 dmg_status dmg_hierarchy_apply(dmg_hierarchy* h, int level, int op, dmg_precision p,

@@ -906,10 +906,10 @@ __global__ void __launch_bounds__(BT) kb_block(const cx<R>* __restrict__ A, cons
   }
 }
 
-// FP32 blocked operator on the matrix cores for nb = 16, 32 or 64 right-hand sides.
+// Blocked operator on the matrix cores (FP32 or FP64) for nb = 16, 32 or 64 right-hand sides.
 // Per site and direction the complex product A_d (24 x 24) X_d (24 x nb) is the real
-// product [[Ar, -Ai], [Ai, Ar]] (48 x 48) [Xr; Xi] (48 x nb), run as 16 x 16 x 4 FP32
-// MFMA tiles: 3 row tiles x nb/16 column tiles x 12 k-steps, accumulated over the five
+// product [[Ar, -Ai], [Ai, Ar]] (48 x 48) [Xr; Xi] (48 x nb), run as 16 x 16 x 4 MFMA
+// tiles: 3 row tiles x nb/16 column tiles x 12 k-steps, accumulated over the five
 // directions in the MFMA registers (direction, then k-step, for every tile).
 typedef float v4f __attribute__((ext_vector_type(4)));
 
@@ -920,18 +920,34 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 // tiles of its column tile in three independent accumulators, so every B fragment read from LDS
 // feeds three MFMAs.  Results pass through LDS to be written as complex entries (row i: real
 // part, row 24 + i: imaginary part).
-template <int NTW>
-__global__ void __launch_bounds__(64 * NTW) kb_block_mfma_p(const float2* __restrict__ A,
-                                                            const float2* __restrict__ in,
-                                                            float2* __restrict__ out, int Lx, int Lt,
-                                                            const float2* __restrict__ sub, const BS* skip) {
+typedef double v4d __attribute__((ext_vector_type(4)));
+template <typename R> struct MfmaT;
+// 16 x 16 x 4 tiles: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; its four results
+// are column l % 16 and rows 4 (l / 16) + v (FP32) or 4 v + l / 16 (FP64).
+template <> struct MfmaT<float> {
+  using acc = v4f;
+  static __device__ inline acc step(float a, float b, acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  static __device__ inline int row(int lk, int v) { return 4 * lk + v; }
+};
+template <> struct MfmaT<double> {
+  using acc = v4d;
+  static __device__ inline acc step(double a, double b, acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  static __device__ inline int row(int lk, int v) { return 4 * v + lk; }
+};
+
+template <typename R, int NTW>
+__global__ void __launch_bounds__(64 * NTW) kb_block_mfma_p(const cx<R>* __restrict__ A, const cx<R>* __restrict__ in,
+                                                            cx<R>* __restrict__ out, int Lx, int Lt,
+                                                            const cx<R>* __restrict__ sub, const BS* skip) {
+  using T = cx<R>;
+  using M = MfmaT<R>;
   constexpr int TB = 64 * NTW;
   constexpr int NBW = 16 * NTW;                    // lanes (right-hand sides)
   constexpr int RA = (NC * NC + TB - 1) / TB;      // block entries staged per thread
   constexpr int RX = NC * NBW / TB;                // field entries staged per thread (= 6)
   if (skip && lanes_all_done(skip, NBW)) return;
-  __shared__ float sa[2][2][NC * NC];              // [stage][re, im][c * NC + i]
-  __shared__ float sx[2][2][NC * NBW];             // [stage][re, im][c * nb + r]
+  __shared__ R sa[2][2][NC * NC];                  // [stage][re, im][c * NC + i]
+  __shared__ R sx[2][2][NC * NBW];                 // [stage][re, im][c * nb + r]
   const int site = blockIdx.x;
   const int X = site % Lx, Tt = site / Lx;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -942,15 +958,15 @@ __global__ void __launch_bounds__(64 * NTW) kb_block_mfma_p(const float2* __rest
   nbS[3] = X + Lx * ((Tt + 1 == Lt) ? 0 : Tt + 1);
   nbS[4] = X + Lx * ((Tt == 0) ? Lt - 1 : Tt - 1);
   const int nout = NC * NBW;
-  float2 ra[RA], rx[RX];
+  T ra[RA], rx[RX];
   auto fetch = [&](int d) {
-    const float2* ad = A + ((int64_t)site * 5 + d) * NC * NC;
+    const T* ad = A + ((int64_t)site * 5 + d) * NC * NC;
 #pragma unroll
     for (int q = 0; q < RA; ++q) {
       const int p = tid + q * TB;
       if (p < NC * NC) ra[q] = ad[p];
     }
-    const float2* xd = in + (int64_t)nbS[d] * nout;
+    const T* xd = in + (int64_t)nbS[d] * nout;
 #pragma unroll
     for (int q = 0; q < RX; ++q) rx[q] = xd[tid + q * TB];
   };
@@ -971,46 +987,46 @@ __global__ void __launch_bounds__(64 * NTW) kb_block_mfma_p(const float2* __rest
   };
   const int li = lane & 15, lk = lane >> 4;
   const int j = 16 * w + li;  // column (right-hand side) of this lane's B fragment
-  v4f acc[3];
+  typename M::acc acc[3];
 #pragma unroll
-  for (int m = 0; m < 3; ++m) acc[m] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int m = 0; m < 3; ++m) acc[m] = typename M::acc{0, 0, 0, 0};
   fetch(0);
   stash(0);
   __syncthreads();
   for (int d = 0; d < 5; ++d) {
     const int st = d & 1;
     if (d + 1 < 5) fetch(d + 1);
-    const float* are = sa[st][0];
-    const float* aim = sa[st][1];
+    const R* are = sa[st][0];
+    const R* aim = sa[st][1];
 #pragma unroll
     for (int kk = 0; kk < 12; ++kk) {
       const int K = 4 * kk + lk;  // row of [Xr; Xi]
       const int c = K < NC ? K : K - NC;
-      const float bval = sx[st][K < NC ? 0 : 1][c * NBW + j];
+      const R bval = sx[st][K < NC ? 0 : 1][c * NBW + j];
 #pragma unroll
       for (int m = 0; m < 3; ++m) {
         const int I = 16 * m + li;  // row of the 48-row product
         const int i = I < NC ? I : I - NC;
-        const float aval = (I < NC) ? (K < NC ? are[c * NC + i] : -aim[c * NC + i])
-                                    : (K < NC ? aim[c * NC + i] : are[c * NC + i]);
-        acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(aval, bval, acc[m], 0, 0, 0);
+        const R aval = (I < NC) ? (K < NC ? are[c * NC + i] : -aim[c * NC + i])
+                                : (K < NC ? aim[c * NC + i] : are[c * NC + i]);
+        acc[m] = M::step(aval, bval, acc[m]);
       }
     }
     if (d + 1 < 5) stash(st ^ 1);
     __syncthreads();
   }
   // result planes [48][nb] in the (now free) field stage 0
-  float* res = &sx[0][0][0];
+  R* res = &sx[0][0][0];
 #pragma unroll
   for (int m = 0; m < 3; ++m)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) res[(16 * m + 4 * lk + v) * NBW + j] = acc[m][v];
+    for (int v = 0; v < 4; ++v) res[(16 * m + M::row(lk, v)) * NBW + j] = acc[m][v];
   __syncthreads();
   for (int o = tid; o < nout; o += TB) {
     const int ii = o / NBW, r = o % NBW;
-    float2 y = make_float2(res[ii * NBW + r], res[(NC + ii) * NBW + r]);
+    T y = make_cx<R>(res[ii * NBW + r], res[(NC + ii) * NBW + r]);
     const int64_t g = (int64_t)site * nout + o;
-    if (sub) y = make_float2(sub[g].x - y.x, sub[g].y - y.y);
+    if (sub) y = make_cx<R>(sub[g].x - y.x, sub[g].y - y.y);
     out[g] = y;
   }
 }
@@ -1018,17 +1034,13 @@ __global__ void __launch_bounds__(64 * NTW) kb_block_mfma_p(const float2* __rest
 template <typename R>
 void launch_b_block(hipStream_t s, const cx<R>* A, const cx<R>* in, cx<R>* out, int Lx, int Lt, int nb,
                     const cx<R>* sub, const BS* skip) {
-  if constexpr (sizeof(R) == sizeof(float)) {
-    if (nb >= 16 && b_block_mfma_enabled()) {
-      const dim3 g((unsigned)(Lx * Lt));
-      const float2 *A2 = (const float2*)A, *in2 = (const float2*)in, *sub2 = (const float2*)sub;
-      float2* out2 = (float2*)out;
-      if (nb == 16) hipLaunchKernelGGL(kb_block_mfma_p<1>, g, dim3(64), 0, s, A2, in2, out2, Lx, Lt, sub2, skip);
-      else if (nb == 32) hipLaunchKernelGGL(kb_block_mfma_p<2>, g, dim3(128), 0, s, A2, in2, out2, Lx, Lt, sub2, skip);
-      else hipLaunchKernelGGL(kb_block_mfma_p<4>, g, dim3(256), 0, s, A2, in2, out2, Lx, Lt, sub2, skip);
-      DMG_LAUNCH_CHECK();
-      return;
-    }
+  if (nb >= 16 && b_block_mfma_enabled()) {
+    const dim3 g((unsigned)(Lx * Lt));
+    if (nb == 16) hipLaunchKernelGGL((kb_block_mfma_p<R, 1>), g, dim3(64), 0, s, A, in, out, Lx, Lt, sub, skip);
+    else if (nb == 32) hipLaunchKernelGGL((kb_block_mfma_p<R, 2>), g, dim3(128), 0, s, A, in, out, Lx, Lt, sub, skip);
+    else hipLaunchKernelGGL((kb_block_mfma_p<R, 4>), g, dim3(256), 0, s, A, in, out, Lx, Lt, sub, skip);
+    DMG_LAUNCH_CHECK();
+    return;
   }
   const size_t one = (size_t)NC * nb * sizeof(cx<R>);
   const size_t lds = 5 * one <= 65536 ? 5 * one : one;

@@ -145,10 +145,11 @@ def _fields(n, nrhs, seed):
     return np.stack([synth.gaussian_complex(n, 64, seed, 11, j) for j in range(nrhs)])
 
 
-@pytest.mark.parametrize("prec,nrhs,mfma", [("fp64", 5, True), ("fp32", 16, True), ("fp32", 16, False),
+@pytest.mark.parametrize("prec,nrhs,mfma", [("fp64", 5, True), ("fp64", 16, True), ("fp64", 40, True),
+                                            ("fp64", 16, False), ("fp32", 16, True), ("fp32", 16, False),
                                             ("fp32", 40, True), ("fp32", 3, True)])
 def test_batched_operators(dmg, inj64, prec, nrhs, mfma):
-    """Multi-RHS fine stencil and 24 x 24 block stencils (matrix-core path for FP32 with
+    """Multi-RHS fine stencil and 24 x 24 block stencils (matrix-core path, FP32 or FP64, with
     16 or more right-hand sides) against the oracle's operators, one product per field."""
     H, g, hg = inj64
     for lvl in range(3):
