@@ -244,6 +244,25 @@ typedef struct {
   double elapsed_ms;
 } dmg_solve_stats;
 
+/* Autotuning of the lockstep stencils (process-wide, all contexts).  The multi-RHS block
+ * stencil on the matrix cores has launch forms with 64, 32 or 16 right-hand sides per
+ * workgroup (form 0, 1, 2; as nb allows) and the FP32 multi-RHS Wilson stencil forms with
+ * 256, 128, 512 or 64 threads per workgroup (form 0 .. 3).  All forms of a kernel compute
+ * the same bits.  Unless off, a lockstep workspace (dmg_solve_batched, dmg_batch_create)
+ * and dmg_hierarchy_apply_batched time every form of a shape (sites, lanes, precision)
+ * the first time they meet it and keep the fastest for the life of the process.
+ *   dmg_autotune: mode 0 off (form 0 everywhere), 1 on (default), 2 on and forget the
+ *     choices made so far.  DMG_E_INVALID for another mode.
+ *   dmg_autotune_force: kernel DMG_TUNE_BLOCK or DMG_TUNE_WILSON; form >= 0 is used for
+ *     every shape (out-of-range forms fall back to form 0), -1 restores the tuned choice.
+ *   dmg_autotune_report: one line per tuned shape (kernel, precision, sites, lanes, chosen
+ *     form, microseconds per launch of each form) into buf (NUL-terminated, truncated to
+ *     len); returns the length the full report needs, NUL included. */
+enum { DMG_TUNE_BLOCK = 0, DMG_TUNE_WILSON = 1 };
+int dmg_autotune(int mode);
+int dmg_autotune_force(int kernel, int form);
+size_t dmg_autotune_report(char* buf, size_t len);
+
 /* Fill p with the paper's defaults.  GMRES-DR (first coarse call, and the fine-grid
  * comparison solver) also ends when, with the relative residual already at or below 1e-10,
  * a cycle lowers it by less than 1 % (a tolerance such as 1e-15 that the arithmetic cannot

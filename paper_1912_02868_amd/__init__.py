@@ -11,4 +11,5 @@ from .dmg import (  # noqa: F401
     OP_APPLY, OP_APPLY_DAG, OP_RESTRICT, OP_PROLONG, DMG_OK, DMG_W_NOT_CONVERGED, DMG_E_INVALID,
     DMG_E_NONFINITE, DMG_E_BUDGET, DMG_E_BREAKDOWN, EXPORTED, LIB_PATH, KT_COARSE_PROJ, KT_BLOCK_APPLY_INT, KT_BLOCK_BATCHED, KT_WILSON_BATCHED,
     SLOT_FREE, SLOT_RUNNING, SLOT_DONE, POOL_MAX_SLOTS, BATCH_MAX_LANES,
+    autotune, autotune_force, autotune_report, TUNE_BLOCK, TUNE_WILSON,
 )

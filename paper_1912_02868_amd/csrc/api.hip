@@ -114,6 +114,28 @@ using namespace dmg;
 
 extern "C" {
 
+int dmg_autotune(int mode) {
+  if (mode < 0 || mode > 2) return DMG_E_INVALID;
+  b_tune_mode(mode);
+  return DMG_OK;
+}
+
+int dmg_autotune_force(int kernel, int form) {
+  if (kernel < 0 || kernel >= TK_COUNT || form < -1 || form > 3) return DMG_E_INVALID;
+  b_tune_force(kernel, form);
+  return DMG_OK;
+}
+
+size_t dmg_autotune_report(char* buf, size_t len) {
+  const std::string r = b_tune_report();
+  if (buf && len > 0) {
+    const size_t n = r.size() < len - 1 ? r.size() : len - 1;
+    std::memcpy(buf, r.data(), n);
+    buf[n] = '\0';
+  }
+  return r.size() + 1;
+}
+
 void dmg_solve_params_default(dmg_solve_params* p) {
   if (!p) return;
   p->tol = 1e-8;
@@ -555,13 +577,13 @@ dmg_status dmg_hierarchy_apply_batched(dmg_hierarchy* h, int level, int op, dmg_
       launch_b_gather<T>(s, (const T*)din, gi.as<T>(), nin, nrhs, nb);
       if (op == DMG_OP_APPLY) {
         const int kt = A.kind == 0 ? DMG_KT_WILSON_BATCHED : DMG_KT_BLOCK_BATCHED;
+        const T* U = (const T*)(sizeof(R) == 8 ? (const void*)A.U64 : (const void*)A.U32);
+        const T* Ab = (const T*)(sizeof(R) == 8 ? (const void*)A.A64 : (const void*)A.A32);
+        if (A.kind == 0) b_tune_wilson<R>(s, U, gi.as<T>(), go.as<T>(), A.m0, A.Lx, A.Lt, nb);
+        else b_tune_block<R>(s, Ab, gi.as<T>(), go.as<T>(), A.Lx, A.Lt, nb);
         hipEvent_t ta = timer_mark(c, kt, s);
-        if (A.kind == 0)
-          launch_b_wilson<R>(s, (const T*)(sizeof(R) == 8 ? (const void*)A.U64 : (const void*)A.U32), gi.as<T>(),
-                             go.as<T>(), A.m0, A.Lx, A.Lt, nb, nullptr);
-        else
-          launch_b_block<R>(s, (const T*)(sizeof(R) == 8 ? (const void*)A.A64 : (const void*)A.A32), gi.as<T>(),
-                            go.as<T>(), A.Lx, A.Lt, nb, nullptr);
+        if (A.kind == 0) launch_b_wilson<R>(s, U, gi.as<T>(), go.as<T>(), A.m0, A.Lx, A.Lt, nb, nullptr);
+        else launch_b_block<R>(s, Ab, gi.as<T>(), go.as<T>(), A.Lx, A.Lt, nb, nullptr);
         if (ta) timer_span(c, kt, ta, timer_mark(c, kt, s), (long long)A.Lx * A.Lt * nb);
       } else if (op == DMG_OP_RESTRICT) {
         launch_b_restrict<R>(s, tr.P((const T*)nullptr), gi.as<T>(), go.as<T>(), tr.Lx, tr.Lt, tr.dof, nb);

@@ -5,6 +5,8 @@
 // small-dense state (BS) and its own convergence flags.
 #pragma once
 
+#include <string>
+
 #include "common.h"
 
 namespace dmg {
@@ -44,6 +46,18 @@ struct BSTail {
 };
 
 int bred_blocks(int64_t n_entries);
+
+// Autotuning (process-wide): launch forms that give the same bits, timed once per shape.
+enum { TK_BLOCK = 0, TK_WILSON = 1, TK_COUNT = 2 };
+int tuned_form(int kernel, int prec_bytes, int sites, int nb);  // 0 (default form) until tuned
+// time the forms of the batched block / Wilson stencil on these buffers (in is read, out written)
+template <typename R>
+void b_tune_block(hipStream_t s, const cx<R>* A, const cx<R>* in, cx<R>* out, int Lx, int Lt, int nb);
+template <typename R>
+void b_tune_wilson(hipStream_t s, const cx<R>* U, const cx<R>* in, cx<R>* out, double m0, int Nx, int Nt, int nb);
+void b_tune_mode(int mode);              // 0 off (default forms), 1 on, 2 on and forget earlier choices
+void b_tune_force(int kernel, int form);  // form >= 0 overrides the choice; -1 restores it
+std::string b_tune_report();
 // FP32 batched block stencil on the matrix cores (nb >= 16); off: the vector-FMA kernel
 bool b_block_mfma_enabled();
 void b_block_mfma_enable(bool on);

@@ -5,6 +5,11 @@
 // right-hand side.  Right-hand sides never mix: a thread owns one right-hand side
 // r = threadIdx.x mod nb throughout a kernel.
 #include <algorithm>
+#include <array>
+#include <cstdio>
+#include <map>
+#include <mutex>
+#include <string>
 
 #include "mrhs.h"
 
@@ -770,13 +775,14 @@ __global__ void __launch_bounds__(BT) kb_wilson(const cx<R>* __restrict__ U, con
 // kernel).  The per-lane arithmetic is the same sequence of operations as kb_wilson's.
 __device__ inline float2 half2of(float4 v, int h) { return h ? make_float2(v.z, v.w) : make_float2(v.x, v.y); }
 
-__global__ void __launch_bounds__(BT) kb_wilson_pair(const float2* __restrict__ U, const float4* __restrict__ in,
-                                                     float4* __restrict__ out, float diag, int Nx, int Nt, int nb,
-                                                     const float4* __restrict__ sub, const BS* skip) {
+template <int TBW>
+__global__ void __launch_bounds__(TBW) kb_wilson_pair_t(const float2* __restrict__ U, const float4* __restrict__ in,
+                                                        float4* __restrict__ out, float diag, int Nx, int Nt, int nb,
+                                                        const float4* __restrict__ sub, const BS* skip) {
   if (skip && lanes_all_done(skip, nb)) return;
   const int hb = nb >> 1;  // lane pairs = float4 per (site, spin); a power of two
   const int lg = __ffs(hb) - 1;
-  const int64_t idx = (int64_t)blockIdx.x * BT + threadIdx.x;
+  const int64_t idx = (int64_t)blockIdx.x * TBW + threadIdx.x;
   const int V = Nx * Nt;
   if (idx >= (int64_t)V * hb) return;
   const int s = (int)(idx >> lg), rp = (int)(idx & (hb - 1));
@@ -827,15 +833,26 @@ __global__ void __launch_bounds__(BT) kb_wilson_pair(const float2* __restrict__ 
   __builtin_nontemporal_store(f4v{r1[0], r1[1], r1[2], r1[3]}, reinterpret_cast<f4v*>(out + i1));
 }
 
+static void launch_wilson_form(hipStream_t s, int form, const float2* U, const float4* in, float4* out, float diag,
+                               int Nx, int Nt, int nb, const float4* sub, const BS* skip) {
+  const int64_t N2 = (int64_t)Nx * Nt * (nb / 2);
+  const int tb = form == 1 ? 128 : form == 2 ? 512 : form == 3 ? 64 : 256;
+  const dim3 g((unsigned)((N2 + tb - 1) / tb));
+  if (tb == 128) hipLaunchKernelGGL(kb_wilson_pair_t<128>, g, dim3(128), 0, s, U, in, out, diag, Nx, Nt, nb, sub, skip);
+  else if (tb == 512) hipLaunchKernelGGL(kb_wilson_pair_t<512>, g, dim3(512), 0, s, U, in, out, diag, Nx, Nt, nb, sub, skip);
+  else if (tb == 64) hipLaunchKernelGGL(kb_wilson_pair_t<64>, g, dim3(64), 0, s, U, in, out, diag, Nx, Nt, nb, sub, skip);
+  else hipLaunchKernelGGL(kb_wilson_pair_t<256>, g, dim3(256), 0, s, U, in, out, diag, Nx, Nt, nb, sub, skip);
+  DMG_LAUNCH_CHECK();
+}
+
+
 template <typename R>
 void launch_b_wilson(hipStream_t s, const cx<R>* U, const cx<R>* in, cx<R>* out, double m0, int Nx, int Nt, int nb,
                      const cx<R>* sub, const BS* skip) {
   if constexpr (sizeof(R) == sizeof(float)) {
     if (nb >= 2) {
-      const int64_t N2 = (int64_t)Nx * Nt * (nb / 2);
-      hipLaunchKernelGGL(kb_wilson_pair, dim3((unsigned)((N2 + BT - 1) / BT)), dim3(BT), 0, s, (const float2*)U,
-                         (const float4*)in, (float4*)out, (float)(m0 + 2.0), Nx, Nt, nb, (const float4*)sub, skip);
-      DMG_LAUNCH_CHECK();
+      launch_wilson_form(s, tuned_form(TK_WILSON, sizeof(R), Nx * Nt, nb), (const float2*)U, (const float4*)in,
+                         (float4*)out, (float)(m0 + 2.0), Nx, Nt, nb, (const float4*)sub, skip);
       return;
     }
   }
@@ -913,8 +930,7 @@ __global__ void __launch_bounds__(BT) kb_block(const cx<R>* __restrict__ A, cons
 // directions in the MFMA registers (direction, then k-step, for every tile).
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-// One workgroup per site with one wavefront per 16-lane column tile (NTW = nb / 16
-// wavefronts).  The five hop directions are streamed through two LDS stages (block d as re / im
+// nb / (16 NTW) workgroups per site, each with NTW wavefronts, one per 16-lane column tile.  The five hop directions are streamed through two LDS stages (block d as re / im
 // planes, the neighbour field of direction d as re / im planes): while the matrix cores work on
 // direction d, the loads of direction d + 1 are in flight.  Each wavefront keeps the three row
 // tiles of its column tile in three independent accumulators, so every B fragment read from LDS
@@ -937,18 +953,19 @@ template <> struct MfmaT<double> {
 
 template <typename R, int NTW>
 __global__ void __launch_bounds__(64 * NTW) kb_block_mfma_p(const cx<R>* __restrict__ A, const cx<R>* __restrict__ in,
-                                                            cx<R>* __restrict__ out, int Lx, int Lt,
+                                                            cx<R>* __restrict__ out, int Lx, int Lt, int nb,
                                                             const cx<R>* __restrict__ sub, const BS* skip) {
   using T = cx<R>;
   using M = MfmaT<R>;
   constexpr int TB = 64 * NTW;
-  constexpr int NBW = 16 * NTW;                    // lanes (right-hand sides)
+  constexpr int NBW = 16 * NTW;                    // lanes (right-hand sides) of this workgroup
   constexpr int RA = (NC * NC + TB - 1) / TB;      // block entries staged per thread
   constexpr int RX = NC * NBW / TB;                // field entries staged per thread (= 6)
-  if (skip && lanes_all_done(skip, NBW)) return;
+  if (skip && lanes_all_done(skip, nb)) return;
   __shared__ R sa[2][2][NC * NC];                  // [stage][re, im][c * NC + i]
   __shared__ R sx[2][2][NC * NBW];                 // [stage][re, im][c * nb + r]
-  const int site = blockIdx.x;
+  const int NG = nb / NBW;                         // workgroups per site
+  const int site = blockIdx.x / NG, lb = (blockIdx.x % NG) * NBW;
   const int X = site % Lx, Tt = site / Lx;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   int nbS[5];
@@ -957,7 +974,7 @@ __global__ void __launch_bounds__(64 * NTW) kb_block_mfma_p(const cx<R>* __restr
   nbS[2] = ((X == 0) ? Lx - 1 : X - 1) + Lx * Tt;
   nbS[3] = X + Lx * ((Tt + 1 == Lt) ? 0 : Tt + 1);
   nbS[4] = X + Lx * ((Tt == 0) ? Lt - 1 : Tt - 1);
-  const int nout = NC * NBW;
+  const int nout = NC * nb;
   T ra[RA], rx[RX];
   auto fetch = [&](int d) {
     const T* ad = A + ((int64_t)site * 5 + d) * NC * NC;
@@ -968,7 +985,10 @@ __global__ void __launch_bounds__(64 * NTW) kb_block_mfma_p(const cx<R>* __restr
     }
     const T* xd = in + (int64_t)nbS[d] * nout;
 #pragma unroll
-    for (int q = 0; q < RX; ++q) rx[q] = xd[tid + q * TB];
+    for (int q = 0; q < RX; ++q) {
+      const int p = tid + q * TB, c = p / NBW, r = p % NBW;
+      rx[q] = xd[c * nb + lb + r];
+    }
   };
   auto stash = [&](int st) {
 #pragma unroll
@@ -1022,24 +1042,144 @@ __global__ void __launch_bounds__(64 * NTW) kb_block_mfma_p(const cx<R>* __restr
 #pragma unroll
     for (int v = 0; v < 4; ++v) res[(16 * m + M::row(lk, v)) * NBW + j] = acc[m][v];
   __syncthreads();
-  for (int o = tid; o < nout; o += TB) {
+  for (int o = tid; o < NC * NBW; o += TB) {
     const int ii = o / NBW, r = o % NBW;
     T y = make_cx<R>(res[ii * NBW + r], res[(NC + ii) * NBW + r]);
-    const int64_t g = (int64_t)site * nout + o;
+    const int64_t g = (int64_t)site * nout + ii * nb + lb + r;
     if (sub) y = make_cx<R>(sub[g].x - y.x, sub[g].y - y.y);
     out[g] = y;
   }
+}
+
+// ---------------------------------------------------------------- autotuning
+// Launch forms that compute the same bits, chosen per shape by timing each once (per process):
+// block stencil on the matrix cores: 16 NTW lanes per workgroup, NTW in {4, 2, 1}; multi-RHS
+// Wilson stencil (FP32): 64, 128, 256 or 512 threads per workgroup.
+namespace {
+struct TuneEntry {
+  int form;
+  float us[4];
+};
+std::mutex g_tune_mu;
+std::map<std::array<long long, 4>, TuneEntry> g_tune;
+int g_tune_mode = 1;
+int g_tune_force[TK_COUNT] = {-1, -1};
+}  // namespace
+
+static int block_forms(int nb) { return nb >= 64 ? 3 : nb >= 32 ? 2 : 1; }  // NTW = 4 >> form (capped by nb)
+static int block_ntw(int nb, int form) {
+  const int top = nb / 16;  // largest NTW for nb lanes
+  int ntw = top >> form;
+  return ntw < 1 ? 1 : ntw;
+}
+
+int tuned_form(int kernel, int prec, int sites, int nb) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (g_tune_force[kernel] >= 0) return g_tune_force[kernel];
+  if (!g_tune_mode) return 0;
+  auto it = g_tune.find({kernel, prec, sites, nb});
+  return it == g_tune.end() ? 0 : it->second.form;
+}
+
+template <typename R>
+static void launch_block_form(hipStream_t s, int form, const cx<R>* A, const cx<R>* in, cx<R>* out, int Lx, int Lt,
+                              int nb, const cx<R>* sub, const BS* skip) {
+  if (form < 0 || form >= block_forms(nb)) form = 0;
+  const int ntw = block_ntw(nb, form);
+  const dim3 g((unsigned)(Lx * Lt * (nb / (16 * ntw))));
+  if (ntw == 4) hipLaunchKernelGGL((kb_block_mfma_p<R, 4>), g, dim3(256), 0, s, A, in, out, Lx, Lt, nb, sub, skip);
+  else if (ntw == 2) hipLaunchKernelGGL((kb_block_mfma_p<R, 2>), g, dim3(128), 0, s, A, in, out, Lx, Lt, nb, sub, skip);
+  else hipLaunchKernelGGL((kb_block_mfma_p<R, 1>), g, dim3(64), 0, s, A, in, out, Lx, Lt, nb, sub, skip);
+  DMG_LAUNCH_CHECK();
+}
+
+// times nforms launch forms (one warm-up and 5 timed launches each) and records the fastest
+template <typename F>
+static void tune_shape(hipStream_t s, int kernel, int prec, int sites, int nb, int nforms, F&& run) {
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!g_tune_mode || g_tune.count({kernel, prec, sites, nb})) return;
+  }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+    (void)hipGetLastError();
+    return;
+  }
+  hipEvent_t a, b;
+  DMG_HIP(hipEventCreate(&a));
+  DMG_HIP(hipEventCreate(&b));
+  TuneEntry e{0, {0.f, 0.f, 0.f, 0.f}};
+  float best = 0.f;
+  for (int f = 0; f < nforms; ++f) {
+    run(f);
+    DMG_HIP(hipEventRecord(a, s));
+    for (int r = 0; r < 5; ++r) run(f);
+    DMG_HIP(hipEventRecord(b, s));
+    DMG_HIP(hipEventSynchronize(b));
+    float ms = 0.f;
+    DMG_HIP(hipEventElapsedTime(&ms, a, b));
+    e.us[f] = ms * 1e3f / 5.f;
+    if (f == 0 || e.us[f] < best) {
+      best = e.us[f];
+      e.form = f;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[{kernel, prec, sites, nb}] = e;
+}
+
+template <typename R>
+void b_tune_block(hipStream_t s, const cx<R>* A, const cx<R>* in, cx<R>* out, int Lx, int Lt, int nb) {
+  if (nb < 16 || !b_block_mfma_enabled()) return;
+  tune_shape(s, TK_BLOCK, sizeof(R), Lx * Lt, nb, block_forms(nb), [&](int f) {
+    launch_block_form<R>(s, f, A, in, out, Lx, Lt, nb, nullptr, nullptr);
+  });
+}
+
+template <typename R>
+void b_tune_wilson(hipStream_t s, const cx<R>* U, const cx<R>* in, cx<R>* out, double m0, int Nx, int Nt, int nb) {
+  if constexpr (sizeof(R) == sizeof(float)) {
+    if (nb < 2) return;
+    tune_shape(s, TK_WILSON, sizeof(R), Nx * Nt, nb, 4, [&](int f) {
+      launch_wilson_form(s, f, (const float2*)U, (const float4*)in, (float4*)out, (float)(m0 + 2.0), Nx, Nt, nb,
+                         nullptr, nullptr);
+    });
+  }
+}
+
+void b_tune_mode(int mode) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_mode = mode ? 1 : 0;
+  if (mode == 2) g_tune.clear();
+}
+
+void b_tune_force(int kernel, int form) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (kernel >= 0 && kernel < TK_COUNT) g_tune_force[kernel] = form;
+}
+
+std::string b_tune_report() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  std::string o;
+  char line[256];
+  for (const auto& kv : g_tune) {
+    const auto& k = kv.first;
+    const auto& e = kv.second;
+    snprintf(line, sizeof(line), "%s fp%lld sites=%lld nb=%lld form=%d us=[%.1f %.1f %.1f %.1f]\n",
+             k[0] == TK_BLOCK ? "block_mfma" : "wilson_pair", 8 * k[1], k[2], k[3], e.form, e.us[0], e.us[1], e.us[2],
+             e.us[3]);
+    o += line;
+  }
+  return o;
 }
 
 template <typename R>
 void launch_b_block(hipStream_t s, const cx<R>* A, const cx<R>* in, cx<R>* out, int Lx, int Lt, int nb,
                     const cx<R>* sub, const BS* skip) {
   if (nb >= 16 && b_block_mfma_enabled()) {
-    const dim3 g((unsigned)(Lx * Lt));
-    if (nb == 16) hipLaunchKernelGGL((kb_block_mfma_p<R, 1>), g, dim3(64), 0, s, A, in, out, Lx, Lt, sub, skip);
-    else if (nb == 32) hipLaunchKernelGGL((kb_block_mfma_p<R, 2>), g, dim3(128), 0, s, A, in, out, Lx, Lt, sub, skip);
-    else hipLaunchKernelGGL((kb_block_mfma_p<R, 4>), g, dim3(256), 0, s, A, in, out, Lx, Lt, sub, skip);
-    DMG_LAUNCH_CHECK();
+    launch_block_form<R>(s, tuned_form(TK_BLOCK, sizeof(R), Lx * Lt, nb), A, in, out, Lx, Lt, nb, sub, skip);
     return;
   }
   const size_t one = (size_t)NC * nb * sizeof(cx<R>);
@@ -1215,5 +1355,9 @@ void launch_b_set_state(hipStream_t s, BS* bs, const int* host_st, int nb) {
 INST(double)
 INST(float)
 #undef INST
+template void b_tune_block<float>(hipStream_t, const float2*, const float2*, float2*, int, int, int);
+template void b_tune_block<double>(hipStream_t, const double2*, const double2*, double2*, int, int, int);
+template void b_tune_wilson<float>(hipStream_t, const float2*, const float2*, float2*, double, int, int, int);
+template void b_tune_wilson<double>(hipStream_t, const double2*, const double2*, double2*, double, int, int, int);
 
 }  // namespace dmg

@@ -151,6 +151,17 @@ struct BPre {
     field(ec, 2, 1);
     field(pr, 2, 1);
     proj.alloc(c, S(), std::max(d->m - d->kk, 1), N(2), nb, es, false);
+    // launch forms of this lane count's stencils, timed once per shape on the (zeroed) scratch fields
+    const bool f64 = sizeof(R) == sizeof(double);
+    const Op& A0 = h->op[0];
+    const T* U = (const T*)(f64 ? (const void*)A0.U64 : (const void*)A0.U32);
+    b_tune_wilson<R>(S(), U, smw[0].as<T>(), smw[0].as<T>() + N(0) * nb, A0.m0, A0.Lx, A0.Lt, nb);
+    for (int l = 1; l < 3; ++l) {
+      const Op& A = h->op[l];
+      const T* Ab = (const T*)(f64 ? (const void*)A.A64 : (const void*)A.A32);
+      if (l == 1) b_tune_block<R>(S(), Ab, smw[1].as<T>(), smw[1].as<T>() + N(1) * nb, A.Lx, A.Lt, nb);
+      else b_tune_block<R>(S(), Ab, bc.as<T>(), ec.as<T>(), A.Lx, A.Lt, nb);
+    }
   }
 
   void apply(int l, const T* in, T* out, const T* sub, const BS* skip) {

@@ -44,11 +44,13 @@ EXPORTED = [
     "dmg_pool_destroy",
     "dmg_batch_create", "dmg_batch_admit", "dmg_batch_step", "dmg_batch_retire", "dmg_batch_slot_state",
     "dmg_batch_destroy",
+    "dmg_autotune", "dmg_autotune_force", "dmg_autotune_report",
 ]
 SLOT_FREE, SLOT_RUNNING, SLOT_DONE = 0, 1, 2
 POOL_MAX_SLOTS = 8
 BATCH_MAX_LANES = 64
 KT_COARSE_PROJ, KT_BLOCK_APPLY_INT, KT_BLOCK_BATCHED, KT_WILSON_BATCHED = 0, 1, 2, 3
+TUNE_BLOCK, TUNE_WILSON = 0, 1
 
 
 class DmgError(RuntimeError):
@@ -161,6 +163,9 @@ def lib():
         "dmg_batch_destroy": (None, [vp]),
         "dmg_kernel_timer_read": (i, [vp, i, C.POINTER(C.c_double), C.POINTER(C.c_longlong),
                                       C.POINTER(C.c_longlong)]),
+        "dmg_autotune": (i, [i]),
+        "dmg_autotune_force": (i, [i, i]),
+        "dmg_autotune_report": (sz, [C.c_char_p, sz]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -410,6 +415,27 @@ def solve_fine(ctx: Context, hier: Hierarchy, method: int, b, x, nrhs: int = 1, 
     st = lib().dmg_solve_fine(ctx.h, hier.h, method, m, k, tol, max_iters, pb, px, nrhs, kb, stats)
     ctx.check(st, "solve_fine")
     return st, [s.as_dict() for s in stats]
+
+
+def autotune(mode: int = 1) -> None:
+    """Autotuning of the lockstep stencils' launch forms: 0 off, 1 on, 2 on and forget choices."""
+    st = lib().dmg_autotune(mode)
+    if st != 0:
+        raise DmgError(st, "autotune: mode")
+
+
+def autotune_force(kernel: int, form: int) -> None:
+    """Use launch form `form` of TUNE_BLOCK / TUNE_WILSON for every shape (-1: tuned choice)."""
+    st = lib().dmg_autotune_force(kernel, form)
+    if st != 0:
+        raise DmgError(st, "autotune_force")
+
+
+def autotune_report() -> str:
+    n = lib().dmg_autotune_report(None, 0)
+    buf = C.create_string_buffer(n)
+    lib().dmg_autotune_report(buf, n)
+    return buf.value.decode()
 
 
 def solve_batched(ctx: Context, hier: Hierarchy, defl, b, x, nrhs: int, params: SolveParams | None = None):

@@ -171,6 +171,36 @@ def test_batched_operators(dmg, inj64, prec, nrhs, mfma):
                 assert rel < 2e-6 and elem < 1e-5, (lvl, r, rel, elem)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_autotuned_forms_bitwise(dmg, inj64, prec):
+    """Every launch form the autotuner may pick (block stencil: 64, 32 or 16 lanes per
+    workgroup; FP32 Wilson stencil: 256, 128, 512 or 64 threads) gives bitwise the same
+    product, and the tuned choice is reported per shape."""
+    H, g, hg = inj64
+    nrhs = 64
+    try:
+        for lvl, kern, nforms in ((0, dmg.TUNE_WILSON, 4), (1, dmg.TUNE_BLOCK, 3), (2, dmg.TUNE_BLOCK, 3)):
+            n = H.levels[lvl].A.shape[0]
+            x = _fields(n, nrhs, 40 + lvl)
+            if prec == "fp32":
+                x = x.astype(np.complex64)
+            outs = []
+            for form in range(nforms):
+                dmg.autotune_force(kern, form)
+                out = np.empty_like(x)
+                hg.apply_batched(lvl, dmg.OP_APPLY, x, out, nrhs)
+                outs.append(out)
+            for out in outs[1:]:
+                assert np.array_equal(out, outs[0]), (lvl, prec)
+    finally:
+        dmg.autotune_force(dmg.TUNE_BLOCK, -1)
+        dmg.autotune_force(dmg.TUNE_WILSON, -1)
+    rep = dmg.autotune_report()
+    assert "block_mfma" in rep and "nb=64" in rep
+    with pytest.raises(dmg.DmgError):
+        dmg.autotune(3)
+
+
 @pytest.mark.parametrize("prec,nrhs", [("fp64", 7), ("fp32", 16)])
 def test_batched_transfers(dmg, inj64, prec, nrhs):
     H, g, hg = inj64
