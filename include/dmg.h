@@ -58,7 +58,10 @@ enum { DMG_PTR_HOST = 0, DMG_PTR_DEVICE = 1 };
 
 /* Precision of the multigrid preconditioner.  The outer FGMRES (Arnoldi
  * vectors, orthogonalisation, least squares, true residual) is always FP64. */
-typedef enum { DMG_FP64 = 0, DMG_FP32 = 1 } dmg_precision;
+/* DMG_FP32_BF16: FP32 fields and arithmetic with the intermediate-grid operator D-hat stored in
+ * bfloat16 (each part of every block entry rounded to FP32, then to bfloat16, nearest even);
+ * a preconditioner precision (and a precision of the level-1 operator hooks). */
+typedef enum { DMG_FP64 = 0, DMG_FP32 = 1, DMG_FP32_BF16 = 2 } dmg_precision;
 
 typedef struct dmg_context dmg_context;
 typedef struct dmg_gauge dmg_gauge;
@@ -178,7 +181,8 @@ size_t dmg_hierarchy_part_bytes(const dmg_hierarchy* h, int level, int part);
  *   DMG_OP_APPLY_DAG: out = A_level^dagger in (level 0, 1, 2)
  *   DMG_OP_RESTRICT: out = P_level^dagger in (level 0 or 1: level -> level + 1)
  *   DMG_OP_PROLONG:  out = P_level in        (level 0 or 1: level + 1 -> level)
- * Buffers are single fields of precision p. */
+ * Buffers are single fields of precision p (DMG_FP32_BF16: FP32 fields; the level-1 operator
+ * reads its BF16-stored blocks).  DMG_E_INVALID for another precision. */
 enum { DMG_OP_APPLY = 0, DMG_OP_APPLY_DAG = 1, DMG_OP_RESTRICT = 2, DMG_OP_PROLONG = 3 };
 /* The multi-right-hand-side kernels of dmg_solve_batched on nrhs fields at once
  * (parity hook): op DMG_OP_APPLY, DMG_OP_RESTRICT or DMG_OP_PROLONG as above; in and

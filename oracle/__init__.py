@@ -16,6 +16,7 @@ Modules
     wilson      the 2D U(1) Wilson-Dirac operator (Methods section)
     mcrit       critical mass from the low spectrum (Results section, "mass gap")
     krylov      CG, GMRES, FGMRES, GMRES-DR and GMRES-Proj (Methods section)
+    precision   bfloat16 rounding of stored blocks (the BF16 preconditioner variant)
     multigrid   near-null vectors, prolongators, Galerkin operators, the cycle,
                 the partial intermediate solve and the outer solve (Methods)
 

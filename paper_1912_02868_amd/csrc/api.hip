@@ -397,6 +397,7 @@ dmg_status dmg_hierarchy_apply(dmg_hierarchy* h, int level, int op, dmg_precisio
   if (!h) return DMG_E_INVALID;
   return guard(h->ctx, [&]() -> dmg_status {
     DMG_CHECK(in && out && level >= 0 && level <= 2, DMG_E_INVALID, "hierarchy_apply: bad arguments");
+    DMG_CHECK(p == DMG_FP64 || p == DMG_FP32 || p == DMG_FP32_BF16, DMG_E_INVALID, "hierarchy_apply: precision");
     const bool is_transfer = op == DMG_OP_RESTRICT || op == DMG_OP_PROLONG;
     DMG_CHECK(!is_transfer || level <= 1, DMG_E_INVALID, "transfers exist between levels 0-1 and 1-2");
     const size_t es = p == DMG_FP64 ? sizeof(double2) : sizeof(float2);
@@ -429,9 +430,10 @@ dmg_status dmg_hierarchy_apply(dmg_hierarchy* h, int level, int op, dmg_precisio
         default: DMG_CHECK(false, DMG_E_INVALID, "unknown op");
       }
     } else {
+      const Op& Af = (p == DMG_FP32_BF16 && level == 1) ? h->op16 : h->op[level];
       switch (op) {
-        case DMG_OP_APPLY: h->op[level].apply(s, (const float2*)din, (float2*)dout, 0, nullptr); break;
-        case DMG_OP_APPLY_DAG: h->op[level].apply(s, (const float2*)din, (float2*)dout, 1, nullptr); break;
+        case DMG_OP_APPLY: Af.apply(s, (const float2*)din, (float2*)dout, 0, nullptr); break;
+        case DMG_OP_APPLY_DAG: Af.apply(s, (const float2*)din, (float2*)dout, 1, nullptr); break;
         case DMG_OP_RESTRICT:
           launch_restrict<float>(s, tr.P32, (const float2*)din, (float2*)dout, tr.Lx, tr.Lt, tr.dof);
           break;
@@ -547,6 +549,8 @@ dmg_status dmg_hierarchy_apply_batched(dmg_hierarchy* h, int level, int op, dmg_
     DMG_CHECK(op == DMG_OP_APPLY || ((op == DMG_OP_RESTRICT || op == DMG_OP_PROLONG) && level <= 1), DMG_E_INVALID,
               "hierarchy_apply_batched: op");
     DMG_CHECK(ptr_kind == DMG_PTR_HOST || ptr_kind == DMG_PTR_DEVICE, DMG_E_INVALID, "pointer kind");
+    DMG_CHECK(p == DMG_FP64 || p == DMG_FP32 || p == DMG_FP32_BF16, DMG_E_INVALID,
+              "hierarchy_apply_batched: precision");
     int nb = 1;
     while (nb < nrhs) nb *= 2;
     const size_t es = p == DMG_FP64 ? sizeof(double2) : sizeof(float2);
@@ -579,10 +583,16 @@ dmg_status dmg_hierarchy_apply_batched(dmg_hierarchy* h, int level, int op, dmg_
         const int kt = A.kind == 0 ? DMG_KT_WILSON_BATCHED : DMG_KT_BLOCK_BATCHED;
         const T* U = (const T*)(sizeof(R) == 8 ? (const void*)A.U64 : (const void*)A.U32);
         const T* Ab = (const T*)(sizeof(R) == 8 ? (const void*)A.A64 : (const void*)A.A32);
+        const bool b16 = sizeof(R) == sizeof(float) && p == DMG_FP32_BF16 && level == 1;
         if (A.kind == 0) b_tune_wilson<R>(s, U, gi.as<T>(), go.as<T>(), A.m0, A.Lx, A.Lt, nb);
+        else if (b16)
+          b_tune_block_bf16(s, h->A16.as<bf16c>(), (const float2*)gi.as<T>(), (float2*)go.as<T>(), A.Lx, A.Lt, nb);
         else b_tune_block<R>(s, Ab, gi.as<T>(), go.as<T>(), A.Lx, A.Lt, nb);
         hipEvent_t ta = timer_mark(c, kt, s);
         if (A.kind == 0) launch_b_wilson<R>(s, U, gi.as<T>(), go.as<T>(), A.m0, A.Lx, A.Lt, nb, nullptr);
+        else if (b16)
+          launch_b_block_bf16(s, h->A16.as<bf16c>(), (const float2*)gi.as<T>(), (float2*)go.as<T>(), A.Lx, A.Lt, nb,
+                              nullptr);
         else launch_b_block<R>(s, Ab, gi.as<T>(), go.as<T>(), A.Lx, A.Lt, nb, nullptr);
         if (ta) timer_span(c, kt, ta, timer_mark(c, kt, s), (long long)A.Lx * A.Lt * nb);
       } else if (op == DMG_OP_RESTRICT) {
@@ -650,12 +660,12 @@ dmg_status dmg_solve_batched(dmg_context* ctx, dmg_hierarchy* h, dmg_deflation* 
     DMG_CHECK(p.tol > 0.0 && p.int_tol > 0.0 && p.coarse_tol_later > 0.0 && p.max_outer_iters >= 1 &&
                   p.int_max_iters >= 1 && p.coarse_max_iters >= 1 && p.outer_m >= 1 && p.outer_m <= 24 &&
                   p.int_m >= 1 && p.int_m <= 24 && p.smooth_steps == 2 && !p.use_x0 && d->m - d->kk <= 24 &&
-                  p.int_mode == 0,
+                  p.int_mode == 0 && (p.precond == DMG_FP64 || p.precond == DMG_FP32 || p.precond == DMG_FP32_BF16),
               DMG_E_INVALID, "solve_batched parameters (restart lengths <= 24, two smoothing steps, no x0, "
-                             "partial intermediate solve)");
+                             "partial intermediate solve, a known precision)");
     const int64_t n = h->op[0].n;
     const size_t fb = sizeof(double2) * n * nrhs;
-    if (p.precond == DMG_FP32) prepare_deflation_fp32(&h->main, d);
+    if (p.precond != DMG_FP64) prepare_deflation_fp32(&h->main, d);
     DevBuf bb, xb;
     const double2* bd = (const double2*)b;
     double2* xd = (double2*)x;

@@ -50,6 +50,21 @@ __host__ __device__ inline double2 to_d(double2 a) { return a; }
 __host__ __device__ inline double2 to_d(float2 a) { return make_double2(a.x, a.y); }
 template <typename R> __host__ __device__ inline cx<R> from_d(double2 a) { return make_cx<R>((R)a.x, (R)a.y); }
 
+// A complex block entry stored as two bfloat16 (the high 16 bits of the FP32 value, rounded to
+// nearest even); loaded as FP32, exactly.
+struct bf16c {
+  unsigned short re, im;
+};
+__host__ __device__ inline double2 ld_blk(const double2* p) { return *p; }
+__host__ __device__ inline float2 ld_blk(const float2* p) { return *p; }
+__device__ inline float2 ld_blk(const bf16c* p) {
+  const bf16c v = *p;
+  return make_float2(__uint_as_float((unsigned)v.re << 16), __uint_as_float((unsigned)v.im << 16));
+}
+// storage type of the blocks of a stencil computing in precision R
+template <typename R, bool B16> struct BlkT { using T = cx<R>; };
+template <> struct BlkT<float, true> { using T = bf16c; };
+
 // ---------------------------------------------------------------- errors
 struct Error {
   dmg_status code;

@@ -55,6 +55,7 @@ template <typename R>
 void b_tune_block(hipStream_t s, const cx<R>* A, const cx<R>* in, cx<R>* out, int Lx, int Lt, int nb);
 template <typename R>
 void b_tune_wilson(hipStream_t s, const cx<R>* U, const cx<R>* in, cx<R>* out, double m0, int Nx, int Nt, int nb);
+void b_tune_block_bf16(hipStream_t s, const bf16c* A, const float2* in, float2* out, int Lx, int Lt, int nb);
 void b_tune_mode(int mode);              // 0 off (default forms), 1 on, 2 on and forget earlier choices
 void b_tune_force(int kernel, int form);  // form >= 0 overrides the choice; -1 restores it
 std::string b_tune_report();
@@ -107,6 +108,9 @@ void launch_b_wilson(hipStream_t s, const cx<R>* U, const cx<R>* in, cx<R>* out,
 template <typename R>
 void launch_b_block(hipStream_t s, const cx<R>* A, const cx<R>* in, cx<R>* out, int Lx, int Lt, int nb,
                     const cx<R>* sub, const BS* skip = nullptr);
+// block stencil with BF16-stored blocks, FP32 fields and arithmetic
+void launch_b_block_bf16(hipStream_t s, const bf16c* A, const float2* in, float2* out, int Lx, int Lt, int nb,
+                         const float2* sub, const BS* skip = nullptr);
 template <typename R>
 void launch_b_restrict(hipStream_t s, const cx<R>* P, const cx<R>* fine, cx<R>* coarse, int Lx, int Lt, int dof,
                        int nb);

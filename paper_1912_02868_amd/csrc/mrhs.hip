@@ -866,8 +866,8 @@ void launch_b_wilson(hipStream_t s, const cx<R>* U, const cx<R>* in, cx<R>* out,
 // The five neighbours' 24 x nb values are staged in LDS together when they fit in
 // 64 KB (one round of global loads), else one direction at a time; thread o owns
 // outputs (row i, right-hand side r) = (o / nb, o % nb), o = threadIdx.x + BT k.
-template <typename R>
-__global__ void __launch_bounds__(BT) kb_block(const cx<R>* __restrict__ A, const cx<R>* __restrict__ in,
+template <typename R, typename B = cx<R>>
+__global__ void __launch_bounds__(BT) kb_block(const B* __restrict__ A, const cx<R>* __restrict__ in,
                                                cx<R>* __restrict__ out, int Lx, int Lt, int nb,
                                                const cx<R>* __restrict__ sub, const BS* skip) {
   if (skip && lanes_all_done(skip, nb)) return;
@@ -896,7 +896,7 @@ __global__ void __launch_bounds__(BT) kb_block(const cx<R>* __restrict__ A, cons
       for (int p = tid; p < nout; p += BT) xs[dd * nout + p] = in[(int64_t)nbS[d0 + dd] * nout + p];
     __syncthreads();
     for (int dd = 0; dd < nd; ++dd) {
-      const T* a = A + ((int64_t)S * 5 + d0 + dd) * NC * NC;
+      const B* a = A + ((int64_t)S * 5 + d0 + dd) * NC * NC;
       const T* xd = xs + dd * nout;
 #pragma unroll
       for (int k = 0; k < OPT; ++k) {
@@ -905,7 +905,7 @@ __global__ void __launch_bounds__(BT) kb_block(const cx<R>* __restrict__ A, cons
           const int i = o / nb, r = o % nb;
           T sacc = make_cx<R>(R(0), R(0));
 #pragma unroll 8
-          for (int c = 0; c < NC; ++c) cfma(sacc, a[c * NC + i], xd[c * nb + r]);
+          for (int c = 0; c < NC; ++c) cfma(sacc, ld_blk(a + c * NC + i), xd[c * nb + r]);
           acc[k] = cadd(acc[k], to_d(sacc));
         }
       }
@@ -951,8 +951,8 @@ template <> struct MfmaT<double> {
   static __device__ inline int row(int lk, int v) { return 4 * v + lk; }
 };
 
-template <typename R, int NTW>
-__global__ void __launch_bounds__(64 * NTW) kb_block_mfma_p(const cx<R>* __restrict__ A, const cx<R>* __restrict__ in,
+template <typename R, int NTW, typename B = cx<R>>
+__global__ void __launch_bounds__(64 * NTW) kb_block_mfma_p(const B* __restrict__ A, const cx<R>* __restrict__ in,
                                                             cx<R>* __restrict__ out, int Lx, int Lt, int nb,
                                                             const cx<R>* __restrict__ sub, const BS* skip) {
   using T = cx<R>;
@@ -977,11 +977,11 @@ __global__ void __launch_bounds__(64 * NTW) kb_block_mfma_p(const cx<R>* __restr
   const int nout = NC * nb;
   T ra[RA], rx[RX];
   auto fetch = [&](int d) {
-    const T* ad = A + ((int64_t)site * 5 + d) * NC * NC;
+    const B* ad = A + ((int64_t)site * 5 + d) * NC * NC;
 #pragma unroll
     for (int q = 0; q < RA; ++q) {
       const int p = tid + q * TB;
-      if (p < NC * NC) ra[q] = ad[p];
+      if (p < NC * NC) ra[q] = ld_blk(ad + p);
     }
     const T* xd = in + (int64_t)nbS[d] * nout;
 #pragma unroll
@@ -1081,15 +1081,16 @@ int tuned_form(int kernel, int prec, int sites, int nb) {
   return it == g_tune.end() ? 0 : it->second.form;
 }
 
-template <typename R>
-static void launch_block_form(hipStream_t s, int form, const cx<R>* A, const cx<R>* in, cx<R>* out, int Lx, int Lt,
+template <typename R, typename B>
+static void launch_block_form(hipStream_t s, int form, const B* A, const cx<R>* in, cx<R>* out, int Lx, int Lt,
                               int nb, const cx<R>* sub, const BS* skip) {
   if (form < 0 || form >= block_forms(nb)) form = 0;
   const int ntw = block_ntw(nb, form);
   const dim3 g((unsigned)(Lx * Lt * (nb / (16 * ntw))));
-  if (ntw == 4) hipLaunchKernelGGL((kb_block_mfma_p<R, 4>), g, dim3(256), 0, s, A, in, out, Lx, Lt, nb, sub, skip);
-  else if (ntw == 2) hipLaunchKernelGGL((kb_block_mfma_p<R, 2>), g, dim3(128), 0, s, A, in, out, Lx, Lt, nb, sub, skip);
-  else hipLaunchKernelGGL((kb_block_mfma_p<R, 1>), g, dim3(64), 0, s, A, in, out, Lx, Lt, nb, sub, skip);
+  if (ntw == 4) hipLaunchKernelGGL((kb_block_mfma_p<R, 4, B>), g, dim3(256), 0, s, A, in, out, Lx, Lt, nb, sub, skip);
+  else if (ntw == 2)
+    hipLaunchKernelGGL((kb_block_mfma_p<R, 2, B>), g, dim3(128), 0, s, A, in, out, Lx, Lt, nb, sub, skip);
+  else hipLaunchKernelGGL((kb_block_mfma_p<R, 1, B>), g, dim3(64), 0, s, A, in, out, Lx, Lt, nb, sub, skip);
   DMG_LAUNCH_CHECK();
 }
 
@@ -1134,7 +1135,14 @@ template <typename R>
 void b_tune_block(hipStream_t s, const cx<R>* A, const cx<R>* in, cx<R>* out, int Lx, int Lt, int nb) {
   if (nb < 16 || !b_block_mfma_enabled()) return;
   tune_shape(s, TK_BLOCK, sizeof(R), Lx * Lt, nb, block_forms(nb), [&](int f) {
-    launch_block_form<R>(s, f, A, in, out, Lx, Lt, nb, nullptr, nullptr);
+    launch_block_form<R, cx<R>>(s, f, A, in, out, Lx, Lt, nb, nullptr, nullptr);
+  });
+}
+
+void b_tune_block_bf16(hipStream_t s, const bf16c* A, const float2* in, float2* out, int Lx, int Lt, int nb) {
+  if (nb < 16 || !b_block_mfma_enabled()) return;
+  tune_shape(s, TK_BLOCK, 2, Lx * Lt, nb, block_forms(nb), [&](int f) {
+    launch_block_form<float, bf16c>(s, f, A, in, out, Lx, Lt, nb, nullptr, nullptr);
   });
 }
 
@@ -1179,12 +1187,24 @@ template <typename R>
 void launch_b_block(hipStream_t s, const cx<R>* A, const cx<R>* in, cx<R>* out, int Lx, int Lt, int nb,
                     const cx<R>* sub, const BS* skip) {
   if (nb >= 16 && b_block_mfma_enabled()) {
-    launch_block_form<R>(s, tuned_form(TK_BLOCK, sizeof(R), Lx * Lt, nb), A, in, out, Lx, Lt, nb, sub, skip);
+    launch_block_form<R, cx<R>>(s, tuned_form(TK_BLOCK, sizeof(R), Lx * Lt, nb), A, in, out, Lx, Lt, nb, sub, skip);
     return;
   }
   const size_t one = (size_t)NC * nb * sizeof(cx<R>);
   const size_t lds = 5 * one <= 65536 ? 5 * one : one;
   hipLaunchKernelGGL(kb_block<R>, dim3(Lx * Lt), dim3(BT), lds, s, A, in, out, Lx, Lt, nb, sub, skip);
+  DMG_LAUNCH_CHECK();
+}
+
+void launch_b_block_bf16(hipStream_t s, const bf16c* A, const float2* in, float2* out, int Lx, int Lt, int nb,
+                         const float2* sub, const BS* skip) {
+  if (nb >= 16 && b_block_mfma_enabled()) {
+    launch_block_form<float, bf16c>(s, tuned_form(TK_BLOCK, 2, Lx * Lt, nb), A, in, out, Lx, Lt, nb, sub, skip);
+    return;
+  }
+  const size_t one = (size_t)NC * nb * sizeof(float2);
+  const size_t lds = 5 * one <= 65536 ? 5 * one : one;
+  hipLaunchKernelGGL((kb_block<float, bf16c>), dim3(Lx * Lt), dim3(BT), lds, s, A, in, out, Lx, Lt, nb, sub, skip);
   DMG_LAUNCH_CHECK();
 }
 

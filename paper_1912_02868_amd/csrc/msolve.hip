@@ -121,6 +121,8 @@ struct BPre {
     if (cap_s) (void)hipStreamDestroy(cap_s);
   }
   hipStream_t S() const { return cur ? cur : sh->s; }
+  // FP32 with the BF16-stored intermediate operator
+  bool bf16() const { return sizeof(R) == sizeof(float) && p->precond == DMG_FP32_BF16; }
   int64_t N(int l) const { return h->op[l].n; }
   const T* Pm(int l) const { return (const T*)h->tr[l].P((const T*)nullptr); }
 
@@ -159,7 +161,10 @@ struct BPre {
     for (int l = 1; l < 3; ++l) {
       const Op& A = h->op[l];
       const T* Ab = (const T*)(f64 ? (const void*)A.A64 : (const void*)A.A32);
-      if (l == 1) b_tune_block<R>(S(), Ab, smw[1].as<T>(), smw[1].as<T>() + N(1) * nb, A.Lx, A.Lt, nb);
+      if (l == 1 && bf16())
+        b_tune_block_bf16(S(), h->A16.as<bf16c>(), (const float2*)smw[1].as<T>(), (float2*)(smw[1].as<T>() + N(1) * nb),
+                          A.Lx, A.Lt, nb);
+      else if (l == 1) b_tune_block<R>(S(), Ab, smw[1].as<T>(), smw[1].as<T>() + N(1) * nb, A.Lx, A.Lt, nb);
       else b_tune_block<R>(S(), Ab, bc.as<T>(), ec.as<T>(), A.Lx, A.Lt, nb);
     }
   }
@@ -172,6 +177,9 @@ struct BPre {
     if (A.kind == 0) {
       const T* U = (const T*)(sizeof(R) == sizeof(double) ? (const void*)A.U64 : (const void*)A.U32);
       launch_b_wilson<R>(S(), U, in, out, A.m0, A.Lx, A.Lt, nb, sub, skip);
+    } else if (l == 1 && bf16()) {
+      launch_b_block_bf16(S(), h->A16.as<bf16c>(), (const float2*)in, (float2*)out, A.Lx, A.Lt, nb,
+                          (const float2*)sub, skip);
     } else {
       const T* Ab = (const T*)(sizeof(R) == sizeof(double) ? (const void*)A.A64 : (const void*)A.A32);
       launch_b_block<R>(S(), Ab, in, out, A.Lx, A.Lt, nb, sub, skip);
@@ -426,7 +434,7 @@ void BWork::init(dmg_hierarchy* hh, dmg_deflation* dd, const dmg_solve_params* p
   Rr.alloc(c, fb);
   for (DevBuf* b : {&B, &X, &Rr}) DMG_HIP(hipMemsetAsync(b->p, 0, b->bytes, s));
   rn.alloc(c, sizeof(double) * NBMAX);
-  if (p.precond == DMG_FP32) {
+  if (p.precond != DMG_FP64) {
     v32.alloc(c, fb / 2);
     z32.alloc(c, fb / 2);
     pc32.alloc(h, dd, &p, &sh, nb);
@@ -471,7 +479,7 @@ void BWork::start_lanes(const std::vector<int>& lanes) {
 
 void BWork::cycle() {
   hipStream_t s = sh.s;
-  const bool fp32 = precond == DMG_FP32;
+  const bool fp32 = precond != DMG_FP64;
   const Op& A = h->op[0];
   const int64_t n = A.n;
   const int64_t ld = n * nb;
@@ -650,7 +658,7 @@ dmg_status dmg_batch_create(dmg_hierarchy* h, dmg_deflation* d, int capacity, co
                   p.int_mode == 0,
               DMG_E_INVALID, "batch parameters (restart lengths <= 24, two smoothing steps, no x0, partial "
                              "intermediate solve)");
-    if (p.precond == DMG_FP32) prepare_deflation_fp32(&h->main, d);
+    if (p.precond != DMG_FP64) prepare_deflation_fp32(&h->main, d);
     int nb = 1;
     while (nb < capacity) nb *= 2;
     std::unique_ptr<dmg_batch> bt(new dmg_batch());

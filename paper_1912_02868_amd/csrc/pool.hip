@@ -189,7 +189,7 @@ dmg_status dmg_pool_admit(dmg_pool* pl, int slot, dmg_hierarchy* h, dmg_deflatio
     }
     // workspace for h first: a budget failure leaves the slot FREE
     prepare_work(h, &sl.w, d, &pl->p);
-    if (pl->p.precond == DMG_FP32) prepare_deflation_fp32(&sl.w, d);
+    if (pl->p.precond != DMG_FP64) prepare_deflation_fp32(&sl.w, d);
     // workspace initialisation may have been queued on the context's stream
     DMG_HIP(hipStreamSynchronize(pl->ctx->stream));
     if (sl.b.bytes != fb) {

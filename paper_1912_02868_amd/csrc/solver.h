@@ -33,6 +33,7 @@ struct Op {
   double m0 = 0.0;
   const double2* A64 = nullptr;
   const float2* A32 = nullptr;
+  const bf16c* A16 = nullptr;  // set: FP32 applies read these BF16 blocks instead of A32
   // out = A in (sub null) or out = sub - A in
   dmg_context* ctx = nullptr;  // for the kernel timer
   int timer_id = -1;            // DMG_KT_* of this operator's stencil, or -1
@@ -46,6 +47,7 @@ struct Op {
   void apply(hipStream_t s, const float2* in, float2* out, int dag, const int* skip,
              const float2* sub = nullptr) const {
     if (kind == 0) launch_wilson<float>(s, U32, in, out, m0, Lx, Lt, dag, 1, skip, sub);
+    else if (A16) launch_block_apply_bf16(s, A16, in, out, Lx, Lt, dag, skip, sub);
     else launch_block_apply<float>(s, A32, in, out, Lx, Lt, dag, skip, sub);
   }
 };
@@ -139,6 +141,8 @@ struct dmg_hierarchy {
   dmg::Op op[3];
   dmg::Transfer tr[2];
   dmg::DevBuf A64[3], A32[3], P64[2], P32[2], null[2];
+  dmg::DevBuf A16;  // BF16 copy of the level-1 blocks
+  dmg::Op op16;     // level-1 operator reading them (FP32 applies)
   int setup_iters[2][64] = {};
   dmg::Work main;  // workspace of dmg_solve, the setup and the deflation build (context stream)
   dmg::BWork* bwork = nullptr;  // workspace of dmg_solve_batched (kept between calls)

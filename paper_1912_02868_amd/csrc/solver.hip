@@ -341,6 +341,12 @@ void build_hierarchy(dmg_hierarchy* h, const double2* start0, const double2* sta
     C.n = (int64_t)CLx * CLt * NC;
     C.A64 = h->A64[lvl + 1].as<double2>();
     C.A32 = h->A32[lvl + 1].as<float2>();
+    if (lvl == 0) {
+      h->A16.alloc(h->ctx, sizeof(bf16c) * ce);
+      launch_d2bf16(s, ce, h->A64[1].as<double2>(), h->A16.as<bf16c>());
+      h->op16 = C;
+      h->op16.A16 = h->A16.as<bf16c>();
+    }
     DMG_HIP(hipStreamSynchronize(s));
   }
 }
@@ -364,8 +370,10 @@ struct Precond {
   DevBuf cg_y;                     // CGNE iterate of the non-deflated coarse solve
   const dmg_solve_params* p = nullptr;
   dmg_deflation* defl = nullptr;
+  bool bf16 = false;  // FP32 with the BF16-stored intermediate operator
 
   Precond(dmg_hierarchy* hh, Work* ww) : h(hh), w(ww) {}
+  const Op& op(int l) const { return (l == 1 && bf16) ? h->op16 : h->op[l]; }
 
   hipStream_t S() const { return w->stream; }
   const T* Pm(int lvl) const { return (const T*)h->tr[lvl].P((const T*)nullptr); }
@@ -373,6 +381,7 @@ struct Precond {
   void ensure(const dmg_solve_params* prm, dmg_deflation* d) {
     p = prm;
     defl = d;
+    bf16 = sizeof(R) == sizeof(float) && prm->precond == DMG_FP32_BF16;
     dmg_context* c = w->ctx;
     const size_t es = sizeof(T);
     if (!sm[0].V.p || smooth_steps != prm->smooth_steps) {
@@ -421,15 +430,15 @@ struct Precond {
     T* V = ws.V.as<T>();
     const int64_t n = ws.n;
     if (smooth_steps == 2) {
-      h->op[lvl].apply(S(), v, V, 0, nullptr);
-      h->op[lvl].apply(S(), V, V + n, 0, nullptr);
+      op(lvl).apply(S(), v, V, 0, nullptr);
+      op(lvl).apply(S(), V, V + n, 0, nullptr);
       w->cnt.mv[lvl] += 2;
       launch_smooth2<R>(S(), v, V, V + n, n, ks->y, yout, rout, PART(w), CNT(w));
       return;
     }
     launch_cycle_start<R>(S(), v, V, n, ks, -1.0, 1, PART(w), CNT(w));
     for (int j = 0; j < smooth_steps; ++j) {
-      h->op[lvl].apply(S(), V + j * n, V + (j + 1) * n, 0, &ks->done);
+      op(lvl).apply(S(), V + j * n, V + (j + 1) * n, 0, &ks->done);
       launch_arnoldi_orth<R>(S(), V, n, n, j, ks, PART(w), CNT(w));
       w->cnt.mv[lvl]++;
     }
@@ -530,7 +539,7 @@ struct Precond {
     int it = 0;
     cg_normal(h, w, 2, 1, b64, cg_y.as<double2>(), p->coarse_tol_first, p->coarse_max_iters, &it);
     double2* x64 = (sizeof(R) == sizeof(double)) ? (double2*)x : ec64.as<double2>();
-    h->op[2].apply(S(), cg_y.as<double2>(), x64, 1, nullptr);
+    op(2).apply(S(), cg_y.as<double2>(), x64, 1, nullptr);
     w->cnt.mv[2]++;
     if constexpr (sizeof(R) == sizeof(float)) launch_cast_d2f(S(), n, ec64.as<double2>(), (float2*)x);
   }
@@ -546,7 +555,7 @@ struct Precond {
     launch_restrict<R>(S(), Pm(1), r1, bc.as<T>(), h->tr[1].Lx, h->tr[1].Lt, NC);
     coarse_solve(bc.as<T>(), ec.as<T>());
     launch_prolong<R>(S(), Pm(1), ec.as<T>(), y1, h->tr[1].Lx, h->tr[1].Lt, NC, 1);
-    h->op[1].apply(S(), y1, q, 0, nullptr, v);  // q = v - D_hat y1
+    op(1).apply(S(), y1, q, 0, nullptr, v);  // q = v - D_hat y1
     w->cnt.mv[1]++;
     smooth(1, q, s1, nullptr);
     launch_axpbyz<R>(S(), n, 1.0, y1, 1.0, s1, out);
@@ -554,7 +563,7 @@ struct Precond {
 
   // partial intermediate solve E1: FGMRES(int_m) on D_hat with M1 to int_tol ||b||
   void partial_solve(const T* b, T* x) {
-    const Op& A = h->op[1];
+    const Op& A = op(1);
     const int64_t n = A.n;
     KState* ks = e1.state();
     T* V = e1.V.as<T>();
@@ -599,7 +608,7 @@ struct Precond {
     if (p->int_mode == 1) cycle1(bh.as<T>(), e1x.as<T>());
     else partial_solve(bh.as<T>(), e1x.as<T>());
     launch_prolong<R>(S(), Pm(0), e1x.as<T>(), y0, h->tr[0].Lx, h->tr[0].Lt, 2, 1);
-    h->op[0].apply(S(), y0, q, 0, nullptr, v);  // q = v - D y0
+    op(0).apply(S(), y0, q, 0, nullptr, v);  // q = v - D y0
     w->cnt.mv[0]++;
     smooth(0, q, s0, nullptr);
     launch_axpbyz<R>(S(), n, 1.0, y0, 1.0, s0, out);
@@ -628,7 +637,9 @@ void prepare_work(dmg_hierarchy* h, Work* w, dmg_deflation* d, const dmg_solve_p
             DMG_E_INVALID, "restart lengths must lie in [1, 64]");
   DMG_CHECK(!d || d->h == h, DMG_E_INVALID, "deflation space belongs to another hierarchy");
   const int64_t n = h->op[0].n;
-  const bool fp32 = p->precond == DMG_FP32;
+  DMG_CHECK(p->precond == DMG_FP64 || p->precond == DMG_FP32 || p->precond == DMG_FP32_BF16, DMG_E_INVALID,
+            "preconditioner precision");
+  const bool fp32 = p->precond != DMG_FP64;
   if (!w->outer.V.p || w->outer.m != p->outer_m || w->outer.n != n) {
     w->outer.alloc(w->ctx, p->outer_m, n, sizeof(double2), true);
     w->or_.alloc(w->ctx, sizeof(double2) * n);
@@ -724,7 +735,7 @@ bool outer_advance(Work* w, int min_iters) {
   hipStream_t s = w->stream;
   const Op& A = h->op[0];
   const int64_t n = A.n;
-  const bool fp32 = p->precond == DMG_FP32;
+  const bool fp32 = p->precond != DMG_FP64;
   if (fp32) w->pc32->ensure(p, R.d);
   else w->pc64->ensure(p, R.d);
   KState* ks = w->outer.state();

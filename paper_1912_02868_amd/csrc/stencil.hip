@@ -87,8 +87,8 @@ void launch_wilson(hipStream_t st, const cx<R>* U, const cx<R>* in, cx<R>* out, 
 // are summed through LDS.  D^dagger = Gamma_5 D Gamma_5: sign flips on x and y.
 constexpr int BA_SITES = 4;  // sites per workgroup: 4 * 5 * 24 = 480 threads
 
-template <typename R>
-__global__ void __launch_bounds__(512) k_block_apply(const cx<R>* __restrict__ A, const cx<R>* __restrict__ in,
+template <typename R, typename B>
+__global__ void __launch_bounds__(512) k_block_apply(const B* __restrict__ A, const cx<R>* __restrict__ in,
                                                      cx<R>* __restrict__ out, int Lx, int Lt, int dagger,
                                                      const int* skip, const cx<R>* __restrict__ sub) {
   if (skip && *skip) return;
@@ -118,10 +118,10 @@ __global__ void __launch_bounds__(512) k_block_apply(const cx<R>* __restrict__ A
   }
   __syncthreads();
   if (active) {
-    const T* a = A + ((int64_t)S * 5 + d) * NC * NC + i;
+    const auto* a = A + ((int64_t)S * 5 + d) * NC * NC + i;
     T acc = make_cx<R>(R(0), R(0));
 #pragma unroll 8
-    for (int j = 0; j < NC; ++j) cfma(acc, a[j * NC], xs[ls][d][j]);
+    for (int j = 0; j < NC; ++j) cfma(acc, ld_blk(a + j * NC), xs[ls][d][j]);
     part[ls][d][i] = acc;
   }
   __syncthreads();
@@ -141,8 +141,37 @@ template <typename R>
 void launch_block_apply(hipStream_t st, const cx<R>* A, const cx<R>* in, cx<R>* out, int Lx, int Lt, int dagger,
                         const int* skip, const cx<R>* sub) {
   const int V = Lx * Lt;
-  hipLaunchKernelGGL(k_block_apply<R>, dim3((V + BA_SITES - 1) / BA_SITES), dim3(BA_SITES * 5 * NC), 0, st, A, in,
-                     out, Lx, Lt, dagger, skip, sub);
+  hipLaunchKernelGGL((k_block_apply<R, cx<R>>), dim3((V + BA_SITES - 1) / BA_SITES), dim3(BA_SITES * 5 * NC), 0, st,
+                     A, in, out, Lx, Lt, dagger, skip, sub);
+  DMG_LAUNCH_CHECK();
+}
+
+void launch_block_apply_bf16(hipStream_t st, const bf16c* A, const float2* in, float2* out, int Lx, int Lt,
+                             int dagger, const int* skip, const float2* sub) {
+  const int V = Lx * Lt;
+  hipLaunchKernelGGL((k_block_apply<float, bf16c>), dim3((V + BA_SITES - 1) / BA_SITES), dim3(BA_SITES * 5 * NC), 0,
+                     st, A, in, out, Lx, Lt, dagger, skip, sub);
+  DMG_LAUNCH_CHECK();
+}
+
+// BF16 copy of FP64 blocks: each part rounded to FP32, then to bfloat16 (nearest, ties to even)
+__global__ void k_d2bf16(int64_t n, const double2* __restrict__ x, bf16c* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  auto rnd = [](double v) {
+    const unsigned u = __float_as_uint((float)v);
+    return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+  };
+  const double2 v = x[i];
+  bf16c o;
+  o.re = rnd(v.x);
+  o.im = rnd(v.y);
+  y[i] = o;
+}
+
+void launch_d2bf16(hipStream_t st, int64_t n, const double2* x, bf16c* y) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_d2bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, x, y);
   DMG_LAUNCH_CHECK();
 }
 

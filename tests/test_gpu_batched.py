@@ -49,7 +49,7 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-@pytest.mark.parametrize("precond", ["fp64", "fp32"])
+@pytest.mark.parametrize("precond", ["fp64", "fp32", "fp32_bf16"])
 def test_batched_64(dmg, ctx, cfg64, precond):
     th, m0, g, h, d, D, lu = cfg64
     nrhs = 6  # padded to 8 lanes
@@ -169,6 +169,24 @@ def test_batched_operators(dmg, inj64, prec, nrhs, mfma):
                 assert rel < tol and elem < tol, (lvl, r, rel, elem)
             else:
                 assert rel < 2e-6 and elem < 1e-5, (lvl, r, rel, elem)
+
+
+@pytest.mark.parametrize("nrhs", [5, 16, 40])
+def test_batched_bf16_block_operator(dmg, inj64, nrhs):
+    """Multi-RHS level-1 stencil with BF16-stored blocks (vector kernel below 16 right-hand
+    sides, matrix cores from 16) against the oracle's blocks rounded to bfloat16."""
+    from oracle.precision import bf16_round
+    H, g, hg = inj64
+    A16 = H.levels[1].A.tocsr(copy=True)
+    A16.data = bf16_round(A16.data)
+    x = _fields(A16.shape[0], nrhs, 60).astype(np.complex64)
+    out = np.empty_like(x)
+    hg.apply_batched(1, dmg.OP_APPLY, x, out, nrhs, bf16=True)
+    for r in range(nrhs):
+        ref = A16 @ x[r].astype(complex)
+        rel = np.linalg.norm(out[r] - ref) / np.linalg.norm(ref)
+        elem = np.max(np.abs(out[r] - ref)) / np.max(np.abs(ref))
+        assert rel < 2e-6 and elem < 1e-5, (r, rel, elem)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])

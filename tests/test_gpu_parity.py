@@ -185,6 +185,29 @@ def test_fp32_operators(dmg, injected):
         assert _rel(od.cpu().numpy().astype(complex), A @ v) < 1e-5
 
 
+def test_bf16_block_operator(dmg, injected):
+    """Level-1 operator with BF16-stored blocks: FP32 product over the oracle's blocks rounded to
+    bfloat16 (through FP32, nearest even), and visibly different from the FP32-block product."""
+    from oracle.precision import bf16_round
+    N, th, m0, H, g, hg = injected
+    A = H.levels[1].A.tocsr(copy=True)
+    A16 = A.copy()
+    A16.data = bf16_round(A16.data)
+    v = synth.gaussian_complex(A.shape[0], N, 1, 8, 5).astype(np.complex64)
+    out16 = np.empty_like(v)
+    out32 = np.empty_like(v)
+    hg.apply(1, dmg.OP_APPLY, v, out16, bf16=True)
+    hg.apply(1, dmg.OP_APPLY, v, out32)
+    ref16 = A16 @ v.astype(complex)
+    assert _rel(out16.astype(complex), ref16) < 2e-6 and _elem(out16.astype(complex), ref16) < 1e-5
+    assert _rel(out16.astype(complex), out32.astype(complex)) > 1e-4
+    # the other levels and the adjoint hook are untouched by the flag
+    hg.apply(1, dmg.OP_APPLY_DAG, v, out16, bf16=True)
+    g5 = np.tile(np.concatenate([np.ones(12), -np.ones(12)]), A.shape[0] // 24)
+    ref_dag = g5 * (A16 @ (g5 * v.astype(complex)))
+    assert _rel(out16.astype(complex), ref_dag) < 2e-6
+
+
 # ---------------------------------------------------------------- deflation space
 def test_gmres_dr_deflation_space(dmg, injected):
     N, th, m0, H, g, hg = injected
@@ -317,6 +340,27 @@ def test_solve_fp32_preconditioner_64(dmg, ctx, injected):
     st, s, x, res = _solve_and_check(dmg, ctx, hg, D, b, d, precond=dmg.FP32)
     assert st == dmg.DMG_OK and res <= 1e-8
     assert _rel(x, spla.splu(D.tocsc()).solve(b)) < 1e-6
+
+
+def test_solve_bf16_preconditioner_64(dmg, ctx, injected):
+    """FP32 preconditioner with the intermediate operator in BF16 (FP64 outer solve): the true
+    residual still reaches 1e-8 and the solution agrees with sparse LU."""
+    N, th, m0, H, g, hg = injected
+    if N != 64:
+        pytest.skip("workload-sized solve")
+    import scipy.sparse.linalg as spla
+    D = H.levels[0].A
+    d = dmg.Deflation(hg, 30, 10)
+    lu = spla.splu(D.tocsc())
+    for j in range(2):
+        b = synth.rhs(64, 0, j)
+        st, s, x, res = _solve_and_check(dmg, ctx, hg, D, b, d, precond=dmg.FP32_BF16)
+        assert st == dmg.DMG_OK and s["converged"] == 1 and res <= 1e-8
+        assert _rel(x, lu.solve(b)) < 1e-6
+    x = np.zeros_like(b)
+    with pytest.raises(dmg.DmgError) as e:
+        dmg.solve(ctx, hg, d, b, x, params=dmg.solve_params(precond=7))
+    assert e.value.code == dmg.DMG_E_INVALID
 
 
 def test_solve_zero_rhs_and_cap(dmg, ctx, injected):
