@@ -163,6 +163,16 @@ def main():
             "mean_outer_iters": float(np.mean([s["outer_iters"] for s in st32])),
             "max_true_rel_resid": float(max(s["true_rel_resid"] for s in st32)),
         }
+        el16, lat16, st16 = timed(dmg.FP32_BF16)
+        out_mixed["bf16_blocks"] = {
+            "value": n_solves / el16, "unit": "solves/s",
+            "dtype": "f32 preconditioner with bf16-stored intermediate blocks, f64 outer",
+            "p50_ms": percentile(lat16, 50), "p99_ms": percentile(lat16, 99),
+            "all_converged_1e-8": all(s["converged"] and s["true_rel_resid"] <= 1e-8 for s in st16),
+            "speedup_vs_fp64": (n_solves / el16) / (n_solves / el64),
+            "mean_outer_iters": float(np.mean([s["outer_iters"] for s in st16])),
+            "max_true_rel_resid": float(max(s["true_rel_resid"] for s in st16)),
+        }
 
     if a.calibrate_copy:
         # plain streaming kernels of known size: uniform_ writes 256 MiB; mul reads 256 MiB
@@ -177,6 +187,7 @@ def main():
     # ------------------------------------------------------------ roofline of the dominant kernel
     roof = coarse_roofline(N, coarse_ms, coarse_launches, coarse_steps, el64)
     roof_int = measure_stencil_roofline(torch, dmg, ctx, res[step_cfgs[0]][1], N)
+    roof_int16 = measure_bf16_stencil(torch, dmg, res[step_cfgs[0]][1], N)
 
     # ------------------------------------------------------------ batched and served forms
     out_batched = None
@@ -225,6 +236,7 @@ def main():
         "served": out_served,
         "roofline": roof,
         "roofline_intermediate_stencil": roof_int,
+        "roofline_intermediate_stencil_bf16": roof_int16,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
@@ -278,6 +290,31 @@ def measure_stencil_roofline(torch, dmg, ctx, h, N, reps=200):
             "algorithmic_bytes_per_launch": bytes_per_launch}
 
 
+def measure_bf16_stencil(torch, dmg, h, N, reps=200):
+    """The same stencil with BF16-stored blocks and FP32 vectors (the BF16 preconditioner
+    variant): 5 x 576 x 4 B of blocks plus two FP32 24-vectors (384 B) per blocked site,
+    timed with stream events around `reps` launches of the apply hook."""
+    L = N // 4
+    sites = L * L
+    x = torch.randn(sites * 24, dtype=torch.complex64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        h.apply(1, dmg.OP_APPLY, x, y, bf16=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        h.apply(1, dmg.OP_APPLY, x, y, bf16=True)
+    e1.record()
+    torch.cuda.synchronize()
+    avg_ms = e0.elapsed_time(e1) / reps
+    bytes_per_launch = sites * (5 * 24 * 24 * 4 + 2 * 24 * 8)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    return {"kernel": "k_block_apply<float, bf16> (intermediate grid, 64x64 sites x 24 dof, BF16 blocks)",
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "avg_launch_us": avg_ms * 1e3,
+            "algorithmic_bytes_per_launch": bytes_per_launch}
+
+
 def build_resident(dmg, ctx, synth, N, c):
     """Hierarchy and a built deflation space (GMRES-DR on the seeded coarse warm-up
     right-hand side) of one configuration: the state a server keeps on the device."""
@@ -305,7 +342,7 @@ def batched_form(torch, dmg, ctx, N, cfgs, nrhs, plain_rate):
     X = torch.empty_like(B[cfgs[0]])
     out = {"workload": f"{N}^2, {nrhs} right-hand sides per lockstep solve, configurations {list(cfgs)}",
            "rhs_per_call": nrhs}
-    for prec in ("fp32", "fp64"):
+    for prec in ("fp32", "fp64", "fp32_bf16"):
         prm = dmg.solve_params(precond=prec)
         g, h, d = res[cfgs[0]]
         dmg.solve_batched(ctx, h, d, B[cfgs[0]], X, nrhs, params=prm)  # workspace
@@ -334,7 +371,8 @@ def batched_form(torch, dmg, ctx, N, cfgs, nrhs, plain_rate):
                 kt[name] = {"ms": ms, "launches": n, "site_lanes": u, "share_of_call": ms * 1e-3 / el1}
             ctx.timer()
         out[prec] = {"value": len(cfgs) * nrhs / el, "unit": "solves/s",
-                     "dtype": ("f32" if prec == "fp32" else "f64") + " preconditioner, f64 outer",
+                     "dtype": {"fp32": "f32", "fp64": "f64", "fp32_bf16": "f32 (bf16 intermediate blocks)"}[prec]
+                     + " preconditioner, f64 outer",
                      "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
                      "all_converged_1e-8": all(s["converged"] and s["true_rel_resid"] <= 1e-8 for s in stats),
                      "max_true_rel_resid": float(max(s["true_rel_resid"] for s in stats)),
