@@ -514,6 +514,316 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
   }
 }
 
+// ---------------------------------------------------------------- persistent GMRES-DR cycle
+// The Arnoldi part of one GMRES-DR cycle (the first coarse solve) in one launch: starting from
+// the j0 + 1 orthonormal columns in V and the cycle's small-dense state (after a deflated
+// restart: the full (k+1) x k block, its rotations, g), the kernel extends the relation
+// A V_j = V_{j+1} Hbar_j column by column up to m, or until the Givens residual reaches
+// tol_abs or the process breaks down, with the same layout and helpers as k_coarse_proj:
+// workgroups own consecutive coarse sites, keep their slices of V in LDS, exchange v_j for
+// the stencil through one global field, and reduce dot products through per-workgroup
+// partials and a flag-array grid barrier.  Gram-Schmidt is classical and always applied
+// twice (the deflation space must satisfy the Arnoldi relation to working accuracy even for
+// the 1e-15 oversolve), with the norm of the twice-orthogonalised vector from its square
+// minus the second-pass coefficients.  Three barriers per column.  Every workgroup holds the
+// same small-dense state; workgroup 0 writes it back (H, R, g, rotations, steps, flags).
+constexpr int CA_NROT = 256;  // rotations held in LDS (restart block plus this cycle's)
+
+struct CAArgs {
+  const double2* A;
+  int Lx, Lt;
+  double2* V;          // basis, ld n entries, columns 0 .. j0 valid on entry
+  KState* ks;
+  int j0, m;
+  double2* xchg;       // exchange field (n entries)
+  double2* partials;   // 2 x CP_QMAX x G
+  unsigned* flags;     // G barrier flags, CP_FLAGPAD apart, zero at launch
+  int* err;
+  int spw;
+};
+
+struct CALayout {
+  size_t Vb, xs, part, wl, hcol, red, res, rc, rs, rp, g, tot;
+  __host__ __device__ CALayout(int spw, int m) {
+    const size_t ne = (size_t)spw * NC;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = cp_align(o + bytes); return at; };
+    Vb = take((size_t)(m + 1) * ne * sizeof(double2));
+    xs = take((size_t)spw * 5 * NC * sizeof(double2));
+    part = take((size_t)(spw * 5 * NC > CP_QMAX * 32 ? spw * 5 * NC : CP_QMAX * 32) * sizeof(double2));
+    wl = take(ne * sizeof(double2));
+    hcol = take((size_t)(m + 2) * sizeof(double2));
+    red = take((size_t)CP_QMAX * sizeof(double2));
+    res = take((size_t)(CP_QMAX + 2) * sizeof(double2));
+    rc = take((size_t)CA_NROT * sizeof(double));
+    rs = take((size_t)CA_NROT * sizeof(double2));
+    rp = take((size_t)CA_NROT * sizeof(int));
+    g = take((size_t)(m + 2) * sizeof(double2));
+    tot = o;
+  }
+};
+
+__global__ void __launch_bounds__(CP_THREADS) k_coarse_arnoldi(CAArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int LDK = MMAX + 1;
+  unsigned gen = 0;
+  bool dead = false;
+  const int G = gridDim.x, gi = blockIdx.x, tid = threadIdx.x;
+  const int V = a.Lx * a.Lt;
+  const int S0 = gi * a.spw;
+  const int nsl = min(a.spw, V - S0);
+  const int ne = nsl * NC;
+  const int m = a.m, j0 = a.j0;
+  const int64_t n = (int64_t)V * NC;
+  const int64_t e0 = (int64_t)S0 * NC;
+  const CALayout L(a.spw, m);
+  double2* Vb = (double2*)(smem + L.Vb);
+  double2* xs = (double2*)(smem + L.xs);
+  double2* part = (double2*)(smem + L.part);
+  double2* wl = (double2*)(smem + L.wl);
+  double2* hcol = (double2*)(smem + L.hcol);
+  double2* red = (double2*)(smem + L.red);
+  double2(*csum)[CP_CHUNKS] = (double2(*)[CP_CHUNKS])(smem + L.part);
+  double2* res = (double2*)(smem + L.res);
+  double* rc = (double*)(smem + L.rc);
+  double2* rs = (double2*)(smem + L.rs);
+  int* rp = (int*)(smem + L.rp);
+  double2* gl = (double2*)(smem + L.g);
+  __shared__ double sh_est;
+  KState* ks = a.ks;
+  double2* xch = a.xchg;
+  if (ks->done) return;  // the cycle start found nothing to do (uniform: read before any write)
+  const int nrot0 = ks->nrot;
+  const double tol_abs = ks->tol_abs;
+  int rbuf = 0;
+
+  auto wg_sums = [&](int nq, auto&& term) {
+    const int q = tid >> 5, c = tid & 31;
+    if (q < nq) {
+      double2 sm = mk(0.0, 0.0);
+      for (int e = c; e < ne; e += 32) sm = cadd(sm, term(q, e));
+      part[q * 32 + c] = sm;
+    }
+    __syncthreads();
+    if (tid < nq) {
+      double2 sm = part[tid * 32];
+      for (int c2 = 1; c2 < 32; ++c2) sm = cadd(sm, part[tid * 32 + c2]);
+      red[tid] = sm;
+    }
+  };
+  auto grid_reduce = [&](int nq) {
+    __syncthreads();
+    double2* P = a.partials + (size_t)rbuf * CP_QMAX * G;
+    if (tid < nq) cp_store(&P[(size_t)tid * G + gi], red[tid]);
+    dead = dead || cp_barrier(a.flags, G, ++gen, a.err);
+    const int q = tid / CP_CHUNKS, c = tid % CP_CHUNKS;
+    if (q < nq) {
+      const int per = (G + CP_CHUNKS - 1) / CP_CHUNKS;
+      const int lo = c * per, hi = min(G, lo + per);
+      double2 sm = mk(0.0, 0.0);
+      for (int b = lo; b < hi; ++b) sm = cadd(sm, cp_load(&P[(size_t)q * G + b]));
+      csum[q][c] = sm;
+    }
+    __syncthreads();
+    if (tid < nq) {
+      double2 sm = csum[tid][0];
+      for (int c2 = 1; c2 < CP_CHUNKS; ++c2) sm = cadd(sm, csum[tid][c2]);
+      res[tid] = sm;
+    }
+    __syncthreads();
+    rbuf ^= 1;
+  };
+
+  // ---------------------------------------------------------------- resident state
+  for (int q = tid; q < nrot0; q += CP_THREADS) {
+    rc[q] = ks->rot_c[q];
+    rs[q] = ks->rot_s[q];
+    rp[q] = ks->rot_p[q];
+  }
+  for (int i = tid; i <= m; i += CP_THREADS) gl[i] = ks->g[i];
+  for (int t = tid; t < (j0 + 1) * ne; t += CP_THREADS) {
+    const int i = t / ne, e = t % ne;
+    Vb[t] = a.V[(int64_t)i * n + e0 + e];
+  }
+  __syncthreads();
+  for (int t = tid; t < ne; t += CP_THREADS) cp_store(&xch[e0 + t], Vb[j0 * ne + t]);
+  dead = dead || cp_barrier(a.flags, G, ++gen, a.err);
+
+  int nrot = nrot0, steps = j0;
+  bool brk = false;
+  double est = ks->est, wn0 = 0.0;
+  for (int j = j0; j < m && !dead; ++j) {
+    // w = A v_j (neighbour values of v_j from the exchange field)
+    for (int t = tid; t < nsl * 5 * NC; t += CP_THREADS) {
+      const int sl = t / (5 * NC), d = (t / NC) % 5, jj = t % NC;
+      const int S = S0 + sl, X = S % a.Lx, Tt = S / a.Lx;
+      int nb;
+      switch (d) {
+        case 0: nb = S; break;
+        case 1: nb = ((X + 1 == a.Lx) ? 0 : X + 1) + a.Lx * Tt; break;
+        case 2: nb = ((X == 0) ? a.Lx - 1 : X - 1) + a.Lx * Tt; break;
+        case 3: nb = X + a.Lx * ((Tt + 1 == a.Lt) ? 0 : Tt + 1); break;
+        default: nb = X + a.Lx * ((Tt == 0) ? a.Lt - 1 : Tt - 1); break;
+      }
+      xs[t] = cp_load(&xch[(int64_t)nb * NC + jj]);
+    }
+    __syncthreads();
+    for (int t = tid; t < nsl * 5 * NC; t += CP_THREADS) {
+      const int sl = t / (5 * NC), d = (t / NC) % 5, i = t % NC;
+      const double2* blk = a.A + ((int64_t)(S0 + sl) * 5 + d) * NC * NC;
+      const double2* xv = xs + (sl * 5 + d) * NC;
+      double2 av[NC / 2];
+      double2 acc = mk(0.0, 0.0);
+#pragma unroll
+      for (int h2 = 0; h2 < 2; ++h2) {
+#pragma unroll
+        for (int jj = 0; jj < NC / 2; ++jj) av[jj] = blk[(h2 * (NC / 2) + jj) * NC + i];
+#pragma unroll
+        for (int jj = 0; jj < NC / 2; ++jj) cfma(acc, av[jj], xv[h2 * (NC / 2) + jj]);
+      }
+      part[t] = acc;
+    }
+    __syncthreads();
+    for (int t = tid; t < ne; t += CP_THREADS) {
+      const int sl = t / NC, i = t % NC;
+      double2 y = part[(sl * 5 + 0) * NC + i];
+      for (int d = 1; d < 5; ++d) y = cadd(y, part[(sl * 5 + d) * NC + i]);
+      wl[t] = y;
+    }
+    __syncthreads();
+    auto dots = [&](int q, int e) {
+      double2 v = mk(0.0, 0.0);
+      if (q <= j) cfmac(v, Vb[q * ne + e], wl[e]);
+      else v.x = cabs2(wl[e]);
+      return v;
+    };
+    // first pass: h = V^H w, ||w||^2
+    wg_sums(j + 2, dots);
+    grid_reduce(j + 2);
+    wn0 = sqrt(res[j + 1].x);
+    if (tid <= j) hcol[tid] = res[tid];
+    for (int t = tid; t < ne; t += CP_THREADS) {
+      double2 w = wl[t];
+      for (int i = 0; i <= j; ++i) w = csub(w, cmul(res[i], Vb[i * ne + t]));
+      wl[t] = w;
+    }
+    __syncthreads();
+    // second pass: h2 = V^H w, ||w||^2; H(:, j) = h + h2
+    wg_sums(j + 2, dots);
+    grid_reduce(j + 2);
+    double hh2 = 0.0;
+    for (int i = 0; i <= j; ++i) hh2 += cabs2(res[i]);
+    double hn = sqrt(fmax(res[j + 1].x - hh2, 0.0));
+    if (!(hn > 1e-12 * wn0)) {
+      hn = 0.0;
+      brk = true;
+    }
+    if (tid <= j) hcol[tid] = cadd(hcol[tid], res[tid]);
+    __syncthreads();
+    // Givens update on one thread of the last wavefront (overlaps the vector update below)
+    if (tid == CP_THREADS - 64) {
+      double2* col = hcol;  // rotated in place (no other thread reads it until the next column)
+      col[j + 1] = mk(hn, 0.0);
+      if (gi == 0) {
+        for (int i = 0; i <= MMAX; ++i) ks->H[LDK * j + i] = (i <= j) ? col[i] : (i == j + 1 ? col[j + 1] : mk(0.0, 0.0));
+      }
+      for (int q = 0; q < nrot; ++q) {
+        const int p = rp[q];
+        if (p + 1 > j + 1) continue;
+        const double2 x0 = col[p], x1 = col[p + 1];
+        col[p] = cadd(cscale(x0, rc[q]), cmul(rs[q], x1));
+        col[p + 1] = csub(cscale(x1, rc[q]), cmul(cconj(rs[q]), x0));
+      }
+      double c;
+      double2 sg;
+      cp_givens(col[j], col[j + 1], c, sg);
+      col[j] = cadd(cscale(col[j], c), cmul(sg, col[j + 1]));
+      col[j + 1] = mk(0.0, 0.0);
+      rc[nrot] = c;
+      rs[nrot] = sg;
+      rp[nrot] = j;
+      const double2 g0 = gl[j], g1 = gl[j + 1];
+      gl[j] = cadd(cscale(g0, c), cmul(sg, g1));
+      gl[j + 1] = csub(cscale(g1, c), cmul(cconj(sg), g0));
+      sh_est = sqrt(cabs2(gl[j + 1]));
+      if (gi == 0) {
+        for (int i = 0; i <= j + 1; ++i) ks->R[LDK * j + i] = col[i];
+        ks->g[j] = gl[j];
+        ks->g[j + 1] = gl[j + 1];
+        ks->rot_c[nrot] = c;
+        ks->rot_s[nrot] = sg;
+        ks->rot_p[nrot] = j;
+      }
+    }
+    // v_{j+1} = (w - V h2) / hn
+    const double inv = hn > 0.0 ? 1.0 / hn : 0.0;
+    for (int t = tid; t < ne; t += CP_THREADS) {
+      double2 w = wl[t];
+      for (int i = 0; i <= j; ++i) w = csub(w, cmul(res[i], Vb[i * ne + t]));
+      const double2 v = hn > 0.0 ? cscale(w, inv) : w;
+      Vb[(j + 1) * ne + t] = v;
+      a.V[(int64_t)(j + 1) * n + e0 + t] = v;
+      cp_store(&xch[e0 + t], v);
+    }
+    __syncthreads();
+    ++nrot;
+    steps = j + 1;
+    est = brk ? 0.0 : sh_est;
+    if (brk || est <= tol_abs) break;
+    if (j + 1 < m) dead = dead || cp_barrier(a.flags, G, ++gen, a.err);
+  }
+  if (gi == 0 && tid == 0) {
+    ks->nrot = nrot;
+    ks->steps = steps;
+    ks->est = est;
+    ks->wn0 = wn0;
+    if (brk) ks->breakdown = 1;
+    if (brk || est <= tol_abs) ks->done = 1;
+  }
+}
+
+size_t coarse_arnoldi_lds(int spw, int m) { return CALayout(spw, m).tot; }
+
+// Returns 1 if the persistent cycle ran (V columns j0+1 .. steps and ks updated), 0 if it
+// cannot run co-resident or its state does not fit (the caller then takes the kernel-per-step
+// path).  Cooperative launch.
+int launch_coarse_arnoldi(hipStream_t st, const double2* A, int Lx, int Lt, double2* V, KState* ks, int nrot_bound,
+                          int j0, int m, double2* xchg, double2* partials, size_t partials_elems, unsigned* flags,
+                          size_t flag_words, int* err) {
+  if (m + 2 > CP_QMAX || m > MMAX || j0 >= m || nrot_bound + (m - j0) > CA_NROT) return 0;
+  const int Vs = Lx * Lt;
+  int spw = (Vs + 31) / 32;
+  if (spw > 10) spw = 10;
+  const int G = (Vs + spw - 1) / spw;
+  if ((size_t)2 * CP_QMAX * G > partials_elems || (size_t)CP_FLAGPAD * G > flag_words) return 0;
+  const size_t lds = coarse_arnoldi_lds(spw, m);
+  if (lds > 160 * 1024) return 0;
+  const void* fn = (const void*)k_coarse_arnoldi;
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  int per_cu = 0, dev = 0, ncu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, CP_THREADS, lds) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (per_cu < 1 || G > per_cu * ncu) return 0;
+  if (hipMemsetAsync(flags, 0, sizeof(unsigned) * CP_FLAGPAD * G, st) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  CAArgs a{A, Lx, Lt, V, ks, j0, m, xchg, partials, flags, err, spw};
+  void* args[] = {&a};
+  if (hipLaunchCooperativeKernel(fn, dim3(G), dim3(CP_THREADS), args, (unsigned)lds, st) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return 1;
+}
+
 size_t coarse_proj_lds(int spw, int mm, int k, size_t es, int a_in_lds) {
   return CPLayout(spw, mm, k, es, a_in_lds).tot;
 }

@@ -116,6 +116,14 @@ int launch_coarse_proj(hipStream_t st, const cx<R>* A, int Lx, int Lt, const cx<
                        double2* partials, size_t partials_elems, int* out_iters, double* out_relres,
                        unsigned* flags, size_t flag_words, int* err, int groups, int coop);
 size_t coarse_proj_flag_words(int G);
+// Arnoldi part of one GMRES-DR cycle on the coarse grid (FP64) as one persistent launch: extends
+// V (ld = n, columns 0 .. j0 orthonormal) and the cycle's state ks from column j0 up to m, or
+// until ks->tol_abs or a breakdown; nrot_bound >= ks->nrot on entry.  Returns 1 if launched,
+// 0 if the shape does not fit (the caller takes the kernel-per-step path).  flags as for
+// launch_coarse_proj; err set on a barrier timeout.
+int launch_coarse_arnoldi(hipStream_t st, const double2* A, int Lx, int Lt, double2* V, KState* ks, int nrot_bound,
+                          int j0, int m, double2* xchg, double2* partials, size_t partials_elems, unsigned* flags,
+                          size_t flag_words, int* err);
 
 // Projection matrices of a deflation space: M = Hbar_k^+ (k x (k+1)) and Pi = Hbar_k M
 // ((k+1) x (k+1)), column-major.

@@ -103,6 +103,7 @@ struct Work {
   // GMRES-DR (FP64)
   KWS dr;
   DevBuf dr_Vtmp, dr_P, dr_work, dr_coef;
+  DevBuf dr_xchg, dr_flags;  // persistent GMRES-DR cycle: exchange field, barrier flags
   int dr_m = 0, dr_k = 0;
   // state of a resumable outer solve (one right-hand side)
   struct Run {
@@ -156,8 +157,9 @@ namespace dmg {
 void build_hierarchy(dmg_hierarchy* h, const double2* start0, const double2* start1, int inject);
 // GMRES-DR on the operator of level lvl (2: coarse) in FP64 from x = 0; fills the
 // deflation space.  Returns the Arnoldi steps taken.
+// persistent: the Arnoldi part of every cycle as one persistent launch where it fits
 int coarse_gmres_dr(dmg_hierarchy* h, Work* w, dmg_deflation* d, const double2* b, double2* x, double tol,
-                    int max_iters, int lvl = 2);
+                    int max_iters, int lvl = 2, int persistent = 1);
 // fine-grid comparison solvers without multigrid: CG on D D^dagger (x = D^dagger y) for
 // nrhs fields at once, or GMRES-DR(m, k) per right-hand side
 dmg_status fine_solve(dmg_hierarchy* h, int method, int m, int k, double tol, int max_iters, const double2* b,

@@ -92,6 +92,8 @@ static void ensure_dr(dmg_hierarchy* h, Work* w, int m, int k, int lvl = 2) {
   w->dr_P.alloc(w->ctx, sizeof(double2) * (size_t)(m + 1) * (k + 1));
   w->dr_work.alloc(w->ctx, sizeof(double2) * dr_work_elems(m, k));
   w->dr_coef.alloc(w->ctx, sizeof(double2) * (MMAX + 2));
+  w->dr_xchg.alloc(w->ctx, sizeof(double2) * (size_t)n);
+  w->dr_flags.alloc(w->ctx, sizeof(unsigned) * coarse_proj_flag_words(256));
   w->dr_m = m;
   w->dr_k = k;
 }
@@ -104,7 +106,7 @@ static void check_dr_status(Work* w) {
 }
 
 int coarse_gmres_dr(dmg_hierarchy* h, Work* w, dmg_deflation* d, const double2* b, double2* x, double tol,
-                    int max_iters, int lvl) {
+                    int max_iters, int lvl, int persistent) {
   const int m = d->m, k = d->k;
   DMG_CHECK(m <= MMAX && k >= 1 && k < m, DMG_E_INVALID, "GMRES-DR sizes");
   ensure_dr(h, w, m, k, lvl);
@@ -114,20 +116,33 @@ int coarse_gmres_dr(dmg_hierarchy* h, Work* w, dmg_deflation* d, const double2* 
   KState* ks = w->dr.state();
   double2* V = w->dr.V.as<double2>();
   int* status = w->flags.as<int>();
+  int* err_d = w->flags.as<int>() + 12;  // grid-barrier timeout of the persistent cycle
   DMG_HIP(hipMemsetAsync(status, 0, sizeof(int), s));
+  DMG_HIP(hipMemsetAsync(err_d, 0, sizeof(int), s));
   DMG_HIP(hipMemsetAsync(x, 0, sizeof(double2) * n, s));
   launch_cycle_start<double>(s, b, V, n, ks, tol, 1, PART(w), CNT(w));
   int j0 = 0, iters = 0;
   KStatus st{};
   double prev_est = -1.0;
   for (;;) {
-    for (int j = j0; j < m; ++j) {
-      A.apply(s, V + (int64_t)j * n, V + (int64_t)(j + 1) * n, 0, &ks->done);
-      launch_arnoldi_orth<double>(s, V, n, n, j, ks, PART(w), CNT(w));
-    }
+    // the rotations on entry: none in the first cycle, the restart block's k (k + 1) / 2 later
+    const bool pers = persistent && A.kind == 1 &&
+                      launch_coarse_arnoldi(s, A.A64, A.Lx, A.Lt, V, ks, j0 == 0 ? 0 : k * (k + 1) / 2, j0, m,
+                                            w->dr_xchg.as<double2>(), PART(w), w->partials.bytes / sizeof(double2),
+                                            w->dr_flags.as<unsigned>(), w->dr_flags.bytes / sizeof(unsigned), err_d);
+    if (!pers)
+      for (int j = j0; j < m; ++j) {
+        A.apply(s, V + (int64_t)j * n, V + (int64_t)(j + 1) * n, 0, &ks->done);
+        launch_arnoldi_orth<double>(s, V, n, n, j, ks, PART(w), CNT(w));
+      }
     launch_ls_solve(s, ks);
     launch_combine<double, double>(s, x, V, n, n, ks, 0, 1);
     sync_status(w, ks, &st);
+    if (pers) {
+      int err = 0;
+      DMG_HIP(hipMemcpy(&err, err_d, sizeof(int), hipMemcpyDeviceToHost));
+      DMG_CHECK(err == 0, DMG_E_HIP, "persistent GMRES-DR cycle: grid barrier timed out");
+    }
     iters += st.steps - j0;
     w->cnt.mv[2] += st.steps - j0;
     if (st.done || iters >= max_iters) break;
@@ -513,10 +528,12 @@ struct Precond {
     if (!defl->ready) {
       const int64_t n = h->op[2].n;
       if constexpr (sizeof(R) == sizeof(double)) {
-        coarse_gmres_dr(h, w, defl, (const double2*)b, (double2*)x, p->coarse_tol_first, p->coarse_max_iters);
+        coarse_gmres_dr(h, w, defl, (const double2*)b, (double2*)x, p->coarse_tol_first, p->coarse_max_iters, 2,
+                        p->coarse_persistent);
       } else {
         launch_cast_f2d(S(), n, (const float2*)b, bc64.as<double2>());
-        coarse_gmres_dr(h, w, defl, bc64.as<double2>(), ec64.as<double2>(), p->coarse_tol_first, p->coarse_max_iters);
+        coarse_gmres_dr(h, w, defl, bc64.as<double2>(), ec64.as<double2>(), p->coarse_tol_first, p->coarse_max_iters, 2,
+                        p->coarse_persistent);
         launch_cast_d2f(S(), n, ec64.as<double2>(), (float2*)x);
       }
       return;
