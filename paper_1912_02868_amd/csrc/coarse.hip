@@ -34,7 +34,6 @@ constexpr int CP_THREADS = 1024;  // 16 wavefronts: enough loads in flight to st
 constexpr int CP_WAVES = CP_THREADS / 64;
 constexpr int CP_RWAVES = 4;    // wavefronts holding the local entries (<= 240 of them)
 constexpr int CP_QMAX = 32;     // quantities per reduction
-constexpr int CP_CHUNKS = 8;    // partial-sum chunks per quantity (fixed summation order)
 
 struct CPArgs {
   const void* A;          // coarse blocks [S][d][col][row]
@@ -175,6 +174,35 @@ __device__ inline double2 cp_wave_sum(double2 v) {
   return v;
 }
 
+// Sum over the 32 lanes of a half-wavefront by a fixed xor tree (every lane gets the same bits).
+__device__ inline double2 cp_half_sum(double2 v) {
+#pragma unroll
+  for (int off = 16; off > 0; off >>= 1) {
+    v.x += __shfl_xor(v.x, off, 64);
+    v.y += __shfl_xor(v.y, off, 64);
+  }
+  return v;
+}
+
+constexpr int CP_GMAX = 256;  // workgroups of one persistent launch (one per compute unit)
+
+// Sum of the G published per-workgroup partials of one quantity by the 32 lanes of a
+// half-wavefront: lane c loads partials c, c + 32, ... (all loads issued before the first
+// add, so the device-scope latency is paid once), adds them in that order, then the
+// half-wavefront tree.  Every workgroup adds the same values in the same order.
+__device__ inline double2 cp_gather_sum(const double2* P, int G, int c) {
+  double2 v[CP_GMAX / 32];
+#pragma unroll
+  for (int u = 0; u < CP_GMAX / 32; ++u) {
+    const int b = c + 32 * u;
+    v[u] = b < G ? cp_load(&P[b]) : mk(0.0, 0.0);
+  }
+  double2 sm = v[0];
+#pragma unroll
+  for (int u = 1; u < CP_GMAX / 32; ++u) sm = cadd(sm, v[u]);
+  return cp_half_sum(sm);
+}
+
 __device__ inline void cp_givens(double2 a, double2 b, double& c, double2& s) {
   const double na = sqrt(cabs2(a)), nb = sqrt(cabs2(b));
   if (nb == 0.0) { c = 1.0; s = mk(0.0, 0.0); return; }
@@ -219,7 +247,6 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
   double2* Mk = (double2*)(smem + L.Hk);
   double2* Pk = (double2*)(smem + L.Rk);
   double2(*red)[CP_RWAVES] = (double2(*)[CP_RWAVES])(smem + L.red);
-  double2(*csum)[CP_CHUNKS] = (double2(*)[CP_CHUNKS])(smem + L.cs);
   double2* res = (double2*)(smem + L.res);
   __shared__ double sh_scal[8];
   __shared__ int sh_flag[4];
@@ -235,21 +262,17 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
 
   // ---------------------------------------------------------------- reduction helpers
   // wg_sums: per-workgroup sums of nq quantities, term(q, e) over the local entries e;
-  // 32 threads per quantity, then one thread adds the 32 partials (fixed order) into
-  // red[q][0].  grid_reduce: publish red[q][0], barrier, every workgroup adds all
-  // workgroups' sums in the same order into res[q].
+  // the 32 lanes of half-wavefront q add every 32nd entry, then the half-wavefront tree
+  // (lane 0 writes red[q][0]).  grid_reduce: publish red[q][0], barrier, every workgroup
+  // adds all workgroups' sums in the same order into res[q].  Quantity q of either step
+  // belongs to threads 32 q .. 32 q + 31 (CP_QMAX * 32 = CP_THREADS).
   auto wg_sums = [&](int nq, auto&& term) {
     const int q = tid >> 5, c = tid & 31;
     if (q < nq) {
       double2 sm = mk(0.0, 0.0);
       for (int e = c; e < ne; e += 32) sm = cadd(sm, term(q, e));
-      part[q * 32 + c] = sm;
-    }
-    __syncthreads();
-    if (tid < nq) {
-      double2 sm = part[tid * 32];
-      for (int c2 = 1; c2 < 32; ++c2) sm = cadd(sm, part[tid * 32 + c2]);
-      red[tid][0] = sm;
+      sm = cp_half_sum(sm);
+      if (c == 0) red[q][0] = sm;
     }
   };
   auto grid_reduce = [&](int nq) {
@@ -257,19 +280,10 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
     double2* P = a.partials + (size_t)rbuf * CP_QMAX * G;
     if (tid < nq) cp_store(&P[(size_t)tid * G + gi], red[tid][0]);
     dead = dead || cp_barrier(a.flags, G, ++gen, a.err);
-    const int q = tid / CP_CHUNKS, c = tid % CP_CHUNKS;
+    const int q = tid >> 5, c = tid & 31;
     if (q < nq) {
-      const int per = (G + CP_CHUNKS - 1) / CP_CHUNKS;
-      const int lo = c * per, hi = min(G, lo + per);
-      double2 sm = mk(0.0, 0.0);
-      for (int b = lo; b < hi; ++b) sm = cadd(sm, cp_load(&P[(size_t)q * G + b]));
-      csum[q][c] = sm;
-    }
-    __syncthreads();
-    if (tid < nq) {
-      double2 sm = csum[tid][0];
-      for (int c2 = 1; c2 < CP_CHUNKS; ++c2) sm = cadd(sm, csum[tid][c2]);
-      res[tid] = sm;
+      const double2 sm = cp_gather_sum(P + (size_t)q * G, G, c);
+      if (c == 0) res[q] = sm;
     }
     __syncthreads();
     rbuf ^= 1;
@@ -583,7 +597,6 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_arnoldi(CAArgs a) {
   double2* wl = (double2*)(smem + L.wl);
   double2* hcol = (double2*)(smem + L.hcol);
   double2* red = (double2*)(smem + L.red);
-  double2(*csum)[CP_CHUNKS] = (double2(*)[CP_CHUNKS])(smem + L.part);
   double2* res = (double2*)(smem + L.res);
   double* rc = (double*)(smem + L.rc);
   double2* rs = (double2*)(smem + L.rs);
@@ -597,18 +610,14 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_arnoldi(CAArgs a) {
   const double tol_abs = ks->tol_abs;
   int rbuf = 0;
 
+  // the reductions of k_coarse_proj (quantity q on threads 32 q .. 32 q + 31)
   auto wg_sums = [&](int nq, auto&& term) {
     const int q = tid >> 5, c = tid & 31;
     if (q < nq) {
       double2 sm = mk(0.0, 0.0);
       for (int e = c; e < ne; e += 32) sm = cadd(sm, term(q, e));
-      part[q * 32 + c] = sm;
-    }
-    __syncthreads();
-    if (tid < nq) {
-      double2 sm = part[tid * 32];
-      for (int c2 = 1; c2 < 32; ++c2) sm = cadd(sm, part[tid * 32 + c2]);
-      red[tid] = sm;
+      sm = cp_half_sum(sm);
+      if (c == 0) red[q] = sm;
     }
   };
   auto grid_reduce = [&](int nq) {
@@ -616,19 +625,10 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_arnoldi(CAArgs a) {
     double2* P = a.partials + (size_t)rbuf * CP_QMAX * G;
     if (tid < nq) cp_store(&P[(size_t)tid * G + gi], red[tid]);
     dead = dead || cp_barrier(a.flags, G, ++gen, a.err);
-    const int q = tid / CP_CHUNKS, c = tid % CP_CHUNKS;
+    const int q = tid >> 5, c = tid & 31;
     if (q < nq) {
-      const int per = (G + CP_CHUNKS - 1) / CP_CHUNKS;
-      const int lo = c * per, hi = min(G, lo + per);
-      double2 sm = mk(0.0, 0.0);
-      for (int b = lo; b < hi; ++b) sm = cadd(sm, cp_load(&P[(size_t)q * G + b]));
-      csum[q][c] = sm;
-    }
-    __syncthreads();
-    if (tid < nq) {
-      double2 sm = csum[tid][0];
-      for (int c2 = 1; c2 < CP_CHUNKS; ++c2) sm = cadd(sm, csum[tid][c2]);
-      res[tid] = sm;
+      const double2 sm = cp_gather_sum(P + (size_t)q * G, G, c);
+      if (c == 0) res[q] = sm;
     }
     __syncthreads();
     rbuf ^= 1;
@@ -795,7 +795,7 @@ int launch_coarse_arnoldi(hipStream_t st, const double2* A, int Lx, int Lt, doub
   int spw = (Vs + 63) / 64;  // about 64 workgroups (measured: 5 % faster per step than 32)
   if (spw > 10) spw = 10;
   const int G = (Vs + spw - 1) / spw;
-  if ((size_t)2 * CP_QMAX * G > partials_elems || (size_t)CP_FLAGPAD * G > flag_words) return 0;
+  if (G > CP_GMAX || (size_t)2 * CP_QMAX * G > partials_elems || (size_t)CP_FLAGPAD * G > flag_words) return 0;
   const size_t lds = coarse_arnoldi_lds(spw, m);
   if (lds > 160 * 1024) return 0;
   const void* fn = (const void*)k_coarse_arnoldi;
@@ -902,8 +902,9 @@ int launch_coarse_proj(hipStream_t st, const cx<R>* A, int Lx, int Lt, const cx<
   int spw = (V + groups - 1) / groups;
   if (spw > 10) spw = 10;  // one thread per local entry
   const int G = (V + spw - 1) / spw;
-  if ((size_t)2 * CP_QMAX * G > partials_elems || (size_t)CP_FLAGPAD * G > flag_words) return 0;
+  if (G > CP_GMAX || (size_t)2 * CP_QMAX * G > partials_elems || (size_t)CP_FLAGPAD * G > flag_words) return 0;
   static_assert(CP_RWAVES * 64 >= 10 * NC, "local entries must sit in the reducing wavefronts");
+  static_assert(CP_QMAX * 32 == CP_THREADS, "one half-wavefront per reduced quantity");
   for (int alds = 1; alds >= 0; --alds) {
     const size_t lds = coarse_proj_lds(spw, mm, k, sizeof(cx<R>), alds);
     if (lds > lds_max) {
