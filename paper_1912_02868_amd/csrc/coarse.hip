@@ -23,8 +23,10 @@
 // difference shows more than 99.99 % cancellation a second pass with an exact
 // norm is taken (one more barrier).  In exact arithmetic this is the Arnoldi
 // process of GMRES; the oracle uses modified Gram-Schmidt twice.
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
+#include <vector>
 
 #include "kernels.h"
 
@@ -55,6 +57,7 @@ struct CPArgs {
   int* err;               // set when a barrier wait exceeds its spin limit
   int spw;                // sites per workgroup
   int a_in_lds;
+  int nl;                 // halo form: bound on own + halo sites of any workgroup (else spw)
 };
 
 constexpr int CP_FLAGPAD = 32;  // one flag per 128-byte line
@@ -133,21 +136,61 @@ __device__ inline bool cp_barrier(unsigned* flags, int G, unsigned gen, int* err
 
 __host__ __device__ inline size_t cp_align(size_t v) { return (v + 15) & ~(size_t)15; }
 
+// Site reached from S in stencil direction d (0: S itself, 1/2: x +/- 1, 3/4: t +/- 1), periodic.
+__host__ __device__ inline int cp_nbr(int S, int d, int Lx, int Lt) {
+  const int X = S % Lx, Tt = S / Lx;
+  switch (d) {
+    case 0: return S;
+    case 1: return ((X + 1 == Lx) ? 0 : X + 1) + Lx * Tt;
+    case 2: return ((X == 0) ? Lx - 1 : X - 1) + Lx * Tt;
+    case 3: return X + Lx * ((Tt + 1 == Lt) ? 0 : Tt + 1);
+    default: return X + Lx * ((Tt == 0) ? Lt - 1 : Tt - 1);
+  }
+}
+
+// Halo of the workgroup owning sites S0 .. S0 + nsl - 1: the other sites its stencil reads,
+// numbered in first-use order (own site sl, direction d ascending).  loc[sl * 5 + d] receives
+// the local index of the site read (own sites 0 .. nsl - 1, halo slots after them); hs the
+// halo sites.  Returns the halo size.  The host uses the same routine to size the LDS.
+__host__ __device__ inline int cp_halo(int S0, int nsl, int Lx, int Lt, int* loc, int* hs) {
+  int nh = 0;
+  for (int sl = 0; sl < nsl; ++sl)
+    for (int d = 0; d < 5; ++d) {
+      const int nb = cp_nbr(S0 + sl, d, Lx, Lt);
+      int li;
+      if (nb >= S0 && nb < S0 + nsl) {
+        li = nb - S0;
+      } else {
+        int h = 0;
+        while (h < nh && hs[h] != nb) ++h;
+        if (h == nh) hs[nh++] = nb;
+        li = nsl + h;
+      }
+      if (loc) loc[sl * 5 + d] = li;
+    }
+  return nh;
+}
+
 // LDS layout (bytes) shared by host sizing and the kernel.
+// halo form (nl > 0): the basis vectors and w hold own + halo entries (nl sites), and there
+// is no exchange staging area.
 struct CPLayout {
-  size_t A, Vb, DVb, xl, rl, wl, xs, part, Hr, rc, rs, g, y, u, Hk, Rk, kc, ks, kp, red, cs, res, tot;
-  __host__ __device__ CPLayout(int spw, int mm, int k, size_t es, int a_in_lds) {
+  size_t A, Vb, DVb, xl, rl, wl, xs, part, Hr, rc, rs, g, y, u, Hk, Rk, kc, ks, kp, red, cs, res, loc, hs, tot;
+  __host__ __device__ CPLayout(int spw, int mm, int k, size_t es, int a_in_lds, int nl = 0) {
     const size_t ne = (size_t)spw * NC;
+    const size_t nle = (size_t)(nl > 0 ? nl : spw) * NC;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = cp_align(o + bytes); return at; };
     A = take(a_in_lds ? (size_t)spw * 5 * NC * NC * es : 0);
-    Vb = take((size_t)(mm + 1) * ne * es);
+    Vb = take((size_t)(mm + 1) * nle * es);
     DVb = take((size_t)(k + 1) * ne * es);
     xl = take(ne * es);
     rl = take(ne * es);
-    wl = take(ne * es);
-    xs = take((size_t)spw * 5 * NC * es);
-    part = take((size_t)(spw * 5 * NC > CP_QMAX * 32 ? spw * 5 * NC : CP_QMAX * 32) * sizeof(double2));
+    wl = take(nle * es);
+    xs = take(nl > 0 ? 0 : (size_t)spw * 5 * NC * es);
+    part = take((size_t)spw * 5 * NC * sizeof(double2));
+    loc = take((size_t)spw * 5 * sizeof(int));
+    hs = take((size_t)spw * 4 * sizeof(int));
     Hr = take((size_t)(mm + 1) * mm * sizeof(double2));
     rc = take((size_t)mm * sizeof(double));
     rs = take((size_t)mm * sizeof(double2));
@@ -216,7 +259,13 @@ __device__ inline double2 cp_div(double2 a, double2 b) {
   return mk((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
 }
 
-template <typename R, bool ALDS>
+// HALO: one grid barrier per Arnoldi step instead of two.  Each workgroup also keeps the
+// basis vectors on its halo sites: w is published with the Gram-Schmidt partials (the
+// exchange field alternates between two halves by step), and after that barrier every
+// workgroup applies the same Gram-Schmidt update to its own and its halo entries, so the
+// next stencil needs no exchange.  The halo values are bitwise the owners' (same inputs,
+// same operations in the same loop).
+template <typename R, bool ALDS, bool HALO>
 __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
   using T = cx<R>;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -229,7 +278,7 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
   const int nsl = min(a.spw, V - S0);
   const int ne = nsl * NC;
   const int mm = a.mm, k = a.k;
-  const CPLayout L(a.spw, mm, k, sizeof(T), ALDS ? 1 : 0);
+  const CPLayout L(a.spw, mm, k, sizeof(T), ALDS ? 1 : 0, HALO ? a.nl : 0);
   T* Ab = (T*)(smem + L.A);
   T* Vb = (T*)(smem + L.Vb);
   T* DVb = (T*)(smem + L.DVb);
@@ -248,6 +297,8 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
   double2* Pk = (double2*)(smem + L.Rk);
   double2(*red)[CP_RWAVES] = (double2(*)[CP_RWAVES])(smem + L.red);
   double2* res = (double2*)(smem + L.res);
+  int* loc = (int*)(smem + L.loc);
+  int* hsite = (int*)(smem + L.hs);
   __shared__ double sh_scal[8];
   __shared__ int sh_flag[4];
 
@@ -259,6 +310,23 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
   const int64_t n = (int64_t)V * NC;
   const int64_t e0 = (int64_t)S0 * NC;
   int rbuf = 0;
+  // halo form: local sites (own, then halo) and the stride of the basis in LDS
+  if (HALO && tid == 0) sh_flag[0] = cp_halo(S0, nsl, a.Lx, a.Lt, loc, hsite);
+  __syncthreads();
+  const int nh = HALO ? sh_flag[0] : 0;
+  const int nle = (nsl + nh) * NC;  // entries of a basis vector in LDS
+  const int vst = HALO ? a.nl * NC : ne;
+  if (HALO && nsl + nh > a.nl) {
+    // cannot happen (the host sized nl with the same routine); stop without touching LDS
+    __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    dead = true;
+  }
+  // halo entries of exchange half `half` into wl[ne ..] (issued right after a barrier)
+  auto load_halo = [&](int half) {
+    const T* src = xch + (size_t)half * n;
+    for (int t = CP_THREADS - 1 - tid; t < nh * NC; t += CP_THREADS)
+      wl[ne + t] = cp_load(&src[(int64_t)hsite[t / NC] * NC + t % NC]);
+  };
 
   // ---------------------------------------------------------------- reduction helpers
   // wg_sums: per-workgroup sums of nq quantities, term(q, e) over the local entries e;
@@ -275,7 +343,7 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
       if (c == 0) red[q][0] = sm;
     }
   };
-  auto grid_reduce = [&](int nq) {
+  auto grid_reduce = [&](int nq, int halo_half = -1) {
     __syncthreads();
     double2* P = a.partials + (size_t)rbuf * CP_QMAX * G;
     if (tid < nq) cp_store(&P[(size_t)tid * G + gi], red[tid][0]);
@@ -285,6 +353,7 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
       const double2 sm = cp_gather_sum(P + (size_t)q * G, G, c);
       if (c == 0) res[q] = sm;
     }
+    if (HALO && halo_half >= 0) load_halo(halo_half);
     __syncthreads();
     rbuf ^= 1;
   };
@@ -345,8 +414,10 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
     }
     // ------------------------------------------------------------ GMRES(mm) cycle from r
     __syncthreads();
+    if (HALO)
+      for (int t = tid; t < ne; t += CP_THREADS) wl[t] = rl[t];
     wg_sums(1, sq(rl));
-    grid_reduce(1);
+    grid_reduce(1, 0);
     double hprev = sqrt(res[0].x);  // beta; xchg holds the unnormalised start vector
     est = hprev;
     if (dead) break;
@@ -363,13 +434,14 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
     // cancellation below which the Pythagorean norm is replaced by a second pass
     const double eta = sizeof(R) == sizeof(float) ? 1e-4 : 1e-8;
     for (int j = 0; j < mm; ++j) {
-      // xchg holds hprev * v_j (written before the last barrier)
+      // xchg holds hprev * v_j (written before the last barrier); halo form: wl holds it
+      // on the own and halo sites
       const double inv = 1.0 / hprev;
-      for (int t = tid; t < ne; t += CP_THREADS) {
-        const T src = (j == 0) ? rl[t] : wl[t];
-        Vb[j * ne + t] = from_d<R>(cscale(to_d(src), inv));
+      for (int t = tid; t < (HALO ? nle : ne); t += CP_THREADS) {
+        const T src = (!HALO && j == 0) ? rl[t] : wl[t];
+        Vb[j * vst + t] = from_d<R>(cscale(to_d(src), inv));
       }
-      for (int t = tid; t < nsl * 5 * NC; t += CP_THREADS) {
+      for (int t = tid; t < (HALO ? 0 : nsl * 5 * NC); t += CP_THREADS) {
         const int sl = t / (5 * NC), d = (t / NC) % 5, jj = t % NC;
         const int S = S0 + sl, X = S % a.Lx, Tt = S / a.Lx;
         int nb;
@@ -386,7 +458,7 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
       for (int t = tid; t < nsl * 5 * NC; t += CP_THREADS) {
         const int sl = t / (5 * NC), d = (t / NC) % 5, i = t % NC;
         const T* blk = ALDS ? (Ab + ((int64_t)sl * 5 + d) * NC * NC) : (Ag + ((int64_t)(S0 + sl) * 5 + d) * NC * NC);
-        const T* xv = xs + (sl * 5 + d) * NC;
+        const T* xv = HALO ? wl + loc[sl * 5 + d] * NC : xs + (sl * 5 + d) * NC;
         T av[NC / 2];
         double2 acc = mk(0.0, 0.0);
 #pragma unroll
@@ -403,18 +475,20 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
         const int sl = t / NC, i = t % NC;
         double2 y = part[(sl * 5 + 0) * NC + i];
         for (int d = 1; d < 5; ++d) y = cadd(y, part[(sl * 5 + d) * NC + i]);
-        wl[t] = from_d<R>(cscale(y, inv));
+        const T wv = from_d<R>(cscale(y, inv));
+        wl[t] = wv;
+        if (HALO) cp_store(&xch[(size_t)((j + 1) & 1) * n + e0 + t], wv);
       }
       __syncthreads();
       // h_i = V_i^H w (i <= j) and ||w||^2 in one reduction
       auto dots = [&](int q, int e) {
         double2 v = mk(0.0, 0.0);
-        if (q <= j) cfmac(v, to_d(Vb[q * ne + e]), to_d(wl[e]));
+        if (q <= j) cfmac(v, to_d(Vb[q * vst + e]), to_d(wl[e]));
         else v.x = cabs2(to_d(wl[e]));
         return v;
       };
       wg_sums(j + 2, dots);
-      grid_reduce(j + 2);
+      grid_reduce(j + 2, (j + 1) & 1);
       const double ww = res[j + 1].x;
       double hh = 0.0;
       for (int i = 0; i <= j; ++i) hh += cabs2(res[i]);
@@ -423,9 +497,9 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
       if (!(hn2 > eta * ww)) {
         // heavy cancellation: apply the first pass, then a second pass with an exact norm
         if (tid <= j) Hr[tid + (mm + 1) * j] = res[tid];
-        for (int t = tid; t < ne; t += CP_THREADS) {
+        for (int t = tid; t < (HALO ? nle : ne); t += CP_THREADS) {
           double2 w = to_d(wl[t]);
-          for (int i = 0; i <= j; ++i) w = csub(w, cmul(res[i], to_d(Vb[i * ne + t])));
+          for (int i = 0; i <= j; ++i) w = csub(w, cmul(res[i], to_d(Vb[i * vst + t])));
           wl[t] = from_d<R>(w);
         }
         __syncthreads();
@@ -435,9 +509,9 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
         for (int i = 0; i <= j; ++i) hh2 += cabs2(res[i]);
         hn2 = res[j + 1].x - hh2;
         if (tid <= j) Hr[tid + (mm + 1) * j] = cadd(Hr[tid + (mm + 1) * j], res[tid]);
-        for (int t = tid; t < ne; t += CP_THREADS) {
+        for (int t = tid; t < (HALO ? nle : ne); t += CP_THREADS) {
           double2 w = to_d(wl[t]);
-          for (int i = 0; i <= j; ++i) w = csub(w, cmul(res[i], to_d(Vb[i * ne + t])));
+          for (int i = 0; i <= j; ++i) w = csub(w, cmul(res[i], to_d(Vb[i * vst + t])));
           wl[t] = from_d<R>(w);
         }
         __syncthreads();
@@ -469,15 +543,15 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
         gv[j + 1] = csub(cscale(g1, c), cmul(cconj(sg), g0));
         sh_scal[0] = sqrt(cabs2(gv[j + 1]));
       }
-      for (int t = tid; t < ne; t += CP_THREADS) {
+      for (int t = tid; t < (HALO ? nle : ne); t += CP_THREADS) {
         double2 w = to_d(wl[t]);
         if (!updated)
-          for (int i = 0; i <= j; ++i) w = csub(w, cmul(res[i], to_d(Vb[i * ne + t])));
+          for (int i = 0; i <= j; ++i) w = csub(w, cmul(res[i], to_d(Vb[i * vst + t])));
         const T ws = from_d<R>(w);
         wl[t] = ws;
-        if (j + 1 < mm) cp_store(&xch[e0 + t], ws);  // hn * v_{j+1} for the next stencil
+        if (!HALO && j + 1 < mm) cp_store(&xch[e0 + t], ws);  // hn * v_{j+1} for the next stencil
       }
-      if (j + 1 < mm) dead = dead || cp_barrier(a.flags, G, ++gen, a.err);
+      if (!HALO && j + 1 < mm) dead = dead || cp_barrier(a.flags, G, ++gen, a.err);
       else __syncthreads();
       est = brk ? 0.0 : sh_scal[0];
       steps = j + 1;
@@ -508,7 +582,7 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
       double2 xv = to_d(xl[t]);
       double2 rv = mk(0.0, 0.0);
       for (int i = 0; i < steps; ++i) {
-        const double2 vi = to_d(Vb[i * ne + t]);
+        const double2 vi = to_d(Vb[i * vst + t]);
         cfma(xv, yv[i], vi);
         cfma(rv, uv[i], vi);
       }
@@ -828,6 +902,15 @@ size_t coarse_proj_lds(int spw, int mm, int k, size_t es, int a_in_lds) {
   return CPLayout(spw, mm, k, es, a_in_lds).tot;
 }
 
+// DMG_COARSE_HALO=0 selects the two-barrier form (the same solve up to rounding order).
+static bool cp_halo_enabled() {
+  static const int on = [] {
+    const char* e = getenv("DMG_COARSE_HALO");
+    return (e && *e == '0') ? 0 : 1;
+  }();
+  return on != 0;
+}
+
 static bool cp_debug() {
   static const int on = [] {
     const char* e = getenv("DMG_DEBUG");
@@ -837,9 +920,15 @@ static bool cp_debug() {
 }
 
 template <typename R>
-static int try_launch(hipStream_t st, CPArgs& a, int G, size_t lds, bool alds, int coop) {
+static const void* proj_fn(bool alds, bool halo) {
+  if (halo) return alds ? (const void*)k_coarse_proj<R, true, true> : (const void*)k_coarse_proj<R, false, true>;
+  return alds ? (const void*)k_coarse_proj<R, true, false> : (const void*)k_coarse_proj<R, false, false>;
+}
+
+template <typename R>
+static int try_launch(hipStream_t st, CPArgs& a, int G, size_t lds, bool alds, bool halo, int coop) {
   void* args[] = {&a};
-  const void* fn = alds ? (const void*)k_coarse_proj<R, true> : (const void*)k_coarse_proj<R, false>;
+  const void* fn = proj_fn<R>(alds, halo);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) {
     if (cp_debug()) fprintf(stderr, "[dmg] coarse kernel: set LDS %zu failed: %s\n", lds, hipGetErrorString(e));
@@ -872,8 +961,13 @@ static int try_launch(hipStream_t st, CPArgs& a, int G, size_t lds, bool alds, i
     // Plain launch: the grid (G <= 256 workgroups, one per CU) always fits the device,
     // so every workgroup is placed once earlier kernels drain; the barrier's spin limit
     // bounds any wait.
-    if (alds) hipLaunchKernelGGL((k_coarse_proj<R, true>), dim3(G), dim3(CP_THREADS), lds, st, a);
-    else hipLaunchKernelGGL((k_coarse_proj<R, false>), dim3(G), dim3(CP_THREADS), lds, st, a);
+    if (halo) {
+      if (alds) hipLaunchKernelGGL((k_coarse_proj<R, true, true>), dim3(G), dim3(CP_THREADS), lds, st, a);
+      else hipLaunchKernelGGL((k_coarse_proj<R, false, true>), dim3(G), dim3(CP_THREADS), lds, st, a);
+    } else {
+      if (alds) hipLaunchKernelGGL((k_coarse_proj<R, true, false>), dim3(G), dim3(CP_THREADS), lds, st, a);
+      else hipLaunchKernelGGL((k_coarse_proj<R, false, false>), dim3(G), dim3(CP_THREADS), lds, st, a);
+    }
     e = hipGetLastError();
   }
   if (e != hipSuccess) {
@@ -905,16 +999,29 @@ int launch_coarse_proj(hipStream_t st, const cx<R>* A, int Lx, int Lt, const cx<
   if (G > CP_GMAX || (size_t)2 * CP_QMAX * G > partials_elems || (size_t)CP_FLAGPAD * G > flag_words) return 0;
   static_assert(CP_RWAVES * 64 >= 10 * NC, "local entries must sit in the reducing wavefronts");
   static_assert(CP_QMAX * 32 == CP_THREADS, "one half-wavefront per reduced quantity");
-  for (int alds = 1; alds >= 0; --alds) {
-    const size_t lds = coarse_proj_lds(spw, mm, k, sizeof(cx<R>), alds);
-    if (lds > lds_max) {
-      if (cp_debug() && alds == 0) fprintf(stderr, "[dmg] coarse kernel: LDS %zu exceeds %zu\n", lds, lds_max);
-      continue;
+  // own + halo sites of the largest halo (same routine as the kernel)
+  int nl = 0;
+  {
+    std::vector<int> hs((size_t)4 * spw);
+    for (int g = 0; g < G; ++g) {
+      const int S0 = g * spw, nsl = std::min(spw, V - S0);
+      nl = std::max(nl, nsl + cp_halo(S0, nsl, Lx, Lt, nullptr, hs.data()));
     }
-    CPArgs a{A, Lx, Lt, DV, DM, DP, k, b, x, tol, mm, max_iters, xchg, partials, out_iters, out_relres,
-             flags, err, spw, alds};
-    if (try_launch<R>(st, a, G, lds, alds == 1, coop)) return 1;
   }
+  // halo form (one barrier per Arnoldi step) first; the blocks in LDS where they fit
+  const int halo_ok = cp_halo_enabled() ? 1 : 0;
+  for (int halo = halo_ok; halo >= 0; --halo)
+    for (int alds = 1; alds >= 0; --alds) {
+      const size_t lds = CPLayout(spw, mm, k, sizeof(cx<R>), alds, halo ? nl : 0).tot;
+      if (lds > lds_max) {
+        if (cp_debug()) fprintf(stderr, "[dmg] coarse kernel (halo %d, blocks in LDS %d): LDS %zu exceeds %zu\n",
+                                halo, alds, lds, lds_max);
+        continue;
+      }
+      CPArgs a{A, Lx, Lt, DV, DM, DP, k, b, x, tol, mm, max_iters, xchg, partials, out_iters, out_relres,
+               flags, err, spw, alds, halo ? nl : spw};
+      if (try_launch<R>(st, a, G, lds, alds == 1, halo == 1, coop)) return 1;
+    }
   return 0;
 }
 

@@ -105,7 +105,7 @@ void launch_proj_solve(hipStream_t s, const double2* Hk, int k, KState* ks);
 // ---------------------------------------------------------------- persistent coarse solve (coarse.hip)
 // One cooperative launch per GMRES-Proj(m, k) coarse solve from x = 0; DM and DP are the
 // projection matrices of launch_defl_prepare.  Returns 0 (nothing
-// launched) when the grid cannot be co-resident; out_iters / out_relres receive the Arnoldi
+// launched) when the grid cannot be co-resident; xchg holds 2 n entries; out_iters / out_relres receive the Arnoldi
 // steps taken and the final recurrence residual relative to ||b||.  flags: barrier words
 // (coarse_proj_flag_words(G) needed, zeroed by the launcher); err: set on a barrier timeout.
 // coop = 1: cooperative launch; 0: plain launch (the grid fits the device by construction).

@@ -429,7 +429,7 @@ struct Precond {
       proj_m = pm;
     }
     if (d && prm->coarse_persistent) {
-      if (!xchg.p) xchg.alloc(c, es * h->op[2].n);
+      if (!xchg.p) xchg.alloc(c, 2 * es * h->op[2].n);  // two halves (halo form)
       if (!bflags.p) bflags.alloc(c, sizeof(unsigned) * coarse_proj_flag_words(256));
     }
     if (!d && !cg_y.p) cg_y.alloc(c, sizeof(double2) * h->op[2].n);
@@ -472,7 +472,7 @@ struct Precond {
     const T* DV = dvec(d);
     const double2* DH = d->H.as<double2>();
     if (p->coarse_persistent) {
-      if (!xchg.p) xchg.alloc(w->ctx, sizeof(T) * n);
+      if (!xchg.p) xchg.alloc(w->ctx, 2 * sizeof(T) * n);
       int* it_d = w->flags.as<int>() + 8;
       double* rr_d = (double*)(w->flags.as<int>() + 16);
       const T* Ab = (const T*)(sizeof(R) == sizeof(double) ? (const void*)A.A64 : (const void*)A.A32);
