@@ -217,17 +217,44 @@ __device__ inline double2 cp_wave_sum(double2 v) {
   return v;
 }
 
-// Sum over the 32 lanes of a half-wavefront by a fixed xor tree (every lane gets the same bits).
-__device__ inline double2 cp_half_sum(double2 v) {
-#pragma unroll
-  for (int off = 16; off > 0; off >>= 1) {
-    v.x += __shfl_xor(v.x, off, 64);
-    v.y += __shfl_xor(v.y, off, 64);
-  }
+// Cross-lane moves without the LDS: a DPP lane permutation (quad_perm / row_ror control) and a
+// read of one lane into a scalar register, on the two 32-bit halves of a double.
+template <int CTRL>
+__device__ inline double cp_dpp(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ inline double cp_lane(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ inline double2 cp_lane(double2 v, int l) { return mk(cp_lane(v.x, l), cp_lane(v.y, l)); }
+
+// Sum over each 16-lane row (neighbour swaps within quads, then rotations by 4 and 8); lanes
+// 0, 16, 32 and 48 hold their rows' sums, always added in the same order.
+__device__ inline double cp_row_sum(double v) {
+  v += cp_dpp<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += cp_dpp<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += cp_dpp<0x124>(v);  // row_ror 4
+  v += cp_dpp<0x128>(v);  // row_ror 8
   return v;
 }
+// Sum over the 32 lanes of each half-wavefront; every lane of a half gets its half's total
+// (rows 0 + 1, rows 2 + 3), the same bits in every workgroup.  Both rows of an active half
+// must be active.
+__device__ inline double2 cp_half_sum(double2 v) {
+  v.x = cp_row_sum(v.x);
+  v.y = cp_row_sum(v.y);
+  const double2 lo = cadd(cp_lane(v, 0), cp_lane(v, 16));
+  const double2 hi = cadd(cp_lane(v, 32), cp_lane(v, 48));
+  return (threadIdx.x & 32) ? hi : lo;
+}
 
-constexpr int CP_GMAX = 256;  // workgroups of one persistent launch (one per compute unit)
+constexpr int CP_GMAX = 128;  // workgroups of one persistent launch (at most one per compute unit)
 
 // Sum of the G published per-workgroup partials of one quantity by the 32 lanes of a
 // half-wavefront: lane c loads partials c, c + 32, ... (all loads issued before the first
@@ -480,79 +507,108 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
         if (HALO) cp_store(&xch[(size_t)((j + 1) & 1) * n + e0 + t], wv);
       }
       __syncthreads();
-      // h_i = V_i^H w (i <= j) and ||w||^2 in one reduction
-      auto dots = [&](int q, int e) {
-        double2 v = mk(0.0, 0.0);
-        if (q <= j) cfmac(v, to_d(Vb[q * vst + e]), to_d(wl[e]));
-        else v.x = cabs2(to_d(wl[e]));
-        return v;
+      // h_i = V_i^H w (i <= j) and ||w||^2 in one reduction: half-wavefront q pairs w with V_q
+      // (q <= j) or with itself (q = j + 1; the real part is ||w||^2)
+      auto arn_dots = [&]() {
+        const int q = tid >> 5, c = tid & 31;
+        if (q < j + 2) {
+          const T* vq = q <= j ? Vb + q * vst : wl;
+          double2 sm = mk(0.0, 0.0);
+          for (int e = c; e < ne; e += 32) cfmac(sm, to_d(vq[e]), to_d(wl[e]));
+          sm = cp_half_sum(sm);
+          if (c == 0) red[q][0] = sm;
+        }
       };
-      wg_sums(j + 2, dots);
-      grid_reduce(j + 2, (j + 1) & 1);
-      const double ww = res[j + 1].x;
-      double hh = 0.0;
-      for (int i = 0; i <= j; ++i) hh += cabs2(res[i]);
-      double hn2 = ww - hh;
-      bool updated = false;
-      if (!(hn2 > eta * ww)) {
-        // heavy cancellation: apply the first pass, then a second pass with an exact norm
-        if (tid <= j) Hr[tid + (mm + 1) * j] = res[tid];
-        for (int t = tid; t < (HALO ? nle : ne); t += CP_THREADS) {
+      // w -= sum_{i <= j} res_i V_i on the own (and halo) entries
+      const int nup = HALO ? nle : ne;
+      auto gs_update = [&]() {
+        for (int t = tid; t < nup; t += CP_THREADS) {
           double2 w = to_d(wl[t]);
           for (int i = 0; i <= j; ++i) w = csub(w, cmul(res[i], to_d(Vb[i * vst + t])));
-          wl[t] = from_d<R>(w);
+          const T ws = from_d<R>(w);
+          wl[t] = ws;
+          if (!HALO && j + 1 < mm) cp_store(&xch[e0 + t], ws);  // hn * v_{j+1} for the next stencil
         }
-        __syncthreads();
-        wg_sums(j + 2, dots);
-        grid_reduce(j + 2);
-        double hh2 = 0.0;
-        for (int i = 0; i <= j; ++i) hh2 += cabs2(res[i]);
-        hn2 = res[j + 1].x - hh2;
-        if (tid <= j) Hr[tid + (mm + 1) * j] = cadd(Hr[tid + (mm + 1) * j], res[tid]);
-        for (int t = tid; t < (HALO ? nle : ne); t += CP_THREADS) {
-          double2 w = to_d(wl[t]);
-          for (int i = 0; i <= j; ++i) w = csub(w, cmul(res[i], to_d(Vb[i * vst + t])));
-          wl[t] = from_d<R>(w);
-        }
-        __syncthreads();
-        updated = true;
-      }
-      double hn = sqrt(fmax(hn2, 0.0));
-      if (!(hn > 1e-12 * sqrt(ww))) { hn = 0.0; brk = true; }
-      // the Givens update (one thread of an otherwise idle wavefront) overlaps the
-      // Gram-Schmidt update, the exchange write and the exchange barrier
-      if (tid == CP_THREADS - 64) {
+      };
+      // Givens update of column j (h_0 .. h_j from src, then hn) on the last wavefront: lane l
+      // loads entry l and rotation l, then the chain runs in every lane on values read from one
+      // lane at a time (scalar registers, no LDS round trip per rotation); lane 0 stores
+      auto givens = [&](const double2* src, double hn) {
         double2* col = Hr + (mm + 1) * j;
-        if (!updated)
-          for (int i = 0; i <= j; ++i) col[i] = res[i];
-        col[j + 1] = mk(hn, 0.0);
+        const double2 hl = lane <= j ? src[lane] : mk(hn, 0.0);
+        const double cl = lane < j ? rc[lane] : 0.0;
+        const double2 sl = lane < j ? rs[lane] : mk(0.0, 0.0);
+        double2 x0 = cp_lane(hl, 0);
+        double2 x1 = cp_lane(hl, 1);
         for (int q = 0; q < j; ++q) {
-          const double2 x0 = col[q], x1 = col[q + 1];
-          col[q] = cadd(cscale(x0, rc[q]), cmul(rs[q], x1));
-          col[q + 1] = csub(cscale(x1, rc[q]), cmul(cconj(rs[q]), x0));
+          const double cq = cp_lane(cl, q);
+          const double2 sq = cp_lane(sl, q);
+          const double2 x2 = cp_lane(hl, q + 2);
+          const double2 out = cadd(cscale(x0, cq), cmul(sq, x1));
+          if (lane == 0) col[q] = out;
+          x0 = csub(cscale(x1, cq), cmul(cconj(sq), x0));
+          x1 = x2;
         }
         double c;
         double2 sg;
-        cp_givens(col[j], col[j + 1], c, sg);
-        col[j] = cadd(cscale(col[j], c), cmul(sg, col[j + 1]));
-        col[j + 1] = mk(0.0, 0.0);
-        rc[j] = c;
-        rs[j] = sg;
-        const double2 g0 = gv[j], g1 = gv[j + 1];
-        gv[j] = cadd(cscale(g0, c), cmul(sg, g1));
-        gv[j + 1] = csub(cscale(g1, c), cmul(cconj(sg), g0));
-        sh_scal[0] = sqrt(cabs2(gv[j + 1]));
+        cp_givens(x0, x1, c, sg);
+        if (lane == 0) {
+          col[j] = cadd(cscale(x0, c), cmul(sg, x1));
+          col[j + 1] = mk(0.0, 0.0);
+          rc[j] = c;
+          rs[j] = sg;
+          const double2 g0 = gv[j], g1 = gv[j + 1];
+          gv[j] = cadd(cscale(g0, c), cmul(sg, g1));
+          gv[j + 1] = csub(cscale(g1, c), cmul(cconj(sg), g0));
+          sh_scal[0] = sqrt(cabs2(gv[j + 1]));
+        }
+      };
+      arn_dots();
+      grid_reduce(j + 2, (j + 1) & 1);
+      const double ww = res[j + 1].x;
+      if (wave == CP_WAVES - 1) {
+        // ||h||^2, the cancellation test and (without a second pass) the rotations, while the
+        // other wavefronts apply the first pass
+        const double rsum = cp_row_sum(lane <= j ? cabs2(res[lane]) : 0.0);
+        const double hh = (cp_lane(rsum, 0) + cp_lane(rsum, 16)) + (cp_lane(rsum, 32) + cp_lane(rsum, 48));
+        const double hn2 = ww - hh;
+        const bool second = !(hn2 > eta * ww);
+        if (second) {
+          if (lane <= j) Hr[lane + (mm + 1) * j] = res[lane];  // first-pass coefficients
+        } else {
+          double hn1 = sqrt(fmax(hn2, 0.0));
+          const bool b = !(hn1 > 1e-12 * sqrt(ww));
+          if (b) hn1 = 0.0;
+          givens(res, hn1);
+          if (lane == 0) {
+            sh_scal[1] = hn1;
+            sh_flag[2] = b ? 1 : 0;
+          }
+        }
+        if (lane == 0) sh_flag[1] = second ? 1 : 0;
       }
-      for (int t = tid; t < (HALO ? nle : ne); t += CP_THREADS) {
-        double2 w = to_d(wl[t]);
-        if (!updated)
-          for (int i = 0; i <= j; ++i) w = csub(w, cmul(res[i], to_d(Vb[i * vst + t])));
-        const T ws = from_d<R>(w);
-        wl[t] = ws;
-        if (!HALO && j + 1 < mm) cp_store(&xch[e0 + t], ws);  // hn * v_{j+1} for the next stencil
+      gs_update();
+      __syncthreads();
+      double hn;
+      if (sh_flag[1]) {
+        // heavy cancellation: a second pass with an exact norm
+        arn_dots();
+        grid_reduce(j + 2);
+        double hh2 = 0.0;
+        for (int i = 0; i <= j; ++i) hh2 += cabs2(res[i]);
+        const double hn2 = res[j + 1].x - hh2;
+        if (tid <= j) Hr[tid + (mm + 1) * j] = cadd(Hr[tid + (mm + 1) * j], res[tid]);
+        gs_update();
+        hn = sqrt(fmax(hn2, 0.0));
+        if (!(hn > 1e-12 * sqrt(ww))) { hn = 0.0; brk = true; }
+        __syncthreads();
+        if (wave == CP_WAVES - 1) givens(Hr + (mm + 1) * j, hn);
+        __syncthreads();
+      } else {
+        hn = sh_scal[1];
+        brk = sh_flag[2] != 0;
       }
       if (!HALO && j + 1 < mm) dead = dead || cp_barrier(a.flags, G, ++gen, a.err);
-      else __syncthreads();
       est = brk ? 0.0 : sh_scal[0];
       steps = j + 1;
       hprev = hn;
