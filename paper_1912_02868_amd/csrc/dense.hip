@@ -14,11 +14,23 @@ __device__ inline double2 cdiv(double2 a, double2 b) {
   const double d = cabs2(b);
   return mk((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
 }
+__device__ inline double cabs1(double2 a) { return fabs(a.x) + fabs(a.y); }
+// principal square root (real part >= 0) from sqrt((|z| +/- Re z) / 2)
 __device__ inline double2 csqrt_(double2 z) {
-  const double r = sqrt(sqrt(cabs2(z)));
-  const double th = 0.5 * atan2(z.y, z.x);
-  return mk(r * cos(th), r * sin(th));
+  const double r = sqrt(cabs2(z));
+  if (r == 0.0) return mk(0.0, 0.0);
+  const double a = sqrt(0.5 * (r + fabs(z.x)));
+  if (z.x >= 0.0) return mk(a, z.y / (2.0 * a));
+  return mk(fabs(z.y) / (2.0 * a), copysign(a, z.y));
 }
+// value of lane l of a wavefront (scalar register read of both 32-bit halves)
+__device__ inline double rd_lane(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ inline double2 rd_lane(double2 v, int l) { return mk(rd_lane(v.x, l), rd_lane(v.y, l)); }
 
 // Givens rotation G = [c s; -conj(s) c] (c real) with G [a; b] = [r; 0].
 __device__ inline void make_givens(double2 a, double2 b, double& c, double2& s) {
@@ -28,6 +40,16 @@ __device__ inline void make_givens(double2 a, double2 b, double& c, double2& s) 
   const double nr = sqrt(na * na + nb * nb);
   c = na / nr;
   s = cscale(cmul(cconj(b), a), 1.0 / (na * nr));
+}
+// The same rotation with the square roots independent of each other and one division:
+// c = |a|^2 / (|a| r), s = conj(b) a / (|a| r), r = sqrt(|a|^2 + |b|^2).
+__device__ inline void make_givens_fast(double2 a, double2 b, double& c, double2& s) {
+  const double na2 = cabs2(a), nb2 = cabs2(b);
+  if (nb2 == 0.0) { c = 1.0; s = mk(0.0, 0.0); return; }
+  if (na2 == 0.0) { c = 0.0; s = cscale(cconj(b), 1.0 / sqrt(nb2)); return; }
+  const double inv = 1.0 / (sqrt(na2) * sqrt(na2 + nb2));
+  c = na2 * inv;
+  s = cscale(cmul(cconj(b), a), inv);
 }
 
 // ---------------------------------------------------------------- least squares
@@ -310,23 +332,30 @@ __device__ void hessenberg(double2* A, double2* X, double2* v, int n) {
 }
 
 // Complex Schur form of the Hessenberg A by single-shift implicit QR (Wilkinson shifts,
-// exceptional shifts every 10 iterations).  Returns 0 on success.
+// exceptional shifts every 10 iterations).  Returns 0 on success.  One wavefront (n <= 64):
+// the deflation test is one ballot over the subdiagonal (|re| + |im| magnitudes, as in the
+// reference QR codes), and each bulge-chasing rotation is one pass in which lane l loads
+// column c0 + l of rows k, k+1, row l of columns k, k+1 and row l of X, applies the rotation
+// from the left and (taking the four left-updated corner entries from their lanes) from the
+// right, and the next rotation's inputs come back through scalar registers.  A wavefront's
+// LDS accesses take effect in program order, so no barrier is needed between rotations.
+static_assert(MMAX <= DW, "one lane per row and column of the restart eigenproblem");
 __device__ int schur_qr(double2* A, double2* X, int n, int* flag_sh) {
   const int t = threadIdx.x;
   const double eps = 2.220446049250313e-16;
   int hi = n - 1, iter = 0, total = 0;
+  __syncthreads();
   while (hi > 0) {
-    // locate the active block [lo, hi]
-    int lo = hi;
-    while (lo > 0) {
-      double sc = cabs_(A[lo - 1 + n * (lo - 1)]) + cabs_(A[lo + n * lo]);
+    // the active block [lo, hi]: lo is the last small subdiagonal at or above hi
+    bool small = false;
+    if (t >= 1 && t <= hi) {
+      double sc = cabs1(A[t - 1 + n * (t - 1)]) + cabs1(A[t + n * t]);
       if (sc == 0.0) sc = 1.0;
-      if (cabs_(A[lo + n * (lo - 1)]) <= eps * sc) break;
-      --lo;
+      small = cabs1(A[t + n * (t - 1)]) <= eps * sc;
     }
-    __syncthreads();
+    const unsigned long long msk = __ballot(small);
+    const int lo = msk ? 63 - __clzll(msk) : 0;
     if (lo > 0 && t == 0) A[lo + n * (lo - 1)] = mk(0.0, 0.0);
-    __syncthreads();
     if (lo == hi) { --hi; iter = 0; continue; }
     if (++total > 60 * n) return 1;
     ++iter;
@@ -340,39 +369,67 @@ __device__ int schur_qr(double2* A, double2* X, int n, int* flag_sh) {
       const double2 disc = csqrt_(cadd(cmul(hm, hm), cmul(b, c)));
       const double2 m0 = cscale(cadd(a, d), 0.5);
       const double2 m1 = cadd(m0, disc), m2 = csub(m0, disc);
-      mu = (cabs_(csub(m1, d)) <= cabs_(csub(m2, d))) ? m1 : m2;
+      mu = (cabs2(csub(m1, d)) <= cabs2(csub(m2, d))) ? m1 : m2;
     }
     double2 x = csub(A[lo + n * lo], mu), y = A[lo + 1 + n * lo];
     for (int k = lo; k < hi; ++k) {
       double cg;
       double2 sg;
-      make_givens(x, y, cg, sg);
-      __syncthreads();
-      // left: rows k, k+1, columns from max(lo, k-1) .. n-1
+      make_givens_fast(x, y, cg, sg);
       const int c0 = (k > lo) ? k - 1 : lo;
-      for (int jc = c0 + t; jc < n; jc += DW) {
-        const double2 p = A[k + n * jc], q = A[k + 1 + n * jc];
-        A[k + n * jc] = cadd(cscale(p, cg), cmul(sg, q));
-        A[k + 1 + n * jc] = csub(cscale(q, cg), cmul(cconj(sg), p));
-      }
-      __syncthreads();
-      // right: columns k, k+1 by G^H, rows 0 .. min(k+2, hi); and X (all rows)
       const int r1 = (k + 2 < hi) ? k + 2 : hi;
-      for (int rr = t; rr < (r1 + 1) + n; rr += DW) {
-        double2* M = (rr <= r1) ? A : X;
-        const int i = (rr <= r1) ? rr : rr - (r1 + 1);
-        const double2 p = M[i + n * k], q = M[i + n * (k + 1)];
-        M[i + n * k] = cadd(cscale(p, cg), cmul(q, cconj(sg)));
-        M[i + n * (k + 1)] = csub(cscale(q, cg), cmul(p, sg));
+      const int jc = c0 + t;
+      const bool lft = jc < n, rgt = t <= r1, xr = t < n;
+      double2 p = mk(0.0, 0.0), q = mk(0.0, 0.0), ra = mk(0.0, 0.0), rb = mk(0.0, 0.0);
+      double2 xa = mk(0.0, 0.0), xb = mk(0.0, 0.0);
+      if (lft) {
+        p = A[k + n * jc];
+        q = A[k + 1 + n * jc];
       }
-      __syncthreads();
+      if (rgt) {
+        ra = A[t + n * k];
+        rb = A[t + n * (k + 1)];
+      }
+      if (xr) {
+        xa = X[t + n * k];
+        xb = X[t + n * (k + 1)];
+      }
+      // from the left on rows k, k+1 (columns c0 ..)
+      const double2 pn = cadd(cscale(p, cg), cmul(sg, q));
+      const double2 qn = csub(cscale(q, cg), cmul(cconj(sg), p));
+      if (lft) {
+        A[k + n * jc] = pn;
+        A[k + 1 + n * jc] = qn;
+      }
+      // rows k, k+1 of columns k, k+1 after the left rotation
+      const double2 r00 = rd_lane(pn, k - c0), r01 = rd_lane(pn, k + 1 - c0);
+      const double2 r10 = rd_lane(qn, k - c0), r11 = rd_lane(qn, k + 1 - c0);
+      if (t == k) {
+        ra = r00;
+        rb = r01;
+      }
+      if (t == k + 1) {
+        ra = r10;
+        rb = r11;
+      }
+      // from the right by G^H on columns k, k+1 (rows 0 .. r1), and on X
+      const double2 ran = cadd(cscale(ra, cg), cmul(rb, cconj(sg)));
+      const double2 rbn = csub(cscale(rb, cg), cmul(ra, sg));
+      if (rgt) {
+        A[t + n * k] = ran;
+        A[t + n * (k + 1)] = rbn;
+      }
+      if (xr) {
+        X[t + n * k] = cadd(cscale(xa, cg), cmul(xb, cconj(sg)));
+        X[t + n * (k + 1)] = csub(cscale(xb, cg), cmul(xa, sg));
+      }
       if (k + 1 < hi) {
-        x = A[k + 1 + n * k];
-        y = A[k + 2 + n * k];
+        x = rd_lane(ran, k + 1);
+        y = rd_lane(ran, k + 2);
       }
     }
-    __syncthreads();
   }
+  __syncthreads();
   (void)flag_sh;
   return 0;
 }
