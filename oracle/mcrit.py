@@ -31,12 +31,17 @@ def critical_mass_dense(theta, antiperiodic=True):
 
 
 def leftmost_eigenvalues(theta, antiperiodic=True, sigma=0.0, k=8, tol=1e-11):
-    """The k eigenvalues of D(0) nearest sigma (shift-invert ARPACK) and the covered radius."""
+    """The k eigenvalues of D(0) nearest sigma (shift-invert ARPACK) and the covered radius.
+
+    Above 256^2 sites the Krylov space is 96 vectors: there the leftmost eigenvalues of
+    some configurations lie within a few per cent of each other and a 32-vector space
+    stalls for hours.  The answer (the k nearest eigenvalues) does not depend on it."""
     D0 = dirac_matrix(theta, 0.0, antiperiodic)
     n = D0.shape[0]
     lu = spla.splu((D0 - sigma * sp.identity(n, format="csc")).tocsc())
     op = spla.LinearOperator((n, n), matvec=lu.solve, dtype=complex)
-    mu = spla.eigs(op, k=k, which="LM", ncv=max(4 * k, 32), tol=tol, maxiter=100000,
+    ncv = 96 if n > 2 * 256 * 256 else max(4 * k, 32)
+    mu = spla.eigs(op, k=k, which="LM", ncv=ncv, tol=tol, maxiter=100000,
                    return_eigenvectors=False)
     lam = sigma + 1.0 / mu
     return lam, float(np.abs(lam - sigma).max())
