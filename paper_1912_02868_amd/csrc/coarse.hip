@@ -273,6 +273,25 @@ __device__ inline double2 cp_gather_sum(const double2* P, int G, int c) {
   return cp_half_sum(sm);
 }
 
+// cp_gather_sum for two quantities at once (loads of both issued before any add).
+__device__ inline void cp_gather_sum2(const double2* P0, const double2* P1, int G, int c, double2& s0, double2& s1) {
+  double2 v[CP_GMAX / 32], w[CP_GMAX / 32];
+#pragma unroll
+  for (int u = 0; u < CP_GMAX / 32; ++u) {
+    const int b = c + 32 * u;
+    v[u] = b < G ? cp_load(&P0[b]) : mk(0.0, 0.0);
+    w[u] = b < G ? cp_load(&P1[b]) : mk(0.0, 0.0);
+  }
+  double2 a0 = v[0], a1 = w[0];
+#pragma unroll
+  for (int u = 1; u < CP_GMAX / 32; ++u) {
+    a0 = cadd(a0, v[u]);
+    a1 = cadd(a1, w[u]);
+  }
+  s0 = cp_half_sum(a0);
+  s1 = cp_half_sum(a1);
+}
+
 __device__ inline void cp_givens(double2 a, double2 b, double& c, double2& s) {
   const double na = sqrt(cabs2(a)), nb = sqrt(cabs2(b));
   if (nb == 0.0) { c = 1.0; s = mk(0.0, 0.0); return; }
@@ -292,8 +311,14 @@ __device__ inline double2 cp_div(double2 a, double2 b) {
 // workgroup applies the same Gram-Schmidt update to its own and its halo entries, so the
 // next stencil needs no exchange.  The halo values are bitwise the owners' (same inputs,
 // same operations in the same loop).
-template <typename R, bool ALDS, bool HALO>
-__global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
+// REG (halo form, at most 4 sites per workgroup): 512 threads, and thread t < 5 * 24 * spw keeps
+// its row of the 24 x 24 blocks in registers for the whole solve (96 VGPRs in FP64), so the
+// stencil reads only v_j (LDS) instead of streaming the blocks from L2 every step.
+template <typename R, bool ALDS, bool HALO, bool REG = false>
+__global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a) {
+  static_assert(!REG || (HALO && !ALDS), "register blocks come with the halo form");
+  constexpr int TPB = REG ? 512 : CP_THREADS;  // threads per workgroup
+  constexpr int NHW = TPB / 32;                // half-wavefronts
   using T = cx<R>;
   extern __shared__ __align__(16) unsigned char smem[];
   unsigned gen = 0;
@@ -351,7 +376,7 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
   // halo entries of exchange half `half` into wl[ne ..] (issued right after a barrier)
   auto load_halo = [&](int half) {
     const T* src = xch + (size_t)half * n;
-    for (int t = CP_THREADS - 1 - tid; t < nh * NC; t += CP_THREADS)
+    for (int t = TPB - 1 - tid; t < nh * NC; t += TPB)
       wl[ne + t] = cp_load(&src[(int64_t)hsite[t / NC] * NC + t % NC]);
   };
 
@@ -360,10 +385,10 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
   // the 32 lanes of half-wavefront q add every 32nd entry, then the half-wavefront tree
   // (lane 0 writes red[q][0]).  grid_reduce: publish red[q][0], barrier, every workgroup
   // adds all workgroups' sums in the same order into res[q].  Quantity q of either step
-  // belongs to threads 32 q .. 32 q + 31 (CP_QMAX * 32 = CP_THREADS).
+  // belongs to half-wavefront q mod NHW (one or two quantities each).
   auto wg_sums = [&](int nq, auto&& term) {
-    const int q = tid >> 5, c = tid & 31;
-    if (q < nq) {
+    const int c = tid & 31;
+    for (int q = tid >> 5; q < nq; q += NHW) {
       double2 sm = mk(0.0, 0.0);
       for (int e = c; e < ne; e += 32) sm = cadd(sm, term(q, e));
       sm = cp_half_sum(sm);
@@ -376,7 +401,15 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
     if (tid < nq) cp_store(&P[(size_t)tid * G + gi], red[tid][0]);
     dead = dead || cp_barrier(a.flags, G, ++gen, a.err);
     const int q = tid >> 5, c = tid & 31;
-    if (q < nq) {
+    if (NHW < CP_QMAX && q + NHW < nq) {
+      // two quantities per half-wavefront, all loads in flight together
+      double2 s0, s1;
+      cp_gather_sum2(P + (size_t)q * G, P + (size_t)(q + NHW) * G, G, c, s0, s1);
+      if (c == 0) {
+        res[q] = s0;
+        res[q + NHW] = s1;
+      }
+    } else if (q < nq) {
       const double2 sm = cp_gather_sum(P + (size_t)q * G, G, c);
       if (c == 0) res[q] = sm;
     }
@@ -387,20 +420,29 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
   auto sq = [&](const T* v) { return [=](int, int e) { return mk(cabs2(to_d(v[e])), 0.0); }; };
 
   // ---------------------------------------------------------------- load the resident data
+  T areg[REG ? NC : 1];
+  if constexpr (REG) {
+    if (tid < nsl * 5 * NC) {
+      const int sl = tid / (5 * NC), d = (tid / NC) % 5, i = tid % NC;
+      const T* blk = Ag + ((int64_t)(S0 + sl) * 5 + d) * NC * NC + i;
+#pragma unroll
+      for (int jj = 0; jj < NC; ++jj) areg[jj] = blk[jj * NC];
+    }
+  }
   if (ALDS) {
     const T* src = Ag + (int64_t)S0 * 5 * NC * NC;
-    for (int t = tid; t < nsl * 5 * NC * NC; t += CP_THREADS) Ab[t] = src[t];
+    for (int t = tid; t < nsl * 5 * NC * NC; t += TPB) Ab[t] = src[t];
   }
-  for (int t = tid; t < (k + 1) * ne; t += CP_THREADS) {
+  for (int t = tid; t < (k + 1) * ne; t += TPB) {
     const int i = t / ne, e = t % ne;
     DVb[t] = DVg[(int64_t)i * n + e0 + e];
   }
-  for (int t = tid; t < ne; t += CP_THREADS) {
+  for (int t = tid; t < ne; t += TPB) {
     rl[t] = bg[e0 + t];
     xl[t] = make_cx<R>(R(0), R(0));
   }
-  for (int t = tid; t < (k + 1) * k; t += CP_THREADS) Mk[t] = a.DM[t];
-  for (int t = tid; t < (k + 1) * (k + 1); t += CP_THREADS) Pk[t] = a.DP[t];
+  for (int t = tid; t < (k + 1) * k; t += TPB) Mk[t] = a.DM[t];
+  for (int t = tid; t < (k + 1) * (k + 1); t += TPB) Pk[t] = a.DP[t];
   __syncthreads();
   // ||b||
   wg_sums(1, sq(rl));
@@ -431,7 +473,7 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
       uv[i] = acc;
     }
     __syncthreads();
-    for (int t = tid; t < ne; t += CP_THREADS) {
+    for (int t = tid; t < ne; t += TPB) {
       double2 xv = to_d(xl[t]), rv = to_d(rl[t]);
       for (int i = 0; i < k; ++i) cfma(xv, yv[i], to_d(DVb[i * ne + t]));
       for (int i = 0; i <= k; ++i) rv = csub(rv, cmul(uv[i], to_d(DVb[i * ne + t])));
@@ -442,7 +484,7 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
     // ------------------------------------------------------------ GMRES(mm) cycle from r
     __syncthreads();
     if (HALO)
-      for (int t = tid; t < ne; t += CP_THREADS) wl[t] = rl[t];
+      for (int t = tid; t < ne; t += TPB) wl[t] = rl[t];
     wg_sums(1, sq(rl));
     grid_reduce(1, 0);
     double hprev = sqrt(res[0].x);  // beta; xchg holds the unnormalised start vector
@@ -464,11 +506,11 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
       // xchg holds hprev * v_j (written before the last barrier); halo form: wl holds it
       // on the own and halo sites
       const double inv = 1.0 / hprev;
-      for (int t = tid; t < (HALO ? nle : ne); t += CP_THREADS) {
+      for (int t = tid; t < (HALO ? nle : ne); t += TPB) {
         const T src = (!HALO && j == 0) ? rl[t] : wl[t];
         Vb[j * vst + t] = from_d<R>(cscale(to_d(src), inv));
       }
-      for (int t = tid; t < (HALO ? 0 : nsl * 5 * NC); t += CP_THREADS) {
+      for (int t = tid; t < (HALO ? 0 : nsl * 5 * NC); t += TPB) {
         const int sl = t / (5 * NC), d = (t / NC) % 5, jj = t % NC;
         const int S = S0 + sl, X = S % a.Lx, Tt = S / a.Lx;
         int nb;
@@ -482,7 +524,15 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
         xs[t] = cp_load(&xch[(int64_t)nb * NC + jj]);
       }
       __syncthreads();
-      for (int t = tid; t < nsl * 5 * NC; t += CP_THREADS) {
+      if (REG && tid < nsl * 5 * NC) {
+        const int sl = tid / (5 * NC), d = (tid / NC) % 5;
+        const T* xv = wl + loc[sl * 5 + d] * NC;
+        double2 acc = mk(0.0, 0.0);
+#pragma unroll
+        for (int jj = 0; jj < NC; ++jj) cfma(acc, to_d(areg[jj]), to_d(xv[jj]));
+        part[tid] = acc;
+      }
+      for (int t = tid; t < (REG ? 0 : nsl * 5 * NC); t += TPB) {
         const int sl = t / (5 * NC), d = (t / NC) % 5, i = t % NC;
         const T* blk = ALDS ? (Ab + ((int64_t)sl * 5 + d) * NC * NC) : (Ag + ((int64_t)(S0 + sl) * 5 + d) * NC * NC);
         const T* xv = HALO ? wl + loc[sl * 5 + d] * NC : xs + (sl * 5 + d) * NC;
@@ -498,7 +548,7 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
         part[t] = acc;
       }
       __syncthreads();
-      for (int t = tid; t < ne; t += CP_THREADS) {
+      for (int t = tid; t < ne; t += TPB) {
         const int sl = t / NC, i = t % NC;
         double2 y = part[(sl * 5 + 0) * NC + i];
         for (int d = 1; d < 5; ++d) y = cadd(y, part[(sl * 5 + d) * NC + i]);
@@ -510,8 +560,8 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
       // h_i = V_i^H w (i <= j) and ||w||^2 in one reduction: half-wavefront q pairs w with V_q
       // (q <= j) or with itself (q = j + 1; the real part is ||w||^2)
       auto arn_dots = [&]() {
-        const int q = tid >> 5, c = tid & 31;
-        if (q < j + 2) {
+        const int c = tid & 31;
+        for (int q = tid >> 5; q < j + 2; q += NHW) {
           const T* vq = q <= j ? Vb + q * vst : wl;
           double2 sm = mk(0.0, 0.0);
           for (int e = c; e < ne; e += 32) cfmac(sm, to_d(vq[e]), to_d(wl[e]));
@@ -522,7 +572,7 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
       // w -= sum_{i <= j} res_i V_i on the own (and halo) entries
       const int nup = HALO ? nle : ne;
       auto gs_update = [&]() {
-        for (int t = tid; t < nup; t += CP_THREADS) {
+        for (int t = tid; t < nup; t += TPB) {
           double2 w = to_d(wl[t]);
           for (int i = 0; i <= j; ++i) w = csub(w, cmul(res[i], to_d(Vb[i * vst + t])));
           const T ws = from_d<R>(w);
@@ -566,7 +616,7 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
       arn_dots();
       grid_reduce(j + 2, (j + 1) & 1);
       const double ww = res[j + 1].x;
-      if (wave == CP_WAVES - 1) {
+      if (wave == (TPB / 64) - 1) {
         // ||h||^2, the cancellation test and (without a second pass) the rotations, while the
         // other wavefronts apply the first pass
         const double rsum = cp_row_sum(lane <= j ? cabs2(res[lane]) : 0.0);
@@ -602,7 +652,7 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
         hn = sqrt(fmax(hn2, 0.0));
         if (!(hn > 1e-12 * sqrt(ww))) { hn = 0.0; brk = true; }
         __syncthreads();
-        if (wave == CP_WAVES - 1) givens(Hr + (mm + 1) * j, hn);
+        if (wave == (TPB / 64) - 1) givens(Hr + (mm + 1) * j, hn);
         __syncthreads();
       } else {
         hn = sh_scal[1];
@@ -634,7 +684,7 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
     }
     __syncthreads();
     const double invn = hprev > 0.0 ? 1.0 / hprev : 0.0;
-    for (int t = tid; t < ne; t += CP_THREADS) {
+    for (int t = tid; t < ne; t += TPB) {
       double2 xv = to_d(xl[t]);
       double2 rv = mk(0.0, 0.0);
       for (int i = 0; i < steps; ++i) {
@@ -651,7 +701,7 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_proj(CPArgs a) {
     if (brk || est <= tol_abs) converged = true;
     if (stop && !converged) break;  // iteration cap
   }
-  for (int t = tid; t < ne; t += CP_THREADS) xg[e0 + t] = xl[t];
+  for (int t = tid; t < ne; t += TPB) xg[e0 + t] = xl[t];
   if (gi == 0 && tid == 0) {
     a.out_iters[0] += iters;  // accumulated over the calls of one outer solve
     a.out_relres[0] = bnorm > 0.0 ? est / bnorm : 0.0;
@@ -976,15 +1026,17 @@ static bool cp_debug() {
 }
 
 template <typename R>
-static const void* proj_fn(bool alds, bool halo) {
+static const void* proj_fn(bool alds, bool halo, bool reg) {
+  if (reg) return (const void*)k_coarse_proj<R, false, true, true>;
   if (halo) return alds ? (const void*)k_coarse_proj<R, true, true> : (const void*)k_coarse_proj<R, false, true>;
   return alds ? (const void*)k_coarse_proj<R, true, false> : (const void*)k_coarse_proj<R, false, false>;
 }
 
 template <typename R>
-static int try_launch(hipStream_t st, CPArgs& a, int G, size_t lds, bool alds, bool halo, int coop) {
+static int try_launch(hipStream_t st, CPArgs& a, int G, size_t lds, bool alds, bool halo, bool reg, int coop) {
   void* args[] = {&a};
-  const void* fn = proj_fn<R>(alds, halo);
+  const void* fn = proj_fn<R>(alds, halo, reg);
+  const int threads = reg ? 512 : CP_THREADS;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) {
     if (cp_debug()) fprintf(stderr, "[dmg] coarse kernel: set LDS %zu failed: %s\n", lds, hipGetErrorString(e));
@@ -992,7 +1044,7 @@ static int try_launch(hipStream_t st, CPArgs& a, int G, size_t lds, bool alds, b
     return 0;
   }
   int per_cu = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, CP_THREADS, lds);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds);
   if (e != hipSuccess) {
     if (cp_debug()) fprintf(stderr, "[dmg] coarse kernel: occupancy query failed: %s\n", hipGetErrorString(e));
     (void)hipGetLastError();
@@ -1004,7 +1056,7 @@ static int try_launch(hipStream_t st, CPArgs& a, int G, size_t lds, bool alds, b
   if (per_cu < 1 || G > per_cu * ncu) {
     if (cp_debug())
       fprintf(stderr, "[dmg] coarse kernel: %d workgroups of %d threads, LDS %zu: %d per CU x %d CUs\n", G,
-              CP_THREADS, lds, per_cu, ncu);
+              threads, lds, per_cu, ncu);
     return 0;
   }
   if (hipMemsetAsync(a.flags, 0, sizeof(unsigned) * CP_FLAGPAD * G, st) != hipSuccess) {
@@ -1012,12 +1064,14 @@ static int try_launch(hipStream_t st, CPArgs& a, int G, size_t lds, bool alds, b
     return 0;
   }
   if (coop) {
-    e = hipLaunchCooperativeKernel(fn, dim3(G), dim3(CP_THREADS), args, (unsigned)lds, st);
+    e = hipLaunchCooperativeKernel(fn, dim3(G), dim3(threads), args, (unsigned)lds, st);
   } else {
     // Plain launch: the grid (G <= 256 workgroups, one per CU) always fits the device,
     // so every workgroup is placed once earlier kernels drain; the barrier's spin limit
     // bounds any wait.
-    if (halo) {
+    if (reg) {
+      hipLaunchKernelGGL((k_coarse_proj<R, false, true, true>), dim3(G), dim3(threads), lds, st, a);
+    } else if (halo) {
       if (alds) hipLaunchKernelGGL((k_coarse_proj<R, true, true>), dim3(G), dim3(CP_THREADS), lds, st, a);
       else hipLaunchKernelGGL((k_coarse_proj<R, false, true>), dim3(G), dim3(CP_THREADS), lds, st, a);
     } else {
@@ -1064,8 +1118,17 @@ int launch_coarse_proj(hipStream_t st, const cx<R>* A, int Lx, int Lt, const cx<
       nl = std::max(nl, nsl + cp_halo(S0, nsl, Lx, Lt, nullptr, hs.data()));
     }
   }
-  // halo form (one barrier per Arnoldi step) first; the blocks in LDS where they fit
+  // halo form (one barrier per Arnoldi step) first: with the blocks in registers (512 threads,
+  // at most 4 sites per workgroup), then with the blocks in LDS where they fit, then from L2
   const int halo_ok = cp_halo_enabled() ? 1 : 0;
+  if (halo_ok && spw * 5 * NC <= 512) {
+    const size_t lds = CPLayout(spw, mm, k, sizeof(cx<R>), 0, nl).tot;
+    if (lds <= lds_max) {
+      CPArgs a{A, Lx, Lt, DV, DM, DP, k, b, x, tol, mm, max_iters, xchg, partials, out_iters, out_relres,
+               flags, err, spw, 0, nl};
+      if (try_launch<R>(st, a, G, lds, false, true, true, coop)) return 1;
+    }
+  }
   for (int halo = halo_ok; halo >= 0; --halo)
     for (int alds = 1; alds >= 0; --alds) {
       const size_t lds = CPLayout(spw, mm, k, sizeof(cx<R>), alds, halo ? nl : 0).tot;
@@ -1076,7 +1139,7 @@ int launch_coarse_proj(hipStream_t st, const cx<R>* A, int Lx, int Lt, const cx<
       }
       CPArgs a{A, Lx, Lt, DV, DM, DP, k, b, x, tol, mm, max_iters, xchg, partials, out_iters, out_relres,
                flags, err, spw, alds, halo ? nl : spw};
-      if (try_launch<R>(st, a, G, lds, alds == 1, halo == 1, coop)) return 1;
+      if (try_launch<R>(st, a, G, lds, alds == 1, halo == 1, false, coop)) return 1;
     }
   return 0;
 }
