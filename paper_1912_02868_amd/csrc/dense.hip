@@ -31,6 +31,36 @@ __device__ inline double rd_lane(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 __device__ inline double2 rd_lane(double2 v, int l) { return mk(rd_lane(v.x, l), rd_lane(v.y, l)); }
+// DPP lane permutation (quad_perm / row_ror control) on both 32-bit halves of a double
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+// Sum over the whole wavefront (all 64 lanes active): rows of 16 by DPP, then the four row
+// sums read into scalar registers; every lane gets the same bits.
+__device__ inline double wave_sum(double v) {
+  v += dpp_d<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_d<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_d<0x124>(v);  // row_ror 4
+  v += dpp_d<0x128>(v);  // row_ror 8
+  return (rd_lane(v, 0) + rd_lane(v, 16)) + (rd_lane(v, 32) + rd_lane(v, 48));
+}
+__device__ inline double2 wave_sum(double2 v) { return mk(wave_sum(v.x), wave_sum(v.y)); }
+// Largest value over the wavefront and the first lane holding it (-1 when no lane compares
+// equal to the maximum, i.e. with NaN)
+__device__ inline int wave_argmax(double v) {
+  double m = v;
+  m = fmax(m, dpp_d<0xB1>(m));
+  m = fmax(m, dpp_d<0x4E>(m));
+  m = fmax(m, dpp_d<0x124>(m));
+  m = fmax(m, dpp_d<0x128>(m));
+  m = fmax(fmax(rd_lane(m, 0), rd_lane(m, 16)), fmax(rd_lane(m, 32), rd_lane(m, 48)));
+  const unsigned long long at = __ballot(v == m);
+  return __ffsll((long long)at) - 1;
+}
 
 // Givens rotation G = [c s; -conj(s) c] (c real) with G [a; b] = [r; 0].
 __device__ inline void make_givens(double2 a, double2 b, double& c, double2& s) {
@@ -41,13 +71,18 @@ __device__ inline void make_givens(double2 a, double2 b, double& c, double2& s) 
   c = na / nr;
   s = cscale(cmul(cconj(b), a), 1.0 / (na * nr));
 }
-// The same rotation with the square roots independent of each other and one division:
-// c = |a|^2 / (|a| r), s = conj(b) a / (|a| r), r = sqrt(|a|^2 + |b|^2).
+// The same rotation with one square root and one division (as in LAPACK's zlartg):
+// c = |a|^2 / d, s = conj(b) a / d, d = |a| r = sqrt(|a|^2 (|a|^2 + |b|^2)); the product is
+// split into two roots only where it would leave the double range.
 __device__ inline void make_givens_fast(double2 a, double2 b, double& c, double2& s) {
   const double na2 = cabs2(a), nb2 = cabs2(b);
   if (nb2 == 0.0) { c = 1.0; s = mk(0.0, 0.0); return; }
   if (na2 == 0.0) { c = 0.0; s = cscale(cconj(b), 1.0 / sqrt(nb2)); return; }
-  const double inv = 1.0 / (sqrt(na2) * sqrt(na2 + nb2));
+  const double h2 = na2 + nb2, pr = na2 * h2;
+  double d;
+  if (pr > 1e-290 && pr < 1e290) d = sqrt(pr);
+  else d = sqrt(na2) * sqrt(h2);
+  const double inv = 1.0 / d;
   c = na2 * inv;
   s = cscale(cmul(cconj(b), a), inv);
 }
@@ -470,15 +505,15 @@ __global__ void __launch_bounds__(DW) k_dr_restart(KState* ks, int m, int k, dou
   __syncthreads();
   for (int p = 0; p < m; ++p) {
     __shared__ int piv;
-    if (t == 0) {
-      int best = p;
-      double bv = cabs_(A[p + m * p]);
-      for (int i = p + 1; i < m; ++i) {
-        const double a = cabs_(A[i + m * p]);
-        if (a > bv) { bv = a; best = i; }
+    {
+      // partial pivoting: the first row of largest modulus (compared squared)
+      const double a2 = (t >= p && t < m) ? cabs2(A[t + m * p]) : -1.0;
+      const int best = wave_argmax(a2);  // -1 if the column holds NaN
+      const double bv = best >= 0 ? rd_lane(a2, best) : 0.0;
+      if (t == 0) {
+        piv = best >= 0 ? best : p;
+        if (!(bv > 0.0)) fail = 1;
       }
-      piv = best;
-      if (bv == 0.0) fail = 1;
     }
     __syncthreads();
     if (fail) break;
@@ -572,35 +607,25 @@ __global__ void __launch_bounds__(DW) k_dr_restart(KState* ks, int m, int k, dou
     W[i + (m + 1) * k] = w;
   }
   __syncthreads();
-  // orthonormalise the k+1 columns (modified Gram-Schmidt, two passes), lanes over rows
+  // orthonormalise the k+1 columns (modified Gram-Schmidt, two passes): lane i holds row i
+  // (m + 1 <= 64) of the column being orthogonalised; dots are wavefront sums
   for (int q = 0; q <= k; ++q) {
+    double2 wq = t <= m ? W[t + (m + 1) * q] : mk(0.0, 0.0);
     for (int pass = 0; pass < 2; ++pass) {
       for (int p = 0; p < q; ++p) {
-        __shared__ double2 red[DW];
-        double2 acc = mk(0.0, 0.0);
-        for (int i = t; i <= m; i += DW) cfmac(acc, W[i + (m + 1) * p], W[i + (m + 1) * q]);
-        red[t] = acc;
-        __syncthreads();
-        double2 dot = mk(0.0, 0.0);
-        for (int l = 0; l < DW; ++l) dot = cadd(dot, red[l]);
-        __syncthreads();
-        for (int i = t; i <= m; i += DW) W[i + (m + 1) * q] = csub(W[i + (m + 1) * q], cmul(dot, W[i + (m + 1) * p]));
-        __syncthreads();
+        const double2 wp = t <= m ? W[t + (m + 1) * p] : mk(0.0, 0.0);
+        double2 pr = mk(0.0, 0.0);
+        cfmac(pr, wp, wq);
+        const double2 dot = wave_sum(pr);
+        wq = csub(wq, cmul(dot, wp));
       }
     }
-    __shared__ double2 red2[DW];
-    double nn = 0.0;
-    for (int i = t; i <= m; i += DW) nn += cabs2(W[i + (m + 1) * q]);
-    red2[t] = mk(nn, 0.0);
-    __syncthreads();
-    double tot = 0.0;
-    for (int l = 0; l < DW; ++l) tot += red2[l].x;
-    __syncthreads();
+    const double tot = wave_sum(cabs2(wq));
     if (!(tot > 0.0)) { if (t == 0) *status = 4; return; }
     const double inv = 1.0 / sqrt(tot);
-    for (int i = t; i <= m; i += DW) W[i + (m + 1) * q] = cscale(W[i + (m + 1) * q], inv);
-    __syncthreads();
+    if (t <= m) W[t + (m + 1) * q] = cscale(wq, inv);
   }
+  __syncthreads();
   // T1 = Hbar P_k  ((m+1) x k); Hk = P^H T1 ((k+1) x k); c_new = P^H s
   for (int e = t; e < (m + 1) * k; e += DW) {
     const int i = e % (m + 1), q = e / (m + 1);
@@ -647,7 +672,8 @@ static size_t dr_lds_bytes(int m, int k) {
 void launch_dr_restart(hipStream_t st, KState* ks, int m, int k, double2* Pout, int final_mode, double2* work,
                        int* status) {
   const size_t shm = dr_lds_bytes(m, k);
-  DMG_CHECK(shm <= 150 * 1024 && (size_t)m * m >= (size_t)(k + 1) * k, DMG_E_INVALID, "GMRES-DR sizes too large");
+  DMG_CHECK(shm <= 150 * 1024 && (size_t)m * m >= (size_t)(k + 1) * k && m + 1 <= DW, DMG_E_INVALID,
+            "GMRES-DR sizes too large");
   DMG_HIP(hipFuncSetAttribute((const void*)k_dr_restart, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
   hipLaunchKernelGGL(k_dr_restart, dim3(1), dim3(DW), shm, st, ks, m, k, Pout, final_mode, work, status);
   DMG_LAUNCH_CHECK();
