@@ -320,48 +320,62 @@ void launch_defl_prepare(hipStream_t s, const double2* Hk, int k, double2* M, do
 // A[i + n * j].
 
 // Hessenberg reduction by Householder reflections, accumulating X (A_orig = X A X^H).
+// One wavefront (n < 64): the norms are wavefront sums over one row per lane, the reflector
+// sits in LDS for broadcast reads, the left update has one lane per column and the right
+// update one lane per row of A and of X; inner products use two accumulators so that the
+// LDS loads of consecutive terms overlap.
 __device__ void hessenberg(double2* A, double2* X, double2* v, int n) {
   const int t = threadIdx.x;
   for (int e = t; e < n * n; e += DW) X[e] = ((e % n) == (e / n)) ? mk(1.0, 0.0) : mk(0.0, 0.0);
   __syncthreads();
   for (int col = 0; col + 2 < n; ++col) {
     // x = A[col+1 .. n-1, col]
-    double xn2 = 0.0;
-    for (int i = col + 2; i < n; ++i) xn2 += cabs2(A[i + n * col]);
-    if (xn2 == 0.0) { __syncthreads(); continue; }
-    const double2 alpha = A[col + 1 + n * col];
+    const double2 xi = (t > col && t < n) ? A[t + n * col] : mk(0.0, 0.0);
+    const double xn2 = wave_sum(t >= col + 2 ? cabs2(xi) : 0.0);
+    if (xn2 == 0.0) continue;
+    const double2 alpha = rd_lane(xi, col + 1);
     const double anorm = cabs_(alpha);
     const double xnorm = sqrt(xn2 + anorm * anorm);
     const double2 ph = anorm > 0.0 ? cscale(alpha, 1.0 / anorm) : mk(1.0, 0.0);
     const double2 beta = cscale(ph, -xnorm);
     // v = x - beta e1 (indices col+1 .. n-1 stored at v[0 .. n-col-2])
     const int len = n - col - 1;
-    for (int i = t; i < len; i += DW) v[i] = (i == 0) ? csub(alpha, beta) : A[col + 1 + i + n * col];
+    const double2 vi = (t == col + 1) ? csub(alpha, beta) : xi;
+    if (t > col && t < n) v[t - col - 1] = vi;
+    const double f = 2.0 / wave_sum(cabs2(vi));
     __syncthreads();
-    double vv = 0.0;
-    for (int i = 0; i < len; ++i) vv += cabs2(v[i]);
-    const double f = 2.0 / vv;
-    // left: A[col+1:, j] -= f v (v^H A[col+1:, j]) for all columns j
-    for (int jc = t; jc < n; jc += DW) {
-      double2 d = mk(0.0, 0.0);
-      for (int i = 0; i < len; ++i) cfmac(d, v[i], A[col + 1 + i + n * jc]);
-      d = cscale(d, f);
-      for (int i = 0; i < len; ++i) A[col + 1 + i + n * jc] = csub(A[col + 1 + i + n * jc], cmul(v[i], d));
+    // left: A[col+1:, j] -= f v (v^H A[col+1:, j]) for the columns j >= col
+    if (t >= col && t < n) {
+      const double2* a = A + col + 1 + n * t;
+      double2 d0 = mk(0.0, 0.0), d1 = mk(0.0, 0.0);
+      int i = 0;
+      for (; i + 1 < len; i += 2) {
+        cfmac(d0, v[i], a[i]);
+        cfmac(d1, v[i + 1], a[i + 1]);
+      }
+      if (i < len) cfmac(d0, v[i], a[i]);
+      const double2 d = cscale(cadd(d0, d1), f);
+      double2* aw = A + col + 1 + n * t;
+      for (int l = 0; l < len; ++l) aw[l] = csub(aw[l], cmul(v[l], d));
     }
     __syncthreads();
     // right: A[i, col+1:] -= f (A[i, col+1:] v) v^H for all rows; same for X
     for (int r = t; r < 2 * n; r += DW) {
       double2* M = (r < n) ? A : X;
       const int i = (r < n) ? r : r - n;
-      double2 d = mk(0.0, 0.0);
-      for (int l = 0; l < len; ++l) cfma(d, M[i + n * (col + 1 + l)], v[l]);
-      d = cscale(d, f);
-      for (int l = 0; l < len; ++l)
-        M[i + n * (col + 1 + l)] = csub(M[i + n * (col + 1 + l)], cmul(d, cconj(v[l])));
+      double2 d0 = mk(0.0, 0.0), d1 = mk(0.0, 0.0);
+      int l = 0;
+      for (; l + 1 < len; l += 2) {
+        cfma(d0, M[i + n * (col + 1 + l)], v[l]);
+        cfma(d1, M[i + n * (col + 2 + l)], v[l + 1]);
+      }
+      if (l < len) cfma(d0, M[i + n * (col + 1 + l)], v[l]);
+      const double2 d = cscale(cadd(d0, d1), f);
+      for (int l2 = 0; l2 < len; ++l2)
+        M[i + n * (col + 1 + l2)] = csub(M[i + n * (col + 1 + l2)], cmul(d, cconj(v[l2])));
     }
     __syncthreads();
-    if (t == 0)
-      for (int i = col + 2; i < n; ++i) A[i + n * col] = mk(0.0, 0.0);
+    if (t >= col + 2 && t < n) A[t + n * col] = mk(0.0, 0.0);
     __syncthreads();
   }
 }
