@@ -26,6 +26,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
+#include <type_traits>
 #include <vector>
 
 #include "kernels.h"
@@ -226,6 +227,14 @@ __device__ inline double cp_dpp(double v) {
   const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
+// DPP move whose lanes without a source (row_shr past the row start) keep `keep`
+template <int CTRL>
+__device__ inline double cp_dpp_or(double v, double keep) {
+  const long long b = __double_as_longlong(v), k = __double_as_longlong(keep);
+  const int lo = __builtin_amdgcn_update_dpp((int)(k & 0xffffffff), (int)(b & 0xffffffff), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(k >> 32), (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 __device__ inline double cp_lane(double v, int l) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), l);
@@ -386,12 +395,20 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
   // (lane 0 writes red[q][0]).  grid_reduce: publish red[q][0], barrier, every workgroup
   // adds all workgroups' sums in the same order into res[q].  Quantity q of either step
   // belongs to half-wavefront q mod NHW (one or two quantities each).
+  // QL lanes per summed quantity: a 16-lane row (512 threads) or a half-wavefront (1024), so
+  // that all CP_QMAX quantities are summed in one pass
+  constexpr int QL = REG ? 16 : 32;
+  static_assert(CP_QMAX * QL == TPB, "one lane group per summed quantity");
+  auto group_sum = [](double2 v) {
+    if constexpr (QL == 16) return mk(cp_row_sum(v.x), cp_row_sum(v.y));
+    else return cp_half_sum(v);
+  };
   auto wg_sums = [&](int nq, auto&& term) {
-    const int c = tid & 31;
-    for (int q = tid >> 5; q < nq; q += NHW) {
+    const int q = tid / QL, c = tid % QL;
+    if (q < nq) {
       double2 sm = mk(0.0, 0.0);
-      for (int e = c; e < ne; e += 32) sm = cadd(sm, term(q, e));
-      sm = cp_half_sum(sm);
+      for (int e = c; e < ne; e += QL) sm = cadd(sm, term(q, e));
+      sm = group_sum(sm);
       if (c == 0) red[q][0] = sm;
     }
   };
@@ -560,12 +577,12 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
       // h_i = V_i^H w (i <= j) and ||w||^2 in one reduction: half-wavefront q pairs w with V_q
       // (q <= j) or with itself (q = j + 1; the real part is ||w||^2)
       auto arn_dots = [&]() {
-        const int c = tid & 31;
-        for (int q = tid >> 5; q < j + 2; q += NHW) {
+        const int q = tid / QL, c = tid % QL;
+        if (q < j + 2) {
           const T* vq = q <= j ? Vb + q * vst : wl;
           double2 sm = mk(0.0, 0.0);
-          for (int e = c; e < ne; e += 32) cfmac(sm, to_d(vq[e]), to_d(wl[e]));
-          sm = cp_half_sum(sm);
+          for (int e = c; e < ne; e += QL) cfmac(sm, to_d(vq[e]), to_d(wl[e]));
+          sm = group_sum(sm);
           if (c == 0) red[q][0] = sm;
         }
       };
@@ -584,21 +601,47 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
       // loads entry l and rotation l, then the chain runs in every lane on values read from one
       // lane at a time (scalar registers, no LDS round trip per rotation); lane 0 stores
       auto givens = [&](const double2* src, double hn) {
+        // Rotation q maps the carried entry x_q and h_{q+1} to col[q] = c_q x_q + s_q h_{q+1}
+        // and x_{q+1} = c_q h_{q+1} - conj(s_q) x_q, an affine map of x_q.  The composed maps
+        // F_q = f_q o ... o f_0 come from an inclusive scan over lanes (rows of 16 by DPP
+        // shifts, then the second row composed with lane 15's), so every x_q is known after
+        // log2 steps instead of a chain of j rotations; lane q then forms col[q].
         double2* col = Hr + (mm + 1) * j;
-        const double2 hl = lane <= j ? src[lane] : mk(hn, 0.0);
-        const double cl = lane < j ? rc[lane] : 0.0;
-        const double2 sl = lane < j ? rs[lane] : mk(0.0, 0.0);
-        double2 x0 = cp_lane(hl, 0);
-        double2 x1 = cp_lane(hl, 1);
-        for (int q = 0; q < j; ++q) {
-          const double cq = cp_lane(cl, q);
-          const double2 sq = cp_lane(sl, q);
-          const double2 x2 = cp_lane(hl, q + 2);
-          const double2 out = cadd(cscale(x0, cq), cmul(sq, x1));
-          if (lane == 0) col[q] = out;
-          x0 = csub(cscale(x1, cq), cmul(cconj(sq), x0));
-          x1 = x2;
+        const double2 h0 = src[0];
+        const double2 hnext = lane + 1 <= j ? src[lane + 1] : mk(hn, 0.0);  // h_{lane+1}
+        const bool live = lane < j;
+        const double cl = live ? rc[lane] : 1.0;
+        const double2 sl = live ? rs[lane] : mk(0.0, 0.0);
+        double2 A = live ? mk(-sl.x, sl.y) : mk(1.0, 0.0);  // -conj(s)
+        double2 Bv = live ? cscale(hnext, cl) : mk(0.0, 0.0);
+        auto step = [&](auto ctrl) {
+          constexpr int C = decltype(ctrl)::value;
+          const double2 Ap = mk(cp_dpp_or<C>(A.x, 1.0), cp_dpp_or<C>(A.y, 0.0));
+          const double2 Bp = mk(cp_dpp_or<C>(Bv.x, 0.0), cp_dpp_or<C>(Bv.y, 0.0));
+          Bv = cadd(cmul(A, Bp), Bv);
+          A = cmul(A, Ap);
+        };
+        step(std::integral_constant<int, 0x111>{});  // row_shr 1
+        step(std::integral_constant<int, 0x112>{});  // row_shr 2
+        step(std::integral_constant<int, 0x114>{});  // row_shr 4
+        step(std::integral_constant<int, 0x118>{});  // row_shr 8
+        {
+          const double2 A15 = cp_lane(A, 15), B15 = cp_lane(Bv, 15);
+          if (lane >= 16) {
+            Bv = cadd(cmul(A, B15), Bv);
+            A = cmul(A, A15);
+          }
         }
+        // x_{lane+1} = F_lane(h_0); x_lane from the lane below (x_0 = h_0)
+        const double2 xn = cadd(cmul(A, h0), Bv);
+        double2 xq = mk(cp_dpp_or<0x111>(xn.x, h0.x), cp_dpp_or<0x111>(xn.y, h0.y));
+        {
+          const double2 x16 = cp_lane(xn, 15);
+          if (lane == 16) xq = x16;
+        }
+        if (live) col[lane] = cadd(cscale(xq, cl), cmul(sl, hnext));
+        const double2 x0 = j > 0 ? cp_lane(xn, j - 1) : h0;
+        const double2 x1 = mk(hn, 0.0);
         double c;
         double2 sg;
         cp_givens(x0, x1, c, sg);
