@@ -301,6 +301,44 @@ __device__ inline void cp_gather_sum2(const double2* P0, const double2* P1, int 
   s1 = cp_half_sum(a1);
 }
 
+// A chain of Givens rotations applied to one Hessenberg column by a wavefront.  Rotation l
+// (lane l < cnt, coefficients cl, sl) maps the carried entry x_l and the column entry
+// h_{l+1} (hnext) to out_l = c_l x_l + s_l h_{l+1} and x_{l+1} = c_l h_{l+1} - conj(s_l) x_l,
+// an affine map of x_l.  The composed maps come from an inclusive scan over lanes (rows of 16
+// by DPP shifts, then the second row composed with lane 15's), so the chain takes log2 steps
+// instead of cnt.  Returns x_l (the carry entering rotation l; x_0 = h0) in each lane and the
+// carry after all cnt rotations.  cnt <= 31; all lanes active.
+__device__ inline double2 cp_rotation_scan(int lane, int cnt, double2 h0, double cl, double2 sl, double2 hnext,
+                                           double2& xlast) {
+  const bool live = lane < cnt;
+  double2 A = live ? mk(-sl.x, sl.y) : mk(1.0, 0.0);  // -conj(s)
+  double2 Bv = live ? cscale(hnext, cl) : mk(0.0, 0.0);
+  auto step = [&](auto ctrl) {
+    constexpr int C = decltype(ctrl)::value;
+    const double2 Ap = mk(cp_dpp_or<C>(A.x, 1.0), cp_dpp_or<C>(A.y, 0.0));
+    const double2 Bp = mk(cp_dpp_or<C>(Bv.x, 0.0), cp_dpp_or<C>(Bv.y, 0.0));
+    Bv = cadd(cmul(A, Bp), Bv);
+    A = cmul(A, Ap);
+  };
+  step(std::integral_constant<int, 0x111>{});  // row_shr 1
+  step(std::integral_constant<int, 0x112>{});  // row_shr 2
+  step(std::integral_constant<int, 0x114>{});  // row_shr 4
+  step(std::integral_constant<int, 0x118>{});  // row_shr 8
+  {
+    const double2 A15 = cp_lane(A, 15), B15 = cp_lane(Bv, 15);
+    if (lane >= 16) {
+      Bv = cadd(cmul(A, B15), Bv);
+      A = cmul(A, A15);
+    }
+  }
+  const double2 xn = cadd(cmul(A, h0), Bv);  // x_{lane+1}
+  double2 xq = mk(cp_dpp_or<0x111>(xn.x, h0.x), cp_dpp_or<0x111>(xn.y, h0.y));
+  const double2 x16 = cp_lane(xn, 15);
+  if (lane == 16) xq = x16;
+  xlast = cnt > 0 ? cp_lane(xn, cnt - 1) : h0;
+  return xq;
+}
+
 __device__ inline void cp_givens(double2 a, double2 b, double& c, double2& s) {
   const double na = sqrt(cabs2(a)), nb = sqrt(cabs2(b));
   if (nb == 0.0) { c = 1.0; s = mk(0.0, 0.0); return; }
@@ -601,46 +639,15 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
       // loads entry l and rotation l, then the chain runs in every lane on values read from one
       // lane at a time (scalar registers, no LDS round trip per rotation); lane 0 stores
       auto givens = [&](const double2* src, double hn) {
-        // Rotation q maps the carried entry x_q and h_{q+1} to col[q] = c_q x_q + s_q h_{q+1}
-        // and x_{q+1} = c_q h_{q+1} - conj(s_q) x_q, an affine map of x_q.  The composed maps
-        // F_q = f_q o ... o f_0 come from an inclusive scan over lanes (rows of 16 by DPP
-        // shifts, then the second row composed with lane 15's), so every x_q is known after
-        // log2 steps instead of a chain of j rotations; lane q then forms col[q].
+        // rotations 0 .. j-1 on the column (h_0 .. h_j, hn) by a lane scan, then the new one
         double2* col = Hr + (mm + 1) * j;
         const double2 h0 = src[0];
         const double2 hnext = lane + 1 <= j ? src[lane + 1] : mk(hn, 0.0);  // h_{lane+1}
-        const bool live = lane < j;
-        const double cl = live ? rc[lane] : 1.0;
-        const double2 sl = live ? rs[lane] : mk(0.0, 0.0);
-        double2 A = live ? mk(-sl.x, sl.y) : mk(1.0, 0.0);  // -conj(s)
-        double2 Bv = live ? cscale(hnext, cl) : mk(0.0, 0.0);
-        auto step = [&](auto ctrl) {
-          constexpr int C = decltype(ctrl)::value;
-          const double2 Ap = mk(cp_dpp_or<C>(A.x, 1.0), cp_dpp_or<C>(A.y, 0.0));
-          const double2 Bp = mk(cp_dpp_or<C>(Bv.x, 0.0), cp_dpp_or<C>(Bv.y, 0.0));
-          Bv = cadd(cmul(A, Bp), Bv);
-          A = cmul(A, Ap);
-        };
-        step(std::integral_constant<int, 0x111>{});  // row_shr 1
-        step(std::integral_constant<int, 0x112>{});  // row_shr 2
-        step(std::integral_constant<int, 0x114>{});  // row_shr 4
-        step(std::integral_constant<int, 0x118>{});  // row_shr 8
-        {
-          const double2 A15 = cp_lane(A, 15), B15 = cp_lane(Bv, 15);
-          if (lane >= 16) {
-            Bv = cadd(cmul(A, B15), Bv);
-            A = cmul(A, A15);
-          }
-        }
-        // x_{lane+1} = F_lane(h_0); x_lane from the lane below (x_0 = h_0)
-        const double2 xn = cadd(cmul(A, h0), Bv);
-        double2 xq = mk(cp_dpp_or<0x111>(xn.x, h0.x), cp_dpp_or<0x111>(xn.y, h0.y));
-        {
-          const double2 x16 = cp_lane(xn, 15);
-          if (lane == 16) xq = x16;
-        }
-        if (live) col[lane] = cadd(cscale(xq, cl), cmul(sl, hnext));
-        const double2 x0 = j > 0 ? cp_lane(xn, j - 1) : h0;
+        const double cl = lane < j ? rc[lane] : 1.0;
+        const double2 sl = lane < j ? rs[lane] : mk(0.0, 0.0);
+        double2 x0;
+        const double2 xq = cp_rotation_scan(lane, j, h0, cl, sl, hnext, x0);
+        if (lane < j) col[lane] = cadd(cscale(xq, cl), cmul(sl, hnext));
         const double2 x1 = mk(hn, 0.0);
         double c;
         double2 sg;
@@ -780,7 +787,7 @@ struct CAArgs {
 };
 
 struct CALayout {
-  size_t Vb, xs, part, wl, hcol, red, res, rc, rs, rp, g, tot;
+  size_t Vb, xs, part, wl, hcol, red, res, rc, rs, rp, g, q0, tot;
   __host__ __device__ CALayout(int spw, int m) {
     const size_t ne = (size_t)spw * NC;
     size_t o = 0;
@@ -796,6 +803,7 @@ struct CALayout {
     rs = take((size_t)CA_NROT * sizeof(double2));
     rp = take((size_t)CA_NROT * sizeof(int));
     g = take((size_t)(m + 2) * sizeof(double2));
+    q0 = take((size_t)m * m * sizeof(double2));  // product of the entry rotations, (j0 + 1)^2 <= m^2
     tot = o;
   }
 };
@@ -825,6 +833,7 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_arnoldi(CAArgs a) {
   double2* rs = (double2*)(smem + L.rs);
   int* rp = (int*)(smem + L.rp);
   double2* gl = (double2*)(smem + L.g);
+  double2* Q0 = (double2*)(smem + L.q0);
   __shared__ double sh_est;
   KState* ks = a.ks;
   double2* xch = a.xchg;
@@ -869,6 +878,19 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_arnoldi(CAArgs a) {
     Vb[t] = a.V[(int64_t)i * n + e0 + e];
   }
   __syncthreads();
+  // Q0 = product of the rotations held on entry (they act on rows 0 .. j0 only): thread l
+  // carries e_l through them, so every new column needs one (j0+1) x (j0+1) product instead of
+  // a chain of nrot0 rotations
+  const int n0 = j0 + 1;
+  if (tid < n0) {
+    for (int i = 0; i < n0; ++i) Q0[i + n0 * tid] = mk(i == tid ? 1.0 : 0.0, 0.0);
+    for (int q = 0; q < nrot0; ++q) {
+      const int p = rp[q];
+      const double2 x0 = Q0[p + n0 * tid], x1 = Q0[p + 1 + n0 * tid];
+      Q0[p + n0 * tid] = cadd(cscale(x0, rc[q]), cmul(rs[q], x1));
+      Q0[p + 1 + n0 * tid] = csub(cscale(x1, rc[q]), cmul(cconj(rs[q]), x0));
+    }
+  }
   for (int t = tid; t < ne; t += CP_THREADS) cp_store(&xch[e0 + t], Vb[j0 * ne + t]);
   dead = dead || cp_barrier(a.flags, G, ++gen, a.err);
 
@@ -943,39 +965,64 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_arnoldi(CAArgs a) {
     }
     if (tid <= j) hcol[tid] = cadd(hcol[tid], res[tid]);
     __syncthreads();
-    // Givens update on one thread of the last wavefront (overlaps the vector update below)
-    if (tid == CP_THREADS - 64) {
+    // Givens update on the last wavefront (overlaps the vector update below): rows 0 .. j0 of
+    // the column through the entry rotations (Q0), then this cycle's rotations at positions
+    // j0 .. j-1 by a lane scan, then the new rotation
+    if (tid >= CP_THREADS - 64) {
+      const int lane = tid & 63;
       double2* col = hcol;  // rotated in place (no other thread reads it until the next column)
-      col[j + 1] = mk(hn, 0.0);
-      if (gi == 0) {
-        for (int i = 0; i <= MMAX; ++i) ks->H[LDK * j + i] = (i <= j) ? col[i] : (i == j + 1 ? col[j + 1] : mk(0.0, 0.0));
+      const double2 hl = lane <= j ? col[lane] : (lane == j + 1 ? mk(hn, 0.0) : mk(0.0, 0.0));
+      if (gi == 0)
+        for (int i = lane; i <= MMAX; i += 64) ks->H[LDK * j + i] = (i <= j) ? col[i] : (i == j + 1 ? mk(hn, 0.0) : mk(0.0, 0.0));
+      double2 y = hl;
+      if (lane < n0) {
+        y = mk(0.0, 0.0);
+        for (int l = 0; l < n0; ++l) cfma(y, Q0[lane + n0 * l], col[l]);
       }
-      for (int q = 0; q < nrot; ++q) {
-        const int p = rp[q];
-        if (p + 1 > j + 1) continue;
-        const double2 x0 = col[p], x1 = col[p + 1];
-        col[p] = cadd(cscale(x0, rc[q]), cmul(rs[q], x1));
-        col[p + 1] = csub(cscale(x1, rc[q]), cmul(cconj(rs[q]), x0));
-      }
+      const int cnt = j - j0;  // this cycle's earlier rotations
+      const int q = nrot0 + lane;
+      const double cl = lane < cnt ? rc[q] : 1.0;
+      const double2 sl = lane < cnt ? rs[q] : mk(0.0, 0.0);
+      const double2 hnext = j0 + lane + 1 <= j ? col[j0 + lane + 1] : mk(hn, 0.0);
+      double2 x0;
+      const double2 xq = cp_rotation_scan(lane, cnt, cp_lane(y, j0), cl, sl, hnext, x0);
+      const double2 x1 = mk(hn, 0.0);
       double c;
       double2 sg;
-      cp_givens(col[j], col[j + 1], c, sg);
-      col[j] = cadd(cscale(col[j], c), cmul(sg, col[j + 1]));
-      col[j + 1] = mk(0.0, 0.0);
-      rc[nrot] = c;
-      rs[nrot] = sg;
-      rp[nrot] = j;
-      const double2 g0 = gl[j], g1 = gl[j + 1];
-      gl[j] = cadd(cscale(g0, c), cmul(sg, g1));
-      gl[j + 1] = csub(cscale(g1, c), cmul(cconj(sg), g0));
-      sh_est = sqrt(cabs2(gl[j + 1]));
+      cp_givens(x0, x1, c, sg);
+      // the rotated column: rows < j0 from Q0, rows j0 .. j-1 from the scan (scan lane l holds
+      // row j0 + l), row j from the new rotation; every lane read col above
+      const double2 o = cadd(cscale(xq, cl), cmul(sl, hnext));
+      const double2 rj = cadd(cscale(x0, c), cmul(sg, x1));
+      if (lane < j0) col[lane] = y;
+      if (lane < cnt) col[j0 + lane] = o;
+      if (lane == 0) {
+        col[j] = rj;
+        col[j + 1] = mk(0.0, 0.0);
+      }
       if (gi == 0) {
-        for (int i = 0; i <= j + 1; ++i) ks->R[LDK * j + i] = col[i];
-        ks->g[j] = gl[j];
-        ks->g[j + 1] = gl[j + 1];
-        ks->rot_c[nrot] = c;
-        ks->rot_s[nrot] = sg;
-        ks->rot_p[nrot] = j;
+        if (lane < j0) ks->R[LDK * j + lane] = y;
+        if (lane < cnt) ks->R[LDK * j + j0 + lane] = o;
+        if (lane == 0) {
+          ks->R[LDK * j + j] = rj;
+          ks->R[LDK * j + j + 1] = mk(0.0, 0.0);
+        }
+      }
+      if (lane == 0) {
+        rc[nrot] = c;
+        rs[nrot] = sg;
+        rp[nrot] = j;
+        const double2 g0 = gl[j], g1 = gl[j + 1];
+        gl[j] = cadd(cscale(g0, c), cmul(sg, g1));
+        gl[j + 1] = csub(cscale(g1, c), cmul(cconj(sg), g0));
+        sh_est = sqrt(cabs2(gl[j + 1]));
+        if (gi == 0) {
+          ks->g[j] = gl[j];
+          ks->g[j + 1] = gl[j + 1];
+          ks->rot_c[nrot] = c;
+          ks->rot_s[nrot] = sg;
+          ks->rot_p[nrot] = j;
+        }
       }
     }
     // v_{j+1} = (w - V h2) / hn
