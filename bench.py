@@ -34,10 +34,10 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 RHS_PER_CONFIG = 5
-# HBM bytes per launch of k_coarse_proj<double, false, true> from the FETCH_SIZE and WRITE_SIZE counter
+# HBM bytes per launch of k_coarse_proj<double, false, true, true> from the FETCH_SIZE and WRITE_SIZE counter
 # passes (scaled by the reference streaming kernels) recorded in profiles/k_coarse_proj_256_hbm_traffic.md;
 # valid while that kernel is unchanged
-COARSE_TRAFFIC_BYTES = 68_675_891
+COARSE_TRAFFIC_BYTES = 64_496_742
 
 
 def parse():
@@ -243,7 +243,7 @@ def main():
 
 
 def coarse_roofline(N, total_ms, launches, steps, timed_s):
-    """Roofline of the persistent coarse GMRES-Proj kernel (k_coarse_proj<double, false, true>),
+    """Roofline of the persistent coarse GMRES-Proj kernel (k_coarse_proj<double, false, true, true>),
     the kernel with the largest share of the timed region.  Algorithmic bytes: every
     Arnoldi step applies the coarse operator once, reading its 5 blocks of 24 x 24
     complex doubles per coarse site (46,080 B per site; Krylov and deflation slices stay
@@ -252,7 +252,7 @@ def coarse_roofline(N, total_ms, launches, steps, timed_s):
     bytes_per_step = sites * 5 * 24 * 24 * 16
     achieved = steps * bytes_per_step / (total_ms * 1e-3) / 1e9 if total_ms > 0 else 0.0
     per_launch = steps / max(launches, 1) * bytes_per_step
-    return {"kernel": "k_coarse_proj<double, false, true> (persistent GMRES-Proj, halo form, coarse grid "
+    return {"kernel": "k_coarse_proj<double, false, true, true> (persistent GMRES-Proj, halo form, blocks in registers, coarse grid "
                       f"{N // 16}x{N // 16} sites x 24 dof)",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
