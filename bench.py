@@ -263,7 +263,7 @@ def coarse_roofline(N, total_ms, launches, steps, timed_s):
             "arnoldi_steps": steps, "us_per_step": total_ms * 1e3 / max(steps, 1),
             "algorithmic_bytes_per_step": bytes_per_step,
             "share_of_timed_region": total_ms * 1e-3 / timed_s if timed_s > 0 else None,
-            "note": "latency bound: two grid barriers per Arnoldi step"}
+            "note": "latency bound: one grid barrier per Arnoldi step"}
 
 
 def measure_stencil_roofline(torch, dmg, ctx, h, N, reps=200):
