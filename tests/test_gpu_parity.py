@@ -401,3 +401,33 @@ def test_persistent_coarse_matches_multikernel(dmg, ctx, injected, precond):
         assert abs(out[1][1][j]["outer_iters"] - out[0][1][j]["outer_iters"]) <= 1
         c0, c1 = out[0][1][j]["coarse_mvps"], out[1][1][j]["coarse_mvps"]
         assert abs(c1 - c0) <= 0.1 * c0 + 5
+
+
+@pytest.mark.parametrize("N", [256, 512])
+def test_persistent_coarse_forms_workload(dmg, ctx, N):
+    """At the workload sizes the one-launch coarse solves take their other forms: at 256^2 the
+    halo form with the blocks in registers (4 coarse sites per workgroup, a 10-site halo) and
+    the GMRES-DR Arnoldi launch with the restart block's rotations as one matrix; at 512^2 the
+    two-barrier form (10 sites per workgroup).  Each must give the kernel-per-step solution:
+    the same true residual bound against the oracle's D, the solution within 1e-6, the same
+    outer iteration count within one."""
+    cfg = 1
+    th = synth.gauge_angles(N, cfg)
+    m0 = synth.bare_mass(N, cfg)
+    g = dmg.Gauge(ctx, th)
+    hg = dmg.Hierarchy(ctx, g, m0, synth.near_null_starts(N, cfg, 0), synth.near_null_starts(N, cfg, 1))
+    D = wilson.dirac_matrix(th, m0)
+    out = {}
+    for persistent in (0, 1):
+        d = dmg.Deflation(hg, 30, 10)
+        xs, ss = [], []
+        for j in range(2):
+            b = synth.rhs(N, cfg, j)
+            st, s, x, res = _solve_and_check(dmg, ctx, hg, D, b, d, coarse_persistent=persistent)
+            assert st == dmg.DMG_OK and res <= 1e-8, (persistent, j, res)
+            xs.append(x)
+            ss.append(s)
+        out[persistent] = (xs, ss)
+    for j in range(2):
+        assert _rel(out[1][0][j], out[0][0][j]) < 1e-6
+        assert abs(out[1][1][j]["outer_iters"] - out[0][1][j]["outer_iters"]) <= 1
