@@ -210,6 +210,52 @@ __device__ void qr_block_lds(KState* ks, int k, double2* scratch) {
   __syncthreads();
 }
 
+// qr_block_serial's rotations with one lane per column of [R | g] ((k+1) x (k+1), k + 1 <= 64):
+// for each rotation every lane updates rows p, p+1 of its own column, the rotation itself from
+// column jc's entries (read by all lanes); the same rotations in the same order.
+__device__ void qr_block_wave(KState* ks, int k, double2* Rq) {
+  const int t = threadIdx.x;
+  const int K1 = k + 1;
+  for (int e = t; e < K1 * k; e += DW) Rq[e] = ks->H[(e % K1) + LD * (e / K1)];
+  for (int i = t; i < K1; i += DW) Rq[K1 * k + i] = ks->c[i];  // column k: g
+  __shared__ double rcq[QRL_MAXROT];
+  __shared__ double2 rsq[QRL_MAXROT];
+  __shared__ int rpq[QRL_MAXROT];
+  __syncthreads();
+  int q = 0;
+  for (int jc = 0; jc < k; ++jc)
+    for (int r = k; r > jc; --r) {
+      double c;
+      double2 sg;
+      make_givens(Rq[r - 1 + K1 * jc], Rq[r + K1 * jc], c, sg);
+      if (t >= jc && t <= k) {
+        double2* col = Rq + K1 * t;
+        const double2 a = col[r - 1], b = col[r];
+        col[r - 1] = cadd(cscale(a, c), cmul(sg, b));
+        col[r] = (t == jc) ? mk(0.0, 0.0) : csub(cscale(b, c), cmul(cconj(sg), a));
+      }
+      if (t == 0) {
+        rcq[q] = c;
+        rsq[q] = sg;
+        rpq[q] = r - 1;
+      }
+      ++q;
+    }
+  __syncthreads();
+  for (int e = t; e < K1 * k; e += DW) ks->R[(e % K1) + LD * (e / K1)] = Rq[e];
+  for (int i = t; i <= MMAX; i += DW) ks->g[i] = (i <= k) ? Rq[K1 * k + i] : mk(0.0, 0.0);
+  for (int i = t; i < q; i += DW) {
+    ks->rot_c[i] = rcq[i];
+    ks->rot_s[i] = rsq[i];
+    ks->rot_p[i] = rpq[i];
+  }
+  if (t == 0) {
+    ks->nrot = q;
+    ks->est = cabs_(Rq[K1 * k + k]);
+  }
+  __syncthreads();
+}
+
 __global__ void k_qr_block(KState* ks, int k) {
   if (threadIdx.x == 0) qr_block_serial(ks, k);
 }
@@ -568,18 +614,29 @@ __global__ void __launch_bounds__(DW) k_dr_restart(KState* ks, int m, int k, dou
   hessenberg(A, X, v, m);
   if (schur_qr(A, X, m, nullptr)) { if (t == 0) *status = 3; return; }
   __syncthreads();
-  // eigenvalues and the order: key (round(|theta| / max|theta|, 12), Im theta, index)
-  for (int i = t; i < m; i += DW) theta[i] = A[i + m * i];
+  // eigenvalues and the order: key (round(|theta| / max|theta|, 12), Im theta, index); lane e
+  // forms its modulus and key once (m <= 64), the maximum is a wavefront max
+  __shared__ double keys[DW];
+  {
+    const double2 th = t < m ? A[t + m * t] : mk(0.0, 0.0);
+    if (t < m) theta[t] = th;
+    const double ab = t < m ? cabs_(th) : 0.0;
+    double mx = ab;
+    mx = fmax(mx, dpp_d<0xB1>(mx));
+    mx = fmax(mx, dpp_d<0x4E>(mx));
+    mx = fmax(mx, dpp_d<0x124>(mx));
+    mx = fmax(mx, dpp_d<0x128>(mx));
+    mx = fmax(fmax(rd_lane(mx, 0), rd_lane(mx, 16)), fmax(rd_lane(mx, 32), rd_lane(mx, 48)));
+    if (mx == 0.0) mx = 1e-300;
+    keys[t] = rint(ab / mx * 1e12);
+  }
   __syncthreads();
-  double mx = 0.0;
-  for (int i = 0; i < m; ++i) mx = fmax(mx, cabs_(theta[i]));
-  if (mx == 0.0) mx = 1e-300;
   for (int e = t; e < m; e += DW) {
-    const double ke = rint(cabs_(theta[e]) / mx * 1e12);
+    const double ke = keys[e];
     int rank = 0;
     for (int o = 0; o < m; ++o) {
       if (o == e) continue;
-      const double ko = rint(cabs_(theta[o]) / mx * 1e12);
+      const double ko = keys[o];
       const bool less = (ko < ke) || (ko == ke && (theta[o].y < theta[e].y || (theta[o].y == theta[e].y && o < e)));
       rank += less ? 1 : 0;
     }
@@ -588,7 +645,11 @@ __global__ void __launch_bounds__(DW) k_dr_restart(KState* ks, int m, int k, dou
   __syncthreads();
   // eigenvectors of the triangular T = A for the selected values, into T1 columns (length m)
   double tn = 0.0;
-  for (int e = 0; e < m * m; ++e) tn += cabs2(A[e]);
+  {
+    double part = 0.0;
+    for (int e = t; e < m * m; e += DW) part += cabs2(A[e]);
+    tn = wave_sum(part);
+  }
   const double smin = fmax(sqrt(tn) * 2.220446049250313e-16, 1e-300);
   for (int q = t; q < k; q += DW) {
     const int e = sel[q];
@@ -665,7 +726,10 @@ __global__ void __launch_bounds__(DW) k_dr_restart(KState* ks, int m, int k, dou
   for (int e = t; e < (m + 1) * (k + 1); e += DW) Pout[e] = W[e];
   __syncthreads();
   __syncthreads();
-  if (!final_mode) qr_block_lds(ks, k, A);  // A is free again: scratch for the block QR
+  if (!final_mode) {  // A is free again: scratch for the block QR
+    if (k + 1 <= DW && k * (k + 1) / 2 <= QRL_MAXROT) qr_block_wave(ks, k, A);
+    else qr_block_lds(ks, k, A);
+  }
   if (t == 0) {
     ks->steps = k;
     ks->done = 0;
