@@ -586,21 +586,29 @@ __global__ void __launch_bounds__(DW) k_dr_restart(KState* ks, int m, int k, dou
       if (t == 0) { const double2 tmp = v[p]; v[p] = v[piv]; v[piv] = tmp; }
     }
     __syncthreads();
+    // multipliers (lane i), then the rank-one update of the trailing block element by element
+    // (column p below the pivot is not read again)
+    __shared__ double2 fct[DW];
     const double2 dp = A[p + m * p];
-    for (int i = p + 1 + t; i < m; i += DW) {
-      const double2 fct = cdiv(A[i + m * p], dp);
-      for (int jc = p; jc < m; ++jc) A[i + m * jc] = csub(A[i + m * jc], cmul(fct, A[p + m * jc]));
-      v[i] = csub(v[i], cmul(fct, v[p]));
+    if (t > p && t < m) {
+      const double2 fi = cdiv(A[t + m * p], dp);
+      fct[t] = fi;
+      v[t] = csub(v[t], cmul(fi, v[p]));
+    }
+    __syncthreads();
+    const int rows = m - p - 1;
+    for (int e = t; e < rows * rows; e += DW) {
+      const int i = p + 1 + e % rows, jc = p + 1 + e / rows;
+      A[i + m * jc] = csub(A[i + m * jc], cmul(fct[i], A[p + m * jc]));
     }
     __syncthreads();
   }
   if (fail) { if (t == 0) *status = 2; return; }
-  if (t == 0) {
-    for (int i = m - 1; i >= 0; --i) {
-      double2 acc = v[i];
-      for (int l = i + 1; l < m; ++l) acc = csub(acc, cmul(A[i + m * l], f[l]));
-      f[i] = cdiv(acc, A[i + m * i]);
-    }
+  // back substitution by columns: f_i from row i, then every row above drops its term
+  for (int i = m - 1; i >= 0; --i) {
+    const double2 fi = cdiv(rd_lane(i == t ? v[t] : mk(0.0, 0.0), i), A[i + m * i]);
+    if (t == 0) f[i] = fi;
+    if (t < i) v[t] = csub(v[t], cmul(A[t + m * i], fi));
   }
   __syncthreads();
   // G = H + |h|^2 f e_m^T into A
