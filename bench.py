@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--serve-configs", type=int, default=4, help="resident configurations per lattice size")
     ap.add_argument("--serve-requests", type=int, default=200, help="requests per arrival rate")
     ap.add_argument("--serve-capacity", type=int, default=16, help="lanes per resident configuration")
+    ap.add_argument("--serve-lane-min", type=int, default=4,
+                    help="waiting requests of an idle configuration that start its lane batch (fewer: single-RHS)")
     ap.add_argument("--scan", action="store_true",
                     help="mass-gap and lattice-size scan of six solvers with power-law fits (prints its own JSON)")
     ap.add_argument("--scan-sizes", default="64,128,256")
@@ -198,7 +200,7 @@ def main():
     out_served = None
     if not a.no_serve:
         out_served = served_form(torch, dmg, ctx, [int(v) for v in a.serve_sizes.split(",")], a.serve_configs,
-                                 a.serve_requests, a.serve_capacity, n_solves / el64)
+                                 a.serve_requests, a.serve_capacity, n_solves / el64, a.serve_lane_min)
 
     # ------------------------------------------------------------ CPU baseline (oracle)
     cpu = None
@@ -440,7 +442,7 @@ def batched_wilson_roofline(torch, dmg, ctx, h, N, nrhs, reps=50):
             "avg_launch_us": avg * 1e3, "algorithmic_bytes_per_launch": byts}
 
 
-def served_form(torch, dmg, ctx, sizes, ncfg, n_req, cap, plain_rate):
+def served_form(torch, dmg, ctx, sizes, ncfg, n_req, cap, plain_rate, lane_min=4):
     """Serving: single-RHS requests, each naming one of the resident configurations
     (every size in `sizes` x configurations 0..ncfg-1, hierarchy and deflation space kept
     on the device), arrive as a seeded Poisson stream; each configuration has a lane
@@ -486,7 +488,6 @@ def served_form(torch, dmg, ctx, sizes, ncfg, n_req, cap, plain_rate):
         busy = {k: {} for k in keys}
         lat, bad = [], 0
         nxt, done = 0, 0
-        lane_min = 4
         t_start = time.perf_counter()
 
         def finish(i, s):
