@@ -17,12 +17,15 @@
 // that precedes the flag store, so the flags need no cache write-back or
 // invalidation.  Its cost grows slowly with the number of
 // workgroups, unlike a single atomic counter whose arrivals serialise; hence few,
-// larger workgroups.  An Arnoldi step costs two barriers: one to exchange v_j for
-// the stencil, one for the Gram-Schmidt reduction.  The orthogonalisation is
-// classical Gram-Schmidt with the norm from ||w||^2 - ||h||^2; when that
-// difference shows more than 99.99 % cancellation a second pass with an exact
-// norm is taken (one more barrier).  In exact arithmetic this is the Arnoldi
-// process of GMRES; the oracle uses modified Gram-Schmidt twice.
+// larger workgroups.  In the two-barrier form an Arnoldi step exchanges v_j for the
+// stencil and then reduces the Gram-Schmidt dots; the halo form (k_coarse_proj's HALO)
+// keeps the basis on each workgroup's halo sites as well and needs only the reduction
+// barrier, and its 512-thread variant (REG) keeps the blocks in registers.  The
+// orthogonalisation is classical Gram-Schmidt with the norm from ||w||^2 - ||h||^2; when
+// that difference shows more than 99.99 % cancellation a second pass with an exact norm
+// is taken (one more barrier).  The Givens rotations of each new Hessenberg column come
+// from a lane scan (cp_rotation_scan).  In exact arithmetic this is the Arnoldi process of
+// GMRES; the oracle uses modified Gram-Schmidt twice.
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -34,8 +37,6 @@
 namespace dmg {
 
 constexpr int CP_THREADS = 1024;  // 16 wavefronts: enough loads in flight to stream the blocks
-constexpr int CP_WAVES = CP_THREADS / 64;
-constexpr int CP_RWAVES = 4;    // wavefronts holding the local entries (<= 240 of them)
 constexpr int CP_QMAX = 32;     // quantities per reduction
 
 struct CPArgs {
@@ -202,7 +203,7 @@ struct CPLayout {
     Hk = take((size_t)(k + 1) * k * sizeof(double2));        // M
     Rk = take((size_t)(k + 1) * (k + 1) * sizeof(double2));  // Pi
     kc = ks = kp = 0;
-    red = take((size_t)CP_QMAX * CP_RWAVES * sizeof(double2));
+    red = take((size_t)CP_QMAX * sizeof(double2));
     cs = part;  // chunk sums reuse the stencil partials (never live at the same time)
     res = take((size_t)(CP_QMAX + 2) * sizeof(double2));
     tot = o;
@@ -394,7 +395,7 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
   double2* uv = (double2*)(smem + L.u);
   double2* Mk = (double2*)(smem + L.Hk);
   double2* Pk = (double2*)(smem + L.Rk);
-  double2(*red)[CP_RWAVES] = (double2(*)[CP_RWAVES])(smem + L.red);
+  double2* red = (double2*)(smem + L.red);
   double2* res = (double2*)(smem + L.res);
   int* loc = (int*)(smem + L.loc);
   int* hsite = (int*)(smem + L.hs);
@@ -428,13 +429,12 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
   };
 
   // ---------------------------------------------------------------- reduction helpers
-  // wg_sums: per-workgroup sums of nq quantities, term(q, e) over the local entries e;
-  // the 32 lanes of half-wavefront q add every 32nd entry, then the half-wavefront tree
-  // (lane 0 writes red[q][0]).  grid_reduce: publish red[q][0], barrier, every workgroup
-  // adds all workgroups' sums in the same order into res[q].  Quantity q of either step
-  // belongs to half-wavefront q mod NHW (one or two quantities each).
-  // QL lanes per summed quantity: a 16-lane row (512 threads) or a half-wavefront (1024), so
-  // that all CP_QMAX quantities are summed in one pass
+  // wg_sums: per-workgroup sums of nq quantities, term(q, e) over the local entries e; the QL
+  // lanes of group q (a 16-lane row with 512 threads, a half-wavefront with 1024, so all
+  // CP_QMAX quantities are summed in one pass) add every QL-th entry, then a fixed DPP tree
+  // (lane 0 of the group writes red[q]).  grid_reduce: publish red[q], barrier, every
+  // workgroup adds all workgroups' sums in the same order into res[q] (half-wavefront q mod
+  // NHW gathers one or two quantities).
   constexpr int QL = REG ? 16 : 32;
   static_assert(CP_QMAX * QL == TPB, "one lane group per summed quantity");
   auto group_sum = [](double2 v) {
@@ -447,13 +447,13 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
       double2 sm = mk(0.0, 0.0);
       for (int e = c; e < ne; e += QL) sm = cadd(sm, term(q, e));
       sm = group_sum(sm);
-      if (c == 0) red[q][0] = sm;
+      if (c == 0) red[q] = sm;
     }
   };
   auto grid_reduce = [&](int nq, int halo_half = -1) {
     __syncthreads();
     double2* P = a.partials + (size_t)rbuf * CP_QMAX * G;
-    if (tid < nq) cp_store(&P[(size_t)tid * G + gi], red[tid][0]);
+    if (tid < nq) cp_store(&P[(size_t)tid * G + gi], red[tid]);
     dead = dead || cp_barrier(a.flags, G, ++gen, a.err);
     const int q = tid >> 5, c = tid & 31;
     if (NHW < CP_QMAX && q + NHW < nq) {
@@ -621,7 +621,7 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
           double2 sm = mk(0.0, 0.0);
           for (int e = c; e < ne; e += QL) cfmac(sm, to_d(vq[e]), to_d(wl[e]));
           sm = group_sum(sm);
-          if (c == 0) red[q][0] = sm;
+          if (c == 0) red[q] = sm;
         }
       };
       // w -= sum_{i <= j} res_i V_i on the own (and halo) entries
@@ -1094,10 +1094,6 @@ int launch_coarse_arnoldi(hipStream_t st, const double2* A, int Lx, int Lt, doub
   return 1;
 }
 
-size_t coarse_proj_lds(int spw, int mm, int k, size_t es, int a_in_lds) {
-  return CPLayout(spw, mm, k, es, a_in_lds).tot;
-}
-
 // DMG_COARSE_HALO=0 selects the two-barrier form (the same solve up to rounding order).
 static bool cp_halo_enabled() {
   static const int on = [] {
@@ -1197,7 +1193,6 @@ int launch_coarse_proj(hipStream_t st, const cx<R>* A, int Lx, int Lt, const cx<
   if (spw > 10) spw = 10;  // one thread per local entry
   const int G = (V + spw - 1) / spw;
   if (G > CP_GMAX || (size_t)2 * CP_QMAX * G > partials_elems || (size_t)CP_FLAGPAD * G > flag_words) return 0;
-  static_assert(CP_RWAVES * 64 >= 10 * NC, "local entries must sit in the reducing wavefronts");
   static_assert(CP_QMAX * 32 == CP_THREADS, "one half-wavefront per reduced quantity");
   // own + halo sites of the largest halo (same routine as the kernel)
   int nl = 0;
