@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--serve-capacity", type=int, default=16, help="lanes per resident configuration")
     ap.add_argument("--serve-lane-min", type=int, default=4,
                     help="waiting requests of an idle configuration that start its lane batch (fewer: single-RHS)")
+    ap.add_argument("--serve-serial", action="store_true",
+                    help="step the lane batches one after another instead of at once (one host thread each)")
     ap.add_argument("--scan", action="store_true",
                     help="mass-gap and lattice-size scan of six solvers with power-law fits (prints its own JSON)")
     ap.add_argument("--scan-sizes", default="64,128,256")
@@ -200,7 +202,8 @@ def main():
     out_served = None
     if not a.no_serve:
         out_served = served_form(torch, dmg, ctx, [int(v) for v in a.serve_sizes.split(",")], a.serve_configs,
-                                 a.serve_requests, a.serve_capacity, n_solves / el64, a.serve_lane_min)
+                                 a.serve_requests, a.serve_capacity, n_solves / el64, a.serve_lane_min,
+                                 not a.serve_serial)
 
     # ------------------------------------------------------------ CPU baseline (oracle)
     cpu = None
@@ -442,15 +445,16 @@ def batched_wilson_roofline(torch, dmg, ctx, h, N, nrhs, reps=50):
             "avg_launch_us": avg * 1e3, "algorithmic_bytes_per_launch": byts}
 
 
-def served_form(torch, dmg, ctx, sizes, ncfg, n_req, cap, plain_rate, lane_min=4):
+def served_form(torch, dmg, ctx, sizes, ncfg, n_req, cap, plain_rate, lane_min=4, concurrent=True):
     """Serving: single-RHS requests, each naming one of the resident configurations
     (every size in `sizes` x configurations 0..ncfg-1, hierarchy and deflation space kept
     on the device), arrive as a seeded Poisson stream; each configuration has a lane
     batch (dmg_batch_*, FP32 preconditioner) that requests join and leave between outer
     cycles.  The host loop admits waiting requests into free lanes (configurations with
     running lanes or a queue of at least four), steps those batches one outer cycle each
-    in turn and retires finished lanes; when no batch runs, the oldest waiting request is
-    solved on its own (dmg_solve).  Latency = arrival to result ready.  The saturated rate (all requests at t = 0) sets
+    (at once from a thread per batch, each batch on its own stream; one after another
+    with concurrent=False) and retires finished lanes; when no batch runs, the oldest
+    waiting request is solved on its own (dmg_solve).  Latency = arrival to result ready.  The saturated rate (all requests at t = 0) sets
     the three arrival rates, 0.5x, 0.9x and 1.2x of it."""
     import synth
 
@@ -478,17 +482,23 @@ def served_form(torch, dmg, ctx, sizes, ncfg, n_req, cap, plain_rate, lane_min=4
                 for i, p in enumerate(picks)], rng
 
     xout = {k: torch.empty(2 * k[0] * k[0], dtype=torch.complex128, device="cuda") for k in keys}
+    from concurrent.futures import FIRST_COMPLETED, ThreadPoolExecutor, wait as futures_wait
+    workers = ThreadPoolExecutor(max_workers=len(keys)) if concurrent else None
 
     def serve(reqs, arrivals):
         """Requests of a configuration with at least `lane_min` waiting (or already running
         lanes) go through its lane batch; a configuration with fewer waiting requests gets
-        its oldest request solved on its own (single-RHS path), so that sparse traffic is
-        not charged a whole lockstep step per request."""
+        its oldest request solved on its own (single-RHS path, only while no batch step is
+        in flight), so that sparse traffic is not charged a whole lockstep step per request.
+        With the worker threads each batch's step runs on its own; a batch whose step ended
+        is retired and refilled at once while the others go on."""
         queues = {k: [] for k in keys}
         busy = {k: {} for k in keys}
+        inflight = {}
         lat, bad = [], 0
         nxt, done = 0, 0
         t_start = time.perf_counter()
+        cur = torch.cuda.current_stream()  # the context's stream
 
         def finish(i, s):
             nonlocal bad, done
@@ -496,14 +506,27 @@ def served_form(torch, dmg, ctx, sizes, ncfg, n_req, cap, plain_rate, lane_min=4
             bad += 0 if (s["converged"] and s["true_rel_resid"] <= 1e-8) else 1
             done += 1
 
+        def retire_done(k):
+            bt = batches[k]
+            for sl in list(busy[k]):
+                if bt.state(sl) == dmg.SLOT_DONE:
+                    i = busy[k].pop(sl)
+                    st, s = bt.retire(sl, xout[k])
+                    cur.synchronize()  # the solution is in xout
+                    finish(i, s)
+
         while done < len(reqs):
             now = time.perf_counter() - t_start
             while nxt < len(reqs) and arrivals[nxt] <= now:
                 queues[reqs[nxt][0]].append(nxt)
                 nxt += 1
+            for k in [k for k, f in inflight.items() if f.done()]:
+                inflight.pop(k).result()
+                retire_done(k)
             # lane batches: configurations with running lanes, or enough waiting requests
-            stepped = False
             for k in keys:
+                if k in inflight:
+                    continue
                 bt = batches[k]
                 if busy[k] or len(queues[k]) >= lane_min:
                     for sl in range(cap):
@@ -515,15 +538,17 @@ def served_form(torch, dmg, ctx, sizes, ncfg, n_req, cap, plain_rate, lane_min=4
                             busy[k][sl] = i
                 if not busy[k]:
                     continue
-                bt.step(1)
-                stepped = True
-                for sl in list(busy[k]):
-                    if bt.state(sl) == dmg.SLOT_DONE:
-                        i = busy[k].pop(sl)
-                        st, s = bt.retire(sl, xout[k])
-                        torch.cuda.synchronize()
-                        finish(i, s)
-            if stepped:
+                if workers:
+                    inflight[k] = workers.submit(bt.step, 1)
+                else:
+                    bt.step(1)
+                    retire_done(k)
+            if inflight:
+                wait_s = arrivals[nxt] - (time.perf_counter() - t_start) if nxt < len(reqs) else None
+                futures_wait(list(inflight.values()), timeout=None if wait_s is None else max(wait_s, 0.0),
+                             return_when=FIRST_COMPLETED)
+                continue
+            if any(busy.values()):
                 continue
             # otherwise the oldest waiting request alone
             heads = [(queues[k][0], k) for k in keys if queues[k]]
@@ -555,6 +580,8 @@ def served_form(torch, dmg, ctx, sizes, ncfg, n_req, cap, plain_rate, lane_min=4
         thr, lat, bad = serve(reqs, arrivals)
         out["rates"].append({"offered_per_s": rate, "fraction_of_saturated": frac, "value": thr, "unit": "solves/s",
                              "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99), "failures": bad})
+    if workers:
+        workers.shutdown()
     for k in keys:
         batches[k].close()
         g, h, d = res[k]

@@ -26,7 +26,8 @@
  *    the context's stream, call returns after the result is on the host) or
  *    DMG_PTR_DEVICE (stream-ordered on the context's stream, not synchronised).
  *  - Every call returns a dmg_status.  Negative values are errors, positive
- *    values warnings; the message of the last failure is dmg_last_error().
+ *    values warnings; the message of the calling thread's last failure is
+ *    dmg_last_error().
  *    Nothing throws or aborts across the ABI.
  *  - Handles are owned by the caller and released with the matching
  *    *_destroy call, which accepts NULL.  A hierarchy refers to its gauge and
@@ -84,7 +85,8 @@ typedef struct {
 dmg_status dmg_context_create(int device, void* hip_stream, const dmg_allocator* alloc,
                               size_t hbm_budget, dmg_context** out);
 void dmg_context_destroy(dmg_context* ctx);
-/* Message of the last failing call on ctx ("" if none).  Valid until the next call. */
+/* Message of the calling thread's last call on ctx ("" if it succeeded; the text is
+ * kept per host thread).  Valid until that thread's next call on ctx. */
 const char* dmg_last_error(const dmg_context* ctx);
 /* Bytes of device memory currently held by the context. */
 size_t dmg_context_bytes_in_use(const dmg_context* ctx);
@@ -327,6 +329,13 @@ dmg_status dmg_solve_batched(dmg_context* ctx, dmg_hierarchy* h, dmg_deflation* 
  * batch's lane count (capacity rounded up to a power of two), so a request gets the
  * same result alone or in any mix on batches of equal capacity.  The deflation space
  * must be READY and is only read.
+ *
+ * Each batch runs on a device stream of its own, so the steps of different batches
+ * overlap on the device: admit, step and retire calls on different batches may come
+ * from different host threads at once (create and destroy do not overlap other calls
+ * on the context; calls on one batch come from one thread at a time).  admit and
+ * retire order that stream against the context's stream, so device b and x stay
+ * stream-ordered on the context's stream as elsewhere.
  *
  *   admit(slot, b)        FREE -> RUNNING (DONE at once for b = 0)
  *   step(min_iters)       ceil(min_iters / outer_m) lockstep cycles; finished -> DONE

@@ -5,6 +5,7 @@
 #include <cstring>
 #include <exception>
 #include <new>
+#include <unordered_map>
 
 #include "mrhs.h"
 #include "solver.h"
@@ -68,22 +69,9 @@ __global__ void k_links(const double* theta, int Nx, int Nt, int anti, double2* 
   U32[e] = make_float2((float)cs, (float)sn);
 }
 
-template <typename F>
-static dmg_status guard(dmg_context* c, F&& f) {
-  try {
-    if (c) c->err.clear();
-    return f();
-  } catch (const Error& e) {
-    if (c) c->err = e.msg;
-    return e.code;
-  } catch (const std::bad_alloc&) {
-    if (c) c->err = "host allocation failed";
-    return DMG_E_NOMEM;
-  } catch (const std::exception& e) {
-    if (c) c->err = e.what();
-    return DMG_E_INVALID;
-  }
-}
+static thread_local std::unordered_map<const dmg_context*, std::string> t_err;
+std::string& err_text(const dmg_context* c) { return t_err[c]; }
+void err_forget(const dmg_context* c) { t_err.erase(c); }
 
 // copy between caller buffers and device scratch
 static void to_device(hipStream_t s, void* dst, const void* src, size_t bytes, int ptr_kind) {
@@ -183,11 +171,14 @@ dmg_status dmg_context_create(int device, void* hip_stream, const dmg_allocator*
   return DMG_OK;
 }
 
-void dmg_context_destroy(dmg_context* ctx) { delete ctx; }
+void dmg_context_destroy(dmg_context* ctx) {
+  if (ctx) err_forget(ctx);
+  delete ctx;
+}
 
 dmg_status dmg_kernel_timer(dmg_context* ctx, int mask) {
   if (!ctx) return DMG_E_INVALID;
-  return guard(ctx, [&]() -> dmg_status {
+  return guarded(ctx, [&]() -> dmg_status {
     DMG_HIP(hipStreamSynchronize(ctx->stream));
     ctx->timing = mask & ((1 << DMG_KT_COUNT) - 1);
     ctx->spans.clear();
@@ -200,7 +191,7 @@ dmg_status dmg_kernel_timer(dmg_context* ctx, int mask) {
 dmg_status dmg_kernel_timer_read(dmg_context* ctx, int kernel, double* total_ms, long long* launches,
                                  long long* units) {
   if (!ctx) return DMG_E_INVALID;
-  return guard(ctx, [&]() -> dmg_status {
+  return guarded(ctx, [&]() -> dmg_status {
     DMG_CHECK(kernel >= 0 && kernel < DMG_KT_COUNT, DMG_E_INVALID, "unknown timed kernel");
     DMG_HIP(hipStreamSynchronize(ctx->stream));
     double ms = 0.0;
@@ -221,7 +212,7 @@ dmg_status dmg_kernel_timer_read(dmg_context* ctx, int kernel, double* total_ms,
   });
 }
 
-const char* dmg_last_error(const dmg_context* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+const char* dmg_last_error(const dmg_context* ctx) { return ctx ? err_text(ctx).c_str() : "null context"; }
 
 size_t dmg_context_bytes_in_use(const dmg_context* ctx) { return ctx ? ctx->in_use : 0; }
 
@@ -235,7 +226,7 @@ dmg_status dmg_context_set_budget(dmg_context* ctx, size_t hbm_budget) {
 dmg_status dmg_gauge_create(dmg_context* ctx, int Nx, int Nt, const double* theta, int t_antiperiodic,
                             dmg_gauge** out) {
   if (!ctx || !out) return DMG_E_INVALID;
-  return guard(ctx, [&]() -> dmg_status {
+  return guarded(ctx, [&]() -> dmg_status {
     *out = nullptr;
     DMG_CHECK(theta, DMG_E_INVALID, "theta is NULL");
     DMG_CHECK(Nx >= 4 && Nt >= 4 && Nx % 2 == 0 && Nt % 2 == 0, DMG_E_INVALID, "lattice extents must be even and >= 4");
@@ -274,7 +265,7 @@ void dmg_gauge_destroy(dmg_gauge* g) {
 dmg_status dmg_apply_dirac(dmg_context* ctx, const dmg_gauge* g, double m0, int dagger, dmg_precision p,
                            const void* in, void* out, int nrhs, int ptr_kind) {
   if (!ctx) return DMG_E_INVALID;
-  return guard(ctx, [&]() -> dmg_status {
+  return guarded(ctx, [&]() -> dmg_status {
     DMG_CHECK(g && in && out && nrhs >= 1, DMG_E_INVALID, "apply_dirac: bad arguments");
     DMG_CHECK(std::isfinite(m0), DMG_E_NONFINITE, "non-finite mass");
     const size_t es = p == DMG_FP64 ? sizeof(double2) : sizeof(float2);
@@ -303,7 +294,7 @@ dmg_status dmg_apply_dirac(dmg_context* ctx, const dmg_gauge* g, double m0, int 
 dmg_status dmg_setup(dmg_context* ctx, const dmg_gauge* g, double m0, const dmg_setup_params* prm, const void* start0,
                      const void* start1, int inject_nullvecs, int ptr_kind, dmg_hierarchy** out) {
   if (!ctx || !out) return DMG_E_INVALID;
-  return guard(ctx, [&]() -> dmg_status {
+  return guarded(ctx, [&]() -> dmg_status {
     *out = nullptr;
     DMG_CHECK(g && start0 && start1, DMG_E_INVALID, "setup: NULL argument");
     DMG_CHECK(g->Nx % 16 == 0 && g->Nt % 16 == 0, DMG_E_INVALID,
@@ -375,7 +366,7 @@ size_t dmg_hierarchy_part_bytes(const dmg_hierarchy* h, int level, int part) {
 
 dmg_status dmg_hierarchy_export(dmg_hierarchy* h, int level, int part, void* host_buf, size_t bytes) {
   if (!h) return DMG_E_INVALID;
-  return guard(h->ctx, [&]() -> dmg_status {
+  return guarded(h->ctx, [&]() -> dmg_status {
     const size_t need = dmg_hierarchy_part_bytes(h, level, part);
     DMG_CHECK(need > 0 && bytes == need && host_buf, DMG_E_INVALID, "export: bad level, part or size");
     const void* src = nullptr;
@@ -395,7 +386,7 @@ dmg_status dmg_hierarchy_export(dmg_hierarchy* h, int level, int part, void* hos
 dmg_status dmg_hierarchy_apply(dmg_hierarchy* h, int level, int op, dmg_precision p, const void* in, void* out,
                                int ptr_kind) {
   if (!h) return DMG_E_INVALID;
-  return guard(h->ctx, [&]() -> dmg_status {
+  return guarded(h->ctx, [&]() -> dmg_status {
     DMG_CHECK(in && out && level >= 0 && level <= 2, DMG_E_INVALID, "hierarchy_apply: bad arguments");
     DMG_CHECK(p == DMG_FP64 || p == DMG_FP32 || p == DMG_FP32_BF16, DMG_E_INVALID, "hierarchy_apply: precision");
     const bool is_transfer = op == DMG_OP_RESTRICT || op == DMG_OP_PROLONG;
@@ -450,7 +441,7 @@ dmg_status dmg_hierarchy_apply(dmg_hierarchy* h, int level, int op, dmg_precisio
 
 dmg_status dmg_deflation_create(dmg_hierarchy* h, int m, int k, dmg_deflation** out) {
   if (!h || !out) return DMG_E_INVALID;
-  return guard(h->ctx, [&]() -> dmg_status {
+  return guarded(h->ctx, [&]() -> dmg_status {
     *out = nullptr;
     DMG_CHECK(m >= 2 && m <= MMAX && k >= 1 && k < m && k <= 31, DMG_E_INVALID,
               "deflation sizes need 1 <= k < m <= 64 and k <= 31");
@@ -466,7 +457,7 @@ dmg_status dmg_deflation_create(dmg_hierarchy* h, int m, int k, dmg_deflation** 
 dmg_status dmg_deflation_build(dmg_deflation* d, const void* rhs, double tol, int ptr_kind) {
   if (!d) return DMG_E_INVALID;
   dmg_hierarchy* h = d->h;
-  return guard(h->ctx, [&]() -> dmg_status {
+  return guarded(h->ctx, [&]() -> dmg_status {
     DMG_CHECK(rhs && tol > 0.0, DMG_E_INVALID, "deflation_build: bad arguments");
     const int64_t n = h->op[2].n;
     DevBuf b, x;
@@ -492,7 +483,7 @@ int dmg_deflation_ready(const dmg_deflation* d) { return d ? d->ready : 0; }
 dmg_status dmg_deflation_export(const dmg_deflation* d, void* V, void* H, int* k_out) {
   if (!d) return DMG_E_INVALID;
   dmg_hierarchy* h = d->h;
-  return guard(h->ctx, [&]() -> dmg_status {
+  return guarded(h->ctx, [&]() -> dmg_status {
     DMG_CHECK(d->ready, DMG_E_INVALID, "deflation space is empty");
     if (k_out) *k_out = d->kk;
     const int64_t n = h->op[2].n;
@@ -507,7 +498,7 @@ void dmg_deflation_destroy(dmg_deflation* d) { delete d; }
 dmg_status dmg_solve(dmg_context* ctx, dmg_hierarchy* h, dmg_deflation* d, const dmg_solve_params* prm, const void* b,
                      void* x, int nrhs, int ptr_kind, dmg_solve_stats* stats) {
   if (!ctx || !h) return DMG_E_INVALID;
-  return guard(ctx, [&]() -> dmg_status {
+  return guarded(ctx, [&]() -> dmg_status {
     DMG_CHECK(h->ctx == ctx, DMG_E_INVALID, "hierarchy belongs to another context");
     DMG_CHECK(b && x && nrhs >= 1, DMG_E_INVALID, "solve: bad arguments");
     dmg_solve_params p;
@@ -543,7 +534,7 @@ dmg_status dmg_solve(dmg_context* ctx, dmg_hierarchy* h, dmg_deflation* d, const
 dmg_status dmg_hierarchy_apply_batched(dmg_hierarchy* h, int level, int op, dmg_precision p, const void* in,
                                        void* out, int nrhs, int ptr_kind, int mfma) {
   if (!h) return DMG_E_INVALID;
-  return guard(h->ctx, [&]() -> dmg_status {
+  return guarded(h->ctx, [&]() -> dmg_status {
     DMG_CHECK(in && out && level >= 0 && level <= 2 && nrhs >= 1 && nrhs <= 64, DMG_E_INVALID,
               "hierarchy_apply_batched: bad arguments");
     DMG_CHECK(op == DMG_OP_APPLY || ((op == DMG_OP_RESTRICT || op == DMG_OP_PROLONG) && level <= 1), DMG_E_INVALID,
@@ -619,7 +610,7 @@ dmg_status dmg_hierarchy_apply_batched(dmg_hierarchy* h, int level, int op, dmg_
 dmg_status dmg_solve_fine(dmg_context* ctx, dmg_hierarchy* h, int method, int m, int k, double tol, int max_iters,
                           const void* b, void* x, int nrhs, int ptr_kind, dmg_solve_stats* stats) {
   if (!ctx || !h) return DMG_E_INVALID;
-  return guard(ctx, [&]() -> dmg_status {
+  return guarded(ctx, [&]() -> dmg_status {
     DMG_CHECK(h->ctx == ctx, DMG_E_INVALID, "hierarchy belongs to another context");
     DMG_CHECK(b && x && nrhs >= 1 && nrhs <= 64 && tol > 0.0 && max_iters >= 1, DMG_E_INVALID,
               "solve_fine: bad arguments");
@@ -648,7 +639,7 @@ dmg_status dmg_solve_fine(dmg_context* ctx, dmg_hierarchy* h, int method, int m,
 dmg_status dmg_solve_batched(dmg_context* ctx, dmg_hierarchy* h, dmg_deflation* d, const dmg_solve_params* prm,
                              const void* b, void* x, int nrhs, int ptr_kind, dmg_solve_stats* stats) {
   if (!ctx || !h) return DMG_E_INVALID;
-  return guard(ctx, [&]() -> dmg_status {
+  return guarded(ctx, [&]() -> dmg_status {
     DMG_CHECK(h->ctx == ctx, DMG_E_INVALID, "hierarchy belongs to another context");
     DMG_CHECK(b && x && nrhs >= 1 && nrhs <= 64, DMG_E_INVALID, "solve_batched: 1 <= nrhs <= 64");
     DMG_CHECK(ptr_kind == DMG_PTR_HOST || ptr_kind == DMG_PTR_DEVICE, DMG_E_INVALID, "pointer kind");

@@ -5,7 +5,9 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <exception>
 #include <mutex>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -126,7 +128,6 @@ struct dmg_context {
   size_t budget = 0;
   size_t in_use = 0;
   std::mutex mu;  // allocation accounting and the kernel timer (batch slots run on host threads)
-  std::string err;
   // kernel timer (dmg_kernel_timer): event pairs per timed kernel, work units per launch
   int timing = 0;  // bit mask of timed kernels
   std::vector<hipEvent_t> ev_pool;
@@ -144,6 +145,29 @@ void timer_span(dmg_context* c, int kernel, hipEvent_t a, hipEvent_t b, long lon
 }  // namespace dmg
 
 namespace dmg {
+// Error text of the calling thread's last call on context c (calls on different lane
+// batches may come from different host threads at once, so the text is kept per thread).
+std::string& err_text(const dmg_context* c);
+// Drops the calling thread's text of a context that is being destroyed.
+void err_forget(const dmg_context* c);
+// Runs an entry point's body: clears the calling thread's error text, turns an Error or a
+// standard exception into its status code and text, so no exception crosses the C ABI.
+template <typename F>
+dmg_status guarded(dmg_context* c, F&& f) {
+  try {
+    if (c) err_text(c).clear();
+    return f();
+  } catch (const Error& e) {
+    if (c) err_text(c) = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    if (c) err_text(c) = "host allocation failed";
+    return DMG_E_NOMEM;
+  } catch (const std::exception& e) {
+    if (c) err_text(c) = e.what();
+    return DMG_E_INVALID;
+  }
+}
 // Device memory through the context's allocator hooks, charged against its budget.
 void* dev_alloc(dmg_context* c, size_t bytes);
 void dev_free(dmg_context* c, void* p, size_t bytes);

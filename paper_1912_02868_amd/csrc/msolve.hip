@@ -395,8 +395,23 @@ struct BWork {
   std::vector<long long> mvr;
   std::vector<std::chrono::steady_clock::time_point> t_in;
   long long mv_prev[3] = {0, 0, 0};
+  // a lane batch (dmg_batch_*) runs on a stream of its own, ordered against the context's
+  // stream by `ev` where caller buffers are read or written
+  hipStream_t own = nullptr;
+  hipEvent_t ev = nullptr;
 
-  void init(dmg_hierarchy* hh, dmg_deflation* dd, const dmg_solve_params* pp, int nb_);
+  ~BWork() {
+    if (own) (void)hipStreamDestroy(own);
+    if (ev) (void)hipEventDestroy(ev);
+  }
+  void init(dmg_hierarchy* hh, dmg_deflation* dd, const dmg_solve_params* pp, int nb_, bool own_stream);
+  // the own stream waits for the work queued so far on the context's stream (device memory
+  // from the context's allocator and caller buffers are ordered on that stream)
+  void order_after_ctx() {
+    if (!own) return;
+    DMG_HIP(hipEventRecord(ev, h->ctx->stream));
+    DMG_HIP(hipStreamWaitEvent(own, ev, 0));
+  }
   void reset_lanes();
   void start_lanes(const std::vector<int>& lanes);  // B lanes hold the right-hand sides
   void cycle();                                     // one outer cycle of every active lane
@@ -413,7 +428,7 @@ void destroy_bwork(BWork* b) {
   delete b;
 }
 
-void BWork::init(dmg_hierarchy* hh, dmg_deflation* dd, const dmg_solve_params* pp, int nb_) {
+void BWork::init(dmg_hierarchy* hh, dmg_deflation* dd, const dmg_solve_params* pp, int nb_, bool own_stream) {
   h = hh;
   d = dd;
   p = *pp;
@@ -424,7 +439,12 @@ void BWork::init(dmg_hierarchy* hh, dmg_deflation* dd, const dmg_solve_params* p
   dm = dd->m;
   dk = dd->kk;
   dmg_context* c = h->ctx;
-  hipStream_t s = c->stream;
+  if (own_stream) {
+    DMG_HIP(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+    DMG_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  }
+  hipStream_t s = own ? own : c->stream;
+  if (own) order_after_ctx();
   sh.init(c, s, nb);
   const int64_t n0 = h->op[0].n;
   const size_t fb = sizeof(double2) * (size_t)n0 * nb;
@@ -555,10 +575,10 @@ void BWork::stats(int r, dmg_solve_stats* o, std::chrono::steady_clock::time_poi
   o->elapsed_ms = std::chrono::duration<double, std::milli>(now - t_in[r]).count();
 }
 
-BWork* create_bwork(dmg_hierarchy* h, dmg_deflation* d, const dmg_solve_params* p, int nb) {
+BWork* create_bwork(dmg_hierarchy* h, dmg_deflation* d, const dmg_solve_params* p, int nb, bool own_stream) {
   BWork* w = new BWork();
   try {
-    w->init(h, d, p, nb);
+    w->init(h, d, p, nb, own_stream);
   } catch (...) {
     delete w;
     throw;
@@ -576,7 +596,7 @@ static BWork* get_bwork(dmg_hierarchy* h, dmg_deflation* d, const dmg_solve_para
   }
   destroy_bwork(w);
   h->bwork = nullptr;
-  h->bwork = create_bwork(h, d, p, nb);
+  h->bwork = create_bwork(h, d, p, nb, false);
   return h->bwork;
 }
 
@@ -618,27 +638,6 @@ struct dmg_batch {
   ~dmg_batch() { destroy_bwork(w); }
 };
 
-namespace {
-
-template <typename F>
-dmg_status guarded(dmg_context* c, F&& f) {
-  try {
-    if (c) c->err.clear();
-    return f();
-  } catch (const Error& e) {
-    if (c) c->err = e.msg;
-    return e.code;
-  } catch (const std::bad_alloc&) {
-    if (c) c->err = "host allocation failed";
-    return DMG_E_NOMEM;
-  } catch (const std::exception& e) {
-    if (c) c->err = e.what();
-    return DMG_E_INVALID;
-  }
-}
-
-}  // namespace
-
 extern "C" {
 
 dmg_status dmg_batch_create(dmg_hierarchy* h, dmg_deflation* d, int capacity, const dmg_solve_params* prm,
@@ -665,8 +664,9 @@ dmg_status dmg_batch_create(dmg_hierarchy* h, dmg_deflation* d, int capacity, co
     bt->h = h;
     bt->d = d;
     bt->cap = capacity;
-    bt->w = create_bwork(h, d, &p, nb);
+    bt->w = create_bwork(h, d, &p, nb, true);
     bt->state.assign(capacity, DMG_SLOT_FREE);
+    DMG_HIP(hipStreamSynchronize(bt->w->sh.s));
     DMG_HIP(hipStreamSynchronize(h->ctx->stream));
     *out = bt.release();
     return DMG_OK;
@@ -682,9 +682,10 @@ dmg_status dmg_batch_admit(dmg_batch* bt, int slot, const void* b, int ptr_kind)
     DMG_CHECK(bt->state[slot] == DMG_SLOT_FREE, DMG_E_INVALID, "batch_admit: slot is busy");
     BWork* w = bt->w;
     const int64_t n = bt->h->op[0].n;
-    hipStream_t s = c->stream;
+    hipStream_t s = w->sh.s;
     DevBuf tmp;
     const double2* src = (const double2*)b;
+    w->order_after_ctx();  // a device b is ordered on the context's stream
     if (ptr_kind == DMG_PTR_HOST) {
       const double* v = (const double*)b;
       for (int64_t i = 0; i < 2 * n; ++i)
@@ -726,15 +727,18 @@ dmg_status dmg_batch_retire(dmg_batch* bt, int slot, void* x, int ptr_kind, dmg_
     DMG_CHECK(bt->state[slot] == DMG_SLOT_DONE, DMG_E_INVALID, "batch_retire: slot has no finished solve");
     BWork* w = bt->w;
     const int64_t n = bt->h->op[0].n;
-    hipStream_t s = c->stream;
+    hipStream_t s = w->sh.s;
+    w->order_after_ctx();
     if (ptr_kind == DMG_PTR_HOST) {
       DevBuf tmp;
       tmp.alloc(c, sizeof(double2) * n);
       launch_b_lane_io(s, w->X.as<double2>(), tmp.as<double2>(), n, w->nb, slot, 0);
       DMG_HIP(hipMemcpyAsync(x, tmp.p, sizeof(double2) * n, hipMemcpyDeviceToHost, s));
       DMG_HIP(hipStreamSynchronize(s));
-    } else {
+    } else {  // x is written in order on the context's stream
       launch_b_lane_io(s, w->X.as<double2>(), (double2*)x, n, w->nb, slot, 0);
+      DMG_HIP(hipEventRecord(w->ev, s));
+      DMG_HIP(hipStreamWaitEvent(c->stream, w->ev, 0));
     }
     if (stats) w->stats(slot, stats, std::chrono::steady_clock::now());
     bt->state[slot] = DMG_SLOT_FREE;

@@ -105,27 +105,6 @@ dmg_pool::~dmg_pool() {
   slots.clear();  // each Work waits for its stream before releasing memory
 }
 
-namespace {
-
-template <typename F>
-dmg_status guarded(dmg_context* c, F&& f) {
-  try {
-    if (c) c->err.clear();
-    return f();
-  } catch (const Error& e) {
-    if (c) c->err = e.msg;
-    return e.code;
-  } catch (const std::bad_alloc&) {
-    if (c) c->err = "host allocation failed";
-    return DMG_E_NOMEM;
-  } catch (const std::exception& e) {
-    if (c) c->err = e.what();
-    return DMG_E_INVALID;
-  }
-}
-
-}  // namespace
-
 extern "C" {
 
 dmg_status dmg_pool_create(dmg_context* ctx, int capacity, const dmg_solve_params* prm, dmg_pool** out) {

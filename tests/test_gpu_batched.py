@@ -319,3 +319,47 @@ def test_lanes_device_and_errors(dmg, ctx, cfg64):
     assert st == dmg.DMG_OK and np.linalg.norm(b - D @ x) / np.linalg.norm(b) <= 1e-8 * (1 + 1e-6)
     assert bt.state(2) == dmg.SLOT_FREE and bt.state(9) == -1
     bt.close()
+
+
+def test_lanes_concurrent_batches(dmg, ctx, cfg64):
+    """Lane batches run on streams of their own: two batches driven at once from two
+    host threads (admit, step and retire interleaved) give bitwise the results they give
+    one after the other, with device right-hand sides written on the context's stream just
+    before admission and device solutions read there just after retirement."""
+    from concurrent.futures import ThreadPoolExecutor
+    th, m0, g, h, d, D, lu = cfg64
+    prm = dmg.solve_params(precond="fp32")
+    cap = 4
+    jobs = [[(j, synth.rhs(64, 0, 40 + j)) for j in range(6)], [(j, synth.rhs(64, 0, 50 + j)) for j in range(6)]]
+
+    def drive(bt, js):
+        queue, busy, out = list(js), {}, {}
+        while queue or busy:
+            for i in range(cap):
+                if queue and bt.state(i) == dmg.SLOT_FREE:
+                    key, b = queue.pop(0)
+                    bd = torch.from_numpy(b).cuda() * 1.0  # written by a kernel on the context's stream
+                    assert bt.admit(i, bd) == dmg.DMG_OK
+                    busy[i] = key
+            bt.step(1)
+            for i in list(busy):
+                if bt.state(i) == dmg.SLOT_DONE:
+                    key = busy.pop(i)
+                    xd = torch.full((2 * 64 * 64,), float("nan"), dtype=torch.complex128, device="cuda")
+                    st, s = bt.retire(i, xd)
+                    out[key] = (xd.cpu().numpy(), st, s)  # read on the context's stream
+        return out
+
+    bts = [dmg.Batch(h, d, cap, prm) for _ in range(2)]
+    with ThreadPoolExecutor(max_workers=2) as ex:  # fresh batches: graphs captured at once
+        both = list(ex.map(drive, bts, jobs))
+    serial = [drive(bt, js) for bt, js in zip(bts, jobs)]
+    for bt in bts:
+        bt.close()
+    for js, a, b in zip(jobs, serial, both):
+        assert set(a) == set(b) == {k for k, _ in js}
+        for key, rhs in js:
+            x, st, s = b[key]
+            assert st == dmg.DMG_OK and s["converged"] == 1
+            assert np.linalg.norm(rhs - D @ x) / np.linalg.norm(rhs) <= 1e-8 * (1 + 1e-6)
+            assert np.array_equal(x, a[key][0]) and s["outer_iters"] == a[key][2]["outer_iters"], key
