@@ -363,3 +363,37 @@ def test_lanes_concurrent_batches(dmg, ctx, cfg64):
             assert st == dmg.DMG_OK and s["converged"] == 1
             assert np.linalg.norm(rhs - D @ x) / np.linalg.norm(rhs) <= 1e-8 * (1 + 1e-6)
             assert np.array_equal(x, a[key][0]) and s["outer_iters"] == a[key][2]["outer_iters"], key
+
+
+def test_error_text_per_thread(dmg, ctx, cfg64):
+    """The error text of a context is kept per host thread: a failing call on one thread
+    leaves another thread's text (of its own successful calls) empty, and each thread reads
+    the message of its own failure."""
+    import threading
+    th, m0, g, h, d, D, lu = cfg64
+    bts = [dmg.Batch(h, d, 4) for _ in range(2)]
+    b = synth.rhs(64, 0, 60)
+    seen = {}
+    ready = threading.Barrier(2)
+
+    def bad():
+        ready.wait()
+        st = dmg.lib().dmg_batch_retire(bts[0].h, 7, None, dmg.PTR_HOST, None)
+        seen["bad"] = (st, dmg.lib().dmg_last_error(ctx.h).decode())
+
+    def good():
+        ready.wait()
+        assert bts[1].admit(0, b) == dmg.DMG_OK
+        bts[1].step(1)
+        seen["good"] = dmg.lib().dmg_last_error(ctx.h).decode()
+
+    ts = [threading.Thread(target=f) for f in (bad, good)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    for bt in bts:
+        bt.close()
+    assert seen["bad"][0] == dmg.DMG_E_INVALID and "batch_retire" in seen["bad"][1]
+    assert seen["good"] == ""
+    assert dmg.lib().dmg_last_error(ctx.h).decode() == ""  # this thread made no failing call
