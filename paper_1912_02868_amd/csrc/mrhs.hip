@@ -170,6 +170,7 @@ __global__ void __launch_bounds__(BT) kb_final(const double2* __restrict__ part,
   const bool skip = a.mode == FIN_ARN1                           ? lanes_all_done(bs, a.nb)
                     : a.mode == FIN_ARN2                         ? !*a.anyp2
                                                                  : false;
+  if (skip) return;  // the same for every thread (no barrier has been passed yet)
   // Each thread adds the partials t and t + BT of every quantity (contiguous per quantity, so
   // a wavefront's loads coalesce; all loads are issued before the first add); a fixed shuffle
   // tree adds the 64 lanes of a wavefront and the wavefronts' sums are added in order.
@@ -205,7 +206,6 @@ __global__ void __launch_bounds__(BT) kb_final(const double2* __restrict__ part,
       st.pass2 = b.pass2;
     }
   }
-  if (skip) return;
 #pragma unroll
   for (int q = 0; q < MQ; ++q) {
     if (q < a.nq) {
