@@ -400,8 +400,11 @@ struct BWork {
   hipStream_t own = nullptr;
   hipEvent_t ev = nullptr;
 
-  ~BWork() {
-    if (own) (void)hipStreamDestroy(own);
+  ~BWork() {  // the members' buffers are released after this body: the own stream is idle by then
+    if (own) {
+      (void)hipStreamSynchronize(own);
+      (void)hipStreamDestroy(own);
+    }
     if (ev) (void)hipEventDestroy(ev);
   }
   void init(dmg_hierarchy* hh, dmg_deflation* dd, const dmg_solve_params* pp, int nb_, bool own_stream);

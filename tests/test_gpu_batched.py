@@ -397,3 +397,26 @@ def test_error_text_per_thread(dmg, ctx, cfg64):
     assert seen["bad"][0] == dmg.DMG_E_INVALID and "batch_retire" in seen["bad"][1]
     assert seen["good"] == ""
     assert dmg.lib().dmg_last_error(ctx.h).decode() == ""  # this thread made no failing call
+
+
+def test_batch_over_budget(dmg, ctx, cfg64):
+    """A lane batch whose workspace does not fit the context's HBM budget is refused with
+    DMG_E_BUDGET (its partly built workspace and stream released), and a batch created
+    afterwards under the full budget solves as usual."""
+    th, m0, g, h, d, D, lu = cfg64
+    before = ctx.bytes_in_use
+    ctx.set_budget(before + (1 << 20))
+    try:
+        with pytest.raises(dmg.DmgError) as e:
+            dmg.Batch(h, d, 8)
+        assert e.value.code == dmg.DMG_E_BUDGET
+    finally:
+        ctx.set_budget(0)
+    torch.cuda.synchronize()
+    assert ctx.bytes_in_use == before
+    b = synth.rhs(64, 0, 70)
+    bt = dmg.Batch(h, d, 8)
+    res = _run_lanes(dmg, bt, 8, [(0, b)])
+    bt.close()
+    x, st, s = res[0]
+    assert st == dmg.DMG_OK and np.linalg.norm(b - D @ x) / np.linalg.norm(b) <= 1e-8 * (1 + 1e-6)
