@@ -468,9 +468,8 @@ __device__ int schur_qr(double2* A, double2* X, int n, int* flag_sh) {
     }
     double2 x = csub(A[lo + n * lo], mu), y = A[lo + 1 + n * lo];
     for (int k = lo; k < hi; ++k) {
-      double cg;
-      double2 sg;
-      make_givens_fast(x, y, cg, sg);
+      // this rotation's LDS operands are loaded first: they do not depend on its coefficients,
+      // so their latency overlaps the square root and division of make_givens_fast
       const int c0 = (k > lo) ? k - 1 : lo;
       const int r1 = (k + 2 < hi) ? k + 2 : hi;
       const int jc = c0 + t;
@@ -489,6 +488,9 @@ __device__ int schur_qr(double2* A, double2* X, int n, int* flag_sh) {
         xa = X[t + n * k];
         xb = X[t + n * (k + 1)];
       }
+      double cg;
+      double2 sg;
+      make_givens_fast(x, y, cg, sg);
       // from the left on rows k, k+1 (columns c0 ..)
       const double2 pn = cadd(cscale(p, cg), cmul(sg, q));
       const double2 qn = csub(cscale(q, cg), cmul(cconj(sg), p));
