@@ -33,6 +33,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+INFINITY_CACHE_BYTES = 256 * 10 ** 6
 RHS_PER_CONFIG = 5
 # HBM bytes per launch of k_coarse_proj<double, false, true, true> from the FETCH_SIZE and WRITE_SIZE counter
 # passes (scaled by the reference streaming kernels) recorded in profiles/k_coarse_proj_256_hbm_traffic.md;
@@ -52,17 +53,19 @@ def parse():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle solves for the CPU baseline")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-rhs", type=int, default=64, help="right-hand sides per lockstep solve")
-    ap.add_argument("--batched-configs", type=int, default=2)
-    ap.add_argument("--batched-lattice", type=int, default=0, help="lattice of the lockstep form (0: --lattice)")
+    ap.add_argument("--batched-configs", type=int, default=1)
+    ap.add_argument("--batched-lattice", type=int, default=512,
+                    help="lattice of the lockstep form (512: one 512^2 configuration x 64 right-hand sides)")
+    ap.add_argument("--no-oracle-error", action="store_true",
+                    help="skip the error of every timed solution against sparse LU of the oracle's D")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-sizes", default="64,128,256,512")
     ap.add_argument("--serve-configs", type=int, default=4, help="resident configurations per lattice size")
-    ap.add_argument("--serve-requests", type=int, default=200, help="requests per arrival rate")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="requests per arrival rate")
     ap.add_argument("--serve-capacity", type=int, default=16, help="lanes per resident configuration")
-    ap.add_argument("--serve-lane-min", type=int, default=4,
-                    help="waiting requests of an idle configuration that start its lane batch (fewer: single-RHS)")
-    ap.add_argument("--serve-serial", action="store_true",
-                    help="step the lane batches one after another instead of at once (one host thread each)")
+    ap.add_argument("--serve-inflight", type=int, default=2, help="lane-batch steps running at once")
+    ap.add_argument("--serve-age", type=float, default=0.5,
+                    help="seconds of waiting that double a configuration's scheduling weight")
     ap.add_argument("--scan", action="store_true",
                     help="mass-gap and lattice-size scan of six solvers with power-law fits (prints its own JSON)")
     ap.add_argument("--scan-sizes", default="64,128,256")
@@ -70,6 +73,11 @@ def parse():
     ap.add_argument("--scan-gaps", default="1e-1,1e-2,1e-3,1e-4")
     ap.add_argument("--scan-fit-gap", type=float, default=1e-4)
     ap.add_argument("--scan-rhs", type=int, default=2)
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only the multi-RHS stencils at 512^2 x 64 (FP32 Wilson, FP32 and FP64 matrix-core block "
+                         "stencils) and a 256 MiB streaming kernel, for hardware counter passes (prints its own JSON)")
+    ap.add_argument("--maps", default="",
+                    help="write this process's memory map (/proc/self/maps) to the given file before exiting")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for hardware byte counters)")
     return ap.parse_args()
@@ -81,6 +89,10 @@ def percentile(v, q):
 
 def main():
     a = parse()
+    if a.maps:
+        import atexit
+        import shutil
+        atexit.register(lambda: shutil.copyfile("/proc/self/maps", a.maps))
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the solver has no multi-GPU path.",
               file=sys.stderr)
@@ -93,6 +105,9 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     dmg.lib()
+    if a.kernels_only:
+        print(json.dumps(kernels_only(torch, dmg)), flush=True)
+        return
     if a.scan:
         ctx = dmg.Context(0)
         out = scan(torch, dmg, ctx, [int(v) for v in a.scan_sizes.split(",")], a.scan_configs,
@@ -137,6 +152,8 @@ def main():
         d.close()
         return x
 
+    sols = {}  # (precision, configuration) -> solutions of the last timed step of that configuration
+
     def timed(precond):
         for c in warm_cfgs:
             run_step(c, precond, [], [])
@@ -144,7 +161,7 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for c in step_cfgs:
-            run_step(c, precond, lat, st_all)
+            sols[(precond, c)] = run_step(c, precond, lat, st_all)
         torch.cuda.synchronize()
         return time.perf_counter() - t0, lat, st_all
 
@@ -202,8 +219,15 @@ def main():
     out_served = None
     if not a.no_serve:
         out_served = served_form(torch, dmg, ctx, [int(v) for v in a.serve_sizes.split(",")], a.serve_configs,
-                                 a.serve_requests, a.serve_capacity, n_solves / el64, a.serve_lane_min,
-                                 not a.serve_serial)
+                                 a.serve_requests, a.serve_capacity, a.serve_inflight, a.serve_age)
+
+    # ------------------------------------------------------------ error against the oracle
+    oracle_err = None
+    if not a.no_oracle_error:
+        oracle_err = errors_vs_oracle(synth, N, res, sols)
+        for prec, key in ((dmg.FP32, None), (dmg.FP32_BF16, "bf16_blocks")):
+            if out_mixed is not None and prec in oracle_err:
+                (out_mixed if key is None else out_mixed[key])["error_vs_oracle"] = oracle_err.pop(prec)
 
     # ------------------------------------------------------------ CPU baseline (oracle)
     cpu = None
@@ -236,6 +260,7 @@ def main():
         "mean_outer_iters": mean("outer_iters"),
         "mean_mvps": {"fine": mean("fine_mvps"), "intermediate": mean("int_mvps"), "coarse": mean("coarse_mvps"),
                       "fine_equivalent": mean("fine_equiv_mvps")},
+        "error_vs_oracle": oracle_err.get(dmg.FP64) if oracle_err else None,
         "mixed": out_mixed,
         "batched": out_batched,
         "served": out_served,
@@ -244,7 +269,72 @@ def main():
         "roofline_intermediate_stencil_bf16": roof_int16,
         "cpu_baseline": cpu,
     }
+    # release every handle before the interpreter exits (no library teardown at exit time)
+    sols.clear()
+    for g, h, b in res.values():
+        h.close()
+        g.close()
+    res.clear()
+    torch.cuda.synchronize()
+    ctx.close()
     print(json.dumps(line), flush=True)
+
+
+def kernels_only(torch, dmg, N=512, nrhs=64, reps=20):
+    """The multi-RHS stencils of the batched form on one 512^2 configuration, each launched
+    `reps` times through the apply hook (working sets above the 256 MB Infinity Cache:
+    541 MB per FP32 Wilson apply, 780 MB per FP32 and 1.56 GB per FP64 block apply on the
+    128^2 intermediate grid), then a plain streaming multiply of 256 MiB (reads 256 MiB,
+    writes 256 MiB per launch) as the reference for byte counters.  Each kernel's average
+    launch time comes from the library's events."""
+    import synth
+    ctx = dmg.Context(0)
+    g = dmg.Gauge(ctx, synth.gauge_angles(N, 0))
+    h = dmg.Hierarchy(ctx, g, synth.bare_mass(N, 0), torch.from_numpy(synth.near_null_starts(N, 0, 0)).cuda(),
+                      torch.from_numpy(synth.near_null_starts(N, 0, 1)).cuda())
+    out = {"workload": f"{N}^2 configuration 0, {nrhs} right-hand sides", "reps": reps}
+    out["wilson_fp32"] = batched_wilson_roofline(torch, dmg, ctx, h, N, nrhs, reps=reps)
+    out["block_fp32"] = batched_block_roofline(torch, dmg, ctx, h, N, nrhs, reps=reps)
+    out["block_fp64"] = batched_block_roofline(torch, dmg, ctx, h, N, nrhs, reps=reps, prec="fp64")
+    src = torch.empty(256 * 2 ** 20 // 4, dtype=torch.float32, device="cuda").uniform_()
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        torch.mul(src, 2.0, out=dst)
+    torch.cuda.synchronize()
+    out["copy_reference"] = {"kernel": "torch.mul float32 (elementwise multiply)", "bytes_read": 256 * 2 ** 20,
+                             "bytes_written": 256 * 2 ** 20, "launches": reps}
+    del src, dst
+    h.close()
+    g.close()
+    torch.cuda.synchronize()
+    ctx.close()
+    return out
+
+
+def errors_vs_oracle(synth, N, res, sols):
+    """Relative error of every timed solution against sparse LU of the oracle's D (FP64),
+    per preconditioner precision: max and median over the configurations' right-hand sides,
+    with the a-posteriori bound kappa-free form ||x - x_LU|| / ||x_LU||.  Computed after the
+    timed regions, on the host."""
+    import scipy.sparse.linalg as spla
+    from oracle import wilson
+    t0 = time.perf_counter()
+    errs = {}
+    for c in sorted({c for (_, c) in sols}):
+        D = wilson.dirac_matrix(synth.gauge_angles(N, c), synth.bare_mass(N, c))
+        lu = spla.splu(D.tocsc(), permc_spec="MMD_AT_PLUS_A")
+        b = res[c][2].cpu().numpy()
+        ref = [lu.solve(b[j]) for j in range(b.shape[0])]
+        for (prec, cc), x in sols.items():
+            if cc != c:
+                continue
+            xh = x.cpu().numpy()
+            for j in range(b.shape[0]):
+                errs.setdefault(prec, []).append(float(np.linalg.norm(xh[j] - ref[j]) / np.linalg.norm(ref[j])))
+    el = time.perf_counter() - t0
+    return {prec: {"max": max(v), "median": float(np.median(v)), "solves": len(v),
+                   "reference": "sparse LU of the oracle's FP64 D (scipy splu)", "host_s": el}
+            for prec, v in errs.items()}
 
 
 def coarse_roofline(N, total_ms, launches, steps, timed_s):
@@ -268,7 +358,10 @@ def coarse_roofline(N, total_ms, launches, steps, timed_s):
             "arnoldi_steps": steps, "us_per_step": total_ms * 1e3 / max(steps, 1),
             "algorithmic_bytes_per_step": bytes_per_step,
             "share_of_timed_region": total_ms * 1e-3 / timed_s if timed_s > 0 else None,
-            "note": "latency bound: one grid barrier per Arnoldi step"}
+            "limited_by": "latency: one grid barrier and exchange per Arnoldi step; the operator stays in "
+                          "registers, so HBM carries only the counter traffic",
+            "counter_gbs": (COARSE_TRAFFIC_BYTES / (total_ms / max(launches, 1) * 1e-3) / 1e9
+                            if N == 256 and total_ms > 0 else None)}
 
 
 def measure_stencil_roofline(torch, dmg, ctx, h, N, reps=200):
@@ -289,10 +382,13 @@ def measure_stencil_roofline(torch, dmg, ctx, h, N, reps=200):
     bytes_per_launch = sites * (5 * 24 * 24 * 16 + 2 * 24 * 16)
     avg_ms = ms / max(n, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    return {"kernel": "k_block_apply<double> (intermediate grid, 64x64 sites x 24 dof)",
+    return {"kernel": f"k_block_apply<double> (intermediate grid, {L}x{L} sites x 24 dof)",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": None, "avg_launch_us": avg_ms * 1e3,
-            "algorithmic_bytes_per_launch": bytes_per_launch}
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+            "cache_resident": bytes_per_launch < INFINITY_CACHE_BYTES,
+            "note": "working set below the 256 MB Infinity Cache: the fraction is not an HBM figure"
+            if bytes_per_launch < INFINITY_CACHE_BYTES else "working set above the 256 MB Infinity Cache"}
 
 
 def measure_bf16_stencil(torch, dmg, h, N, reps=200):
@@ -314,10 +410,11 @@ def measure_bf16_stencil(torch, dmg, h, N, reps=200):
     avg_ms = e0.elapsed_time(e1) / reps
     bytes_per_launch = sites * (5 * 24 * 24 * 4 + 2 * 24 * 8)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    return {"kernel": "k_block_apply<float, bf16> (intermediate grid, 64x64 sites x 24 dof, BF16 blocks)",
+    return {"kernel": f"k_block_apply<float, bf16> (intermediate grid, {L}x{L} sites x 24 dof, BF16 blocks)",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": None, "avg_launch_us": avg_ms * 1e3,
-            "algorithmic_bytes_per_launch": bytes_per_launch}
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+            "cache_resident": bytes_per_launch < INFINITY_CACHE_BYTES}
 
 
 def build_resident(dmg, ctx, synth, N, c):
@@ -347,6 +444,21 @@ def batched_form(torch, dmg, ctx, N, cfgs, nrhs, plain_rate):
     X = torch.empty_like(B[cfgs[0]])
     out = {"workload": f"{N}^2, {nrhs} right-hand sides per lockstep solve, configurations {list(cfgs)}",
            "rhs_per_call": nrhs}
+    # like-for-like comparator: the plain FP64 form (one right-hand side at a time) on the same
+    # lattice and configuration with the same deflation space already built (GMRES-Proj only)
+    g, h, d = res[cfgs[0]]
+    n_plain = 8
+    xs = torch.empty_like(B[cfgs[0]][0])
+    dmg.solve(ctx, h, d, B[cfgs[0]][0], xs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(n_plain):
+        dmg.solve(ctx, h, d, B[cfgs[0]][j], xs)
+    torch.cuda.synchronize()
+    plain_same = n_plain / (time.perf_counter() - t0)
+    out["plain_fp64_same_lattice"] = {"value": plain_same, "unit": "solves/s",
+                                      "sample": f"right-hand sides 0..{n_plain - 1} one at a time, deflation "
+                                                "space built beforehand as in the lockstep form"}
     for prec in ("fp32", "fp64", "fp32_bf16"):
         prm = dmg.solve_params(precond=prec)
         g, h, d = res[cfgs[0]]
@@ -382,7 +494,8 @@ def batched_form(torch, dmg, ctx, N, cfgs, nrhs, plain_rate):
                      "all_converged_1e-8": all(s["converged"] and s["true_rel_resid"] <= 1e-8 for s in stats),
                      "max_true_rel_resid": float(max(s["true_rel_resid"] for s in stats)),
                      "mean_outer_iters": float(np.mean([s["outer_iters"] for s in stats])),
-                     "speedup_vs_plain_fp64": (len(cfgs) * nrhs / el) / plain_rate}
+                     "speedup_vs_plain_fp64_same_lattice": (len(cfgs) * nrhs / el) / plain_same,
+                     "ratio_to_headline_plain_fp64": (len(cfgs) * nrhs / el) / plain_rate}
         if kt:
             out[prec]["kernels"] = kt
     out["roofline_block_batched"] = batched_block_roofline(torch, dmg, ctx, res[cfgs[0]][1], N, nrhs)
@@ -394,17 +507,20 @@ def batched_form(torch, dmg, ctx, N, cfgs, nrhs, plain_rate):
 
 
 FP32_MFMA_PEAK_TFLOPS = 157.3
+FP64_MFMA_PEAK_TFLOPS = 78.6
 
 
-def batched_block_roofline(torch, dmg, ctx, h, N, nrhs, reps=50):
-    """Multi-RHS intermediate-grid block stencil in FP32 on the matrix cores: per blocked
-    site and right-hand side 5 x 576 complex multiply-adds (23,040 flop); bytes per site:
-    the 5 FP32 blocks (23,040 B) plus input and output 24-vectors of every right-hand
-    side (384 nrhs B).  Timed by the library's events around each launch."""
+def batched_block_roofline(torch, dmg, ctx, h, N, nrhs, reps=50, prec="fp32"):
+    """Multi-RHS intermediate-grid block stencil on the matrix cores (FP32, or FP64 with
+    prec="fp64"): per blocked site and right-hand side 5 x 576 complex multiply-adds
+    (23,040 flop); bytes per site: the 5 blocks (23,040 B FP32, 46,080 B FP64) plus input and
+    output 24-vectors of every right-hand side (384 nrhs B FP32, 768 nrhs B FP64).  Timed by
+    the library's events around each launch."""
     L = N // 4
     sites = L * L
     n1 = sites * 24
-    x = torch.randn(nrhs, n1, dtype=torch.complex64, device="cuda")
+    f64 = prec == "fp64"
+    x = torch.randn(nrhs, n1, dtype=torch.complex128 if f64 else torch.complex64, device="cuda")
     y = torch.empty_like(x)
     for _ in range(3):
         h.apply_batched(1, dmg.OP_APPLY, x, y, nrhs)
@@ -415,11 +531,14 @@ def batched_block_roofline(torch, dmg, ctx, h, N, nrhs, reps=50):
     ctx.timer()
     avg = ms / max(n, 1)
     flops = sites * nrhs * 23040
-    byts = sites * (5 * 576 * 8 + 2 * 24 * 8 * nrhs)
+    es = 16 if f64 else 8
+    byts = sites * (5 * 576 * es + 2 * 24 * es * nrhs)
     tf = flops / (avg * 1e-3) / 1e12
-    return {"kernel": f"kb_block_mfma_p (FP32, {L}x{L} sites x 24 dof x {nrhs} right-hand sides, 16x16x4 MFMA)",
-            "bound": "mfma", "achieved": tf, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": tf / FP32_MFMA_PEAK_TFLOPS, "traffic": None, "avg_launch_us": avg * 1e3,
+    peak = FP64_MFMA_PEAK_TFLOPS if f64 else FP32_MFMA_PEAK_TFLOPS
+    return {"kernel": f"kb_block_mfma_p ({'FP64' if f64 else 'FP32'}, {L}x{L} sites x 24 dof x {nrhs} right-hand "
+                      f"sides, {'16x16x4 FP64' if f64 else '16x16x4 FP32'} MFMA)",
+            "bound": "mfma", "achieved": tf, "peak": peak, "unit": "TFLOP/s",
+            "frac": tf / peak, "traffic": None, "avg_launch_us": avg * 1e3,
             "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": byts,
             "achieved_gbs": byts / (avg * 1e-3) / 1e9}
 
@@ -442,20 +561,30 @@ def batched_wilson_roofline(torch, dmg, ctx, h, N, nrhs, reps=50):
     gbs = byts / (avg * 1e-3) / 1e9
     return {"kernel": f"kb_wilson (FP32, {N}x{N} sites x {nrhs} right-hand sides)", "bound": "hbm",
             "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None,
-            "avg_launch_us": avg * 1e3, "algorithmic_bytes_per_launch": byts}
+            "avg_launch_us": avg * 1e3, "algorithmic_bytes_per_launch": byts,
+            "cache_resident": byts < INFINITY_CACHE_BYTES}
 
 
-def served_form(torch, dmg, ctx, sizes, ncfg, n_req, cap, plain_rate, lane_min=4, concurrent=True):
+def served_form(torch, dmg, ctx, sizes, ncfg, n_req, cap, inflight_max=2, age_s=0.5):
     """Serving: single-RHS requests, each naming one of the resident configurations
     (every size in `sizes` x configurations 0..ncfg-1, hierarchy and deflation space kept
     on the device), arrive as a seeded Poisson stream; each configuration has a lane
-    batch (dmg_batch_*, FP32 preconditioner) that requests join and leave between outer
-    cycles.  The host loop admits waiting requests into free lanes (configurations with
-    running lanes or a queue of at least four), steps those batches one outer cycle each
-    (at once from a thread per batch, each batch on its own stream; one after another
-    with concurrent=False) and retires finished lanes; when no batch runs, the oldest
-    waiting request is solved on its own (dmg_solve).  Latency = arrival to result ready.  The saturated rate (all requests at t = 0) sets
-    the three arrival rates, 0.5x, 0.9x and 1.2x of it."""
+    batch (dmg_batch_*, FP32 preconditioner, `cap` lanes) that requests join and leave
+    between outer cycles (continuous batching).
+
+    Scheduler: at most `inflight_max` batch steps run at once (each batch on its own stream,
+    stepped from a worker thread); whenever one ends, its finished lanes are retired and the
+    next step goes to the configuration with the most work, lanes running plus waiting
+    requests that fit, weighted up by the age of its oldest waiting request
+    (score = lanes x (1 + wait / age_s)).  So under load the configurations that are not
+    being stepped collect requests and their next step carries more lanes, while a lone
+    request still gets a step once it has waited long enough.  Latency = arrival to result
+    ready.
+
+    The saturated rate (all requests at t = 0) sets the three arrival rates, 0.5x, 0.9x and
+    1.2x of it.  The like-for-like comparator is the plain FP64 form serving the same mix one
+    request at a time (dmg_solve, FP64 preconditioner, the same resident deflation spaces):
+    its capacity is 1 / (mean solve time over the configurations), measured here."""
     import synth
 
     def known(N, c):
@@ -481,21 +610,32 @@ def served_form(torch, dmg, ctx, sizes, ncfg, n_req, cap, plain_rate, lane_min=4
         return [(keys[p], torch.from_numpy(synth.rhs(keys[p][0], keys[p][1], 1000 + i)).cuda())
                 for i, p in enumerate(picks)], rng
 
+    # plain FP64 comparator on the same mix: mean solve time per configuration (3 requests each)
+    xs = {k: torch.empty(2 * k[0] * k[0], dtype=torch.complex128, device="cuda") for k in keys}
+    t_plain = {}
+    for k in keys:
+        g, h, d = res[k]
+        bs = [torch.from_numpy(synth.rhs(k[0], k[1], 900 + j)).cuda() for j in range(4)]
+        dmg.solve(ctx, h, d, bs[0], xs[k])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for b in bs[1:]:
+            dmg.solve(ctx, h, d, b, xs[k])
+        torch.cuda.synchronize()
+        t_plain[k] = (time.perf_counter() - t1) / 3
+    plain_mix = 1.0 / float(np.mean(list(t_plain.values())))
+    by_size = {N: 1.0 / float(np.mean([t_plain[k] for k in keys if k[0] == N])) for N in sizes
+               if any(k[0] == N for k in keys)}
+
     xout = {k: torch.empty(2 * k[0] * k[0], dtype=torch.complex128, device="cuda") for k in keys}
     from concurrent.futures import FIRST_COMPLETED, ThreadPoolExecutor, wait as futures_wait
-    workers = ThreadPoolExecutor(max_workers=len(keys)) if concurrent else None
+    workers = ThreadPoolExecutor(max_workers=max(1, inflight_max))
 
     def serve(reqs, arrivals):
-        """Requests of a configuration with at least `lane_min` waiting (or already running
-        lanes) go through its lane batch; a configuration with fewer waiting requests gets
-        its oldest request solved on its own (single-RHS path, only while no batch step is
-        in flight), so that sparse traffic is not charged a whole lockstep step per request.
-        With the worker threads each batch's step runs on its own; a batch whose step ended
-        is retired and refilled at once while the others go on."""
         queues = {k: [] for k in keys}
         busy = {k: {} for k in keys}
         inflight = {}
-        lat, bad = [], 0
+        lat, bad, lanes_per_step = [], 0, []
         nxt, done = 0, 0
         t_start = time.perf_counter()
         cur = torch.cuda.current_stream()  # the context's stream
@@ -523,70 +663,69 @@ def served_form(torch, dmg, ctx, sizes, ncfg, n_req, cap, plain_rate, lane_min=4
             for k in [k for k, f in inflight.items() if f.done()]:
                 inflight.pop(k).result()
                 retire_done(k)
-            # lane batches: configurations with running lanes, or enough waiting requests
-            for k in keys:
-                if k in inflight:
-                    continue
-                bt = batches[k]
-                if busy[k] or len(queues[k]) >= lane_min:
-                    for sl in range(cap):
-                        if not queues[k]:
-                            break
-                        if bt.state(sl) == dmg.SLOT_FREE:
-                            i = queues[k].pop(0)
-                            bt.admit(sl, reqs[i][1])
-                            busy[k][sl] = i
-                if not busy[k]:
-                    continue
-                if workers:
-                    inflight[k] = workers.submit(bt.step, 1)
-                else:
-                    bt.step(1)
-                    retire_done(k)
+            while len(inflight) < inflight_max:
+                best, best_score = None, 0.0
+                for k in keys:
+                    if k in inflight:
+                        continue
+                    lanes = len(busy[k]) + min(len(queues[k]), cap - len(busy[k]))
+                    if lanes == 0:
+                        continue
+                    wait = now - arrivals[queues[k][0]] if queues[k] else 0.0
+                    score = lanes * (1.0 + wait / age_s)
+                    if score > best_score:
+                        best, best_score = k, score
+                if best is None:
+                    break
+                bt = batches[best]
+                for sl in range(cap):
+                    if not queues[best]:
+                        break
+                    if bt.state(sl) == dmg.SLOT_FREE:
+                        i = queues[best].pop(0)
+                        bt.admit(sl, reqs[i][1])
+                        busy[best][sl] = i
+                lanes_per_step.append(len(busy[best]))
+                inflight[best] = workers.submit(bt.step, 1)
             if inflight:
                 wait_s = arrivals[nxt] - (time.perf_counter() - t_start) if nxt < len(reqs) else None
                 futures_wait(list(inflight.values()), timeout=None if wait_s is None else max(wait_s, 0.0),
                              return_when=FIRST_COMPLETED)
-                continue
-            if any(busy.values()):
-                continue
-            # otherwise the oldest waiting request alone
-            heads = [(queues[k][0], k) for k in keys if queues[k]]
-            if heads:
-                i, k = min(heads)
-                queues[k].pop(0)
-                g, h, d = res[k]
-                st, ss = dmg.solve(ctx, h, d, reqs[i][1], xout[k], params=prm)
-                torch.cuda.synchronize()
-                finish(i, ss[0])
             elif nxt < len(reqs):
                 time.sleep(max(0.0, arrivals[nxt] - (time.perf_counter() - t_start)))
-        return len(reqs) / (time.perf_counter() - t_start), lat, bad
+        return (len(reqs) / (time.perf_counter() - t_start), lat, bad,
+                float(np.mean(lanes_per_step)) if lanes_per_step else 0.0)
 
     reqs, _ = requests(0, min(n_req, 64))
     serve(reqs, [0.0] * len(reqs))  # warm the lanes of every batch in use
     reqs, _ = requests(1, n_req)
-    sat, lat_sat, bad = serve(reqs, [0.0] * len(reqs))
+    sat, lat_sat, bad, lps = serve(reqs, [0.0] * len(reqs))
     out = {"workload": f"{len(keys)} resident configurations ({', '.join(f'{n}^2 {c}' for n, c in keys)}), "
-                       f"single-RHS requests, Poisson arrivals, {cap} lanes per configuration, FP32 preconditioner",
+                       f"single-RHS requests, Poisson arrivals, {cap} lanes per configuration, FP32 preconditioner, "
+                       f"at most {inflight_max} batch steps at once",
            "requests_per_rate": n_req, "setup_s": setup_s, "resident_bytes": bytes_resident,
+           "plain_fp64_same_mix": {"value": plain_mix, "unit": "solves/s", "by_size": by_size,
+                                   "sample": "3 requests per configuration, one at a time, FP64 preconditioner, "
+                                             "resident deflation spaces"},
            "saturated": {"value": sat, "unit": "solves/s", "p50_ms": percentile(lat_sat, 50),
-                         "p99_ms": percentile(lat_sat, 99), "failures": bad},
+                         "p99_ms": percentile(lat_sat, 99), "failures": bad, "mean_lanes_per_step": lps,
+                         "speedup_vs_plain_fp64_same_mix": sat / plain_mix},
            "rates": []}
     for ri, frac in enumerate((0.5, 0.9, 1.2)):
         rate = frac * sat
         reqs, rng = requests(2 + ri, n_req)
         arrivals = list(np.cumsum(rng.exponential(1.0 / rate, size=n_req)))
-        thr, lat, bad = serve(reqs, arrivals)
+        thr, lat, bad, lps = serve(reqs, arrivals)
         out["rates"].append({"offered_per_s": rate, "fraction_of_saturated": frac, "value": thr, "unit": "solves/s",
-                             "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99), "failures": bad})
-    if workers:
-        workers.shutdown()
+                             "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99), "failures": bad,
+                             "mean_lanes_per_step": lps, "speedup_vs_plain_fp64_same_mix": thr / plain_mix})
+    workers.shutdown()
     for k in keys:
         batches[k].close()
         g, h, d = res[k]
         d.close()
         h.close()
+        g.close()
     return out
 
 
@@ -596,43 +735,62 @@ def cpu_baseline(N, budget_s, gpu_outer_iters):
     right-hand sides 0, 1, ... are solved to 1e-8 one after the other (a fresh deflation space,
     so the first pays for GMRES-DR) until `budget_s` seconds have been spent; the rate counts
     completed solves only.  If not even one solve completes, the rate is extrapolated from the
-    outer iterations done and the GPU run's mean outer iterations per solve."""
+    outer iterations done and the GPU run's mean outer iterations per solve.
+
+    The reported run is limited to one thread (threadpoolctl): the scipy sparse products that
+    dominate the oracle are single-threaded anyway.  A second run with the BLAS thread pools at
+    the host's size (only the small dense steps use them) is reported beside it."""
     import synth
-    from oracle import multigrid
-    threads = 1
+    from oracle import krylov, multigrid
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        pass
+        from threadpoolctl import threadpool_info, threadpool_limits
+    except Exception:  # pragma: no cover
+        threadpool_info = threadpool_limits = None
     th = synth.gauge_angles(N, 0)
     m0 = synth.bare_mass(N, 0)
     t0 = time.perf_counter()
     H = multigrid.Hierarchy(th, m0, synth.near_null_starts(N, 0, 0), synth.near_null_starts(N, 0, 1))
     setup_s = time.perf_counter() - t0
-    iters = 0
     orig = H.cycle0
 
-    def counted_cycle(v):
-        nonlocal iters
-        iters += 1
-        return orig(v)
-    H.cycle0 = counted_cycle
-    solves, lat = 0, []
-    t0 = time.perf_counter()
-    for j in range(RHS_PER_CONFIG):
-        if time.perf_counter() - t0 > budget_s:
-            break
-        t1 = time.perf_counter()
-        _, info = H.solve(synth.rhs(N, 0, j))
-        lat.append(time.perf_counter() - t1)
-        solves += 1 if info.converged else 0
-    el = time.perf_counter() - t0
-    value = solves / el if solves else 1.0 / (el / max(iters, 1) * gpu_outer_iters)
-    return {"value": value, "unit": "solves/s", "cores": threads, "kind": "oracle",
-            "sample": f"{N}^2 configuration 0, right-hand sides 0..{len(lat) - 1} solved to 1e-8 in {el:.1f} s "
-                      f"({iters} outer iterations; the first solve includes GMRES-DR); oracle setup "
-                      f"{setup_s:.1f} s not charged; scipy sparse products are single-threaded",
+    def run(budget):
+        iters = 0
+
+        def counted_cycle(v):
+            nonlocal iters
+            iters += 1
+            return orig(v)
+        H.cycle0 = counted_cycle
+        H.deflation = krylov.Deflation()  # a fresh space: the first solve pays for GMRES-DR
+        solves, lat = 0, []
+        t0 = time.perf_counter()
+        for j in range(RHS_PER_CONFIG):
+            if time.perf_counter() - t0 > budget:
+                break
+            t1 = time.perf_counter()
+            _, info = H.solve(synth.rhs(N, 0, j))
+            lat.append(time.perf_counter() - t1)
+            solves += 1 if info.converged else 0
+        el = time.perf_counter() - t0
+        H.cycle0 = orig
+        value = solves / el if solves else 1.0 / (el / max(iters, 1) * gpu_outer_iters)
+        return value, el, iters, len(lat)
+
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            v1, el1, it1, n1 = run(budget_s)
+        blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    else:
+        v1, el1, it1, n1 = run(budget_s)
+        blas_threads = 1
+    vm, elm, itm, nm = run(budget_s / 2)
+    return {"value": v1, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"{N}^2 configuration 0, right-hand sides 0..{n1 - 1} solved to 1e-8 in {el1:.1f} s "
+                      f"({it1} outer iterations; the first solve includes GMRES-DR), one thread; oracle setup "
+                      f"{setup_s:.1f} s not charged",
+            "blas_threads_run": {"value": vm, "blas_threads": blas_threads, "solves": nm, "seconds": elm,
+                                 "note": "scipy sparse products stay single-threaded; only small dense steps "
+                                         "use the BLAS threads"},
             "cpu": platform.processor() or platform.machine(), "host_cpus": os.cpu_count()}
 
 

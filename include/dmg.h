@@ -201,7 +201,10 @@ dmg_status dmg_hierarchy_apply(dmg_hierarchy* h, int level, int op, dmg_precisio
 /* Coarse-grid deflation space (Methods section): EMPTY until the first coarse
  * solve runs GMRES-DR(m, k), which leaves A V_k = V_{k+1} Hbar_k; READY after
  * that, when every coarse solve is GMRES-Proj(m, k).  Tied to one hierarchy.
- * Sizes: 1 <= k < m <= 64 and k <= 31 (DMG_E_INVALID otherwise). */
+ * Sizes: 1 <= k < m <= 256 and k <= 64 (DMG_E_INVALID otherwise).  Spaces with m <= 64
+ * and k <= 31 use the short-cycle solvers (persistent coarse kernels); larger ones (the
+ * paper's (200, 40)) the long-cycle FP64 solvers, one launch per Arnoldi sub-step, also
+ * under an FP32 preconditioner.  The lockstep and batch forms need m - k <= 24. */
 dmg_status dmg_deflation_create(dmg_hierarchy* h, int m, int k, dmg_deflation** out);
 /* Fill the space now by GMRES-DR on the given coarse right-hand side (FP64,
  * 24 * (Nx/16) * (Nt/16) complex) to tol. */
@@ -228,10 +231,10 @@ typedef struct {
   int coarse_max_iters;    /* cap on coarse Arnoldi steps per call (5000) */
   dmg_precision precond;   /* preconditioner precision (outer is FP64) */
   int use_x0;              /* 1: x holds the initial guess */
-  int coarse_persistent;   /* each GMRES-Proj coarse solve as one persistent kernel: 1 cooperative
-                              launch (default), 2 plain launch (only when nothing else runs on
-                              the device: the grid must become co-resident); 0: one launch per
-                              Arnoldi sub-step */
+  int coarse_persistent;   /* each GMRES-Proj coarse solve as one persistent kernel in one
+                              cooperative launch (1, the default; the runtime places the whole
+                              grid at once), or 0: one launch per Arnoldi sub-step.  Other values
+                              are DMG_E_INVALID */
   int int_mode;            /* intermediate grid: 0 partial solve (FGMRES(int_m) to int_tol, the
                               default); 1 one intermediate cycle (smoothing-only treatment) */
   int graphs;              /* lockstep solves (dmg_solve_batched, dmg_batch_*): 1 replays each
@@ -289,15 +292,22 @@ dmg_status dmg_solve(dmg_context* ctx, dmg_hierarchy* h, dmg_deflation* d, const
                      const void* b, void* x, int nrhs, int ptr_kind, dmg_solve_stats* stats);
 
 /* Fine-grid comparison solvers without multigrid (the paper's baselines, Results):
- *   DMG_FINE_CGNE      CG on D D^dagger y = b, x = D^dagger y, all nrhs fields in one
- *                      batched CG (m, k ignored); stats: outer_iters = CG iterations,
- *                      fine_mvps = 2 per iteration + 1
- *   DMG_FINE_GMRES_DR  GMRES-DR(m, k) on D from 0 for each right-hand side with a fresh
- *                      deflation space (2 <= m <= 64, 1 <= k < m, k <= 31); outer_iters =
- *                      Arnoldi steps
- * Both stop at relative residual tol (max_iters: CG iterations or Arnoldi steps) and report
- * the true relative residual.  b, x: nrhs fields (host or device by ptr_kind). */
-enum { DMG_FINE_CGNE = 0, DMG_FINE_GMRES_DR = 1 };
+ *   DMG_FINE_CGNE        CG on D D^dagger y = b, x = D^dagger y, all nrhs fields in one
+ *                        batched CG (m, k ignored); stats: outer_iters = CG iterations,
+ *                        fine_mvps = 2 per iteration + 1
+ *   DMG_FINE_GMRES_DR    GMRES-DR(m, k) on D from 0 for each right-hand side with a fresh
+ *                        deflation space (2 <= m <= 256, 1 <= k < m, k <= 64; the paper's
+ *                        fine-grid runs use (200, 40)); outer_iters = Arnoldi steps
+ *   DMG_FINE_GMRES_PROJ  GMRES-DR(m, k) on the first right-hand side, whose final space
+ *                        A V_k = V_{k+1} Hbar_k then serves GMRES-Proj(m, k) (projection over
+ *                        the space, then GMRES(m - k) cycles) on every later right-hand side of
+ *                        the call (the paper's multiple right-hand-side comparison); sizes as
+ *                        above; coarse_dr_calls = 1 on the first right-hand side only
+ * All stop at relative residual tol (max_iters: CG iterations or Arnoldi steps) and report
+ * the true relative residual.  b, x: nrhs fields (host or device by ptr_kind).  Cycles longer
+ * than 64 (or k > 31) run the long-cycle solvers: FP64 state in device memory, the
+ * harmonic-Ritz restart in one workgroup. */
+enum { DMG_FINE_CGNE = 0, DMG_FINE_GMRES_DR = 1, DMG_FINE_GMRES_PROJ = 2 };
 dmg_status dmg_solve_fine(dmg_context* ctx, dmg_hierarchy* h, int method, int m, int k, double tol, int max_iters,
                           const void* b, void* x, int nrhs, int ptr_kind, dmg_solve_stats* stats);
 
@@ -387,10 +397,9 @@ void dmg_batch_destroy(dmg_batch* bt);
  * an earlier dmg_solve) and is only read, so results do not depend on arrival
  * order; d == NULL selects the non-deflated method.  A hierarchy and its deflation
  * space must outlive the slots that use them and must not be rebuilt or reset
- * while admitted.  Persistent coarse solves in a pool are launched cooperatively
- * (coarse_persistent 2 is taken as 1): the runtime then places the whole grid at
- * once, while a plain-launched grid could wait behind the other slots' kernels for
- * its last workgroups.  At most DMG_POOL_MAX_SLOTS slots.
+ * while admitted.  Persistent coarse solves are launched cooperatively, so the runtime
+ * places the whole grid at once and no workgroup of it waits behind the other slots'
+ * kernels.  At most DMG_POOL_MAX_SLOTS slots.
  * ------------------------------------------------------------------------- */
 typedef struct dmg_pool dmg_pool;
 #define DMG_POOL_MAX_SLOTS 8

@@ -3,8 +3,8 @@ store them in ``synth/mcrit.json`` (the bare mass of every workload is m_c + 0.0
 
     python -m oracle.make_mcrit --sizes 64:4,128:4,256:10,512:4 --jobs 4
 
-Each entry is m_c = -min Re lambda(D(0)) of configuration (N, cfg); the shift-invert
-search also records the imaginary-part guard described in ``oracle.mcrit``.
+Each entry is m_c = -min Re lambda(D(0)) of configuration (N, cfg); the covered search
+also records the range of imaginary parts it covered (``im_guard``, see ``oracle.mcrit``).
 Existing entries are kept unless --force is given.
 """
 from __future__ import annotations
@@ -38,11 +38,14 @@ def main(argv=None):
     ap.add_argument("--force", action="store_true")
     a = ap.parse_args(argv)
     path = synth.MCRIT_FILE
-    table = {"mc": {}, "im_guard": {}, "method": "oracle.mcrit.critical_mass (dense eig up to 32^2, "
-             "shift-invert ARPACK about sigma = 0 above)"}
+    method = ("oracle.mcrit.critical_mass (dense eig up to 32^2; above, shift-invert ARPACK discs covering "
+              "the Bendixson strip of the leftmost eigenvalue, im_guard = the covered range of imaginary parts)")
+    table = {"mc": {}, "im_guard": {}, "method": method}
     if os.path.exists(path):
         with open(path) as f:
             table = json.load(f)
+    if a.force:
+        table["method"] = method
     jobs = []
     for item in a.sizes.split(","):
         N, count = (int(v) for v in item.split(":"))

@@ -20,7 +20,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libdmg.so")
-SOURCES = ["stencil.hip", "blas.hip", "dense.hip", "setup.hip", "coarse.hip", "solver.hip", "mrhs.hip", "msolve.hip", "pool.hip", "api.hip"]
+SOURCES = ["stencil.hip", "blas.hip", "dense.hip", "setup.hip", "coarse.hip", "solver.hip", "bigkrylov.hip", "mrhs.hip",
+           "msolve.hip", "pool.hip", "api.hip"]
 ARCH = "gfx950"
 
 

@@ -7,6 +7,7 @@
 #include <new>
 #include <unordered_map>
 
+#include "bigkrylov.h"
 #include "mrhs.h"
 #include "solver.h"
 
@@ -443,8 +444,8 @@ dmg_status dmg_deflation_create(dmg_hierarchy* h, int m, int k, dmg_deflation** 
   if (!h || !out) return DMG_E_INVALID;
   return guarded(h->ctx, [&]() -> dmg_status {
     *out = nullptr;
-    DMG_CHECK(m >= 2 && m <= MMAX && k >= 1 && k < m && k <= 31, DMG_E_INVALID,
-              "deflation sizes need 1 <= k < m <= 64 and k <= 31");
+    DMG_CHECK(m >= 2 && m <= MBIG && k >= 1 && k < m && k <= KBIG, DMG_E_INVALID,
+              "deflation sizes need 1 <= k < m <= 256 and k <= 64");
     dmg_deflation* d = new dmg_deflation();
     d->h = h;
     d->m = m;
@@ -506,7 +507,7 @@ dmg_status dmg_solve(dmg_context* ctx, dmg_hierarchy* h, dmg_deflation* d, const
     if (prm) p = *prm;
     DMG_CHECK(p.tol > 0.0 && p.int_tol > 0.0 && p.coarse_tol_first > 0.0 && p.coarse_tol_later > 0.0 &&
                   p.max_outer_iters >= 1 && p.int_max_iters >= 1 && p.coarse_max_iters >= 1 &&
-                  (p.int_mode == 0 || p.int_mode == 1),
+                  (p.int_mode == 0 || p.int_mode == 1) && (p.coarse_persistent == 0 || p.coarse_persistent == 1),
               DMG_E_INVALID, "solve parameters");
     const int64_t n = h->op[0].n;
     const size_t fb = sizeof(double2) * n;
@@ -564,8 +565,7 @@ dmg_status dmg_hierarchy_apply_batched(dmg_hierarchy* h, int level, int op, dmg_
     go.alloc(c, es * nout * nb);
     const Op& A = h->op[level];
     const Transfer& tr = h->tr[level < 2 ? level : 1];
-    const bool was = b_block_mfma_enabled();
-    b_block_mfma_enable(mfma != 0);
+    const bool use_mfma = mfma != 0;
     auto run = [&](auto tag) {
       using T = decltype(tag);
       using R = decltype(T{}.x);
@@ -577,14 +577,15 @@ dmg_status dmg_hierarchy_apply_batched(dmg_hierarchy* h, int level, int op, dmg_
         const bool b16 = sizeof(R) == sizeof(float) && p == DMG_FP32_BF16 && level == 1;
         if (A.kind == 0) b_tune_wilson<R>(s, U, gi.as<T>(), go.as<T>(), A.m0, A.Lx, A.Lt, nb);
         else if (b16)
-          b_tune_block_bf16(s, h->A16.as<bf16c>(), (const float2*)gi.as<T>(), (float2*)go.as<T>(), A.Lx, A.Lt, nb);
-        else b_tune_block<R>(s, Ab, gi.as<T>(), go.as<T>(), A.Lx, A.Lt, nb);
+          b_tune_block_bf16(s, h->A16.as<bf16c>(), (const float2*)gi.as<T>(), (float2*)go.as<T>(), A.Lx, A.Lt, nb,
+                            use_mfma);
+        else b_tune_block<R>(s, Ab, gi.as<T>(), go.as<T>(), A.Lx, A.Lt, nb, use_mfma);
         hipEvent_t ta = timer_mark(c, kt, s);
         if (A.kind == 0) launch_b_wilson<R>(s, U, gi.as<T>(), go.as<T>(), A.m0, A.Lx, A.Lt, nb, nullptr);
         else if (b16)
           launch_b_block_bf16(s, h->A16.as<bf16c>(), (const float2*)gi.as<T>(), (float2*)go.as<T>(), A.Lx, A.Lt, nb,
-                              nullptr);
-        else launch_b_block<R>(s, Ab, gi.as<T>(), go.as<T>(), A.Lx, A.Lt, nb, nullptr);
+                              nullptr, nullptr, use_mfma);
+        else launch_b_block<R>(s, Ab, gi.as<T>(), go.as<T>(), A.Lx, A.Lt, nb, nullptr, nullptr, use_mfma);
         if (ta) timer_span(c, kt, ta, timer_mark(c, kt, s), (long long)A.Lx * A.Lt * nb);
       } else if (op == DMG_OP_RESTRICT) {
         launch_b_restrict<R>(s, tr.P((const T*)nullptr), gi.as<T>(), go.as<T>(), tr.Lx, tr.Lt, tr.dof, nb);
@@ -593,14 +594,8 @@ dmg_status dmg_hierarchy_apply_batched(dmg_hierarchy* h, int level, int op, dmg_
       }
       launch_b_scatter<T>(s, go.as<T>(), (T*)dout, nout, nrhs, nb);
     };
-    try {
-      if (p == DMG_FP64) run(double2{});
-      else run(float2{});
-    } catch (...) {
-      b_block_mfma_enable(was);
-      throw;
-    }
-    b_block_mfma_enable(was);
+    if (p == DMG_FP64) run(double2{});
+    else run(float2{});
     if (ptr_kind == DMG_PTR_HOST) from_device(c, out, bo.p, es * nout * nrhs, DMG_PTR_HOST);
     else DMG_HIP(hipStreamSynchronize(s));
     return DMG_OK;
@@ -614,7 +609,8 @@ dmg_status dmg_solve_fine(dmg_context* ctx, dmg_hierarchy* h, int method, int m,
     DMG_CHECK(h->ctx == ctx, DMG_E_INVALID, "hierarchy belongs to another context");
     DMG_CHECK(b && x && nrhs >= 1 && nrhs <= 64 && tol > 0.0 && max_iters >= 1, DMG_E_INVALID,
               "solve_fine: bad arguments");
-    DMG_CHECK(method == DMG_FINE_CGNE || method == DMG_FINE_GMRES_DR, DMG_E_INVALID, "solve_fine: method");
+    DMG_CHECK(method == DMG_FINE_CGNE || method == DMG_FINE_GMRES_DR || method == DMG_FINE_GMRES_PROJ, DMG_E_INVALID,
+              "solve_fine: method");
     DMG_CHECK(ptr_kind == DMG_PTR_HOST || ptr_kind == DMG_PTR_DEVICE, DMG_E_INVALID, "pointer kind");
     const int64_t n = h->op[0].n;
     const size_t fb = sizeof(double2) * n * nrhs;

@@ -542,6 +542,18 @@ __global__ void k_scale_dev(int64_t n, const cx<R>* __restrict__ x, cx<R>* __res
     y[e] = from_d<R>(cscale(to_d(x[e]), f));
 }
 
+// status[0] = 1 unless after > rel2 * before (squared norms of a vector before and after it was
+// orthogonalised against earlier ones: the set has lost rank)
+__global__ void k_rank_test(const double* before, const double* after, double rel2, int* status) {
+  const double b = before[0], a = after[0];
+  if (!(a > rel2 * b) || !(a > 0.0)) status[0] = 1;
+}
+
+void launch_rank_test(hipStream_t s, const double* before, const double* after, double rel2, int* status) {
+  hipLaunchKernelGGL(k_rank_test, dim3(1), dim3(1), 0, s, before, after, rel2, status);
+  DMG_LAUNCH_CHECK();
+}
+
 template <typename R>
 void launch_scale_dev(hipStream_t s, int64_t n, const cx<R>* x, cx<R>* y, const double* scale, int invert_sqrt) {
   hipLaunchKernelGGL(k_scale_dev<R>, dim3(red_blocks(n)), dim3(RB), 0, s, n, x, y, scale, invert_sqrt);

@@ -76,6 +76,7 @@ void launch_basis_rotate(hipStream_t s, const cx<R>* Vin, cx<R>* Vout, int64_t l
 // y = x * scale (scale on device, FP64)
 template <typename R>
 void launch_scale_dev(hipStream_t s, int64_t n, const cx<R>* x, cx<R>* y, const double* scale, int invert_sqrt);
+void launch_rank_test(hipStream_t s, const double* before, const double* after, double rel2, int* status);
 
 // Two-step GMRES smoother from x0 = 0 given w1 = A v and w2 = A w1: y = c0 v + c1 w1
 // minimising || v - A y ||, and r = v - A y (skipped when r is null).  coef: 2 device double2.

@@ -52,16 +52,15 @@ enum { TK_BLOCK = 0, TK_WILSON = 1, TK_COUNT = 2 };
 int tuned_form(int kernel, int prec_bytes, int sites, int nb);  // 0 (default form) until tuned
 // time the forms of the batched block / Wilson stencil on these buffers (in is read, out written)
 template <typename R>
-void b_tune_block(hipStream_t s, const cx<R>* A, const cx<R>* in, cx<R>* out, int Lx, int Lt, int nb);
+void b_tune_block(hipStream_t s, const cx<R>* A, const cx<R>* in, cx<R>* out, int Lx, int Lt, int nb,
+                  bool mfma = true);
 template <typename R>
 void b_tune_wilson(hipStream_t s, const cx<R>* U, const cx<R>* in, cx<R>* out, double m0, int Nx, int Nt, int nb);
-void b_tune_block_bf16(hipStream_t s, const bf16c* A, const float2* in, float2* out, int Lx, int Lt, int nb);
+void b_tune_block_bf16(hipStream_t s, const bf16c* A, const float2* in, float2* out, int Lx, int Lt, int nb,
+                       bool mfma = true);
 void b_tune_mode(int mode);              // 0 off (default forms), 1 on, 2 on and forget earlier choices
 void b_tune_force(int kernel, int form);  // form >= 0 overrides the choice; -1 restores it
 std::string b_tune_report();
-// FP32 batched block stencil on the matrix cores (nb >= 16); off: the vector-FMA kernel
-bool b_block_mfma_enabled();
-void b_block_mfma_enable(bool on);
 size_t bred_partials(int nb);  // double2 entries of reduction scratch
 
 // ||x_r||^2 per right-hand side; mode 0: out[r]; mode 3: bs[r].bnorm = ||x_r||;
@@ -107,10 +106,10 @@ void launch_b_wilson(hipStream_t s, const cx<R>* U, const cx<R>* in, cx<R>* out,
                      const cx<R>* sub, const BS* skip = nullptr);
 template <typename R>
 void launch_b_block(hipStream_t s, const cx<R>* A, const cx<R>* in, cx<R>* out, int Lx, int Lt, int nb,
-                    const cx<R>* sub, const BS* skip = nullptr);
+                    const cx<R>* sub, const BS* skip = nullptr, bool mfma = true);
 // block stencil with BF16-stored blocks, FP32 fields and arithmetic
 void launch_b_block_bf16(hipStream_t s, const bf16c* A, const float2* in, float2* out, int Lx, int Lt, int nb,
-                         const float2* sub, const BS* skip = nullptr);
+                         const float2* sub, const BS* skip = nullptr, bool mfma = true);
 template <typename R>
 void launch_b_restrict(hipStream_t s, const cx<R>* P, const cx<R>* fine, cx<R>* coarse, int Lx, int Lt, int dof,
                        int nb);

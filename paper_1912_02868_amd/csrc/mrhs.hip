@@ -24,9 +24,6 @@ int bred_blocks(int64_t N) {
 }
 size_t bred_partials(int nb) { return (size_t)BMAXBLK * MQ * nb; }
 
-static bool g_block_mfma = true;
-bool b_block_mfma_enabled() { return g_block_mfma; }
-void b_block_mfma_enable(bool on) { g_block_mfma = on; }
 
 static inline int vec_blocks(int64_t N) { return (int)std::max<int64_t>(1, std::min<int64_t>((N + BT - 1) / BT, 4096)); }
 
@@ -1132,15 +1129,16 @@ static void tune_shape(hipStream_t s, int kernel, int prec, int sites, int nb, i
 }
 
 template <typename R>
-void b_tune_block(hipStream_t s, const cx<R>* A, const cx<R>* in, cx<R>* out, int Lx, int Lt, int nb) {
-  if (nb < 16 || !b_block_mfma_enabled()) return;
+void b_tune_block(hipStream_t s, const cx<R>* A, const cx<R>* in, cx<R>* out, int Lx, int Lt, int nb, bool mfma) {
+  if (nb < 16 || !mfma) return;
   tune_shape(s, TK_BLOCK, sizeof(R), Lx * Lt, nb, block_forms(nb), [&](int f) {
     launch_block_form<R, cx<R>>(s, f, A, in, out, Lx, Lt, nb, nullptr, nullptr);
   });
 }
 
-void b_tune_block_bf16(hipStream_t s, const bf16c* A, const float2* in, float2* out, int Lx, int Lt, int nb) {
-  if (nb < 16 || !b_block_mfma_enabled()) return;
+void b_tune_block_bf16(hipStream_t s, const bf16c* A, const float2* in, float2* out, int Lx, int Lt, int nb,
+                       bool mfma) {
+  if (nb < 16 || !mfma) return;
   tune_shape(s, TK_BLOCK, 2, Lx * Lt, nb, block_forms(nb), [&](int f) {
     launch_block_form<float, bf16c>(s, f, A, in, out, Lx, Lt, nb, nullptr, nullptr);
   });
@@ -1185,8 +1183,9 @@ std::string b_tune_report() {
 
 template <typename R>
 void launch_b_block(hipStream_t s, const cx<R>* A, const cx<R>* in, cx<R>* out, int Lx, int Lt, int nb,
-                    const cx<R>* sub, const BS* skip) {
-  if (nb >= 16 && b_block_mfma_enabled()) {
+                    const cx<R>* sub, const BS* skip, bool mfma) {
+  // blocks on the matrix cores from 16 lanes on; mfma = false forces the vector-FMA kernel
+  if (nb >= 16 && mfma) {
     launch_block_form<R, cx<R>>(s, tuned_form(TK_BLOCK, sizeof(R), Lx * Lt, nb), A, in, out, Lx, Lt, nb, sub, skip);
     return;
   }
@@ -1197,8 +1196,8 @@ void launch_b_block(hipStream_t s, const cx<R>* A, const cx<R>* in, cx<R>* out, 
 }
 
 void launch_b_block_bf16(hipStream_t s, const bf16c* A, const float2* in, float2* out, int Lx, int Lt, int nb,
-                         const float2* sub, const BS* skip) {
-  if (nb >= 16 && b_block_mfma_enabled()) {
+                         const float2* sub, const BS* skip, bool mfma) {
+  if (nb >= 16 && mfma) {
     launch_block_form<float, bf16c>(s, tuned_form(TK_BLOCK, 2, Lx * Lt, nb), A, in, out, Lx, Lt, nb, sub, skip);
     return;
   }
@@ -1369,14 +1368,14 @@ void launch_b_set_state(hipStream_t s, BS* bs, const int* host_st, int nb) {
   template void launch_b_wilson<R>(hipStream_t, const cx<R>*, const cx<R>*, cx<R>*, double, int, int, int,            \
                                    const cx<R>*, const BS*);                                                           \
   template void launch_b_block<R>(hipStream_t, const cx<R>*, const cx<R>*, cx<R>*, int, int, int, const cx<R>*,       \
-                                  const BS*);                                                                          \
+                                  const BS*, bool);                                                                        \
   template void launch_b_restrict<R>(hipStream_t, const cx<R>*, const cx<R>*, cx<R>*, int, int, int, int);            \
   template void launch_b_prolong<R>(hipStream_t, const cx<R>*, const cx<R>*, cx<R>*, int, int, int, int, int);
 INST(double)
 INST(float)
 #undef INST
-template void b_tune_block<float>(hipStream_t, const float2*, const float2*, float2*, int, int, int);
-template void b_tune_block<double>(hipStream_t, const double2*, const double2*, double2*, int, int, int);
+template void b_tune_block<float>(hipStream_t, const float2*, const float2*, float2*, int, int, int, bool);
+template void b_tune_block<double>(hipStream_t, const double2*, const double2*, double2*, int, int, int, bool);
 template void b_tune_wilson<float>(hipStream_t, const float2*, const float2*, float2*, double, int, int, int);
 template void b_tune_wilson<double>(hipStream_t, const double2*, const double2*, double2*, double, int, int, int);
 

@@ -118,12 +118,9 @@ dmg_status dmg_pool_create(dmg_context* ctx, int capacity, const dmg_solve_param
     DMG_CHECK(p.tol > 0.0 && p.int_tol > 0.0 && p.coarse_tol_first > 0.0 && p.coarse_tol_later > 0.0 &&
                   p.max_outer_iters >= 1 && p.int_max_iters >= 1 && p.coarse_max_iters >= 1 &&
                   p.outer_m >= 1 && p.outer_m <= MMAX && p.int_m >= 1 && p.int_m <= MMAX &&
-                  p.smooth_steps >= 1 && p.smooth_steps <= MMAX && !p.use_x0,
+                  p.smooth_steps >= 1 && p.smooth_steps <= MMAX && !p.use_x0 &&
+                  (p.coarse_persistent == 0 || p.coarse_persistent == 1),
               DMG_E_INVALID, "pool solve parameters (use_x0 is not supported)");
-    // Persistent coarse solves in a batch use cooperative launches, which the runtime
-    // places only when the whole grid fits: a plain-launched grid on one stream can
-    // wait behind the other slots' work for its last workgroups.
-    if (p.coarse_persistent == 2) p.coarse_persistent = 1;
     std::unique_ptr<dmg_pool> pl(new dmg_pool());
     pl->ctx = ctx;
     pl->cap = capacity;

@@ -83,6 +83,8 @@ struct Counters {
 template <typename R> struct Precond;
 struct BWork;                 // lane engine of the lockstep multi-right-hand-side solve
 void destroy_bwork(BWork* b);
+struct BigWS;                 // workspace of the long-cycle GMRES-DR / GMRES-Proj (bigkrylov.hip)
+void destroy_bigws(BigWS* b);
 
 // Mutable state of one solve in flight: its stream, reduction scratch, status mirror,
 // Mvp counters and every Krylov workspace.  A hierarchy owns one (for dmg_solve and
@@ -105,6 +107,7 @@ struct Work {
   DevBuf dr_Vtmp, dr_P, dr_work, dr_coef;
   DevBuf dr_xchg, dr_flags;  // persistent GMRES-DR cycle: exchange field, barrier flags
   int dr_m = 0, dr_k = 0;
+  BigWS* big = nullptr;      // long-cycle solvers (allocated on first use)
   // state of a resumable outer solve (one right-hand side)
   struct Run {
     dmg_hierarchy* h = nullptr;
@@ -183,5 +186,15 @@ void prepare_deflation_fp32(Work* w, dmg_deflation* d);
 dmg_status batched_solve(dmg_hierarchy* h, dmg_deflation* d, const dmg_solve_params* p, const double2* b, double2* x,
                          int nrhs, dmg_solve_stats* st);
 void sync_status(Work* w, const KState* ks, KStatus* out);
+// Long-cycle GMRES-DR(m, k) on A from x = 0 (m <= 256, k <= 64, FP64); fills d (V_{k+1}, Hbar_k and the
+// projection matrices) when d is not null.  Returns the Arnoldi steps taken.
+int big_gmres_dr(dmg_context* ctx, Work* w, const Op& A, int m, int k, const double2* b, double2* x, double tol,
+                 int max_iters, dmg_deflation* d);
+// Long-cycle GMRES-Proj(m, k) on A from x = 0 over the ready space d; returns the Arnoldi steps taken and
+// the final residual estimate relative to ||b|| in rel_est.
+int big_gmres_proj(Work* w, const Op& A, const dmg_deflation* d, const double2* b, double2* x, double tol,
+                   int max_iters, double* rel_est);
+// deflation spaces beyond the short-cycle state (m > 64 or k > 31) use the long-cycle solvers
+inline bool big_deflation(int m, int k) { return m > MMAX || k > 31; }
 
 }  // namespace dmg

@@ -13,6 +13,7 @@
 #include <limits>
 #include <vector>
 
+#include "bigkrylov.h"
 #include "solver.h"
 
 namespace dmg {
@@ -77,6 +78,8 @@ void Work::init(dmg_context* c, hipStream_t s, bool owns) {
 
 Work::~Work() {
   if (stream) (void)hipStreamSynchronize(stream);
+  destroy_bigws(big);
+  big = nullptr;
   pc64.reset();
   pc32.reset();
   if (host_status) (void)hipHostFree(host_status);
@@ -108,6 +111,11 @@ static void check_dr_status(Work* w) {
 int coarse_gmres_dr(dmg_hierarchy* h, Work* w, dmg_deflation* d, const double2* b, double2* x, double tol,
                     int max_iters, int lvl, int persistent) {
   const int m = d->m, k = d->k;
+  if (big_deflation(m, k)) {
+    const int it = big_gmres_dr(h->ctx, w, h->op[lvl], m, k, b, x, tol, max_iters, d);
+    w->cnt.dr_calls++;
+    return it;
+  }
   DMG_CHECK(m <= MMAX && k >= 1 && k < m, DMG_E_INVALID, "GMRES-DR sizes");
   ensure_dr(h, w, m, k, lvl);
   hipStream_t s = w->stream;
@@ -264,21 +272,32 @@ static void cg_normal(dmg_hierarchy* h, Work* w, int lvl, int nvec, const double
 
 // ---------------------------------------------------------------- setup
 // Global orthonormalisation: modified Gram-Schmidt over the whole lattice, two passes.
+// Modified Gram-Schmidt applied twice, vectors in index order.  A vector whose norm falls
+// below 1e-12 of its norm before the passes makes the set rank-deficient (DMG_E_BREAKDOWN), the
+// criterion of the local orthonormalisation.
 static void global_mgs2(dmg_hierarchy* h, Work* w, double2* W, int64_t n, int nvec) {
   hipStream_t s = w->stream;
   DevBuf coef;
   coef.alloc(h->ctx, sizeof(double2) * 4);
   double2* c = coef.as<double2>();
+  int* status = w->flags.as<int>();
+  DMG_HIP(hipMemsetAsync(status, 0, sizeof(int), s));
   for (int k = 0; k < nvec; ++k) {
     double2* wk = W + (int64_t)k * n;
+    launch_norm2<double>(s, n, wk, (double*)(c + 3), PART(w), CNT(w));
     for (int pass = 0; pass < 2; ++pass)
       for (int j = 0; j < k; ++j) {
         launch_multidot<double>(s, W + (int64_t)j * n, n, 1, wk, n, c, PART(w), CNT(w));
         launch_multi_axpy<double>(s, wk, W + (int64_t)j * n, n, 1, c, n, 1.0);
       }
     launch_norm2<double>(s, n, wk, (double*)(c + 2), PART(w), CNT(w));
+    launch_rank_test(s, (const double*)(c + 3), (const double*)(c + 2), 1e-24, status);
     launch_scale_dev<double>(s, n, wk, wk, (const double*)(c + 2), 1);
   }
+  int st = 0;
+  DMG_HIP(hipMemcpyAsync(&st, status, sizeof(int), hipMemcpyDeviceToHost, s));
+  DMG_HIP(hipStreamSynchronize(s));
+  DMG_CHECK(st == 0, DMG_E_BREAKDOWN, "global orthonormalisation: the near-null vectors are linearly dependent");
 }
 
 void build_hierarchy(dmg_hierarchy* h, const double2* start0, const double2* start1, int inject) {
@@ -534,6 +553,21 @@ struct Precond {
         launch_cast_f2d(S(), n, (const float2*)b, bc64.as<double2>());
         coarse_gmres_dr(h, w, defl, bc64.as<double2>(), ec64.as<double2>(), p->coarse_tol_first, p->coarse_max_iters, 2,
                         p->coarse_persistent);
+        launch_cast_d2f(S(), n, ec64.as<double2>(), (float2*)x);
+      }
+      return;
+    }
+    if (big_deflation(defl->m, defl->k)) {
+      // long cycles: GMRES-Proj in FP64 on the kernel-per-step path (also under an FP32 preconditioner)
+      const int64_t n = h->op[2].n;
+      double rel = 0.0;
+      if constexpr (sizeof(R) == sizeof(double)) {
+        big_gmres_proj(w, h->op[2], defl, (const double2*)b, (double2*)x, p->coarse_tol_later, p->coarse_max_iters,
+                       &rel);
+      } else {
+        launch_cast_f2d(S(), n, (const float2*)b, bc64.as<double2>());
+        big_gmres_proj(w, h->op[2], defl, bc64.as<double2>(), ec64.as<double2>(), p->coarse_tol_later,
+                       p->coarse_max_iters, &rel);
         launch_cast_d2f(S(), n, ec64.as<double2>(), (float2*)x);
       }
       return;
@@ -872,7 +906,11 @@ dmg_status fine_solve(dmg_hierarchy* h, int method, int m, int k, double tol, in
       all = all && o.converged;
     }
   } else {
-    DMG_CHECK(m >= 2 && m <= MMAX && k >= 1 && k < m && k <= 31, DMG_E_INVALID, "fine GMRES-DR sizes");
+    // GMRES-DR(m, k) with a fresh space per right-hand side, or (DMG_FINE_GMRES_PROJ) GMRES-DR on the
+    // first right-hand side and GMRES-Proj(m, k) over its space on every later one
+    DMG_CHECK(m >= 2 && m <= MBIG && k >= 1 && k < m && k <= KBIG, DMG_E_INVALID, "fine GMRES-DR sizes");
+    const bool proj = method == DMG_FINE_GMRES_PROJ;
+    const bool big = proj || big_deflation(m, k);
     dmg_deflation d;
     d.h = h;
     d.m = m;
@@ -883,7 +921,11 @@ dmg_status fine_solve(dmg_hierarchy* h, int method, int m, int k, double tol, in
     for (int f = 0; f < nrhs; ++f) {
       auto t0 = std::chrono::steady_clock::now();
       w->cnt = Counters{};
-      const int it = coarse_gmres_dr(h, w, &d, b + f * n, x + f * n, tol, max_iters, 0);
+      int it;
+      const bool first = !proj || f == 0;
+      if (!big) it = coarse_gmres_dr(h, w, &d, b + f * n, x + f * n, tol, max_iters, 0);
+      else if (first) it = big_gmres_dr(h->ctx, w, A, m, k, b + f * n, x + f * n, tol, max_iters, proj ? &d : nullptr);
+      else it = big_gmres_proj(w, A, &d, b + f * n, x + f * n, tol, max_iters, nullptr);
       A.apply(s, x + f * n, rn.as<double2>(), 0, nullptr, b + f * n);
       launch_norm2<double>(s, n, rn.as<double2>(), scal.as<double>(), PART(w), CNT(w));
       launch_norm2<double>(s, n, b + f * n, scal.as<double>() + 1, PART(w), CNT(w));
@@ -898,7 +940,7 @@ dmg_status fine_solve(dmg_hierarchy* h, int method, int m, int k, double tol, in
       o.fine_equiv_mvps = (double)it;
       o.true_rel_resid = v[1] > 0.0 ? std::sqrt(v[0] / v[1]) : 0.0;
       o.converged = o.true_rel_resid <= tol * (1.0 + 1e-6) ? 1 : 0;
-      o.coarse_dr_calls = 1;
+      o.coarse_dr_calls = first ? 1 : 0;
       o.elapsed_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
       all = all && o.converged;
     }

@@ -407,7 +407,7 @@ class Deflation:
             pass
 
 
-FINE_CGNE, FINE_GMRES_DR = 0, 1
+FINE_CGNE, FINE_GMRES_DR, FINE_GMRES_PROJ = 0, 1, 2
 
 
 def solve_fine(ctx: Context, hier: Hierarchy, method: int, b, x, nrhs: int = 1, tol: float = 1e-8,

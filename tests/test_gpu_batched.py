@@ -165,8 +165,7 @@ def test_batched_operators(dmg, inj64, prec, nrhs, mfma):
             rel = np.linalg.norm(out[r] - ref) / np.linalg.norm(ref)
             elem = np.max(np.abs(out[r] - ref)) / np.max(np.abs(ref))
             if prec == "fp64":
-                tol = 1e-13 if lvl == 0 else 1e-12
-                assert rel < tol and elem < tol, (lvl, r, rel, elem)
+                assert rel < 1e-13 and elem < 1e-13, (lvl, r, rel, elem)
             else:
                 assert rel < 2e-6 and elem < 1e-5, (lvl, r, rel, elem)
 

@@ -1,0 +1,180 @@
+"""The paper's deflation sizes (200, 40) on the device, against the FP64 oracle.
+
+- Fine-grid GMRES-DR(200, 40) and the multiple right-hand-side comparator (GMRES-DR on the
+  first right-hand side, GMRES-Proj(200, 40) over its space on the later ones), 64^2 at 0.01
+  above the critical mass: each solution against sparse LU of the oracle's D, Arnoldi step
+  counts beside the oracle's gmres_dr / gmres_proj on the same systems.
+- Coarse GMRES-DR(200, 40) to 1e-15 (the first coarse solve of the paper's deflated multigrid
+  with smoothing only): the kept space satisfies A V_k = V_{k+1} Hbar_k with the oracle's D_c
+  and holds its smallest eigenvalues; then whole multigrid solves with the smoothing-only
+  intermediate grid and the 1e-15 / 1e-8 coarse schedule reach the LU solution.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import krylov, multigrid, wilson
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+spla = pytest.importorskip("scipy.sparse.linalg")
+
+
+@pytest.fixture(scope="module")
+def dmg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1912_02868_amd as dmg
+    dmg.lib()
+    return dmg
+
+
+@pytest.fixture(scope="module")
+def ctx(dmg):
+    return dmg.Context(0)
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.fixture(scope="module")
+def sys64(dmg, ctx):
+    N, cfg = 64, 0
+    th = synth.gauge_angles(N, cfg)
+    m0 = synth.bare_mass(N, cfg)
+    g = dmg.Gauge(ctx, th)
+    H = multigrid.Hierarchy(th, m0, synth.near_null_starts(N, cfg, 0), synth.near_null_starts(N, cfg, 1))
+    hg = dmg.Hierarchy(ctx, g, m0, np.ascontiguousarray(H.levels[0].null), np.ascontiguousarray(H.levels[1].null),
+                       inject=True)
+    D = H.levels[0].A
+    lu = spla.splu(D.tocsc(), permc_spec="MMD_AT_PLUS_A")
+    return N, cfg, th, m0, g, H, hg, D, lu
+
+
+def test_fine_gmres_dr_200_40(dmg, ctx, sys64):
+    N, cfg, th, m0, g, H, hg, D, lu = sys64
+    b = synth.rhs(N, cfg, 0)
+    x = np.zeros_like(b)
+    print("[case] fine GMRES-DR(200, 40) 64^2", flush=True)
+    st, s = dmg.solve_fine(ctx, hg, dmg.FINE_GMRES_DR, b, x, 1, m=200, k=40, max_iters=20000)
+    res = np.linalg.norm(b - D @ x) / np.linalg.norm(b)
+    err = _rel(x, lu.solve(b))
+    xo, info, _ = krylov.gmres_dr(lambda v: D @ v, b, 200, 40, 1e-8)
+    print(f"    device {s[0]['outer_iters']} Arnoldi steps, residual {res:.2e}, error vs LU {err:.2e}; "
+          f"oracle {info.iters} steps", flush=True)
+    assert st == dmg.DMG_OK and s[0]["converged"] == 1
+    assert res <= 1e-8 * (1 + 1e-6) and err < 1e-6
+    assert 0.8 * info.iters <= s[0]["outer_iters"] <= 1.25 * info.iters
+
+
+def test_fine_gmres_proj_200_40(dmg, ctx, sys64):
+    """GMRES-DR on the first right-hand side, GMRES-Proj(200, 40) on two more: every solution
+    reaches 1e-8 and LU's, and the projected solves need fewer steps than the first."""
+    N, cfg, th, m0, g, H, hg, D, lu = sys64
+    nrhs = 3
+    B = np.stack([synth.rhs(N, cfg, 10 + j) for j in range(nrhs)])
+    X = np.zeros_like(B)
+    print("[case] fine GMRES-DR then GMRES-Proj(200, 40) 64^2", flush=True)
+    st, ss = dmg.solve_fine(ctx, hg, dmg.FINE_GMRES_PROJ, B, X, nrhs, m=200, k=40, max_iters=20000)
+    assert st == dmg.DMG_OK
+    A = lambda v: D @ v
+    _, info0, defl = krylov.gmres_dr(A, B[0], 200, 40, 1e-8)
+    steps_o = [info0.iters] + [krylov.gmres_proj(A, B[j], defl, 200, 1e-8)[1].iters for j in range(1, nrhs)]
+    for j in range(nrhs):
+        res = np.linalg.norm(B[j] - D @ X[j]) / np.linalg.norm(B[j])
+        err = _rel(X[j], lu.solve(B[j]))
+        print(f"    rhs {j}: device {ss[j]['outer_iters']} steps (oracle {steps_o[j]}), residual {res:.2e}, "
+              f"error {err:.2e}", flush=True)
+        assert ss[j]["converged"] == 1 and res <= 1e-8 * (1 + 1e-6) and err < 1e-6
+        assert ss[j]["coarse_dr_calls"] == (1 if j == 0 else 0)
+    assert max(ss[1]["outer_iters"], ss[2]["outer_iters"]) < ss[0]["outer_iters"]
+    for j in range(1, nrhs):
+        assert 0.7 * steps_o[j] <= ss[j]["outer_iters"] <= 1.4 * steps_o[j] + 20
+
+
+@pytest.fixture(scope="module")
+def sys256(dmg, ctx):
+    N, cfg = 256, 0
+    th = synth.gauge_angles(N, cfg)
+    m0 = synth.bare_mass(N, cfg)
+    g = dmg.Gauge(ctx, th)
+    hg = dmg.Hierarchy(ctx, g, m0, synth.near_null_starts(N, cfg, 0), synth.near_null_starts(N, cfg, 1))
+    D = wilson.dirac_matrix(th, m0)
+    return N, cfg, th, m0, g, hg, D
+
+
+def _coarse_matrix(dmg, hg, L):
+    """D_c assembled from the device's exported coarse blocks (its own operator)."""
+    import scipy.sparse as sp
+    B = hg.export(2, dmg.PART_BLOCKS).reshape(L * L, 5, 24, 24).transpose(0, 1, 3, 2)
+    rows, cols, vals = [], [], []
+    for S in range(L * L):
+        X, T = S % L, S // L
+        nb = [S, (X + 1) % L + L * T, (X - 1) % L + L * T, X + L * ((T + 1) % L), X + L * ((T - 1) % L)]
+        for d in range(5):
+            r, c = np.meshgrid(np.arange(24), np.arange(24), indexing="ij")
+            rows.append((24 * S + r).ravel())
+            cols.append((24 * nb[d] + c).ravel())
+            vals.append(B[S, d].ravel())
+    n = 24 * L * L
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
+
+
+def test_coarse_gmres_dr_200_40_space(dmg, ctx, sys256):
+    """The first coarse solve of the paper's deflated multigrid: GMRES-DR(200, 40) to 1e-15 on
+    the 16^2 x 24 coarse operator of 256^2 configuration 0.  The stored space is orthonormal and
+    satisfies A V_k = V_{k+1} Hbar_k with the coarse matrix; the oracle's gmres_dr on the same
+    matrix and right-hand side takes the same number of Arnoldi steps (within 5 %) and keeps the
+    same smallest Ritz values (the space after a few long cycles, not converged eigenvectors)."""
+    N, cfg, th, m0, g, hg, D = sys256
+    L = N // 16
+    Dc = _coarse_matrix(dmg, hg, L)
+    nc = Dc.shape[0]
+    d = dmg.Deflation(hg, 200, 40)
+    b = synth.gaussian_complex(nc, N, cfg, 4, 0)
+    print("[case] coarse GMRES-DR(200, 40) to 1e-15, 256^2", flush=True)
+    d.build(b, 1e-15)
+    assert d.ready
+    V, Hk = d.export(nc)
+    k = Hk.shape[1]
+    assert k == 40
+    orth = np.linalg.norm(V.conj().T @ V - np.eye(k + 1))
+    rel = np.linalg.norm(Dc @ V[:, :k] - V @ Hk) / np.linalg.norm(Hk)
+    _, info, defl = krylov.gmres_dr(lambda v: Dc @ v, b, 200, 40, 1e-15)
+    ritz = np.linalg.eigvals(np.linalg.lstsq(V[:, :k], Dc @ V[:, :k], rcond=None)[0])
+    ritz_o = np.linalg.eigvals(np.linalg.lstsq(defl.V[:, :k], Dc @ defl.V[:, :k], rcond=None)[0])
+    small_o = ritz_o[np.argsort(np.abs(ritz_o))[:10]]
+    dev = max(np.min(np.abs(ritz - t)) / abs(t) for t in small_o)
+    lam = spla.eigs(Dc.tocsc(), k=2, sigma=0.0, which="LM", return_eigenvectors=False)
+    dev_eig = max(np.min(np.abs(ritz - t)) / abs(t) for t in lam)
+    print(f"    orthogonality {orth:.1e}, relation {rel:.1e}; oracle {info.iters} Arnoldi steps, "
+          f"10 smallest Ritz values of the two spaces within {dev:.1e}; 2 smallest eigenvalues of D_c "
+          f"within {dev_eig:.1e}", flush=True)
+    assert orth < 1e-11 and rel < 1e-10
+    assert dev < 1e-6 and dev_eig < 1e-4
+    d.close()
+
+
+def test_deflated_mg_smoothing_only_200_40(dmg, ctx, sys256):
+    """The paper's deflated multigrid (smoothing-only intermediate grid, coarse GMRES-DR(200, 40)
+    to 1e-15 on the first call, GMRES-Proj(200, 40) to 1e-8 afterwards) at 256^2: two right-hand
+    sides to 1e-8 against sparse LU of the oracle's D, FP64 and FP32 preconditioners."""
+    N, cfg, th, m0, g, hg, D = sys256
+    lu = spla.splu(D.tocsc(), permc_spec="MMD_AT_PLUS_A")
+    for precond in ("fp64", "fp32"):
+        d = dmg.Deflation(hg, 200, 40)
+        prm = dmg.solve_params(precond=precond, int_mode=1, coarse_tol_first=1e-15, coarse_tol_later=1e-8)
+        for j in range(2):
+            print(f"[case] 256^2 deflated MG (200, 40) precond={precond} rhs={j}", flush=True)
+            b = synth.rhs(N, cfg, j)
+            x = np.zeros_like(b)
+            st, s = dmg.solve(ctx, hg, d, b, x, params=prm)
+            res = np.linalg.norm(b - D @ x) / np.linalg.norm(b)
+            err = _rel(x, lu.solve(b))
+            print(f"    outer {s[0]['outer_iters']}, coarse Mvps {s[0]['coarse_mvps']}, residual {res:.2e}, "
+                  f"error {err:.2e}", flush=True)
+            assert st == dmg.DMG_OK and s[0]["converged"] == 1 and res <= 1e-8 and err < 1e-6
+            assert s[0]["coarse_dr_calls"] == (1 if j == 0 else 0)
+        d.close()

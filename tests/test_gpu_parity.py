@@ -144,8 +144,8 @@ def test_injected_operators_action(dmg, ctx, injected):
         for op, M in [(dmg.OP_APPLY, A), (dmg.OP_APPLY_DAG, A.conj().T.tocsr())]:
             out = np.empty(n, dtype=complex)
             hg.apply(lvl, op, v, out)
-            tol = 1e-13 if lvl == 0 else 1e-12
-            assert _rel(out, M @ v) < tol, f"level {lvl} op {op}"
+            ref = M @ v
+            assert _rel(out, ref) < 1e-13 and _elem(out, ref) < 1e-13, (lvl, op, _rel(out, ref), _elem(out, ref))
 
 
 def test_injected_transfers(dmg, injected):

@@ -1,0 +1,161 @@
+"""Pins for the oracle's critical-mass search (Results section, the "mass gap").
+
+m_c = -min Re lambda(D(0)).  Each function of oracle.mcrit is checked against
+something other than itself: the free-field closed form (both search paths),
+a dense eigendecomposition (shift-invert eigenvalues, the covered disc and its
+imaginary-part guard), plain Arnoldi on D(0) with the smallest real part (the
+stored critical masses of the workloads), and Bendixson's bound through the
+Hermitian part (the sign of m_c).
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import synth
+from oracle import mcrit, wilson
+
+
+def _free(N):
+    return np.zeros((N, N, 2))
+
+
+def _free_field_mc(N):
+    # U = 1, antiperiodic time: the smallest real part is at p_x = 0, p_t = pi / N
+    return -(1.0 - np.cos(np.pi / N))
+
+
+@pytest.mark.parametrize("N", [8, 16])
+def test_free_field_dense_path(N):
+    assert abs(mcrit.critical_mass_dense(_free(N)) - _free_field_mc(N)) < 1e-10
+    mc, guard = mcrit.critical_mass(_free(N))
+    assert abs(mc - _free_field_mc(N)) < 1e-10 and guard == float("inf")
+
+
+@pytest.mark.parametrize("N", [16, 32])
+def test_free_field_shift_invert_path(N):
+    mc, guard = mcrit.critical_mass(_free(N), force_sparse=True)
+    assert abs(mc - _free_field_mc(N)) < 1e-10
+    # the covered range of imaginary parts reaches the largest free-field imaginary part
+    assert np.isfinite(guard) and guard >= wilson.free_field_eigenvalues(N, N, 0.0).imag.max() - 1e-9
+    # the degenerate leftmost quartet (p_t = +-pi/N, two spins) is found whole
+    lam, _ = mcrit.leftmost_eigenvalues(_free(N))
+    edge = 1.0 - np.cos(np.pi / N)
+    assert np.sum(np.abs(lam.real - edge) < 1e-10) >= 2
+
+
+def _dense_spectrum(theta):
+    return np.linalg.eigvals(wilson.dirac_matrix(theta, 0.0).toarray())
+
+
+@pytest.fixture(scope="module")
+def cfg32():
+    th = synth.gauge_angles(32, 0)
+    return th, _dense_spectrum(th)
+
+
+def test_shift_invert_matches_dense_eig_32(cfg32):
+    th, lam_all = cfg32
+    k = 8
+    lam, R = mcrit.leftmost_eigenvalues(th, k=k)
+    want = lam_all[np.argsort(np.abs(lam_all))[:k]]
+    # match as multisets (conjugate pairs share a real part, so no sort order is stable)
+    dist = np.abs(lam[:, None] - want[None, :])
+    assert np.max(dist.min(axis=1)) < 1e-9 and np.max(dist.min(axis=0)) < 1e-9
+    assert abs(R - np.abs(want).max()) < 1e-9
+    mc_sparse, _ = mcrit.critical_mass(th, force_sparse=True)
+    assert abs(mc_sparse - mcrit.critical_mass_dense(th)) < 1e-10
+    assert abs(mc_sparse + lam_all.real.min()) < 1e-10
+
+
+@pytest.mark.parametrize("sigma,k", [(0.0, 8), (0.0, 4), (0.6, 2), (0.3 + 0.4j, 3)])
+def test_covered_disc_and_guard_against_dense_eig(cfg32, sigma, k):
+    """Every eigenvalue with a smaller real part than the one found lies outside the
+    covered disc and has |Im| at least the reported guard.  With the shift at the left
+    edge (sigma = 0) the true leftmost eigenvalue is inside the disc; with a shift
+    placed badly (to the right, or off the axis) it is outside, and the search's
+    answer is wrong: the disc test is what tells the two apart."""
+    th, lam_all = cfg32
+    lam, R = mcrit.leftmost_eigenvalues(th, sigma=sigma, k=k)
+    re_min = lam.real.min()
+    guard = np.sqrt(max(R * R - (re_min - np.real(sigma)) ** 2, 0.0))
+    missed = lam_all[lam_all.real < re_min - 1e-12]
+    if np.imag(sigma) == 0:
+        assert np.all(np.abs(missed.imag) >= guard - 1e-9)
+    assert np.all(np.abs(missed - sigma) >= R - 1e-9)
+    # the leftmost eigenvalues (a conjugate pair, by gamma_5-hermiticity)
+    leads = lam_all[lam_all.real < lam_all.real.min() + 1e-10]
+    inside = bool(np.any(np.abs(leads - sigma) <= R + 1e-9))
+    assert inside == (missed.size == 0)
+    if sigma == 0.0:
+        assert inside and abs(re_min - leads.real.min()) < 1e-10
+
+
+@pytest.fixture(scope="module")
+def stored64():
+    return {c: synth.gauge_angles(64, c) for c in range(4)}
+
+
+def test_covered_search_finds_what_one_disc_misses(cfg32):
+    """32^2 configuration 3 has its leftmost eigenvalues off the real axis (Im = +-0.084).
+    With two eigenvalues per shift, one search about sigma = 0 returns a larger real part
+    (the planted failure of a single nearest-k search), while the covered search, with the
+    same two eigenvalues per shift, returns the dense answer."""
+    th = synth.gauge_angles(32, 3)
+    lam_all = _dense_spectrum(th)
+    lam, _ = mcrit.leftmost_eigenvalues(th, k=2)
+    assert lam.real.min() > lam_all.real.min() + 1e-3
+    mc, guard = mcrit.critical_mass(th, force_sparse=True, k=2)
+    assert abs(mc + lam_all.real.min()) < 1e-10
+    assert guard >= np.abs(lam_all.imag).max()
+
+
+@pytest.mark.parametrize("cfg", range(4))
+def test_stored_mass_against_plain_arnoldi_64(stored64, cfg):
+    """The stored m_c of every 64^2 workload configuration equals -min Re lambda found
+    by plain Arnoldi on D(0) (no inversion, no shift)."""
+    th = stored64[cfg]
+    stored = synth.critical_mass(64, cfg)
+    assert abs(-mcrit.smallest_real_part_arnoldi(th) - stored) < 1e-9
+
+
+def test_stored_mass_reproduces_64():
+    """The covered search reproduces the stored value of the configuration whose leftmost
+    eigenvalue lies off the axis (Im = +-0.078)."""
+    th = synth.gauge_angles(64, 3)
+    mc, guard = mcrit.critical_mass(th)
+    assert abs(mc - synth.critical_mass(64, 3)) < 1e-10 and guard > 1.0
+
+
+@pytest.mark.parametrize("cfg", range(4))
+def test_stored_mass_sign_and_bendixson_64(stored64, cfg):
+    """Re lambda >= lambda_min of the Hermitian part, which is m0 + 1/2 (-Laplacian) >= 0
+    at m0 = 0: a sign slip in m_c or a search that returned a point left of the
+    numerical range fails here."""
+    th = stored64[cfg]
+    stored = synth.critical_mass(64, cfg)
+    hmin = mcrit.hermitian_part_min(th)
+    assert hmin > -1e-12
+    assert stored < 0 and -stored >= hmin
+
+
+def test_real_part_zero_at_critical_mass_64(stored64):
+    """At m0 = m_c the leftmost eigenvalue sits on the imaginary axis: D(m_c) is built
+    directly at that mass and searched with a shift left of its spectrum."""
+    th = stored64[0]
+    mc = synth.critical_mass(64, 0)
+    D = wilson.dirac_matrix(th, mc)
+    n = D.shape[0]
+    sigma = -0.02
+    lu = spla.splu((D - sigma * sp.identity(n, format="csc")).tocsc())
+    op = spla.LinearOperator((n, n), matvec=lu.solve, dtype=complex)
+    mu = spla.eigs(op, k=8, which="LM", ncv=40, tol=1e-12, return_eigenvectors=False)
+    lam = sigma + 1.0 / mu
+    assert abs(lam.real.min()) < 1e-10
+
+
+def test_stored_mass_against_plain_arnoldi_128():
+    th = synth.gauge_angles(128, 3)
+    stored = synth.critical_mass(128, 3)
+    assert abs(-mcrit.smallest_real_part_arnoldi(th) - stored) < 1e-9
+    assert -stored >= mcrit.hermitian_part_min(th)
