@@ -196,6 +196,28 @@ dmg_status dmg_hierarchy_apply_batched(dmg_hierarchy* h, int level, int op, dmg_
 dmg_status dmg_hierarchy_apply(dmg_hierarchy* h, int level, int op, dmg_precision p,
                                const void* in, void* out, int ptr_kind);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): dmg_hierarchy_apply_batched without any device or
+ * pinned allocation.  The lane-interleaved copies of in and out that the multi-RHS kernels
+ * work on live in a static device array of DMG_STATIC_SCRATCH_BYTES per GPU, held from the
+ * library's load until the process ends.
+ *   in, out: DEVICE pointers (nrhs consecutive fields of precision p, as in
+ *     dmg_hierarchy_apply_batched); the call is stream-ordered on the context's stream and
+ *     returns without synchronising.  The caller owns in and out.
+ *   The lane-interleaved input (rounded up to 256 bytes) plus output, element size x field
+ *   length x nrhs rounded up to a power of two, must fit DMG_STATIC_SCRATCH_BYTES;
+ *   larger requests fail with DMG_E_INVALID (nothing is launched).
+ *   Every call on one GPU shares that GPU's array: calls whose work overlaps on the device
+ *   (other streams, other host threads, other contexts of the same device) race and must be
+ *   ordered by the caller.  The array needs no clearing between calls (every element a call
+ *   reads was written earlier in that call).
+ *   Results are bitwise those of dmg_hierarchy_apply_batched (same kernels; a launch form
+ *   not tuned yet is the default form, and all forms give the same bits).  No autotuning
+ *   runs and no kernel timer events are recorded. */
+#define DMG_STATIC_SCRATCH_BYTES (64u << 20)
+dmg_status dmg_hierarchy_apply_batched_static(dmg_hierarchy* h, int level, int op, dmg_precision p, const void* in,
+                                              void* out, int nrhs, int mfma);
+
 /* -------------------------------------------------------------- deflation */
 
 /* Coarse-grid deflation space (Methods section): EMPTY until the first coarse

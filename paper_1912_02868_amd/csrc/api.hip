@@ -155,6 +155,34 @@ dmg_context::~dmg_context() {
   for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
 }
 
+// ---------------------------------------------------------------- static scratch
+// Device memory of dmg_hierarchy_apply_batched_static: the lane-interleaved copies of its
+// input and output fields.  Every device the library runs on holds one copy of the array
+// until the process ends.  Host code never passes the array's name to a kernel (on the host
+// it is only a stand-in symbol): it uses the device address hipGetSymbolAddress returned
+// for that device, looked up once per device with the device current (at context creation).
+static __device__ __align__(256) unsigned char scratch[DMG_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+hipError_t g_scratch_err[SCRATCH_MAX_DEVICES] = {};
+
+// device address of `scratch` on `device`, which must be current; nullptr if the lookup failed
+void* scratch_lookup(int device) {
+  if (device < 0 || device >= SCRATCH_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device] && g_scratch_err[device] == hipSuccess) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e == hipSuccess && p) g_scratch_ptr[device] = p;
+    else g_scratch_err[device] = e != hipSuccess ? e : hipErrorInvalidSymbol;
+  }
+  return g_scratch_ptr[device];
+}
+}  // namespace
+
 dmg_status dmg_context_create(int device, void* hip_stream, const dmg_allocator* alloc, size_t hbm_budget,
                               dmg_context** out) {
   if (!out) return DMG_E_INVALID;
@@ -168,6 +196,7 @@ dmg_status dmg_context_create(int device, void* hip_stream, const dmg_allocator*
   c->stream = (hipStream_t)hip_stream;
   if (alloc) c->alloc = *alloc;
   c->budget = hbm_budget;
+  c->scratch = scratch_lookup(device);  // once per device; a failure is reported by the static entry point
   *out = c;
   return DMG_OK;
 }
@@ -598,6 +627,67 @@ dmg_status dmg_hierarchy_apply_batched(dmg_hierarchy* h, int level, int op, dmg_
     else run(float2{});
     if (ptr_kind == DMG_PTR_HOST) from_device(c, out, bo.p, es * nout * nrhs, DMG_PTR_HOST);
     else DMG_HIP(hipStreamSynchronize(s));
+    return DMG_OK;
+  });
+}
+
+dmg_status dmg_hierarchy_apply_batched_static(dmg_hierarchy* h, int level, int op, dmg_precision p, const void* in,
+                                              void* out, int nrhs, int mfma) {
+  if (!h) return DMG_E_INVALID;
+  return guarded(h->ctx, [&]() -> dmg_status {
+    DMG_CHECK(in && out && level >= 0 && level <= 2 && nrhs >= 1 && nrhs <= 64, DMG_E_INVALID,
+              "hierarchy_apply_batched_static: bad arguments");
+    DMG_CHECK(op == DMG_OP_APPLY || ((op == DMG_OP_RESTRICT || op == DMG_OP_PROLONG) && level <= 1), DMG_E_INVALID,
+              "hierarchy_apply_batched_static: op");
+    DMG_CHECK(p == DMG_FP64 || p == DMG_FP32 || p == DMG_FP32_BF16, DMG_E_INVALID,
+              "hierarchy_apply_batched_static: precision");
+    dmg_context* c = h->ctx;
+    DMG_CHECK(c->scratch != nullptr, DMG_E_HIP,
+              "hierarchy_apply_batched_static: the static scratch array has no device address on this device");
+    int nb = 1;
+    while (nb < nrhs) nb *= 2;
+    const size_t es = p == DMG_FP64 ? sizeof(double2) : sizeof(float2);
+    int64_t nin = h->op[level].n, nout = h->op[level].n;
+    if (op == DMG_OP_RESTRICT) nout = h->op[level + 1].n;
+    if (op == DMG_OP_PROLONG) nin = h->op[level + 1].n;
+    // lane-interleaved input and output copies, each starting on a 256-byte boundary
+    const size_t in_bytes = (es * (size_t)nin * nb + 255) & ~(size_t)255;
+    const size_t out_bytes = es * (size_t)nout * nb;
+    DMG_CHECK(in_bytes + out_bytes <= (size_t)DMG_STATIC_SCRATCH_BYTES, DMG_E_INVALID,
+              "hierarchy_apply_batched_static: " + std::to_string(in_bytes + out_bytes) +
+                  " bytes of lane-interleaved fields exceed the static scratch of " +
+                  std::to_string((size_t)DMG_STATIC_SCRATCH_BYTES) + " bytes");
+    unsigned char* base = (unsigned char*)c->scratch;
+    hipStream_t s = c->stream;
+    const Op& A = h->op[level];
+    const Transfer& tr = h->tr[level < 2 ? level : 1];
+    const bool use_mfma = mfma != 0;
+    // the same kernels and launch forms as dmg_hierarchy_apply_batched (a shape not tuned yet takes
+    // its default form; all forms give the same bits), without tuning runs or timer events
+    auto run = [&](auto tag) {
+      using T = decltype(tag);
+      using R = decltype(T{}.x);
+      T* gi = (T*)base;
+      T* go = (T*)(base + in_bytes);
+      launch_b_gather<T>(s, (const T*)in, gi, nin, nrhs, nb);
+      if (op == DMG_OP_APPLY) {
+        const T* U = (const T*)(sizeof(R) == 8 ? (const void*)A.U64 : (const void*)A.U32);
+        const T* Ab = (const T*)(sizeof(R) == 8 ? (const void*)A.A64 : (const void*)A.A32);
+        const bool b16 = sizeof(R) == sizeof(float) && p == DMG_FP32_BF16 && level == 1;
+        if (A.kind == 0) launch_b_wilson<R>(s, U, gi, go, A.m0, A.Lx, A.Lt, nb, nullptr);
+        else if (b16)
+          launch_b_block_bf16(s, h->A16.as<bf16c>(), (const float2*)gi, (float2*)go, A.Lx, A.Lt, nb, nullptr, nullptr,
+                              use_mfma);
+        else launch_b_block<R>(s, Ab, gi, go, A.Lx, A.Lt, nb, nullptr, nullptr, use_mfma);
+      } else if (op == DMG_OP_RESTRICT) {
+        launch_b_restrict<R>(s, tr.P((const T*)nullptr), gi, go, tr.Lx, tr.Lt, tr.dof, nb);
+      } else {
+        launch_b_prolong<R>(s, tr.P((const T*)nullptr), gi, go, tr.Lx, tr.Lt, tr.dof, nb, 0);
+      }
+      launch_b_scatter<T>(s, go, (T*)out, nout, nrhs, nb);
+    };
+    if (p == DMG_FP64) run(double2{});
+    else run(float2{});
     return DMG_OK;
   });
 }

@@ -135,6 +135,7 @@ struct dmg_context {
   struct Span { int kernel; hipEvent_t a, b; long long units; };
   std::vector<Span> spans;
   long long pending_units[4] = {0, 0, 0, 0};
+  void* scratch = nullptr;  // this device's address of the static scratch array (api.hip)
   ~dmg_context();
 };
 

@@ -35,7 +35,7 @@ EXPORTED = [
     "dmg_context_set_budget",
     "dmg_gauge_create", "dmg_gauge_destroy", "dmg_apply_dirac",
     "dmg_setup", "dmg_hierarchy_destroy", "dmg_hierarchy_export", "dmg_hierarchy_part_bytes",
-    "dmg_hierarchy_apply", "dmg_hierarchy_apply_batched",
+    "dmg_hierarchy_apply", "dmg_hierarchy_apply_batched", "dmg_hierarchy_apply_batched_static",
     "dmg_deflation_create", "dmg_deflation_build", "dmg_deflation_reset", "dmg_deflation_ready",
     "dmg_deflation_export", "dmg_deflation_destroy",
     "dmg_solve_params_default", "dmg_setup_params_default", "dmg_solve", "dmg_solve_batched", "dmg_solve_fine",
@@ -137,6 +137,7 @@ def lib():
         "dmg_hierarchy_part_bytes": (sz, [vp, i, i]),
         "dmg_hierarchy_apply": (i, [vp, i, i, i, vp, vp, i]),
         "dmg_hierarchy_apply_batched": (i, [vp, i, i, i, vp, vp, i, i, i]),
+        "dmg_hierarchy_apply_batched_static": (i, [vp, i, i, i, vp, vp, i, i]),
         "dmg_deflation_create": (i, [vp, i, i, pp]),
         "dmg_deflation_build": (i, [vp, vp, d, i]),
         "dmg_deflation_reset": (None, [vp]),
@@ -354,6 +355,20 @@ class Hierarchy:
         pout, _ = _ptr(out)
         self.ctx.check(lib().dmg_hierarchy_apply_batched(self.h, level, op, prec, pin, pout, nrhs, kind,
                                                          1 if mfma else 0), "hierarchy_apply_batched")
+        return out
+
+    def apply_batched_static(self, level: int, op: int, x, out, nrhs: int, mfma: bool = True, bf16: bool = False):
+        """apply_batched without device allocation (the library's static scratch array); device
+        tensors only, stream-ordered on the context's stream."""
+        prec = FP32 if str(getattr(x, "dtype", "")).endswith("complex64") else FP64
+        if bf16:
+            prec = FP32_BF16
+        pin, kind = _ptr(x)
+        pout, kind2 = _ptr(out)
+        if kind != PTR_DEVICE or kind2 != PTR_DEVICE:
+            raise ValueError("apply_batched_static takes device tensors")
+        self.ctx.check(lib().dmg_hierarchy_apply_batched_static(self.h, level, op, prec, pin, pout, nrhs,
+                                                                1 if mfma else 0), "hierarchy_apply_batched_static")
         return out
 
     def close(self):
