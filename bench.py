@@ -63,8 +63,8 @@ def parse():
     ap.add_argument("--serve-configs", type=int, default=4, help="resident configurations per lattice size")
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests per arrival rate")
     ap.add_argument("--serve-capacity", type=int, default=16, help="lanes per resident configuration")
-    ap.add_argument("--serve-inflight", type=int, default=2, help="lane-batch steps running at once")
-    ap.add_argument("--serve-age", type=float, default=0.5,
+    ap.add_argument("--serve-inflight", type=int, default=3, help="lane-batch steps running at once")
+    ap.add_argument("--serve-age", type=float, default=0.1,
                     help="seconds of waiting that double a configuration's scheduling weight")
     ap.add_argument("--scan", action="store_true",
                     help="mass-gap and lattice-size scan of six solvers with power-law fits (prints its own JSON)")
@@ -81,6 +81,11 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for hardware byte counters)")
     return ap.parse_args()
+
+
+def progress(msg):
+    """A line on stderr per stage, so a long run shows it is alive."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def percentile(v, q):
@@ -167,6 +172,7 @@ def main():
 
     # the dominant kernel (the persistent coarse solve) is timed with HIP events by the
     # library itself, launch by launch, over the timed FP64 region
+    progress(f"setup of {len(need)} hierarchies done; plain FP64 form")
     ctx.timer(dmg.KT_COARSE_PROJ)
     el64, lat64, st64 = timed(dmg.FP64)
     coarse_ms, coarse_launches, coarse_steps = ctx.timer_read(dmg.KT_COARSE_PROJ)
@@ -174,6 +180,7 @@ def main():
     n_solves = len(step_cfgs) * RHS_PER_CONFIG
     ok64 = all(s["converged"] and s["true_rel_resid"] <= 1e-8 for s in st64)
     out_mixed = None
+    progress(f"plain FP64: {n_solves / el64:.2f} solves/s")
     if not a.no_mixed:
         el32, lat32, st32 = timed(dmg.FP32)
         ok32 = all(s["converged"] and s["true_rel_resid"] <= 1e-8 for s in st32)
@@ -184,6 +191,7 @@ def main():
             "mean_outer_iters": float(np.mean([s["outer_iters"] for s in st32])),
             "max_true_rel_resid": float(max(s["true_rel_resid"] for s in st32)),
         }
+        progress(f"FP32 preconditioner: {n_solves / el32:.2f} solves/s")
         el16, lat16, st16 = timed(dmg.FP32_BF16)
         out_mixed["bf16_blocks"] = {
             "value": n_solves / el16, "unit": "solves/s",
@@ -211,17 +219,20 @@ def main():
     roof_int16 = measure_bf16_stencil(torch, dmg, res[step_cfgs[0]][1], N)
 
     # ------------------------------------------------------------ batched and served forms
+    progress("stencil rooflines done")
     out_batched = None
     if not a.no_batched:
         NB = a.batched_lattice or N
         cfgs_b = step_cfgs[:a.batched_configs] if NB == N else list(range(a.batched_configs))
         out_batched = batched_form(torch, dmg, ctx, NB, cfgs_b, a.batched_rhs, n_solves / el64)
+    progress("batched form done")
     out_served = None
     if not a.no_serve:
         out_served = served_form(torch, dmg, ctx, [int(v) for v in a.serve_sizes.split(",")], a.serve_configs,
                                  a.serve_requests, a.serve_capacity, a.serve_inflight, a.serve_age)
 
     # ------------------------------------------------------------ error against the oracle
+    progress("served form done")
     oracle_err = None
     if not a.no_oracle_error:
         oracle_err = errors_vs_oracle(synth, N, res, sols)
@@ -230,6 +241,7 @@ def main():
                 (out_mixed if key is None else out_mixed[key])["error_vs_oracle"] = oracle_err.pop(prec)
 
     # ------------------------------------------------------------ CPU baseline (oracle)
+    progress("errors against the oracle done")
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(N, a.cpu_budget, np.mean([s["outer_iters"] for s in st64]))
@@ -301,6 +313,7 @@ def kernels_only(torch, dmg, N=512, nrhs=64, reps=20):
     for _ in range(reps):
         torch.mul(src, 2.0, out=dst)
     torch.cuda.synchronize()
+    out["autotune"] = dmg.autotune_report().strip().splitlines()
     out["copy_reference"] = {"kernel": "torch.mul float32 (elementwise multiply)", "bytes_read": 256 * 2 ** 20,
                              "bytes_written": 256 * 2 ** 20, "launches": reps}
     del src, dst
@@ -321,6 +334,7 @@ def errors_vs_oracle(synth, N, res, sols):
     t0 = time.perf_counter()
     errs = {}
     for c in sorted({c for (_, c) in sols}):
+        progress(f"sparse LU of configuration {c}")
         D = wilson.dirac_matrix(synth.gauge_angles(N, c), synth.bare_mass(N, c))
         lu = spla.splu(D.tocsc(), permc_spec="MMD_AT_PLUS_A")
         b = res[c][2].cpu().numpy()
@@ -460,6 +474,7 @@ def batched_form(torch, dmg, ctx, N, cfgs, nrhs, plain_rate):
                                       "sample": f"right-hand sides 0..{n_plain - 1} one at a time, deflation "
                                                 "space built beforehand as in the lockstep form"}
     for prec in ("fp32", "fp64", "fp32_bf16"):
+        progress(f"batched {prec}")
         prm = dmg.solve_params(precond=prec)
         g, h, d = res[cfgs[0]]
         dmg.solve_batched(ctx, h, d, B[cfgs[0]], X, nrhs, params=prm)  # workspace
@@ -565,7 +580,7 @@ def batched_wilson_roofline(torch, dmg, ctx, h, N, nrhs, reps=50):
             "cache_resident": byts < INFINITY_CACHE_BYTES}
 
 
-def served_form(torch, dmg, ctx, sizes, ncfg, n_req, cap, inflight_max=2, age_s=0.5):
+def served_form(torch, dmg, ctx, sizes, ncfg, n_req, cap, inflight_max=3, age_s=0.1):
     """Serving: single-RHS requests, each naming one of the resident configurations
     (every size in `sizes` x configurations 0..ncfg-1, hierarchy and deflation space kept
     on the device), arrive as a seeded Poisson stream; each configuration has a lane
@@ -624,6 +639,7 @@ def served_form(torch, dmg, ctx, sizes, ncfg, n_req, cap, inflight_max=2, age_s=
         torch.cuda.synchronize()
         t_plain[k] = (time.perf_counter() - t1) / 3
     plain_mix = 1.0 / float(np.mean(list(t_plain.values())))
+    progress(f"served: {len(keys)} configurations resident, plain FP64 on the same mix {plain_mix:.2f} solves/s")
     by_size = {N: 1.0 / float(np.mean([t_plain[k] for k in keys if k[0] == N])) for N in sizes
                if any(k[0] == N for k in keys)}
 
@@ -711,11 +727,13 @@ def served_form(torch, dmg, ctx, sizes, ncfg, n_req, cap, inflight_max=2, age_s=
                          "p99_ms": percentile(lat_sat, 99), "failures": bad, "mean_lanes_per_step": lps,
                          "speedup_vs_plain_fp64_same_mix": sat / plain_mix},
            "rates": []}
+    progress(f"served: saturated {sat:.1f} solves/s")
     for ri, frac in enumerate((0.5, 0.9, 1.2)):
         rate = frac * sat
         reqs, rng = requests(2 + ri, n_req)
         arrivals = list(np.cumsum(rng.exponential(1.0 / rate, size=n_req)))
         thr, lat, bad, lps = serve(reqs, arrivals)
+        progress(f"served: {frac} x saturated offered, {thr:.1f} solves/s delivered")
         out["rates"].append({"offered_per_s": rate, "fraction_of_saturated": frac, "value": thr, "unit": "solves/s",
                              "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99), "failures": bad,
                              "mean_lanes_per_step": lps, "speedup_vs_plain_fp64_same_mix": thr / plain_mix})
@@ -797,7 +815,7 @@ def cpu_baseline(N, budget_s, gpu_outer_iters):
 # ---------------------------------------------------------------- mass-gap / lattice-size scan
 SCAN_METHODS = ("deflated MG with partial solves", "deflated MG", "GMRES-DR", "nondeflated MG with partial solve",
                 "CGNE", "nondeflated MG")
-FINE_DR_M, FINE_DR_K = 48, 16  # the paper's fine GMRES-DR is (200, 40); the device restart (LDS-resident) takes m <= 48
+FINE_DR_M, FINE_DR_K = 200, 40  # the paper's fine-grid GMRES-DR (the long-cycle solver)
 
 
 def power_fit(sizes, values):
@@ -828,9 +846,14 @@ def scan(torch, dmg, ctx, sizes, ncfg, gaps, fit_gap, nrhs):
     gaps = sorted(set(gaps + [fit_gap]), reverse=True)
     rows = []
     t_start = time.perf_counter()
+    skipped = []
     for N in sizes:
         for c in range(ncfg):
-            mc = synth.critical_mass(N, c)
+            try:
+                mc = synth.critical_mass(N, c)
+            except KeyError:
+                skipped.append(f"{N}/{c}")
+                continue
             g = dmg.Gauge(ctx, synth.gauge_angles(N, c))
             B = [torch.from_numpy(synth.rhs(N, c, j)).cuda() for j in range(nrhs)]
             X = torch.empty_like(B[0])
@@ -890,7 +913,7 @@ def scan(torch, dmg, ctx, sizes, ncfg, gaps, fit_gap, nrhs):
             "sizes": sizes, "configs_per_size": ncfg, "gaps": gaps, "rhs_per_config": nrhs,
             "fit_gap": fit_gap, "size_measure": "lattice sites", "alpha_fits": fits,
             "alpha_fits_by_gap": fits_by_gap,
-            "fine_gmres_dr": [FINE_DR_M, FINE_DR_K], "rows": rows,
+            "fine_gmres_dr": [FINE_DR_M, FINE_DR_K], "configs_without_stored_mass": skipped, "rows": rows,
             "wall_s": time.perf_counter() - t_start}
 
 

@@ -278,7 +278,7 @@ typedef struct {
 /* Autotuning of the lockstep stencils (process-wide, all contexts).  The multi-RHS block
  * stencil on the matrix cores has launch forms with 64, 32 or 16 right-hand sides per
  * workgroup (form 0, 1, 2; as nb allows) and the FP32 multi-RHS Wilson stencil forms with
- * 256, 128, 512 or 64 threads per workgroup (form 0 .. 3).  All forms of a kernel compute
+ * 256, 128, 512, 64 or 1024 threads per workgroup (form 0 .. 4).  All forms of a kernel compute
  * the same bits.  Unless off, a lockstep workspace (dmg_solve_batched, dmg_batch_create)
  * and dmg_hierarchy_apply_batched time every form of a shape (sites, lanes, precision)
  * the first time they meet it and keep the fastest for the life of the process.

@@ -1,7 +1,7 @@
 """Compute the critical masses of the synthetic configurations with the oracle and
 store them in ``synth/mcrit.json`` (the bare mass of every workload is m_c + 0.01).
 
-    python -m oracle.make_mcrit --sizes 64:4,128:4,256:10,512:4 --jobs 4
+    python -m oracle.make_mcrit --sizes 64:10,128:10,256:10,512:4 --jobs 4 --redo-guard-below 1.0
 
 Each entry is m_c = -min Re lambda(D(0)) of configuration (N, cfg); the covered search
 also records the range of imaginary parts it covered (``im_guard``, see ``oracle.mcrit``).
@@ -36,6 +36,9 @@ def main(argv=None):
     ap.add_argument("--sizes", default="64:4,128:4,256:10,512:4", help="N:count list")
     ap.add_argument("--jobs", type=int, default=1)
     ap.add_argument("--force", action="store_true")
+    ap.add_argument("--redo-guard-below", type=float, default=0.0,
+                    help="recompute entries whose covered range of imaginary parts is below this (a search "
+                         "that did not cover the strip)")
     a = ap.parse_args(argv)
     path = synth.MCRIT_FILE
     method = ("oracle.mcrit.critical_mass (dense eig up to 32^2; above, shift-invert ARPACK discs covering "
@@ -50,7 +53,9 @@ def main(argv=None):
     for item in a.sizes.split(","):
         N, count = (int(v) for v in item.split(":"))
         for cfg in range(count):
-            if a.force or f"{N}/{cfg}" not in table["mc"]:
+            key = f"{N}/{cfg}"
+            stale = table["im_guard"].get(key, float("inf")) < a.redo_guard_below
+            if a.force or key not in table["mc"] or stale:
                 jobs.append((N, cfg))
     with Pool(max(1, a.jobs)) as pool:
         for N, cfg, mc, guard, dt in pool.imap_unordered(_one, jobs):

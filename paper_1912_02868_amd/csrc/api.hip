@@ -110,7 +110,7 @@ int dmg_autotune(int mode) {
 }
 
 int dmg_autotune_force(int kernel, int form) {
-  if (kernel < 0 || kernel >= TK_COUNT || form < -1 || form > 3) return DMG_E_INVALID;
+  if (kernel < 0 || kernel >= TK_COUNT || form < -1 || form > 4) return DMG_E_INVALID;
   b_tune_force(kernel, form);
   return DMG_OK;
 }

@@ -63,6 +63,17 @@ __device__ inline float2 ld_blk(const bf16c* p) {
   const bf16c v = *p;
   return make_float2(__uint_as_float((unsigned)v.re << 16), __uint_as_float((unsigned)v.im << 16));
 }
+// XCD-aware workgroup order.  The dispatcher hands workgroup b of a grid of G to compute die
+// (XCD) b % 8, and each of the 8 XCDs has its own L2.  The logical block returned here gives each
+// XCD one contiguous range of [0, G) (XCD x: blocks start_x .. start_x + count_x - 1, in dispatch
+// order), so neighbouring sites of a stencil are worked on by the same XCD, close in time, and
+// their shared neighbour fields come from that XCD's L2 instead of the fabric.  A bijection on
+// [0, G) for any G.
+__device__ inline int xcd_block(int b, int G) {
+  const int q = G >> 3, r = G & 7, x = b & 7;
+  return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 // storage type of the blocks of a stencil computing in precision R
 template <typename R, bool B16> struct BlkT { using T = cx<R>; };
 template <> struct BlkT<float, true> { using T = bf16c; };

@@ -191,12 +191,12 @@ def test_batched_bf16_block_operator(dmg, inj64, nrhs):
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_autotuned_forms_bitwise(dmg, inj64, prec):
     """Every launch form the autotuner may pick (block stencil: 64, 32 or 16 lanes per
-    workgroup; FP32 Wilson stencil: 256, 128, 512 or 64 threads) gives bitwise the same
+    workgroup; FP32 Wilson stencil: 256, 128, 512, 64 or 1024 threads) gives bitwise the same
     product, and the tuned choice is reported per shape."""
     H, g, hg = inj64
     nrhs = 64
     try:
-        for lvl, kern, nforms in ((0, dmg.TUNE_WILSON, 4), (1, dmg.TUNE_BLOCK, 3), (2, dmg.TUNE_BLOCK, 3)):
+        for lvl, kern, nforms in ((0, dmg.TUNE_WILSON, 5), (1, dmg.TUNE_BLOCK, 3), (2, dmg.TUNE_BLOCK, 3)):
             n = H.levels[lvl].A.shape[0]
             x = _fields(n, nrhs, 40 + lvl)
             if prec == "fp32":
