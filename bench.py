@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--scan-gaps", default="1e-1,1e-2,1e-3,1e-4")
     ap.add_argument("--scan-fit-gap", type=float, default=1e-4)
     ap.add_argument("--scan-rhs", type=int, default=2)
+    ap.add_argument("--scan-coarse", default="200,40",
+                    help="coarse GMRES-DR / GMRES-Proj (m, k) of the deflated multigrid methods (the paper's 200,40)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the multi-RHS stencils at 512^2 x 64 (FP32 Wilson, FP32 and FP64 matrix-core block "
                          "stencils) and a 256 MiB streaming kernel, for hardware counter passes (prints its own JSON)")
@@ -116,7 +118,9 @@ def main():
     if a.scan:
         ctx = dmg.Context(0)
         out = scan(torch, dmg, ctx, [int(v) for v in a.scan_sizes.split(",")], a.scan_configs,
-                   [float(v) for v in a.scan_gaps.split(",")], a.scan_fit_gap, a.scan_rhs)
+                   [float(v) for v in a.scan_gaps.split(",")], a.scan_fit_gap, a.scan_rhs,
+                   tuple(int(v) for v in a.scan_coarse.split(",")))
+        ctx.close()
         print(json.dumps(out), flush=True)
         return
     N = a.lattice
@@ -833,7 +837,7 @@ def power_fit(sizes, values):
     return float(coef[0]), float(se)
 
 
-def scan(torch, dmg, ctx, sizes, ncfg, gaps, fit_gap, nrhs):
+def scan(torch, dmg, ctx, sizes, ncfg, gaps, fit_gap, nrhs, coarse=(200, 40)):
     """Fine-equivalent Mvps (eq. (1)) of six solvers over mass gaps m0 - m_c and lattice sizes,
     on the synthetic ensembles (not the paper's configurations): deflated multigrid with the
     partial intermediate solve (the default), deflated multigrid with intermediate smoothing
@@ -864,7 +868,7 @@ def scan(torch, dmg, ctx, sizes, ncfg, gaps, fit_gap, nrhs):
                 torch.cuda.synchronize()
                 setup_s = time.perf_counter() - t0
                 for meth in SCAN_METHODS:
-                    d = dmg.Deflation(h, 30, 10) if meth.startswith("deflated") else None
+                    d = dmg.Deflation(h, *coarse) if meth.startswith("deflated") else None
                     prm = dmg.solve_params()
                     if meth in ("deflated MG", "nondeflated MG"):
                         prm = dmg.solve_params(int_mode=1, coarse_tol_first=1e-15, coarse_tol_later=1e-8)
@@ -913,7 +917,8 @@ def scan(torch, dmg, ctx, sizes, ncfg, gaps, fit_gap, nrhs):
             "sizes": sizes, "configs_per_size": ncfg, "gaps": gaps, "rhs_per_config": nrhs,
             "fit_gap": fit_gap, "size_measure": "lattice sites", "alpha_fits": fits,
             "alpha_fits_by_gap": fits_by_gap,
-            "fine_gmres_dr": [FINE_DR_M, FINE_DR_K], "configs_without_stored_mass": skipped, "rows": rows,
+            "fine_gmres_dr": [FINE_DR_M, FINE_DR_K], "coarse_deflation": list(coarse),
+            "configs_without_stored_mass": skipped, "rows": rows,
             "wall_s": time.perf_counter() - t_start}
 
 
