@@ -36,11 +36,12 @@ def main(argv=None):
     ap.add_argument("--sizes", default="64:4,128:4,256:10,512:4", help="N:count list")
     ap.add_argument("--jobs", type=int, default=1)
     ap.add_argument("--force", action="store_true")
+    ap.add_argument("--out", default=None, help="table to read and update (default: the stored one)")
     ap.add_argument("--redo-guard-below", type=float, default=0.0,
                     help="recompute entries whose covered range of imaginary parts is below this (a search "
                          "that did not cover the strip)")
     a = ap.parse_args(argv)
-    path = synth.MCRIT_FILE
+    path = a.out or synth.MCRIT_FILE
     method = ("oracle.mcrit.critical_mass (dense eig up to 32^2; above, shift-invert ARPACK discs covering "
               "the Bendixson strip of the leftmost eigenvalue, im_guard = the covered range of imaginary parts)")
     table = {"mc": {}, "im_guard": {}, "method": method}

@@ -340,13 +340,19 @@ __device__ inline double2 cp_rotation_scan(int lane, int cnt, double2 h0, double
   return xq;
 }
 
+// Givens rotation [c s; -conj(s) c] with c real and [c s; -conj(s) c] [a; b] = [r; 0]:
+// c = |a| / r, s = conj(b) a / (|a| r), r = sqrt(|a|^2 + |b|^2), both from the one reciprocal
+// square root of |a|^2 r^2 (rsqrt, within an ulp or two; two roots and a division only where
+// that product would leave the double range).  It sits on the serial path of every Arnoldi
+// step, where square roots and divisions are long dependent instruction chains.
 __device__ inline void cp_givens(double2 a, double2 b, double& c, double2& s) {
-  const double na = sqrt(cabs2(a)), nb = sqrt(cabs2(b));
-  if (nb == 0.0) { c = 1.0; s = mk(0.0, 0.0); return; }
-  if (na == 0.0) { c = 0.0; s = cscale(cconj(b), 1.0 / nb); return; }
-  const double nr = sqrt(na * na + nb * nb);
-  c = na / nr;
-  s = cscale(cmul(cconj(b), a), 1.0 / (na * nr));
+  const double na2 = cabs2(a), nb2 = cabs2(b);
+  if (nb2 == 0.0) { c = 1.0; s = mk(0.0, 0.0); return; }
+  if (na2 == 0.0) { c = 0.0; s = cscale(cconj(b), rsqrt(nb2)); return; }
+  const double h2 = na2 + nb2, pr = na2 * h2;
+  const double inv = (pr > 1e-290 && pr < 1e290) ? rsqrt(pr) : 1.0 / (sqrt(na2) * sqrt(h2));
+  c = na2 * inv;
+  s = cscale(cmul(cconj(b), a), inv);
 }
 __device__ inline double2 cp_div(double2 a, double2 b) {
   const double d = cabs2(b);
@@ -395,7 +401,6 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
   double2* uv = (double2*)(smem + L.u);
   double2* Mk = (double2*)(smem + L.Hk);
   double2* Pk = (double2*)(smem + L.Rk);
-  double2* red = (double2*)(smem + L.red);
   double2* res = (double2*)(smem + L.res);
   int* loc = (int*)(smem + L.loc);
   int* hsite = (int*)(smem + L.hs);
@@ -432,28 +437,29 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
   // wg_sums: per-workgroup sums of nq quantities, term(q, e) over the local entries e; the QL
   // lanes of group q (a 16-lane row with 512 threads, a half-wavefront with 1024, so all
   // CP_QMAX quantities are summed in one pass) add every QL-th entry, then a fixed DPP tree
-  // (lane 0 of the group writes red[q]).  grid_reduce: publish red[q], barrier, every
-  // workgroup adds all workgroups' sums in the same order into res[q] (half-wavefront q mod
-  // NHW gathers one or two quantities).
+  // (lane 0 of the group publishes the sum straight to this workgroup's slot of quantity q).
+  // grid_reduce: barrier, then every workgroup adds all workgroups' sums in the same order into
+  // res[q] (half-wavefront q mod NHW gathers one or two quantities).
   constexpr int QL = REG ? 16 : 32;
   static_assert(CP_QMAX * QL == TPB, "one lane group per summed quantity");
   auto group_sum = [](double2 v) {
     if constexpr (QL == 16) return mk(cp_row_sum(v.x), cp_row_sum(v.y));
     else return cp_half_sum(v);
   };
+  auto publish = [&](int q, double2 v) { cp_store(&a.partials[((size_t)rbuf * CP_QMAX + q) * G + gi], v); };
   auto wg_sums = [&](int nq, auto&& term) {
     const int q = tid / QL, c = tid % QL;
     if (q < nq) {
       double2 sm = mk(0.0, 0.0);
       for (int e = c; e < ne; e += QL) sm = cadd(sm, term(q, e));
       sm = group_sum(sm);
-      if (c == 0) red[q] = sm;
+      if (c == 0) publish(q, sm);
     }
   };
+  // the barrier's own wait and workgroup barrier order every wavefront's published sums (and
+  // exchange stores) before the flag store
   auto grid_reduce = [&](int nq, int halo_half = -1) {
-    __syncthreads();
     double2* P = a.partials + (size_t)rbuf * CP_QMAX * G;
-    if (tid < nq) cp_store(&P[(size_t)tid * G + gi], red[tid]);
     dead = dead || cp_barrier(a.flags, G, ++gen, a.err);
     const int q = tid >> 5, c = tid & 31;
     if (NHW < CP_QMAX && q + NHW < nq) {
@@ -578,7 +584,8 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
         }
         xs[t] = cp_load(&xch[(int64_t)nb * NC + jj]);
       }
-      __syncthreads();
+      // the halo form's stencil reads w itself, not the scaled copy or an exchange load
+      if (!HALO) __syncthreads();
       if (REG && tid < nsl * 5 * NC) {
         const int sl = tid / (5 * NC), d = (tid / NC) % 5;
         const T* xv = wl + loc[sl * 5 + d] * NC;
@@ -621,7 +628,7 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
           double2 sm = mk(0.0, 0.0);
           for (int e = c; e < ne; e += QL) cfmac(sm, to_d(vq[e]), to_d(wl[e]));
           sm = group_sum(sm);
-          if (c == 0) red[q] = sm;
+          if (c == 0) publish(q, sm);
         }
       };
       // w -= sum_{i <= j} res_i V_i on the own (and halo) entries
@@ -677,7 +684,7 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
           if (lane <= j) Hr[lane + (mm + 1) * j] = res[lane];  // first-pass coefficients
         } else {
           double hn1 = sqrt(fmax(hn2, 0.0));
-          const bool b = !(hn1 > 1e-12 * sqrt(ww));
+          const bool b = !(hn2 > 1e-24 * ww);  // hn1 <= 1e-12 ||w|| without a second root
           if (b) hn1 = 0.0;
           givens(res, hn1);
           if (lane == 0) {

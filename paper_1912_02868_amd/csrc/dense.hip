@@ -426,16 +426,41 @@ __device__ void hessenberg(double2* A, double2* X, double2* v, int n) {
   }
 }
 
+// Givens rotation as make_givens_fast with the reciprocal square root of |a|^2 (|a|^2 + |b|^2)
+// taken directly (rsqrt, within an ulp or two) instead of a square root and a division.
+__device__ inline void make_givens_rs(double2 a, double2 b, double& c, double2& s) {
+  const double na2 = cabs2(a), nb2 = cabs2(b);
+  if (nb2 == 0.0) { c = 1.0; s = mk(0.0, 0.0); return; }
+  if (na2 == 0.0) { c = 0.0; s = cscale(cconj(b), rsqrt(nb2)); return; }
+  const double h2 = na2 + nb2, pr = na2 * h2;
+  const double inv = (pr > 1e-290 && pr < 1e290) ? rsqrt(pr) : 1.0 / (sqrt(na2) * sqrt(h2));
+  c = na2 * inv;
+  s = cscale(cmul(cconj(b), a), inv);
+}
+
 // Complex Schur form of the Hessenberg A by single-shift implicit QR (Wilkinson shifts,
-// exceptional shifts every 10 iterations).  Returns 0 on success.  One wavefront (n <= 64):
+// exceptional shifts every 10 iterations).  Returns 0 on success.  One wavefront (n <= 64);
 // the deflation test is one ballot over the subdiagonal (|re| + |im| magnitudes, as in the
-// reference QR codes), and each bulge-chasing rotation is one pass in which lane l loads
-// column c0 + l of rows k, k+1, row l of columns k, k+1 and row l of X, applies the rotation
-// from the left and (taking the four left-updated corner entries from their lanes) from the
-// right, and the next rotation's inputs come back through scalar registers.  A wavefront's
-// LDS accesses take effect in program order, so no barrier is needed between rotations.
+// reference QR codes).
+//
+// A sweep chases the bulge with its updates deferred, so that the chain of rotations never
+// waits on the LDS and a rotation costs few instructions (one wavefront issues them one at a
+// time).  Rotation k mixes rows and columns k, k+1 of the active block [lo, hi].  Every lane
+// t plays two parts:
+//  - column t (t >= k-1): it holds the current A[k, t] and A[k+1, t] and applies the left
+//    rotation; its row-k result is final under the left rotations and the row-(k+1) result
+//    is carried to the next rotation.  Lanes k-1, k, k+1 hold the bulge pair and the 2 x 2
+//    diagonal block; lanes beyond read the untouched A[k+1, t] from the LDS.
+//  - row t (t <= k+2): it holds A[t, k] and A[t, k+1] after the left rotation and applies the
+//    right one; its column-k result is final and the column-(k+1) result is carried.  Rows
+//    above k read A[t, k+1] as the column lane wrote it; rows k and k+1 take the block from
+//    lanes k, k+1 (two lane reads), row k+2 has a zero in column k.
+//  - row t of X in the same way against the untouched X[t, k+1].
+// The next rotation's bulge pair and block come back from rows k+1, k+2 by lane reads.  Left
+// and right rotations commute and each entry sees its rotations in the plain sweep's order,
+// so the result equals that of applying every rotation to whole rows and columns in turn.
 static_assert(MMAX <= DW, "one lane per row and column of the restart eigenproblem");
-__device__ int schur_qr(double2* A, double2* X, int n, int* flag_sh) {
+__device__ int schur_qr(double2* A, double2* X, int n) {
   const int t = threadIdx.x;
   const double eps = 2.220446049250313e-16;
   int hi = n - 1, iter = 0, total = 0;
@@ -466,68 +491,74 @@ __device__ int schur_qr(double2* A, double2* X, int n, int* flag_sh) {
       const double2 m1 = cadd(m0, disc), m2 = csub(m0, disc);
       mu = (cabs2(csub(m1, d)) <= cabs2(csub(m2, d))) ? m1 : m2;
     }
+    const bool in = t < n;
+    double2 P = (t >= lo && in) ? A[lo + n * t] : mk(0.0, 0.0);  // column part: A[k, t]
+    double2 Q = mk(0.0, 0.0);                                    // column part: A[k+1, t]
+    double2 RC = (t < lo) ? A[t + n * lo] : mk(0.0, 0.0);        // row part: A[t, k]
+    double2 XC = in ? X[t + n * lo] : mk(0.0, 0.0);              // X[t, k]
     double2 x = csub(A[lo + n * lo], mu), y = A[lo + 1 + n * lo];
     for (int k = lo; k < hi; ++k) {
-      // this rotation's LDS operands are loaded first: they do not depend on its coefficients,
-      // so their latency overlaps the square root and division of make_givens_fast
-      const int c0 = (k > lo) ? k - 1 : lo;
-      const int r1 = (k + 2 < hi) ? k + 2 : hi;
-      const int jc = c0 + t;
-      const bool lft = jc < n, rgt = t <= r1, xr = t < n;
-      double2 p = mk(0.0, 0.0), q = mk(0.0, 0.0), ra = mk(0.0, 0.0), rb = mk(0.0, 0.0);
-      double2 xa = mk(0.0, 0.0), xb = mk(0.0, 0.0);
-      if (lft) {
-        p = A[k + n * jc];
-        q = A[k + 1 + n * jc];
-      }
-      if (rgt) {
-        ra = A[t + n * k];
-        rb = A[t + n * (k + 1)];
-      }
-      if (xr) {
-        xa = X[t + n * k];
-        xb = X[t + n * (k + 1)];
-      }
+      // untouched operands first: their latency overlaps the rotation's coefficients
+      if (t >= (k > lo ? k + 1 : lo) && in) Q = A[k + 1 + n * t];
+      const bool rl = t <= k - 1 || (t == k + 2 && t <= hi);
+      double2 RB = rl ? A[t + n * (k + 1)] : mk(0.0, 0.0);
+      const double2 XB = in ? X[t + n * (k + 1)] : mk(0.0, 0.0);
       double cg;
       double2 sg;
-      make_givens_fast(x, y, cg, sg);
-      // from the left on rows k, k+1 (columns c0 ..)
-      const double2 pn = cadd(cscale(p, cg), cmul(sg, q));
-      const double2 qn = csub(cscale(q, cg), cmul(cconj(sg), p));
-      if (lft) {
-        A[k + n * jc] = pn;
-        A[k + 1 + n * jc] = qn;
+      make_givens_rs(x, y, cg, sg);
+      const double2 csg = cconj(sg);
+      // left rotation (lanes k-1 .. n-1 are meaningful)
+      const double2 PN = cadd(cscale(P, cg), cmul(sg, Q));
+      const double2 QN = csub(cscale(Q, cg), cmul(csg, P));
+      if ((k > lo && t == k - 1) || (t >= k + 2 && in)) A[k + n * t] = PN;
+      if (k > lo && t == k - 1) A[k + 1 + n * t] = mk(0.0, 0.0);
+      if (t >= k + 2) P = QN;
+      // rows k, k+1 of the block; row k+2 has a zero in column k
+      const double2 pk1 = rd_lane(PN, k + 1), qk = rd_lane(QN, k);
+      double2 RA = RC;
+      if (t == k) { RA = PN; RB = pk1; }
+      if (t == k + 1) { RA = qk; RB = QN; }
+      if (t == k + 2) RA = mk(0.0, 0.0);
+      // right rotation (rows 0 .. k+2 are meaningful)
+      const double2 RAN = cadd(cscale(RA, cg), cmul(RB, csg));
+      const double2 RBN = csub(cscale(RB, cg), cmul(RA, sg));
+      if (t <= k) {
+        A[t + n * k] = RAN;
+        RC = RBN;
       }
-      // rows k, k+1 of columns k, k+1 after the left rotation
-      const double2 r00 = rd_lane(pn, k - c0), r01 = rd_lane(pn, k + 1 - c0);
-      const double2 r10 = rd_lane(qn, k - c0), r11 = rd_lane(qn, k + 1 - c0);
-      if (t == k) {
-        ra = r00;
-        rb = r01;
-      }
-      if (t == k + 1) {
-        ra = r10;
-        rb = r11;
-      }
-      // from the right by G^H on columns k, k+1 (rows 0 .. r1), and on X
-      const double2 ran = cadd(cscale(ra, cg), cmul(rb, cconj(sg)));
-      const double2 rbn = csub(cscale(rb, cg), cmul(ra, sg));
-      if (rgt) {
-        A[t + n * k] = ran;
-        A[t + n * (k + 1)] = rbn;
-      }
-      if (xr) {
-        X[t + n * k] = cadd(cscale(xa, cg), cmul(xb, cconj(sg)));
-        X[t + n * (k + 1)] = csub(cscale(xb, cg), cmul(xa, sg));
+      const double2 XN = cadd(cscale(XC, cg), cmul(XB, csg));
+      const double2 XCN = csub(cscale(XB, cg), cmul(XC, sg));
+      if (in) {
+        X[t + n * k] = XN;
+        XC = XCN;
       }
       if (k + 1 < hi) {
-        x = rd_lane(ran, k + 1);
-        y = rd_lane(ran, k + 2);
+        // the next bulge pair (rows k+1, k+2 of column k) into lane k, the block's first
+        // column into lane k+1
+        const double2 xn = rd_lane(RAN, k + 1), yn = rd_lane(RAN, k + 2), a21 = rd_lane(RBN, k + 2);
+        if (t == k) {
+          P = xn;
+          Q = yn;
+        }
+        if (t == k + 1) {
+          P = RBN;
+          Q = a21;
+        }
+        x = xn;
+        y = yn;
+      } else {
+        // last rotation: write back the block's last row and every carried entry
+        if (t == hi) {
+          A[hi + n * (hi - 1)] = RAN;
+          A[hi + n * hi] = RBN;
+        }
+        if (t < hi) A[t + n * hi] = RC;
+        if (t >= hi + 1 && in) A[hi + n * t] = P;
+        if (in) X[t + n * hi] = XC;
       }
     }
   }
   __syncthreads();
-  (void)flag_sh;
   return 0;
 }
 
@@ -622,7 +653,7 @@ __global__ void __launch_bounds__(DW) k_dr_restart(KState* ks, int m, int k, dou
   }
   __syncthreads();
   hessenberg(A, X, v, m);
-  if (schur_qr(A, X, m, nullptr)) { if (t == 0) *status = 3; return; }
+  if (schur_qr(A, X, m)) { if (t == 0) *status = 3; return; }
   __syncthreads();
   // eigenvalues and the order: key (round(|theta| / max|theta|, 12), Im theta, index); lane e
   // forms its modulus and key once (m <= 64), the maximum is a wavefront max
