@@ -141,7 +141,8 @@ def critical_mass(theta, antiperiodic=True, k=16, force_sparse=False, verbose=Fa
         half_prev = half
         kk = k
         y = covered + 0.9 * half
-    # the leftmost eigenvalue to full accuracy: shift-invert about the one found
+    # the leftmost eigenvalue to full accuracy: shift-invert about the one found.  The value
+    # from the covering discs (Arnoldi tolerance 1e-8) can be off by far more than 1e-8 for an
+    # ill-conditioned pair, so only the converged eigenvalues give the answer.
     lam, _ = leftmost_eigenvalues(theta, antiperiodic, sigma=lead, k=4, tol=1e-13)
-    re_min = min(re_min, float(lam.real.min()))
-    return -re_min, float(ymax)
+    return -float(lam.real.min()), float(ymax)
