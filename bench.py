@@ -70,6 +70,11 @@ def parse():
                     help="mass-gap and lattice-size scan of six solvers with power-law fits (prints its own JSON)")
     ap.add_argument("--scan-sizes", default="64,128,256")
     ap.add_argument("--scan-configs", type=int, default=2)
+    ap.add_argument("--scan-first-config", type=int, default=0,
+                    help="first configuration of the scan (configurations first .. first + count - 1)")
+    ap.add_argument("--scan-merge", default="",
+                    help="comma-separated files holding earlier --scan outputs: combine their rows, refit and print "
+                         "(no GPU)")
     ap.add_argument("--scan-gaps", default="1e-1,1e-2,1e-3,1e-4")
     ap.add_argument("--scan-fit-gap", type=float, default=1e-4)
     ap.add_argument("--scan-rhs", type=int, default=2)
@@ -100,6 +105,9 @@ def main():
         import atexit
         import shutil
         atexit.register(lambda: shutil.copyfile("/proc/self/maps", a.maps))
+    if a.scan_merge:
+        print(json.dumps(scan_merge(a.scan_merge.split(","), a.scan_fit_gap)), flush=True)
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the solver has no multi-GPU path.",
               file=sys.stderr)
@@ -119,7 +127,7 @@ def main():
         ctx = dmg.Context(0)
         out = scan(torch, dmg, ctx, [int(v) for v in a.scan_sizes.split(",")], a.scan_configs,
                    [float(v) for v in a.scan_gaps.split(",")], a.scan_fit_gap, a.scan_rhs,
-                   tuple(int(v) for v in a.scan_coarse.split(",")))
+                   tuple(int(v) for v in a.scan_coarse.split(",")), a.scan_first_config)
         ctx.close()
         print(json.dumps(out), flush=True)
         return
@@ -837,7 +845,37 @@ def power_fit(sizes, values):
     return float(coef[0]), float(se)
 
 
-def scan(torch, dmg, ctx, sizes, ncfg, gaps, fit_gap, nrhs, coarse=(200, 40)):
+def scan_fits(rows, gap):
+    """alpha in Mvps = size^alpha per method over the converged rows at one mass gap."""
+    out = {}
+    for meth in SCAN_METHODS:
+        pts = [(r["N"] * r["N"], r["fine_equiv_mvps"]) for r in rows
+               if r["method"] == meth and r["gap"] == gap and r["converged"]]
+        if len({p[0] for p in pts}) >= 2:
+            a_, se = power_fit([p[0] for p in pts], [p[1] for p in pts])
+            out[meth] = {"alpha": a_, "stderr": se, "points": len(pts)}
+    return out
+
+
+def scan_merge(paths, fit_gap):
+    """Rows of several scan runs (each file's last line is a --scan JSON line) combined and refitted."""
+    runs = []
+    for path in paths:
+        with open(path) as f:
+            runs.append(json.loads([ln for ln in f.read().splitlines() if ln.strip()][-1]))
+    rows = [r for run in runs for r in run["rows"]]
+    gaps = sorted({r["gap"] for r in rows}, reverse=True)
+    return {"scan": runs[0]["scan"], "merged_from": paths, "sizes": sorted({r["N"] for r in rows}),
+            "configs": {str(N): sorted({r["cfg"] for r in rows if r["N"] == N}) for N in sorted({r["N"] for r in rows})},
+            "gaps": gaps, "rhs_per_config": runs[0]["rhs_per_config"], "fit_gap": fit_gap,
+            "size_measure": "lattice sites", "alpha_fits": scan_fits(rows, fit_gap),
+            "alpha_fits_by_gap": {f"{gap:g}": scan_fits(rows, gap) for gap in gaps},
+            "fine_gmres_dr": runs[0]["fine_gmres_dr"], "coarse_deflation": runs[0]["coarse_deflation"],
+            "configs_without_stored_mass": sorted({c for run in runs for c in run["configs_without_stored_mass"]}),
+            "rows": rows, "wall_s": sum(run["wall_s"] for run in runs)}
+
+
+def scan(torch, dmg, ctx, sizes, ncfg, gaps, fit_gap, nrhs, coarse=(200, 40), first=0):
     """Fine-equivalent Mvps (eq. (1)) of six solvers over mass gaps m0 - m_c and lattice sizes,
     on the synthetic ensembles (not the paper's configurations): deflated multigrid with the
     partial intermediate solve (the default), deflated multigrid with intermediate smoothing
@@ -852,7 +890,7 @@ def scan(torch, dmg, ctx, sizes, ncfg, gaps, fit_gap, nrhs, coarse=(200, 40)):
     t_start = time.perf_counter()
     skipped = []
     for N in sizes:
-        for c in range(ncfg):
+        for c in range(first, first + ncfg):
             try:
                 mc = synth.critical_mass(N, c)
             except KeyError:
@@ -901,20 +939,10 @@ def scan(torch, dmg, ctx, sizes, ncfg, gaps, fit_gap, nrhs, coarse=(200, 40)):
                           f"Mvps, converged {row['converged']}, {el:.1f} s", file=sys.stderr, flush=True)
                 h.close()
             g.close()
-    def fits_at(gap):
-        out = {}
-        for meth in SCAN_METHODS:
-            pts = [(r["N"] * r["N"], r["fine_equiv_mvps"]) for r in rows
-                   if r["method"] == meth and r["gap"] == gap and r["converged"]]
-            if len({p[0] for p in pts}) >= 2:
-                a_, se = power_fit([p[0] for p in pts], [p[1] for p in pts])
-                out[meth] = {"alpha": a_, "stderr": se, "points": len(pts)}
-        return out
-
-    fits = fits_at(fit_gap)
-    fits_by_gap = {f"{gap:g}": fits_at(gap) for gap in gaps}
+    fits = scan_fits(rows, fit_gap)
+    fits_by_gap = {f"{gap:g}": scan_fits(rows, gap) for gap in gaps}
     return {"scan": "fine-equivalent Mvps vs mass gap and lattice size (synthetic ensembles)",
-            "sizes": sizes, "configs_per_size": ncfg, "gaps": gaps, "rhs_per_config": nrhs,
+            "sizes": sizes, "configs_per_size": ncfg, "first_config": first, "gaps": gaps, "rhs_per_config": nrhs,
             "fit_gap": fit_gap, "size_measure": "lattice sites", "alpha_fits": fits,
             "alpha_fits_by_gap": fits_by_gap,
             "fine_gmres_dr": [FINE_DR_M, FINE_DR_K], "coarse_deflation": list(coarse),
