@@ -884,21 +884,41 @@ dmg_status fine_solve(dmg_hierarchy* h, int method, int m, int k, double tol, in
     w->cnt = Counters{};
     cg_normal(h, w, 0, nrhs, b, y.as<double2>(), tol, max_iters, its.data());
     for (int f = 0; f < nrhs; ++f) A.apply(s, y.as<double2>() + f * n, x + f * n, 1, nullptr);
-    DevBuf rn, scal;
+    DevBuf rn, dy, scal;
     rn.alloc(h->ctx, sizeof(double2) * n);
     scal.alloc(h->ctx, sizeof(double) * 2);
     auto t1 = std::chrono::steady_clock::now();
     for (int f = 0; f < nrhs; ++f) {
-      A.apply(s, x + f * n, rn.as<double2>(), 0, nullptr, b + f * n);
-      launch_norm2<double>(s, n, rn.as<double2>(), scal.as<double>(), PART(w), CNT(w));
-      launch_norm2<double>(s, n, b + f * n, scal.as<double>() + 1, PART(w), CNT(w));
+      double2* yf = y.as<double2>() + f * n;
+      double2* xf = x + f * n;
       double v[2];
-      DMG_HIP(hipMemcpyAsync(v, scal.p, sizeof(v), hipMemcpyDeviceToHost, s));
-      DMG_HIP(hipStreamSynchronize(s));
+      auto true_residual = [&]() {  // rn = b - D x, v = (||rn||^2, ||b||^2)
+        A.apply(s, xf, rn.as<double2>(), 0, nullptr, b + f * n);
+        launch_norm2<double>(s, n, rn.as<double2>(), scal.as<double>(), PART(w), CNT(w));
+        launch_norm2<double>(s, n, b + f * n, scal.as<double>() + 1, PART(w), CNT(w));
+        DMG_HIP(hipMemcpyAsync(v, scal.p, sizeof(v), hipMemcpyDeviceToHost, s));
+        DMG_HIP(hipStreamSynchronize(s));
+      };
+      true_residual();
+      // Near the critical mass the recursively updated residual of CG on D D^dagger drifts from
+      // the true one (by about 1e-8 relative at a mass gap of 1e-4): while the true residual is
+      // above tol, CG is restarted on D D^dagger dy = b - D x from dy = 0 and y += dy.
+      int passes = 0;
+      while (passes < 8 && its[f] < max_iters && v[1] > 0.0 && std::sqrt(v[0] / v[1]) > tol) {
+        if (!dy.p) dy.alloc(h->ctx, sizeof(double2) * n);
+        const double tol_r = 0.9 * tol * std::sqrt(v[1] / v[0]);  // relative to ||b - D x||
+        int it = 0;
+        cg_normal(h, w, 0, 1, rn.as<double2>(), dy.as<double2>(), tol_r, max_iters - its[f], &it);
+        its[f] += it;
+        launch_axpby<double>(s, n, 1.0, dy.as<double2>(), 1.0, yf);
+        A.apply(s, yf, xf, 1, nullptr);
+        ++passes;
+        true_residual();
+      }
       dmg_solve_stats& o = st[f];
       o = dmg_solve_stats{};
       o.outer_iters = its[f];
-      o.fine_mvps = 2LL * its[f] + 1;
+      o.fine_mvps = 2LL * its[f] + 1 + 2LL * passes;
       o.fine_equiv_mvps = (double)o.fine_mvps;
       o.true_rel_resid = v[1] > 0.0 ? std::sqrt(v[0] / v[1]) : 0.0;
       o.converged = o.true_rel_resid <= tol * (1.0 + 1e-6) ? 1 : 0;
