@@ -559,6 +559,10 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
       for (int i = 0; i <= mm; ++i) gv[i] = mk(0.0, 0.0);
       gv[0] = mk(hprev, 0.0);
     }
+    // the rotation wavefront keeps this cycle's rotations (lane l: rotation l) and the last
+    // entry of g in registers; the LDS copies serve the least-squares solve at the end
+    double rot_c = 1.0;
+    double2 rot_s = mk(0.0, 0.0), gcur = mk(hprev, 0.0);
     int steps = 0;
     bool brk = false, stop = false;
     // cancellation below which the Pythagorean norm is replaced by a second pass
@@ -650,8 +654,8 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
         double2* col = Hr + (mm + 1) * j;
         const double2 h0 = src[0];
         const double2 hnext = lane + 1 <= j ? src[lane + 1] : mk(hn, 0.0);  // h_{lane+1}
-        const double cl = lane < j ? rc[lane] : 1.0;
-        const double2 sl = lane < j ? rs[lane] : mk(0.0, 0.0);
+        const double cl = lane < j ? rot_c : 1.0;
+        const double2 sl = lane < j ? rot_s : mk(0.0, 0.0);
         double2 x0;
         const double2 xq = cp_rotation_scan(lane, j, h0, cl, sl, hnext, x0);
         if (lane < j) col[lane] = cadd(cscale(xq, cl), cmul(sl, hnext));
@@ -659,15 +663,21 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
         double c;
         double2 sg;
         cp_givens(x0, x1, c, sg);
+        // g_j = c g_j + s g_{j+1} and g_{j+1} = -conj(s) g_j with g_{j+1} = 0 before this rotation
+        const double2 gj = cscale(gcur, c), gn = csub(mk(0.0, 0.0), cmul(cconj(sg), gcur));
+        if (lane == j) {
+          rot_c = c;
+          rot_s = sg;
+        }
+        gcur = gn;
         if (lane == 0) {
           col[j] = cadd(cscale(x0, c), cmul(sg, x1));
           col[j + 1] = mk(0.0, 0.0);
           rc[j] = c;
           rs[j] = sg;
-          const double2 g0 = gv[j], g1 = gv[j + 1];
-          gv[j] = cadd(cscale(g0, c), cmul(sg, g1));
-          gv[j + 1] = csub(cscale(g1, c), cmul(cconj(sg), g0));
-          sh_scal[0] = sqrt(cabs2(gv[j + 1]));
+          gv[j] = gj;
+          gv[j + 1] = gn;
+          sh_scal[0] = cabs2(gn);  // squared residual estimate
         }
       };
       arn_dots();
@@ -716,11 +726,12 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
         brk = sh_flag[2] != 0;
       }
       if (!HALO && j + 1 < mm) dead = dead || cp_barrier(a.flags, G, ++gen, a.err);
-      est = brk ? 0.0 : sh_scal[0];
+      est = brk ? 0.0 : sh_scal[0];  // squared until the cycle ends
       steps = j + 1;
       hprev = hn;
-      if (dead || brk || est <= tol_abs || iters + steps >= a.max_iters) { stop = true; break; }
+      if (dead || brk || est <= tol_abs * tol_abs || iters + steps >= a.max_iters) { stop = true; break; }
     }
+    est = sqrt(est);  // every step above left the squared estimate
     // ------------------------------------------------------------ end of cycle: x += V y, r = V u
     if (tid == 0) {
       for (int i = steps - 1; i >= 0; --i) {
