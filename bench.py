@@ -214,6 +214,17 @@ def main():
             "mean_outer_iters": float(np.mean([s["outer_iters"] for s in st16])),
             "max_true_rel_resid": float(max(s["true_rel_resid"] for s in st16)),
         }
+        progress(f"BF16 intermediate blocks: {n_solves / el16:.2f} solves/s")
+        el16c, lat16c, st16c = timed(dmg.FP32_BF16C)
+        out_mixed["bf16_coarse_blocks"] = {
+            "value": n_solves / el16c, "unit": "solves/s",
+            "dtype": "f32 preconditioner with the coarse blocks rounded to bf16 (f32 accumulate), f64 outer",
+            "p50_ms": percentile(lat16c, 50), "p99_ms": percentile(lat16c, 99),
+            "all_converged_1e-8": all(s["converged"] and s["true_rel_resid"] <= 1e-8 for s in st16c),
+            "speedup_vs_fp64": (n_solves / el16c) / (n_solves / el64),
+            "mean_outer_iters": float(np.mean([s["outer_iters"] for s in st16c])),
+            "max_true_rel_resid": float(max(s["true_rel_resid"] for s in st16c)),
+        }
 
     if a.calibrate_copy:
         # plain streaming kernels of known size: uniform_ writes 256 MiB; mul reads 256 MiB
@@ -248,7 +259,7 @@ def main():
     oracle_err = None
     if not a.no_oracle_error:
         oracle_err = errors_vs_oracle(synth, N, res, sols)
-        for prec, key in ((dmg.FP32, None), (dmg.FP32_BF16, "bf16_blocks")):
+        for prec, key in ((dmg.FP32, None), (dmg.FP32_BF16, "bf16_blocks"), (dmg.FP32_BF16C, "bf16_coarse_blocks")):
             if out_mixed is not None and prec in oracle_err:
                 (out_mixed if key is None else out_mixed[key])["error_vs_oracle"] = oracle_err.pop(prec)
 

@@ -61,8 +61,13 @@ enum { DMG_PTR_HOST = 0, DMG_PTR_DEVICE = 1 };
  * vectors, orthogonalisation, least squares, true residual) is always FP64. */
 /* DMG_FP32_BF16: FP32 fields and arithmetic with the intermediate-grid operator D-hat stored in
  * bfloat16 (each part of every block entry rounded to FP32, then to bfloat16, nearest even);
- * a preconditioner precision (and a precision of the level-1 operator hooks). */
-typedef enum { DMG_FP64 = 0, DMG_FP32 = 1, DMG_FP32_BF16 = 2 } dmg_precision;
+ * a preconditioner precision (and a precision of the level-1 operator hooks).
+ * DMG_FP32_BF16C: FP32 fields and arithmetic with the coarse-grid operator D_c rounded to
+ * bfloat16 the same way (FP32 accumulation; the rounded entries are held as FP32 values, since
+ * the persistent coarse kernel loads them into registers once per solve); the deflation space
+ * is built in FP64 on the unrounded D_c.  A preconditioner precision of dmg_solve and the pools
+ * (not of the lockstep forms) and of the single-field level-2 operator hook. */
+typedef enum { DMG_FP64 = 0, DMG_FP32 = 1, DMG_FP32_BF16 = 2, DMG_FP32_BF16C = 3 } dmg_precision;
 
 typedef struct dmg_context dmg_context;
 typedef struct dmg_gauge dmg_gauge;

@@ -418,7 +418,8 @@ dmg_status dmg_hierarchy_apply(dmg_hierarchy* h, int level, int op, dmg_precisio
   if (!h) return DMG_E_INVALID;
   return guarded(h->ctx, [&]() -> dmg_status {
     DMG_CHECK(in && out && level >= 0 && level <= 2, DMG_E_INVALID, "hierarchy_apply: bad arguments");
-    DMG_CHECK(p == DMG_FP64 || p == DMG_FP32 || p == DMG_FP32_BF16, DMG_E_INVALID, "hierarchy_apply: precision");
+    DMG_CHECK(p == DMG_FP64 || p == DMG_FP32 || p == DMG_FP32_BF16 || p == DMG_FP32_BF16C, DMG_E_INVALID,
+              "hierarchy_apply: precision");
     const bool is_transfer = op == DMG_OP_RESTRICT || op == DMG_OP_PROLONG;
     DMG_CHECK(!is_transfer || level <= 1, DMG_E_INVALID, "transfers exist between levels 0-1 and 1-2");
     const size_t es = p == DMG_FP64 ? sizeof(double2) : sizeof(float2);
@@ -451,7 +452,9 @@ dmg_status dmg_hierarchy_apply(dmg_hierarchy* h, int level, int op, dmg_precisio
         default: DMG_CHECK(false, DMG_E_INVALID, "unknown op");
       }
     } else {
-      const Op& Af = (p == DMG_FP32_BF16 && level == 1) ? h->op16 : h->op[level];
+      const Op& Af = (p == DMG_FP32_BF16 && level == 1)    ? h->op16
+                     : (p == DMG_FP32_BF16C && level == 2) ? h->opc16
+                                                           : h->op[level];
       switch (op) {
         case DMG_OP_APPLY: Af.apply(s, (const float2*)din, (float2*)dout, 0, nullptr); break;
         case DMG_OP_APPLY_DAG: Af.apply(s, (const float2*)din, (float2*)dout, 1, nullptr); break;

@@ -150,6 +150,8 @@ void launch_galerkin(hipStream_t s, const double2* fineA, const double2* P, int 
 void launch_d2f(hipStream_t s, int64_t ncomplex, const double2* x, float2* y);
 // BF16 copy of FP64 blocks (re, im each rounded to FP32, then to bfloat16, nearest even)
 void launch_d2bf16(hipStream_t s, int64_t ncomplex, const double2* x, bf16c* y);
+// each part rounded to FP32, then to bfloat16 (nearest even), kept as FP32
+void launch_d2bf16f(hipStream_t s, int64_t ncomplex, const double2* x, float2* y);
 // block stencil with BF16-stored blocks, FP32 vectors and arithmetic
 void launch_block_apply_bf16(hipStream_t st, const bf16c* A, const float2* in, float2* out, int Lx, int Lt,
                              int dagger, const int* skip, const float2* sub);

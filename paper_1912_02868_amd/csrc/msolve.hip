@@ -657,9 +657,9 @@ dmg_status dmg_batch_create(dmg_hierarchy* h, dmg_deflation* d, int capacity, co
     DMG_CHECK(p.tol > 0.0 && p.int_tol > 0.0 && p.coarse_tol_later > 0.0 && p.max_outer_iters >= 1 &&
                   p.int_max_iters >= 1 && p.coarse_max_iters >= 1 && p.outer_m >= 1 && p.outer_m <= MB &&
                   p.int_m >= 1 && p.int_m <= MB && p.smooth_steps == 2 && !p.use_x0 && d->m - d->kk <= MB &&
-                  p.int_mode == 0,
+                  p.int_mode == 0 && (p.precond == DMG_FP64 || p.precond == DMG_FP32 || p.precond == DMG_FP32_BF16),
               DMG_E_INVALID, "batch parameters (restart lengths <= 24, two smoothing steps, no x0, partial "
-                             "intermediate solve)");
+                             "intermediate solve, a precision of the lockstep form)");
     if (p.precond != DMG_FP64) prepare_deflation_fp32(&h->main, d);
     int nb = 1;
     while (nb < capacity) nb *= 2;

@@ -147,6 +147,8 @@ struct dmg_hierarchy {
   dmg::DevBuf A64[3], A32[3], P64[2], P32[2], null[2];
   dmg::DevBuf A16;  // BF16 copy of the level-1 blocks
   dmg::Op op16;     // level-1 operator reading them (FP32 applies)
+  dmg::DevBuf A32c16;  // level-2 blocks rounded to bfloat16, held as FP32
+  dmg::Op opc16;       // level-2 operator reading them (FP32 applies)
   int setup_iters[2][64] = {};
   dmg::Work main;  // workspace of dmg_solve, the setup and the deflation build (context stream)
   dmg::BWork* bwork = nullptr;  // workspace of dmg_solve_batched (kept between calls)

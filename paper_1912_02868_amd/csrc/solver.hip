@@ -380,6 +380,11 @@ void build_hierarchy(dmg_hierarchy* h, const double2* start0, const double2* sta
       launch_d2bf16(s, ce, h->A64[1].as<double2>(), h->A16.as<bf16c>());
       h->op16 = C;
       h->op16.A16 = h->A16.as<bf16c>();
+    } else {
+      h->A32c16.alloc(h->ctx, sizeof(float2) * ce);
+      launch_d2bf16f(s, ce, h->A64[2].as<double2>(), h->A32c16.as<float2>());
+      h->opc16 = C;
+      h->opc16.A32 = h->A32c16.as<float2>();
     }
     DMG_HIP(hipStreamSynchronize(s));
   }
@@ -404,10 +409,11 @@ struct Precond {
   DevBuf cg_y;                     // CGNE iterate of the non-deflated coarse solve
   const dmg_solve_params* p = nullptr;
   dmg_deflation* defl = nullptr;
-  bool bf16 = false;  // FP32 with the BF16-stored intermediate operator
+  bool bf16 = false;   // FP32 with the BF16-stored intermediate operator
+  bool bf16c = false;  // FP32 with the BF16-rounded coarse operator
 
   Precond(dmg_hierarchy* hh, Work* ww) : h(hh), w(ww) {}
-  const Op& op(int l) const { return (l == 1 && bf16) ? h->op16 : h->op[l]; }
+  const Op& op(int l) const { return (l == 1 && bf16) ? h->op16 : (l == 2 && bf16c) ? h->opc16 : h->op[l]; }
 
   hipStream_t S() const { return w->stream; }
   const T* Pm(int lvl) const { return (const T*)h->tr[lvl].P((const T*)nullptr); }
@@ -416,6 +422,7 @@ struct Precond {
     p = prm;
     defl = d;
     bf16 = sizeof(R) == sizeof(float) && prm->precond == DMG_FP32_BF16;
+    bf16c = sizeof(R) == sizeof(float) && prm->precond == DMG_FP32_BF16C;
     dmg_context* c = w->ctx;
     const size_t es = sizeof(T);
     if (!sm[0].V.p || smooth_steps != prm->smooth_steps) {
@@ -484,7 +491,7 @@ struct Precond {
   // GMRES-Proj(m, k): projection over the deflation space, then GMRES(m - k) cycles.
   void gmres_proj(const T* b, T* x, double tol) {
     dmg_deflation* d = defl;
-    const Op& A = h->op[2];
+    const Op& A = op(2);
     const int64_t n = A.n;
     const int k = d->kk;
     const int mm = std::max(d->m - k, 1);
@@ -688,8 +695,9 @@ void prepare_work(dmg_hierarchy* h, Work* w, dmg_deflation* d, const dmg_solve_p
             DMG_E_INVALID, "restart lengths must lie in [1, 64]");
   DMG_CHECK(!d || d->h == h, DMG_E_INVALID, "deflation space belongs to another hierarchy");
   const int64_t n = h->op[0].n;
-  DMG_CHECK(p->precond == DMG_FP64 || p->precond == DMG_FP32 || p->precond == DMG_FP32_BF16, DMG_E_INVALID,
-            "preconditioner precision");
+  DMG_CHECK(p->precond == DMG_FP64 || p->precond == DMG_FP32 || p->precond == DMG_FP32_BF16 ||
+                p->precond == DMG_FP32_BF16C,
+            DMG_E_INVALID, "preconditioner precision");
   const bool fp32 = p->precond != DMG_FP64;
   if (!w->outer.V.p || w->outer.m != p->outer_m || w->outer.n != n) {
     w->outer.alloc(w->ctx, p->outer_m, n, sizeof(double2), true);

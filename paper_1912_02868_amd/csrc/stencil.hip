@@ -175,6 +175,24 @@ void launch_d2bf16(hipStream_t st, int64_t n, const double2* x, bf16c* y) {
   DMG_LAUNCH_CHECK();
 }
 
+// The same rounding to bfloat16, the result held as FP32 (the low 16 bits zero)
+__global__ void k_d2bf16f(int64_t n, const double2* __restrict__ x, float2* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  auto rnd = [](double v) {
+    const unsigned u = __float_as_uint((float)v);
+    return __uint_as_float(((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16) << 16);
+  };
+  const double2 v = x[i];
+  y[i] = make_float2(rnd(v.x), rnd(v.y));
+}
+
+void launch_d2bf16f(hipStream_t st, int64_t n, const double2* x, float2* y) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_d2bf16f, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, x, y);
+  DMG_LAUNCH_CHECK();
+}
+
 // Restriction: coarse(B, 12 c + k) = sum_{s in B} sum_{i < h} conj(P[s][c h + i][k]) fine[s][c h + i],
 // h = dof / 2.  One workgroup per block; thread (g, o) sums the terms q = g, g + G, ... of
 // output o, then the G partials are added through LDS in a fixed order.

@@ -26,7 +26,7 @@ DMG_E_BUDGET = -4
 DMG_E_NOMEM = -5
 DMG_E_BREAKDOWN = -6
 PTR_HOST, PTR_DEVICE = 0, 1
-FP64, FP32, FP32_BF16 = 0, 1, 2
+FP64, FP32, FP32_BF16, FP32_BF16C = 0, 1, 2, 3
 PART_NULLVECS, PART_P, PART_BLOCKS, PART_SETUP_ITERS = 0, 1, 2, 3
 OP_APPLY, OP_APPLY_DAG, OP_RESTRICT, OP_PROLONG = 0, 1, 2, 3
 
@@ -181,7 +181,7 @@ def solve_params(**kw) -> SolveParams:
     lib().dmg_solve_params_default(C.byref(p))
     for k, v in kw.items():
         if k == "precond" and isinstance(v, str):
-            v = {"fp64": FP64, "fp32": FP32, "fp32_bf16": FP32_BF16}[v]
+            v = {"fp64": FP64, "fp32": FP32, "fp32_bf16": FP32_BF16, "fp32_bf16c": FP32_BF16C}[v]
         setattr(p, k, v)
     return p
 
@@ -336,11 +336,14 @@ class Hierarchy:
         self.ctx.check(lib().dmg_hierarchy_export(self.h, level, part, buf.ctypes.data_as(C.c_void_p), nb), "export")
         return buf
 
-    def apply(self, level: int, op: int, x, out, bf16: bool = False):
-        """Operator / transfer hook on single fields (bf16: complex64 fields, level-1 blocks in BF16)."""
+    def apply(self, level: int, op: int, x, out, bf16: bool = False, bf16c: bool = False):
+        """Operator / transfer hook on single fields (bf16: complex64 fields, level-1 blocks in BF16;
+        bf16c: complex64 fields, level-2 blocks rounded to BF16)."""
         prec = FP32 if str(getattr(x, "dtype", "")).endswith("complex64") else FP64
         if bf16:
             prec = FP32_BF16
+        if bf16c:
+            prec = FP32_BF16C
         pin, kind = _ptr(x)
         pout, _ = _ptr(out)
         self.ctx.check(lib().dmg_hierarchy_apply(self.h, level, op, prec, pin, pout, kind), "hierarchy_apply")

@@ -208,6 +208,34 @@ def test_bf16_block_operator(dmg, injected):
     assert _rel(out16.astype(complex), ref_dag) < 2e-6
 
 
+def test_bf16_coarse_operator(dmg, injected):
+    """Level-2 operator with its blocks rounded to bfloat16 (the coarse variant of the precision
+    form): FP32 product over the oracle's coarse blocks rounded through FP32 to bfloat16, visibly
+    different from the FP32-block product; the intermediate level is unchanged by the flag."""
+    from oracle.precision import bf16_round
+    N, th, m0, H, g, hg = injected
+    if N // 16 < 3:
+        # a 1 x 1 coarse lattice: the assembled matrix adds the five blocks of the one site before
+        # any rounding, the device rounds each block
+        pytest.skip("coarse lattice with distinct neighbours")
+    A = H.levels[2].A.tocsr(copy=True)
+    A16 = A.copy()
+    A16.data = bf16_round(A16.data)
+    v = synth.gaussian_complex(A.shape[0], N, 1, 8, 6).astype(np.complex64)
+    out16 = np.empty_like(v)
+    out32 = np.empty_like(v)
+    hg.apply(2, dmg.OP_APPLY, v, out16, bf16c=True)
+    hg.apply(2, dmg.OP_APPLY, v, out32)
+    ref16 = A16 @ v.astype(complex)
+    assert _rel(out16.astype(complex), ref16) < 2e-6 and _elem(out16.astype(complex), ref16) < 1e-5
+    assert _rel(out16.astype(complex), out32.astype(complex)) > 1e-4
+    v1 = synth.gaussian_complex(H.levels[1].A.shape[0], N, 1, 8, 7).astype(np.complex64)
+    o1, o1c = np.empty_like(v1), np.empty_like(v1)
+    hg.apply(1, dmg.OP_APPLY, v1, o1)
+    hg.apply(1, dmg.OP_APPLY, v1, o1c, bf16c=True)
+    assert np.array_equal(o1, o1c)
+
+
 # ---------------------------------------------------------------- deflation space
 def test_gmres_dr_deflation_space(dmg, injected):
     N, th, m0, H, g, hg = injected
@@ -363,6 +391,29 @@ def test_solve_bf16_preconditioner_64(dmg, ctx, injected):
     assert e.value.code == dmg.DMG_E_INVALID
 
 
+def test_solve_bf16_coarse_preconditioner_64(dmg, ctx, injected):
+    """FP32 preconditioner with the coarse operator rounded to BF16 (FP64 outer solve): the true
+    residual reaches 1e-8, the solution agrees with sparse LU, and the lockstep forms refuse the
+    precision."""
+    N, th, m0, H, g, hg = injected
+    if N != 64:
+        pytest.skip("workload-sized solve")
+    import scipy.sparse.linalg as spla
+    D = H.levels[0].A
+    d = dmg.Deflation(hg, 30, 10)
+    lu = spla.splu(D.tocsc())
+    for j in range(2):
+        b = synth.rhs(64, 0, j)
+        st, s, x, res = _solve_and_check(dmg, ctx, hg, D, b, d, precond=dmg.FP32_BF16C)
+        assert st == dmg.DMG_OK and s["converged"] == 1 and res <= 1e-8
+        assert _rel(x, lu.solve(b)) < 1e-6
+    B = np.stack([synth.rhs(64, 0, j) for j in range(2)])
+    X = np.zeros_like(B)
+    with pytest.raises(dmg.DmgError) as e:
+        dmg.solve_batched(ctx, hg, d, B, X, 2, params=dmg.solve_params(precond=dmg.FP32_BF16C))
+    assert e.value.code == dmg.DMG_E_INVALID
+
+
 def test_solve_zero_rhs_and_cap(dmg, ctx, injected):
     N, th, m0, H, g, hg = injected
     if N != 16:
@@ -431,3 +482,29 @@ def test_persistent_coarse_forms_workload(dmg, ctx, N):
     for j in range(2):
         assert _rel(out[1][0][j], out[0][0][j]) < 1e-6
         assert abs(out[1][1][j]["outer_iters"] - out[0][1][j]["outer_iters"]) <= 1
+
+
+def test_fine_cgne_true_residual_near_critical(dmg, ctx):
+    """At a mass gap of 1e-4 the recursively updated residual of CG on D D^dagger drifts from the
+    true one by about 1e-8; the fine CGNE restarts on the true residual until it meets the
+    tolerance (64^2 configurations 0 and 3, one right-hand side each, checked with the oracle's D)."""
+    import scipy.sparse.linalg as spla
+    for cfg in (0, 3):
+        th = synth.gauge_angles(64, cfg)
+        m0 = synth.critical_mass(64, cfg) + 1e-4
+        g = dmg.Gauge(ctx, th)
+        hg = dmg.Hierarchy(ctx, g, m0, synth.near_null_starts(64, cfg, 0), synth.near_null_starts(64, cfg, 1))
+        D = wilson.dirac_matrix(th, m0)
+        b = synth.rhs(64, cfg, 0)
+        x = np.zeros_like(b)
+        print(f"[case] fine CGNE 64^2 configuration {cfg} at gap 1e-4", flush=True)
+        st, s = dmg.solve_fine(ctx, hg, dmg.FINE_CGNE, b, x, 1, max_iters=200000)
+        res = np.linalg.norm(b - D @ x) / np.linalg.norm(b)
+        print(f"    {s[0]['outer_iters']} iterations, true residual {res:.2e}", flush=True)
+        assert st == dmg.DMG_OK and s[0]["converged"] == 1
+        assert res <= 1e-8 * (1 + 1e-6) and abs(res - s[0]["true_rel_resid"]) < 1e-12
+        lu = spla.splu(D.tocsc(), permc_spec="MMD_AT_PLUS_A")
+        # the solution to the accuracy the residual bound allows at this conditioning
+        assert _rel(x, lu.solve(b)) < 1e-3
+        hg.close()
+        g.close()

@@ -1,9 +1,9 @@
 """GPU results at the workload sizes and on the edge cases, against the FP64 oracle.
 
 - 256^2 (the plain and precision forms): the solution of a GMRES-DR first solve and a
-  GMRES-Proj later solve against sparse LU of the oracle's D, for the FP64, FP32 and
-  BF16-block preconditioners (the FP32 forms take the register-block persistent coarse
-  kernel with four coarse sites per workgroup there).
+  GMRES-Proj later solve against sparse LU of the oracle's D, for the FP64, FP32,
+  BF16-intermediate-block and BF16-coarse-block preconditioners (the FP32 forms take the
+  register-block persistent coarse kernel with four coarse sites per workgroup there).
 - 512^2 x 64 right-hand sides (the batched form): every lane's true residual with the
   oracle's D, and the solution against sparse LU for a sample of lanes.
 - Setup without injection: the near-null vectors the device computed satisfy their
@@ -65,7 +65,7 @@ def cfg256(dmg, ctx):
     return N, cfg, g, h, D, lu
 
 
-@pytest.mark.parametrize("precond", ["fp64", "fp32", "fp32_bf16"])
+@pytest.mark.parametrize("precond", ["fp64", "fp32", "fp32_bf16", "fp32_bf16c"])
 def test_solution_vs_lu_256(dmg, ctx, cfg256, precond):
     """RHS 0 (first coarse call GMRES-DR) and RHS 1 (GMRES-Proj) of 256^2 configuration 0:
     true residual <= 1e-8 with the oracle's D, solution within 1e-6 of sparse LU."""
