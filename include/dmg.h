@@ -228,8 +228,9 @@ dmg_status dmg_hierarchy_apply_batched_static(dmg_hierarchy* h, int level, int o
 /* Coarse-grid deflation space (Methods section): EMPTY until the first coarse
  * solve runs GMRES-DR(m, k), which leaves A V_k = V_{k+1} Hbar_k; READY after
  * that, when every coarse solve is GMRES-Proj(m, k).  Tied to one hierarchy.
- * Sizes: 1 <= k < m <= 256 and k <= 64 (DMG_E_INVALID otherwise).  Spaces with m <= 64
- * and k <= 31 use the short-cycle solvers (persistent coarse kernels); larger ones (the
+ * Sizes: 1 <= k < m <= 256 and k <= 64 (DMG_E_INVALID otherwise).  Spaces with m <= 63
+ * and k <= 31 whose deflated restart fits one workgroup's LDS (every such space with
+ * m <= 40) use the short-cycle solvers (persistent coarse kernels); larger ones (the
  * paper's (200, 40)) the long-cycle FP64 solvers, one launch per Arnoldi sub-step, also
  * under an FP32 preconditioner.  The lockstep and batch forms need m - k <= 24. */
 dmg_status dmg_deflation_create(dmg_hierarchy* h, int m, int k, dmg_deflation** out);
@@ -331,9 +332,10 @@ dmg_status dmg_solve(dmg_context* ctx, dmg_hierarchy* h, dmg_deflation* d, const
  *                        the call (the paper's multiple right-hand-side comparison); sizes as
  *                        above; coarse_dr_calls = 1 on the first right-hand side only
  * All stop at relative residual tol (max_iters: CG iterations or Arnoldi steps) and report
- * the true relative residual.  b, x: nrhs fields (host or device by ptr_kind).  Cycles longer
- * than 64 (or k > 31) run the long-cycle solvers: FP64 state in device memory, the
- * harmonic-Ritz restart in one workgroup. */
+ * the true relative residual.  b, x: nrhs fields (host or device by ptr_kind).  Sizes that
+ * the short-cycle state does not hold (as for the coarse deflation space above) run the
+ * long-cycle solvers: FP64 state in device memory, the harmonic-Ritz restart in one
+ * workgroup. */
 enum { DMG_FINE_CGNE = 0, DMG_FINE_GMRES_DR = 1, DMG_FINE_GMRES_PROJ = 2 };
 dmg_status dmg_solve_fine(dmg_context* ctx, dmg_hierarchy* h, int method, int m, int k, double tol, int max_iters,
                           const void* b, void* x, int nrhs, int ptr_kind, dmg_solve_stats* stats);

@@ -562,30 +562,393 @@ __device__ int schur_qr(double2* A, double2* X, int n) {
   return 0;
 }
 
-// ---------------------------------------------------------------- GMRES-DR deflated restart
-// Inputs in ks: H ((m+1) x m, unrotated), c, u = c - H d (the residual coordinates s).
-// Scratch: work (global) of at least (3 m m + 4 (m+1)(k+1) + 8 m + 64) double2.
-// Output: P ((m+1) x (k+1), ld m+1) in Pout; ks->H <- Hbar_k, ks->c <- P^H s, rotations
-// reset for the full block (unless final_mode), steps = k.
-__global__ void __launch_bounds__(DW) k_dr_restart(KState* ks, int m, int k, double2* Pout, int final_mode,
-                                                   double2* work, int* status) {
-  extern __shared__ double2 sh[];
+// ---------------------------------------------------------------- harmonic Ritz eigenproblem on several wavefronts
+// The eigenvalues of the restart's Hessenberg matrix, the choice of the k smallest and their
+// eigenvectors, for orders up to EIG_NMAX, in one workgroup of EIG_WAVES wavefronts (the
+// one-wavefront QR algorithm is a chain of dependent rotations; here the work of each step is
+// spread over lanes and the steps of different eigenvalues run side by side).
+constexpr int EIG_NMAX = 32;
+constexpr int EIG_WAVES = 5;
+constexpr int EIG_THREADS = 64 * EIG_WAVES;  // 32 roots x 2 chains x 4 lanes, then 10 inverse iterations
+constexpr int EIG_HALVES = 2 * EIG_WAVES;
+constexpr int EIG_MAXIT = 80;
+
+__device__ inline int lane_id() { return threadIdx.x & 63; }
+// DPP lane permutation of a double for controls under which every lane reads a valid lane
+template <int CTRL>
+__device__ inline double dpp_v(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffff), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+// sum over each quad of lanes; the four lanes get the same bits
+__device__ inline double2 quad_sum(double2 v) {
+  v = cadd(v, mk(dpp_v<0xB1>(v.x), dpp_v<0xB1>(v.y)));  // quad_perm [1, 0, 3, 2]
+  v = cadd(v, mk(dpp_v<0x4E>(v.x), dpp_v<0x4E>(v.y)));  // quad_perm [2, 3, 0, 1]
+  return v;
+}
+// value of lane 7 - i of each group of eight lanes (row_half_mirror)
+__device__ inline double2 half_mirror(double2 v) { return mk(dpp_v<0x141>(v.x), dpp_v<0x141>(v.y)); }
+// value of lane p of this lane's half (32 lanes) of the wavefront
+__device__ inline double2 rd_half(double2 v, int p) {
+  const double2 lo = rd_lane(v, p), hi = rd_lane(v, 32 + p);
+  return (lane_id() & 32) ? hi : lo;
+}
+// sum over this lane's half of the wavefront (all lanes active): rows of 16 by DPP, then the
+// half's two row sums from scalar registers
+__device__ inline double half_sum(double v) {
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  v += dpp_d<0x124>(v);
+  v += dpp_d<0x128>(v);
+  const double lo = rd_lane(v, 0) + rd_lane(v, 16), hi = rd_lane(v, 32) + rd_lane(v, 48);
+  return (lane_id() & 32) ? hi : lo;
+}
+// 1 / b with one division
+__device__ inline double2 crcp(double2 b) {
+  const double d = 1.0 / cabs2(b);
+  return mk(b.x * d, -b.y * d);
+}
+// packed upper triangle of an n x n matrix: row p holds columns p .. n-1
+__device__ inline int upk_off(int p, int n) { return p * n - p * (p - 1) / 2; }
+
+// Global scratch of the restart (double2 entries unless stated): the Hessenberg form A (m x m)
+// and its basis X (m x m), f = H^{-H} e_m (m), the eigenvalues (m), the selected eigenvectors
+// of A ((m+1) x k, rows < m used), the selected indices (k ints), the path flag (1 int: 0 when
+// the several-wavefront step produced them, 1 when the QR algorithm must) and the order whose
+// eigenvalues the several-wavefront step left in theta (1 int, 0 if none).
+struct DrWork {
+  double2* A;
+  double2* X;
+  double2* f;
+  double2* theta;
+  double2* Y;
+  int* sel;
+  int* flag;
+  int* prev;
+};
+__host__ __device__ inline DrWork dr_layout(double2* w, int m, int k) {
+  DrWork d;
+  d.A = w;
+  d.X = d.A + m * m;
+  d.f = d.X + m * m;
+  d.theta = d.f + m;
+  d.Y = d.theta + m;
+  d.sel = (int*)(d.Y + (m + 1) * k);
+  d.flag = d.sel + k;
+  d.prev = d.flag + 1;
+  return d;
+}
+
+// Eigenvalues by the Aberth-Ehrlich iteration on p(z) = det(A - z I), all roots at once:
+//   z_e <- z_e - N_e / (1 - N_e sum_{j != e} 1 / (z_e - z_j)),   N_e = p(z_e) / p'(z_e),
+// which converges cubically to simple roots.  p is evaluated by Hyman's method: x_{n-1} = 1 and
+// rows n-1, ..., 1 of (A - z I) x = 0 give x_{n-2}, ..., x_0 in turn through the subdiagonal;
+// the residual of row 0 is then p(z) times a factor independent of z (the product of the
+// subdiagonal entries), and the recurrence differentiated in z gives p'(z) with the same
+// factor.  Hyman's evaluation has a backward error of the order of the QR algorithm's, so the
+// roots are as accurate; subdiagonal entries below eps ||A||_F are raised to that size (a
+// perturbation of the same order).  Lanes 8e .. 8e+7 own root e: the first four carry x(z_e),
+// the last four x'(z_e), lane l of a chain holding the entries j = l, l + 4, ... in registers;
+// a row's sum is a quad sum, the two chains meet through the half-row mirror.  Starting points
+// lie on a circle about c = trace(A) / n of radius 0.7 ||A - c I||_F / sqrt(n) (the root mean
+// square distance of the eigenvalues from c is at most ||A - c I||_F / sqrt(n)).  A root is
+// settled once its correction is below 4 eps |z| or, having fallen below 1e-10 |z|, stops
+// shrinking (the rounding level of an ill-conditioned root).  Without convergence within
+// EIG_MAXIT steps or with a non-finite value (multiple or tightly clustered roots, where the
+// iteration converges only linearly) the kernel leaves the flag at 1 and the QR algorithm runs.
+// Then the k of smallest modulus are chosen (the restart's order) and their eigenvectors found
+// by two steps of inverse iteration, as in the reference eigenvector codes for Hessenberg
+// matrices: LU of A - lam I with partial pivoting between the two rows the Hessenberg structure
+// leaves in a column, a first solve U y = (1, ..., 1)^T (an implicit right-hand side), then
+// (A - lam I) y' = y / ||y||; pivots below eps ||A||_F are raised to that size, and a value
+// within that distance of an earlier chosen one is moved by it.  Each half wavefront takes one
+// eigenvalue (lane j holds column j in the factorisation, row j in the solves).
+__global__ void __launch_bounds__(EIG_THREADS) k_dr_eig(double2* work, int n, int k, int warm, const int* status) {
+  extern __shared__ double2 esh[];
+  double2* Ar = esh;  // EIG_NMAX x EIG_NMAX, row-major, zero beyond n
+  const int upk = n * (n + 1) / 2;
+  double2* U = Ar + EIG_NMAX * EIG_NMAX;  // EIG_HALVES packed upper triangles
+  double2* Lm = U + EIG_HALVES * upk;     // EIG_HALVES x 32 multipliers
+  double2* rU = Lm + EIG_HALVES * 32;     // EIG_HALVES x 32 reciprocal pivots
+  int* pv = (int*)(rU + EIG_HALVES * 32);  // EIG_HALVES x 32 row exchanges
+  __shared__ double2 zs[EIG_NMAX], rs[EIG_NMAX], lam[EIG_NMAX];
+  __shared__ double st0[EIG_NMAX + 1];
+  __shared__ double2 c0s;
+  __shared__ double nrm[2];
+  __shared__ double keys[64];
+  __shared__ int sel[EIG_NMAX];
+  if (*status != 0) return;
+  const DrWork d = dr_layout(work, n, k);
   const int t = threadIdx.x;
-  (void)work;
-  double2* A = sh;                           // m x m
-  double2* X = A + m * m;                    // m x m
-  double2* v = X + m * m;                    // m + 1
-  double2* Hb = v + (m + 1);                 // (m+1) x m copy of Hbar
-  double2* W = Hb + (m + 1) * m;             // (m+1) x (k+1)
-  double2* T1 = W + (m + 1) * (k + 1);       // (m+1) x k
-  double2* f = T1 + (m + 1) * k;             // m
-  double2* s = f + m;                        // m + 1
-  double2* theta = s + m + 1;                // m
-  int* sel = (int*)(theta + m);              // k ints
+  const double eps = 2.220446049250313e-16;
+  for (int e = t; e < EIG_NMAX * EIG_NMAX; e += EIG_THREADS) {
+    const int r = e / EIG_NMAX, j = e % EIG_NMAX;
+    Ar[e] = (r < n && j < n) ? d.A[r + n * j] : mk(0.0, 0.0);
+  }
+  __syncthreads();
+  if (t < 64) {
+    double fro2 = 0.0;
+    double2 tr = mk(0.0, 0.0);
+    for (int e = t; e < n * n; e += 64) fro2 += cabs2(Ar[(e / n) * EIG_NMAX + e % n]);
+    if (t < n) tr = Ar[t * (EIG_NMAX + 1)];
+    fro2 = wave_sum(fro2);
+    tr = wave_sum(tr);
+    const double2 c0 = cscale(tr, 1.0 / n);
+    double d2 = 0.0;
+    for (int e = t; e < n * n; e += 64) {
+      const int r = e / n, j = e % n;
+      const double2 a = Ar[r * EIG_NMAX + j];
+      d2 += cabs2(r == j ? csub(a, c0) : a);
+    }
+    d2 = wave_sum(d2);
+    if (t == 0) {
+      c0s = c0;
+      nrm[0] = fmax(sqrt(fro2), 1e-300);
+      nrm[1] = 0.7 * sqrt(d2 / n);
+    }
+  }
+  __syncthreads();
+  const double small = eps * nrm[0];
+  if (t < EIG_NMAX) {
+    double2 sb = Ar[t * EIG_NMAX + max(t - 1, 0)];
+    if (!(cabs_(sb) >= small)) sb = mk(small, 0.0);
+    rs[t] = (t >= 1 && t < n) ? crcp(sb) : mk(0.0, 0.0);
+    st0[t] = (t == n) ? 1.0 : 0.0;
+  }
+  if (t == EIG_NMAX) st0[t] = (n == EIG_NMAX) ? 1.0 : 0.0;
+  // start from the previous restart's eigenvalues when it solved a problem of this order here
+  // (the spectra of consecutive restarts are close: about half the steps), else from the circle
+  const bool from_prev = warm && *d.prev == n;
+  const int e = t >> 3, c = (t >> 2) & 1, l = t & 3, g8 = t & 7;
+  const bool act = e < n;
+  double2 zz = mk(0.0, 0.0);
+  if (act) {
+    if (from_prev) {
+      zz = d.theta[e];
+    } else {
+      double sn, cs;
+      sincos(6.283185307179586 * e / n + 0.4, &sn, &cs);
+      zz = mk(c0s.x + nrm[1] * cs, c0s.y + nrm[1] * sn);
+    }
+    if (g8 == 0) zs[e] = zz;
+  }
+  __syncthreads();
+  if (t == 0) *d.prev = 0;
+  bool done = !act;
+  double wprev = 1e300;
+  int ok = 0;
+  for (int it = 0; it < EIG_MAXIT; ++it) {
+    double2 w = mk(0.0, 0.0);
+    if (t < 4 * 64) {  // the fifth wavefront holds no root
+      // Hyman's recurrence over the rows of the zero-padded EIG_NMAX x EIG_NMAX matrix, unrolled so
+      // that every slot index is a constant.  Rows above n - 1 give zero (their reciprocal
+      // subdiagonal is zero) and the row at n adds the start value (x_{n-1} = 1, x'_{n-1} = 0).
+      // Slots below r / 4 hold only entries j < r - 1, still zero, and are left out of row r's
+      // sum; the slot that holds the newest entry y_r is added last, after the older ones.
+      const double cx = (c == 0) ? 1.0 : 0.0, cd = (c == 1) ? 1.0 : 0.0;
+      double2 y[8];
+#pragma unroll
+      for (int s = 0; s < 8; ++s) y[s] = mk(0.0, 0.0);
+      double2 ycur = mk(0.0, 0.0);
+#pragma unroll
+      for (int r = EIG_NMAX; r >= 1; --r) {
+        const int sr = r >> 2;
+        double2 a0 = mk(0.0, 0.0), a1 = mk(0.0, 0.0);
+#pragma unroll
+        for (int s = sr + 1; s < 8; ++s) {
+          if ((s & 1) == 0) cfma(a0, Ar[(r % EIG_NMAX) * EIG_NMAX + l + 4 * s], y[s]);
+          else cfma(a1, Ar[(r % EIG_NMAX) * EIG_NMAX + l + 4 * s], y[s]);
+        }
+        double2 acc = cadd(a0, a1);
+        if (sr < 8) cfma(acc, Ar[(r % EIG_NMAX) * EIG_NMAX + l + 4 * sr], y[sr]);
+        double2 full = csub(quad_sum(acc), cmul(zz, ycur));
+        const double2 py = half_mirror(ycur);  // x_r on the derivative chain
+        full.x -= cd * py.x;
+        full.y -= cd * py.y;
+        double2 yn = cmul(full, cscale(rs[r % EIG_NMAX], -1.0));
+        yn.x += cx * st0[r];
+        if (l == ((r - 1) & 3)) y[(r - 1) >> 2] = yn;
+        ycur = yn;
+      }
+      double2 a0 = mk(0.0, 0.0), a1 = mk(0.0, 0.0);
+#pragma unroll
+      for (int s = 0; s < 8; s += 2) {
+        cfma(a0, Ar[l + 4 * s], y[s]);
+        cfma(a1, Ar[l + 4 * s + 4], y[s + 1]);
+      }
+      double2 full = csub(quad_sum(cadd(a0, a1)), cmul(zz, ycur));
+      const double2 py = half_mirror(ycur);
+      full.x -= cd * py.x;
+      full.y -= cd * py.y;
+      const double2 other = half_mirror(full);  // p on the derivative chain, p' on the other
+      const double2 N = (c == 0) ? cdiv(full, other) : cdiv(other, full);
+      // sum over the other roots, two terms per lane, then over the eight lanes of the root
+      double2 Sv = mk(0.0, 0.0);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int j = g8 + 8 * u;
+        const double2 term = crcp(csub(zz, zs[min(j, n - 1)]));
+        if (j < n && j != e) Sv = cadd(Sv, term);
+      }
+      Sv = quad_sum(Sv);
+      Sv = cadd(Sv, half_mirror(Sv));
+      w = cdiv(N, csub(mk(1.0, 0.0), cmul(N, Sv)));
+      if (done) w = mk(0.0, 0.0);
+    }
+    if (__syncthreads_or(act && !(isfinite(w.x) && isfinite(w.y)))) break;
+    zz = csub(zz, w);
+    if (!done) {
+      const double aw = cabs_(w), az = cabs_(zz);
+      done = aw <= 4.0 * eps * az || (wprev <= 1e-10 * az && aw >= 0.5 * wprev);
+      wprev = aw;
+    }
+    if (act && g8 == 0) zs[e] = zz;
+    if (!__syncthreads_or(act && !done)) {
+      ok = 1;
+      break;
+    }
+  }
+  if (!ok) return;  // the flag stays 1
+  if (act && g8 == 0) d.theta[e] = zz;
+  // the k of smallest modulus: key (round(|theta| / max|theta|, 12), Im theta, index)
+  if (t < 64) {
+    const double2 th = t < n ? zs[t] : mk(0.0, 0.0);
+    const double ab = t < n ? cabs_(th) : 0.0;
+    double mx = ab;
+    mx = fmax(mx, dpp_d<0xB1>(mx));
+    mx = fmax(mx, dpp_d<0x4E>(mx));
+    mx = fmax(mx, dpp_d<0x124>(mx));
+    mx = fmax(mx, dpp_d<0x128>(mx));
+    mx = fmax(fmax(rd_lane(mx, 0), rd_lane(mx, 16)), fmax(rd_lane(mx, 32), rd_lane(mx, 48)));
+    if (mx == 0.0) mx = 1e-300;
+    keys[t] = rint(ab / mx * 1e12);
+  }
+  __syncthreads();
+  if (t < n) {
+    const double ke = keys[t];
+    int rank = 0;
+    for (int o = 0; o < n; ++o) {
+      if (o == t) continue;
+      const double ko = keys[o];
+      const bool less = (ko < ke) || (ko == ke && (zs[o].y < zs[t].y || (zs[o].y == zs[t].y && o < t)));
+      rank += less ? 1 : 0;
+    }
+    if (rank < k) sel[rank] = t;
+  }
+  __syncthreads();
+  if (t == 0) {
+    for (int q = 0; q < k; ++q) {
+      double2 lq = zs[sel[q]];
+      for (int again = 1, guard = 0; again && guard < 4 * k; ++guard) {
+        again = 0;
+        for (int p = 0; p < q; ++p)
+          if (cabs_(csub(lq, lam[p])) < small) {
+            lq = cadd(lq, mk(small, 0.0));
+            again = 1;
+          }
+      }
+      lam[q] = lq;
+      d.sel[q] = sel[q];
+    }
+  }
+  __syncthreads();
+  // inverse iteration, one eigenvalue per half wavefront
+  const int hw = t >> 5, j = t & 31;
+  const bool cj = j < n;
+  double2* Uh = U + hw * upk;
+  double2* Lh = Lm + hw * 32;
+  double2* rh = rU + hw * 32;
+  int* ph = pv + hw * 32;
+  for (int q0 = 0; q0 < k; q0 += EIG_HALVES) {
+    const int qq = q0 + hw, q = min(qq, k - 1);
+    const double2 lm = lam[q];
+    double2 cr = cj ? Ar[j] : mk(0.0, 0.0);
+    if (j == 0) cr = csub(cr, lm);
+    for (int p = 0; p + 1 < n; ++p) {
+      double2 nr = (cj && j >= p) ? Ar[(p + 1) * EIG_NMAX + j] : mk(0.0, 0.0);
+      if (j == p + 1) nr = csub(nr, lm);
+      const double2 a = rd_half(cr, p), b = Ar[(p + 1) * EIG_NMAX + p];
+      const bool sw = cabs2(b) > cabs2(a);
+      double2 piv = sw ? b : a;
+      const double2 oth = sw ? a : b;
+      if (!(cabs_(piv) >= small)) piv = mk(small, 0.0);
+      const double2 ip = crcp(piv), lf = cmul(oth, ip);
+      const double2 urow = (j == p) ? piv : (sw ? nr : cr), orow = sw ? cr : nr;
+      if (cj && j >= p) Uh[upk_off(p, n) + j - p] = urow;
+      if (j == 0) {
+        Lh[p] = lf;
+        rh[p] = ip;
+        ph[p] = sw ? 1 : 0;
+      }
+      cr = csub(orow, cmul(lf, urow));
+    }
+    {
+      double2 piv = rd_half(cr, n - 1);
+      if (!(cabs_(piv) >= small)) piv = mk(small, 0.0);
+      if (j == 0) rh[n - 1] = crcp(piv);
+    }
+    __syncthreads();
+    double2 v = mk(cj ? 1.0 : 0.0, 0.0), yv = mk(0.0, 0.0);
+    for (int step = 0; step < 2; ++step) {
+      if (step == 1) {
+        // the factorisation's row operations on the normalised first solution
+        v = yv;
+        for (int p = 0; p + 1 < n; ++p) {
+          const double2 a = rd_half(v, p), b = rd_half(v, p + 1);
+          const bool sw = ph[p] != 0;
+          const double2 top = sw ? b : a;
+          const double2 bot = csub(sw ? a : b, cmul(Lh[p], top));
+          if (j == p) v = top;
+          if (j == p + 1) v = bot;
+        }
+      }
+      for (int i = n - 1; i >= 0; --i) {
+        const double2 yi = cmul(rd_half(v, i), rh[i]);
+        if (j == i) yv = yi;
+        if (j < i) v = csub(v, cmul(Uh[upk_off(j, n) + i - j], yi));
+      }
+      const double nn = half_sum(cj ? cabs2(yv) : 0.0);
+      yv = cscale(yv, 1.0 / sqrt(nn));
+    }
+    if (cj && qq < k) d.Y[j + (n + 1) * qq] = yv;
+    __syncthreads();
+  }
+  if (t == 0) {
+    *d.flag = 0;
+    *d.prev = n;
+  }
+}
+
+static size_t dr_eig_lds_bytes(int n) {
+  return sizeof(double2) * ((size_t)EIG_NMAX * EIG_NMAX + (size_t)EIG_HALVES * (n * (n + 1) / 2) + 2 * EIG_HALVES * 32 +
+                            EIG_HALVES * 32 / 4);
+}
+
+// ---------------------------------------------------------------- GMRES-DR deflated restart
+// Inputs in ks: H ((m+1) x m, unrotated), c, u = c - H d (the residual coordinates s).  Three
+// launches on one stream: k_dr_pre forms the harmonic Ritz matrix H + |h|^2 f e_m^T and its
+// Hessenberg form; k_dr_eig (orders up to EIG_NMAX) its eigenvalues, the choice of k and their
+// eigenvectors; k_dr_post takes the QR algorithm where k_dr_eig did not run or did not settle,
+// then forms the new basis change.  Scratch: work (global) of dr_work_elems(m, k) double2.
+// Output: P ((m+1) x (k+1), ld m+1) in Pout; ks->H <- Hbar_k, ks->c <- P^H s, rotations reset
+// for the full block (unless final_mode), steps = k.  status[0] becomes nonzero on failure
+// (2: singular H, 3: no QR convergence, 4: dependent kept vectors); a launch that finds it
+// nonzero does nothing.
+__global__ void __launch_bounds__(DW) k_dr_pre(KState* ks, int m, int k, double2* work, int* status) {
+  extern __shared__ double2 sh[];
+  if (*status != 0) return;
+  const int t = threadIdx.x;
+  const DrWork d = dr_layout(work, m, k);
+  double2* A = sh;            // m x m
+  double2* X = A + m * m;     // m x m
+  double2* v = X + m * m;     // m + 1
+  double2* Hb = v + (m + 1);  // (m+1) x m copy of Hbar
+  double2* f = Hb + (m + 1) * m;  // m
   __shared__ int fail;
   if (t == 0) fail = 0;
   for (int e = t; e < (m + 1) * m; e += DW) Hb[e] = ks->H[(e % (m + 1)) + LD * (e / (m + 1))];
-  for (int i = t; i <= m; i += DW) s[i] = ks->u[i];
   __syncthreads();
   const double h = Hb[m + (m + 1) * (m - 1)].x;  // h_{m+1,m}, real >= 0
 
@@ -653,57 +1016,104 @@ __global__ void __launch_bounds__(DW) k_dr_restart(KState* ks, int m, int k, dou
   }
   __syncthreads();
   hessenberg(A, X, v, m);
-  if (schur_qr(A, X, m)) { if (t == 0) *status = 3; return; }
   __syncthreads();
-  // eigenvalues and the order: key (round(|theta| / max|theta|, 12), Im theta, index); lane e
-  // forms its modulus and key once (m <= 64), the maximum is a wavefront max
-  __shared__ double keys[DW];
-  {
-    const double2 th = t < m ? A[t + m * t] : mk(0.0, 0.0);
-    if (t < m) theta[t] = th;
-    const double ab = t < m ? cabs_(th) : 0.0;
-    double mx = ab;
-    mx = fmax(mx, dpp_d<0xB1>(mx));
-    mx = fmax(mx, dpp_d<0x4E>(mx));
-    mx = fmax(mx, dpp_d<0x124>(mx));
-    mx = fmax(mx, dpp_d<0x128>(mx));
-    mx = fmax(fmax(rd_lane(mx, 0), rd_lane(mx, 16)), fmax(rd_lane(mx, 32), rd_lane(mx, 48)));
-    if (mx == 0.0) mx = 1e-300;
-    keys[t] = rint(ab / mx * 1e12);
+  for (int e = t; e < m * m; e += DW) {
+    d.A[e] = A[e];
+    d.X[e] = X[e];
+  }
+  for (int i = t; i < m; i += DW) d.f[i] = f[i];
+  if (t == 0) *d.flag = 1;
+}
+
+static size_t dr_pre_lds_bytes(int m) {
+  return sizeof(double2) * ((size_t)2 * m * m + (m + 1) + (size_t)(m + 1) * m + m);
+}
+
+__global__ void __launch_bounds__(DW) k_dr_post(KState* ks, int m, int k, double2* Pout, int final_mode,
+                                                double2* work, int* status) {
+  extern __shared__ double2 sh[];
+  if (*status != 0) return;
+  const int t = threadIdx.x;
+  const DrWork d = dr_layout(work, m, k);
+  double2* A = sh;                           // m x m
+  double2* X = A + m * m;                    // m x m
+  double2* v = X + m * m;                    // m + 1
+  double2* Hb = v + (m + 1);                 // (m+1) x m copy of Hbar
+  double2* W = Hb + (m + 1) * m;             // (m+1) x (k+1)
+  double2* T1 = W + (m + 1) * (k + 1);       // (m+1) x k
+  double2* f = T1 + (m + 1) * k;             // m
+  double2* s = f + m;                        // m + 1
+  double2* theta = s + m + 1;                // m
+  int* sel = (int*)(theta + m);              // k ints
+  (void)v;
+  const bool fast = *d.flag == 0;
+  for (int e = t; e < (m + 1) * m; e += DW) Hb[e] = ks->H[(e % (m + 1)) + LD * (e / (m + 1))];
+  for (int i = t; i <= m; i += DW) s[i] = ks->u[i];
+  for (int e = t; e < m * m; e += DW) {
+    X[e] = d.X[e];
+    if (!fast) A[e] = d.A[e];
+  }
+  for (int i = t; i < m; i += DW) f[i] = d.f[i];
+  if (fast) {
+    for (int i = t; i < m; i += DW) theta[i] = d.theta[i];
+    for (int q = t; q < k; q += DW) sel[q] = d.sel[q];
+    for (int e = t; e < (m + 1) * k; e += DW) T1[e] = (e % (m + 1) < m) ? d.Y[e] : mk(0.0, 0.0);
   }
   __syncthreads();
-  for (int e = t; e < m; e += DW) {
-    const double ke = keys[e];
-    int rank = 0;
-    for (int o = 0; o < m; ++o) {
-      if (o == e) continue;
-      const double ko = keys[o];
-      const bool less = (ko < ke) || (ko == ke && (theta[o].y < theta[e].y || (theta[o].y == theta[e].y && o < e)));
-      rank += less ? 1 : 0;
+  const double h = Hb[m + (m + 1) * (m - 1)].x;  // h_{m+1,m}, real >= 0
+  if (!fast) {
+    if (schur_qr(A, X, m)) { if (t == 0) *status = 3; return; }
+    if (t < m) theta[t] = A[t + m * t];
+    __syncthreads();
+    // the order: key (round(|theta| / max|theta|, 12), Im theta, index); lane e forms its modulus
+    // and key once (m <= 64), the maximum is a wavefront max
+    __shared__ double keys[DW];
+    {
+      const double2 th = t < m ? theta[t] : mk(0.0, 0.0);
+      const double ab = t < m ? cabs_(th) : 0.0;
+      double mx = ab;
+      mx = fmax(mx, dpp_d<0xB1>(mx));
+      mx = fmax(mx, dpp_d<0x4E>(mx));
+      mx = fmax(mx, dpp_d<0x124>(mx));
+      mx = fmax(mx, dpp_d<0x128>(mx));
+      mx = fmax(fmax(rd_lane(mx, 0), rd_lane(mx, 16)), fmax(rd_lane(mx, 32), rd_lane(mx, 48)));
+      if (mx == 0.0) mx = 1e-300;
+      keys[t] = rint(ab / mx * 1e12);
     }
-    if (rank < k) sel[rank] = e;
-  }
-  __syncthreads();
-  // eigenvectors of the triangular T = A for the selected values, into T1 columns (length m)
-  double tn = 0.0;
-  {
-    double part = 0.0;
-    for (int e = t; e < m * m; e += DW) part += cabs2(A[e]);
-    tn = wave_sum(part);
-  }
-  const double smin = fmax(sqrt(tn) * 2.220446049250313e-16, 1e-300);
-  for (int q = t; q < k; q += DW) {
-    const int e = sel[q];
-    double2* y = T1 + (m + 1) * q;
-    for (int i = 0; i < m; ++i) y[i] = mk(0.0, 0.0);
-    y[e] = mk(1.0, 0.0);
-    const double2 lam = A[e + m * e];
-    for (int i = e - 1; i >= 0; --i) {
-      double2 acc = mk(0.0, 0.0);
-      for (int l = i + 1; l <= e; ++l) cfma(acc, A[i + m * l], y[l]);
-      double2 den = csub(A[i + m * i], lam);
-      if (cabs_(den) < smin) den = mk(smin, 0.0);
-      y[i] = cscale(cdiv(acc, den), -1.0);
+    __syncthreads();
+    for (int e = t; e < m; e += DW) {
+      const double ke = keys[e];
+      int rank = 0;
+      for (int o = 0; o < m; ++o) {
+        if (o == e) continue;
+        const double ko = keys[o];
+        const bool less = (ko < ke) || (ko == ke && (theta[o].y < theta[e].y || (theta[o].y == theta[e].y && o < e)));
+        rank += less ? 1 : 0;
+      }
+      if (rank < k) sel[rank] = e;
+    }
+    __syncthreads();
+    // eigenvectors of the triangular T = A for the selected values, into T1 columns (length m)
+    double tn = 0.0;
+    {
+      double part = 0.0;
+      for (int e = t; e < m * m; e += DW) part += cabs2(A[e]);
+      tn = wave_sum(part);
+    }
+    const double smin = fmax(sqrt(tn) * 2.220446049250313e-16, 1e-300);
+    for (int q = t; q < k; q += DW) {
+      const int e = sel[q];
+      double2* y = T1 + (m + 1) * q;
+      for (int i = 0; i < m; ++i) y[i] = mk(0.0, 0.0);
+      y[e] = mk(1.0, 0.0);
+      const double2 lam = A[e + m * e];
+      for (int i = e - 1; i >= 0; --i) {
+        double2 acc = mk(0.0, 0.0);
+        for (int l = i + 1; l <= e; ++l) cfma(acc, A[i + m * l], y[l]);
+        double2 den = csub(A[i + m * i], lam);
+        if (cabs_(den) < smin) den = mk(smin, 0.0);
+        y[i] = cscale(cdiv(acc, den), -1.0);
+      }
     }
   }
   __syncthreads();
@@ -775,26 +1185,47 @@ __global__ void __launch_bounds__(DW) k_dr_restart(KState* ks, int m, int k, dou
     ks->steps = k;
     ks->done = 0;
     ks->breakdown = 0;
-    *status = 0;
   }
 }
 
-size_t dr_work_elems(int m, int k) {
-  return (size_t)(m + 1) * m + 2 * (size_t)(m + 1) * (k + 1) + (size_t)(m + 1) * k + 4 * (size_t)m + 64;
-}
 
-static size_t dr_lds_bytes(int m, int k) {
+size_t dr_work_elems(int m, int k) { return (size_t)2 * m * m + 2 * (size_t)m + (size_t)(m + 1) * k + (k + 3) / 2 + 2; }
+
+static size_t dr_post_lds_bytes(int m, int k) {
   return sizeof(double2) * ((size_t)2 * m * m + (m + 1) + (size_t)(m + 1) * m + (size_t)(m + 1) * (k + 1) +
                             (size_t)(m + 1) * k + m + (m + 1) + m + (k + 1) / 2 + 2);
 }
 
+static size_t dr_post_static_lds() {
+  static size_t bytes = 0;
+  if (!bytes) {
+    hipFuncAttributes fa;
+    if (hipFuncGetAttributes(&fa, (const void*)k_dr_post) != hipSuccess) return (size_t)1 << 30;
+    bytes = fa.sharedSizeBytes + 1;
+  }
+  return bytes;
+}
+
+bool dr_restart_fits(int m, int k) {
+  return k >= 1 && m + 1 <= DW && (size_t)m * m >= (size_t)(k + 1) * k &&
+         dr_post_lds_bytes(m, k) + dr_post_static_lds() <= 160 * 1024;
+}
+
 void launch_dr_restart(hipStream_t st, KState* ks, int m, int k, double2* Pout, int final_mode, double2* work,
-                       int* status) {
-  const size_t shm = dr_lds_bytes(m, k);
-  DMG_CHECK(shm <= 150 * 1024 && (size_t)m * m >= (size_t)(k + 1) * k && m + 1 <= DW, DMG_E_INVALID,
-            "GMRES-DR sizes too large");
-  DMG_HIP(hipFuncSetAttribute((const void*)k_dr_restart, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-  hipLaunchKernelGGL(k_dr_restart, dim3(1), dim3(DW), shm, st, ks, m, k, Pout, final_mode, work, status);
+                       int* status, int warm) {
+  const size_t shp = dr_pre_lds_bytes(m), sho = dr_post_lds_bytes(m, k);
+  DMG_CHECK(dr_restart_fits(m, k), DMG_E_INVALID, "GMRES-DR sizes too large for the one-workgroup restart");
+  DMG_HIP(hipFuncSetAttribute((const void*)k_dr_pre, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shp));
+  DMG_HIP(hipFuncSetAttribute((const void*)k_dr_post, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sho));
+  hipLaunchKernelGGL(k_dr_pre, dim3(1), dim3(DW), shp, st, ks, m, k, work, status);
+  DMG_LAUNCH_CHECK();
+  if (m <= EIG_NMAX) {
+    const size_t she = dr_eig_lds_bytes(m);
+    DMG_HIP(hipFuncSetAttribute((const void*)k_dr_eig, hipFuncAttributeMaxDynamicSharedMemorySize, (int)she));
+    hipLaunchKernelGGL(k_dr_eig, dim3(1), dim3(EIG_THREADS), she, st, work, m, k, warm, (const int*)status);
+    DMG_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(k_dr_post, dim3(1), dim3(DW), sho, st, ks, m, k, Pout, final_mode, work, status);
   DMG_LAUNCH_CHECK();
 }
 

@@ -93,10 +93,14 @@ void launch_ls_solve(hipStream_t s, KState* ks);
 // GMRES-DR deflated restart (harmonic Ritz, k smallest, new Hbar_k, c, rotations) on the
 // small matrices.  Writes the (m+1) x (k+1) basis change to Pout (ld m+1).
 // final_mode = 1: last compression (harmonic residual direction instead of s).
-// work: device scratch of dr_work_elems(m, k) entries; status[0] = 0 on success.
+// work: device scratch of dr_work_elems(m, k) entries; status[0] stays 0 on success.  warm = 1
+// lets the eigenvalue iteration start from the previous restart's eigenvalues held in work
+// (restarts after the first of one solve, same m and k).
 size_t dr_work_elems(int m, int k);
+// whether the one-workgroup restart holds (m, k) in LDS (else the long-cycle solvers run)
+bool dr_restart_fits(int m, int k);
 void launch_dr_restart(hipStream_t s, KState* ks, int m, int k, double2* Pout, int final_mode, double2* work,
-                       int* status);
+                       int* status, int warm);
 // After a restart: rotations for the full (k+1) x k block and the rotated rhs.
 void launch_qr_block(hipStream_t s, KState* ks, int k);
 // GMRES-Proj projection: given c = V_{k+1}^H r in ks->c, d = argmin ||c - Hbar_k d|| using the

@@ -196,7 +196,8 @@ int big_gmres_dr(dmg_context* ctx, Work* w, const Op& A, int m, int k, const dou
 // the final residual estimate relative to ||b|| in rel_est.
 int big_gmres_proj(Work* w, const Op& A, const dmg_deflation* d, const double2* b, double2* x, double tol,
                    int max_iters, double* rel_est);
-// deflation spaces beyond the short-cycle state (m > 64 or k > 31) use the long-cycle solvers
-inline bool big_deflation(int m, int k) { return m > MMAX || k > 31; }
+// deflation spaces beyond the short-cycle state (m > 64, k > 31, or a restart too large for one
+// workgroup's LDS) use the long-cycle solvers
+inline bool big_deflation(int m, int k) { return m > MMAX || k > 31 || !dr_restart_fits(m, k); }
 
 }  // namespace dmg

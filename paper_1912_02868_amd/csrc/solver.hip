@@ -129,7 +129,7 @@ int coarse_gmres_dr(dmg_hierarchy* h, Work* w, dmg_deflation* d, const double2* 
   DMG_HIP(hipMemsetAsync(err_d, 0, sizeof(int), s));
   DMG_HIP(hipMemsetAsync(x, 0, sizeof(double2) * n, s));
   launch_cycle_start<double>(s, b, V, n, ks, tol, 1, PART(w), CNT(w));
-  int j0 = 0, iters = 0;
+  int j0 = 0, iters = 0, restarts = 0;
   KStatus st{};
   double prev_est = -1.0;
   for (;;) {
@@ -159,7 +159,7 @@ int coarse_gmres_dr(dmg_hierarchy* h, Work* w, dmg_deflation* d, const double2* 
     if (prev_est > 0.0 && st.est > 0.99 * prev_est && st.est <= 1e-10 * st.bnorm) break;
     prev_est = st.est;
     // deflated restart: keep the k smallest harmonic Ritz vectors and the residual
-    launch_dr_restart(s, ks, m, k, w->dr_P.as<double2>(), 0, w->dr_work.as<double2>(), status);
+    launch_dr_restart(s, ks, m, k, w->dr_P.as<double2>(), 0, w->dr_work.as<double2>(), status, restarts++ > 0);
     launch_basis_rotate<double>(s, V, w->dr_Vtmp.as<double2>(), n, n, w->dr_P.as<double2>(), m + 1, m + 1, k + 1);
     DMG_HIP(hipMemcpyAsync(V, w->dr_Vtmp.p, sizeof(double2) * n * (k + 1), hipMemcpyDeviceToDevice, s));
     // re-orthogonalise v_{k+1} against v_1 .. v_k
@@ -174,7 +174,7 @@ int coarse_gmres_dr(dmg_hierarchy* h, Work* w, dmg_deflation* d, const double2* 
   // store the deflation space A V_k = V_{k+1} Hbar_k
   const int cols = st.steps;
   if (cols > k && !st.breakdown) {
-    launch_dr_restart(s, ks, cols, k, w->dr_P.as<double2>(), 1, w->dr_work.as<double2>(), status);
+    launch_dr_restart(s, ks, cols, k, w->dr_P.as<double2>(), 1, w->dr_work.as<double2>(), status, 0);
     d->V64.alloc(h->ctx, sizeof(double2) * (size_t)n * (k + 1));
     d->H.alloc(h->ctx, sizeof(double2) * (size_t)(k + 1) * k);
     launch_basis_rotate<double>(s, V, d->V64.as<double2>(), n, n, w->dr_P.as<double2>(), cols + 1, cols + 1, k + 1);
