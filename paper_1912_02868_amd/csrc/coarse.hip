@@ -102,7 +102,13 @@ __device__ inline void cp_wait_stores() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 // Every wavefront waits for its own exchange stores before the workgroup barrier: a
 // wavefront's wait covers only its own outstanding stores, so the flag store of
 // wavefront 0 alone would not order the other wavefronts' stores before it.
-__device__ inline bool cp_barrier(unsigned* flags, int G, unsigned gen, int* err) {
+struct CpNoHook {
+  __device__ void operator()() const {}
+};
+// `during` runs on the workgroup's last wavefront after the flag store, while wavefront 0 waits
+// for the other workgroups' flags (work that does not feed this reduction).
+template <typename Hook = CpNoHook>
+__device__ inline bool cp_barrier(unsigned* flags, int G, unsigned gen, int* err, Hook during = Hook()) {
   __shared__ int aborted;
   cp_wait_stores();
   __syncthreads();
@@ -132,6 +138,7 @@ __device__ inline bool cp_barrier(unsigned* flags, int G, unsigned gen, int* err
       aborted = 1;
     }
   }
+  if (threadIdx.x >= blockDim.x - 64) during();
   __syncthreads();
   return aborted != 0;
 }
@@ -406,6 +413,9 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
   int* hsite = (int*)(smem + L.hs);
   __shared__ double sh_scal[8];
   __shared__ int sh_flag[4];
+  __shared__ double2 pg_hnext[64], pg_h0;  // a deferred Givens update's column (lane l: h_{l+1})
+  __shared__ double pg_hn;
+  __shared__ int pg_j;
 
   const T* Ag = (const T*)a.A;
   const T* DVg = (const T*)a.DV;
@@ -458,9 +468,9 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
   };
   // the barrier's own wait and workgroup barrier order every wavefront's published sums (and
   // exchange stores) before the flag store
-  auto grid_reduce = [&](int nq, int halo_half = -1) {
+  auto grid_reduce_h = [&](int nq, int halo_half, auto during) {
     double2* P = a.partials + (size_t)rbuf * CP_QMAX * G;
-    dead = dead || cp_barrier(a.flags, G, ++gen, a.err);
+    dead = dead || cp_barrier(a.flags, G, ++gen, a.err, during);
     const int q = tid >> 5, c = tid & 31;
     if (NHW < CP_QMAX && q + NHW < nq) {
       // two quantities per half-wavefront, all loads in flight together
@@ -478,6 +488,7 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
     __syncthreads();
     rbuf ^= 1;
   };
+  auto grid_reduce = [&](int nq, int halo_half = -1) { grid_reduce_h(nq, halo_half, CpNoHook()); };
   auto sq = [&](const T* v) { return [=](int, int e) { return mk(cabs2(to_d(v[e])), 0.0); }; };
 
   // ---------------------------------------------------------------- load the resident data
@@ -567,6 +578,13 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
     bool brk = false, stop = false;
     // cancellation below which the Pythagorean norm is replaced by a second pass
     const double eta = sizeof(R) == sizeof(float) ? 1e-4 : 1e-8;
+    // A column's Givens update needs only h and hn, so in the one-pass case the rotation wavefront
+    // keeps them in registers and applies the rotation during the next grid barrier, while
+    // wavefront 0 waits for the other workgroups; the residual test of column j then comes
+    // after the next column's stencil and sums, and if it stops the solve, that column is
+    // dropped (its v_{j+1} = Vb[j + 1] closes the cycle).  pend is uniform.
+    // The rotation's inputs wait in LDS (pg_*), not in registers that every thread would hold.
+    bool pend = false, vlast_in_vb = false;
     for (int j = 0; j < mm; ++j) {
       // xchg holds hprev * v_j (written before the last barrier); halo form: wl holds it
       // on the own and halo sites
@@ -649,11 +667,9 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
       // Givens update of column j (h_0 .. h_j from src, then hn) on the last wavefront: lane l
       // loads entry l and rotation l, then the chain runs in every lane on values read from one
       // lane at a time (scalar registers, no LDS round trip per rotation); lane 0 stores
-      auto givens = [&](const double2* src, double hn) {
+      auto givens_r = [&](int j, double2 h0, double2 hnext, double hn) {
         // rotations 0 .. j-1 on the column (h_0 .. h_j, hn) by a lane scan, then the new one
         double2* col = Hr + (mm + 1) * j;
-        const double2 h0 = src[0];
-        const double2 hnext = lane + 1 <= j ? src[lane + 1] : mk(hn, 0.0);  // h_{lane+1}
         const double cl = lane < j ? rot_c : 1.0;
         const double2 sl = lane < j ? rot_s : mk(0.0, 0.0);
         double2 x0;
@@ -680,12 +696,30 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
           sh_scal[0] = cabs2(gn);  // squared residual estimate
         }
       };
+      auto givens = [&](const double2* src, double hn) {
+        givens_r(j, src[0], lane + 1 <= j ? src[lane + 1] : mk(hn, 0.0), hn);  // lane l: h_{l+1}
+      };
+      auto run_pending = [&]() {
+        if (wave == (TPB / 64) - 1) givens_r(pg_j, pg_h0, pg_hnext[lane], pg_hn);
+      };
       arn_dots();
-      grid_reduce(j + 2, (j + 1) & 1);
+      const bool had_pend = pend;
+      grid_reduce_h(j + 2, (j + 1) & 1, [&]() {
+        if (had_pend) run_pending();
+      });
+      pend = false;
+      if (had_pend && !dead && sh_scal[0] <= tol_abs * tol_abs) {
+        // column j - 1 met the tolerance: drop column j
+        est = sh_scal[0];
+        steps = j;
+        vlast_in_vb = true;
+        stop = true;
+        break;
+      }
       const double ww = res[j + 1].x;
       if (wave == (TPB / 64) - 1) {
-        // ||h||^2, the cancellation test and (without a second pass) the rotations, while the
-        // other wavefronts apply the first pass
+        // ||h||^2, the cancellation test and (without a second pass) the rotation's inputs,
+        // while the other wavefronts apply the first pass
         const double rsum = cp_row_sum(lane <= j ? cabs2(res[lane]) : 0.0);
         const double hh = (cp_lane(rsum, 0) + cp_lane(rsum, 16)) + (cp_lane(rsum, 32) + cp_lane(rsum, 48));
         const double hn2 = ww - hh;
@@ -696,8 +730,11 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
           double hn1 = sqrt(fmax(hn2, 0.0));
           const bool b = !(hn2 > 1e-24 * ww);  // hn1 <= 1e-12 ||w|| without a second root
           if (b) hn1 = 0.0;
-          givens(res, hn1);
+          pg_hnext[lane] = lane + 1 <= j ? res[lane + 1] : mk(hn1, 0.0);  // lane l: h_{l+1}
           if (lane == 0) {
+            pg_j = j;
+            pg_h0 = res[0];
+            pg_hn = hn1;
             sh_scal[1] = hn1;
             sh_flag[2] = b ? 1 : 0;
           }
@@ -724,12 +761,28 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
       } else {
         hn = sh_scal[1];
         brk = sh_flag[2] != 0;
+        pend = true;
       }
-      if (!HALO && j + 1 < mm) dead = dead || cp_barrier(a.flags, G, ++gen, a.err);
-      est = brk ? 0.0 : sh_scal[0];  // squared until the cycle ends
+      if (!HALO && j + 1 < mm) {
+        // the two-barrier form's second barrier carries the rotation
+        const bool p2 = pend;
+        dead = dead || cp_barrier(a.flags, G, ++gen, a.err, [&]() {
+          if (p2) run_pending();
+        });
+        pend = false;
+      }
       steps = j + 1;
       hprev = hn;
-      if (dead || brk || est <= tol_abs * tol_abs || iters + steps >= a.max_iters) { stop = true; break; }
+      const bool halt = dead || brk || iters + steps >= a.max_iters;
+      if (pend && (halt || j + 1 == mm)) {
+        run_pending();
+        __syncthreads();
+        pend = false;
+      }
+      if (!pend) {
+        est = brk ? 0.0 : sh_scal[0];  // squared until the cycle ends
+        if (halt || est <= tol_abs * tol_abs) { stop = true; break; }
+      }
     }
     est = sqrt(est);  // every step above left the squared estimate
     // ------------------------------------------------------------ end of cycle: x += V y, r = V u
@@ -751,7 +804,9 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
       }
     }
     __syncthreads();
-    const double invn = hprev > 0.0 ? 1.0 / hprev : 0.0;
+    // v_steps: hprev * v_steps is in wl, or v_steps itself in Vb when a column was dropped
+    const double invn = vlast_in_vb ? 1.0 : (hprev > 0.0 ? 1.0 / hprev : 0.0);
+    const T* vlast = vlast_in_vb ? Vb + steps * vst : wl;
     for (int t = tid; t < ne; t += TPB) {
       double2 xv = to_d(xl[t]);
       double2 rv = mk(0.0, 0.0);
@@ -760,7 +815,7 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
         cfma(xv, yv[i], vi);
         cfma(rv, uv[i], vi);
       }
-      cfma(rv, uv[steps], cscale(to_d(wl[t]), invn));
+      cfma(rv, uv[steps], cscale(to_d(vlast[t]), invn));
       xl[t] = from_d<R>(xv);
       rl[t] = from_d<R>(rv);
     }
