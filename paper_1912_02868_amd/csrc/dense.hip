@@ -1206,6 +1206,13 @@ static size_t dr_post_static_lds() {
   return bytes;
 }
 
+// DMG_RESTART_QR=1 sends every restart to the QR algorithm (read at each launch, so that one
+// process can compare the two eigenvalue paths).
+static bool dr_force_qr() {
+  const char* e = getenv("DMG_RESTART_QR");
+  return e && *e && *e != '0';
+}
+
 bool dr_restart_fits(int m, int k) {
   return k >= 1 && m + 1 <= DW && (size_t)m * m >= (size_t)(k + 1) * k &&
          dr_post_lds_bytes(m, k) + dr_post_static_lds() <= 160 * 1024;
@@ -1219,7 +1226,7 @@ void launch_dr_restart(hipStream_t st, KState* ks, int m, int k, double2* Pout, 
   DMG_HIP(hipFuncSetAttribute((const void*)k_dr_post, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sho));
   hipLaunchKernelGGL(k_dr_pre, dim3(1), dim3(DW), shp, st, ks, m, k, work, status);
   DMG_LAUNCH_CHECK();
-  if (m <= EIG_NMAX) {
+  if (m <= EIG_NMAX && !dr_force_qr()) {
     const size_t she = dr_eig_lds_bytes(m);
     DMG_HIP(hipFuncSetAttribute((const void*)k_dr_eig, hipFuncAttributeMaxDynamicSharedMemorySize, (int)she));
     hipLaunchKernelGGL(k_dr_eig, dim3(1), dim3(EIG_THREADS), she, st, work, m, k, warm, (const int*)status);

@@ -260,6 +260,53 @@ def test_gmres_dr_deflation_space(dmg, injected):
         assert np.min(np.abs(ritz - t)) < 1e-3 * abs(t) + 1e-6
 
 
+def test_gmres_dr_space_both_eigen_paths_and_oracle(dmg, injected, monkeypatch):
+    """GMRES-DR(30, 10) to 1e-8 on the oracle's 64^2 coarse matrix, with the restart's eigenvalues
+    from the simultaneous iteration (the default for m <= 32) and from the QR algorithm
+    (DMG_RESTART_QR=1): both kept spaces satisfy A V_k = V_{k+1} Hbar_k, and their Ritz values
+    equal each other's and those of the oracle's gmres_dr space on the same matrix and right-hand
+    side (every restart ranks the same harmonic Ritz values, so the spaces agree to rounding)."""
+    N, th, m0, H, g, hg = injected
+    if N != 64:
+        pytest.skip("needs a coarse space larger than m")
+    from oracle import krylov
+    Dc = H.levels[2].A.toarray()
+    nc = Dc.shape[0]
+    b = synth.gaussian_complex(nc, 64, 0, 4, 0)
+
+    def ritz(V, k):
+        return np.linalg.eigvals(np.linalg.lstsq(V[:, :k], Dc @ V[:, :k], rcond=None)[0])
+
+    def dist(a, b_):
+        return max(np.min(np.abs(a - t)) / abs(t) for t in b_)
+
+    got = {}
+    for mode in ("simultaneous", "qr"):
+        if mode == "qr":
+            monkeypatch.setenv("DMG_RESTART_QR", "1")
+        else:
+            monkeypatch.delenv("DMG_RESTART_QR", raising=False)
+        print(f"[case] GMRES-DR(30, 10) 64^2 coarse, restart eigenvalues by {mode}", flush=True)
+        d = dmg.Deflation(hg, 30, 10)
+        d.build(b, 1e-8)
+        assert d.ready
+        V, Hk = d.export(nc)
+        d.close()
+        k = Hk.shape[1]
+        assert k == 10
+        assert np.linalg.norm(V.conj().T @ V - np.eye(k + 1)) < 1e-11
+        assert np.linalg.norm(Dc @ V[:, :k] - V @ Hk) / np.linalg.norm(Hk) < 1e-10
+        got[mode] = ritz(V, k)
+    monkeypatch.delenv("DMG_RESTART_QR", raising=False)
+    _, info, defl = krylov.gmres_dr(lambda v: Dc @ v, b, 30, 10, 1e-8)
+    ro = ritz(defl.V, 10)
+    d_paths = dist(got["simultaneous"], got["qr"])
+    d_or = max(dist(got["simultaneous"], ro), dist(got["qr"], ro))
+    print(f"    Ritz values: paths within {d_paths:.1e}, oracle within {d_or:.1e}", flush=True)
+    # measured: 1.1e-14 and 5e-14
+    assert d_paths < 1e-10 and d_or < 1e-9
+
+
 # ---------------------------------------------------------------- whole solves
 def _solve_and_check(dmg, ctx, hg, D, b, defl=None, **kw):
     x = np.zeros_like(b)
