@@ -1142,17 +1142,15 @@ int launch_coarse_arnoldi(hipStream_t st, const double2* A, int Lx, int Lt, doub
   const size_t lds = coarse_arnoldi_lds(spw, m);
   if (lds > 160 * 1024) return 0;
   const void* fn = (const void*)k_coarse_arnoldi;
-  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
+  if (ensure_dyn_lds(fn, lds) != hipSuccess) {
     (void)hipGetLastError();
     return 0;
   }
-  int per_cu = 0, dev = 0, ncu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, CP_THREADS, lds) != hipSuccess) {
+  int per_cu = 0, ncu = 0;
+  if (occupancy_cached(fn, CP_THREADS, lds, &per_cu, &ncu) != hipSuccess) {
     (void)hipGetLastError();
     return 0;
   }
-  (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (per_cu < 1 || G > per_cu * ncu) return 0;
   if (hipMemsetAsync(flags, 0, sizeof(unsigned) * CP_FLAGPAD * G, st) != hipSuccess) {
     (void)hipGetLastError();
@@ -1196,22 +1194,19 @@ static int try_launch(hipStream_t st, CPArgs& a, int G, size_t lds, bool alds, b
   void* args[] = {&a};
   const void* fn = proj_fn<R>(alds, halo, reg);
   const int threads = reg ? 512 : CP_THREADS;
-  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = ensure_dyn_lds(fn, lds);
   if (e != hipSuccess) {
     if (cp_debug()) fprintf(stderr, "[dmg] coarse kernel: set LDS %zu failed: %s\n", lds, hipGetErrorString(e));
     (void)hipGetLastError();
     return 0;
   }
-  int per_cu = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds);
+  int per_cu = 0, ncu = 0;
+  e = occupancy_cached(fn, threads, lds, &per_cu, &ncu);
   if (e != hipSuccess) {
     if (cp_debug()) fprintf(stderr, "[dmg] coarse kernel: occupancy query failed: %s\n", hipGetErrorString(e));
     (void)hipGetLastError();
     return 0;
   }
-  int dev = 0, ncu = 0;
-  (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (per_cu < 1 || G > per_cu * ncu) {
     if (cp_debug())
       fprintf(stderr, "[dmg] coarse kernel: %d workgroups of %d threads, LDS %zu: %d per CU x %d CUs\n", G,

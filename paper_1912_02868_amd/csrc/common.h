@@ -105,6 +105,66 @@ constexpr int BLK = 4;      // blocking factor per direction
 constexpr int MMAX = 64;    // largest Krylov cycle held by the small-dense state
 constexpr int ROTMAX = MMAX * (MMAX + 1) / 2 + 2 * MMAX;
 
+// ---------------------------------------------------------------- launch attributes
+// Raise fn's dynamic-LDS limit on the current device to at least `bytes`; the attribute call is
+// made only when a launch needs more than this process last set for that function.
+inline hipError_t ensure_dyn_lds(const void* fn, size_t bytes) {
+  struct Set {
+    int dev;
+    const void* fn;
+    size_t bytes;
+  };
+  static std::mutex mu;
+  static std::vector<Set> done;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lock(mu);
+  Set* hit = nullptr;
+  for (auto& e : done)
+    if (e.dev == dev && e.fn == fn) hit = &e;
+  if (hit && hit->bytes >= bytes) return hipSuccess;
+  const hipError_t r = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (r == hipSuccess) {
+    if (hit) hit->bytes = bytes;
+    else done.push_back({dev, fn, bytes});
+  }
+  return r;
+}
+// Workgroups of fn (threads, lds) that one compute unit holds, and the compute units of the
+// current device, remembered per (device, fn, threads, lds).
+inline hipError_t occupancy_cached(const void* fn, int threads, size_t lds, int* per_cu, int* ncu) {
+  struct Fit {
+    int dev;
+    const void* fn;
+    int threads;
+    size_t lds;
+    int per_cu, ncu;
+  };
+  static std::mutex mu;
+  static std::vector<Fit> known;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    for (const auto& e : known)
+      if (e.dev == dev && e.fn == fn && e.threads == threads && e.lds == lds) {
+        *per_cu = e.per_cu;
+        *ncu = e.ncu;
+        return hipSuccess;
+      }
+  }
+  int pc = 0, nc = 0;
+  hipError_t r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, fn, threads, lds);
+  if (r != hipSuccess) return r;
+  r = hipDeviceGetAttribute(&nc, hipDeviceAttributeMultiprocessorCount, dev);
+  if (r != hipSuccess) return r;
+  std::lock_guard<std::mutex> lock(mu);
+  known.push_back({dev, fn, threads, lds, pc, nc});
+  *per_cu = pc;
+  *ncu = nc;
+  return hipSuccess;
+}
+
 // Small-dense state of one Krylov cycle, resident in device memory (FP64).
 // Column-major (m + 1) x m Hessenberg: H[i + (MMAX + 1) * j].
 struct KState {

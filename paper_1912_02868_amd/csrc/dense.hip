@@ -1222,13 +1222,13 @@ void launch_dr_restart(hipStream_t st, KState* ks, int m, int k, double2* Pout, 
                        int* status, int warm) {
   const size_t shp = dr_pre_lds_bytes(m), sho = dr_post_lds_bytes(m, k);
   DMG_CHECK(dr_restart_fits(m, k), DMG_E_INVALID, "GMRES-DR sizes too large for the one-workgroup restart");
-  DMG_HIP(hipFuncSetAttribute((const void*)k_dr_pre, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shp));
-  DMG_HIP(hipFuncSetAttribute((const void*)k_dr_post, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sho));
+  DMG_HIP(ensure_dyn_lds((const void*)k_dr_pre, shp));
+  DMG_HIP(ensure_dyn_lds((const void*)k_dr_post, sho));
   hipLaunchKernelGGL(k_dr_pre, dim3(1), dim3(DW), shp, st, ks, m, k, work, status);
   DMG_LAUNCH_CHECK();
   if (m <= EIG_NMAX && !dr_force_qr()) {
     const size_t she = dr_eig_lds_bytes(m);
-    DMG_HIP(hipFuncSetAttribute((const void*)k_dr_eig, hipFuncAttributeMaxDynamicSharedMemorySize, (int)she));
+    DMG_HIP(ensure_dyn_lds((const void*)k_dr_eig, she));
     hipLaunchKernelGGL(k_dr_eig, dim3(1), dim3(EIG_THREADS), she, st, work, m, k, warm, (const int*)status);
     DMG_LAUNCH_CHECK();
   }

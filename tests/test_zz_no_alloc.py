@@ -6,6 +6,8 @@ the FP64 oracle's operators (1e-13 FP64, 2e-6 FP32).  The library's device memor
 accounting and torch's allocator statistics do not move during the calls, and a
 request larger than the static scratch fails with DMG_E_INVALID.
 """
+import gc
+
 import numpy as np
 import pytest
 
@@ -46,11 +48,18 @@ def _check(dmg, ctx, H, hg, level, op, nrhs, dtype):
     x = torch.from_numpy(_fields(n_in, nrhs, 10 * level + op, dtype)).cuda()
     y_static = torch.full((nrhs, n_out), complex(np.nan, np.nan), dtype=x.dtype, device="cuda")
     y_alloc = torch.empty_like(y_static)
-    torch.cuda.synchronize()
-    used, torch_bytes = ctx.bytes_in_use, torch.cuda.memory_allocated()
-    hg.apply_batched_static(level, op, x, y_static, nrhs)
-    torch.cuda.synchronize()
-    assert ctx.bytes_in_use == used and torch.cuda.memory_allocated() == torch_bytes
+    # objects of earlier tests that wait for the cycle collector release their device memory
+    # through torch's allocator whenever it runs: collect them first and keep it off meanwhile
+    gc.collect()
+    gc.disable()
+    try:
+        torch.cuda.synchronize()
+        used, torch_bytes = ctx.bytes_in_use, torch.cuda.memory_allocated()
+        hg.apply_batched_static(level, op, x, y_static, nrhs)
+        torch.cuda.synchronize()
+        assert ctx.bytes_in_use == used and torch.cuda.memory_allocated() == torch_bytes
+    finally:
+        gc.enable()
     hg.apply_batched(level, op, x, y_alloc, nrhs)
     torch.cuda.synchronize()
     ys, ya, xh = y_static.cpu().numpy(), y_alloc.cpu().numpy(), x.cpu().numpy().astype(complex)
