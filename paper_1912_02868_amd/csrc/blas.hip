@@ -602,24 +602,29 @@ void launch_multi_axpy(hipStream_t s, cx<R>* w, const cx<R>* V, int64_t ld, int 
   DMG_LAUNCH_CHECK();
 }
 
+// Vout[:, jc] = sum_i P[i, jc] Vin[:, i]: one thread per (entry, output column), the sum in i order.
 template <typename R>
 __global__ void __launch_bounds__(RB) k_basis_rotate(const cx<R>* __restrict__ Vin, cx<R>* __restrict__ Vout,
                                                      int64_t ld, int64_t n, const double2* __restrict__ P, int ldp,
                                                      int rows, int cols) {
+  const int jc = blockIdx.y;
+  const double2* pc = P + (int64_t)ldp * jc;
   const int64_t stride = (int64_t)gridDim.x * RB;
   for (int64_t e = (int64_t)blockIdx.x * RB + threadIdx.x; e < n; e += stride) {
-    for (int jc = 0; jc < cols; ++jc) {
-      double2 acc = mk(0.0, 0.0);
-      for (int i = 0; i < rows; ++i) cfma(acc, P[i + (int64_t)ldp * jc], to_d(Vin[(int64_t)i * ld + e]));
-      Vout[(int64_t)jc * ld + e] = from_d<R>(acc);
-    }
+    double2 acc = mk(0.0, 0.0);
+    for (int i = 0; i < rows; ++i) cfma(acc, pc[i], to_d(Vin[(int64_t)i * ld + e]));
+    Vout[(int64_t)jc * ld + e] = from_d<R>(acc);
   }
 }
 
 template <typename R>
 void launch_basis_rotate(hipStream_t s, const cx<R>* Vin, cx<R>* Vout, int64_t ld, int64_t n, const double2* P,
                          int ldp, int rows, int cols) {
-  hipLaunchKernelGGL(k_basis_rotate<R>, dim3(red_blocks(n)), dim3(RB), 0, s, Vin, Vout, ld, n, P, ldp, rows, cols);
+  int64_t gx = (n + RB - 1) / RB;
+  if (gx > 1024) gx = 1024;
+  if (gx < 1) gx = 1;
+  hipLaunchKernelGGL(k_basis_rotate<R>, dim3((unsigned)gx, (unsigned)cols), dim3(RB), 0, s, Vin, Vout, ld, n, P, ldp,
+                     rows, cols);
   DMG_LAUNCH_CHECK();
 }
 

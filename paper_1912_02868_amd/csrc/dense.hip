@@ -384,8 +384,12 @@ __device__ void hessenberg(double2* A, double2* X, double2* v, int n) {
     const double xnorm = sqrt(xn2 + anorm * anorm);
     const double2 ph = anorm > 0.0 ? cscale(alpha, 1.0 / anorm) : mk(1.0, 0.0);
     const double2 beta = cscale(ph, -xnorm);
-    // v = x - beta e1 (indices col+1 .. n-1 stored at v[0 .. n-col-2])
-    const int len = n - col - 1;
+    // v = x - beta e1 (indices col+1 .. n-1 stored at v[0 .. n-col-2]); the reflector ends at the
+    // column's last nonzero row (after a deflated restart the matrix is banded: a dense leading
+    // block whose bulge each reflector moves one row down), and the zeros beyond it would add
+    // exact zeros to every product below
+    const unsigned long long nzr = __ballot(t > col && t < n && (xi.x != 0.0 || xi.y != 0.0));
+    const int len = (63 - __clzll(nzr)) - col;
     const double2 vi = (t == col + 1) ? csub(alpha, beta) : xi;
     if (t > col && t < n) v[t - col - 1] = vi;
     const double f = 2.0 / wave_sum(cabs2(vi));
