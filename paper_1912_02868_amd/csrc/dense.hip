@@ -88,11 +88,11 @@ __device__ inline void make_givens_fast(double2 a, double2 b, double& c, double2
 }
 
 // ---------------------------------------------------------------- least squares
-// y = R^{-1} g over the completed steps (R and g staged in LDS by all threads, the
-// back-substitution by one), then u = c - H y with one thread per row.
+// y = R^{-1} g over the completed steps by columns on one wavefront (lane i holds the running
+// g_i; column l gives y_l from lane l, then every lane above drops its term), R staged in LDS;
+// then u = c - H y with one thread per row.
 __global__ void __launch_bounds__(DW) k_ls_solve(KState* ks) {
   __shared__ double2 Rs[MMAX * MMAX];
-  __shared__ double2 gs[MMAX + 1];
   __shared__ double2 ys[MMAX + 1];
   const int t = threadIdx.x;
   const int n = ks->steps;
@@ -100,22 +100,22 @@ __global__ void __launch_bounds__(DW) k_ls_solve(KState* ks) {
     const int i = e % n, l = e / n;
     Rs[e] = (i <= l) ? ks->R[i + LD * l] : mk(0.0, 0.0);
   }
-  for (int i = t; i < n; i += DW) gs[i] = ks->g[i];
+  double2 acc = t < n ? ks->g[t] : mk(0.0, 0.0);
   __syncthreads();
-  if (t == 0) {
-    for (int i = n - 1; i >= 0; --i) {
-      double2 acc = gs[i];
-      for (int l = i + 1; l < n; ++l) acc = csub(acc, cmul(Rs[i + n * l], ys[l]));
-      const double2 d = Rs[i + n * i];
-      ys[i] = cabs2(d) > 0.0 ? cdiv(acc, d) : mk(0.0, 0.0);
-    }
+  for (int l = n - 1; l >= 0; --l) {
+    const double2 r = t < l ? Rs[t + n * l] : mk(0.0, 0.0);
+    const double2 d = Rs[l + n * l];
+    const double2 al = rd_lane(acc, l);
+    const double2 yl = cabs2(d) > 0.0 ? cdiv(al, d) : mk(0.0, 0.0);
+    if (t == l) ys[l] = yl;
+    if (t < l) acc = csub(acc, cmul(r, yl));
   }
   __syncthreads();
   for (int i = t; i < n; i += DW) ks->y[i] = ys[i];
   for (int i = t; i <= n; i += DW) {
-    double2 acc = ks->c[i];
-    for (int l = 0; l < n; ++l) acc = csub(acc, cmul(ks->H[i + LD * l], ys[l]));
-    ks->u[i] = acc;
+    double2 a2 = ks->c[i];
+    for (int l = 0; l < n; ++l) a2 = csub(a2, cmul(ks->H[i + LD * l], ys[l]));
+    ks->u[i] = a2;
   }
 }
 

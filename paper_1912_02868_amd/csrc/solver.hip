@@ -145,11 +145,17 @@ int coarse_gmres_dr(dmg_hierarchy* h, Work* w, dmg_deflation* d, const double2* 
       }
     launch_ls_solve(s, ks);
     launch_combine<double, double>(s, x, V, n, n, ks, 0, 1);
-    sync_status(w, ks, &st);
     if (pers) {
-      int err = 0;
-      DMG_HIP(hipMemcpy(&err, err_d, sizeof(int), hipMemcpyDeviceToHost));
-      DMG_CHECK(err == 0, DMG_E_HIP, "persistent GMRES-DR cycle: grid barrier timed out");
+      // the cycle's status and the grid barrier's error word in one round trip
+      static_assert(sizeof(KStatus) <= 128, "the error word follows the status in the 256-byte pinned buffer");
+      int* herr = (int*)((char*)w->host_status + 128);
+      DMG_HIP(hipMemcpyAsync(w->host_status, &ks->nrot, sizeof(KStatus), hipMemcpyDeviceToHost, s));
+      DMG_HIP(hipMemcpyAsync(herr, err_d, sizeof(int), hipMemcpyDeviceToHost, s));
+      DMG_HIP(hipStreamSynchronize(s));
+      st = *w->host_status;
+      DMG_CHECK(*herr == 0, DMG_E_HIP, "persistent GMRES-DR cycle: grid barrier timed out");
+    } else {
+      sync_status(w, ks, &st);
     }
     iters += st.steps - j0;
     w->cnt.mv[2] += st.steps - j0;
