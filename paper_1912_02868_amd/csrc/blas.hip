@@ -283,6 +283,103 @@ __global__ void __launch_bounds__(RB) k_arn_normalize(cx<R>* __restrict__ V, int
   }
 }
 
+// One-pass classical Gram-Schmidt with the Pythagorean norm, for Krylov solves that only
+// precondition (the partial intermediate solve): (a1) h = V^H w and ||w||^2 in one reduction;
+// the last workgroup forms hn^2 = ||w||^2 - ||h||^2 and, unless that cancels to eta ||w||^2 or
+// less, stores h_{j+1,j} = hn and does the column's Givens update and convergence test as
+// k_arn_update_norm does; (b1) w = (w - V h) / hn.  Where it cancels, ks->pass2 = 1, (b1) leaves
+// w - V h unscaled and the caller runs the exact second pass (k_arn_dots2, k_arn_update_norm,
+// k_arn_normalize).  In exact arithmetic the same column as the two-pass form.
+template <typename R>
+__global__ void __launch_bounds__(RB) k_arn_dots_all(const cx<R>* __restrict__ V, int64_t ld, int64_t n, int j,
+                                                     KState* ks, double2* partials, unsigned* counter, double eta) {
+  if (ks->done) return;
+  __shared__ double2 lds[RW][MMAX + 2];
+  __shared__ double2 res[MMAX + 2];
+  const cx<R>* w = V + (int64_t)(j + 1) * ld;
+  block_dots<R>(V, ld, j + 1, w, n, true, lds);
+  publish(lds, j + 2, partials);
+  if (!last_block(counter)) return;
+  last_sums(partials, j + 2, lds, res);
+  constexpr int LD = MMAX + 1;
+  for (int q = threadIdx.x; q <= MMAX; q += RB) {
+    if (q <= j) ks->H[LD * j + q] = res[q];
+    else if (q > j + 1) ks->H[LD * j + q] = mk(0.0, 0.0);
+  }
+  __shared__ int one_pass;
+  if (threadIdx.x == 0) {
+    const double ww = res[j + 1].x;
+    double hh = 0.0;
+    for (int q = 0; q <= j; ++q) hh += cabs2(res[q]);
+    const double hn2 = ww - hh;
+    ks->wn0 = sqrt(ww);
+    one_pass = hn2 > eta * ww ? 1 : 0;
+    ks->pass2 = one_pass ? 0 : 1;
+    if (one_pass) ks->H[LD * j + j + 1] = mk(sqrt(hn2), 0.0);
+  }
+  __syncthreads();
+  if (!one_pass) return;
+  givens_update(ks, j);
+  if (threadIdx.x == 0 && ks->est <= ks->tol_abs) ks->done = 1;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(RB) k_arn_update1(cx<R>* __restrict__ V, int64_t ld, int64_t n, int j,
+                                                    const KState* ks) {
+  if (ks->done && ks->breakdown) return;
+  __shared__ double2 coef[MMAX + 2];
+  constexpr int LD = MMAX + 1;
+  for (int i = threadIdx.x; i <= j; i += RB) coef[i] = ks->H[LD * j + i];
+  __syncthreads();
+  const double inv = ks->pass2 ? 1.0 : 1.0 / ks->H[LD * j + j + 1].x;
+  cx<R>* w = V + (int64_t)(j + 1) * ld;
+  const int64_t stride = (int64_t)gridDim.x * RB;
+  for (int64_t e = (int64_t)blockIdx.x * RB + threadIdx.x; e < n; e += stride) {
+    double2 acc = to_d(w[e]);
+    for (int i = 0; i <= j; ++i) acc = csub(acc, cmul(coef[i], to_d(V[(int64_t)i * ld + e])));
+    w[e] = from_d<R>(cscale(acc, inv));
+  }
+}
+
+// second pass after k_arn_update1 left w - V h: h2 = V^H w, H[i, j] += h2_i
+template <typename R>
+__global__ void __launch_bounds__(RB) k_arn_dots2(const cx<R>* __restrict__ V, int64_t ld, int64_t n, int j,
+                                                  KState* ks, double2* partials, unsigned* counter) {
+  if (ks->done) return;
+  __shared__ double2 lds[RW][MMAX + 2];
+  __shared__ double2 coef[MMAX + 2];
+  constexpr int LD = MMAX + 1;
+  const cx<R>* w = V + (int64_t)(j + 1) * ld;
+  block_dots<R>(V, ld, j + 1, w, n, false, lds);
+  publish(lds, j + 1, partials);
+  if (!last_block(counter)) return;
+  last_sums(partials, j + 1, lds, coef);
+  for (int q = threadIdx.x; q <= j; q += RB) {
+    ks->h2[q] = coef[q];
+    ks->H[LD * j + q] = cadd(ks->H[LD * j + q], coef[q]);
+  }
+}
+
+template <typename R>
+void launch_arnoldi_orth1(hipStream_t s, cx<R>* V, int64_t ld, int64_t n, int j, KState* ks, double2* partials,
+                          unsigned* counter) {
+  const int G = red_blocks(n);
+  const double eta = sizeof(R) == sizeof(float) ? 1e-4 : 1e-8;
+  hipLaunchKernelGGL(k_arn_dots_all<R>, dim3(G), dim3(RB), 0, s, V, ld, n, j, ks, partials, counter, eta);
+  hipLaunchKernelGGL(k_arn_update1<R>, dim3(G), dim3(RB), 0, s, V, ld, n, j, (const KState*)ks);
+  DMG_LAUNCH_CHECK();
+}
+
+template <typename R>
+void launch_arnoldi_pass2(hipStream_t s, cx<R>* V, int64_t ld, int64_t n, int j, KState* ks, double2* partials,
+                          unsigned* counter) {
+  const int G = red_blocks(n);
+  hipLaunchKernelGGL(k_arn_dots2<R>, dim3(G), dim3(RB), 0, s, V, ld, n, j, ks, partials, counter);
+  hipLaunchKernelGGL(k_arn_update_norm<R>, dim3(G), dim3(RB), 0, s, V, ld, n, j, ks, partials, counter);
+  hipLaunchKernelGGL(k_arn_normalize<R>, dim3(G), dim3(RB), 0, s, V, ld, n, j, ks);
+  DMG_LAUNCH_CHECK();
+}
+
 template <typename R>
 void launch_arnoldi_orth(hipStream_t s, cx<R>* V, int64_t ld, int64_t n, int j, KState* ks, double2* partials,
                          unsigned* counter) {
@@ -630,6 +727,8 @@ void launch_basis_rotate(hipStream_t s, const cx<R>* Vin, cx<R>* Vout, int64_t l
 
 #define INST(R)                                                                                                     \
   template void launch_arnoldi_orth<R>(hipStream_t, cx<R>*, int64_t, int64_t, int, KState*, double2*, unsigned*); \
+  template void launch_arnoldi_orth1<R>(hipStream_t, cx<R>*, int64_t, int64_t, int, KState*, double2*, unsigned*); \
+  template void launch_arnoldi_pass2<R>(hipStream_t, cx<R>*, int64_t, int64_t, int, KState*, double2*, unsigned*); \
   template void launch_combine<R, R>(hipStream_t, cx<R>*, const cx<R>*, int64_t, int64_t, const KState*, int, int); \
   template void launch_axpby<R>(hipStream_t, int64_t, double, const cx<R>*, double, cx<R>*);                       \
   template void launch_xmy<R>(hipStream_t, int64_t, const cx<R>*, cx<R>*);                                         \

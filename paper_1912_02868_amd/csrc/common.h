@@ -187,6 +187,7 @@ struct KState {
   double beta;                    // norm of the starting residual
   double wn0;                     // ||A v_j|| before orthogonalisation
   double bnorm;                   // ||b|| of the enclosing solve
+  int pass2;                      // one-pass Gram-Schmidt cancelled: the exact second pass is due
   double scratch[8];
 };
 

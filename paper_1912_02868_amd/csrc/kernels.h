@@ -36,6 +36,15 @@ int red_blocks(int64_t n);
 template <typename R>
 void launch_arnoldi_orth(hipStream_t s, cx<R>* V, int64_t ld, int64_t n, int j, KState* ks, double2* partials,
                          unsigned* counter);
+// One-pass variant for solves that only precondition: h = V^H w and ||w||^2 in one reduction,
+// the norm from their difference, w = (w - V h) / hn; when that difference cancels, ks->pass2
+// is set and launch_arnoldi_pass2 must follow (exact second pass, norm, Givens, scaling).
+template <typename R>
+void launch_arnoldi_orth1(hipStream_t s, cx<R>* V, int64_t ld, int64_t n, int j, KState* ks, double2* partials,
+                          unsigned* counter);
+template <typename R>
+void launch_arnoldi_pass2(hipStream_t s, cx<R>* V, int64_t ld, int64_t n, int j, KState* ks, double2* partials,
+                          unsigned* counter);
 
 // x (+)= sum_i coef[i] * V_i, coef = ks->y (use_u = 0) or ks->u (use_u = 1), count = ks->steps (+1 if use_u)
 template <typename R, typename RX>

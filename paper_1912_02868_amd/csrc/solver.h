@@ -64,6 +64,7 @@ struct Transfer {  // P from level l (Lx x Lt sites, dof per site) to level l + 
 struct KStatus {
   int nrot, steps, done, breakdown;
   double tol_abs, est, beta, wn0, bnorm;
+  int pass2;
 };
 
 // Krylov workspace: basis V (m + 1 fields), optional Z (m fields), small-dense state.

@@ -645,8 +645,12 @@ struct Precond {
         cycle1(V + j * n, Z + j * n);
         A.apply(S(), Z + j * n, V + (j + 1) * n, 0, nullptr);
         w->cnt.mv[1]++;
-        launch_arnoldi_orth<R>(S(), V, n, n, j, ks, PART(w), CNT(w));
+        launch_arnoldi_orth1<R>(S(), V, n, n, j, ks, PART(w), CNT(w));
         sync_status(w, ks, &st);
+        if (st.pass2) {
+          launch_arnoldi_pass2<R>(S(), V, n, n, j, ks, PART(w), CNT(w));
+          sync_status(w, ks, &st);
+        }
         if (st.done) break;
       }
       launch_ls_solve(S(), ks);
