@@ -364,7 +364,9 @@ template <typename R>
 void launch_arnoldi_orth1(hipStream_t s, cx<R>* V, int64_t ld, int64_t n, int j, KState* ks, double2* partials,
                           unsigned* counter) {
   const int G = red_blocks(n);
-  const double eta = sizeof(R) == sizeof(float) ? 1e-4 : 1e-8;
+  // DMG_ARNOLDI_TWO_PASS=1 takes the second pass at every step (read at each call)
+  const char* e = getenv("DMG_ARNOLDI_TWO_PASS");
+  const double eta = (e && *e && *e != '0') ? 2.0 : (sizeof(R) == sizeof(float) ? 1e-4 : 1e-8);
   hipLaunchKernelGGL(k_arn_dots_all<R>, dim3(G), dim3(RB), 0, s, V, ld, n, j, ks, partials, counter, eta);
   hipLaunchKernelGGL(k_arn_update1<R>, dim3(G), dim3(RB), 0, s, V, ld, n, j, (const KState*)ks);
   DMG_LAUNCH_CHECK();

@@ -461,6 +461,38 @@ def test_solve_bf16_coarse_preconditioner_64(dmg, ctx, injected):
     assert e.value.code == dmg.DMG_E_INVALID
 
 
+def test_partial_solve_second_pass_path(dmg, ctx, injected, monkeypatch):
+    """The partial intermediate solve's one-pass Gram-Schmidt and its exact second pass (forced at
+    every step by DMG_ARNOLDI_TWO_PASS=1): both reach 1e-8 with the solution of sparse LU, with the
+    same outer and intermediate step counts (equal columns in exact arithmetic)."""
+    N, th, m0, H, g, hg = injected
+    if N != 64:
+        pytest.skip("workload-sized solve")
+    import scipy.sparse.linalg as spla
+    D = H.levels[0].A
+    lu = spla.splu(D.tocsc())
+    b = synth.rhs(64, 0, 3)
+    xl = lu.solve(b)
+    out = {}
+    for mode in ("one pass", "second pass forced"):
+        if mode == "one pass":
+            monkeypatch.delenv("DMG_ARNOLDI_TWO_PASS", raising=False)
+        else:
+            monkeypatch.setenv("DMG_ARNOLDI_TWO_PASS", "1")
+        print(f"[case] 64^2 solve, partial solve Gram-Schmidt: {mode}", flush=True)
+        d = dmg.Deflation(hg, 30, 10)
+        st, s, x, res = _solve_and_check(dmg, ctx, hg, D, b, d)
+        d.close()
+        assert st == dmg.DMG_OK and s["converged"] == 1 and res <= 1e-8
+        assert _rel(x, xl) < 1e-6
+        out[mode] = (s["outer_iters"], s["int_mvps"], x)
+    monkeypatch.delenv("DMG_ARNOLDI_TWO_PASS", raising=False)
+    a, bb = out["one pass"], out["second pass forced"]
+    print(f"    outer {a[0]} / {bb[0]}, intermediate Mvps {a[1]} / {bb[1]}, difference {_rel(a[2], bb[2]):.1e}",
+          flush=True)
+    assert a[0] == bb[0] and a[1] == bb[1] and _rel(a[2], bb[2]) < 1e-8
+
+
 def test_solve_zero_rhs_and_cap(dmg, ctx, injected):
     N, th, m0, H, g, hg = injected
     if N != 16:
