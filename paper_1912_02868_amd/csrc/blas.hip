@@ -44,19 +44,30 @@ __device__ inline double2 wg_result(double2 (*lds)[MMAX + 2], int q) {
 }
 
 // Ticket: true in exactly one (the last) workgroup, after all partials are visible.
+// The partial sums travel with device-scope atomic stores and loads, which go to the device's
+// coherence point rather than a compute die's own L2: each wavefront waits for its own stores
+// to complete before the workgroup barrier and the ticket, and the last workgroup loads the
+// partials after its ticket returned.  No fence is needed, so no L2 write-back or invalidation
+// (which a device-scope fence costs on every workgroup, and which would also evict the vectors
+// the next kernels read).
+__device__ inline void st_dev(double2* p, double2 v) {
+  __hip_atomic_store(&p->x, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&p->y, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline double2 ld_dev(const double2* p) {
+  return mk(__hip_atomic_load(&p->x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+            __hip_atomic_load(&p->y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
 __device__ inline bool last_block(unsigned* counter) {
   __shared__ int am_last;
-  __threadfence();
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wavefront's partial stores have completed
   __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned t = atomicAdd(counter, 1u);
+    const unsigned t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     am_last = (t == gridDim.x * gridDim.y - 1) ? 1 : 0;
   }
   __syncthreads();
-  if (am_last) {
-    __threadfence();
-    if (threadIdx.x == 0) *counter = 0u;
-  }
+  if (am_last && threadIdx.x == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return am_last != 0;
 }
 
@@ -94,7 +105,7 @@ __device__ void block_dots(const cx<R>* __restrict__ V, int64_t ld, int nv, cons
 // Publish the workgroup sums of quantities q < nq as partials[q][blockIdx].
 __device__ inline void publish(double2 (*lds)[MMAX + 2], int nq, double2* partials) {
   __syncthreads();
-  for (int q = threadIdx.x; q < nq; q += RB) partials[(int64_t)q * gridDim.x + blockIdx.x] = wg_result(lds, q);
+  for (int q = threadIdx.x; q < nq; q += RB) st_dev(&partials[(int64_t)q * gridDim.x + blockIdx.x], wg_result(lds, q));
 }
 
 // In the last workgroup: res[q] = sum over workgroups of partials[q][b], in a fixed order,
@@ -105,7 +116,7 @@ __device__ void last_sums(const double2* partials, int nq, double2 (*lds)[MMAX +
   for (int q0 = 0; q0 < nq; q0 += QB) {
     double2 v[QB];
 #pragma unroll
-    for (int u = 0; u < QB; ++u) v[u] = (q0 + u < nq && t < nblk) ? partials[(int64_t)(q0 + u) * nblk + t] : mk(0.0, 0.0);
+    for (int u = 0; u < QB; ++u) v[u] = (q0 + u < nq && t < nblk) ? ld_dev(&partials[(int64_t)(q0 + u) * nblk + t]) : mk(0.0, 0.0);
 #pragma unroll
     for (int u = 0; u < QB; ++u)
       if (q0 + u < nq) wg_accumulate(lds, q0 + u, v[u]);
