@@ -37,18 +37,32 @@ __global__ void __launch_bounds__(SB) k_batched_dots(int64_t n, const double2* _
   if (threadIdx.x == 0) {
     double2 r = red[0];
     for (int w = 1; w < SB / 64; ++w) r = cadd(r, red[w]);
-    partials[(int64_t)f * gridDim.x + blockIdx.x] = r;
+    // device-scope atomic stores reach the coherence point: after the wait below no fence (and
+    // so no L2 write-back) is needed before the ticket, nor an invalidation after it
+    double2* pp = &partials[(int64_t)f * gridDim.x + blockIdx.x];
+    __hip_atomic_store(&pp->x, r.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&pp->y, r.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    const unsigned t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    am_last = (t == gridDim.x * gridDim.y - 1) ? 1 : 0;
   }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) am_last = (atomicAdd(counter, 1u) == gridDim.x * gridDim.y - 1) ? 1 : 0;
   __syncthreads();
   if (!am_last) return;
-  __threadfence();
-  if (threadIdx.x == 0) *counter = 0u;
+  if (threadIdx.x == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   for (int q = threadIdx.x; q < (int)gridDim.y; q += SB) {
+    const double2* pq = partials + (int64_t)q * gridDim.x;
     double2 r = mk(0.0, 0.0);
-    for (int bb = 0; bb < (int)gridDim.x; ++bb) r = cadd(r, partials[(int64_t)q * gridDim.x + bb]);
+    for (int b0 = 0; b0 < (int)gridDim.x; b0 += 8) {
+      double2 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        v[u] = b0 + u < (int)gridDim.x ? mk(__hip_atomic_load(&pq[b0 + u].x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                                            __hip_atomic_load(&pq[b0 + u].y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                                       : mk(0.0, 0.0);
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (b0 + u < (int)gridDim.x) r = cadd(r, v[u]);
+    }
     out[2 * q] = r.x;
     out[2 * q + 1] = r.y;
   }
