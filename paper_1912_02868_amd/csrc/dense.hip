@@ -669,7 +669,8 @@ __host__ __device__ inline DrWork dr_layout(double2* w, int m, int k) {
 // (A - lam I) y' = y / ||y||; pivots below eps ||A||_F are raised to that size, and a value
 // within that distance of an earlier chosen one is moved by it.  Each half wavefront takes one
 // eigenvalue (lane j holds column j in the factorisation, row j in the solves).
-__global__ void __launch_bounds__(EIG_THREADS) k_dr_eig(double2* work, int n, int k, int warm, const int* status) {
+__global__ void __launch_bounds__(EIG_THREADS) k_dr_eig(double2* work, int n, int k, int warm, int maxit,
+                                                         const int* status) {
   extern __shared__ double2 esh[];
   double2* Ar = esh;  // EIG_NMAX x EIG_NMAX, row-major, zero beyond n
   const int upk = n * (n + 1) / 2;
@@ -743,7 +744,7 @@ __global__ void __launch_bounds__(EIG_THREADS) k_dr_eig(double2* work, int n, in
   bool done = !act;
   double wprev = 1e300;
   int ok = 0;
-  for (int it = 0; it < EIG_MAXIT; ++it) {
+  for (int it = 0; it < maxit; ++it) {
     double2 w = mk(0.0, 0.0);
     if (t < 4 * 64) {  // the fifth wavefront holds no root
       // Hyman's recurrence over the rows of the zero-padded EIG_NMAX x EIG_NMAX matrix, unrolled so
@@ -1210,11 +1211,12 @@ static size_t dr_post_static_lds() {
   return bytes;
 }
 
-// DMG_RESTART_QR=1 sends every restart to the QR algorithm (read at each launch, so that one
-// process can compare the two eigenvalue paths).
-static bool dr_force_qr() {
+// DMG_RESTART_QR=1 sends every restart to the QR algorithm; DMG_RESTART_QR=2 runs the
+// simultaneous iteration with no steps, so that it gives up and the QR algorithm takes over
+// (read at each launch, so that one process can compare the eigenvalue paths).
+static int dr_force_qr() {
   const char* e = getenv("DMG_RESTART_QR");
-  return e && *e && *e != '0';
+  return (e && *e) ? atoi(e) : 0;
 }
 
 bool dr_restart_fits(int m, int k) {
@@ -1230,10 +1232,12 @@ void launch_dr_restart(hipStream_t st, KState* ks, int m, int k, double2* Pout, 
   DMG_HIP(ensure_dyn_lds((const void*)k_dr_post, sho));
   hipLaunchKernelGGL(k_dr_pre, dim3(1), dim3(DW), shp, st, ks, m, k, work, status);
   DMG_LAUNCH_CHECK();
-  if (m <= EIG_NMAX && !dr_force_qr()) {
+  const int force = dr_force_qr();
+  if (m <= EIG_NMAX && force != 1) {
     const size_t she = dr_eig_lds_bytes(m);
     DMG_HIP(ensure_dyn_lds((const void*)k_dr_eig, she));
-    hipLaunchKernelGGL(k_dr_eig, dim3(1), dim3(EIG_THREADS), she, st, work, m, k, warm, (const int*)status);
+    hipLaunchKernelGGL(k_dr_eig, dim3(1), dim3(EIG_THREADS), she, st, work, m, k, warm, force == 2 ? 0 : EIG_MAXIT,
+                       (const int*)status);
     DMG_LAUNCH_CHECK();
   }
   hipLaunchKernelGGL(k_dr_post, dim3(1), dim3(DW), sho, st, ks, m, k, Pout, final_mode, work, status);
