@@ -119,10 +119,14 @@ __global__ void __launch_bounds__(512) k_block_apply(const B* __restrict__ A, co
   __syncthreads();
   if (active) {
     const auto* a = A + ((int64_t)S * 5 + d) * NC * NC + i;
-    T acc = make_cx<R>(R(0), R(0));
-#pragma unroll 8
-    for (int j = 0; j < NC; ++j) cfma(acc, ld_blk(a + j * NC), xs[ls][d][j]);
-    part[ls][d][i] = acc;
+    // all 24 block loads in flight at once; two accumulators halve the dependent chain
+    T acc = make_cx<R>(R(0), R(0)), acc2 = make_cx<R>(R(0), R(0));
+#pragma unroll
+    for (int j = 0; j < NC; j += 2) {
+      cfma(acc, ld_blk(a + j * NC), xs[ls][d][j]);
+      cfma(acc2, ld_blk(a + (j + 1) * NC), xs[ls][d][j + 1]);
+    }
+    part[ls][d][i] = cadd(acc, acc2);
   }
   __syncthreads();
   if (active && d == 0) {
