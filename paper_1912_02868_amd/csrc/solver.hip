@@ -830,8 +830,12 @@ bool outer_advance(Work* w, int min_iters) {
       }
       A.apply(s, zj, V + (int64_t)(j + 1) * n, 0, nullptr);
       w->cnt.mv[0]++;
-      launch_arnoldi_orth<double>(s, V, n, n, j, ks, PART(w), CNT(w));
+      launch_arnoldi_orth1<double>(s, V, n, n, j, ks, PART(w), CNT(w));
       sync_status(w, ks, &st);
+      if (st.pass2) {
+        launch_arnoldi_pass2<double>(s, V, n, n, j, ks, PART(w), CNT(w));
+        sync_status(w, ks, &st);
+      }
       if (st.done) break;
     }
     launch_ls_solve(s, ks);
