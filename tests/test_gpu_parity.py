@@ -463,9 +463,10 @@ def test_solve_bf16_coarse_preconditioner_64(dmg, ctx, injected):
 
 
 def test_partial_solve_second_pass_path(dmg, ctx, injected, monkeypatch):
-    """The partial intermediate solve's one-pass Gram-Schmidt and its exact second pass (forced at
-    every step by DMG_ARNOLDI_TWO_PASS=1): both reach 1e-8 with the solution of sparse LU, with the
-    same outer and intermediate step counts (equal columns in exact arithmetic)."""
+    """The one-pass Gram-Schmidt of the outer FGMRES and the partial intermediate solve, and its
+    exact second pass (forced at every step by DMG_ARNOLDI_TWO_PASS=1): both reach 1e-8 with the
+    solution of sparse LU, with the same outer and intermediate step counts (equal columns in exact
+    arithmetic)."""
     N, th, m0, H, g, hg = injected
     if N != 64:
         pytest.skip("workload-sized solve")
