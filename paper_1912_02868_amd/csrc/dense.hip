@@ -1,7 +1,8 @@
 // Small dense FP64 work of the Krylov solvers, done on the device by one
-// workgroup: least-squares back-substitution, the GMRES-DR deflated restart
-// (harmonic Ritz eigenproblem, choice of the k smallest, new basis change and
-// Hbar_k), Givens QR of a full (k+1) x k block, and the GMRES-Proj projection.
+// workgroup per launch: least-squares back-substitution, the GMRES-DR deflated
+// restart (harmonic Ritz eigenproblem on several wavefronts or by the QR
+// algorithm, choice of the k smallest, new basis change and Hbar_k), Givens QR of
+// a full (k+1) x k block, and the GMRES-Proj projection.
 #include "kernels.h"
 
 namespace dmg {
