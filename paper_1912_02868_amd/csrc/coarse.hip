@@ -857,6 +857,7 @@ struct CAArgs {
   unsigned* flags;     // G barrier flags, CP_FLAGPAD apart, zero at launch
   int* err;
   int spw;
+  double eta;          // cancellation below which the Pythagorean norm gives way to a second pass
 };
 
 struct CALayout {
@@ -1015,28 +1016,37 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_arnoldi(CAArgs a) {
       else v.x = cabs2(wl[e]);
       return v;
     };
-    // first pass: h = V^H w, ||w||^2
+    // h = V^H w and ||w||^2 in one reduction; the norm of w - V h from ||w||^2 - ||h||^2 unless
+    // that difference shows cancellation beyond eta, in which case w - V h goes through an exact
+    // second pass (H(:, j) = h + h2)
     wg_sums(j + 2, dots);
     grid_reduce(j + 2);
-    wn0 = sqrt(res[j + 1].x);
+    const double ww = res[j + 1].x;
+    wn0 = sqrt(ww);
+    double hh = 0.0;
+    for (int i = 0; i <= j; ++i) hh += cabs2(res[i]);
+    double hn;
     if (tid <= j) hcol[tid] = res[tid];
-    for (int t = tid; t < ne; t += CP_THREADS) {
-      double2 w = wl[t];
-      for (int i = 0; i <= j; ++i) w = csub(w, cmul(res[i], Vb[i * ne + t]));
-      wl[t] = w;
+    if (!(ww - hh > a.eta * ww)) {
+      for (int t = tid; t < ne; t += CP_THREADS) {
+        double2 w = wl[t];
+        for (int i = 0; i <= j; ++i) w = csub(w, cmul(res[i], Vb[i * ne + t]));
+        wl[t] = w;
+      }
+      __syncthreads();
+      wg_sums(j + 2, dots);
+      grid_reduce(j + 2);
+      double hh2 = 0.0;
+      for (int i = 0; i <= j; ++i) hh2 += cabs2(res[i]);
+      hn = sqrt(fmax(res[j + 1].x - hh2, 0.0));
+      if (!(hn > 1e-12 * wn0)) {
+        hn = 0.0;
+        brk = true;
+      }
+      if (tid <= j) hcol[tid] = cadd(hcol[tid], res[tid]);
+    } else {
+      hn = sqrt(ww - hh);  // above sqrt(eta) ||w||: no breakdown
     }
-    __syncthreads();
-    // second pass: h2 = V^H w, ||w||^2; H(:, j) = h + h2
-    wg_sums(j + 2, dots);
-    grid_reduce(j + 2);
-    double hh2 = 0.0;
-    for (int i = 0; i <= j; ++i) hh2 += cabs2(res[i]);
-    double hn = sqrt(fmax(res[j + 1].x - hh2, 0.0));
-    if (!(hn > 1e-12 * wn0)) {
-      hn = 0.0;
-      brk = true;
-    }
-    if (tid <= j) hcol[tid] = cadd(hcol[tid], res[tid]);
     __syncthreads();
     // Givens update on the last wavefront (overlaps the vector update below): rows 0 .. j0 of
     // the column through the entry rotations (Q0), then this cycle's rotations at positions
@@ -1098,7 +1108,7 @@ __global__ void __launch_bounds__(CP_THREADS) k_coarse_arnoldi(CAArgs a) {
         }
       }
     }
-    // v_{j+1} = (w - V h2) / hn
+    // v_{j+1} = (w - V h) / hn, h of the last pass
     const double inv = hn > 0.0 ? 1.0 / hn : 0.0;
     for (int t = tid; t < ne; t += CP_THREADS) {
       double2 w = wl[t];
@@ -1156,7 +1166,10 @@ int launch_coarse_arnoldi(hipStream_t st, const double2* A, int Lx, int Lt, doub
     (void)hipGetLastError();
     return 0;
   }
-  CAArgs a{A, Lx, Lt, V, ks, j0, m, xchg, partials, flags, err, spw};
+  // DMG_ARNOLDI_TWO_PASS=1 takes the second pass at every step (read at each call)
+  const char* e2 = getenv("DMG_ARNOLDI_TWO_PASS");
+  const double eta = (e2 && *e2 && *e2 != '0') ? 2.0 : 1e-8;
+  CAArgs a{A, Lx, Lt, V, ks, j0, m, xchg, partials, flags, err, spw, eta};
   void* args[] = {&a};
   if (hipLaunchCooperativeKernel(fn, dim3(G), dim3(CP_THREADS), args, (unsigned)lds, st) != hipSuccess) {
     (void)hipGetLastError();

@@ -263,10 +263,12 @@ def test_gmres_dr_deflation_space(dmg, injected):
 def test_gmres_dr_space_both_eigen_paths_and_oracle(dmg, injected, monkeypatch):
     """GMRES-DR(30, 10) to 1e-8 on the oracle's 64^2 coarse matrix, with the restart's eigenvalues
     from the simultaneous iteration (the default for m <= 32), from the QR algorithm alone
-    (DMG_RESTART_QR=1), and from the QR algorithm after the simultaneous iteration gave up
-    (DMG_RESTART_QR=2): every kept space satisfies A V_k = V_{k+1} Hbar_k, and their Ritz values
-    equal each other's and those of the oracle's gmres_dr space on the same matrix and right-hand
-    side (every restart ranks the same harmonic Ritz values, so the spaces agree to rounding)."""
+    (DMG_RESTART_QR=1), from the QR algorithm after the simultaneous iteration gave up
+    (DMG_RESTART_QR=2), and with the Arnoldi's exact second Gram-Schmidt pass at every step
+    (DMG_ARNOLDI_TWO_PASS=1; by default one pass with the Pythagorean norm): every kept space
+    satisfies A V_k = V_{k+1} Hbar_k, and their Ritz values equal each other's and those of the
+    oracle's gmres_dr space on the same matrix and right-hand side (every restart ranks the same
+    harmonic Ritz values, so the spaces agree to rounding)."""
     N, th, m0, H, g, hg = injected
     if N != 64:
         pytest.skip("needs a coarse space larger than m")
@@ -282,11 +284,15 @@ def test_gmres_dr_space_both_eigen_paths_and_oracle(dmg, injected, monkeypatch):
         return max(np.min(np.abs(a - t)) / abs(t) for t in b_)
 
     got = {}
-    for mode in ("simultaneous", "qr", "qr after giving up"):
-        if mode == "simultaneous":
+    for mode in ("simultaneous", "qr", "qr after giving up", "second pass forced"):
+        if mode in ("simultaneous", "second pass forced"):
             monkeypatch.delenv("DMG_RESTART_QR", raising=False)
         else:
             monkeypatch.setenv("DMG_RESTART_QR", "1" if mode == "qr" else "2")
+        if mode == "second pass forced":
+            monkeypatch.setenv("DMG_ARNOLDI_TWO_PASS", "1")
+        else:
+            monkeypatch.delenv("DMG_ARNOLDI_TWO_PASS", raising=False)
         print(f"[case] GMRES-DR(30, 10) 64^2 coarse, restart eigenvalues by {mode}", flush=True)
         d = dmg.Deflation(hg, 30, 10)
         d.build(b, 1e-8)
@@ -299,9 +305,10 @@ def test_gmres_dr_space_both_eigen_paths_and_oracle(dmg, injected, monkeypatch):
         assert np.linalg.norm(Dc @ V[:, :k] - V @ Hk) / np.linalg.norm(Hk) < 1e-10
         got[mode] = ritz(V, k)
     monkeypatch.delenv("DMG_RESTART_QR", raising=False)
+    monkeypatch.delenv("DMG_ARNOLDI_TWO_PASS", raising=False)
     _, info, defl = krylov.gmres_dr(lambda v: Dc @ v, b, 30, 10, 1e-8)
     ro = ritz(defl.V, 10)
-    d_paths = max(dist(got["simultaneous"], got["qr"]), dist(got["qr after giving up"], got["qr"]))
+    d_paths = max(dist(got[mm], got["qr"]) for mm in got if mm != "qr")
     d_or = max(dist(got[mm], ro) for mm in got)
     print(f"    Ritz values: paths within {d_paths:.1e}, oracle within {d_or:.1e}", flush=True)
     # measured: 1.1e-14 and 5e-14
