@@ -373,8 +373,12 @@ __device__ inline double2 cp_div(double2 a, double2 b) {
 // next stencil needs no exchange.  The halo values are bitwise the owners' (same inputs,
 // same operations in the same loop).
 // REG (halo form, at most 4 sites per workgroup): 512 threads, and thread t < 5 * 24 * spw keeps
-// its row of the 24 x 24 blocks in registers for the whole solve (96 VGPRs in FP64), so the
-// stencil reads only v_j (LDS) instead of streaming the blocks from L2 every step.
+// 24 entries of the 24 x 24 blocks in registers for the whole solve (96 VGPRs in FP64), so the
+// stencil reads only v_j (LDS) instead of streaming the blocks from L2 every step.  Thread t
+// serves block t / 24 (site-major, directions 0 .. 4): with u = t % 24 it holds rows u / 2 and
+// u / 2 + 12 over the column half u % 2, so it reads only half of v_j's 24 entries (the LDS
+// bandwidth bounds this phase: every thread of a block reads the same values), and the two
+// threads of a pair (adjacent lanes) exchange one half-row sum by DPP.
 template <typename R, bool ALDS, bool HALO, bool REG = false>
 __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a) {
   static_assert(!REG || (HALO && !ALDS), "register blocks come with the halo form");
@@ -436,11 +440,19 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
     __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     dead = true;
   }
-  // halo entries of exchange half `half` into wl[ne ..] (issued right after a barrier)
-  auto load_halo = [&](int half) {
+  // halo entries of exchange half `half` into wl[ne ..], right after a barrier: thread
+  // TPB - 1 - t loads entry t (at most one per thread for every supported halo; the loop
+  // covers the rest) and issues that load before the reduction's gather loads, so that both
+  // device-scope round trips are in flight together
+  auto halo_load1 = [&](int half, T& hv) {
+    const int t = TPB - 1 - tid;
+    if (t < nh * NC) hv = cp_load(&xch[(size_t)half * n + (int64_t)hsite[t / NC] * NC + t % NC]);
+  };
+  auto halo_store = [&](int half, const T& hv) {
     const T* src = xch + (size_t)half * n;
-    for (int t = TPB - 1 - tid; t < nh * NC; t += TPB)
-      wl[ne + t] = cp_load(&src[(int64_t)hsite[t / NC] * NC + t % NC]);
+    int t = TPB - 1 - tid;
+    if (t < nh * NC) wl[ne + t] = hv;
+    for (t += TPB; t < nh * NC; t += TPB) wl[ne + t] = cp_load(&src[(int64_t)hsite[t / NC] * NC + t % NC]);
   };
 
   // ---------------------------------------------------------------- reduction helpers
@@ -471,6 +483,8 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
   auto grid_reduce_h = [&](int nq, int halo_half, auto during) {
     double2* P = a.partials + (size_t)rbuf * CP_QMAX * G;
     dead = dead || cp_barrier(a.flags, G, ++gen, a.err, during);
+    T hv = make_cx<R>(R(0), R(0));
+    if (HALO && halo_half >= 0) halo_load1(halo_half, hv);
     const int q = tid >> 5, c = tid & 31;
     if (NHW < CP_QMAX && q + NHW < nq) {
       // two quantities per half-wavefront, all loads in flight together
@@ -484,7 +498,7 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
       const double2 sm = cp_gather_sum(P + (size_t)q * G, G, c);
       if (c == 0) res[q] = sm;
     }
-    if (HALO && halo_half >= 0) load_halo(halo_half);
+    if (HALO && halo_half >= 0) halo_store(halo_half, hv);
     __syncthreads();
     rbuf ^= 1;
   };
@@ -495,10 +509,13 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
   T areg[REG ? NC : 1];
   if constexpr (REG) {
     if (tid < nsl * 5 * NC) {
-      const int sl = tid / (5 * NC), d = (tid / NC) % 5, i = tid % NC;
-      const T* blk = Ag + ((int64_t)(S0 + sl) * 5 + d) * NC * NC + i;
+      const int u = tid % NC, r = u >> 1, c0 = (u & 1) * (NC / 2);
+      const T* blk = Ag + ((int64_t)S0 * 5 + tid / NC) * NC * NC;  // block (site, direction) of t / 24
 #pragma unroll
-      for (int jj = 0; jj < NC; ++jj) areg[jj] = blk[jj * NC];
+      for (int c = 0; c < NC / 2; ++c) {
+        areg[c] = blk[(c0 + c) * NC + r];
+        areg[NC / 2 + c] = blk[(c0 + c) * NC + r + NC / 2];
+      }
     }
   }
   if (ALDS) {
@@ -609,12 +626,20 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
       // the halo form's stencil reads w itself, not the scaled copy or an exchange load
       if (!HALO) __syncthreads();
       if (REG && tid < nsl * 5 * NC) {
-        const int sl = tid / (5 * NC), d = (tid / NC) % 5;
-        const T* xv = wl + loc[sl * 5 + d] * NC;
-        double2 acc = mk(0.0, 0.0);
+        const int g = tid / NC, u = tid % NC, odd = u & 1;
+        const T* xv = wl + loc[g] * NC + odd * (NC / 2);
+        double2 a0 = mk(0.0, 0.0), a1 = mk(0.0, 0.0);
 #pragma unroll
-        for (int jj = 0; jj < NC; ++jj) cfma(acc, to_d(areg[jj]), to_d(xv[jj]));
-        part[tid] = acc;
+        for (int c = 0; c < NC / 2; ++c) {
+          const double2 xc = to_d(xv[c]);
+          cfma(a0, to_d(areg[c]), xc);
+          cfma(a1, to_d(areg[NC / 2 + c]), xc);
+        }
+        // the even thread of the pair completes row u / 2, the odd one row u / 2 + 12 (first
+        // column half first in both); a pair never straddles a block or a wavefront
+        const double2 send = odd ? a0 : a1;
+        const double2 recv = mk(cp_dpp<0xB1>(send.x), cp_dpp<0xB1>(send.y));  // quad_perm [1, 0, 3, 2]
+        part[g * NC + (u >> 1) + odd * (NC / 2)] = odd ? cadd(recv, a1) : cadd(a0, recv);
       }
       for (int t = tid; t < (REG ? 0 : nsl * 5 * NC); t += TPB) {
         const int sl = t / (5 * NC), d = (t / NC) % 5, i = t % NC;
