@@ -97,8 +97,10 @@ __device__ inline void cp_wait_stores() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 // barriers; a wait longer than the spin limit sets *err and gives up, so no wave
 // can hang the device.
 // Returns true when the grid must stop: some wait (here or in another workgroup) ran
-// past its spin limit.  After that every barrier returns at once, and the caller
-// leaves its loops, so the whole grid drains quickly.
+// past its spin limit.  A workgroup that stops publishes no more flags, so a wait for one
+// of its flags finds *err set (it is read every 64 spins) and stops too, and the callers
+// leave their loops: the whole grid drains quickly.  *err is not read on the fast path,
+// where its round trip would delay the flag store or the first poll.
 // Every wavefront waits for its own exchange stores before the workgroup barrier: a
 // wavefront's wait covers only its own outstanding stores, so the flag store of
 // wavefront 0 alone would not order the other wavefronts' stores before it.
@@ -113,30 +115,33 @@ __device__ inline bool cp_barrier(unsigned* flags, int G, unsigned gen, int* err
   cp_wait_stores();
   __syncthreads();
   if (threadIdx.x == 0) {
-    aborted = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     // relaxed: every datum the flag publishes was stored with a device-scope atomic
     // that completed before the workgroup barrier above
     __hip_atomic_store(&flags[blockIdx.x * CP_FLAGPAD], gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    aborted = 0;
   }
   __syncthreads();
-  if (threadIdx.x < 64 && !aborted) {
-    bool timed_out = false;
-    for (int b = threadIdx.x; b < G && !timed_out; b += 64) {
+  if (threadIdx.x < 64) {
+    bool stop = false, timed_out = false;
+    for (int b = threadIdx.x; b < G && !stop; b += 64) {
       long spins = 0;
       // relaxed: the published data is read with device-scope atomics after this wait,
       // so no cache invalidation is needed (it would also evict the operator's blocks)
       while (__hip_atomic_load(&flags[b * CP_FLAGPAD], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
         __builtin_amdgcn_s_sleep(1);
-        if (++spins > (1L << 22)) {
-          timed_out = true;
+        ++spins;
+        if ((spins & 63) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+          stop = true;  // some workgroup gave up: its flag may never come
+          break;
+        }
+        if (spins > (1L << 22)) {
+          stop = timed_out = true;
           break;
         }
       }
     }
-    if (timed_out) {
-      __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      aborted = 1;
-    }
+    if (timed_out) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (stop) aborted = 1;
   }
   if (threadIdx.x >= blockDim.x - 64) during();
   __syncthreads();
@@ -811,22 +816,27 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
     }
     est = sqrt(est);  // every step above left the squared estimate
     // ------------------------------------------------------------ end of cycle: x += V y, r = V u
-    if (tid == 0) {
-      for (int i = steps - 1; i >= 0; --i) {
-        double2 acc = gv[i];
-        for (int l = i + 1; l < steps; ++l) acc = csub(acc, cmul(Hr[i + (mm + 1) * l], yv[l]));
-        const double2 d = Hr[i + (mm + 1) * i];
-        yv[i] = cabs2(d) > 0.0 ? cp_div(acc, d) : mk(0.0, 0.0);
+    if (wave == 0) {
+      // y = R^{-1} g by columns on one wavefront: lane i carries g_i - sum_{l > i} R_il y_l;
+      // y_l comes from lane l's carry (a scalar read), then every lane i < l drops its term
+      double2 acc = lane < steps ? gv[lane] : mk(0.0, 0.0);
+      for (int l = steps - 1; l >= 0; --l) {
+        const double2 d = Hr[l + (mm + 1) * l];
+        const double2 yl = cabs2(d) > 0.0 ? cp_div(cp_lane(acc, l), d) : mk(0.0, 0.0);
+        if (lane == l) yv[l] = yl;
+        if (lane < l) acc = csub(acc, cmul(Hr[lane + (mm + 1) * l], yl));
       }
-      // residual coordinates: u = Omega^H (g_steps e_steps)
-      for (int i = 0; i <= steps; ++i) uv[i] = mk(0.0, 0.0);
-      uv[steps] = brk ? mk(0.0, 0.0) : gv[steps];
+      // residual coordinates u = Omega^H (g_steps e_steps), Omega^H applying the inverse
+      // rotations [c -s; conj(s) c] from the last one down: with u_q = 0 on entry, rotation q
+      // leaves u_{q+1} = c_q t and carries t <- -s_q t down to u_q (t = g_steps at first)
+      const double cl = lane < steps ? rc[lane] : 1.0;
+      const double2 sl = lane < steps ? rs[lane] : mk(0.0, 0.0);
+      double2 tc = brk ? mk(0.0, 0.0) : gv[steps];
       for (int q = steps - 1; q >= 0; --q) {
-        const double2 x0 = uv[q], x1 = uv[q + 1];
-        // inverse of [c s; -conj(s) c] is [c -s; conj(s) c]
-        uv[q] = csub(cscale(x0, rc[q]), cmul(rs[q], x1));
-        uv[q + 1] = cadd(cmul(cconj(rs[q]), x0), cscale(x1, rc[q]));
+        if (lane == q + 1) uv[q + 1] = cscale(tc, cp_lane(cl, q));
+        tc = csub(mk(0.0, 0.0), cmul(cp_lane(sl, q), tc));
       }
+      if (lane == 0) uv[0] = tc;
     }
     __syncthreads();
     // v_steps: hprev * v_steps is in wl, or v_steps itself in Vb when a column was dropped
