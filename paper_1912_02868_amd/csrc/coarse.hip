@@ -874,11 +874,12 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
 // tol_abs or the process breaks down, with the same layout and helpers as k_coarse_proj:
 // workgroups own consecutive coarse sites, keep their slices of V in LDS, exchange v_j for
 // the stencil through one global field, and reduce dot products through per-workgroup
-// partials and a flag-array grid barrier.  Gram-Schmidt is classical and always applied
-// twice (the deflation space must satisfy the Arnoldi relation to working accuracy even for
-// the 1e-15 oversolve), with the norm of the twice-orthogonalised vector from its square
-// minus the second-pass coefficients.  Three barriers per column.  Every workgroup holds the
-// same small-dense state; workgroup 0 writes it back (H, R, g, rotations, steps, flags).
+// partials and a flag-array grid barrier.  Gram-Schmidt is classical: one pass with the norm
+// from ||w||^2 - ||h||^2, and a second, exact pass when that difference shows cancellation
+// beyond eta (the Arnoldi relation holds to working accuracy either way, since H holds the
+// coefficients actually subtracted).  Two barriers per column (exchange and reduction), three
+// with a second pass.  Every workgroup holds the same small-dense state; workgroup 0 writes it
+// back (H, R, g, rotations, steps, flags).
 constexpr int CA_NROT = 256;  // rotations held in LDS (restart block plus this cycle's)
 
 struct CAArgs {
