@@ -818,13 +818,19 @@ __global__ void __launch_bounds__(REG ? 512 : CP_THREADS) k_coarse_proj(CPArgs a
     // ------------------------------------------------------------ end of cycle: x += V y, r = V u
     if (wave == 0) {
       // y = R^{-1} g by columns on one wavefront: lane i carries g_i - sum_{l > i} R_il y_l;
-      // y_l comes from lane l's carry (a scalar read), then every lane i < l drops its term
+      // y_l = carry_l / R_ll from lane l's carry and reciprocal (scalar reads; the reciprocals
+      // are taken beforehand, one per lane), then every lane i < l drops its term, with its
+      // entry of the next column already loaded
       double2 acc = lane < steps ? gv[lane] : mk(0.0, 0.0);
+      const double2 dl = lane < steps ? Hr[lane + (mm + 1) * lane] : mk(1.0, 0.0);
+      const double2 rdl = cabs2(dl) > 0.0 ? cp_div(mk(1.0, 0.0), dl) : mk(0.0, 0.0);
+      double2 rcol = (steps > 0 && lane < steps) ? Hr[lane + (mm + 1) * (steps - 1)] : mk(0.0, 0.0);
       for (int l = steps - 1; l >= 0; --l) {
-        const double2 d = Hr[l + (mm + 1) * l];
-        const double2 yl = cabs2(d) > 0.0 ? cp_div(cp_lane(acc, l), d) : mk(0.0, 0.0);
+        const double2 rnx = (l > 0 && lane < l) ? Hr[lane + (mm + 1) * (l - 1)] : mk(0.0, 0.0);
+        const double2 yl = cmul(cp_lane(acc, l), cp_lane(rdl, l));
         if (lane == l) yv[l] = yl;
-        if (lane < l) acc = csub(acc, cmul(Hr[lane + (mm + 1) * l], yl));
+        if (lane < l) acc = csub(acc, cmul(rcol, yl));
+        rcol = rnx;
       }
       // residual coordinates u = Omega^H (g_steps e_steps), Omega^H applying the inverse
       // rotations [c -s; conj(s) c] from the last one down: with u_q = 0 on entry, rotation q
