@@ -38,7 +38,7 @@ RHS_PER_CONFIG = 5
 # HBM bytes per launch of k_coarse_proj<double, false, true, true> from the FETCH_SIZE and WRITE_SIZE counter
 # passes (scaled by the reference streaming kernels) recorded in profiles/k_coarse_proj_256_hbm_traffic.md;
 # valid while that kernel is unchanged
-COARSE_TRAFFIC_BYTES = 65_068_032
+COARSE_TRAFFIC_BYTES = 65_012_838
 
 
 def parse():
