@@ -91,16 +91,29 @@ __device__ inline void make_givens_fast(double2 a, double2 b, double& c, double2
 // ---------------------------------------------------------------- least squares
 // y = R^{-1} g over the completed steps by columns on one wavefront (lane i holds the running
 // g_i; column l gives y_l from lane l, then every lane above drops its term), R staged in LDS;
-// then u = c - H y with one thread per row.
+// then u = c - H y with one thread per row, H staged in the same LDS when it fits.  Each lane
+// issues eight staging loads before it stores any (the loads are independent; one at a time,
+// each would wait a full L2 round trip).
+__device__ inline void ls_stage(double2* dst, const double2* src, int rows, int cols, bool upper) {
+  const int t = threadIdx.x, ne = rows * cols;
+  for (int e0 = t; e0 < ne; e0 += 8 * DW) {
+    double2 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * DW, i = e % rows, l = e / rows;
+      v[u] = (e < ne && (!upper || i <= l)) ? src[i + LD * l] : mk(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (e0 + u * DW < ne) dst[e0 + u * DW] = v[u];
+  }
+}
 __global__ void __launch_bounds__(DW) k_ls_solve(KState* ks) {
   __shared__ double2 Rs[MMAX * MMAX];
   __shared__ double2 ys[MMAX + 1];
   const int t = threadIdx.x;
   const int n = ks->steps;
-  for (int e = t; e < n * n; e += DW) {
-    const int i = e % n, l = e / n;
-    Rs[e] = (i <= l) ? ks->R[i + LD * l] : mk(0.0, 0.0);
-  }
+  ls_stage(Rs, ks->R, n, n, true);
   double2 acc = t < n ? ks->g[t] : mk(0.0, 0.0);
   __syncthreads();
   for (int l = n - 1; l >= 0; --l) {
@@ -113,9 +126,15 @@ __global__ void __launch_bounds__(DW) k_ls_solve(KState* ks) {
   }
   __syncthreads();
   for (int i = t; i < n; i += DW) ks->y[i] = ys[i];
+  const bool staged = (n + 1) * n <= MMAX * MMAX;
+  if (staged) ls_stage(Rs, ks->H, n + 1, n, false);  // R is no longer read
+  __syncthreads();
   for (int i = t; i <= n; i += DW) {
     double2 a2 = ks->c[i];
-    for (int l = 0; l < n; ++l) a2 = csub(a2, cmul(ks->H[i + LD * l], ys[l]));
+    if (staged)
+      for (int l = 0; l < n; ++l) a2 = csub(a2, cmul(Rs[i + (n + 1) * l], ys[l]));
+    else
+      for (int l = 0; l < n; ++l) a2 = csub(a2, cmul(ks->H[i + LD * l], ys[l]));
     ks->u[i] = a2;
   }
 }
