@@ -977,59 +977,58 @@ __global__ void __launch_bounds__(DW) k_dr_pre(KState* ks, int m, int k, double2
   __syncthreads();
   const double h = Hb[m + (m + 1) * (m - 1)].x;  // h_{m+1,m}, real >= 0
 
-  // f = H^{-H} e_m : Gaussian elimination with partial pivoting on M = H^H (in A), rhs in v
-  for (int e = t; e < m * m; e += DW) {
-    const int i = e % m, j = e / m;
-    A[e] = cconj(Hb[j + (m + 1) * i]);
-  }
-  for (int i = t; i < m; i += DW) v[i] = (i == m - 1) ? mk(1.0, 0.0) : mk(0.0, 0.0);
+  // f = H^{-H} e_m from the LU factors of H itself (P H = L U, partial pivoting).  H is upper
+  // Hessenberg outside its leading restart block, so column p has nonzeros only in rows
+  // p .. hi_p (hi_p = p + 1 past the block): the pivot is chosen among those rows and the
+  // elimination updates only them.  With E_p the elimination of column p and P_p its row swap,
+  // H^H f = e_m gives f = P_0 E_0^H P_1 E_1^H ... U^{-H} e_m, where U^{-H} e_m = e_m / conj(u_mm)
+  // and E_p^H changes only entry p (by the multipliers of column p).
+  __shared__ int hiv[MMAX], pvv[MMAX];
+  for (int e = t; e < m * m; e += DW) A[e] = Hb[(e % m) + (m + 1) * (e / m)];
   __syncthreads();
   for (int p = 0; p < m; ++p) {
-    __shared__ int piv;
-    {
-      // partial pivoting: the first row of largest modulus (compared squared)
-      const double a2 = (t >= p && t < m) ? cabs2(A[t + m * p]) : -1.0;
-      const int best = wave_argmax(a2);  // -1 if the column holds NaN
-      const double bv = best >= 0 ? rd_lane(a2, best) : 0.0;
-      if (t == 0) {
-        piv = best >= 0 ? best : p;
-        if (!(bv > 0.0)) fail = 1;
-      }
+    const double2 ap = (t >= p && t < m) ? A[t + m * p] : mk(0.0, 0.0);
+    const unsigned long long nz = __ballot(t >= p && t < m && (ap.x != 0.0 || ap.y != 0.0));
+    const int hi = nz ? 63 - __clzll(nz) : p;  // last row with a nonzero in column p
+    const double a2 = (t >= p && t <= hi) ? cabs2(ap) : -1.0;
+    const int piv = wave_argmax(a2);  // the first row of largest modulus; -1 on NaN
+    const double bv = piv >= 0 ? rd_lane(a2, piv) : 0.0;
+    if (!(bv > 0.0)) {  // uniform: singular (or not finite)
+      if (t == 0) fail = 1;
+      break;
+    }
+    if (t == 0) {
+      hiv[p] = hi;
+      pvv[p] = piv;
+    }
+    if (piv != p && t >= p && t < m) {  // swap rows p and piv in columns p .. m-1
+      const double2 x = A[p + m * t];
+      A[p + m * t] = A[piv + m * t];
+      A[piv + m * t] = x;
     }
     __syncthreads();
-    if (fail) break;
-    if (piv != p) {
-      for (int jc = t; jc < m; jc += DW) {
-        const double2 tmp = A[p + m * jc];
-        A[p + m * jc] = A[piv + m * jc];
-        A[piv + m * jc] = tmp;
-      }
-      if (t == 0) { const double2 tmp = v[p]; v[p] = v[piv]; v[piv] = tmp; }
-    }
-    __syncthreads();
-    // multipliers (lane i), then the rank-one update of the trailing block element by element
-    // (column p below the pivot is not read again)
-    __shared__ double2 fct[DW];
     const double2 dp = A[p + m * p];
-    if (t > p && t < m) {
-      const double2 fi = cdiv(A[t + m * p], dp);
-      fct[t] = fi;
-      v[t] = csub(v[t], cmul(fi, v[p]));
-    }
+    if (t > p && t <= hi) A[t + m * p] = cdiv(A[t + m * p], dp);  // multipliers, kept in place
     __syncthreads();
-    const int rows = m - p - 1;
-    for (int e = t; e < rows * rows; e += DW) {
-      const int i = p + 1 + e % rows, jc = p + 1 + e / rows;
-      A[i + m * jc] = csub(A[i + m * jc], cmul(fct[i], A[p + m * jc]));
+    if (t > p && t < m) {  // rows p+1 .. hi of column t
+      const double2 up = A[p + m * t];
+      for (int r = p + 1; r <= hi; ++r) A[r + m * t] = csub(A[r + m * t], cmul(A[r + m * p], up));
     }
     __syncthreads();
   }
+  __syncthreads();
   if (fail) { if (t == 0) *status = 2; return; }
-  // back substitution by columns: f_i from row i, then every row above drops its term
-  for (int i = m - 1; i >= 0; --i) {
-    const double2 fi = cdiv(rd_lane(i == t ? v[t] : mk(0.0, 0.0), i), A[i + m * i]);
-    if (t == 0) f[i] = fi;
-    if (t < i) v[t] = csub(v[t], cmul(A[t + m * i], fi));
+  if (t == 0) {
+    for (int i = 0; i < m - 1; ++i) v[i] = mk(0.0, 0.0);
+    v[m - 1] = cdiv(mk(1.0, 0.0), cconj(A[(m - 1) + m * (m - 1)]));
+    for (int p = m - 2; p >= 0; --p) {
+      double2 zp = v[p];
+      for (int r = p + 1; r <= hiv[p]; ++r) zp = csub(zp, cmul(cconj(A[r + m * p]), v[r]));
+      const int q = pvv[p];
+      v[p] = v[q];
+      v[q] = zp;
+    }
+    for (int i = 0; i < m; ++i) f[i] = v[i];
   }
   __syncthreads();
   // G = H + |h|^2 f e_m^T into A
