@@ -89,6 +89,35 @@ def test_solution_vs_lu_256(dmg, ctx, cfg256, precond):
     d.close()
 
 
+@pytest.mark.parametrize("precond", ["fp64", "fp32"])
+def test_persistent_coarse_solve_repeatable_256(dmg, ctx, cfg256, precond):
+    """One right-hand side solved twice with the same deflation space (built by the GMRES-DR of a
+    first solve): bitwise the same solution and the same statistics.  Every GMRES-Proj coarse
+    solve is one persistent launch of 64 workgroups (register stencil split over lane pairs,
+    least squares on one wavefront) whose grid-wide sums are added in a fixed order, so its result
+    must not depend on the order in which the workgroups arrive."""
+    N, cfg, g, h, D, lu = cfg256
+    d = dmg.Deflation(h, 30, 10)
+    prm = dmg.solve_params(precond=precond)
+    b0 = synth.rhs(N, cfg, 0)
+    st, _ = dmg.solve(ctx, h, d, b0, np.zeros_like(b0), params=prm)
+    assert st == dmg.DMG_OK
+    b = synth.rhs(N, cfg, 2)
+    runs = []
+    for rep in range(2):
+        print(f"[case] 256^2 repeated solve precond={precond} rhs=2 run {rep}", flush=True)
+        x = np.zeros_like(b)
+        st, stats = dmg.solve(ctx, h, d, b, x, params=prm)
+        assert st == dmg.DMG_OK and stats[0]["converged"] == 1
+        runs.append((x, stats[0]))
+    d.close()
+    (xa, sa), (xb, sb) = runs
+    assert np.array_equal(xa, xb)
+    for key in ("outer_iters", "fine_mvps", "int_mvps", "coarse_mvps", "true_rel_resid", "coarse_calls"):
+        assert sa[key] == sb[key], key
+    assert sa["coarse_dr_calls"] == 0 and _resid(D, b, xa) <= 1e-8
+
+
 # ---------------------------------------------------------------- 512^2 x 64 lockstep vs the oracle
 @pytest.fixture(scope="module")
 def cfg512(dmg, ctx):
