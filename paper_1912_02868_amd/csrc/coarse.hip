@@ -24,7 +24,8 @@
 // orthogonalisation is classical Gram-Schmidt with the norm from ||w||^2 - ||h||^2; when
 // that difference shows more than 99.99 % cancellation a second pass with an exact norm
 // is taken (one more barrier).  The Givens rotations of each new Hessenberg column come
-// from a lane scan (cp_rotation_scan).  In exact arithmetic this is the Arnoldi process of
+// from a lane scan (cp_rotation_scan), and each cycle's least-squares solve and residual
+// coordinates run on one wavefront.  In exact arithmetic this is the Arnoldi process of
 // GMRES; the oracle uses modified Gram-Schmidt twice.
 #include <algorithm>
 #include <cstdio>
