@@ -1230,6 +1230,16 @@ static bool cp_halo_enabled() {
   return on != 0;
 }
 
+// Target number of workgroups of the persistent GMRES-Proj launch (DMG_COARSE_GROUPS, default 64).
+static int cp_groups_default() {
+  static const int g = [] {
+    const char* e = getenv("DMG_COARSE_GROUPS");
+    const int v = e ? atoi(e) : 0;
+    return (v >= 1 && v <= CP_GMAX) ? v : 64;
+  }();
+  return g;
+}
+
 static bool cp_debug() {
   static const int on = [] {
     const char* e = getenv("DMG_DEBUG");
@@ -1312,7 +1322,7 @@ int launch_coarse_proj(hipStream_t st, const cx<R>* A, int Lx, int Lt, const cx<
   if (mm + 2 > CP_QMAX || k + 1 > CP_QMAX || mm < 1) return 0;
   const int V = Lx * Lt;
   const size_t lds_max = 160 * 1024;
-  if (groups <= 0) groups = 64;
+  if (groups <= 0) groups = cp_groups_default();
   int spw = (V + groups - 1) / groups;
   if (spw > 10) spw = 10;  // one thread per local entry
   const int G = (V + spw - 1) / spw;
