@@ -88,3 +88,24 @@ def test_bench_power_fit():
     assert se > 0 and abs(a - 0.37) < 4 * se
     a, se = bench.power_fit([100.0, 100.0], [3.0, 4.0])
     assert se is None
+
+
+def test_bench_coarse_traffic_matches_its_profile():
+    """The HBM bytes per launch that bench.py reports for the persistent coarse kernel are the
+    counter values recorded in profiles/k_coarse_proj_256_hbm_traffic.md (FETCH_SIZE x 2 plus
+    WRITE_SIZE, KiB per dispatch, the scale factors the reference kernels of known size give)."""
+    import bench
+    txt = open(os.path.join(ROOT, "profiles", "k_coarse_proj_256_hbm_traffic.md")).read()
+    row = re.search(r"\|\s*`k_coarse_proj<double, false, true, true>`\s*\|\s*(\d+)\s*\|\s*([\d,.]+)\s*\|\s*([\d,.]+)\s*\|",
+                    txt)
+    assert row, "coarse kernel row missing from the traffic profile"
+    fetch, write = (float(row.group(k).replace(",", "")) for k in (2, 3))
+    ref = re.search(r"\|\s*`vectorized_elementwise_kernel<\.\.\. mul \.\.\.>`[^|]*\|\s*\d+\s*\|\s*([\d,.]+)\s*\|\s*([\d,.]+)\s*\|",
+                    txt)
+    assert ref, "reference kernel row missing from the traffic profile"
+    # the reference kernel reads and writes 256 MiB per launch: the counters' scale factors
+    fscale = 262144.0 / float(ref.group(1).replace(",", ""))
+    wscale = 262144.0 / float(ref.group(2).replace(",", ""))
+    assert abs(fscale - 2.0) < 0.01 and abs(wscale - 1.0) < 0.01
+    expect = (round(fscale) * fetch + round(wscale) * write) * 1024
+    assert abs(bench.COARSE_TRAFFIC_BYTES - expect) <= 1024
